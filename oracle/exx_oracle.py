@@ -1,0 +1,342 @@
+"""Plain FP64 CPU oracle for the RI-LVL real-space exchange matrix.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or runs
+this module; only the tests, the package's smoke check and the benchmark's CPU
+baseline leg do.  It shares no code with the GPU library: it reads the inputs
+written by the seeded generator (``synth``) and recomputes everything,
+including the atom-pair screening, on its own.
+
+What is computed (non-periodic case, i.e. only the lattice vector R = 0 of the
+paper's real-space exchange equation, Sec. "Description of the real-space
+formalism", Eq. (realspace_exchange)):
+
+    K_ik = sum_{j,l} sum_{mu,nu} C^mu_ij V_{mu nu} C^nu_kl D_jl
+    E_x  = -1/4 sum_{i,k} K_ik D_ik
+
+with the RI-LVL pair restriction (same section): C^mu_ij = 0 unless the
+auxiliary function mu sits on the atom of i or on the atom of j.  C^mu is
+symmetric in (i, j) (it expands the product phi_i phi_j).  The paper does not
+write E_x; the energy convention is the usual exchange energy for a
+closed-shell density matrix scaled as stated above.
+
+Routes (three independent evaluations of the same definition):
+
+* ``k_4index``  forms the 4-index tensor (ij|kl) = sum C V C in i-slabs and
+  contracts it with D; it also returns E_x contracted directly from (ij|kl).
+* ``k_eigen``   uses D = sum_m lambda_m v_m v_m^T, so that
+  K = sum_m lambda_m U_m V U_m^T with U_m[:, mu] = C^mu v_m.
+* ``k_rows``    evaluates whole rows K[i, :] from the definition with the
+  structural zeros of C and V skipped; usable at any system size.
+
+Gradients (``gradients``) follow from E_x being quadratic in C and D and
+linear in V:  dE/dD = -1/2 K,  dE/dC^mu = -1/2 sum_nu V_{mu nu} D C^nu D,
+dE/dV_{mu nu} = -1/4 tr(C^mu D C^nu D); per stored layout entry the mirrored
+copies are summed (off-site C and V blocks are each stored once for both
+orientations).  Forces use the synthetic analytic dependence of C and V on
+the atom positions (C ~ exp(-r/1.5), V ~ exp(-r^2/8)), with D held fixed.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# screening and index bookkeeping (independent of the generator's own code)
+
+
+def screened_pairs(pos, r_cut, sys_off):
+    """Atom pairs (A <= B, same system) with squared distance <= r_cut^2.
+
+    The squared distance is (dx*dx + dy*dy) + dz*dz in float64.  Returned in
+    lexicographic order, which is the storage order of the C and V blocks."""
+    out_a, out_b = [], []
+    rc2 = r_cut * r_cut
+    for s in range(len(sys_off) - 1):
+        lo, hi = int(sys_off[s]), int(sys_off[s + 1])
+        P = pos[lo:hi]
+        dx = P[:, None, 0] - P[None, :, 0]
+        dy = P[:, None, 1] - P[None, :, 1]
+        dz = P[:, None, 2] - P[None, :, 2]
+        r2 = (dx * dx + dy * dy) + dz * dz
+        a, b = np.nonzero(np.triu(r2 <= rc2))
+        out_a.append(a + lo)
+        out_b.append(b + lo)
+    return np.concatenate(out_a).astype(np.int32), np.concatenate(out_b).astype(np.int32)
+
+
+class Blocks:
+    """Read access to the C / V / D inputs of one system (atoms lo..hi-1)."""
+
+    def __init__(self, inputs, s=0):
+        sysm, lay = inputs.system, inputs.layout
+        self.lo, self.hi = int(sysm.sys_off[s]), int(sysm.sys_off[s + 1])
+        self.nat = self.hi - self.lo
+        sp = sysm.species[self.lo:self.hi]
+        from synth.water import N_AUX, N_BASIS  # species table (input metadata)
+        self.nb = N_BASIS[sp].astype(np.int64)
+        self.na = N_AUX[sp].astype(np.int64)
+        self.bo = np.concatenate([[0], np.cumsum(self.nb)])
+        self.ao = np.concatenate([[0], np.cumsum(self.na)])
+        self.n, self.naux = int(self.bo[-1]), int(self.ao[-1])
+        self.pos = sysm.pos[self.lo:self.hi]
+        self.r_cut = sysm.r_cut
+        pa, pb = screened_pairs(sysm.pos, sysm.r_cut, sysm.sys_off)
+        if not (np.array_equal(pa, lay.pair_a) and np.array_equal(pb, lay.pair_b)):
+            raise ValueError("input layout does not match the oracle's screening")
+        sel = (pa >= self.lo) & (pa < self.hi)
+        self.pidx = np.nonzero(sel)[0]
+        self.pa, self.pb = pa[sel] - self.lo, pb[sel] - self.lo
+        self.C, self.V = inputs.C, inputs.V
+        self.c_off, self.v_off = lay.c_off, lay.v_off
+        d0 = int(lay.sys_bas_off[s])
+        self.D = inputs.D[d0:d0 + self.n * self.n].reshape(self.n, self.n)
+        self.pair_of = {}
+        for q, (a, b) in enumerate(zip(self.pa, self.pb)):
+            self.pair_of[(int(a), int(b))] = q
+        self.nbrs = [[] for _ in range(self.nat)]
+        for a, b in zip(self.pa, self.pb):
+            self.nbrs[a].append(int(b))
+            if a != b:
+                self.nbrs[b].append(int(a))
+        for lst in self.nbrs:
+            lst.sort()
+
+    def c_block(self, q):
+        p = self.pidx[q]
+        a, b = self.pa[q], self.pb[q]
+        blk = self.C[self.c_off[p]:self.c_off[p + 1]]
+        if a == b:
+            return blk.reshape(self.na[a], self.nb[a], self.nb[a])
+        return blk.reshape(self.na[a] + self.na[b], self.nb[a], self.nb[b])
+
+    def v_block(self, q):
+        p = self.pidx[q]
+        a, b = self.pa[q], self.pb[q]
+        return self.V[self.v_off[p]:self.v_off[p + 1]].reshape(self.na[a], self.na[b])
+
+    # dense forms (small systems only)
+    def dense_C(self):
+        """C3[mu, i, j] over the whole system (n_aux x n x n)."""
+        C3 = np.zeros((self.naux, self.n, self.n))
+        for q, (a, b) in enumerate(zip(self.pa, self.pb)):
+            blk = self.c_block(q)
+            ia, ib = slice(self.bo[a], self.bo[a + 1]), slice(self.bo[b], self.bo[b + 1])
+            if a == b:
+                C3[self.ao[a]:self.ao[a + 1], ia, ia] = blk
+                continue
+            for owner, part in ((a, blk[:self.na[a]]), (b, blk[self.na[a]:])):
+                mu = slice(self.ao[owner], self.ao[owner + 1])
+                C3[mu, ia, ib] = part
+                C3[mu, ib, ia] = part.transpose(0, 2, 1)
+        return C3
+
+    def dense_V(self):
+        Vd = np.zeros((self.naux, self.naux))
+        for q, (a, b) in enumerate(zip(self.pa, self.pb)):
+            blk = self.v_block(q)
+            ma, mb = slice(self.ao[a], self.ao[a + 1]), slice(self.ao[b], self.ao[b + 1])
+            Vd[ma, mb] = blk
+            if a != b:
+                Vd[mb, ma] = blk.T
+        return Vd
+
+
+def exchange_energy(K, D):
+    """E_x = -1/4 sum_ik K_ik D_ik."""
+    return -0.25 * float(np.sum(K * D))
+
+
+# ----------------------------------------------------------------------------
+# route 1: the 4-index tensor
+
+
+def k_4index(inputs, s=0, slab=8):
+    """K from (ij|kl) = sum_{mu nu} C^mu_ij V_{mu nu} C^nu_kl, in i-slabs.
+
+    Returns (K, E_from_K, E_direct) where E_direct contracts (ij|kl) with
+    D_ik D_jl without forming K (k summed first, then j and l)."""
+    blk = Blocks(inputs, s)
+    n = blk.n
+    B = blk.dense_C().reshape(blk.naux, n * n)       # B[mu, (k,l)]
+    VB = blk.dense_V() @ B                            # (V B)[mu, (k,l)]
+    D = blk.D
+    K = np.zeros((n, n))
+    e_direct = 0.0
+    for i0 in range(0, n, slab):
+        i1 = min(n, i0 + slab)
+        rows = B.reshape(blk.naux, n, n)[:, i0:i1, :].reshape(blk.naux, -1)
+        eri = (rows.T @ VB).reshape(i1 - i0, n, n, n)  # (ij|kl), i in slab
+        K[i0:i1] = np.einsum("ijkl,jl->ik", eri, D, optimize=True)
+        t = np.einsum("ijkl,ik->ijl", eri, D[i0:i1], optimize=True)
+        e_direct += float(np.sum(t * D[None, :, :]))
+    return K, exchange_energy(K, D), -0.25 * e_direct
+
+
+# ----------------------------------------------------------------------------
+# route 2: eigen-decomposition of D
+
+
+def k_eigen(inputs, s=0):
+    blk = Blocks(inputs, s)
+    n = blk.n
+    lam, vec = np.linalg.eigh(blk.D)
+    C3 = blk.dense_C()
+    U = (C3.reshape(-1, n) @ vec).reshape(blk.naux, n, n)      # U[mu, i, m]
+    W = (blk.dense_V() @ U.reshape(blk.naux, -1)).reshape(blk.naux, n, n)
+    Ul = U * lam[None, None, :]
+    K = np.einsum("aim,akm->ik", Ul, W, optimize=True)
+    return K
+
+
+# ----------------------------------------------------------------------------
+# route 3: rows of K from the definition, structural zeros skipped
+
+
+def k_rows(inputs, rows, s=0, blk=None):
+    """K[rows, :] for rows given as basis indices local to system s.
+
+    For row i:  u^mu = C^mu[i, :];  t^mu = D u^mu;  y^nu = sum_mu V_{nu mu} t^mu;
+    K[i, k] = sum_nu sum_l C^nu_kl y^nu_l."""
+    if blk is None:
+        blk = Blocks(inputs, s)
+    atom_of = np.repeat(np.arange(blk.nat), blk.nb)
+    D = blk.D
+    out = np.zeros((len(rows), blk.n))
+    for r, i in enumerate(rows):
+        I = int(atom_of[i])
+        ii = i - blk.bo[I]
+        # u^mu restricted to the aux functions whose C^mu has a nonzero row i
+        mu_idx, u_rows = [], []
+        for J in blk.nbrs[I]:
+            a, b = (I, J) if I <= J else (J, I)
+            cb = blk.c_block(blk.pair_of[(a, b)])
+            if I == J:
+                u = np.zeros((blk.na[I], blk.n))
+                u[:, blk.bo[I]:blk.bo[I + 1]] = cb[:, ii, :]
+                mu_idx.append(np.arange(blk.ao[I], blk.ao[I + 1]))
+                u_rows.append(u)
+                continue
+            if I < J:   # block rows: basis of I, cols: basis of J
+                rowpart = cb[:, ii, :]                     # [m, j in J]
+            else:       # block rows: basis of J, cols: basis of I
+                rowpart = cb[:, :, ii]
+            na_a = blk.na[a]
+            for owner, part in ((a, rowpart[:na_a]), (b, rowpart[na_a:])):
+                u = np.zeros((blk.na[owner], blk.n))
+                u[:, blk.bo[J]:blk.bo[J + 1]] = part
+                mu_idx.append(np.arange(blk.ao[owner], blk.ao[owner + 1]))
+                u_rows.append(u)
+        mu_idx = np.concatenate(mu_idx)
+        Ufull = np.concatenate(u_rows)
+        # several blocks contribute to the same mu (mu on I appears for every J)
+        uniq, inv = np.unique(mu_idx, return_inverse=True)
+        Um = np.zeros((len(uniq), blk.n))
+        np.add.at(Um, inv, Ufull)
+        t = Um @ D                                         # t^mu (D symmetric)
+        # y^nu for every nu coupled by V to some mu in uniq
+        aux_atom = np.repeat(np.arange(blk.nat), blk.na)
+        mu_atoms = np.unique(aux_atom[uniq])
+        y = {}
+        for P in mu_atoms:
+            selP = aux_atom[uniq] == P
+            tP = t[selP]
+            locP = uniq[selP] - blk.ao[P]
+            for Q in blk.nbrs[P]:
+                a, b = (P, Q) if P <= Q else (Q, P)
+                vb = blk.v_block(blk.pair_of[(a, b)])
+                VPQ = vb if P <= Q else vb.T                 # [mu on P, nu on Q]
+                contrib = VPQ[locP].T @ tP                   # [nu on Q, n]
+                y[Q] = y.get(Q, 0.0) + contrib
+        # K[i, k] = sum_nu (C^nu y^nu)[k]
+        Ki = np.zeros(blk.n)
+        for Q, yQ in y.items():
+            for J in blk.nbrs[Q]:
+                a, b = (Q, J) if Q <= J else (J, Q)
+                cb = blk.c_block(blk.pair_of[(a, b)])
+                sq, sj = slice(blk.bo[Q], blk.bo[Q + 1]), slice(blk.bo[J], blk.bo[J + 1])
+                if Q == J:
+                    Ki[sq] += np.einsum("nkl,nl->k", cb, yQ[:, sq])
+                    continue
+                part = cb[:blk.na[a]] if Q == a else cb[blk.na[a]:]
+                if Q < J:   # part[nu, k in Q, l in J]
+                    Ki[sq] += np.einsum("nkl,nl->k", part, yQ[:, sj])
+                    Ki[sj] += np.einsum("nkl,nk->l", part, yQ[:, sq])
+                else:       # part[nu, k in J, l in Q]
+                    Ki[sj] += np.einsum("nkl,nl->k", part, yQ[:, sq])
+                    Ki[sq] += np.einsum("nkl,nk->l", part, yQ[:, sj])
+        out[r] = Ki
+    return out
+
+
+def k_full_rows(inputs, s=0):
+    """The whole K of system s via the row route (moderate sizes only)."""
+    blk = Blocks(inputs, s)
+    return k_rows(inputs, np.arange(blk.n), s, blk)
+
+
+# ----------------------------------------------------------------------------
+# gradients and forces (dense; small systems)
+
+
+def gradients(inputs, s=0):
+    """dE/dC, dE/dV (stored layouts, entries of system s only), dE/dD (dense).
+
+    Returns dict with 'E', 'K', 'dC' (flat, layout of C), 'dV', 'dD',
+    'sC' and 'sV' (per stored pair q of the system: <dE/dblock, block>)."""
+    blk = Blocks(inputs, s)
+    n = blk.n
+    C3 = blk.dense_C()
+    Vd = blk.dense_V()
+    D = blk.D
+    DCD = np.einsum("ab,mbc,cd->mad", D, C3, D, optimize=True)     # D C^nu D
+    G = -0.5 * (Vd @ DCD.reshape(blk.naux, -1)).reshape(blk.naux, n, n)
+    Q = np.einsum("mab,bc->mac", C3, D, optimize=True)              # C^mu D
+    tau = Q.reshape(blk.naux, -1) @ Q.transpose(0, 2, 1).reshape(blk.naux, -1).T
+    lam, vec = np.linalg.eigh(D)
+    K = k_eigen(inputs, s)
+    E = exchange_energy(K, D)
+    dC = np.zeros_like(inputs.C)
+    dV = np.zeros_like(inputs.V)
+    sC = np.zeros(len(blk.pa))
+    sV = np.zeros(len(blk.pa))
+    for q, (a, b) in enumerate(zip(blk.pa, blk.pb)):
+        p = blk.pidx[q]
+        ia, ib = slice(blk.bo[a], blk.bo[a + 1]), slice(blk.bo[b], blk.bo[b + 1])
+        ma, mb = slice(blk.ao[a], blk.ao[a + 1]), slice(blk.ao[b], blk.ao[b + 1])
+        if a == b:
+            g = G[ma, ia, ia]
+            vg = -0.25 * tau[ma, ma]
+        else:
+            g = np.concatenate([G[ma, ia, ib], G[mb, ia, ib]]) * 2.0
+            vg = -0.5 * tau[ma, mb]
+        dC[blk.c_off[p]:blk.c_off[p + 1]] = g.ravel()
+        dV[blk.v_off[p]:blk.v_off[p + 1]] = vg.ravel()
+        sC[q] = float(np.sum(g * blk.c_block(q)))
+        sV[q] = float(np.sum(vg * blk.v_block(q)))
+    return dict(E=E, K=K, dC=dC, dV=dV, dD=-0.5 * K, sC=sC, sV=sV, blk=blk)
+
+
+def forces(inputs, grads, c_decay=1.5, v_2s2=8.0):
+    """-dE/dR_A through C_AB ~ exp(-r/c_decay) and V_AB ~ exp(-r^2/v_2s2).
+
+    On-site blocks do not depend on positions; D is held fixed."""
+    blk = grads["blk"]
+    F = np.zeros((blk.nat, 3))
+    for q, (a, b) in enumerate(zip(blk.pa, blk.pb)):
+        if a == b:
+            continue
+        d = blk.pos[a] - blk.pos[b]
+        r = math.sqrt(float(d @ d))
+        # dE/dR_a = sC * (-1/c_decay) d/r + sV * (-2/v_2s2) d
+        g = grads["sC"][q] * (-1.0 / c_decay) * d / r + grads["sV"][q] * (-2.0 / v_2s2) * d
+        F[a] -= g
+        F[b] += g
+    return F
+
+
+def energy_at(inputs_fn, pos):
+    """E_x of the inputs regenerated at positions pos (helper for FD tests)."""
+    inp = inputs_fn(pos)
+    K = k_eigen(inp)
+    return exchange_energy(K, Blocks(inp).D)

@@ -1,0 +1,365 @@
+"""Seeded synthetic water / ice systems and their RI-LVL inputs C, V, D.
+
+This module only produces inputs: atom positions, species, and the three
+arrays the exchange build consumes (RI coefficients C, the screened auxiliary
+Coulomb matrix V, the density matrix D), in the block layouts the library's
+boundary documents.  It contains none of the exchange arithmetic; both the
+CPU oracle and the GPU path read what it writes.
+
+Recipe (the paper's workloads are FHI-aims water/ice with "light" species,
+8 basis functions per atom on average; here the species counts and value
+distributions are synthetic stand-ins):
+
+* species O: 14 basis / 40 auxiliary functions; H: 5 basis / 15 auxiliary.
+* O sites: a jittered 2.8 A half-integer cubic grid (clusters) or a jittered
+  diamond-like lattice with 3.1 A O-O nearest-neighbour distance (ice boxes).
+  Jitter is uniform in [-0.15, 0.15] A per coordinate.
+* each O carries two H at 0.96 A with a 104.5 degree H-O-H angle, oriented by
+  a uniformly random unit quaternion.
+* atom order is molecule by molecule: O, H, H.
+* one inclusive cutoff r <= r_cut on atom-pair distance decides which C, V and
+  D blocks exist (all other blocks are structurally zero).
+* C block of pair (A, B), A != B: N(0,1) * exp(-r_AB / 1.5), aux of A first,
+  then aux of B; on-site blocks: N(0,1), symmetric in the two basis indices.
+* D block (A, B): N(0,1) * exp(-r_AB / 2.0), D symmetric, on-site block
+  symmetric N(0,1).
+* V block (A, B) = exp(-r_AB^2 / 8) * (L_s(A) L_s(B)^T), L_s an n_aux(s) x 40
+  matrix of N(0,1)/sqrt(40) entries per species (SPD by the Schur product
+  theorem before screening).
+
+Random numbers come from per-block keyed streams (seed, kind, label_a,
+label_b), so values follow atoms under any permutation of the atom order.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+# species table: index -> (name, n_basis, n_aux)
+SPECIES_NAMES = ("O", "H")
+N_BASIS = np.array([14, 5], dtype=np.int32)
+N_AUX = np.array([40, 15], dtype=np.int32)
+O, H = 0, 1
+
+C_DECAY = 1.5          # A, C ~ exp(-r / C_DECAY)
+D_DECAY = 2.0          # A, D ~ exp(-r / D_DECAY)
+V_GAUSS_2S2 = 8.0      # A^2, V ~ exp(-r^2 / V_GAUSS_2S2)  (2 * 2.0^2)
+L_RANK = 40            # inner dimension of the per-species V factors
+
+_KIND_GEOM, _KIND_C, _KIND_D, _KIND_V, _KIND_BATCH = 1, 2, 3, 4, 5
+
+OH_BOND = 0.96
+HOH_ANGLE = math.radians(104.5)
+JITTER = 0.15
+
+
+@dataclass
+class System:
+    """A set of atoms, possibly several independent clusters (a batch)."""
+    species: np.ndarray            # (n_atoms,) int32
+    pos: np.ndarray                # (n_atoms, 3) float64, Angstrom
+    r_cut: float
+    seed: int
+    labels: np.ndarray = None      # (n_atoms,) int64, persistent ids for RNG keys
+    sys_off: np.ndarray = None     # (n_systems + 1,) int32 atom offsets
+    name: str = ""
+
+    def __post_init__(self):
+        self.species = np.ascontiguousarray(self.species, dtype=np.int32)
+        self.pos = np.ascontiguousarray(self.pos, dtype=np.float64)
+        n = len(self.species)
+        if self.labels is None:
+            self.labels = np.arange(n, dtype=np.int64)
+        self.labels = np.ascontiguousarray(self.labels, dtype=np.int64)
+        if self.sys_off is None:
+            self.sys_off = np.array([0, n], dtype=np.int32)
+        self.sys_off = np.ascontiguousarray(self.sys_off, dtype=np.int32)
+
+    @property
+    def n_atoms(self):
+        return len(self.species)
+
+    @property
+    def n_systems(self):
+        return len(self.sys_off) - 1
+
+    def nbas(self):
+        return N_BASIS[self.species]
+
+    def naux(self):
+        return N_AUX[self.species]
+
+
+@dataclass
+class Layout:
+    """Block layout of C and V (canonical pairs) and of dense D/K per system."""
+    pair_a: np.ndarray             # (n_pairs,) int32, A <= B, lexicographic
+    pair_b: np.ndarray
+    c_off: np.ndarray              # (n_pairs + 1,) int64
+    v_off: np.ndarray              # (n_pairs + 1,) int64
+    bas_off: np.ndarray            # (n_atoms,) basis offset within its system
+    sys_bas_off: np.ndarray        # (n_systems + 1,) int64, offsets of dense blocks in D/K
+    sys_nbas: np.ndarray           # (n_systems,) int64
+
+    @property
+    def n_pairs(self):
+        return len(self.pair_a)
+
+    @property
+    def d_size(self):
+        return int(self.sys_bas_off[-1])
+
+
+@dataclass
+class Inputs:
+    system: System
+    layout: Layout
+    C: np.ndarray                  # flat float64, pair blocks
+    V: np.ndarray                  # flat float64, pair blocks
+    D: np.ndarray                  # flat float64, dense per system (concatenated)
+    extra: dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------------------
+# geometry
+
+def _rng(*key):
+    return np.random.default_rng(np.random.SeedSequence([int(k) for k in key]))
+
+
+def _random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def _waters_from_oxygens(o_pos, rng):
+    """Jitter O sites, add two H per O; atom order O, H, H per molecule."""
+    n = len(o_pos)
+    o = o_pos + rng.uniform(-JITTER, JITTER, size=(n, 3))
+    half = 0.5 * HOH_ANGLE
+    h1_local = OH_BOND * np.array([math.sin(half), 0.0, math.cos(half)])
+    h2_local = OH_BOND * np.array([-math.sin(half), 0.0, math.cos(half)])
+    pos = np.empty((3 * n, 3))
+    for m in range(n):
+        R = _random_rotation(rng)
+        pos[3 * m] = o[m]
+        pos[3 * m + 1] = o[m] + R @ h1_local
+        pos[3 * m + 2] = o[m] + R @ h2_local
+    species = np.tile(np.array([O, H, H], dtype=np.int32), n)
+    return species, pos
+
+
+def cubic_cluster_sites(n_mol, spacing=2.8):
+    """The n_mol sites of a half-integer cubic grid nearest its centre.
+
+    Ties in distance are broken lexicographically by (x, y, z)."""
+    m = int(math.ceil(n_mol ** (1.0 / 3.0))) // 2 + 2
+    g = np.arange(-m, m) + 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    sites = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1) * spacing
+    r2 = np.round((sites ** 2).sum(1), 9)
+    order = np.lexsort((sites[:, 2], sites[:, 1], sites[:, 0], r2))
+    return sites[order[:n_mol]]
+
+
+def water_cluster(n_mol, seed, r_cut=6.0, spacing=2.8):
+    """Non-periodic water cluster on a jittered cubic grid."""
+    rng = _rng(seed, _KIND_GEOM)
+    species, pos = _waters_from_oxygens(cubic_cluster_sites(n_mol, spacing), rng)
+    return System(species, pos, r_cut, seed, name=f"water_cluster_{n_mol}")
+
+
+ICE_NN = 3.1
+
+
+def diamond_sites(nx, ny, nz, nn=ICE_NN):
+    """O sites of a diamond-like lattice, nearest-neighbour distance nn."""
+    a = 4.0 * nn / math.sqrt(3.0)
+    fcc = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    basis = np.concatenate([fcc, fcc + 0.25])
+    sites = []
+    for ix in range(nx):
+        for iy in range(ny):
+            for iz in range(nz):
+                for b in basis:
+                    sites.append((np.array([ix, iy, iz]) + b) * a)
+    return np.array(sites), a
+
+
+def ice_box(nx, ny, nz, seed, r_cut=6.0):
+    """Open (non-periodic) ice-like box of 8*nx*ny*nz water molecules."""
+    rng = _rng(seed, _KIND_GEOM)
+    sites, _ = diamond_sites(nx, ny, nz)
+    species, pos = _waters_from_oxygens(sites, rng)
+    return System(species, pos, r_cut, seed, name=f"ice_box_{nx}x{ny}x{nz}")
+
+
+def cluster_batch(n_clusters=64, batch_seed=123, n_min=8, n_max=128, r_cut=6.0):
+    """Independent water clusters of uneven sizes, concatenated as one batch.
+
+    Cluster c has n_c ~ U{n_min..n_max} molecules (drawn from the batch
+    seed) and uses seed c for its geometry and values."""
+    rng = _rng(batch_seed, _KIND_BATCH)
+    sizes = rng.integers(n_min, n_max + 1, size=n_clusters)
+    species, pos, labels, off = [], [], [], [0]
+    for c, n in enumerate(sizes):
+        s = water_cluster(int(n), seed=c, r_cut=r_cut)
+        species.append(s.species)
+        # keep clusters far apart; pairs never cross systems anyway
+        pos.append(s.pos + np.array([1000.0 * c, 0.0, 0.0]))
+        labels.append(np.arange(s.n_atoms, dtype=np.int64))  # keys also carry seed c
+        off.append(off[-1] + s.n_atoms)
+    sysm = System(np.concatenate(species), np.concatenate(pos), r_cut, batch_seed,
+                  labels=np.concatenate(labels), sys_off=np.array(off, dtype=np.int32),
+                  name=f"cluster_batch_{n_clusters}")
+    sysm.cluster_seeds = list(range(n_clusters))
+    return sysm
+
+
+def permuted(system, perm):
+    """The same system with atoms reordered (labels follow the atoms)."""
+    perm = np.asarray(perm)
+    assert system.n_systems == 1
+    return System(system.species[perm], system.pos[perm], system.r_cut, system.seed,
+                  labels=system.labels[perm], name=system.name + "_perm")
+
+
+# ----------------------------------------------------------------------------
+# block layout
+
+def canonical_pairs(system):
+    """All (A, B), A <= B, same system, |R_A - R_B|^2 <= r_cut^2, lexicographic.
+
+    The squared distance is formed as dx*dx + dy*dy + dz*dz in float64,
+    left to right, without fused multiply-add."""
+    pa, pb = [], []
+    rc2 = system.r_cut * system.r_cut
+    for s in range(system.n_systems):
+        lo, hi = int(system.sys_off[s]), int(system.sys_off[s + 1])
+        P = system.pos[lo:hi]
+        for a in range(hi - lo):
+            d = P[a:] - P[a]
+            dx, dy, dz = d[:, 0], d[:, 1], d[:, 2]
+            r2 = (dx * dx + dy * dy) + dz * dz
+            idx = np.nonzero(r2 <= rc2)[0]
+            pa.append(np.full(len(idx), lo + a, dtype=np.int32))
+            pb.append((lo + a + idx).astype(np.int32))
+    return np.concatenate(pa), np.concatenate(pb)
+
+
+def make_layout(system):
+    pa, pb = canonical_pairs(system)
+    nb, na = system.nbas().astype(np.int64), system.naux().astype(np.int64)
+    csz = np.where(pa == pb, na[pa] * nb[pa] * nb[pa], (na[pa] + na[pb]) * nb[pa] * nb[pb])
+    vsz = na[pa] * na[pb]
+    c_off = np.concatenate([[0], np.cumsum(csz)]).astype(np.int64)
+    v_off = np.concatenate([[0], np.cumsum(vsz)]).astype(np.int64)
+    bas_off = np.zeros(system.n_atoms, dtype=np.int64)
+    sys_nbas = np.zeros(system.n_systems, dtype=np.int64)
+    for s in range(system.n_systems):
+        lo, hi = int(system.sys_off[s]), int(system.sys_off[s + 1])
+        bas_off[lo:hi] = np.concatenate([[0], np.cumsum(nb[lo:hi])[:-1]])
+        sys_nbas[s] = nb[lo:hi].sum()
+    sys_bas_off = np.concatenate([[0], np.cumsum(sys_nbas ** 2)]).astype(np.int64)
+    return Layout(pa, pb, c_off, v_off, bas_off, sys_bas_off, sys_nbas)
+
+
+# ----------------------------------------------------------------------------
+# values
+
+def _sym_upper(x):
+    """Mirror the upper triangle (incl. diagonal) of the last two axes."""
+    u = np.triu(x)
+    return u + np.swapaxes(np.triu(x, 1), -1, -2)
+
+
+def v_factors(seed):
+    rng = _rng(seed, _KIND_V)
+    return [rng.normal(size=(int(N_AUX[s]), L_RANK)) / math.sqrt(L_RANK)
+            for s in range(len(N_AUX))]
+
+
+def make_inputs(system, layout=None, zero_D=False):
+    """Generate C, V, D for a system in the library's block layouts."""
+    if layout is None:
+        layout = make_layout(system)
+    sp, lab, pos = system.species, system.labels, system.pos
+    nb, na = N_BASIS, N_AUX
+    C = np.empty(int(layout.c_off[-1]))
+    V = np.empty(int(layout.v_off[-1]))
+    D = np.zeros(layout.d_size)
+    L = v_factors(system.seed)
+    seeds = getattr(system, "cluster_seeds", None)
+    atom_sys = np.zeros(system.n_atoms, dtype=np.int64)
+    for s in range(system.n_systems):
+        atom_sys[system.sys_off[s]:system.sys_off[s + 1]] = s
+    for p in range(layout.n_pairs):
+        A, B = int(layout.pair_a[p]), int(layout.pair_b[p])
+        sA, sB = int(sp[A]), int(sp[B])
+        seed = system.seed if seeds is None else seeds[atom_sys[A]]
+        Ls = L if seeds is None else v_factors(seed)
+        d = pos[A] - pos[B]
+        r = math.sqrt(float(d @ d))
+        c0, c1 = int(layout.c_off[p]), int(layout.c_off[p + 1])
+        v0, v1 = int(layout.v_off[p]), int(layout.v_off[p + 1])
+        so = int(layout.sys_bas_off[atom_sys[A]])
+        n_s = int(layout.sys_nbas[atom_sys[A]])
+        ia, ib = int(layout.bas_off[A]), int(layout.bas_off[B])
+        if A == B:
+            rng_c = _rng(seed, _KIND_C, lab[A], lab[A])
+            blk = _sym_upper(rng_c.normal(size=(na[sA], nb[sA], nb[sA])))
+            C[c0:c1] = blk.ravel()
+            V[v0:v1] = (Ls[sA] @ Ls[sA].T).ravel()
+            rng_d = _rng(seed, _KIND_D, lab[A], lab[A])
+            dblk = _sym_upper(rng_d.normal(size=(nb[sA], nb[sA])))
+        else:
+            # generate in label orientation (lower label first), then map
+            flip = lab[A] > lab[B]
+            la, lb = (lab[B], lab[A]) if flip else (lab[A], lab[B])
+            s1, s2 = (sB, sA) if flip else (sA, sB)
+            rng_c = _rng(seed, _KIND_C, la, lb)
+            blk = rng_c.normal(size=(na[s1] + na[s2], nb[s1], nb[s2])) * math.exp(-r / C_DECAY)
+            if flip:  # label order (B, A) -> index order (A, B)
+                blk = np.concatenate([blk[na[s1]:], blk[:na[s1]]], axis=0).transpose(0, 2, 1)
+            C[c0:c1] = np.ascontiguousarray(blk).ravel()
+            V[v0:v1] = (math.exp(-r * r / V_GAUSS_2S2) * (Ls[sA] @ Ls[sB].T)).ravel()
+            rng_d = _rng(seed, _KIND_D, la, lb)
+            dblk = rng_d.normal(size=(nb[s1], nb[s2])) * math.exp(-r / D_DECAY)
+            if flip:
+                dblk = dblk.T
+        if not zero_D:
+            Dm = D[so:so + n_s * n_s].reshape(n_s, n_s)
+            Dm[ia:ia + nb[sA], ib:ib + nb[sB]] = dblk
+            Dm[ib:ib + nb[sB], ia:ia + nb[sA]] = dblk.T
+    return Inputs(system, layout, C, V, D)
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+
+def config(n, seed=0):
+    """Workload n (1-based) at full size.
+
+    1: 8-molecule cluster (24 atoms), r_cut 6 A.
+    2: 256-molecule open ice box (768 atoms), r_cut 6 A.
+    3: batch of 64 clusters of 8..128 molecules, r_cut 6 A.
+    4: the 768-atom box again (differentiation workload).
+    5: 1024-molecule ice box (3072 atoms), r_cut 8 A (periodic in the paper's
+       sense; handled as the open box here when periodic images are off)."""
+    if n == 1:
+        return water_cluster(8, seed)
+    if n in (2, 4):
+        return ice_box(4, 4, 2, seed)
+    if n == 3:
+        return cluster_batch()
+    if n == 5:
+        return ice_box(8, 4, 4, seed, r_cut=8.0)
+    raise ValueError(n)

@@ -1,0 +1,390 @@
+"""Independent checks ("pins") of the CPU oracle.
+
+Each pin compares the oracle with something other than itself: a closed form
+for a special input, brute force on a tiny input, an algebraic invariant of
+the definition, the paper's own regrouped formula, or finite differences.
+Inputs are built dense-first here and packed into the library layout by this
+module's own packer, so a mistake in the oracle's unpacking also shows up.
+
+Every pin returns (ok, detail) so the mutation tests can reuse them.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import synth
+from oracle import exx_oracle as O
+
+TOL = 1e-12
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    s = max(np.abs(a).max(), np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / s)
+
+
+# ----------------------------------------------------------------------------
+# dense-first random problems packed into the layout
+
+
+def _offsets(sysm):
+    nb = synth.N_BASIS[sysm.species].astype(int)
+    na = synth.N_AUX[sysm.species].astype(int)
+    return nb, na, np.concatenate([[0], np.cumsum(nb)]), np.concatenate([[0], np.cumsum(na)])
+
+
+def random_problem(sysm, seed, d_rank1=None):
+    """Dense C3, V, D with the RI-LVL structure, plus the packed Inputs.
+
+    Off-site V blocks are generic (not symmetric); D is symmetric unless a
+    rank-1 pair (v, w) is requested, in which case D = v w^T."""
+    rng = np.random.default_rng(seed)
+    lay = synth.make_layout(sysm)
+    nb, na, bo, ao = _offsets(sysm)
+    n, naux = bo[-1], ao[-1]
+    C3 = np.zeros((naux, n, n))
+    Vd = np.zeros((naux, naux))
+    C = np.empty(int(lay.c_off[-1]))
+    V = np.empty(int(lay.v_off[-1]))
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        ia, ib = slice(bo[a], bo[a + 1]), slice(bo[b], bo[b + 1])
+        ma, mb = slice(ao[a], ao[a + 1]), slice(ao[b], ao[b + 1])
+        if a == b:
+            x = rng.normal(size=(na[a], nb[a], nb[a]))
+            x = x + x.transpose(0, 2, 1)
+            C3[ma, ia, ia] = x
+            C[lay.c_off[p]:lay.c_off[p + 1]] = x.ravel()
+            v = rng.normal(size=(na[a], na[a]))
+            v = v + v.T
+            Vd[ma, ma] = v
+        else:
+            x = rng.normal(size=(na[a] + na[b], nb[a], nb[b]))
+            C3[ma, ia, ib] = x[:na[a]]
+            C3[ma, ib, ia] = x[:na[a]].transpose(0, 2, 1)
+            C3[mb, ia, ib] = x[na[a]:]
+            C3[mb, ib, ia] = x[na[a]:].transpose(0, 2, 1)
+            C[lay.c_off[p]:lay.c_off[p + 1]] = x.ravel()
+            v = rng.normal(size=(na[a], na[b]))
+            Vd[ma, mb] = v
+            Vd[mb, ma] = v.T
+        V[lay.v_off[p]:lay.v_off[p + 1]] = v.ravel()
+    if d_rank1 is None:
+        Dd = rng.normal(size=(n, n))
+        Dd = Dd + Dd.T
+    else:
+        v, w = d_rank1
+        Dd = np.outer(v, w)
+    inp = synth.Inputs(sysm, lay, C, V, Dd.ravel().copy())
+    return inp, C3, Vd, Dd
+
+
+# ----------------------------------------------------------------------------
+# pins
+
+
+def pin_rank1_closed_form(route="4index", seed=1):
+    """D = v w^T  =>  K = U V W^T with U[:, mu] = C^mu v, W[:, nu] = C^nu w;
+    for w = v:  E_x = -1/4 q^T V q with q_mu = v^T C^mu v."""
+    sysm = synth.water_cluster(2, seed)
+    nb, *_ = _offsets(sysm)
+    rng = np.random.default_rng(seed + 100)
+    n = int(nb.sum())
+    v, w = rng.normal(size=n), rng.normal(size=n)
+    inp, C3, Vd, _ = random_problem(sysm, seed, d_rank1=(v, w))
+    U = np.einsum("mij,j->im", C3, v)
+    W = np.einsum("mij,j->im", C3, w)
+    K_closed = U @ Vd @ W.T
+    K = _route(inp, route)
+    ok1 = rel(K, K_closed) < TOL
+    inp2, C3, Vd, Dd = random_problem(sysm, seed, d_rank1=(v, v))
+    q = np.einsum("i,mij,j->m", v, C3, v)
+    E_closed = -0.25 * q @ Vd @ q
+    E = O.exchange_energy(_route(inp2, route), Dd)
+    ok2 = abs(E - E_closed) <= TOL * abs(E_closed)
+    return ok1 and ok2, f"K rel {rel(K, K_closed):.2e}  E {E:.6e} vs {E_closed:.6e}"
+
+
+def _route(inp, route):
+    if route == "4index":
+        return O.k_4index(inp)[0]
+    if route == "eigen":
+        return O.k_eigen(inp)
+    if route == "rows":
+        return O.k_full_rows(inp)
+    raise ValueError(route)
+
+
+def pin_brute_force(seed=2, n_entries=12):
+    """K_ik by explicit loops over j, l, mu, nu on a two-hydrogen system."""
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.7]])
+    sysm = synth.System(np.array([synth.H, synth.H]), pos, 6.0, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    K = O.k_4index(inp)[0]
+    Kr = O.k_full_rows(inp)
+    rng = np.random.default_rng(seed)
+    n, naux = Dd.shape[0], Vd.shape[0]
+    worst = 0.0
+    for _ in range(n_entries):
+        i, k = (int(x) for x in rng.integers(0, n, 2))
+        s = 0.0
+        for j in range(n):
+            for l in range(n):
+                for mu in range(naux):
+                    cij = C3[mu, i, j]
+                    if cij == 0.0:
+                        continue
+                    for nu in range(naux):
+                        s += cij * Vd[mu, nu] * C3[nu, k, l] * Dd[j, l]
+        worst = max(worst, abs(K[i, k] - s) / max(abs(s), 1e-12), abs(Kr[i, k] - s) / max(abs(s), 1e-12))
+    return worst < 1e-12, f"worst rel {worst:.2e}"
+
+
+def pin_invariants(route="4index", seed=3):
+    """K = K^T for symmetric D; K linear in D; D = 0 gives K = 0."""
+    sysm = synth.water_cluster(2, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    K1 = _route(inp, route)
+    sym = rel(K1, K1.T)
+    rng = np.random.default_rng(seed)
+    D2 = rng.normal(size=Dd.shape)
+    D2 = D2 + D2.T
+    a, b = 0.7, -1.3
+    inp2 = synth.Inputs(sysm, inp.layout, inp.C, inp.V, D2.ravel().copy())
+    inp3 = synth.Inputs(sysm, inp.layout, inp.C, inp.V, (a * Dd + b * D2).ravel())
+    K2, K3 = _route(inp2, route), _route(inp3, route)
+    lin = rel(K3, a * K1 + b * K2)
+    inp0 = synth.Inputs(sysm, inp.layout, inp.C, inp.V, np.zeros_like(inp.D))
+    zero = float(np.abs(_route(inp0, route)).max())
+    ok = sym < TOL and lin < TOL and zero == 0.0
+    return ok, f"sym {sym:.1e} lin {lin:.1e} zero {zero}"
+
+
+def pin_permutation(route="rows", seed=4):
+    """Reordering the atoms permutes K the same way (generator keyed by label)."""
+    sysm = synth.water_cluster(3, seed)
+    inp = synth.make_inputs(sysm)
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(sysm.n_atoms)
+    sp = synth.permuted(sysm, perm)
+    inp_p = synth.make_inputs(sp)
+    K = _route(inp, route)
+    Kp = _route(inp_p, route)
+    nb = synth.N_BASIS[sysm.species]
+    bo = np.concatenate([[0], np.cumsum(nb)])
+    bidx = np.concatenate([np.arange(bo[a], bo[a + 1]) for a in perm])
+    r = rel(Kp, K[np.ix_(bidx, bidx)])
+    return r < TOL, f"perm rel {r:.1e}"
+
+
+def pin_energy_direct(seed=5):
+    """E_x from K equals E_x contracted directly from (ij|kl) with D (x) D."""
+    sysm = synth.water_cluster(2, seed)
+    inp, *_ = random_problem(sysm, seed)
+    K, e1, e2 = O.k_4index(inp)
+    return abs(e1 - e2) <= TOL * abs(e1), f"{e1:.12e} vs {e2:.12e}"
+
+
+def pin_routes_agree(seed=6):
+    """The 4-index, eigen and row routes give the same K."""
+    sysm = synth.water_cluster(2, seed)
+    inp, *_ = random_problem(sysm, seed)
+    K4 = O.k_4index(inp)[0]
+    r1, r2 = rel(K4, O.k_eigen(inp)), rel(K4, O.k_full_rows(inp))
+    return max(r1, r2) < TOL, f"eigen {r1:.1e} rows {r2:.1e}"
+
+
+def paper_regrouped_X(C3, Vd, Dd, aux_atom, bas_atom):
+    """The paper's pair-grouped exchange with intermediates E, F, G, H at R = 0
+    (Eq. ri_lvl_exchange_matrix with Eq. temp, Sec. "Description of the
+    real-space formalism"), with on-site coefficient blocks counted once by
+    halving them in the row-owned part M (the paper is silent on this)."""
+    naux, n, _ = C3.shape
+    own = aux_atom[:, None] == bas_atom[None, :]            # mu on atom of i
+    M = C3 * own[:, :, None]                                 # rows of C^mu on A(mu)
+    onsite = own[:, :, None] & own[:, None, :]
+    M = np.where(onsite, 0.5 * C3, M)
+    # E^nu_{jk} = sum_l C^nu_{jl} D_{kl}, nu on the atom of j
+    E = np.einsum("njl,kl->njk", M, Dd)
+    # F^nu_{ik} = sum_{mu on A(i)} C^mu_{ik} V_{mu nu}
+    F = np.einsum("mik,mn->nik", M, Vd)
+    # G^nu_{il} = sum_{mu on A(i)} E^mu_{il} V_{mu nu}
+    G = np.einsum("mil,mn->nil", E, Vd)
+    # H^nu_{il} = sum_k F^nu_{ki} D_{kl}
+    H = np.einsum("nki,kl->nil", F, Dd)
+    # X_ij = sum_{k, nu on A(j)} F^nu_ik E^nu_jk + sum_{l, nu on A(l)} (2G + H)^nu_il C^nu_lj
+    X = np.einsum("nik,njk->ij", F, E) + np.einsum("nil,nlj->ij", 2.0 * G + H, M)
+    return X
+
+
+def pin_paper_regrouping(seed=7):
+    """The symmetric part of the paper's regrouped X equals K."""
+    sysm = synth.water_cluster(2, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    nb, na, *_ = _offsets(sysm)
+    aux_atom = np.repeat(np.arange(sysm.n_atoms), na)
+    bas_atom = np.repeat(np.arange(sysm.n_atoms), nb)
+    X = paper_regrouped_X(C3, Vd, Dd, aux_atom, bas_atom)
+    K = O.k_4index(inp)[0]
+    r = rel(0.5 * (X + X.T), K)
+    return r < TOL, f"sym(X) vs K rel {r:.1e}"
+
+
+# ----------------------------------------------------------------------------
+# gradient pins
+
+
+def _grads(seed):
+    sysm = synth.water_cluster(2, seed)
+    inp = synth.make_inputs(sysm)
+    return sysm, inp, O.gradients(inp)
+
+
+def pin_euler(seed=8):
+    """E is homogeneous of degree 2 in C and D and degree 1 in V."""
+    sysm, inp, g = _grads(seed)
+    E = g["E"]
+    Dd = g["blk"].D
+    eC = float(g["dC"] @ inp.C) / (2 * E) - 1
+    eV = float(g["dV"] @ inp.V) / E - 1
+    eD = float(np.sum(g["dD"] * Dd)) / (2 * E) - 1
+    ok = max(abs(eC), abs(eV), abs(eD)) < 1e-12
+    return ok, f"C {eC:.1e} V {eV:.1e} D {eD:.1e}"
+
+
+def _energy(inp):
+    return O.exchange_energy(O.k_eigen(inp), O.Blocks(inp).D)
+
+
+def pin_fd_params(seed=9, h=1e-4, n_entries=6):
+    """Central differences of E_x in stored C, V entries and symmetric D pairs."""
+    sysm, inp, g = _grads(seed)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for arr_name in ("C", "V"):
+        arr = getattr(inp, arr_name)
+        grad = g["d" + arr_name]
+        for idx in rng.integers(0, arr.size, n_entries):
+            a0 = arr[idx]
+            arr[idx] = a0 + h
+            ep = _energy(inp)
+            arr[idx] = a0 - h
+            em = _energy(inp)
+            arr[idx] = a0
+            fd = (ep - em) / (2 * h)
+            worst = max(worst, abs(fd - grad[idx]) / max(abs(grad[idx]), 1e-3))
+    n = int(math.isqrt(inp.D.size))
+    Dm = inp.D.reshape(n, n)
+    for _ in range(n_entries):
+        i, k = (int(x) for x in rng.integers(0, n, 2))
+        d0 = Dm[i, k]
+        for s in (+1, -1):
+            Dm[i, k] = d0 + s * h
+            Dm[k, i] = d0 + s * h
+            if s > 0:
+                ep = _energy(inp)
+            else:
+                em = _energy(inp)
+        Dm[i, k] = d0
+        Dm[k, i] = d0
+        fd = (ep - em) / (2 * h)
+        an = g["dD"][i, k] * (1 if i == k else 2)
+        worst = max(worst, abs(fd - an) / max(abs(an), 1e-3))
+    return worst < 1e-6, f"worst rel {worst:.1e}"
+
+
+def pin_dD_is_minus_half_K(seed=10):
+    """dE/dD = -1/2 K, checked by central differences along a random symmetric direction."""
+    sysm, inp, g = _grads(seed)
+    n = int(math.isqrt(inp.D.size))
+    rng = np.random.default_rng(seed)
+    Z = rng.normal(size=(n, n))
+    Z = Z + Z.T
+    D0 = inp.D.copy()
+    h = 1e-5
+    inp.D[:] = (D0.reshape(n, n) + h * Z).ravel()
+    ep = _energy(inp)
+    inp.D[:] = (D0.reshape(n, n) - h * Z).ravel()
+    em = _energy(inp)
+    inp.D[:] = D0
+    fd = (ep - em) / (2 * h)
+    an = float(np.sum(-0.5 * g["K"] * Z))
+    return abs(fd - an) < 1e-7 * abs(an), f"fd {fd:.10e} an {an:.10e}"
+
+
+def pin_force_invariants(seed=11):
+    """Forces from distance-only dependence: sum F = 0, sum R x F = 0."""
+    sysm, inp, g = _grads(seed)
+    F = O.forces(inp, g)
+    scale = np.abs(F).max()
+    t = np.abs(F.sum(0)).max() / scale
+    tq = np.abs(np.cross(sysm.pos, F).sum(0)).max() / scale
+    return max(t, tq) < 1e-12, f"sumF {t:.1e} torque {tq:.1e}"
+
+
+def inputs_at(sysm, layout, D_fixed, pos):
+    s2 = synth.System(sysm.species, pos, sysm.r_cut, sysm.seed, labels=sysm.labels)
+    inp = synth.make_inputs(s2, layout)
+    inp.D[:] = D_fixed
+    return inp
+
+
+def pin_fd_forces(seed=12, h=1e-4, n_checks=4):
+    """Central differences (step 1e-4 A) of E_x in atom positions; pair lists
+    frozen at the reference geometry, D held fixed."""
+    sysm, inp, g = _grads(seed)
+    F = O.forces(inp, g)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(n_checks):
+        A, x = int(rng.integers(0, sysm.n_atoms)), int(rng.integers(0, 3))
+        pp, pm = sysm.pos.copy(), sysm.pos.copy()
+        pp[A, x] += h
+        pm[A, x] -= h
+        ep = _energy(inputs_at(sysm, inp.layout, inp.D, pp))
+        em = _energy(inputs_at(sysm, inp.layout, inp.D, pm))
+        fd = -(ep - em) / (2 * h)
+        worst = max(worst, abs(fd - F[A, x]) / max(abs(F[A, x]), 1e-2))
+    return worst < 1e-6, f"worst rel {worst:.1e}"
+
+
+def pin_screening(seed=13):
+    """Pair screening equals an explicit loop over all atom pairs."""
+    ok = True
+    for sysm in (synth.config(1), synth.cluster_batch(3, n_min=8, n_max=30)):
+        pa, pb = O.screened_pairs(sysm.pos, sysm.r_cut, sysm.sys_off)
+        got = set(zip(pa.tolist(), pb.tolist()))
+        want = set()
+        rc2 = sysm.r_cut * sysm.r_cut
+        for s in range(sysm.n_systems):
+            lo, hi = int(sysm.sys_off[s]), int(sysm.sys_off[s + 1])
+            for a in range(lo, hi):
+                for b in range(a, hi):
+                    dx, dy, dz = (float(sysm.pos[a, c] - sysm.pos[b, c]) for c in range(3))
+                    if (dx * dx + dy * dy) + dz * dz <= rc2:
+                        want.add((a, b))
+        ok = ok and got == want and len(want) < (sysm.n_atoms * (sysm.n_atoms + 1)) // 2
+    return ok, "screened pair sets equal"
+
+
+ALL_PINS = {
+    "screening": pin_screening,
+    "rank1_4index": lambda: pin_rank1_closed_form("4index"),
+    "rank1_rows": lambda: pin_rank1_closed_form("rows"),
+    "brute_force": pin_brute_force,
+    "invariants_4index": lambda: pin_invariants("4index"),
+    "invariants_rows": lambda: pin_invariants("rows"),
+    "invariants_eigen": lambda: pin_invariants("eigen"),
+    "permutation_rows": lambda: pin_permutation("rows"),
+    "permutation_4index": lambda: pin_permutation("4index"),
+    "energy_direct": pin_energy_direct,
+    "routes_agree": pin_routes_agree,
+    "paper_regrouping": pin_paper_regrouping,
+    "euler": pin_euler,
+    "fd_params": pin_fd_params,
+    "dD_minus_half_K": pin_dD_is_minus_half_K,
+    "force_invariants": pin_force_invariants,
+    "fd_forces": pin_fd_forces,
+}

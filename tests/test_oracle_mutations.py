@@ -1,0 +1,53 @@
+"""Plant plausible mistakes in a copy of the oracle and check that at least
+one pin catches each of them (the pins are strong enough to matter)."""
+import os
+import types
+
+import pytest
+
+from tests import pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "oracle", "exx_oracle.py")
+
+MUTATIONS = {
+    "no_mirror_of_C": ("C3[mu, ib, ia] = part.transpose(0, 2, 1)", "pass"),
+    "swapped_aux_owner": ("for owner, part in ((a, blk[:self.na[a]]), (b, blk[self.na[a]:])):",
+                          "for owner, part in ((b, blk[:self.na[a]]), (a, blk[self.na[a]:])):"),
+    "V_not_mirrored": ("Vd[mb, ma] = blk.T", "pass"),
+    "D_transposed_in_4index": ('K[i0:i1] = np.einsum("ijkl,jl->ik", eri, D, optimize=True)',
+                               'K[i0:i1] = np.einsum("ijkl,lj->ik", eri, D, optimize=True)'),
+    "energy_factor": ("return -0.25 * float(np.sum(K * D))", "return -0.5 * float(np.sum(K * D))"),
+    "onsite_dV_factor": ("vg = -0.25 * tau[ma, ma]", "vg = -0.5 * tau[ma, ma]"),
+    "offsite_dC_factor": ("g = np.concatenate([G[ma, ia, ib], G[mb, ia, ib]]) * 2.0",
+                          "g = np.concatenate([G[ma, ia, ib], G[mb, ia, ib]])"),
+    "force_V_sign": ("grads[\"sV\"][q] * (-2.0 / v_2s2) * d", "grads[\"sV\"][q] * (2.0 / v_2s2) * d"),
+    "rows_wrong_orientation": ('Ki[sq] += np.einsum("nkl,nk->l", part, yQ[:, sj])',
+                               'Ki[sq] += np.einsum("nkl,nl->k", part, yQ[:, sj])'),
+    "rows_missing_transpose_term": ('Ki[sj] += np.einsum("nkl,nk->l", part, yQ[:, sq])', "pass"),
+    "eigen_missing_lambda": ("Ul = U * lam[None, None, :]", "Ul = U"),
+    "screening_strict": ("a, b = np.nonzero(np.triu(r2 <= rc2))", "a, b = np.nonzero(np.triu(r2 < 0.81 * rc2))"),
+}
+
+
+def _mutant(old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique / missing: {old!r}"
+    mod = types.ModuleType("exx_oracle_mutant")
+    exec(compile(src.replace(old, new), "exx_oracle_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name, monkeypatch):
+    mod = _mutant(*MUTATIONS[name])
+    monkeypatch.setattr(pins, "O", mod)
+    failed = []
+    for pin_name, pin in pins.ALL_PINS.items():
+        try:
+            ok, _ = pin()
+        except Exception:
+            ok = False
+        if not ok:
+            failed.append(pin_name)
+    assert failed, f"mutation {name} was not caught by any pin"
