@@ -1,0 +1,165 @@
+/*
+ * exx.h -- C ABI of the MI355X RI-LVL exact-exchange library (libexx.so).
+ *
+ * The library evaluates the non-periodic (lattice vector R = 0) real-space
+ * exchange matrix of the localized resolution-of-identity method
+ * (Kokott et al., Sec. "Description of the real-space formalism",
+ * Eq. realspace_exchange at R = 0, with the RI-LVL pair restriction
+ * C^mu_ij = 0 unless the auxiliary function mu sits on the atom of i or j):
+ *
+ *     K_ik = sum_{j,l} sum_{mu,nu} C^mu_ij V_{mu nu} C^nu_kl D_jl
+ *     E_x  = -1/4 sum_{i,k} K_ik D_ik
+ *
+ * and the derivatives of E_x.  All floating-point arrays are IEEE binary64.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Atoms carry a species s; species s has n_basis[s] basis and n_aux[s]
+ * auxiliary functions.  Basis functions are numbered atom by atom inside each
+ * system (a batch holds several independent systems / clusters).
+ *
+ * Screening: atoms A, B form a pair when (dx*dx + dy*dy) + dz*dz <= r_cut^2
+ * (float64, no fused multiply-add), dx = x_A - x_B.  One cutoff is used for
+ * the blocks of C, V and D (RI-LVL pair restriction for C, distance-screened
+ * V, and the density-matrix pattern).  Pairs never cross systems.
+ *
+ * Canonical pairs are (A, B) with A <= B, in lexicographic order; their
+ * storage offsets are returned by exx_plan_pairs().
+ *
+ *   C (device, read-only): for pair (A, B), A < B, a block
+ *       [n_aux(A) + n_aux(B)][n_basis(A)][n_basis(B)]; rows m < n_aux(A) hold
+ *       C^mu_ij for mu = m-th aux of A, i on A, j on B; rows m >= n_aux(A)
+ *       hold mu = (m - n_aux(A))-th aux of B.  C^mu_ji = C^mu_ij is implied.
+ *       On-site pair (A, A): block [n_aux(A)][n_basis(A)][n_basis(A)] stored
+ *       in full; the library uses (C_ij + C_ji)/2, so it should be symmetric.
+ *   V (device, read-only): pair (A, B), a block [n_aux(A)][n_aux(B)] holding
+ *       V_{mu nu} = V_{nu mu}, mu on A, nu on B.  On-site blocks in full.
+ *   D, K (device): dense, row-major, symmetric, one n_s x n_s block per
+ *       system s (n_s = sum of n_basis over its atoms), blocks concatenated
+ *       in system order.  D entries of atom pairs beyond r_cut are not read
+ *       (treated as zero).
+ *
+ * Ownership: the caller owns every device array passed in; the plan owns its
+ * bookkeeping lists and workspace.  Output arrays are fully overwritten
+ * (never accumulated into).  Calls are asynchronous on the HIP stream given
+ * as `stream` (a hipStream_t, NULL = default stream); host outputs are
+ * written before the call returns.
+ *
+ * Errors: every int-returning entry point returns EXX_OK (0) or a negative
+ * code; exx_last_error() describes the last failure of the calling thread.
+ * Nothing aborts or throws across the ABI.
+ */
+#ifndef EXX_H
+#define EXX_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXX_OK            0
+#define EXX_EINVAL       -1   /* bad argument: null pointer, size, range */
+#define EXX_ENOMEM       -2   /* device or host allocation failed */
+#define EXX_EDEVICE      -3   /* HIP runtime error */
+#define EXX_ESTATE       -4   /* plan in the wrong state (e.g. host-only plan) */
+#define EXX_EUNSUPPORTED -5   /* option not implemented */
+
+/* arithmetic of the contraction stages */
+#define EXX_PREC_FP64     0   /* binary64 everywhere (FP64 MFMA + FP64 FMA) */
+#define EXX_PREC_FP32     1   /* binary32 operands and MFMA, binary32 accumulation */
+
+/* plan flags */
+#define EXX_PLAN_HOST_ONLY 1u /* build the lists on the host only; no device use */
+
+typedef struct exx_plan_s* exx_plan;
+
+typedef struct {
+    int32_t n_atoms;
+    int32_t n_species;
+    const int32_t* species;      /* host [n_atoms], values 0..n_species-1 */
+    const double* positions;     /* host [n_atoms][3], Angstrom */
+    const int32_t* n_basis;      /* host [n_species], 1..64 */
+    const int32_t* n_aux;        /* host [n_species], 1..256 */
+    double r_cut;                /* Angstrom, > 0 */
+    int32_t n_systems;           /* >= 1 */
+    const int32_t* sys_atom_off; /* host [n_systems + 1], increasing, first 0,
+                                    last n_atoms; may be NULL if n_systems == 1 */
+} exx_system;
+
+typedef struct {
+    int64_t n_atoms, n_systems, n_pairs;
+    int64_t c_size, v_size, d_size;     /* element counts of C, V, D (= K) */
+    int64_t n_basis_max;                /* largest system */
+    int64_t workspace_bytes;            /* device bytes held by the plan */
+    int64_t flops_fp64;                 /* algorithmic flops of one build_K */
+} exx_info;
+
+/* Build a plan for one geometry: screening, canonical pairs, neighbour
+ * lists and all task lists (atom-pair / atom-quartet block lists) of the
+ * exchange build.  The bookkeeping runs on the current HIP device unless
+ * flags has EXX_PLAN_HOST_ONLY.  The plan keeps copies of everything it needs
+ * from *sys.  Returns EXX_EINVAL for malformed systems.  Errors leave *out
+ * NULL. */
+int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out);
+
+/* Release the plan and its device memory (after work on it has finished). */
+int exx_plan_destroy(exx_plan plan);
+
+/* Sizes and counts of the plan (host struct written). */
+int exx_plan_info(exx_plan plan, exx_info* info);
+
+/* Canonical pair layout, written to caller-owned host arrays: pair_a and
+ * pair_b [n_pairs] (int32 atom indices), c_off and v_off [n_pairs + 1]
+ * (int64 element offsets of each pair's C and V block).  Any pointer may be
+ * NULL to skip that array. */
+int exx_plan_pairs(exx_plan plan, int32_t* pair_a, int32_t* pair_b,
+                   int64_t* c_off, int64_t* v_off);
+
+/* Neighbour lists as built on the device (for inspection and tests):
+ * nbr_ptr [n_atoms + 1], nbr_atom [nbr_ptr[n_atoms]], host arrays.  Pass
+ * nbr_atom = NULL to read nbr_ptr only (the total count). */
+int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom);
+
+/* The exchange matrix K (definition above) and, if Ex != NULL, the energies
+ * E_x of every system (device array [n_systems], binary64).
+ * C, V, D: device inputs in the layouts above.  K: device output, d_size
+ * doubles, exactly symmetric.  precision: EXX_PREC_*.
+ * Sizes are those of exx_plan_info().  Returns EXX_ESTATE for a host-only
+ * plan. */
+int build_K(exx_plan plan, const double* C, const double* V, const double* D,
+            int precision, double* K, double* Ex, void* stream);
+
+/* E_x = -1/4 sum_ik K_ik D_ik for every system (device Ex [n_systems]),
+ * a fixed-order binary64 reduction (bitwise reproducible). */
+int exchange_energy(exx_plan plan, const double* K, const double* D,
+                    double* Ex, void* stream);
+
+/* Gradients of the scaled energy gE * E_x (gE is dL/dE_x of the caller):
+ *   dD (device, d_size, dense, symmetric): dE/dD_ik = -1/2 K_ik, the
+ *       derivative with respect to each stored entry of the dense D;
+ *   dC (device, c_size): derivative per stored C entry (the two mirrored
+ *       uses of an off-site entry summed); on-site entries each counted once;
+ *   dV (device, v_size): per stored V entry, off-site blocks counting both
+ *       V_{mu nu} and V_{nu mu};
+ *   forces (device [n_atoms][3], may be NULL): -d(gE E_x)/dR for the
+ *       synthetic model C_AB ~ exp(-r_AB / c_decay), V_AB ~ exp(-r_AB^2 / v_2s2)
+ *       (on-site blocks position independent, D held fixed).
+ * Any of dC, dV, dD may be NULL to skip it. */
+int exchange_backward(exx_plan plan, const double* C, const double* V,
+                      const double* D, double gE, int precision,
+                      double* dC, double* dV, double* dD, double* forces,
+                      double c_decay, double v_2s2, void* stream);
+
+/* Algorithmic flop count of one stage of build_K (stage -1 = total):
+ * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction. */
+int64_t exx_plan_flops(exx_plan plan, int stage);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* exx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXX_H */

@@ -1,0 +1,176 @@
+"""ctypes binding of libexx.so: argument marshalling only.
+
+Device arrays are passed as raw pointers (torch tensors supply them through
+``data_ptr()``), the HIP stream as ``torch.cuda.current_stream().cuda_stream``.
+Every step of the computation runs in the library's kernels; if the library
+is missing the import fails loudly (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libexx.so")
+
+EXX_OK, EXX_EINVAL, EXX_ENOMEM, EXX_EDEVICE, EXX_ESTATE, EXX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PREC_FP64, PREC_FP32 = 0, 1
+PLAN_HOST_ONLY = 1
+
+_lib = None
+
+
+class ExxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libexx error {code}: {msg}")
+        self.code = code
+
+
+class _System(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int32),
+        ("n_species", ctypes.c_int32),
+        ("species", ctypes.POINTER(ctypes.c_int32)),
+        ("positions", ctypes.POINTER(ctypes.c_double)),
+        ("n_basis", ctypes.POINTER(ctypes.c_int32)),
+        ("n_aux", ctypes.POINTER(ctypes.c_int32)),
+        ("r_cut", ctypes.c_double),
+        ("n_systems", ctypes.c_int32),
+        ("sys_atom_off", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n_atoms", "n_systems", "n_pairs", "c_size", "v_size", "d_size",
+        "n_basis_max", "workspace_bytes", "flops_fp64")]
+
+
+EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pairs",
+           "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
+           "exx_plan_flops", "exx_last_error")
+
+
+def lib():
+    """Load libexx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2403_10343_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.exx_plan_create.argtypes = [ctypes.POINTER(_System), ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.exx_plan_destroy.argtypes = [vp]
+    L.exx_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.exx_plan_pairs.argtypes = [vp, vp, vp, vp, vp]
+    L.exx_plan_neighbors.argtypes = [vp, vp, vp]
+    L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
+    L.exchange_backward.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exx_plan_flops.argtypes = [vp, ctypes.c_int]
+    L.exx_plan_flops.restype = i64
+    L.exx_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("exx_plan_flops", "exx_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != EXX_OK:
+        raise ExxError(rc, lib().exx_last_error().decode())
+
+
+def _ptr(x):
+    """Raw device/host pointer of a torch tensor (or None)."""
+    if x is None:
+        return None
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Plan:
+    """An exchange plan for one geometry (owns the device task lists)."""
+
+    def __init__(self, species, positions, n_basis, n_aux, r_cut, sys_atom_off=None, host_only=False):
+        species = np.ascontiguousarray(species, dtype=np.int32)
+        positions = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        n_basis = np.ascontiguousarray(n_basis, dtype=np.int32)
+        n_aux = np.ascontiguousarray(n_aux, dtype=np.int32)
+        n_sys = 1 if sys_atom_off is None else len(sys_atom_off) - 1
+        off = None if sys_atom_off is None else np.ascontiguousarray(sys_atom_off, dtype=np.int32)
+        i32p, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+        s = _System(len(species), len(n_basis), species.ctypes.data_as(i32p),
+                    positions.ctypes.data_as(dp), n_basis.ctypes.data_as(i32p),
+                    n_aux.ctypes.data_as(i32p), float(r_cut), n_sys,
+                    off.ctypes.data_as(i32p) if off is not None else None)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib().exx_plan_create(ctypes.byref(s), PLAN_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        self._h = h
+        self.n_atoms = len(species)
+        self.n_systems = n_sys
+        self.info = self._info()
+
+    @classmethod
+    def for_system(cls, system, host_only=False):
+        """Plan for a ``synth.System``-like object (species, pos, r_cut, sys_off)."""
+        from synth.water import N_AUX, N_BASIS
+        return cls(system.species, system.pos, N_BASIS, N_AUX, system.r_cut,
+                   system.sys_off if system.n_systems > 1 else None, host_only)
+
+    def _info(self):
+        inf = _Info()
+        _check(lib().exx_plan_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def pairs(self):
+        n = self.info["n_pairs"]
+        pa, pb = np.empty(n, np.int32), np.empty(n, np.int32)
+        co, vo = np.empty(n + 1, np.int64), np.empty(n + 1, np.int64)
+        _check(lib().exx_plan_pairs(self._h, pa.ctypes.data, pb.ctypes.data, co.ctypes.data, vo.ctypes.data))
+        return pa, pb, co, vo
+
+    def neighbors(self):
+        ptr = np.empty(self.n_atoms + 1, np.int32)
+        _check(lib().exx_plan_neighbors(self._h, ptr.ctypes.data, None))
+        atoms = np.empty(int(ptr[-1]), np.int32)
+        _check(lib().exx_plan_neighbors(self._h, ptr.ctypes.data, atoms.ctypes.data))
+        return ptr, atoms
+
+    def flops(self, stage=-1):
+        return int(lib().exx_plan_flops(self._h, stage))
+
+    def build_K(self, C, V, D, K, Ex=None, precision=PREC_FP64, stream=None):
+        _check(lib().build_K(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
+                             _stream(stream)))
+
+    def exchange_energy(self, K, D, Ex, stream=None):
+        _check(lib().exchange_energy(self._h, _ptr(K), _ptr(D), _ptr(Ex), _stream(stream)))
+
+    def exchange_backward(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
+                          precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None):
+        _check(lib().exchange_backward(self._h, _ptr(C), _ptr(V), _ptr(D), float(gE), int(precision),
+                                       _ptr(dC), _ptr(dV), _ptr(dD), _ptr(forces),
+                                       float(c_decay), float(v_2s2), _stream(stream)))
+
+    def close(self):
+        if self._h is not None:
+            lib().exx_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

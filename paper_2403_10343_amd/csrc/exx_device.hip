@@ -1,0 +1,731 @@
+// libexx: RI-LVL exact-exchange build on MI355X (gfx950).
+//
+// Evaluates K_ik = sum_{jl} sum_{mu nu} C^mu_ij V_{mu nu} C^nu_kl D_jl for
+// non-periodic systems (lattice vector R = 0 of Eq. realspace_exchange) and
+// E_x = -1/4 sum K_ik D_ik.  Writing C^mu = M^mu + M^mu^T with M^mu the rows
+// of C^mu on the atom of mu (on-site block halved), the sum splits into the
+// terms of the paper's pair-grouped form (Eq. ri_lvl_exchange_matrix with the
+// intermediates of Eq. temp):
+//   T2 = sum V M^mu D M^nu^T      (the F*E term)
+//   T1 = sum V M^mu D M^nu        (the G term)
+//   T3 = sum V M^mu^T D M^nu      (the H term)
+//   K  = T2 + T3 + T1 + T1^T.
+// The paper's form carries 2G and is symmetrised here: with
+// H'_P = sum_Q (V_PQ (x) D_PQ) T_Q + 2 G, the product X = T^T H' equals
+// T3 + 2 T1^T and K = T2 + (X + X^T) / 2.
+//
+// Kernels (one wavefront per task, four tasks per workgroup):
+//   k_repack  C pair blocks -> row-owned T_P
+//   k_E       E_P = T_P D over N2[P]           (FP64 MFMA 16x16x4)
+//   k_H       H'_P: F = V T_Q (MFMA), D contraction (FMA), G part (MFMA)
+//   k_T2      T2 pair blocks into K            (MFMA, two chained stages)
+//   k_final   K = T2 + sym(T^T H'), owner-computes, atomic-free
+//   k_energy  E_x per system, fixed-order reduction
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/exx.h"
+#include "exx_internal.h"
+
+using namespace exx;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4_f64: lane L supplies A[L%16][L/16] and B[L/16][L%16];
+// accumulator element v of lane L is C[L/16 + 4v][L%16].
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                          \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess)                                                      \
+      return fail(_e == hipErrorOutOfMemory ? EXX_ENOMEM : EXX_EDEVICE,        \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device-side plan
+
+struct DevPlan {
+  int n_atoms, n_sys;
+  int *nb, *na, *atom_sys, *bo;
+  int64_t *sys_n, *sys_d_off;
+  int *nbr_ptr, *nbr_atom, *nbr_pair, *nbr_lcol, *nbr_owner;
+  int *pair_a, *pair_b;
+  int64_t *c_off, *v_off;
+  int *n_loc, *m_loc;
+  int64_t *map_off, *col1g_off, *col2g_off;
+  int *map1, *map2, *col1g, *col2g;
+  int64_t *t_off, *e_off;
+  EItem* e_items;
+  int *ct_run_ptr, *ct_klen;
+  Run* runs;
+  HItem* h_items;
+  int *hc_q_ptr, *hc_q, *hc_x_ptr, *hc_x;
+  int* t2_items;
+  FItem* f_items;
+  int* f_plist;
+  int *en_sys, *en_beg, *en_end;
+  double *T, *E, *H, *epart;
+};
+
+struct exx_plan_s {
+  HostPlan hp;
+  bool host_only = false;
+  int device = -1;
+  DevPlan d{};
+  std::vector<void*> allocs;
+  int64_t dev_bytes = 0;
+};
+
+template <typename X>
+static int upload(exx_plan_s* p, X*& dst, const std::vector<X>& src) {
+  dst = nullptr;
+  if (src.empty()) return 0;
+  size_t bytes = src.size() * sizeof(X);
+  HIP_TRY(hipMalloc((void**)&dst, bytes));
+  p->allocs.push_back(dst);
+  p->dev_bytes += bytes;
+  HIP_TRY(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
+  return 0;
+}
+
+static int alloc_buf(exx_plan_s* p, double*& dst, int64_t n) {
+  dst = nullptr;
+  if (n <= 0) return 0;
+  HIP_TRY(hipMalloc((void**)&dst, n * sizeof(double)));
+  p->allocs.push_back(dst);
+  p->dev_bytes += n * sizeof(double);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// screening on the device: one workgroup per atom A, all B of its system in
+// chunks of 256, ordered compaction by a workgroup prefix sum.
+
+__device__ __forceinline__ bool within_cut(const double* pos, int a, int b, double rc2) {
+  double dx = __dsub_rn(pos[3 * a], pos[3 * b]);
+  double dy = __dsub_rn(pos[3 * a + 1], pos[3 * b + 1]);
+  double dz = __dsub_rn(pos[3 * a + 2], pos[3 * b + 2]);
+  double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  return r2 <= rc2;
+}
+
+__global__ __launch_bounds__(256) void k_nbr_count(const double* pos, const int* atom_sys,
+                                                   const int* sys_atom_off, double rc2, int* count) {
+  const int a = blockIdx.x;
+  const int s = atom_sys[a];
+  const int lo = sys_atom_off[s], hi = sys_atom_off[s + 1];
+  __shared__ int part[256];
+  int c = 0;
+  for (int b = lo + threadIdx.x; b < hi; b += 256) c += within_cut(pos, a, b, rc2) ? 1 : 0;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[a] = part[0];
+}
+
+__global__ __launch_bounds__(256) void k_nbr_fill(const double* pos, const int* atom_sys,
+                                                  const int* sys_atom_off, double rc2,
+                                                  const int* ptr, int* out) {
+  const int a = blockIdx.x;
+  const int s = atom_sys[a];
+  const int lo = sys_atom_off[s], hi = sys_atom_off[s + 1];
+  __shared__ int scan[256];
+  int base = ptr[a];
+  for (int b0 = lo; b0 < hi; b0 += 256) {
+    const int b = b0 + threadIdx.x;
+    const int f = (b < hi && within_cut(pos, a, b, rc2)) ? 1 : 0;
+    scan[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {  // inclusive Hillis-Steele scan
+      int v = (threadIdx.x >= w) ? scan[threadIdx.x - w] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (f) out[base + scan[threadIdx.x] - 1] = b;
+    base += scan[255];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 0: row-owned coefficients T_P from the canonical C pair blocks.
+// One workgroup per neighbour entry (P, J): the s_P x n_basis(J) sub-block.
+
+__global__ __launch_bounds__(256) void k_repack(const double* __restrict__ C, DevPlan d) {
+  const int k = blockIdx.x;
+  const int P = d.nbr_owner[k], J = d.nbr_atom[k], p = d.nbr_pair[k];
+  const int aP = d.na[P], bP = d.nb[P], bJ = d.nb[J], aJ = d.na[J];
+  const int nP = d.n_loc[P], lc = d.nbr_lcol[k];
+  const int sP = aP * bP;
+  const double* Cp = C + d.c_off[p];
+  double* TP = d.T + d.t_off[P];
+  const int nel = sP * bJ;
+  for (int e = threadIdx.x; e < nel; e += 256) {
+    const int r = e / bJ, j = e - r * bJ;
+    const int mu = r / bP, i = r - mu * bP;
+    double v;
+    if (P < J)
+      v = Cp[(size_t)(mu * bP + i) * bJ + j];
+    else if (P > J)
+      v = Cp[(size_t)((aJ + mu) * bJ + j) * bP + i];
+    else
+      v = 0.5 * Cp[(size_t)(mu * bP + i) * bP + j];
+    TP[(size_t)r * nP + lc + j] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 1: E_P = T_P D, 32 x 32 output per wavefront, k over runs of relevant
+// neighbours (block-sparse D).
+
+__global__ __launch_bounds__(256) void k_E(const double* __restrict__ D, DevPlan d, int n_items) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= n_items) return;
+  const int L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const EItem it = d.e_items[w];
+  const int P = it.P;
+  const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
+  const int s = d.atom_sys[P];
+  const int64_t ns = d.sys_n[s];
+  const double* Ds = D + d.sys_d_off[s];
+  const double* TP = d.T + d.t_off[P];
+  int gc[2];
+  for (int h = 0; h < 2; ++h) {
+    const int c = it.c0 + 16 * h + lr;
+    gc[h] = (c < mP) ? d.col2g[d.col2g_off[P] + c] : -1;
+  }
+  const int row0 = it.r0 + lr, row1 = it.r0 + 16 + lr;
+  const bool rv0 = row0 < sP, rv1 = row1 < sP;
+  d4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  const int rb = d.ct_run_ptr[it.ct], re = d.ct_run_ptr[it.ct + 1];
+  const int klen = d.ct_klen[it.ct];
+  int r = rb, rstart = 0;
+  for (int kb = 0; kb < klen; kb += 4) {
+    while (kb >= rstart + d.runs[r].len) { rstart += d.runs[r].len; ++r; }
+    const int kk = kb + lk;
+    const bool kv = kk < klen;
+    int lc = 0, gr = 0;
+    if (kv) {
+      int rr = r, off = kk - rstart;
+      const Run R0 = d.runs[r];
+      if (off >= R0.len) { off -= R0.len; rr = r + 1; }
+      const Run R = (rr == r) ? R0 : d.runs[rr];
+      lc = R.lcol + off;
+      gr = R.grow + off;
+    }
+    (void)re;
+    const double a0 = (kv && rv0) ? TP[(size_t)row0 * nP + lc] : 0.0;
+    const double a1 = (kv && rv1) ? TP[(size_t)row1 * nP + lc] : 0.0;
+    const double b0 = (kv && gc[0] >= 0) ? Ds[(size_t)gr * ns + gc[0]] : 0.0;
+    const double b1 = (kv && gc[1] >= 0) ? Ds[(size_t)gr * ns + gc[1]] : 0.0;
+    acc[0][0] = mfma64(a0, b0, acc[0][0]);
+    acc[0][1] = mfma64(a0, b1, acc[0][1]);
+    acc[1][0] = mfma64(a1, b0, acc[1][0]);
+    acc[1][1] = mfma64(a1, b1, acc[1][1]);
+  }
+  double* EP = d.E + d.e_off[P];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int col = it.c0 + 16 * y + lr;
+      if (col >= mP) continue;
+      for (int v = 0; v < 4; ++v) {
+        const int row = it.r0 + 16 * x + lk + 4 * v;
+        if (row < sP) EP[(size_t)row * mP + col] = acc[x][y][v];
+      }
+    }
+}
+
+// V_PQ[mu][nu] (mu on P, nu on Q) from the canonical V block of pair p.
+__device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP, int aQ, int mu, int nu) {
+  return (P <= Q) ? Vp[mu * aQ + nu] : Vp[nu * aP + mu];
+}
+
+// ---------------------------------------------------------------------------
+// stage 2: H'_P[(mu, j), c] for a 16-wide aux tile and a 16-wide column tile.
+//   F[mu, l, c] = sum_nu V_PQ[mu, nu] T_Q[(nu, l), c]           (MFMA)
+//   H[(mu, j), c] += sum_l D[j, l] F[mu, l, c]                  (FMA)
+//   H[(nu, l), c in X] += 2 sum_mu' V_XP[mu', nu] E_X[(mu', c), l]  (MFMA, G part)
+
+__global__ __launch_bounds__(256) void k_H(const double* __restrict__ V, const double* __restrict__ D,
+                                           DevPlan d, int n_items) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= n_items) return;
+  const int L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const HItem it = d.h_items[w];
+  const int P = it.P;
+  const int aP = d.na[P], bP = d.nb[P], mP = d.m_loc[P];
+  const int s = d.atom_sys[P];
+  const int64_t ns = d.sys_n[s];
+  const double* Ds = D + d.sys_d_off[s];
+  const int c = it.c0 + lr;
+  const bool cv = c < mP;
+  const int g = cv ? d.col2g[d.col2g_off[P] + c] : -1;
+  const int muA = it.mu0 + lr;  // A-operand row (aux of P)
+  const bool muv = muA < aP;
+  d4 H[NB_MAX];
+#pragma unroll
+  for (int j = 0; j < NB_MAX; ++j) H[j] = d4{0, 0, 0, 0};
+
+  for (int qi = d.hc_q_ptr[it.hc]; qi < d.hc_q_ptr[it.hc + 1]; ++qi) {
+    const int k = d.hc_q[qi];
+    const int Q = d.nbr_atom[k], p = d.nbr_pair[k];
+    const int aQ = d.na[Q], bQ = d.nb[Q], nQ = d.n_loc[Q];
+    const double* Vp = V + d.v_off[p];
+    const double* TQ = d.T + d.t_off[Q];
+    const int lcQ = cv ? d.map1[d.map_off[Q] + g] : -1;
+    d4 F[NB_MAX];
+#pragma unroll
+    for (int l = 0; l < NB_MAX; ++l) F[l] = d4{0, 0, 0, 0};
+    for (int n0 = 0; n0 < aQ; n0 += 4) {
+      const int nu = n0 + lk;
+      const bool nv = nu < aQ;
+      const double a = (muv && nv) ? v_elem(Vp, P, Q, aP, aQ, muA, nu) : 0.0;
+      const bool bv = nv && lcQ >= 0;
+      const double* trow = TQ + (size_t)(nu * bQ) * nQ + lcQ;
+#pragma unroll
+      for (int l = 0; l < NB_MAX; ++l)
+        if (l < bQ) F[l] = mfma64(a, bv ? trow[(size_t)l * nQ] : 0.0, F[l]);
+    }
+    const double* Dp = Ds + (size_t)d.bo[P] * ns + d.bo[Q];
+#pragma unroll
+    for (int l = 0; l < NB_MAX; ++l) {
+      if (l >= bQ) break;
+#pragma unroll
+      for (int j = 0; j < NB_MAX; ++j) {
+        if (j >= bP) break;
+        const double dv = Dp[(size_t)j * ns + l];
+        H[j] += dv * F[l];
+      }
+    }
+  }
+  for (int xi = d.hc_x_ptr[it.hc]; xi < d.hc_x_ptr[it.hc + 1]; ++xi) {
+    const int k = d.hc_x[xi];
+    const int X = d.nbr_atom[k], p = d.nbr_pair[k];
+    const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X];
+    const double* Vp = V + d.v_off[p];
+    const double* EX = d.E + d.e_off[X];
+    const int* m2X = d.map2 + d.map_off[X];
+    const int iX = g - d.bo[X];
+    const bool xv = cv && iX >= 0 && iX < bX;
+    for (int k0 = 0; k0 < aX; k0 += 4) {
+      const int mu2 = k0 + lk;
+      const bool mv = mu2 < aX;
+      // A[nu][mu'] = 2 V_XP[mu'][nu] = 2 V_PX[nu][mu']
+      const double a = (muv && mv) ? 2.0 * v_elem(Vp, P, X, aP, aX, muA, mu2) : 0.0;
+      const double* erow = EX + (size_t)(mu2 * bX + iX) * mX;
+#pragma unroll
+      for (int l = 0; l < NB_MAX; ++l) {
+        if (l >= bP) break;
+        const int col = m2X[d.bo[P] + l];
+        H[l] = mfma64(a, (xv && mv) ? erow[col] : 0.0, H[l]);
+      }
+    }
+  }
+  double* HP = d.H + d.e_off[P];
+#pragma unroll
+  for (int j = 0; j < NB_MAX; ++j) {
+    if (j >= bP) break;
+    for (int v = 0; v < 4; ++v) {
+      const int mu = it.mu0 + lk + 4 * v;
+      if (mu < aP && cv) HP[(size_t)(mu * bP + j) * mP + c] = H[j][v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 3: T2[P, Q] = sum_{mu, l} E_P[(mu, i), l] F[mu, k, l],
+//          F[mu, k, l] = sum_nu V_PQ[mu, nu] T_Q[(nu, k), l], l over N[Q].
+// Stage-one accumulator element v is directly the stage-two B operand.
+
+__global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double* __restrict__ K,
+                                            DevPlan d, int n_items) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= n_items) return;
+  const int L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const int p = d.t2_items[w];
+  const int P = d.pair_a[p], Q = d.pair_b[p];
+  const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
+  const int nQ = d.n_loc[Q], mP = d.m_loc[P];
+  const int s = d.atom_sys[P];
+  const int64_t ns = d.sys_n[s];
+  const double* Vp = V + d.v_off[p];
+  const double* TQ = d.T + d.t_off[Q];
+  const double* EP = d.E + d.e_off[P];
+  const int* cg = d.col1g + d.col1g_off[Q];
+  const int* m2P = d.map2 + d.map_off[P];
+  d4 acc = d4{0, 0, 0, 0};
+  for (int l = 0; l < nQ; ++l) {
+    const int ce = m2P[cg[l]];
+    for (int mu0 = 0; mu0 < aP; mu0 += 16) {
+      d4 F = d4{0, 0, 0, 0};
+      const int muA = mu0 + lr;
+      for (int n0 = 0; n0 < aQ; n0 += 4) {
+        const int nu = n0 + lk;
+        const bool nv = nu < aQ;
+        const double a = (muA < aP && nv) ? v_elem(Vp, P, Q, aP, aQ, muA, nu) : 0.0;
+        const double b = (nv && lr < bQ) ? TQ[(size_t)(nu * bQ + lr) * nQ + l] : 0.0;
+        F = mfma64(a, b, F);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int mu = mu0 + 4 * v + lk;
+        const double a2 = (mu < aP && lr < bP) ? EP[(size_t)(mu * bP + lr) * mP + ce] : 0.0;
+        acc = mfma64(a2, F[v], acc);
+      }
+    }
+  }
+  double* Ks = K + d.sys_d_off[s];
+  const int bPo = d.bo[P], bQo = d.bo[Q];
+  for (int v = 0; v < 4; ++v) {
+    const int i = lk + 4 * v, k = lr;
+    if (i < bP && k < bQ) {
+      Ks[(size_t)(bPo + i) * ns + bQo + k] = acc[v];
+      if (P != Q) Ks[(size_t)(bQo + k) * ns + bPo + i] = acc[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 4: K = T2 + (X + X^T)/2 with X = sum_P T_P^T H'_P, 32 x 32 tile pairs
+// of the upper triangle, each written once together with its mirror.
+
+__global__ __launch_bounds__(256) void k_final(double* __restrict__ K, DevPlan d, int n_items) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= n_items) return;
+  const int L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const FItem it = d.f_items[w];
+  const int s = it.sys;
+  const int64_t ns = d.sys_n[s];
+  int gI[2], gL[2];
+  for (int h = 0; h < 2; ++h) {
+    gI[h] = it.gI0 + 16 * h + lr;
+    gL[h] = it.gL0 + 16 * h + lr;
+  }
+  d4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  for (int pi = it.pbeg; pi < it.pend; ++pi) {
+    const int P = d.f_plist[pi];
+    const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
+    const int* m1 = d.map1 + d.map_off[P];
+    const int* m2 = d.map2 + d.map_off[P];
+    const double* TP = d.T + d.t_off[P];
+    const double* HP = d.H + d.e_off[P];
+    int cI1[2], cI2[2], cL1[2], cL2[2];
+    for (int h = 0; h < 2; ++h) {
+      cI1[h] = gI[h] < ns ? m1[gI[h]] : -1;
+      cI2[h] = gI[h] < ns ? m2[gI[h]] : -1;
+      cL1[h] = gL[h] < ns ? m1[gL[h]] : -1;
+      cL2[h] = gL[h] < ns ? m2[gL[h]] : -1;
+    }
+    for (int r0 = 0; r0 < sP; r0 += 4) {
+      const int r = r0 + lk;
+      const bool rv = r < sP;
+      const double* Tr = TP + (size_t)r * nP;
+      const double* Hr = HP + (size_t)r * mP;
+      double aT[2], aH[2], bH[2], bT[2];
+      for (int h = 0; h < 2; ++h) {
+        aT[h] = (rv && cI1[h] >= 0) ? Tr[cI1[h]] : 0.0;
+        aH[h] = (rv && cI2[h] >= 0) ? Hr[cI2[h]] : 0.0;
+        bH[h] = (rv && cL2[h] >= 0) ? Hr[cL2[h]] : 0.0;
+        bT[h] = (rv && cL1[h] >= 0) ? Tr[cL1[h]] : 0.0;
+      }
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+          acc[x][y] = mfma64(aT[x], bH[y], acc[x][y]);
+          acc[x][y] = mfma64(aH[x], bT[y], acc[x][y]);
+        }
+    }
+  }
+  double* Ks = K + d.sys_d_off[s];
+  const bool diag = it.gI0 == it.gL0;
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      for (int v = 0; v < 4; ++v) {
+        const int i = it.gI0 + 16 * x + lk + 4 * v;
+        const int l = it.gL0 + 16 * y + lr;
+        if (i >= ns || l >= ns) continue;
+        if (diag && i > l) continue;
+        const double val = Ks[(size_t)i * ns + l] + 0.5 * acc[x][y][v];
+        Ks[(size_t)i * ns + l] = val;
+        if (i != l) Ks[(size_t)l * ns + i] = val;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// energy: per-chunk tree reduction, then per-system ordered sum.
+
+__global__ __launch_bounds__(256) void k_energy_part(const double* K, const double* D, DevPlan d,
+                                                     int n_chunks) {
+  const int c = blockIdx.x;
+  if (c >= n_chunks) return;
+  const int s = d.en_sys[c];
+  const int64_t base = d.sys_d_off[s];
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int e = d.en_beg[c] + threadIdx.x; e < d.en_end[c]; e += 256) acc += K[base + e] * D[base + e];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.epart[c] = part[0];
+}
+
+__global__ void k_energy_sum(double* Ex, DevPlan d, int n_chunks) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n_sys) return;
+  double acc = 0.0;
+  for (int c = 0; c < n_chunks; ++c)
+    if (d.en_sys[c] == s) acc += d.epart[c];
+  Ex[s] = -0.25 * acc;
+}
+
+__global__ void k_zero(double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// plan creation
+
+static int device_neighbors(exx_plan_s* pl) {
+  HostPlan& hp = pl->hp;
+  double* dpos = nullptr;
+  int *dsys = nullptr, *doff = nullptr, *dcnt = nullptr, *dptr = nullptr, *dout = nullptr;
+  auto cleanup = [&]() {
+    hipFree(dpos); hipFree(dsys); hipFree(doff); hipFree(dcnt); hipFree(dptr); hipFree(dout);
+  };
+  const int NA = hp.n_atoms;
+  hipError_t e = hipSuccess;
+#define NB_TRY(x) do { e = (x); if (e != hipSuccess) { cleanup(); return fail(EXX_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e)); } } while (0)
+  NB_TRY(hipMalloc((void**)&dpos, sizeof(double) * 3 * NA));
+  NB_TRY(hipMalloc((void**)&dsys, sizeof(int) * NA));
+  NB_TRY(hipMalloc((void**)&doff, sizeof(int) * (hp.n_sys + 1)));
+  NB_TRY(hipMalloc((void**)&dcnt, sizeof(int) * NA));
+  NB_TRY(hipMemcpy(dpos, hp.pos.data(), sizeof(double) * 3 * NA, hipMemcpyHostToDevice));
+  NB_TRY(hipMemcpy(dsys, hp.atom_sys.data(), sizeof(int) * NA, hipMemcpyHostToDevice));
+  NB_TRY(hipMemcpy(doff, hp.sys_atom_off.data(), sizeof(int) * (hp.n_sys + 1), hipMemcpyHostToDevice));
+  const double rc2 = hp.r_cut * hp.r_cut;
+  hipLaunchKernelGGL(k_nbr_count, dim3(NA), dim3(256), 0, 0, dpos, dsys, doff, rc2, dcnt);
+  NB_TRY(hipGetLastError());
+  std::vector<int> cnt(NA);
+  NB_TRY(hipMemcpy(cnt.data(), dcnt, sizeof(int) * NA, hipMemcpyDeviceToHost));
+  hp.nbr_ptr.assign(NA + 1, 0);
+  for (int a = 0; a < NA; ++a) hp.nbr_ptr[a + 1] = hp.nbr_ptr[a] + cnt[a];
+  NB_TRY(hipMalloc((void**)&dptr, sizeof(int) * (NA + 1)));
+  NB_TRY(hipMalloc((void**)&dout, sizeof(int) * std::max(1, hp.nbr_ptr[NA])));
+  NB_TRY(hipMemcpy(dptr, hp.nbr_ptr.data(), sizeof(int) * (NA + 1), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_nbr_fill, dim3(NA), dim3(256), 0, 0, dpos, dsys, doff, rc2, dptr, dout);
+  NB_TRY(hipGetLastError());
+  hp.nbr_atom.resize(hp.nbr_ptr[NA]);
+  NB_TRY(hipMemcpy(hp.nbr_atom.data(), dout, sizeof(int) * hp.nbr_ptr[NA], hipMemcpyDeviceToHost));
+#undef NB_TRY
+  cleanup();
+  return 0;
+}
+
+static int upload_plan(exx_plan_s* pl) {
+  HostPlan& hp = pl->hp;
+  DevPlan& d = pl->d;
+  d.n_atoms = hp.n_atoms;
+  d.n_sys = hp.n_sys;
+  int rc = 0;
+#define UP(field) if ((rc = upload(pl, d.field, hp.field)) != 0) return rc
+  UP(nb); UP(na); UP(atom_sys); UP(bo); UP(sys_n); UP(sys_d_off);
+  UP(nbr_ptr); UP(nbr_atom); UP(nbr_pair); UP(nbr_lcol); UP(nbr_owner);
+  UP(pair_a); UP(pair_b); UP(c_off); UP(v_off); UP(n_loc); UP(m_loc);
+  UP(map_off); UP(col1g_off); UP(col2g_off); UP(map1); UP(map2); UP(col1g); UP(col2g);
+  UP(t_off); UP(e_off); UP(e_items); UP(ct_run_ptr); UP(ct_klen); UP(runs);
+  UP(h_items); UP(hc_q_ptr); UP(hc_q); UP(hc_x_ptr); UP(hc_x); UP(t2_items);
+  UP(f_items); UP(f_plist); UP(en_sys); UP(en_beg); UP(en_end);
+#undef UP
+  if ((rc = alloc_buf(pl, d.T, hp.t_total))) return rc;
+  if ((rc = alloc_buf(pl, d.E, hp.e_total))) return rc;
+  if ((rc = alloc_buf(pl, d.H, hp.e_total))) return rc;
+  if ((rc = alloc_buf(pl, d.epart, (int64_t)hp.en_sys.size()))) return rc;
+  return 0;
+}
+
+static void release(exx_plan_s* pl) {
+  for (void* p : pl->allocs) hipFree(p);
+  pl->allocs.clear();
+}
+
+extern "C" {
+
+const char* exx_last_error(void) { return g_err.c_str(); }
+
+int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
+  g_err.clear();
+  if (!out) return fail(EXX_EINVAL, "exx_plan_create: out is NULL");
+  *out = nullptr;
+  if (!sys) return fail(EXX_EINVAL, "exx_plan_create: sys is NULL");
+  exx_plan_s* pl = new (std::nothrow) exx_plan_s();
+  if (!pl) return fail(EXX_ENOMEM, "exx_plan_create: host allocation");
+  pl->host_only = (flags & EXX_PLAN_HOST_ONLY) != 0;
+  std::string err;
+  int rc = describe_system(sys->n_atoms, sys->n_species, sys->species, sys->positions, sys->n_basis,
+                           sys->n_aux, sys->r_cut, sys->n_systems, sys->sys_atom_off, pl->hp, err);
+  if (rc != 0) {
+    delete pl;
+    return fail(rc, err);
+  }
+  if (pl->host_only) {
+    host_neighbors(pl->hp);
+  } else {
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+      delete pl;
+      return fail(EXX_EDEVICE, "exx_plan_create: no HIP device");
+    }
+    if ((rc = device_neighbors(pl)) != 0) {
+      delete pl;
+      return rc;
+    }
+  }
+  try {
+    rc = derive_lists(pl->hp, err);
+  } catch (const std::bad_alloc&) {
+    delete pl;
+    return fail(EXX_ENOMEM, "exx_plan_create: host allocation in list building");
+  }
+  if (rc != 0) {
+    delete pl;
+    return fail(EXX_EDEVICE, err);
+  }
+  if (!pl->host_only) {
+    if ((rc = upload_plan(pl)) != 0) {
+      release(pl);
+      delete pl;
+      return rc;
+    }
+  }
+  *out = pl;
+  return EXX_OK;
+}
+
+int exx_plan_destroy(exx_plan plan) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_destroy: NULL plan");
+  release(plan);
+  delete plan;
+  return EXX_OK;
+}
+
+int exx_plan_info(exx_plan plan, exx_info* info) {
+  if (!plan || !info) return fail(EXX_EINVAL, "exx_plan_info: NULL argument");
+  const HostPlan& hp = plan->hp;
+  info->n_atoms = hp.n_atoms;
+  info->n_systems = hp.n_sys;
+  info->n_pairs = (int64_t)hp.pair_a.size();
+  info->c_size = hp.c_off.empty() ? 0 : hp.c_off.back();
+  info->v_size = hp.v_off.empty() ? 0 : hp.v_off.back();
+  info->d_size = hp.d_size;
+  info->n_basis_max = hp.n_basis_max;
+  info->workspace_bytes = plan->dev_bytes;
+  info->flops_fp64 = hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
+  return EXX_OK;
+}
+
+int exx_plan_pairs(exx_plan plan, int32_t* pair_a, int32_t* pair_b, int64_t* c_off, int64_t* v_off) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_pairs: NULL plan");
+  const HostPlan& hp = plan->hp;
+  const size_t n = hp.pair_a.size();
+  if (pair_a) std::memcpy(pair_a, hp.pair_a.data(), n * sizeof(int32_t));
+  if (pair_b) std::memcpy(pair_b, hp.pair_b.data(), n * sizeof(int32_t));
+  if (c_off) std::memcpy(c_off, hp.c_off.data(), (n + 1) * sizeof(int64_t));
+  if (v_off) std::memcpy(v_off, hp.v_off.data(), (n + 1) * sizeof(int64_t));
+  return EXX_OK;
+}
+
+int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom) {
+  if (!plan || !nbr_ptr) return fail(EXX_EINVAL, "exx_plan_neighbors: NULL argument");
+  const HostPlan& hp = plan->hp;
+  std::memcpy(nbr_ptr, hp.nbr_ptr.data(), hp.nbr_ptr.size() * sizeof(int32_t));
+  if (nbr_atom) std::memcpy(nbr_atom, hp.nbr_atom.data(), hp.nbr_atom.size() * sizeof(int32_t));
+  return EXX_OK;
+}
+
+int64_t exx_plan_flops(exx_plan plan, int stage) {
+  if (!plan) return -1;
+  const HostPlan& hp = plan->hp;
+  if (stage < 0) return hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
+  if (stage > 4) return -1;
+  return hp.flops[stage];
+}
+
+static int launch_energy(exx_plan plan, const double* K, const double* D, double* Ex, hipStream_t st) {
+  const int nch = (int)plan->hp.en_sys.size();
+  hipLaunchKernelGGL(k_energy_part, dim3(nch), dim3(256), 0, st, K, D, plan->d, nch);
+  hipLaunchKernelGGL(k_energy_sum, dim3((plan->hp.n_sys + 63) / 64), dim3(64), 0, st, Ex, plan->d, nch);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+int build_K(exx_plan plan, const double* C, const double* V, const double* D, int precision,
+            double* K, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "build_K: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "build_K: host-only plan");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K: NULL array");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EUNSUPPORTED, "build_K: precision not implemented");
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, hp.d_size);
+  hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, d);
+  const int nE = (int)hp.e_items.size();
+  hipLaunchKernelGGL(k_E, dim3((nE + 3) / 4), dim3(256), 0, st, D, d, nE);
+  const int nH = (int)hp.h_items.size();
+  hipLaunchKernelGGL(k_H, dim3((nH + 3) / 4), dim3(256), 0, st, V, D, d, nH);
+  const int nT = (int)hp.t2_items.size();
+  hipLaunchKernelGGL(k_T2, dim3((nT + 3) / 4), dim3(256), 0, st, V, K, d, nT);
+  const int nF = (int)hp.f_items.size();
+  hipLaunchKernelGGL(k_final, dim3((nF + 3) / 4), dim3(256), 0, st, K, d, nF);
+  HIP_TRY(hipGetLastError());
+  if (Ex) return launch_energy(plan, K, D, Ex, st);
+  return EXX_OK;
+}
+
+int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exchange_energy: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exchange_energy: host-only plan");
+  if (!K || !D || !Ex) return fail(EXX_EINVAL, "exchange_energy: NULL array");
+  return launch_energy(plan, K, D, Ex, (hipStream_t)stream);
+}
+
+int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, double gE,
+                      int precision, double* dC, double* dV, double* dD, double* forces,
+                      double c_decay, double v_2s2, void* stream) {
+  (void)C; (void)V; (void)D; (void)gE; (void)precision; (void)dC; (void)dV; (void)dD;
+  (void)forces; (void)c_decay; (void)v_2s2; (void)stream;
+  if (!plan) return fail(EXX_EINVAL, "exchange_backward: NULL plan");
+  return fail(EXX_EUNSUPPORTED, "exchange_backward: not implemented yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal plan structure of libexx (not part of the ABI).
+//
+// Notation (non-periodic RI-LVL exchange, lattice vector R = 0):
+//   N[P]   atoms within r_cut of atom P, P included, sorted by index.
+//   N2[P]  union of N[J] over J in N[P], sorted.
+//   T_P    row-owned RI coefficients of aux atom P: rows (mu, i) with mu and
+//          i on P (s_P = n_aux(P) * n_basis(P) rows), columns the basis
+//          functions of N[P] (n_P columns).  T_P[(mu,i), j] = C^mu_ij for
+//          j off P and C^mu_ij / 2 for j on P, so that C^mu = M^mu + M^mu^T.
+//   E_P    = T_P D restricted to columns N2[P]          (s_P x m_P)
+//   H_P    = sum_Q (V_PQ (x) D_PQ) T_Q  + 2 G-part       (s_P x m_P)
+//   T2     = sum V M D M^T (pair blocks, written into K first)
+//   K      = T2 + sym(T^T H)
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace exx {
+
+constexpr int NB_MAX = 16;   // basis functions per atom supported by the kernels
+constexpr int NA_MAX = 64;   // auxiliary functions per atom supported by the kernels
+
+struct Run { int lcol, grow, len; };           // k-range of the E GEMM
+struct EItem { int P, r0, c0, ct; };           // E tile: rows r0.., cols c0.., column tile ct
+struct HItem { int P, mu0, c0, hc; };          // H tile: mu0..mu0+15, cols c0..c0+15, list id hc
+struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)
+
+struct HostPlan {
+  // system description
+  int n_atoms = 0, n_sys = 0;
+  double r_cut = 0;
+  std::vector<int> species, nb, na, atom_sys, bo;   // per atom
+  std::vector<double> pos;                          // 3 * n_atoms
+  std::vector<int> sys_atom_off;                    // n_sys + 1
+  std::vector<int64_t> sys_n, sys_d_off;            // basis count, offset of dense block
+  int64_t d_size = 0, n_basis_max = 0;
+  // neighbour lists (CSR) and canonical pairs
+  std::vector<int> nbr_ptr, nbr_atom, nbr_pair, nbr_lcol, nbr_owner;
+  std::vector<int> pair_a, pair_b;
+  std::vector<int64_t> c_off, v_off;
+  std::vector<int> n_loc;                           // n_P
+  // N2 lists
+  std::vector<int> n2_ptr, n2_atom;
+  std::vector<int> m_loc;                           // m_P
+  // maps (per atom, over the basis of its system)
+  std::vector<int64_t> map_off;
+  std::vector<int> map1, map2;
+  std::vector<int64_t> col1g_off, col2g_off;
+  std::vector<int> col1g, col2g;
+  // workspace layout
+  std::vector<int64_t> t_off, e_off;
+  int64_t t_total = 0, e_total = 0;
+  // task lists
+  std::vector<EItem> e_items;
+  std::vector<int> ct_run_ptr, ct_klen;
+  std::vector<Run> runs;
+  std::vector<HItem> h_items;
+  std::vector<int> hc_q_ptr, hc_q, hc_x_ptr, hc_x;
+  std::vector<int> t2_items;                        // canonical pair ids
+  std::vector<FItem> f_items;
+  std::vector<int> f_plist;
+  std::vector<int> en_sys, en_beg, en_end;          // energy chunks
+  // flop counts: [0] repack (0), [1] E, [2] H, [3] T2, [4] final
+  int64_t flops[5] = {0, 0, 0, 0, 0};
+  int64_t issued[5] = {0, 0, 0, 0, 0};
+};
+
+// Validate a system and fill the description part of a HostPlan.
+int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_t* species,
+                    const double* positions, const int32_t* n_basis, const int32_t* n_aux,
+                    double r_cut, int32_t n_systems, const int32_t* sys_atom_off,
+                    HostPlan& hp, std::string& err);
+
+// Host version of the screened neighbour lists (same arithmetic as the
+// device builder): nbr_ptr / nbr_atom only.
+void host_neighbors(HostPlan& hp);
+
+// Everything derived from the neighbour lists: canonical pairs and their
+// storage offsets, N2, maps, workspace layout, all task lists, flop counts.
+int derive_lists(HostPlan& hp, std::string& err);
+
+}  // namespace exx

@@ -1,0 +1,424 @@
+// Host-side bookkeeping of an exchange plan: validation, canonical pairs,
+// second neighbourhoods, column maps, workspace layout and the task lists of
+// every kernel (the atom-pair / atom-quartet block lists of the build).
+//
+// The lists mirror the grouping of the pair-restricted exchange sum by atom
+// pairs (Sec. "Description of the real-space formalism", Eq.
+// ri_lvl_exchange_matrix): every task is keyed by the auxiliary atom P that
+// owns the row-owned coefficient block T_P, and by output tiles.
+#include "exx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+
+namespace exx {
+
+int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_t* species,
+                    const double* positions, const int32_t* n_basis, const int32_t* n_aux,
+                    double r_cut, int32_t n_systems, const int32_t* sys_atom_off,
+                    HostPlan& hp, std::string& err) {
+  if (n_atoms <= 0 || n_species <= 0 || !species || !positions || !n_basis || !n_aux) {
+    err = "exx_system: null array or non-positive count";
+    return -1;
+  }
+  if (!(r_cut > 0) || !std::isfinite(r_cut)) { err = "exx_system: r_cut must be positive"; return -1; }
+  if (n_systems < 1 || (n_systems > 1 && !sys_atom_off)) { err = "exx_system: bad n_systems / sys_atom_off"; return -1; }
+  for (int s = 0; s < n_species; ++s) {
+    if (n_basis[s] < 1 || n_aux[s] < 1) { err = "exx_system: species with no functions"; return -1; }
+    if (n_basis[s] > NB_MAX || n_aux[s] > NA_MAX) {
+      err = "exx_system: species exceeds the supported per-atom sizes (basis <= 16, aux <= 64)";
+      return -5;
+    }
+  }
+  hp.n_atoms = n_atoms;
+  hp.n_sys = n_systems;
+  hp.r_cut = r_cut;
+  hp.species.assign(species, species + n_atoms);
+  hp.pos.assign(positions, positions + 3 * (size_t)n_atoms);
+  for (double x : hp.pos) if (!std::isfinite(x)) { err = "exx_system: non-finite position"; return -1; }
+  hp.sys_atom_off.resize(n_systems + 1);
+  if (sys_atom_off) {
+    for (int s = 0; s <= n_systems; ++s) hp.sys_atom_off[s] = sys_atom_off[s];
+  } else {
+    hp.sys_atom_off[0] = 0;
+    hp.sys_atom_off[1] = n_atoms;
+  }
+  if (hp.sys_atom_off[0] != 0 || hp.sys_atom_off[n_systems] != n_atoms) {
+    err = "exx_system: sys_atom_off must start at 0 and end at n_atoms";
+    return -1;
+  }
+  for (int s = 0; s < n_systems; ++s)
+    if (hp.sys_atom_off[s + 1] <= hp.sys_atom_off[s]) { err = "exx_system: empty or decreasing system"; return -1; }
+  hp.nb.resize(n_atoms);
+  hp.na.resize(n_atoms);
+  hp.atom_sys.resize(n_atoms);
+  hp.bo.resize(n_atoms);
+  hp.sys_n.assign(n_systems, 0);
+  hp.sys_d_off.assign(n_systems + 1, 0);
+  for (int s = 0; s < n_systems; ++s) {
+    int64_t off = 0;
+    for (int a = hp.sys_atom_off[s]; a < hp.sys_atom_off[s + 1]; ++a) {
+      int sp = species[a];
+      if (sp < 0 || sp >= n_species) { err = "exx_system: species index out of range"; return -1; }
+      hp.nb[a] = n_basis[sp];
+      hp.na[a] = n_aux[sp];
+      hp.atom_sys[a] = s;
+      hp.bo[a] = (int)off;
+      off += n_basis[sp];
+    }
+    if (off > (int64_t)1 << 30) { err = "exx_system: system too large"; return -1; }
+    hp.sys_n[s] = off;
+    hp.sys_d_off[s + 1] = hp.sys_d_off[s] + off * off;
+    hp.n_basis_max = std::max(hp.n_basis_max, off);
+  }
+  hp.d_size = hp.sys_d_off[n_systems];
+  return 0;
+}
+
+#pragma clang fp contract(off)
+void host_neighbors(HostPlan& hp) {
+  const double rc2 = hp.r_cut * hp.r_cut;
+  hp.nbr_ptr.assign(hp.n_atoms + 1, 0);
+  hp.nbr_atom.clear();
+  for (int s = 0; s < hp.n_sys; ++s) {
+    const int lo = hp.sys_atom_off[s], hi = hp.sys_atom_off[s + 1];
+    for (int a = lo; a < hi; ++a) {
+      const double* pa = &hp.pos[3 * (size_t)a];
+      for (int b = lo; b < hi; ++b) {
+        const double* pb = &hp.pos[3 * (size_t)b];
+        volatile double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
+        volatile double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        volatile double r2 = (xx + yy);
+        r2 = r2 + zz;
+        if (r2 <= rc2) hp.nbr_atom.push_back(b);
+      }
+      hp.nbr_ptr[a + 1] = (int)hp.nbr_atom.size();
+    }
+  }
+}
+
+namespace {
+
+int64_t ceil_to(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+int derive_lists(HostPlan& hp, std::string& err) {
+  const int NA = hp.n_atoms;
+  const auto& np = hp.nbr_ptr;
+  const auto& nat = hp.nbr_atom;
+  const int64_t nn = np[NA];
+  // every atom must be its own neighbour
+  for (int a = 0; a < NA; ++a) {
+    if (!std::binary_search(nat.begin() + np[a], nat.begin() + np[a + 1], a)) {
+      err = "neighbour list lost an atom's self pair";
+      return -3;
+    }
+  }
+  // ---- canonical pairs (A <= B, lexicographic) and pair id of every entry
+  hp.nbr_pair.assign(nn, -1);
+  hp.nbr_owner.assign(nn, 0);
+  hp.pair_a.clear();
+  hp.pair_b.clear();
+  for (int a = 0; a < NA; ++a)
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      hp.nbr_owner[k] = a;
+      if (nat[k] >= a) {
+        hp.nbr_pair[k] = (int)hp.pair_a.size();
+        hp.pair_a.push_back(a);
+        hp.pair_b.push_back(nat[k]);
+      }
+    }
+  for (int a = 0; a < NA; ++a)
+    for (int k = np[a]; k < np[a + 1]; ++k)
+      if (nat[k] < a) {
+        int b = nat[k];
+        auto it = std::lower_bound(nat.begin() + np[b], nat.begin() + np[b + 1], a);
+        if (it == nat.begin() + np[b + 1] || *it != a) { err = "neighbour list not symmetric"; return -3; }
+        hp.nbr_pair[k] = hp.nbr_pair[it - nat.begin()];
+      }
+  const int64_t npairs = (int64_t)hp.pair_a.size();
+  hp.c_off.assign(npairs + 1, 0);
+  hp.v_off.assign(npairs + 1, 0);
+  for (int64_t p = 0; p < npairs; ++p) {
+    int a = hp.pair_a[p], b = hp.pair_b[p];
+    int64_t cs = (a == b) ? (int64_t)hp.na[a] * hp.nb[a] * hp.nb[a]
+                          : (int64_t)(hp.na[a] + hp.na[b]) * hp.nb[a] * hp.nb[b];
+    hp.c_off[p + 1] = hp.c_off[p] + cs;
+    hp.v_off[p + 1] = hp.v_off[p] + (int64_t)hp.na[a] * hp.na[b];
+  }
+  // ---- local columns of T_P
+  hp.nbr_lcol.assign(nn, 0);
+  hp.n_loc.assign(NA, 0);
+  for (int a = 0; a < NA; ++a) {
+    int c = 0;
+    for (int k = np[a]; k < np[a + 1]; ++k) { hp.nbr_lcol[k] = c; c += hp.nb[nat[k]]; }
+    hp.n_loc[a] = c;
+  }
+  // ---- N2
+  hp.n2_ptr.assign(NA + 1, 0);
+  hp.n2_atom.clear();
+  hp.m_loc.assign(NA, 0);
+  std::vector<int> stamp(NA, -1);
+  std::vector<int> tmp;
+  for (int a = 0; a < NA; ++a) {
+    tmp.clear();
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      int j = nat[k];
+      for (int k2 = np[j]; k2 < np[j + 1]; ++k2) {
+        int l = nat[k2];
+        if (stamp[l] != a) { stamp[l] = a; tmp.push_back(l); }
+      }
+    }
+    std::sort(tmp.begin(), tmp.end());
+    int m = 0;
+    for (int l : tmp) { hp.n2_atom.push_back(l); m += hp.nb[l]; }
+    hp.n2_ptr[a + 1] = (int)hp.n2_atom.size();
+    hp.m_loc[a] = m;
+  }
+  // ---- per-atom maps over the basis of its system, column -> system basis
+  hp.map_off.assign(NA + 1, 0);
+  for (int a = 0; a < NA; ++a) hp.map_off[a + 1] = hp.map_off[a] + hp.sys_n[hp.atom_sys[a]];
+  hp.map1.assign(hp.map_off[NA], -1);
+  hp.map2.assign(hp.map_off[NA], -1);
+  hp.col1g_off.assign(NA + 1, 0);
+  hp.col2g_off.assign(NA + 1, 0);
+  for (int a = 0; a < NA; ++a) {
+    hp.col1g_off[a + 1] = hp.col1g_off[a] + hp.n_loc[a];
+    hp.col2g_off[a + 1] = hp.col2g_off[a] + hp.m_loc[a];
+  }
+  hp.col1g.assign(hp.col1g_off[NA], 0);
+  hp.col2g.assign(hp.col2g_off[NA], 0);
+  for (int a = 0; a < NA; ++a) {
+    int c = 0;
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      int j = nat[k];
+      for (int x = 0; x < hp.nb[j]; ++x, ++c) {
+        hp.map1[hp.map_off[a] + hp.bo[j] + x] = c;
+        hp.col1g[hp.col1g_off[a] + c] = hp.bo[j] + x;
+      }
+    }
+    c = 0;
+    for (int k = hp.n2_ptr[a]; k < hp.n2_ptr[a + 1]; ++k) {
+      int l = hp.n2_atom[k];
+      for (int x = 0; x < hp.nb[l]; ++x, ++c) {
+        hp.map2[hp.map_off[a] + hp.bo[l] + x] = c;
+        hp.col2g[hp.col2g_off[a] + c] = hp.bo[l] + x;
+      }
+    }
+  }
+  // ---- workspace layout
+  hp.t_off.assign(NA + 1, 0);
+  hp.e_off.assign(NA + 1, 0);
+  for (int a = 0; a < NA; ++a) {
+    int64_t s = (int64_t)hp.na[a] * hp.nb[a];
+    hp.t_off[a + 1] = hp.t_off[a] + ceil_to(s * hp.n_loc[a], 2);
+    hp.e_off[a + 1] = hp.e_off[a] + ceil_to(s * hp.m_loc[a], 2);
+  }
+  hp.t_total = hp.t_off[NA];
+  hp.e_total = hp.e_off[NA];
+  for (auto& f : hp.flops) f = 0;
+  for (auto& f : hp.issued) f = 0;
+  // atom of every column of N2[P] (scratch)
+  std::vector<int> mark(NA, -1);
+  // ---- E tasks: column tiles of 32, k-runs of relevant neighbours J
+  hp.e_items.clear();
+  hp.ct_run_ptr.assign(1, 0);
+  hp.ct_klen.clear();
+  hp.runs.clear();
+  int stampv = 0;
+  std::vector<int> stamp2(NA, -1);
+  for (int a = 0; a < NA; ++a) {
+    const int sP = hp.na[a] * hp.nb[a];
+    // structural flops: sum_J b_J sum_{L in N[J]} b_L
+    int64_t kk = 0;
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      int j = nat[k];
+      int64_t sl = 0;
+      for (int k2 = np[j]; k2 < np[j + 1]; ++k2) sl += hp.nb[nat[k2]];
+      kk += (int64_t)hp.nb[j] * sl;
+    }
+    hp.flops[1] += 2 * (int64_t)sP * kk;
+    const int mP = hp.m_loc[a];
+    for (int c0 = 0; c0 < mP; c0 += 32) {
+      ++stampv;
+      int c1 = std::min(mP, c0 + 32);
+      for (int c = c0; c < c1; ++c) {
+        int g = hp.col2g[hp.col2g_off[a] + c];
+        // atom of g: search the N2 list
+        (void)g;
+      }
+      // atoms covering [c0, c1): walk N2[a]
+      {
+        int c = 0;
+        for (int k = hp.n2_ptr[a]; k < hp.n2_ptr[a + 1]; ++k) {
+          int l = hp.n2_atom[k];
+          if (c < c1 && c + hp.nb[l] > c0) stamp2[l] = stampv;
+          c += hp.nb[l];
+          if (c >= c1) break;
+        }
+      }
+      const int ct = (int)hp.ct_klen.size();
+      int klen = 0;
+      Run cur{-1, -1, 0};
+      int prevJ = -2;
+      for (int k = np[a]; k < np[a + 1]; ++k) {
+        int j = nat[k];
+        bool rel = false;
+        for (int k2 = np[j]; k2 < np[j + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
+        if (!rel) { prevJ = -2; continue; }
+        if (cur.len > 0 && j == prevJ + 1) {
+          cur.len += hp.nb[j];
+        } else {
+          if (cur.len > 0) hp.runs.push_back(cur);
+          cur = Run{hp.nbr_lcol[k], hp.bo[j], hp.nb[j]};
+        }
+        prevJ = j;
+        klen += hp.nb[j];
+      }
+      if (cur.len > 0) hp.runs.push_back(cur);
+      hp.ct_run_ptr.push_back((int)hp.runs.size());
+      hp.ct_klen.push_back(klen);
+      for (int r0 = 0; r0 < sP; r0 += 32) {
+        hp.e_items.push_back(EItem{a, r0, c0, ct});
+        hp.issued[1] += 2LL * 32 * 32 * ceil_to(klen, 4);
+      }
+    }
+  }
+  std::stable_sort(hp.e_items.begin(), hp.e_items.end(), [&](const EItem& x, const EItem& y) {
+    return hp.ct_klen[x.ct] > hp.ct_klen[y.ct];
+  });
+  // ---- H tasks: column tiles of 16; Q-lists (V (x) D part) and X-lists (G part)
+  hp.h_items.clear();
+  hp.hc_q_ptr.assign(1, 0);
+  hp.hc_x_ptr.assign(1, 0);
+  hp.hc_q.clear();
+  hp.hc_x.clear();
+  std::vector<int64_t> hc_cost;
+  for (int a = 0; a < NA; ++a) {
+    const int aP = hp.na[a], bP = hp.nb[a], mP = hp.m_loc[a];
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      int q = nat[k];
+      hp.flops[2] += 2LL * aP * hp.na[q] * hp.nb[q] * hp.n_loc[q];   // F = V T
+      hp.flops[2] += 2LL * aP * bP * hp.nb[q] * hp.n_loc[q];          // D contraction
+      hp.flops[2] += 2LL * aP * hp.na[q] * bP * hp.nb[q];             // G part
+    }
+    for (int c0 = 0; c0 < mP; c0 += 16) {
+      ++stampv;
+      int c1 = std::min(mP, c0 + 16);
+      {
+        int c = 0;
+        for (int k = hp.n2_ptr[a]; k < hp.n2_ptr[a + 1]; ++k) {
+          int l = hp.n2_atom[k];
+          if (c < c1 && c + hp.nb[l] > c0) stamp2[l] = stampv;
+          c += hp.nb[l];
+          if (c >= c1) break;
+        }
+      }
+      const int hc = (int)hc_cost.size();
+      int64_t cost = 0;
+      for (int k = np[a]; k < np[a + 1]; ++k) {
+        int q = nat[k];
+        bool rel = false;
+        for (int k2 = np[q]; k2 < np[q + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
+        if (rel) {
+          hp.hc_q.push_back(k);
+          cost += (int64_t)((hp.na[q] + 3) / 4) * hp.nb[q] * 16 + (int64_t)hp.nb[q] * bP;
+        }
+        if (stamp2[q] == stampv) {
+          hp.hc_x.push_back(k);
+          cost += (int64_t)((hp.na[q] + 3) / 4) * bP * 16;
+        }
+      }
+      hp.hc_q_ptr.push_back((int)hp.hc_q.size());
+      hp.hc_x_ptr.push_back((int)hp.hc_x.size());
+      hc_cost.push_back(cost);
+      for (int mu0 = 0; mu0 < aP; mu0 += 16) hp.h_items.push_back(HItem{a, mu0, c0, hc});
+    }
+  }
+  std::stable_sort(hp.h_items.begin(), hp.h_items.end(),
+                   [&](const HItem& x, const HItem& y) { return hc_cost[x.hc] > hc_cost[y.hc]; });
+  // ---- T2 tasks: every canonical pair
+  hp.t2_items.resize(npairs);
+  std::iota(hp.t2_items.begin(), hp.t2_items.end(), 0);
+  for (int64_t p = 0; p < npairs; ++p) {
+    int a = hp.pair_a[p], b = hp.pair_b[p];
+    hp.flops[3] += 2LL * hp.na[a] * hp.na[b] * hp.nb[b] * hp.n_loc[b] + 2LL * hp.na[a] * hp.nb[a] * hp.nb[b] * hp.n_loc[b];
+  }
+  std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) {
+    auto cst = [&](int p) { int b = hp.pair_b[p]; return (int64_t)hp.na[hp.pair_a[p]] * hp.na[b] * hp.n_loc[b]; };
+    return cst(x) > cst(y);
+  });
+  // ---- final tasks: 32 x 32 tile pairs (upper triangle) with their P-lists
+  hp.f_items.clear();
+  hp.f_plist.clear();
+  std::vector<std::pair<int64_t, int>> fcost;
+  std::vector<FItem> fit;
+  for (int s = 0; s < hp.n_sys; ++s) {
+    const int lo = hp.sys_atom_off[s], hi = hp.sys_atom_off[s + 1];
+    const int nt = (int)((hp.sys_n[s] + 31) / 32);
+    std::vector<std::vector<int>> lists((size_t)nt * nt);
+    std::vector<int> t1, t2;
+    for (int a = lo; a < hi; ++a) {
+      const int64_t sP = (int64_t)hp.na[a] * hp.nb[a];
+      hp.flops[4] += 2LL * hp.n_loc[a] * sP * hp.m_loc[a];
+      t1.clear();
+      t2.clear();
+      for (int k = np[a]; k < np[a + 1]; ++k) {
+        int j = nat[k];
+        for (int t = hp.bo[j] / 32; t <= (hp.bo[j] + hp.nb[j] - 1) / 32; ++t) t1.push_back(t);
+      }
+      for (int k = hp.n2_ptr[a]; k < hp.n2_ptr[a + 1]; ++k) {
+        int l = hp.n2_atom[k];
+        for (int t = hp.bo[l] / 32; t <= (hp.bo[l] + hp.nb[l] - 1) / 32; ++t) t2.push_back(t);
+      }
+      std::sort(t1.begin(), t1.end());
+      t1.erase(std::unique(t1.begin(), t1.end()), t1.end());
+      std::sort(t2.begin(), t2.end());
+      t2.erase(std::unique(t2.begin(), t2.end()), t2.end());
+      for (int x : t1)
+        for (int y : t2) {
+          int i = std::min(x, y), l = std::max(x, y);
+          auto& v = lists[(size_t)i * nt + l];
+          if (v.empty() || v.back() != a) v.push_back(a);
+        }
+    }
+    for (int i = 0; i < nt; ++i)
+      for (int l = i; l < nt; ++l) {
+        auto& v = lists[(size_t)i * nt + l];
+        if (v.empty()) continue;
+        FItem f{};
+        f.sys = s;
+        f.gI0 = 32 * i;
+        f.gL0 = 32 * l;
+        f.pbeg = (int)hp.f_plist.size();
+        int64_t cost = 0;
+        for (int a : v) { hp.f_plist.push_back(a); cost += (int64_t)hp.na[a] * hp.nb[a]; }
+        f.pend = (int)hp.f_plist.size();
+        hp.issued[4] += 2LL * 2 * 32 * 32 * cost;
+        fcost.push_back({cost, (int)fit.size()});
+        fit.push_back(f);
+      }
+  }
+  std::stable_sort(fcost.begin(), fcost.end(), [](auto& x, auto& y) { return x.first > y.first; });
+  for (auto& c : fcost) hp.f_items.push_back(fit[c.second]);
+  // ---- energy chunks
+  hp.en_sys.clear();
+  hp.en_beg.clear();
+  hp.en_end.clear();
+  const int64_t CH = 1 << 16;
+  for (int s = 0; s < hp.n_sys; ++s) {
+    int64_t n2 = hp.sys_n[s] * hp.sys_n[s];
+    for (int64_t b = 0; b < n2; b += CH) {
+      hp.en_sys.push_back(s);
+      hp.en_beg.push_back((int)b);
+      hp.en_end.push_back((int)std::min(n2, b + CH));
+    }
+  }
+  for (int i = 1; i < 5; ++i) hp.flops[0] += 0;
+  return 0;
+}
+
+}  // namespace exx
