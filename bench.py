@@ -1,0 +1,145 @@
+#!/usr/bin/env python
+"""Benchmark: RI-LVL exchange-matrix (K) builds per second on one MI355X.
+
+A step is one complete build_K call (zero-fill, repack of C, E = M D, the V
+stage, the T2 blocks, the final owner-computes contraction and the E_x
+reduction) on the 768-atom open ice box (256 H2O, 6144 basis / 17920 aux
+functions, r_cut 6 A) with C, V, D already resident in HBM.
+
+Prints ONE JSON line (rank 0).  The "roofline" object describes the dominant
+kernel, timed with HIP events recorded by the library on its launch stream
+during the timed steps; "cpu_baseline" times the CPU oracle (row route) on a
+bounded sample of rows of the same workload, scaled to builds/s.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
+WORKLOADS = {
+    "ice768": (2, "ice_box_4x4x2_768_atoms_6144_basis_rcut6"),
+    "water24": (1, "water_cluster_8_24_atoms_192_basis_rcut6"),
+}
+
+
+def cpu_baseline(inp, seconds=15.0, max_rows=64):
+    """Time the oracle's row route on a bounded sample of rows."""
+    import numpy as np
+    from oracle import exx_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    blk = O.Blocks(inp)
+    n = blk.n
+    rng = np.random.default_rng(0)
+    order = rng.permutation(n)
+    done, t0 = 0, time.perf_counter()
+    while done < max_rows and time.perf_counter() - t0 < seconds:
+        O.k_rows(inp, order[done:done + 1], blk=blk)
+        done += 1
+    dt = time.perf_counter() - t0
+    rows_per_s = done / dt
+    return {"value": rows_per_s / n, "unit": "builds/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} random rows of K ({n} rows per build) by the oracle's row route, "
+                      f"{dt:.1f} s; builds/s = rows/s / {n}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ice768", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the exchange build here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2403_10343_amd as exx
+
+    cfg, wname = WORKLOADS[args.workload]
+    sysm = synth.config(cfg)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    dev = torch.device("cuda:0")
+    C, V, D = (torch.from_numpy(a).to(dev) for a in (inp.C, inp.V, inp.D))
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=dev)
+    Ex = torch.empty(plan.n_systems, dtype=torch.float64, device=dev)
+    prec = exx.PREC_FP64
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.build_K(C, V, D, K, Ex, precision=prec)
+    torch.cuda.synchronize()
+
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.build_K(C, V, D, K, Ex, precision=prec, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, nrec = plan.stage_times()
+    plan.set_profiling(False)
+
+    elapsed = t1 - t0
+    builds_per_s = args.steps / elapsed
+    avg_ms = stage_ms / max(nrec, 1)
+    names = exx._lib.STAGE_NAMES
+    dom = int(np.argmax(avg_ms))
+    flops_dom = plan.flops(dom) if dom <= 4 else 0
+    achieved = flops_dom / (avg_ms[dom] * 1e-3) if avg_ms[dom] > 0 else 0.0
+    total_flops = plan.flops()
+    e_x = float(Ex[0].item())
+
+    out = {
+        "metric": "K-matrix builds/s (RI-LVL exchange, FP64 path)",
+        "value": builds_per_s,
+        "unit": "builds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "atoms": sysm.n_atoms,
+                   "basis": int(inp.layout.sys_nbas[0]), "aux": int(synth.N_AUX[sysm.species].sum()),
+                   "r_cut_A": sysm.r_cut, "precision": args.precision},
+        "roofline": {"bound": "mfma", "kernel": f"k_{names[dom]}", "achieved": achieved / 1e12,
+                     "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"],
+                     "traffic": None},
+        "algorithmic_gflop_per_build": total_flops / 1e9,
+        "whole_build_tflops": total_flops * builds_per_s / 1e12,
+        "whole_build_frac_fp64_peak": total_flops * builds_per_s / PEAK["fp64"],
+        "stage_ms": {names[i]: float(avg_ms[i]) for i in range(len(names))},
+        "stage_tflops": {names[i]: (plan.flops(i) / (avg_ms[i] * 1e-3) / 1e12 if i <= 4 and avg_ms[i] > 0 else 0.0)
+                         for i in range(len(names))},
+        "E_x": e_x,
+        "E_x_per_atom": e_x / sysm.n_atoms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inp, seconds=args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,8 +80,8 @@ typedef struct {
     int32_t n_species;
     const int32_t* species;      /* host [n_atoms], values 0..n_species-1 */
     const double* positions;     /* host [n_atoms][3], Angstrom */
-    const int32_t* n_basis;      /* host [n_species], 1..64 */
-    const int32_t* n_aux;        /* host [n_species], 1..256 */
+    const int32_t* n_basis;      /* host [n_species], 1..16 */
+    const int32_t* n_aux;        /* host [n_species], 1..64 */
     double r_cut;                /* Angstrom, > 0 */
     int32_t n_systems;           /* >= 1 */
     const int32_t* sys_atom_off; /* host [n_systems + 1], increasing, first 0,
@@ -155,6 +155,17 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
 /* Algorithmic flop count of one stage of build_K (stage -1 = total):
  * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction. */
 int64_t exx_plan_flops(exx_plan plan, int stage);
+
+/* Instrumentation: when enabled, build_K records HIP events on its stream at
+ * the boundaries of its EXX_N_STAGES stages (0 zero-fill + repack of C,
+ * 1 E = M D, 2 V stage, 3 T2 blocks, 4 final contraction, 5 energy), for up
+ * to 512 builds.  exx_plan_stage_times() waits for the recorded builds, adds
+ * their per-stage durations into ms[EXX_N_STAGES] (milliseconds, host
+ * array), stores how many builds were recorded in *n_builds and starts a new
+ * recording.  Enabling (or re-enabling) clears earlier records. */
+#define EXX_N_STAGES 6
+int exx_plan_set_profiling(exx_plan plan, int enable);
+int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* exx_last_error(void);

@@ -50,7 +50,9 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pairs",
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
-           "exx_plan_flops", "exx_last_error")
+           "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times")
+N_STAGES = 6
+STAGE_NAMES = ("repack", "E", "H", "T2", "final", "energy")
 
 
 def lib():
@@ -70,6 +72,8 @@ def lib():
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exx_plan_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.exx_plan_stage_times.argtypes = [vp, vp, vp]
     L.exx_plan_flops.argtypes = [vp, ctypes.c_int]
     L.exx_plan_flops.restype = i64
     L.exx_last_error.restype = ctypes.c_char_p
@@ -163,6 +167,16 @@ class Plan:
         _check(lib().exchange_backward(self._h, _ptr(C), _ptr(V), _ptr(D), float(gE), int(precision),
                                        _ptr(dC), _ptr(dV), _ptr(dD), _ptr(forces),
                                        float(c_decay), float(v_2s2), _stream(stream)))
+
+    def set_profiling(self, enable=True):
+        _check(lib().exx_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """(per-stage milliseconds summed over recorded builds, number of builds)."""
+        ms = np.zeros(N_STAGES)
+        n = ctypes.c_int64()
+        _check(lib().exx_plan_stage_times(self._h, ms.ctypes.data, ctypes.byref(n)))
+        return ms, int(n.value)
 
     def close(self):
         if self._h is not None:

@@ -83,6 +83,9 @@ struct DevPlan {
   double *T, *E, *H, *epart;
 };
 
+constexpr int N_STAGE_EV = 7;   // boundaries: start, repack, E, H, T2, final, energy
+constexpr int MAX_PROFILED = 512;
+
 struct exx_plan_s {
   HostPlan hp;
   bool host_only = false;
@@ -90,6 +93,10 @@ struct exx_plan_s {
   DevPlan d{};
   std::vector<void*> allocs;
   int64_t dev_bytes = 0;
+  // optional per-stage timing of build_K (HIP events on the build's stream)
+  bool profiling = false;
+  std::vector<hipEvent_t> events;   // MAX_PROFILED * N_STAGE_EV, created lazily
+  int n_recorded = 0;
 };
 
 template <typename X>
@@ -577,6 +584,15 @@ static int upload_plan(exx_plan_s* pl) {
 static void release(exx_plan_s* pl) {
   for (void* p : pl->allocs) hipFree(p);
   pl->allocs.clear();
+  for (hipEvent_t e : pl->events) hipEventDestroy(e);
+  pl->events.clear();
+}
+
+// Record boundary `i` of the current profiled build (no-op when off or full).
+static void stage_mark(exx_plan_s* pl, int i, hipStream_t st) {
+  if (!pl->profiling || pl->n_recorded >= MAX_PROFILED) return;
+  hipEventRecord(pl->events[(size_t)pl->n_recorded * N_STAGE_EV + i], st);
+  if (i == N_STAGE_EV - 1) ++pl->n_recorded;
 }
 
 extern "C" {
@@ -688,6 +704,35 @@ static int launch_energy(exx_plan plan, const double* K, const double* D, double
   return EXX_OK;
 }
 
+int exx_plan_set_profiling(exx_plan plan, int enable) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_set_profiling: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_plan_set_profiling: host-only plan");
+  if (enable && plan->events.empty()) {
+    plan->events.resize((size_t)MAX_PROFILED * N_STAGE_EV);
+    for (auto& e : plan->events) HIP_TRY(hipEventCreate(&e));
+  }
+  plan->profiling = enable != 0;
+  plan->n_recorded = 0;
+  return EXX_OK;
+}
+
+int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds) {
+  if (!plan || !ms || !n_builds) return fail(EXX_EINVAL, "exx_plan_stage_times: NULL argument");
+  for (int i = 0; i < EXX_N_STAGES; ++i) ms[i] = 0.0;
+  *n_builds = plan->n_recorded;
+  for (int b = 0; b < plan->n_recorded; ++b) {
+    hipEvent_t* ev = &plan->events[(size_t)b * N_STAGE_EV];
+    HIP_TRY(hipEventSynchronize(ev[N_STAGE_EV - 1]));
+    for (int i = 0; i < EXX_N_STAGES; ++i) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[i] += t;
+    }
+  }
+  plan->n_recorded = 0;
+  return EXX_OK;
+}
+
 int build_K(exx_plan plan, const double* C, const double* V, const double* D, int precision,
             double* K, double* Ex, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "build_K: NULL plan");
@@ -697,19 +742,27 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
   DevPlan& d = plan->d;
+  stage_mark(plan, 0, st);
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, hp.d_size);
   hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, d);
+  stage_mark(plan, 1, st);
   const int nE = (int)hp.e_items.size();
   hipLaunchKernelGGL(k_E, dim3((nE + 3) / 4), dim3(256), 0, st, D, d, nE);
+  stage_mark(plan, 2, st);
   const int nH = (int)hp.h_items.size();
   hipLaunchKernelGGL(k_H, dim3((nH + 3) / 4), dim3(256), 0, st, V, D, d, nH);
+  stage_mark(plan, 3, st);
   const int nT = (int)hp.t2_items.size();
   hipLaunchKernelGGL(k_T2, dim3((nT + 3) / 4), dim3(256), 0, st, V, K, d, nT);
+  stage_mark(plan, 4, st);
   const int nF = (int)hp.f_items.size();
   hipLaunchKernelGGL(k_final, dim3((nF + 3) / 4), dim3(256), 0, st, K, d, nF);
+  stage_mark(plan, 5, st);
   HIP_TRY(hipGetLastError());
-  if (Ex) return launch_energy(plan, K, D, Ex, st);
-  return EXX_OK;
+  int rc = EXX_OK;
+  if (Ex) rc = launch_energy(plan, K, D, Ex, st);
+  stage_mark(plan, 6, st);
+  return rc;
 }
 
 int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {
