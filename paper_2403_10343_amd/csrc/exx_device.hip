@@ -74,8 +74,10 @@ struct DevPlan {
   EItem* e_items;
   int *ct_run_ptr, *ct_klen;
   Run* runs;
-  HItem* h_items;
-  int *hc_q_ptr, *hc_q, *hc_x_ptr, *hc_x;
+  int *grp_first, *grp_unit_ptr, *grp_col_ptr, *grp_cols;
+  Unit* grp_units;
+  GTile* g_tiles;
+  Slot4 *gq, *gx;
   int* t2_items;
   FItem* f_items;
   int* f_plist;
@@ -97,6 +99,9 @@ struct exx_plan_s {
   bool profiling = false;
   std::vector<hipEvent_t> events;   // MAX_PROFILED * N_STAGE_EV, created lazily
   int n_recorded = 0;
+  int t2_nt = 4;                    // aux tiles of 16 needed by the largest atom
+  size_t h_lds = 0;                 // dynamic LDS bytes of k_H
+  size_t t2_lds = 0;                // dynamic LDS bytes of k_T2
 };
 
 template <typename X>
@@ -271,94 +276,146 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
 }
 
 // ---------------------------------------------------------------------------
-// stage 2: H'_P[(mu, j), c] for a 16-wide aux tile and a 16-wide column tile.
-//   F[mu, l, c] = sum_nu V_PQ[mu, nu] T_Q[(nu, l), c]           (MFMA)
-//   H[(mu, j), c] += sum_l D[j, l] F[mu, l, c]                  (FMA)
-//   H[(nu, l), c in X] += 2 sum_mu' V_XP[mu', nu] E_X[(mu', c), l]  (MFMA, G part)
+// Workgroups are dealt to the eight XCDs in turn.  Tasks are renumbered so
+// that each XCD receives one contiguous range of the (locality-ordered) task
+// list: neighbouring tasks share T / E / D blocks in that XCD's L2.  The grid
+// is padded to a multiple of eight workgroups.
+__device__ __forceinline__ int xcd_task(int n_padded) {
+  const int per = n_padded >> 3;
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
 
-__global__ __launch_bounds__(256) void k_H(const double* __restrict__ V, const double* __restrict__ D,
-                                           DevPlan d, int n_items) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= n_items) return;
-  const int L = threadIdx.x & 63;
+// ---------------------------------------------------------------------------
+// stage 2: H'_P[(mu, j), c] for a group of consecutive atoms (one wavefront
+// per 16-wide aux tile of each group atom) and 16 columns c of the group's
+// second neighbourhood.  For every Q in the tile's Q-list the block
+// T_Q[:, c] is staged once in LDS and shared by all wavefronts, then per
+// column c (two chained MFMAs, the first result feeding the second as its
+// B operand):
+//   F_c[l][mu] = sum_nu T_Q[(nu, l), c] V_PQ[mu, nu]
+//   H_c[j][mu] += sum_l D_PQ[j, l] F_c[l][mu]
+// G part for columns c on atom X in N[P]:
+//   H_c[l][nu] += 2 sum_mu' E_X[(mu', c), l] V_XP[mu', nu].
+
+constexpr int LDS_PITCH = 17;   // doubles per staged row (16 columns + 1: no bank conflicts)
+
+__global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict__ V,
+                                                         const double* __restrict__ D, DevPlan d,
+                                                         int n_tiles, int n_padded) {
+  extern __shared__ double sT[];
+  const int ti = xcd_task(n_padded);
+  if (ti >= n_tiles) return;
+  const GTile tl = d.g_tiles[ti];
+  const int g = tl.grp;
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
-  const HItem it = d.h_items[w];
-  const int P = it.P;
+  const int u0 = d.grp_unit_ptr[g];
+  const bool active = wv < d.grp_unit_ptr[g + 1] - u0;
+  const Unit un = d.grp_units[active ? u0 + wv : u0];
+  const int P = un.P, mu0 = un.mu0, slot = un.slot;
   const int aP = d.na[P], bP = d.nb[P], mP = d.m_loc[P];
   const int s = d.atom_sys[P];
   const int64_t ns = d.sys_n[s];
   const double* Ds = D + d.sys_d_off[s];
-  const int c = it.c0 + lr;
-  const bool cv = c < mP;
-  const int g = cv ? d.col2g[d.col2g_off[P] + c] : -1;
-  const int muA = it.mu0 + lr;  // A-operand row (aux of P)
-  const bool muv = muA < aP;
-  d4 H[NB_MAX];
+  const int* gcol = d.grp_cols + tl.col_beg;
+  const int ncols = tl.ncols;
+  const int muB = mu0 + lr;      // B-operand column (aux of P)
+  const bool muv = muB < aP;
+  d4 Hc[16];
 #pragma unroll
-  for (int j = 0; j < NB_MAX; ++j) H[j] = d4{0, 0, 0, 0};
+  for (int c = 0; c < 16; ++c) Hc[c] = d4{0, 0, 0, 0};
 
-  for (int qi = d.hc_q_ptr[it.hc]; qi < d.hc_q_ptr[it.hc + 1]; ++qi) {
-    const int k = d.hc_q[qi];
-    const int Q = d.nbr_atom[k], p = d.nbr_pair[k];
-    const int aQ = d.na[Q], bQ = d.nb[Q], nQ = d.n_loc[Q];
-    const double* Vp = V + d.v_off[p];
+  // staging role of this thread: column tc, rows r0, r0 + step, ...
+  const int tc = threadIdx.x & 15;
+  const int tstep = blockDim.x >> 4;
+  const int tgc = tc < ncols ? gcol[tc] : -1;
+
+  for (int e = tl.q_beg; e < tl.q_end; ++e) {
+    const Slot4 qe = d.gq[e];
+    const int Q = qe.atom;
+    const int aQ = d.na[Q], bQ = d.nb[Q], nQ = d.n_loc[Q], sQ = aQ * bQ;
+    const int lcq = tgc >= 0 ? d.map1[d.map_off[Q] + tgc] : -1;
     const double* TQ = d.T + d.t_off[Q];
-    const int lcQ = cv ? d.map1[d.map_off[Q] + g] : -1;
-    d4 F[NB_MAX];
-#pragma unroll
-    for (int l = 0; l < NB_MAX; ++l) F[l] = d4{0, 0, 0, 0};
-    for (int n0 = 0; n0 < aQ; n0 += 4) {
-      const int nu = n0 + lk;
-      const bool nv = nu < aQ;
-      const double a = (muv && nv) ? v_elem(Vp, P, Q, aP, aQ, muA, nu) : 0.0;
-      const bool bv = nv && lcQ >= 0;
-      const double* trow = TQ + (size_t)(nu * bQ) * nQ + lcQ;
-#pragma unroll
-      for (int l = 0; l < NB_MAX; ++l)
-        if (l < bQ) F[l] = mfma64(a, bv ? trow[(size_t)l * nQ] : 0.0, F[l]);
-    }
-    const double* Dp = Ds + (size_t)d.bo[P] * ns + d.bo[Q];
-#pragma unroll
-    for (int l = 0; l < NB_MAX; ++l) {
-      if (l >= bQ) break;
-#pragma unroll
-      for (int j = 0; j < NB_MAX; ++j) {
-        if (j >= bP) break;
-        const double dv = Dp[(size_t)j * ns + l];
-        H[j] += dv * F[l];
-      }
-    }
-  }
-  for (int xi = d.hc_x_ptr[it.hc]; xi < d.hc_x_ptr[it.hc + 1]; ++xi) {
-    const int k = d.hc_x[xi];
-    const int X = d.nbr_atom[k], p = d.nbr_pair[k];
-    const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X];
+    __syncthreads();
+    for (int r = threadIdx.x >> 4; r < sQ; r += tstep)
+      sT[r * LDS_PITCH + tc] = lcq >= 0 ? TQ[(size_t)r * nQ + lcq] : 0.0;
+    __syncthreads();
+    const int p = slot == 0 ? qe.p0 : (slot == 1 ? qe.p1 : qe.p2);
+    if (!active || p < 0) continue;
     const double* Vp = V + d.v_off[p];
-    const double* EX = d.E + d.e_off[X];
-    const int* m2X = d.map2 + d.map_off[X];
-    const int iX = g - d.bo[X];
-    const bool xv = cv && iX >= 0 && iX < bX;
-    for (int k0 = 0; k0 < aX; k0 += 4) {
-      const int mu2 = k0 + lk;
-      const bool mv = mu2 < aX;
-      // A[nu][mu'] = 2 V_XP[mu'][nu] = 2 V_PX[nu][mu']
-      const double a = (muv && mv) ? 2.0 * v_elem(Vp, P, X, aP, aX, muA, mu2) : 0.0;
-      const double* erow = EX + (size_t)(mu2 * bX + iX) * mX;
+    const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
+    double vb[NA_MAX / 4];
 #pragma unroll
-      for (int l = 0; l < NB_MAX; ++l) {
-        if (l >= bP) break;
-        const int col = m2X[d.bo[P] + l];
-        H[l] = mfma64(a, (xv && mv) ? erow[col] : 0.0, H[l]);
+    for (int q = 0; q < NA_MAX / 4; ++q) {
+      const int nu = 4 * q + lk;
+      vb[q] = (q < nsQ && muv && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, muB, nu) : 0.0;
+    }
+    double da[NB_MAX / 4];
+    const double* DPQ = Ds + (size_t)d.bo[P] * ns + d.bo[Q];
+#pragma unroll
+    for (int q = 0; q < NB_MAX / 4; ++q) {
+      const int l = 4 * q + lk;
+      da[q] = (lr < bP && l < bQ) ? DPQ[(size_t)lr * ns + l] : 0.0;
+    }
+    const bool lv = lr < bQ;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c < ncols) {
+        d4 F = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < NA_MAX / 4; ++q) {
+          if (q < nsQ) {
+            const int nu = 4 * q + lk;
+            const double a = (lv && nu < aQ) ? sT[(nu * bQ + lr) * LDS_PITCH + c] : 0.0;
+            F = mfma64(a, vb[q], F);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NB_MAX / 4; ++q)
+          if (q < nlQ) Hc[c] = mfma64(da[q], F[q], Hc[c]);
       }
     }
   }
-  double* HP = d.H + d.e_off[P];
+  if (active) {
+    for (int e = tl.x_beg; e < tl.x_end; ++e) {
+      const Slot4 xe = d.gx[e];
+      const int p = slot == 0 ? xe.p0 : (slot == 1 ? xe.p1 : xe.p2);
+      if (p < 0) continue;
+      const int X = xe.atom;
+      const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
+      const double* Vp = V + d.v_off[p];
+      const int colx = lr < bP ? d.map2[d.map_off[X] + d.bo[P] + lr] : 0;
+      const double* EX = d.E + d.e_off[X] + colx;
+      const int nsX = (aX + 3) >> 2;
 #pragma unroll
-  for (int j = 0; j < NB_MAX; ++j) {
-    if (j >= bP) break;
-    for (int v = 0; v < 4; ++v) {
-      const int mu = it.mu0 + lk + 4 * v;
-      if (mu < aP && cv) HP[(size_t)(mu * bP + j) * mP + c] = H[j][v];
+      for (int c = 0; c < 16; ++c) {
+        const int ic = (c < ncols) ? gcol[c] - boX : -1;
+        if (ic >= 0 && ic < bX) {
+#pragma unroll
+          for (int q = 0; q < NA_MAX / 4; ++q) {
+            if (q < nsX) {
+              const int m2 = 4 * q + lk;
+              const bool mv = m2 < aX;
+              const double a = (mv && lr < bP) ? EX[(size_t)(m2 * bX + ic) * mX] : 0.0;
+              const double b = (mv && muv) ? 2.0 * v_elem(Vp, P, X, aP, aX, muB, m2) : 0.0;
+              Hc[c] = mfma64(a, b, Hc[c]);
+            }
+          }
+        }
+      }
+    }
+    double* HP = d.H + d.e_off[P];
+    const int* m2P = d.map2 + d.map_off[P];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int col = (c < ncols) ? m2P[gcol[c]] : -1;
+      if (col >= 0 && muv) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = lk + 4 * v;
+          if (j < bP) HP[(size_t)(muB * bP + j) * mP + col] = Hc[c][v];
+        }
+      }
     }
   }
 }
@@ -366,53 +423,106 @@ __global__ __launch_bounds__(256) void k_H(const double* __restrict__ V, const d
 // ---------------------------------------------------------------------------
 // stage 3: T2[P, Q] = sum_{mu, l} E_P[(mu, i), l] F[mu, k, l],
 //          F[mu, k, l] = sum_nu V_PQ[mu, nu] T_Q[(nu, k), l], l over N[Q].
-// Stage-one accumulator element v is directly the stage-two B operand.
+// One workgroup of four wavefronts per canonical pair.  Columns l are
+// processed in chunks of T2_COLS: the chunk of T_Q and the matching columns
+// of E_P are staged in LDS with coalesced loads; each wavefront takes two
+// columns.  Per column, the stage-one accumulator element v is directly the
+// stage-two B operand.  The four partial sums are added in a fixed order.
 
+constexpr int T2_COLS = 8;
+constexpr int T2_PITCH = T2_COLS + 1;
+
+template <int NT, int NS>
 __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double* __restrict__ K,
-                                            DevPlan d, int n_items) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+                                            DevPlan d, int n_items, int n_padded) {
+  extern __shared__ double sm[];
+  const int w = xcd_task(n_padded);
   if (w >= n_items) return;
-  const int L = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
   const int p = d.t2_items[w];
   const int P = d.pair_a[p], Q = d.pair_b[p];
   const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
+  const int sP = aP * bP, sQ = aQ * bQ;
   const int nQ = d.n_loc[Q], mP = d.m_loc[P];
   const int s = d.atom_sys[P];
   const int64_t ns = d.sys_n[s];
   const double* Vp = V + d.v_off[p];
-  const double* TQ = d.T + d.t_off[Q];
-  const double* EP = d.E + d.e_off[P];
   const int* cg = d.col1g + d.col1g_off[Q];
   const int* m2P = d.map2 + d.map_off[P];
-  d4 acc = d4{0, 0, 0, 0};
-  for (int l = 0; l < nQ; ++l) {
-    const int ce = m2P[cg[l]];
-    for (int mu0 = 0; mu0 < aP; mu0 += 16) {
-      d4 F = d4{0, 0, 0, 0};
-      const int muA = mu0 + lr;
-      for (int n0 = 0; n0 < aQ; n0 += 4) {
-        const int nu = n0 + lk;
-        const bool nv = nu < aQ;
-        const double a = (muA < aP && nv) ? v_elem(Vp, P, Q, aP, aQ, muA, nu) : 0.0;
-        const double b = (nv && lr < bQ) ? TQ[(size_t)(nu * bQ + lr) * nQ + l] : 0.0;
-        F = mfma64(a, b, F);
-      }
+  const double* TQ = d.T + d.t_off[Q];
+  const double* EP = d.E + d.e_off[P];
+  double* sT = sm;                                  // [sQ][T2_PITCH]
+  double* sE = sm + (size_t)sQ * T2_PITCH;          // [sP][T2_PITCH]
+  const int nt = (aP + 15) >> 4, nsr = (aQ + 3) >> 2;
+  double va[NT][NS];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int mu = mu0 + 4 * v + lk;
-        const double a2 = (mu < aP && lr < bP) ? EP[(size_t)(mu * bP + lr) * mP + ce] : 0.0;
-        acc = mfma64(a2, F[v], acc);
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int mu = 16 * t + lr, nu = 4 * q + lk;
+      va[t][q] = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
+    }
+  const bool kv = lr < bQ, iv = lr < bP;
+  // staging role: column tc of the chunk, rows r0, r0 + 32, ...
+  const int tc = threadIdx.x & (T2_COLS - 1);
+  d4 acc = d4{0, 0, 0, 0};
+  for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
+    const int l = l0 + tc;
+    const bool cvld = l < nQ;
+    const int ce = cvld ? m2P[cg[l]] : 0;
+    __syncthreads();
+    for (int r = threadIdx.x >> 3; r < sQ; r += 32) sT[r * T2_PITCH + tc] = cvld ? TQ[(size_t)r * nQ + l] : 0.0;
+    for (int r = threadIdx.x >> 3; r < sP; r += 32) sE[r * T2_PITCH + tc] = cvld ? EP[(size_t)r * mP + ce] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < T2_COLS / 4; ++h) {
+      const int c = wv * (T2_COLS / 4) + h;
+      if (l0 + c < nQ) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (t < nt) {
+            d4 F = d4{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+              if (q < nsr) {
+                const int nu = 4 * q + lk;
+                const double b = (kv && nu < aQ) ? sT[(nu * bQ + lr) * T2_PITCH + c] : 0.0;
+                F = mfma64(va[t][q], b, F);
+              }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int mu = 16 * t + 4 * v + lk;
+              const double a2 = (iv && mu < aP) ? sE[(mu * bP + lr) * T2_PITCH + c] : 0.0;
+              acc = mfma64(a2, F[v], acc);
+            }
+          }
+        }
       }
     }
   }
-  double* Ks = K + d.sys_d_off[s];
-  const int bPo = d.bo[P], bQo = d.bo[Q];
-  for (int v = 0; v < 4; ++v) {
-    const int i = lk + 4 * v, k = lr;
-    if (i < bP && k < bQ) {
-      Ks[(size_t)(bPo + i) * ns + bQo + k] = acc[v];
-      if (P != Q) Ks[(size_t)(bQo + k) * ns + bPo + i] = acc[v];
+  // fixed-order reduction of the four wavefront partials
+  __syncthreads();
+  double* red = sm;
+  for (int v = 0; v < 4; ++v) red[(wv * 4 + v) * 64 + L] = acc[v];
+  __syncthreads();
+  if (wv == 0) {
+    for (int v = 0; v < 4; ++v) {
+      double x = red[v * 64 + L];
+      x += red[(4 + v) * 64 + L];
+      x += red[(8 + v) * 64 + L];
+      x += red[(12 + v) * 64 + L];
+      acc[v] = x;
+    }
+    double* Ks = K + d.sys_d_off[s];
+    const int bPo = d.bo[P], bQo = d.bo[Q];
+    for (int v = 0; v < 4; ++v) {
+      const int i = lk + 4 * v, k = lr;
+      if (i < bP && k < bQ) {
+        Ks[(size_t)(bPo + i) * ns + bQo + k] = acc[v];
+        if (P != Q) Ks[(size_t)(bQo + k) * ns + bPo + i] = acc[v];
+      }
     }
   }
 }
@@ -571,7 +681,8 @@ static int upload_plan(exx_plan_s* pl) {
   UP(pair_a); UP(pair_b); UP(c_off); UP(v_off); UP(n_loc); UP(m_loc);
   UP(map_off); UP(col1g_off); UP(col2g_off); UP(map1); UP(map2); UP(col1g); UP(col2g);
   UP(t_off); UP(e_off); UP(e_items); UP(ct_run_ptr); UP(ct_klen); UP(runs);
-  UP(h_items); UP(hc_q_ptr); UP(hc_q); UP(hc_x_ptr); UP(hc_x); UP(t2_items);
+  UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
+  UP(g_tiles); UP(gq); UP(gx); UP(t2_items);
   UP(f_items); UP(f_plist); UP(en_sys); UP(en_beg); UP(en_end);
 #undef UP
   if ((rc = alloc_buf(pl, d.T, hp.t_total))) return rc;
@@ -635,6 +746,15 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
   if (rc != 0) {
     delete pl;
     return fail(EXX_EDEVICE, err);
+  }
+  {
+    int amax = 1;
+    for (int a = 0; a < pl->hp.n_atoms; ++a) amax = std::max(amax, pl->hp.na[a]);
+    pl->t2_nt = (amax + 15) / 16;
+    int smax = 1;
+    for (int a = 0; a < pl->hp.n_atoms; ++a) smax = std::max(smax, pl->hp.na[a] * pl->hp.nb[a]);
+    pl->h_lds = (size_t)smax * LDS_PITCH * sizeof(double);
+    pl->t2_lds = std::max((size_t)2 * smax * T2_PITCH, (size_t)16 * 64) * sizeof(double);
   }
   if (!pl->host_only) {
     if ((rc = upload_plan(pl)) != 0) {
@@ -749,11 +869,16 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   const int nE = (int)hp.e_items.size();
   hipLaunchKernelGGL(k_E, dim3((nE + 3) / 4), dim3(256), 0, st, D, d, nE);
   stage_mark(plan, 2, st);
-  const int nH = (int)hp.h_items.size();
-  hipLaunchKernelGGL(k_H, dim3((nH + 3) / 4), dim3(256), 0, st, V, D, d, nH);
+  const int nH = (int)hp.g_tiles.size(), nHp = (nH + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_H, dim3(nHp), dim3(64 * hp.h_waves), plan->h_lds, st, V, D, d, nH, nHp);
   stage_mark(plan, 3, st);
-  const int nT = (int)hp.t2_items.size();
-  hipLaunchKernelGGL(k_T2, dim3((nT + 3) / 4), dim3(256), 0, st, V, K, d, nT);
+  const int nT = (int)hp.t2_items.size(), nTp = (nT + 7) / 8 * 8;
+  switch (plan->t2_nt) {
+    case 1: hipLaunchKernelGGL((k_T2<1, 4>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+    case 2: hipLaunchKernelGGL((k_T2<2, 8>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+    case 3: hipLaunchKernelGGL((k_T2<3, 12>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+    default: hipLaunchKernelGGL((k_T2<4, 16>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+  }
   stage_mark(plan, 4, st);
   const int nF = (int)hp.f_items.size();
   hipLaunchKernelGGL(k_final, dim3((nF + 3) / 4), dim3(256), 0, st, K, d, nF);

@@ -23,7 +23,13 @@ constexpr int NA_MAX = 64;   // auxiliary functions per atom supported by the ke
 
 struct Run { int lcol, grow, len; };           // k-range of the E GEMM
 struct EItem { int P, r0, c0, ct; };           // E tile: rows r0.., cols c0.., column tile ct
-struct HItem { int P, mu0, c0, hc; };          // H tile: mu0..mu0+15, cols c0..c0+15, list id hc
+struct Unit { int P, mu0, slot, pad; };        // one wavefront of an H group: atom, aux tile, slot
+struct GTile { int grp, col_beg, ncols, q_beg, q_end, x_beg, x_end, pad; };  // H group x 16 columns
+struct Slot4 { int atom, p0, p1, p2; };      // list entry: atom, pair id with group slots 0..2 (-1: none)
+
+constexpr int GROUP_ATOMS = 3;       // atoms per H group (slots)
+constexpr int GROUP_WAVES = 8;       // wavefronts per H workgroup at most
+constexpr double GROUP_RADIUS = 2.5; // A, group atoms lie within this of the first
 struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)
 
 struct HostPlan {
@@ -55,8 +61,11 @@ struct HostPlan {
   std::vector<EItem> e_items;
   std::vector<int> ct_run_ptr, ct_klen;
   std::vector<Run> runs;
-  std::vector<HItem> h_items;
-  std::vector<int> hc_q_ptr, hc_q, hc_x_ptr, hc_x;
+  std::vector<int> grp_first, grp_unit_ptr, grp_col_ptr, grp_cols;
+  std::vector<Unit> grp_units;
+  std::vector<GTile> g_tiles;
+  std::vector<Slot4> gq, gx;
+  int h_waves = 1;
   std::vector<int> t2_items;                        // canonical pair ids
   std::vector<FItem> f_items;
   std::vector<int> f_plist;

@@ -287,59 +287,103 @@ int derive_lists(HostPlan& hp, std::string& err) {
       }
     }
   }
-  std::stable_sort(hp.e_items.begin(), hp.e_items.end(), [&](const EItem& x, const EItem& y) {
-    return hp.ct_klen[x.ct] > hp.ct_klen[y.ct];
-  });
-  // ---- H tasks: column tiles of 16; Q-lists (V (x) D part) and X-lists (G part)
-  hp.h_items.clear();
-  hp.hc_q_ptr.assign(1, 0);
-  hp.hc_x_ptr.assign(1, 0);
-  hp.hc_q.clear();
-  hp.hc_x.clear();
-  std::vector<int64_t> hc_cost;
+  // ---- H tasks: atom groups (runs of consecutive, nearby atoms of one
+  // system; one wavefront per 16-wide aux tile of each atom) x 16-wide tiles
+  // of the group's second-neighbourhood columns.  Q-lists (V (x) D part) and
+  // X-lists (G part) carry the pair id of every group atom with Q / X.
   for (int a = 0; a < NA; ++a) {
-    const int aP = hp.na[a], bP = hp.nb[a], mP = hp.m_loc[a];
+    const int aP = hp.na[a], bP = hp.nb[a];
     for (int k = np[a]; k < np[a + 1]; ++k) {
       int q = nat[k];
       hp.flops[2] += 2LL * aP * hp.na[q] * hp.nb[q] * hp.n_loc[q];   // F = V T
       hp.flops[2] += 2LL * aP * bP * hp.nb[q] * hp.n_loc[q];          // D contraction
       hp.flops[2] += 2LL * aP * hp.na[q] * bP * hp.nb[q];             // G part
     }
-    for (int c0 = 0; c0 < mP; c0 += 16) {
+  }
+  hp.grp_first.clear();
+  hp.grp_unit_ptr.assign(1, 0);
+  hp.grp_units.clear();
+  hp.grp_col_ptr.assign(1, 0);
+  hp.grp_cols.clear();
+  hp.g_tiles.clear();
+  hp.gq.clear();
+  hp.gx.clear();
+  hp.h_waves = 1;
+  {
+    const double gr2 = GROUP_RADIUS * GROUP_RADIUS;
+    int a = 0;
+    while (a < NA) {
+      const int s = hp.atom_sys[a];
+      int n = 1, units = (hp.na[a] + 15) / 16;
+      while (a + n < NA && n < GROUP_ATOMS && hp.atom_sys[a + n] == s) {
+        const int b = a + n;
+        const int u = (hp.na[b] + 15) / 16;
+        double dx = hp.pos[3 * a] - hp.pos[3 * b], dy = hp.pos[3 * a + 1] - hp.pos[3 * b + 1],
+               dz = hp.pos[3 * a + 2] - hp.pos[3 * b + 2];
+        if (units + u > GROUP_WAVES || dx * dx + dy * dy + dz * dz > gr2) break;
+        units += u;
+        ++n;
+      }
+      const int g = (int)hp.grp_first.size();
+      hp.grp_first.push_back(a);
+      for (int t = 0; t < n; ++t)
+        for (int mu0 = 0; mu0 < hp.na[a + t]; mu0 += 16) hp.grp_units.push_back(Unit{a + t, mu0, t, 0});
+      hp.grp_unit_ptr.push_back((int)hp.grp_units.size());
+      hp.h_waves = std::max(hp.h_waves, units);
+      // union of N2 over the group, as system basis columns
       ++stampv;
-      int c1 = std::min(mP, c0 + 16);
-      {
-        int c = 0;
-        for (int k = hp.n2_ptr[a]; k < hp.n2_ptr[a + 1]; ++k) {
+      std::vector<int> atoms;
+      for (int t = 0; t < n; ++t)
+        for (int k = hp.n2_ptr[a + t]; k < hp.n2_ptr[a + t + 1]; ++k) {
           int l = hp.n2_atom[k];
-          if (c < c1 && c + hp.nb[l] > c0) stamp2[l] = stampv;
-          c += hp.nb[l];
-          if (c >= c1) break;
+          if (stamp2[l] != stampv) { stamp2[l] = stampv; atoms.push_back(l); }
         }
+      std::sort(atoms.begin(), atoms.end());
+      const int col0 = (int)hp.grp_cols.size();
+      std::vector<int> col_atom;
+      for (int l : atoms)
+        for (int x = 0; x < hp.nb[l]; ++x) { hp.grp_cols.push_back(hp.bo[l] + x); col_atom.push_back(l); }
+      hp.grp_col_ptr.push_back((int)hp.grp_cols.size());
+      const int ncol = (int)col_atom.size();
+      // neighbours of the group (union of N[P]) with the pair id per group slot
+      std::vector<int> nbrs;
+      ++stampv;
+      for (int t = 0; t < n; ++t)
+        for (int k = np[a + t]; k < np[a + t + 1]; ++k)
+          if (stamp2[nat[k]] != stampv) { stamp2[nat[k]] = stampv; nbrs.push_back(nat[k]); }
+      std::sort(nbrs.begin(), nbrs.end());
+      auto pair_slots = [&](int q) {
+        Slot4 e{q, -1, -1, -1};
+        int* sl = &e.p0;
+        for (int t = 0; t < n; ++t) {
+          auto it = std::lower_bound(nat.begin() + np[a + t], nat.begin() + np[a + t + 1], q);
+          if (it != nat.begin() + np[a + t + 1] && *it == q) sl[t] = hp.nbr_pair[it - nat.begin()];
+        }
+        return e;
+      };
+      for (int c0 = 0; c0 < ncol; c0 += 16) {
+        const int c1 = std::min(ncol, c0 + 16);
+        ++stampv;
+        for (int c = c0; c < c1; ++c) stamp2[col_atom[c]] = stampv;
+        GTile tl{};
+        tl.grp = g;
+        tl.col_beg = col0 + c0;
+        tl.ncols = c1 - c0;
+        tl.q_beg = (int)hp.gq.size();
+        tl.x_beg = (int)hp.gx.size();
+        for (int q : nbrs) {
+          bool rel = false;
+          for (int k2 = np[q]; k2 < np[q + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
+          if (rel) hp.gq.push_back(pair_slots(q));
+          if (stamp2[q] == stampv) hp.gx.push_back(pair_slots(q));
+        }
+        tl.q_end = (int)hp.gq.size();
+        tl.x_end = (int)hp.gx.size();
+        hp.g_tiles.push_back(tl);
       }
-      const int hc = (int)hc_cost.size();
-      int64_t cost = 0;
-      for (int k = np[a]; k < np[a + 1]; ++k) {
-        int q = nat[k];
-        bool rel = false;
-        for (int k2 = np[q]; k2 < np[q + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
-        if (rel) {
-          hp.hc_q.push_back(k);
-          cost += (int64_t)((hp.na[q] + 3) / 4) * hp.nb[q] * 16 + (int64_t)hp.nb[q] * bP;
-        }
-        if (stamp2[q] == stampv) {
-          hp.hc_x.push_back(k);
-          cost += (int64_t)((hp.na[q] + 3) / 4) * bP * 16;
-        }
-      }
-      hp.hc_q_ptr.push_back((int)hp.hc_q.size());
-      hp.hc_x_ptr.push_back((int)hp.hc_x.size());
-      hc_cost.push_back(cost);
-      for (int mu0 = 0; mu0 < aP; mu0 += 16) hp.h_items.push_back(HItem{a, mu0, c0, hc});
+      a += n;
     }
   }
-  std::stable_sort(hp.h_items.begin(), hp.h_items.end(),
-                   [&](const HItem& x, const HItem& y) { return hc_cost[x.hc] > hc_cost[y.hc]; });
   // ---- T2 tasks: every canonical pair
   hp.t2_items.resize(npairs);
   std::iota(hp.t2_items.begin(), hp.t2_items.end(), 0);
@@ -347,10 +391,6 @@ int derive_lists(HostPlan& hp, std::string& err) {
     int a = hp.pair_a[p], b = hp.pair_b[p];
     hp.flops[3] += 2LL * hp.na[a] * hp.na[b] * hp.nb[b] * hp.n_loc[b] + 2LL * hp.na[a] * hp.nb[a] * hp.nb[b] * hp.n_loc[b];
   }
-  std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) {
-    auto cst = [&](int p) { int b = hp.pair_b[p]; return (int64_t)hp.na[hp.pair_a[p]] * hp.na[b] * hp.n_loc[b]; };
-    return cst(x) > cst(y);
-  });
   // ---- final tasks: 32 x 32 tile pairs (upper triangle) with their P-lists
   hp.f_items.clear();
   hp.f_plist.clear();
