@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the exchange build here runs on a single MI355X "
@@ -133,9 +135,19 @@ def main():
         "stage_ms": {names[i]: float(avg_ms[i]) for i in range(len(names))},
         "stage_tflops": {names[i]: (plan.flops(i) / (avg_ms[i] * 1e-3) / 1e12 if i <= 4 and avg_ms[i] > 0 else 0.0)
                          for i in range(len(names))},
+        "stage_issued_mfma_frac": {names[i]: (plan.flops(10 + i) / (avg_ms[i] * 1e-3) / PEAK["fp64"]
+                                              if i <= 4 and avg_ms[i] > 0 else 0.0) for i in range(len(names))},
         "E_x": e_x,
         "E_x_per_atom": e_x / sysm.n_atoms,
     }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, seconds=args.cpu_seconds)
     print(json.dumps(out), flush=True)

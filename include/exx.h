@@ -153,7 +153,10 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
                       double c_decay, double v_2s2, void* stream);
 
 /* Algorithmic flop count of one stage of build_K (stage -1 = total):
- * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction. */
+ * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction:
+ * 2*m*n*k summed over the structurally nonzero blocks.  Stages 10..14 give
+ * the flops the MFMA instructions of stage 0..4 actually issue (tile padding
+ * included). */
 int64_t exx_plan_flops(exx_plan plan, int stage);
 
 /* Instrumentation: when enabled, build_K records HIP events on its stream at

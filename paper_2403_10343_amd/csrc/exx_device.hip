@@ -82,7 +82,9 @@ struct DevPlan {
   FItem* f_items;
   int* f_plist;
   int *en_sys, *en_beg, *en_end;
-  double *T, *E, *H, *epart;
+  YTile* y_tiles;
+  int64_t* y_off;
+  double *T, *E, *H, *Y, *epart;
 };
 
 constexpr int N_STAGE_EV = 7;   // boundaries: start, repack, E, H, T2, final, energy
@@ -303,6 +305,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
                                                          const double* __restrict__ D, DevPlan d,
                                                          int n_tiles, int n_padded) {
   extern __shared__ double sT[];
+  __shared__ int sColQ[16];
   const int ti = xcd_task(n_padded);
   if (ti >= n_tiles) return;
   const GTile tl = d.g_tiles[ti];
@@ -337,6 +340,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
     const int lcq = tgc >= 0 ? d.map1[d.map_off[Q] + tgc] : -1;
     const double* TQ = d.T + d.t_off[Q];
     __syncthreads();
+    if (threadIdx.x < 16) sColQ[tc] = lcq >= 0;
     for (int r = threadIdx.x >> 4; r < sQ; r += tstep)
       sT[r * LDS_PITCH + tc] = lcq >= 0 ? TQ[(size_t)r * nQ + lcq] : 0.0;
     __syncthreads();
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
     const bool lv = lr < bQ;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      if (c < ncols) {
+      if (c < ncols && sColQ[c]) {
         d4 F = d4{0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < NA_MAX / 4; ++q) {
@@ -440,8 +444,9 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
   if (w >= n_items) return;
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
-  const int p = d.t2_items[w];
-  const int P = d.pair_a[p], Q = d.pair_b[p];
+  const int p = d.t2_items[w] >> 1;
+  const bool flip = d.t2_items[w] & 1;
+  const int P = flip ? d.pair_b[p] : d.pair_a[p], Q = flip ? d.pair_a[p] : d.pair_b[p];
   const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
   const int sP = aP * bP, sQ = aQ * bQ;
   const int nQ = d.n_loc[Q], mP = d.m_loc[P];
@@ -528,71 +533,149 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
 }
 
 // ---------------------------------------------------------------------------
-// stage 4: K = T2 + (X + X^T)/2 with X = sum_P T_P^T H'_P, 32 x 32 tile pairs
-// of the upper triangle, each written once together with its mirror.
+// stage 4a: Y_P = T_P^T H'_P for every aux atom P (n_P x m_P, K = s_P), a
+// batched GEMM with both operands stored k-major.  64 x 64 tile per
+// workgroup of four wavefronts (32 x 32 each), k-steps of 16 staged in
+// double-buffered LDS with coalesced row loads.
 
-__global__ __launch_bounds__(256) void k_final(double* __restrict__ K, DevPlan d, int n_items) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+constexpr int YT = 64, YK = 16, YPITCH = YT + 4;
+
+__global__ __launch_bounds__(256) void k_Y(DevPlan d, int n_tiles, int n_padded) {
+  __shared__ double As[2][YK][YPITCH];
+  __shared__ double Bs[2][YK][YPITCH];
+  const int ti = xcd_task(n_padded);
+  if (ti >= n_tiles) return;
+  const YTile yt = d.y_tiles[ti];
+  const int P = yt.P;
+  const int Kd = d.na[P] * d.nb[P], M = d.n_loc[P], N = d.m_loc[P];
+  const double* A = d.T + d.t_off[P];   // A(m, k) = T_P[k * M + m]
+  const double* B = d.H + d.e_off[P];   // B(k, n) = H'_P[k * N + n]
+  const int t = threadIdx.x;
+  const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  // global -> LDS staging role: row kr = t / 16 of the k-step, 4 columns
+  const int kr = t >> 4, cc = (t & 15) * 4;
+  double ra[4], rb[4];
+  auto gload = [&](int k0) {
+    const int k = k0 + kr;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int m = yt.m0 + cc + x, n = yt.n0 + cc + x;
+      ra[x] = (k < Kd && m < M) ? A[(size_t)k * M + m] : 0.0;
+      rb[x] = (k < Kd && n < N) ? B[(size_t)k * N + n] : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      As[buf][kr][cc + x] = ra[x];
+      Bs[buf][kr][cc + x] = rb[x];
+    }
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < Kd; k0 += YK) {
+    const bool more = k0 + YK < Kd;
+    if (more) gload(k0 + YK);
+#pragma unroll
+    for (int ks = 0; ks < YK; ks += 4) {
+      double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
+      double b0 = Bs[buf][ks + lk][wn + lr], b1 = Bs[buf][ks + lk][wn + 16 + lr];
+      acc[0][0] = mfma64(a0, b0, acc[0][0]);
+      acc[0][1] = mfma64(a0, b1, acc[0][1]);
+      acc[1][0] = mfma64(a1, b0, acc[1][0]);
+      acc[1][1] = mfma64(a1, b1, acc[1][1]);
+    }
+    if (more) {
+      sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  double* Y = d.Y + d.y_off[P];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int n = yt.n0 + wn + 16 * y + lr;
+      if (n >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = yt.m0 + wm + 16 * x + lk + 4 * v;
+        if (m < M) Y[(size_t)m * N + n] = acc[x][y][v];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage 4b: K = T2 + (X + X^T)/2 with X[i, l] = sum_P Y_P[c1_P(i), c2_P(l)]
+// (c1: column of T_P, c2: column of H'_P).  One workgroup per 32 x 32 tile
+// pair of the upper triangle; the aux atoms of its list are visited in a
+// fixed order.  X[i, l] is gathered with l fastest across threads and
+// X[l, i] with i fastest (both coalesced), the two halves are combined in
+// LDS, and every element is written together with its mirror.
+
+__global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPlan d, int n_items,
+                                                   int n_padded) {
+  __shared__ int cmap[4][32];      // c1(I rows), c2(I rows), c1(L cols), c2(L cols)
+  __shared__ double xa[32][33], xb[32][33];
+  const int w = xcd_task(n_padded);
   if (w >= n_items) return;
-  const int L = threadIdx.x & 63;
-  const int lr = L & 15, lk = L >> 4;
   const FItem it = d.f_items[w];
   const int s = it.sys;
   const int64_t ns = d.sys_n[s];
-  int gI[2], gL[2];
-  for (int h = 0; h < 2; ++h) {
-    gI[h] = it.gI0 + 16 * h + lr;
-    gL[h] = it.gL0 + 16 * h + lr;
-  }
-  d4 acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  const int t = threadIdx.x;
+  const int ta = t & 31, tb = t >> 5;   // element (tb + 8 r, ta)
+  double acc_a[4] = {0, 0, 0, 0}, acc_b[4] = {0, 0, 0, 0};
   for (int pi = it.pbeg; pi < it.pend; ++pi) {
     const int P = d.f_plist[pi];
-    const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
-    const int* m1 = d.map1 + d.map_off[P];
-    const int* m2 = d.map2 + d.map_off[P];
-    const double* TP = d.T + d.t_off[P];
-    const double* HP = d.H + d.e_off[P];
-    int cI1[2], cI2[2], cL1[2], cL2[2];
-    for (int h = 0; h < 2; ++h) {
-      cI1[h] = gI[h] < ns ? m1[gI[h]] : -1;
-      cI2[h] = gI[h] < ns ? m2[gI[h]] : -1;
-      cL1[h] = gL[h] < ns ? m1[gL[h]] : -1;
-      cL2[h] = gL[h] < ns ? m2[gL[h]] : -1;
+    const int nP_ = d.m_loc[P];
+    const double* Y = d.Y + d.y_off[P];
+    __syncthreads();
+    if (t < 128) {
+      const int which = t >> 5, x = t & 31;
+      const int g = ((which < 2) ? it.gI0 : it.gL0) + x;
+      const int* mp = ((which & 1) ? d.map2 : d.map1) + d.map_off[P];
+      cmap[which][x] = g < ns ? mp[g] : -1;
     }
-    for (int r0 = 0; r0 < sP; r0 += 4) {
-      const int r = r0 + lk;
-      const bool rv = r < sP;
-      const double* Tr = TP + (size_t)r * nP;
-      const double* Hr = HP + (size_t)r * mP;
-      double aT[2], aH[2], bH[2], bT[2];
-      for (int h = 0; h < 2; ++h) {
-        aT[h] = (rv && cI1[h] >= 0) ? Tr[cI1[h]] : 0.0;
-        aH[h] = (rv && cI2[h] >= 0) ? Hr[cI2[h]] : 0.0;
-        bH[h] = (rv && cL2[h] >= 0) ? Hr[cL2[h]] : 0.0;
-        bT[h] = (rv && cL1[h] >= 0) ? Tr[cL1[h]] : 0.0;
-      }
-      for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) {
-          acc[x][y] = mfma64(aT[x], bH[y], acc[x][y]);
-          acc[x][y] = mfma64(aH[x], bT[y], acc[x][y]);
-        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = tb + 8 * r;
+      // X[i = I0 + ii, l = L0 + ta] = Y_P[c1(i), c2(l)]
+      const int c1 = cmap[0][ii], c2 = cmap[3][ta];
+      if (c1 >= 0 && c2 >= 0) acc_a[r] += Y[(size_t)c1 * nP_ + c2];
+      // X[l = L0 + ii, i = I0 + ta] = Y_P[c1(l), c2(i)], stored at (ta, ii)
+      const int d1 = cmap[2][ii], d2 = cmap[1][ta];
+      if (d1 >= 0 && d2 >= 0) acc_b[r] += Y[(size_t)d1 * nP_ + d2];
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    xa[tb + 8 * r][ta] = acc_a[r];
+    xb[ta][tb + 8 * r] = acc_b[r];
+  }
+  __syncthreads();
   double* Ks = K + d.sys_d_off[s];
   const bool diag = it.gI0 == it.gL0;
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y)
-      for (int v = 0; v < 4; ++v) {
-        const int i = it.gI0 + 16 * x + lk + 4 * v;
-        const int l = it.gL0 + 16 * y + lr;
-        if (i >= ns || l >= ns) continue;
-        if (diag && i > l) continue;
-        const double val = Ks[(size_t)i * ns + l] + 0.5 * acc[x][y][v];
-        Ks[(size_t)i * ns + l] = val;
-        if (i != l) Ks[(size_t)l * ns + i] = val;
-      }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ii = tb + 8 * r, ll = ta;
+    const int i = it.gI0 + ii, l = it.gL0 + ll;
+    if (i >= ns || l >= ns) continue;
+    if (diag && i > l) continue;
+    const double val = Ks[(size_t)i * ns + l] + 0.5 * (xa[ii][ll] + xb[ii][ll]);
+    Ks[(size_t)i * ns + l] = val;
+    if (i != l) Ks[(size_t)l * ns + i] = val;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -683,11 +766,12 @@ static int upload_plan(exx_plan_s* pl) {
   UP(t_off); UP(e_off); UP(e_items); UP(ct_run_ptr); UP(ct_klen); UP(runs);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
   UP(g_tiles); UP(gq); UP(gx); UP(t2_items);
-  UP(f_items); UP(f_plist); UP(en_sys); UP(en_beg); UP(en_end);
+  UP(f_items); UP(f_plist); UP(en_sys); UP(en_beg); UP(en_end); UP(y_tiles); UP(y_off);
 #undef UP
   if ((rc = alloc_buf(pl, d.T, hp.t_total))) return rc;
   if ((rc = alloc_buf(pl, d.E, hp.e_total))) return rc;
   if ((rc = alloc_buf(pl, d.H, hp.e_total))) return rc;
+  if ((rc = alloc_buf(pl, d.Y, hp.y_total))) return rc;
   if ((rc = alloc_buf(pl, d.epart, (int64_t)hp.en_sys.size()))) return rc;
   return 0;
 }
@@ -812,6 +896,7 @@ int64_t exx_plan_flops(exx_plan plan, int stage) {
   if (!plan) return -1;
   const HostPlan& hp = plan->hp;
   if (stage < 0) return hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
+  if (stage >= 10 && stage <= 14) return hp.issued[stage - 10];
   if (stage > 4) return -1;
   return hp.flops[stage];
 }
@@ -880,8 +965,10 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
     default: hipLaunchKernelGGL((k_T2<4, 16>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
   }
   stage_mark(plan, 4, st);
-  const int nF = (int)hp.f_items.size();
-  hipLaunchKernelGGL(k_final, dim3((nF + 3) / 4), dim3(256), 0, st, K, d, nF);
+  const int nY = (int)hp.y_tiles.size(), nYp = (nY + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_Y, dim3(nYp), dim3(256), 0, st, d, nY, nYp);
+  const int nF = (int)hp.f_items.size(), nFp = (nF + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_symreduce, dim3(nFp), dim3(256), 0, st, K, d, nF, nFp);
   stage_mark(plan, 5, st);
   HIP_TRY(hipGetLastError());
   int rc = EXX_OK;

@@ -379,17 +379,40 @@ int derive_lists(HostPlan& hp, std::string& err) {
         }
         tl.q_end = (int)hp.gq.size();
         tl.x_end = (int)hp.gx.size();
+        for (int e = tl.q_beg; e < tl.q_end; ++e) {
+          const int q = hp.gq[e].atom;
+          const int* sl = &hp.gq[e].p0;
+          for (int t = 0; t < n; ++t)
+            if (sl[t] >= 0)
+              hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * tl.ncols *
+                              (((hp.na[q] + 3) / 4) + ((hp.nb[q] + 3) / 4));
+        }
+        for (int e = tl.x_beg; e < tl.x_end; ++e) {
+          const int x = hp.gx[e].atom;
+          const int* sl = &hp.gx[e].p0;
+          int cx = 0;
+          for (int c = c0; c < c1; ++c) cx += (col_atom[c] == x);
+          for (int t = 0; t < n; ++t)
+            if (sl[t] >= 0) hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * cx * ((hp.na[x] + 3) / 4);
+        }
         hp.g_tiles.push_back(tl);
       }
       a += n;
     }
   }
-  // ---- T2 tasks: every canonical pair
+  // ---- T2 tasks: every canonical pair, oriented (bit 0) so that the atom
+  // with fewer 16-wide aux tiles is the row side P (less MFMA padding)
   hp.t2_items.resize(npairs);
-  std::iota(hp.t2_items.begin(), hp.t2_items.end(), 0);
   for (int64_t p = 0; p < npairs; ++p) {
     int a = hp.pair_a[p], b = hp.pair_b[p];
+    auto cost = [&](int x, int y) {
+      return (int64_t)((hp.na[x] + 15) / 16) * (((hp.na[y] + 3) / 4) + 4) * hp.n_loc[y];
+    };
+    const bool flip = cost(b, a) < cost(a, b);
+    if (flip) std::swap(a, b);
+    hp.t2_items[p] = (int)(2 * p + (flip ? 1 : 0));
     hp.flops[3] += 2LL * hp.na[a] * hp.na[b] * hp.nb[b] * hp.n_loc[b] + 2LL * hp.na[a] * hp.nb[a] * hp.nb[b] * hp.n_loc[b];
+    hp.issued[3] += 2048LL * cost(a, b);
   }
   // ---- final tasks: 32 x 32 tile pairs (upper triangle) with their P-lists
   hp.f_items.clear();
@@ -437,13 +460,24 @@ int derive_lists(HostPlan& hp, std::string& err) {
         int64_t cost = 0;
         for (int a : v) { hp.f_plist.push_back(a); cost += (int64_t)hp.na[a] * hp.nb[a]; }
         f.pend = (int)hp.f_plist.size();
-        hp.issued[4] += 2LL * 2 * 32 * 32 * cost;
+
         fcost.push_back({cost, (int)fit.size()});
         fit.push_back(f);
       }
   }
   std::stable_sort(fcost.begin(), fcost.end(), [](auto& x, auto& y) { return x.first > y.first; });
   for (auto& c : fcost) hp.f_items.push_back(fit[c.second]);
+  // ---- Y_P = T_P^T H'_P tiles (64 x 64), P-major for L2 locality
+  hp.y_off.assign(NA + 1, 0);
+  hp.y_tiles.clear();
+  for (int a = 0; a < NA; ++a) {
+    hp.y_off[a + 1] = hp.y_off[a] + ceil_to((int64_t)hp.n_loc[a] * hp.m_loc[a], 2);
+    for (int n0 = 0; n0 < hp.m_loc[a]; n0 += 64)
+      for (int m0 = 0; m0 < hp.n_loc[a]; m0 += 64) hp.y_tiles.push_back(YTile{a, m0, n0, 0});
+  }
+  hp.y_total = hp.y_off[NA];
+  hp.issued[4] = 0;
+  for (const auto& t : hp.y_tiles) hp.issued[4] += 2LL * 64 * 64 * ceil_to((int64_t)hp.na[t.P] * hp.nb[t.P], 16);
   // ---- energy chunks
   hp.en_sys.clear();
   hp.en_beg.clear();
