@@ -74,6 +74,10 @@ struct DevPlan {
   EItem* e_items;
   int *ct_run_ptr, *ct_klen;
   Run* runs;
+  EItem* gd_items;
+  int *gd_run_ptr, *gd_klen;
+  Run* gd_runs;
+  double* pos;
   int *grp_first, *grp_unit_ptr, *grp_col_ptr, *grp_cols;
   Unit* grp_units;
   GTile* g_tiles;
@@ -84,7 +88,7 @@ struct DevPlan {
   int *en_sys, *en_beg, *en_end;
   YTile* y_tiles;
   int64_t* y_off;
-  double *T, *E, *H, *Y, *epart;
+  double *T, *E, *H, *Y, *GD, *sC, *sV, *epart;
 };
 
 constexpr int N_STAGE_EV = 7;   // boundaries: start, repack, E, H, T2, final, energy
@@ -104,6 +108,8 @@ struct exx_plan_s {
   int t2_nt = 4;                    // aux tiles of 16 needed by the largest atom
   size_t h_lds = 0;                 // dynamic LDS bytes of k_H
   size_t t2_lds = 0;                // dynamic LDS bytes of k_T2
+  double* dC_scratch = nullptr;     // gradient buffers used when the caller passes NULL
+  double* dV_scratch = nullptr;
 };
 
 template <typename X>
@@ -209,75 +215,6 @@ __global__ __launch_bounds__(256) void k_repack(const double* __restrict__ C, De
 }
 
 // ---------------------------------------------------------------------------
-// stage 1: E_P = T_P D, 32 x 32 output per wavefront, k over runs of relevant
-// neighbours (block-sparse D).
-
-__global__ __launch_bounds__(256) void k_E(const double* __restrict__ D, DevPlan d, int n_items) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= n_items) return;
-  const int L = threadIdx.x & 63;
-  const int lr = L & 15, lk = L >> 4;
-  const EItem it = d.e_items[w];
-  const int P = it.P;
-  const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
-  const int s = d.atom_sys[P];
-  const int64_t ns = d.sys_n[s];
-  const double* Ds = D + d.sys_d_off[s];
-  const double* TP = d.T + d.t_off[P];
-  int gc[2];
-  for (int h = 0; h < 2; ++h) {
-    const int c = it.c0 + 16 * h + lr;
-    gc[h] = (c < mP) ? d.col2g[d.col2g_off[P] + c] : -1;
-  }
-  const int row0 = it.r0 + lr, row1 = it.r0 + 16 + lr;
-  const bool rv0 = row0 < sP, rv1 = row1 < sP;
-  d4 acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
-  const int rb = d.ct_run_ptr[it.ct], re = d.ct_run_ptr[it.ct + 1];
-  const int klen = d.ct_klen[it.ct];
-  int r = rb, rstart = 0;
-  for (int kb = 0; kb < klen; kb += 4) {
-    while (kb >= rstart + d.runs[r].len) { rstart += d.runs[r].len; ++r; }
-    const int kk = kb + lk;
-    const bool kv = kk < klen;
-    int lc = 0, gr = 0;
-    if (kv) {
-      int rr = r, off = kk - rstart;
-      const Run R0 = d.runs[r];
-      if (off >= R0.len) { off -= R0.len; rr = r + 1; }
-      const Run R = (rr == r) ? R0 : d.runs[rr];
-      lc = R.lcol + off;
-      gr = R.grow + off;
-    }
-    (void)re;
-    const double a0 = (kv && rv0) ? TP[(size_t)row0 * nP + lc] : 0.0;
-    const double a1 = (kv && rv1) ? TP[(size_t)row1 * nP + lc] : 0.0;
-    const double b0 = (kv && gc[0] >= 0) ? Ds[(size_t)gr * ns + gc[0]] : 0.0;
-    const double b1 = (kv && gc[1] >= 0) ? Ds[(size_t)gr * ns + gc[1]] : 0.0;
-    acc[0][0] = mfma64(a0, b0, acc[0][0]);
-    acc[0][1] = mfma64(a0, b1, acc[0][1]);
-    acc[1][0] = mfma64(a1, b0, acc[1][0]);
-    acc[1][1] = mfma64(a1, b1, acc[1][1]);
-  }
-  double* EP = d.E + d.e_off[P];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) {
-      const int col = it.c0 + 16 * y + lr;
-      if (col >= mP) continue;
-      for (int v = 0; v < 4; ++v) {
-        const int row = it.r0 + 16 * x + lk + 4 * v;
-        if (row < sP) EP[(size_t)row * mP + col] = acc[x][y][v];
-      }
-    }
-}
-
-// V_PQ[mu][nu] (mu on P, nu on Q) from the canonical V block of pair p.
-__device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP, int aQ, int mu, int nu) {
-  return (P <= Q) ? Vp[mu * aQ + nu] : Vp[nu * aP + mu];
-}
-
-// ---------------------------------------------------------------------------
 // Workgroups are dealt to the eight XCDs in turn.  Tasks are renumbered so
 // that each XCD receives one contiguous range of the (locality-ordered) task
 // list: neighbouring tasks share T / E / D blocks in that XCD's L2.  The grid
@@ -285,6 +222,92 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
 __device__ __forceinline__ int xcd_task(int n_padded) {
   const int per = n_padded >> 3;
   return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// stage 1 (and its adjoint): O_P = A_P D restricted to block-sparse D, where
+// A_P has s_P rows.  Forward: A = T_P (columns N[P]), O = E_P (columns
+// N2[P]).  Gradient: A = H_P (columns N2[P]), O = G_P (columns N[P]).  One
+// 32 x 32 output tile per wavefront; k runs over the runs of input atoms J
+// whose neighbourhood meets the tile's atoms.
+
+struct RowD {
+  const double* A;
+  const int64_t* a_off;
+  const int* a_ld;
+  double* O;
+  const int64_t* o_off;
+  const int* o_ld;
+  const int* ocolg;
+  const int64_t* ocolg_off;
+  const EItem* items;
+  const int* run_ptr;
+  const int* klen;
+  const Run* runs;
+};
+
+__global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
+                                              int n_padded) {
+  const int w = xcd_task(n_padded) * 4 + (threadIdx.x >> 6);
+  if (w >= n_items) return;
+  const int L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const EItem it = r.items[w];
+  const int P = it.P;
+  const int sP = d.na[P] * d.nb[P], lda = r.a_ld[P], ldo = r.o_ld[P];
+  const int s = d.atom_sys[P];
+  const int64_t ns = d.sys_n[s];
+  const double* Ds = D + d.sys_d_off[s];
+  const double* AP = r.A + r.a_off[P];
+  int gc[2];
+  for (int h = 0; h < 2; ++h) {
+    const int c = it.c0 + 16 * h + lr;
+    gc[h] = (c < ldo) ? r.ocolg[r.ocolg_off[P] + c] : -1;
+  }
+  const int row0 = it.r0 + lr, row1 = it.r0 + 16 + lr;
+  const bool rv0 = row0 < sP, rv1 = row1 < sP;
+  d4 acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  const int klen = r.klen[it.ct];
+  int rr0 = r.run_ptr[it.ct], rstart = 0;
+  for (int kb = 0; kb < klen; kb += 4) {
+    while (kb >= rstart + r.runs[rr0].len) { rstart += r.runs[rr0].len; ++rr0; }
+    const int kk = kb + lk;
+    const bool kv = kk < klen;
+    int lc = 0, gr = 0;
+    if (kv) {
+      int q = rr0, off = kk - rstart;
+      const Run R0 = r.runs[rr0];
+      if (off >= R0.len) { off -= R0.len; q = rr0 + 1; }
+      const Run R = (q == rr0) ? R0 : r.runs[q];
+      lc = R.lcol + off;
+      gr = R.grow + off;
+    }
+    const double a0 = (kv && rv0) ? AP[(size_t)row0 * lda + lc] : 0.0;
+    const double a1 = (kv && rv1) ? AP[(size_t)row1 * lda + lc] : 0.0;
+    const double b0 = (kv && gc[0] >= 0) ? Ds[(size_t)gr * ns + gc[0]] : 0.0;
+    const double b1 = (kv && gc[1] >= 0) ? Ds[(size_t)gr * ns + gc[1]] : 0.0;
+    acc[0][0] = mfma64(a0, b0, acc[0][0]);
+    acc[0][1] = mfma64(a0, b1, acc[0][1]);
+    acc[1][0] = mfma64(a1, b0, acc[1][0]);
+    acc[1][1] = mfma64(a1, b1, acc[1][1]);
+  }
+  double* OP = r.O + r.o_off[P];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) {
+      const int col = it.c0 + 16 * y + lr;
+      if (col >= ldo) continue;
+      for (int v = 0; v < 4; ++v) {
+        const int row = it.r0 + 16 * x + lk + 4 * v;
+        if (row < sP) OP[(size_t)row * ldo + col] = acc[x][y][v];
+      }
+    }
+}
+
+// V_PQ[mu][nu] (mu on P, nu on Q) from the canonical V block of pair p.
+__device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP, int aQ, int mu, int nu) {
+  return (P <= Q) ? Vp[mu * aQ + nu] : Vp[nu * aP + mu];
 }
 
 // ---------------------------------------------------------------------------
@@ -303,7 +326,8 @@ constexpr int LDS_PITCH = 17;   // doubles per staged row (16 columns + 1: no ba
 
 __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict__ V,
                                                          const double* __restrict__ D, DevPlan d,
-                                                         int n_tiles, int n_padded) {
+                                                         int n_tiles, int n_padded, double gscale,
+                                                         int g_only) {
   extern __shared__ double sT[];
   __shared__ int sColQ[16];
   const int ti = xcd_task(n_padded);
@@ -333,7 +357,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
   const int tstep = blockDim.x >> 4;
   const int tgc = tc < ncols ? gcol[tc] : -1;
 
-  for (int e = tl.q_beg; e < tl.q_end; ++e) {
+  for (int e = g_only ? tl.q_end : tl.q_beg; e < tl.q_end; ++e) {
     const Slot4 qe = d.gq[e];
     const int Q = qe.atom;
     const int aQ = d.na[Q], bQ = d.nb[Q], nQ = d.n_loc[Q], sQ = aQ * bQ;
@@ -401,7 +425,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
               const int m2 = 4 * q + lk;
               const bool mv = m2 < aX;
               const double a = (mv && lr < bP) ? EX[(size_t)(m2 * bX + ic) * mX] : 0.0;
-              const double b = (mv && muv) ? 2.0 * v_elem(Vp, P, X, aP, aX, muB, m2) : 0.0;
+              const double b = (mv && muv) ? gscale * v_elem(Vp, P, X, aP, aX, muB, m2) : 0.0;
               Hc[c] = mfma64(a, b, Hc[c]);
             }
           }
@@ -417,7 +441,10 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int j = lk + 4 * v;
-          if (j < bP) HP[(size_t)(muB * bP + j) * mP + col] = Hc[c][v];
+          if (j < bP) {
+            double* h = HP + (size_t)(muB * bP + j) * mP + col;
+            *h = g_only ? *h + Hc[c][v] : Hc[c][v];
+          }
         }
       }
     }
@@ -714,6 +741,227 @@ __global__ void k_zero(double* x, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// backward.  dE/dC^mu = -1/2 sum_nu V_{mu nu} D C^nu D.  With the row-owned
+// M^mu, the gradient per row-owned entry is -sum_nu V_{mu nu} (D C^nu D) on
+// rows of P; writing C^nu = M^nu + M^nu^T gives the rows-of-P blocks
+//   G_P = (H_P + Gt_P) D,   H_P = rows of P of D F^mu,  F^mu = sum_nu V M^nu,
+// where Gt_P is exactly the G term of the forward V stage taken once.  The
+// un-repack maps G_P back to the canonical C layout (the on-site halving
+// of the repack appears as a factor 1/2).
+
+__global__ __launch_bounds__(256) void k_unrepack(const double* __restrict__ GD, double* __restrict__ dC,
+                                                  DevPlan d, double scale) {
+  const int k = blockIdx.x;
+  const int P = d.nbr_owner[k], J = d.nbr_atom[k], p = d.nbr_pair[k];
+  const int aP = d.na[P], bP = d.nb[P], bJ = d.nb[J], aJ = d.na[J];
+  const int nP = d.n_loc[P], lc = d.nbr_lcol[k];
+  const int sP = aP * bP;
+  double* Cp = dC + d.c_off[p];
+  const double* GP = GD + d.t_off[P];
+  const int nel = sP * bJ;
+  for (int e = threadIdx.x; e < nel; e += 256) {
+    const int r = e / bJ, j = e - r * bJ;
+    const int mu = r / bP, i = r - mu * bP;
+    const double v = scale * GP[(size_t)r * nP + lc + j];
+    if (P < J)
+      Cp[(size_t)(mu * bP + i) * bJ + j] = v;
+    else if (P > J)
+      Cp[(size_t)((aJ + mu) * bJ + j) * bP + i] = v;
+    else
+      Cp[(size_t)(mu * bP + i) * bP + j] = 0.5 * v;
+  }
+}
+
+// <X, Y> over every canonical pair block (offsets off[p]..off[p+1]),
+// fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_block_dot(const double* __restrict__ X, const double* __restrict__ Y,
+                                                   const int64_t* __restrict__ off, double* __restrict__ out) {
+  const int p = blockIdx.x;
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int64_t e = off[p] + threadIdx.x; e < off[p + 1]; e += 256) acc += X[e] * Y[e];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = part[0];
+}
+
+// dE/dV.  tau_{mu nu} = tr(C^mu D C^nu D) = 2 (tA + tB),
+//   tA[mu][nu] = sum_{i in P, l in Q} E_P[(mu, i), l] E_Q[(nu, l), i]
+//   tB[mu][nu] = sum_{i in P, j in N[Q]} E_P[(mu, i), j] Y[(nu, i), j],
+//   Y[(nu, i), j] = sum_{l in Q} D[i, l] T_Q[(nu, l), j].
+// Off-site stored entries carry both V_{mu nu} and V_{nu mu}.  Same LDS
+// staging as the T2 kernel (columns j of N[Q] in chunks).
+
+template <int NTP, int NTQ>
+__global__ __launch_bounds__(256) void k_dV(const double* __restrict__ V, const double* __restrict__ D,
+                                            double* __restrict__ dV, DevPlan d, double gE, int n_items,
+                                            int n_padded) {
+  extern __shared__ double sm[];
+  const int w = xcd_task(n_padded);
+  if (w >= n_items) return;
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const int p = w;
+  const int P = d.pair_a[p], Q = d.pair_b[p];
+  const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
+  const int sP = aP * bP, sQ = aQ * bQ;
+  const int nQ = d.n_loc[Q], mP = d.m_loc[P], mQ = d.m_loc[Q];
+  const int s = d.atom_sys[P];
+  const int64_t ns = d.sys_n[s];
+  const int* cg = d.col1g + d.col1g_off[Q];
+  const int* m2P = d.map2 + d.map_off[P];
+  const int* m2Q = d.map2 + d.map_off[Q];
+  const double* TQ = d.T + d.t_off[Q];
+  const double* EP = d.E + d.e_off[P];
+  const double* EQ = d.E + d.e_off[Q];
+  double* sT = sm;
+  double* sE = sm + (size_t)sQ * T2_PITCH;
+  const int ntp = (aP + 15) >> 4, ntq = (aQ + 15) >> 4;
+  // D_PQ fragments: A[i][l] with i = lr, l = 4 q + lk
+  double da[NB_MAX / 4];
+  const double* DPQ = D + d.sys_d_off[s] + (size_t)d.bo[P] * ns + d.bo[Q];
+#pragma unroll
+  for (int q = 0; q < NB_MAX / 4; ++q) {
+    const int l = 4 * q + lk;
+    da[q] = (lr < bP && l < bQ) ? DPQ[(size_t)lr * ns + l] : 0.0;
+  }
+  const int nlq = (bQ + 3) >> 2, nip = (bP + 3) >> 2;
+  d4 acc[NTP][NTQ];
+#pragma unroll
+  for (int x = 0; x < NTP; ++x)
+#pragma unroll
+    for (int y = 0; y < NTQ; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  const int tc = threadIdx.x & (T2_COLS - 1);
+  for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
+    const int l = l0 + tc;
+    const bool cvld = l < nQ;
+    const int ce = cvld ? m2P[cg[l]] : 0;
+    __syncthreads();
+    for (int r = threadIdx.x >> 3; r < sQ; r += 32) sT[r * T2_PITCH + tc] = cvld ? TQ[(size_t)r * nQ + l] : 0.0;
+    for (int r = threadIdx.x >> 3; r < sP; r += 32) sE[r * T2_PITCH + tc] = cvld ? EP[(size_t)r * mP + ce] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < T2_COLS / 4; ++h) {
+      const int c = wv * (T2_COLS / 4) + h;
+      if (l0 + c < nQ) {
+#pragma unroll
+        for (int y = 0; y < NTQ; ++y) {
+          if (y < ntq) {
+            // Yt[i][nu] = sum_l D[i, l] T_Q[(nu, l), j]
+            d4 Yt = d4{0, 0, 0, 0};
+            const int nu = 16 * y + lr;
+#pragma unroll
+            for (int q = 0; q < NB_MAX / 4; ++q) {
+              if (q < nlq) {
+                const int lq = 4 * q + lk;
+                const double b = (nu < aQ && lq < bQ) ? sT[(nu * bQ + lq) * T2_PITCH + c] : 0.0;
+                Yt = mfma64(da[q], b, Yt);
+              }
+            }
+            // tB[mu][nu] += sum_i E_P[(mu, i), j] Yt[i][nu]
+#pragma unroll
+            for (int x = 0; x < NTP; ++x) {
+              if (x < ntp) {
+                const int mu = 16 * x + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  if (v < nip) {
+                    const int i = 4 * v + lk;
+                    const double a = (mu < aP && i < bP) ? sE[(mu * bP + i) * T2_PITCH + c] : 0.0;
+                    acc[x][y] = mfma64(a, Yt[v], acc[x][y]);
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  // tA: k = (i, l) flattened, k-steps dealt round-robin to the wavefronts
+  {
+    const int K2 = bP * bQ, nk = (K2 + 3) >> 2;
+    for (int q = wv; q < nk; q += 4) {
+      const int kf = 4 * q + lk;
+      const bool kv = kf < K2;
+      const int i = kv ? kf / bQ : 0, l = kv ? kf - i * bQ : 0;
+      const int cP = kv ? m2P[d.bo[Q] + l] : 0, cQ = kv ? m2Q[d.bo[P] + i] : 0;
+#pragma unroll
+      for (int y = 0; y < NTQ; ++y) {
+        if (y < ntq) {
+          const int nu = 16 * y + lr;
+          const double b = (kv && nu < aQ) ? EQ[(size_t)(nu * bQ + l) * mQ + cQ] : 0.0;
+#pragma unroll
+          for (int x = 0; x < NTP; ++x) {
+            if (x < ntp) {
+              const int mu = 16 * x + lr;
+              const double a = (kv && mu < aP) ? EP[(size_t)(mu * bP + i) * mP + cP] : 0.0;
+              acc[x][y] = mfma64(a, b, acc[x][y]);
+            }
+          }
+        }
+      }
+    }
+  }
+  // fixed-order reduction of the four wavefront partials, tile by tile
+  const double f = -0.5 * gE * (P != Q ? 2.0 : 1.0);
+  double* dVp = dV + d.v_off[p];
+#pragma unroll
+  for (int x = 0; x < NTP; ++x)
+#pragma unroll
+    for (int y = 0; y < NTQ; ++y) {
+      if (x < ntp && y < ntq) {
+        __syncthreads();
+        for (int v = 0; v < 4; ++v) sm[(wv * 4 + v) * 64 + L] = acc[x][y][v];
+        __syncthreads();
+        if (wv == 0) {
+          for (int v = 0; v < 4; ++v) {
+            double t = sm[v * 64 + L];
+            t += sm[(4 + v) * 64 + L];
+            t += sm[(8 + v) * 64 + L];
+            t += sm[(12 + v) * 64 + L];
+            const int mu = 16 * x + lk + 4 * v, nu = 16 * y + lr;
+            if (mu < aP && nu < aQ) dVp[(size_t)mu * aQ + nu] = f * t;
+          }
+        }
+      }
+    }
+}
+
+// forces: -dE/dR_A = -sum_{J in N[A], J != A} [sC (-1/c_decay) d/r + sV (-2/v_2s2) d],
+// d = R_A - R_J; sC, sV are the per-pair <gradient, block> sums.
+__global__ void k_forces(const double* __restrict__ pos, const double* __restrict__ sC,
+                         const double* __restrict__ sV, double* __restrict__ F, DevPlan d,
+                         double c_decay, double v_2s2) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= d.n_atoms) return;
+  double f0 = 0, f1 = 0, f2 = 0;
+  for (int k = d.nbr_ptr[A]; k < d.nbr_ptr[A + 1]; ++k) {
+    const int J = d.nbr_atom[k];
+    if (J == A) continue;
+    const int p = d.nbr_pair[k];
+    const double dx = pos[3 * A] - pos[3 * J], dy = pos[3 * A + 1] - pos[3 * J + 1], dz = pos[3 * A + 2] - pos[3 * J + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double gc = sC[p] * (-1.0 / c_decay) / r, gv = sV[p] * (-2.0 / v_2s2);
+    f0 -= (gc + gv) * dx;
+    f1 -= (gc + gv) * dy;
+    f2 -= (gc + gv) * dz;
+  }
+  F[3 * A] = f0;
+  F[3 * A + 1] = f1;
+  F[3 * A + 2] = f2;
+}
+
+__global__ void k_scale(double* x, int64_t n, double a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= a;
+}
+
+// ---------------------------------------------------------------------------
 // plan creation
 
 static int device_neighbors(exx_plan_s* pl) {
@@ -764,6 +1012,7 @@ static int upload_plan(exx_plan_s* pl) {
   UP(pair_a); UP(pair_b); UP(c_off); UP(v_off); UP(n_loc); UP(m_loc);
   UP(map_off); UP(col1g_off); UP(col2g_off); UP(map1); UP(map2); UP(col1g); UP(col2g);
   UP(t_off); UP(e_off); UP(e_items); UP(ct_run_ptr); UP(ct_klen); UP(runs);
+  UP(gd_items); UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
   UP(g_tiles); UP(gq); UP(gx); UP(t2_items);
   UP(f_items); UP(f_plist); UP(en_sys); UP(en_beg); UP(en_end); UP(y_tiles); UP(y_off);
@@ -772,6 +1021,9 @@ static int upload_plan(exx_plan_s* pl) {
   if ((rc = alloc_buf(pl, d.E, hp.e_total))) return rc;
   if ((rc = alloc_buf(pl, d.H, hp.e_total))) return rc;
   if ((rc = alloc_buf(pl, d.Y, hp.y_total))) return rc;
+  if ((rc = alloc_buf(pl, d.GD, hp.t_total))) return rc;
+  if ((rc = alloc_buf(pl, d.sC, (int64_t)hp.pair_a.size()))) return rc;
+  if ((rc = alloc_buf(pl, d.sV, (int64_t)hp.pair_a.size()))) return rc;
   if ((rc = alloc_buf(pl, d.epart, (int64_t)hp.en_sys.size()))) return rc;
   return 0;
 }
@@ -938,6 +1190,71 @@ int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds) {
   return EXX_OK;
 }
 
+static RowD rowd_E(exx_plan plan) {
+  DevPlan& d = plan->d;
+  return RowD{d.T, d.t_off, d.n_loc, d.E, d.e_off, d.m_loc, d.col2g, d.col2g_off,
+              d.e_items, d.ct_run_ptr, d.ct_klen, d.runs};
+}
+
+static RowD rowd_GD(exx_plan plan) {
+  DevPlan& d = plan->d;
+  return RowD{d.H, d.e_off, d.m_loc, d.GD, d.t_off, d.n_loc, d.col1g, d.col1g_off,
+              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs};
+}
+
+static void launch_rowD(exx_plan plan, const double* D, const RowD& r, int n, hipStream_t st) {
+  const int nwg = (n + 3) / 4, nwgp = (nwg + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_rowD, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
+}
+
+// repack C into T_P, then E_P = T_P D (stage mark 1 in between)
+static void launch_repack_E(exx_plan plan, const double* C, const double* D, hipStream_t st, bool mark) {
+  const HostPlan& hp = plan->hp;
+  hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, plan->d);
+  if (mark) stage_mark(plan, 1, st);
+  launch_rowD(plan, D, rowd_E(plan), (int)hp.e_items.size(), st);
+}
+
+static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int g_only,
+                     hipStream_t st) {
+  const HostPlan& hp = plan->hp;
+  const int nH = (int)hp.g_tiles.size(), nHp = (nH + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_H, dim3(nHp), dim3(64 * hp.h_waves), g_only ? 0 : plan->h_lds, st, V, D, plan->d,
+                     nH, nHp, gscale, g_only);
+}
+
+static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st) {
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  const int nT = (int)hp.t2_items.size(), nTp = (nT + 7) / 8 * 8;
+  switch (plan->t2_nt) {
+    case 1: hipLaunchKernelGGL((k_T2<1, 4>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+    case 2: hipLaunchKernelGGL((k_T2<2, 8>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+    case 3: hipLaunchKernelGGL((k_T2<3, 12>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+    default: hipLaunchKernelGGL((k_T2<4, 16>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+  }
+}
+
+static void launch_final(exx_plan plan, double* K, hipStream_t st) {
+  const HostPlan& hp = plan->hp;
+  const int nY = (int)hp.y_tiles.size(), nYp = (nY + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_Y, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+  const int nF = (int)hp.f_items.size(), nFp = (nF + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_symreduce, dim3(nFp), dim3(256), 0, st, K, plan->d, nF, nFp);
+}
+
+static void launch_dV(exx_plan plan, const double* V, const double* D, double* dV, double gE, hipStream_t st) {
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  const int nP = (int)hp.pair_a.size(), nPp = (nP + 7) / 8 * 8;
+  switch (plan->t2_nt) {
+    case 1: hipLaunchKernelGGL((k_dV<1, 1>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
+    case 2: hipLaunchKernelGGL((k_dV<2, 2>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
+    case 3: hipLaunchKernelGGL((k_dV<3, 3>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
+    default: hipLaunchKernelGGL((k_dV<4, 4>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
+  }
+}
+
 int build_K(exx_plan plan, const double* C, const double* V, const double* D, int precision,
             double* K, double* Ex, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "build_K: NULL plan");
@@ -949,26 +1266,13 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   DevPlan& d = plan->d;
   stage_mark(plan, 0, st);
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, hp.d_size);
-  hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, d);
-  stage_mark(plan, 1, st);
-  const int nE = (int)hp.e_items.size();
-  hipLaunchKernelGGL(k_E, dim3((nE + 3) / 4), dim3(256), 0, st, D, d, nE);
+  launch_repack_E(plan, C, D, st, true);
   stage_mark(plan, 2, st);
-  const int nH = (int)hp.g_tiles.size(), nHp = (nH + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_H, dim3(nHp), dim3(64 * hp.h_waves), plan->h_lds, st, V, D, d, nH, nHp);
+  launch_H(plan, V, D, 2.0, 0, st);
   stage_mark(plan, 3, st);
-  const int nT = (int)hp.t2_items.size(), nTp = (nT + 7) / 8 * 8;
-  switch (plan->t2_nt) {
-    case 1: hipLaunchKernelGGL((k_T2<1, 4>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-    case 2: hipLaunchKernelGGL((k_T2<2, 8>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-    case 3: hipLaunchKernelGGL((k_T2<3, 12>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-    default: hipLaunchKernelGGL((k_T2<4, 16>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-  }
+  launch_T2(plan, V, K, st);
   stage_mark(plan, 4, st);
-  const int nY = (int)hp.y_tiles.size(), nYp = (nY + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_Y, dim3(nYp), dim3(256), 0, st, d, nY, nYp);
-  const int nF = (int)hp.f_items.size(), nFp = (nF + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_symreduce, dim3(nFp), dim3(256), 0, st, K, d, nF, nFp);
+  launch_final(plan, K, st);
   stage_mark(plan, 5, st);
   HIP_TRY(hipGetLastError());
   int rc = EXX_OK;
@@ -987,10 +1291,53 @@ int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex,
 int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, double gE,
                       int precision, double* dC, double* dV, double* dD, double* forces,
                       double c_decay, double v_2s2, void* stream) {
-  (void)C; (void)V; (void)D; (void)gE; (void)precision; (void)dC; (void)dV; (void)dD;
-  (void)forces; (void)c_decay; (void)v_2s2; (void)stream;
   if (!plan) return fail(EXX_EINVAL, "exchange_backward: NULL plan");
-  return fail(EXX_EUNSUPPORTED, "exchange_backward: not implemented yet");
+  if (plan->host_only) return fail(EXX_ESTATE, "exchange_backward: host-only plan");
+  if (!C || !V || !D) return fail(EXX_EINVAL, "exchange_backward: NULL input array");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EUNSUPPORTED, "exchange_backward: precision not implemented");
+  if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, "exchange_backward: decay lengths must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  const bool needC = dC || forces, needV = dV || forces;
+  if (needC && !dC && !plan->dC_scratch) {
+    HIP_TRY(hipMalloc((void**)&plan->dC_scratch, sizeof(double) * std::max<int64_t>(1, hp.c_off.back())));
+    plan->allocs.push_back(plan->dC_scratch);
+  }
+  if (needV && !dV && !plan->dV_scratch) {
+    HIP_TRY(hipMalloc((void**)&plan->dV_scratch, sizeof(double) * std::max<int64_t>(1, hp.v_off.back())));
+    plan->allocs.push_back(plan->dV_scratch);
+  }
+  double* dCb = dC ? dC : plan->dC_scratch;
+  double* dVb = dV ? dV : plan->dV_scratch;
+  launch_repack_E(plan, C, D, st, false);
+  if (dD) {
+    // dE/dD = -1/2 K: the forward build into dD, then scaled
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, dD, hp.d_size);
+    launch_H(plan, V, D, 2.0, 0, st);
+    launch_T2(plan, V, dD, st);
+    launch_final(plan, dD, st);
+    hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, st, dD, hp.d_size, -0.5 * gE);
+    if (needC) launch_H(plan, V, D, -1.0, 1, st);   // G term taken once
+  } else if (needC) {
+    launch_H(plan, V, D, 1.0, 0, st);
+  }
+  if (needC) {
+    launch_rowD(plan, D, rowd_GD(plan), (int)hp.gd_items.size(), st);
+    hipLaunchKernelGGL(k_unrepack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, d.GD, dCb, d, -gE);
+    if (forces)
+      hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dCb, C, d.c_off, d.sC);
+  }
+  if (needV) {
+    launch_dV(plan, V, D, dVb, gE, st);
+    if (forces)
+      hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dVb, V, d.v_off, d.sV);
+  }
+  if (forces)
+    hipLaunchKernelGGL(k_forces, dim3((hp.n_atoms + 127) / 128), dim3(128), 0, st, d.pos, d.sC, d.sV, forces, d,
+                       c_decay, v_2s2);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
 }
 
 }  // extern "C"

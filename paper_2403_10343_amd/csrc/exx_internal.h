@@ -62,6 +62,9 @@ struct HostPlan {
   std::vector<EItem> e_items;
   std::vector<int> ct_run_ptr, ct_klen;
   std::vector<Run> runs;
+  std::vector<EItem> gd_items;                       // G_P = H_P D (backward)
+  std::vector<int> gd_run_ptr, gd_klen;
+  std::vector<Run> gd_runs;
   std::vector<int> grp_first, grp_unit_ptr, grp_col_ptr, grp_cols;
   std::vector<Unit> grp_units;
   std::vector<GTile> g_tiles;

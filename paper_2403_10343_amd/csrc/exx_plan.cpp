@@ -221,19 +221,71 @@ int derive_lists(HostPlan& hp, std::string& err) {
   hp.e_total = hp.e_off[NA];
   for (auto& f : hp.flops) f = 0;
   for (auto& f : hp.issued) f = 0;
-  // atom of every column of N2[P] (scratch)
-  std::vector<int> mark(NA, -1);
-  // ---- E tasks: column tiles of 32, k-runs of relevant neighbours J
-  hp.e_items.clear();
-  hp.ct_run_ptr.assign(1, 0);
-  hp.ct_klen.clear();
-  hp.runs.clear();
+  // ---- block-sparse "rows of P times D" tasks.  E_P = T_P D takes the
+  // columns of N[P] as k and produces the columns of N2[P]; the gradient
+  // product G_P = H_P D takes N2[P] as k and produces N[P].  Output column
+  // tiles of 32; the k-range of a tile is the list of runs of input atoms J
+  // with some tile atom in N[J] (D is zero elsewhere).
   int stampv = 0;
   std::vector<int> stamp2(NA, -1);
+  auto rowd_lists = [&](bool grad, std::vector<EItem>& items, std::vector<int>& run_ptr,
+                        std::vector<int>& klens, std::vector<Run>& runs, int64_t& issued) {
+    items.clear();
+    run_ptr.assign(1, 0);
+    klens.clear();
+    runs.clear();
+    for (int a = 0; a < NA; ++a) {
+      const int sP = hp.na[a] * hp.nb[a];
+      // input atoms (k side) and output atoms (column side) with local offsets
+      const int* in_b = grad ? &hp.n2_atom[hp.n2_ptr[a]] : &nat[np[a]];
+      const int n_in = grad ? hp.n2_ptr[a + 1] - hp.n2_ptr[a] : np[a + 1] - np[a];
+      const int* out_b = grad ? &nat[np[a]] : &hp.n2_atom[hp.n2_ptr[a]];
+      const int n_out = grad ? np[a + 1] - np[a] : hp.n2_ptr[a + 1] - hp.n2_ptr[a];
+      const int mOut = grad ? hp.n_loc[a] : hp.m_loc[a];
+      for (int c0 = 0; c0 < mOut; c0 += 32) {
+        ++stampv;
+        const int c1 = std::min(mOut, c0 + 32);
+        int c = 0;
+        for (int k = 0; k < n_out; ++k) {
+          const int l = out_b[k];
+          if (c < c1 && c + hp.nb[l] > c0) stamp2[l] = stampv;
+          c += hp.nb[l];
+          if (c >= c1) break;
+        }
+        const int ct = (int)klens.size();
+        int klen = 0, lcol = 0, prevJ = -2;
+        Run cur{-1, -1, 0};
+        for (int k = 0; k < n_in; ++k) {
+          const int j = in_b[k];
+          bool rel = false;
+          for (int k2 = np[j]; k2 < np[j + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
+          if (rel) {
+            if (cur.len > 0 && j == prevJ + 1) {
+              cur.len += hp.nb[j];
+            } else {
+              if (cur.len > 0) runs.push_back(cur);
+              cur = Run{lcol, hp.bo[j], hp.nb[j]};
+            }
+            prevJ = j;
+            klen += hp.nb[j];
+          } else {
+            prevJ = -2;
+          }
+          lcol += hp.nb[j];
+        }
+        if (cur.len > 0) runs.push_back(cur);
+        run_ptr.push_back((int)runs.size());
+        klens.push_back(klen);
+        for (int r0 = 0; r0 < sP; r0 += 32) {
+          items.push_back(EItem{a, r0, c0, ct});
+          issued += 2LL * 32 * 32 * ceil_to(klen, 4);
+        }
+      }
+    }
+  };
   for (int a = 0; a < NA; ++a) {
     const int sP = hp.na[a] * hp.nb[a];
-    // structural flops: sum_J b_J sum_{L in N[J]} b_L
-    int64_t kk = 0;
+    int64_t kk = 0;   // structural flops: sum_J b_J sum_{L in N[J]} b_L
     for (int k = np[a]; k < np[a + 1]; ++k) {
       int j = nat[k];
       int64_t sl = 0;
@@ -241,52 +293,10 @@ int derive_lists(HostPlan& hp, std::string& err) {
       kk += (int64_t)hp.nb[j] * sl;
     }
     hp.flops[1] += 2 * (int64_t)sP * kk;
-    const int mP = hp.m_loc[a];
-    for (int c0 = 0; c0 < mP; c0 += 32) {
-      ++stampv;
-      int c1 = std::min(mP, c0 + 32);
-      for (int c = c0; c < c1; ++c) {
-        int g = hp.col2g[hp.col2g_off[a] + c];
-        // atom of g: search the N2 list
-        (void)g;
-      }
-      // atoms covering [c0, c1): walk N2[a]
-      {
-        int c = 0;
-        for (int k = hp.n2_ptr[a]; k < hp.n2_ptr[a + 1]; ++k) {
-          int l = hp.n2_atom[k];
-          if (c < c1 && c + hp.nb[l] > c0) stamp2[l] = stampv;
-          c += hp.nb[l];
-          if (c >= c1) break;
-        }
-      }
-      const int ct = (int)hp.ct_klen.size();
-      int klen = 0;
-      Run cur{-1, -1, 0};
-      int prevJ = -2;
-      for (int k = np[a]; k < np[a + 1]; ++k) {
-        int j = nat[k];
-        bool rel = false;
-        for (int k2 = np[j]; k2 < np[j + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
-        if (!rel) { prevJ = -2; continue; }
-        if (cur.len > 0 && j == prevJ + 1) {
-          cur.len += hp.nb[j];
-        } else {
-          if (cur.len > 0) hp.runs.push_back(cur);
-          cur = Run{hp.nbr_lcol[k], hp.bo[j], hp.nb[j]};
-        }
-        prevJ = j;
-        klen += hp.nb[j];
-      }
-      if (cur.len > 0) hp.runs.push_back(cur);
-      hp.ct_run_ptr.push_back((int)hp.runs.size());
-      hp.ct_klen.push_back(klen);
-      for (int r0 = 0; r0 < sP; r0 += 32) {
-        hp.e_items.push_back(EItem{a, r0, c0, ct});
-        hp.issued[1] += 2LL * 32 * 32 * ceil_to(klen, 4);
-      }
-    }
   }
+  rowd_lists(false, hp.e_items, hp.ct_run_ptr, hp.ct_klen, hp.runs, hp.issued[1]);
+  int64_t gd_issued = 0;
+  rowd_lists(true, hp.gd_items, hp.gd_run_ptr, hp.gd_klen, hp.gd_runs, gd_issued);
   // ---- H tasks: atom groups (runs of consecutive, nearby atoms of one
   // system; one wavefront per 16-wide aux tile of each atom) x 16-wide tiles
   // of the group's second-neighbourhood columns.  Q-lists (V (x) D part) and

@@ -1,0 +1,107 @@
+"""exchange_backward (FP64) against the CPU oracle, finite differences and
+identities that hold at any size."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exx_oracle as O
+from tests.gpu_util import device_inputs, relmax, run_build, system_block
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def exx():
+    import paper_2403_10343_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def backward(plan, inp, gE=1.0, want=("dC", "dV", "dD", "F")):
+    dev = "cuda:0"
+    C, V, D = device_inputs(inp, torch)
+    out = {}
+    dC = torch.empty_like(C) if "dC" in want else None
+    dV = torch.empty_like(V) if "dV" in want else None
+    dD = torch.empty_like(D) if "dD" in want else None
+    F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device=dev) if "F" in want else None
+    plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, forces=F)
+    torch.cuda.synchronize()
+    for k, x in (("dC", dC), ("dV", dV), ("dD", dD), ("F", F)):
+        if x is not None:
+            out[k] = x.cpu().numpy()
+    if "F" in out:
+        out["F"] = out["F"].reshape(-1, 3)
+    return out
+
+
+@pytest.mark.parametrize("n_mol,seed", [(1, 1), (2, 2), (8, 0)])
+def test_gradients_match_oracle(exx, n_mol, seed):
+    sysm = synth.water_cluster(n_mol, seed)
+    print("backward cluster", n_mol, flush=True)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    g = backward(plan, inp)
+    go = O.gradients(inp)
+    assert relmax(g["dC"], go["dC"]) < 1e-10
+    assert relmax(g["dV"], go["dV"]) < 1e-10
+    assert relmax(system_block(g["dD"], inp.layout, 0), go["dD"]) < 1e-10
+    Fo = O.forces(inp, go)
+    assert relmax(g["F"], Fo) < 1e-10
+
+
+def test_partial_outputs_and_scaling(exx):
+    sysm = synth.water_cluster(2, 5)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    full = backward(plan, inp, gE=1.0)
+    part = backward(plan, inp, gE=-2.5, want=("dC",))
+    assert relmax(part["dC"], -2.5 * full["dC"]) < 1e-13
+    only_f = backward(plan, inp, gE=1.0, want=("F",))
+    assert relmax(only_f["F"], full["F"]) < 1e-13
+    only_v = backward(plan, inp, gE=1.0, want=("dV",))
+    assert np.array_equal(only_v["dV"], full["dV"])
+
+
+def test_forces_central_differences(exx):
+    """-dE/dR by central differences (1e-4 A) of the GPU FP64 energy, pair
+    lists frozen at the reference geometry, D held fixed."""
+    sysm = synth.water_cluster(3, 11)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    F = backward(plan, inp, want=("F",))["F"]
+    rng = np.random.default_rng(3)
+    h = 1e-4
+    for _ in range(6):
+        A, x = int(rng.integers(0, sysm.n_atoms)), int(rng.integers(0, 3))
+        es = []
+        for sgn in (+1, -1):
+            pos = sysm.pos.copy()
+            pos[A, x] += sgn * h
+            s2 = synth.System(sysm.species, pos, sysm.r_cut, sysm.seed)
+            i2 = synth.make_inputs(s2, inp.layout)
+            i2.D[:] = inp.D
+            _, Ex = run_build(plan, i2, torch)
+            es.append(Ex[0])
+        fd = -(es[0] - es[1]) / (2 * h)
+        assert abs(fd - F[A, x]) < 1e-6 * max(1.0, abs(F[A, x])), (A, x, fd, F[A, x])
+
+
+def test_identities_on_768_atom_box(exx):
+    """Euler identities (E is quadratic in C and D, linear in V), force and
+    torque balance, and dE/dD = -K/2 at full size."""
+    inp = synth.make_inputs(synth.config(4))
+    sysm = inp.system
+    plan = exx.Plan.for_system(sysm)
+    K, Ex = run_build(plan, inp, torch)
+    g = backward(plan, inp)
+    E = Ex[0]
+    assert abs(g["dC"] @ inp.C - 2 * E) < 1e-10 * abs(E)
+    assert abs(g["dV"] @ inp.V - E) < 1e-10 * abs(E)
+    assert abs(g["dD"] @ inp.D - 2 * E) < 1e-10 * abs(E)
+    assert np.array_equal(g["dD"], -0.5 * K)
+    F = g["F"]
+    scale = np.abs(F).max()
+    assert np.abs(F.sum(0)).max() < 1e-10 * scale * sysm.n_atoms
+    assert np.abs(np.cross(sysm.pos, F).sum(0)).max() < 1e-10 * scale * sysm.n_atoms * 30
