@@ -131,6 +131,17 @@ int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom);
 int build_K(exx_plan plan, const double* C, const double* V, const double* D,
             int precision, double* K, double* Ex, void* stream);
 
+/* Capture one build_K (FP64, these exact arrays) on `stream` into a HIP
+ * graph owned by the plan, replacing any earlier one; exx_graph_launch()
+ * replays it.  The arrays must stay valid while the graph is used.  The
+ * captured work is kernel launches only (buffers are cleared by kernels).
+ * `stream` must be a created stream (capture on the default stream is
+ * rejected with EXX_EINVAL).  Replays on one plan must not overlap: they
+ * share the plan's workspace. */
+int exx_graph_build(exx_plan plan, const double* C, const double* V, const double* D,
+                    double* K, double* Ex, void* stream);
+int exx_graph_launch(exx_plan plan, void* stream);
+
 /* E_x = -1/4 sum_ik K_ik D_ik for every system (device Ex [n_systems]),
  * a fixed-order binary64 reduction (bitwise reproducible). */
 int exchange_energy(exx_plan plan, const double* K, const double* D,

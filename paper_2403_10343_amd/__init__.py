@@ -1,4 +1,16 @@
 """MI355X RI-LVL exact-exchange build: thin Python layer over libexx.so."""
 from ._lib import (PREC_FP32, PREC_FP64, ExxError, Plan, lib)  # noqa: F401
 
-__all__ = ["Plan", "ExxError", "PREC_FP64", "PREC_FP32", "lib"]
+
+def exchange_energy(plan, C, V, D, precision=PREC_FP64):
+    """Differentiable E_x per system (see paper_2403_10343_amd.autograd)."""
+    from .autograd import exchange_energy as f
+    return f(plan, C, V, D, precision)
+
+
+def exchange_forces(plan, C, V, D, c_decay=1.5, v_2s2=8.0, gE=1.0):
+    from .autograd import exchange_forces as f
+    return f(plan, C, V, D, c_decay, v_2s2, gE)
+
+
+__all__ = ["Plan", "ExxError", "PREC_FP64", "PREC_FP32", "lib", "exchange_energy", "exchange_forces"]

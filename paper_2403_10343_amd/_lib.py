@@ -50,7 +50,8 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pairs",
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
-           "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times")
+           "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
+           "exx_graph_build", "exx_graph_launch")
 N_STAGES = 6
 STAGE_NAMES = ("repack", "E", "H", "T2", "final", "energy")
 
@@ -72,6 +73,8 @@ def lib():
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exx_graph_build.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.exx_graph_launch.argtypes = [vp, vp]
     L.exx_plan_set_profiling.argtypes = [vp, ctypes.c_int]
     L.exx_plan_stage_times.argtypes = [vp, vp, vp]
     L.exx_plan_flops.argtypes = [vp, ctypes.c_int]
@@ -167,6 +170,13 @@ class Plan:
         _check(lib().exchange_backward(self._h, _ptr(C), _ptr(V), _ptr(D), float(gE), int(precision),
                                        _ptr(dC), _ptr(dV), _ptr(dD), _ptr(forces),
                                        float(c_decay), float(v_2s2), _stream(stream)))
+
+    def graph_build(self, C, V, D, K, Ex, stream):
+        """Capture one FP64 build_K on `stream` (a created stream) into a HIP graph."""
+        _check(lib().exx_graph_build(self._h, _ptr(C), _ptr(V), _ptr(D), _ptr(K), _ptr(Ex), _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        _check(lib().exx_graph_launch(self._h, _stream(stream)))
 
     def set_profiling(self, enable=True):
         _check(lib().exx_plan_set_profiling(self._h, 1 if enable else 0))

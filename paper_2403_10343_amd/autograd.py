@@ -1,0 +1,48 @@
+"""torch.autograd binding of the exchange energy (argument marshalling only).
+
+``exchange_energy(plan, C, V, D)`` returns E_x per system; its backward calls
+the library's exchange_backward kernels for dE/dC, dE/dV and dE/dD.
+``exchange_forces(plan, C, V, D)`` returns -dE_x/dR for the synthetic
+exp(-r/1.5) / exp(-r^2/8) position dependence of C and V.
+"""
+import torch
+
+from ._lib import PREC_FP64
+
+
+class _ExchangeEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, C, V, D, plan, precision):
+        K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=C.device)
+        Ex = torch.empty(plan.n_systems, dtype=torch.float64, device=C.device)
+        plan.build_K(C, V, D, K, Ex, precision=precision)
+        ctx.save_for_backward(C, V, D)
+        ctx.plan, ctx.precision = plan, precision
+        return Ex
+
+    @staticmethod
+    def backward(ctx, gEx):
+        C, V, D = ctx.saved_tensors
+        g = gEx.detach().cpu()
+        if not bool(torch.all(g == g[0])):
+            raise NotImplementedError("exchange_energy backward needs the same upstream gradient for every system")
+        gE = float(g[0])
+        need = ctx.needs_input_grad
+        dC = torch.empty_like(C) if need[0] else None
+        dV = torch.empty_like(V) if need[1] else None
+        dD = torch.empty_like(D) if need[2] else None
+        if dC is not None or dV is not None or dD is not None:
+            ctx.plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, precision=ctx.precision)
+        return dC, dV, dD, None, None
+
+
+def exchange_energy(plan, C, V, D, precision=PREC_FP64):
+    """E_x of every system of the plan (differentiable in C, V and D)."""
+    return _ExchangeEnergy.apply(C, V, D, plan, precision)
+
+
+def exchange_forces(plan, C, V, D, c_decay=1.5, v_2s2=8.0, gE=1.0):
+    """Atomic forces -d(gE E_x)/dR, shape (n_atoms, 3)."""
+    F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device=C.device)
+    plan.exchange_backward(C, V, D, gE, forces=F, c_decay=c_decay, v_2s2=v_2s2)
+    return F.view(-1, 3)

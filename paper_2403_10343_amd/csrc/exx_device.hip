@@ -108,6 +108,8 @@ struct exx_plan_s {
   int t2_nt = 4;                    // aux tiles of 16 needed by the largest atom
   size_t h_lds = 0;                 // dynamic LDS bytes of k_H
   size_t t2_lds = 0;                // dynamic LDS bytes of k_T2
+  hipGraph_t graph = nullptr;       // captured build_K (exx_graph_build)
+  hipGraphExec_t graph_exec = nullptr;
   double* dC_scratch = nullptr;     // gradient buffers used when the caller passes NULL
   double* dV_scratch = nullptr;
 };
@@ -1029,6 +1031,10 @@ static int upload_plan(exx_plan_s* pl) {
 }
 
 static void release(exx_plan_s* pl) {
+  if (pl->graph_exec) hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) hipGraphDestroy(pl->graph);
+  pl->graph_exec = nullptr;
+  pl->graph = nullptr;
   for (void* p : pl->allocs) hipFree(p);
   pl->allocs.clear();
   for (hipEvent_t e : pl->events) hipEventDestroy(e);
@@ -1279,6 +1285,36 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
   stage_mark(plan, 6, st);
   return rc;
+}
+
+int exx_graph_build(exx_plan plan, const double* C, const double* V, const double* D, double* K, double* Ex,
+                    void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_graph_build: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_graph_build: host-only plan");
+  if (!stream) return fail(EXX_EINVAL, "exx_graph_build: capture needs a created (non-default) stream");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "exx_graph_build: NULL array");
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->graph_exec) { hipGraphExecDestroy(plan->graph_exec); plan->graph_exec = nullptr; }
+  if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+  const bool prof = plan->profiling;
+  plan->profiling = false;
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = build_K(plan, C, V, D, EXX_PREC_FP64, K, Ex, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  plan->profiling = prof;
+  if (rc != EXX_OK) { if (g) hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return fail(EXX_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  plan->graph = g;
+  HIP_TRY(hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0));
+  return EXX_OK;
+}
+
+int exx_graph_launch(exx_plan plan, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_graph_launch: NULL plan");
+  if (!plan->graph_exec) return fail(EXX_ESTATE, "exx_graph_launch: no graph built");
+  HIP_TRY(hipGraphLaunch(plan->graph_exec, (hipStream_t)stream));
+  return EXX_OK;
 }
 
 int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {

@@ -105,3 +105,21 @@ def test_identities_on_768_atom_box(exx):
     scale = np.abs(F).max()
     assert np.abs(F.sum(0)).max() < 1e-10 * scale * sysm.n_atoms
     assert np.abs(np.cross(sysm.pos, F).sum(0)).max() < 1e-10 * scale * sysm.n_atoms * 30
+
+
+def test_autograd_function(exx):
+    sysm = synth.water_cluster(2, 8)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    C, V, D = device_inputs(inp, torch)
+    C.requires_grad_(True)
+    V.requires_grad_(True)
+    D.requires_grad_(True)
+    Ex = exx.exchange_energy(plan, C, V, D)
+    (3.0 * Ex.sum()).backward()
+    go = O.gradients(inp)
+    assert relmax(C.grad.cpu().numpy(), 3.0 * go["dC"]) < 1e-10
+    assert relmax(V.grad.cpu().numpy(), 3.0 * go["dV"]) < 1e-10
+    assert relmax(system_block(D.grad.cpu().numpy(), inp.layout, 0), 3.0 * go["dD"]) < 1e-10
+    F = exx.exchange_forces(plan, C.detach(), V.detach(), D.detach()).cpu().numpy()
+    assert relmax(F, O.forces(inp, go)) < 1e-10
