@@ -313,25 +313,99 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
 }
 
 // ---------------------------------------------------------------------------
-// stage 2: H'_P[(mu, j), c] for a group of consecutive atoms (one wavefront
-// per 16-wide aux tile of each group atom) and 16 columns c of the group's
-// second neighbourhood.  For every Q in the tile's Q-list the block
-// T_Q[:, c] is staged once in LDS and shared by all wavefronts, then per
-// column c (two chained MFMAs, the first result feeding the second as its
-// B operand):
+// stage 2: H'_P[(mu, j), c] for a group of consecutive atoms (its "units"
+// are the 16-wide aux tiles of the group atoms) and H_COLS columns c of the
+// group's second neighbourhood.  Four wavefronts per workgroup, each owning
+// H_CPW of the columns and looping over all units, so the SIMDs carry equal
+// work.  For every Q of the tile's Q-list, T_Q[:, columns] is staged once in
+// LDS, then per (unit, column) two chained MFMAs (the first result feeding
+// the second as its B operand):
 //   F_c[l][mu] = sum_nu T_Q[(nu, l), c] V_PQ[mu, nu]
 //   H_c[j][mu] += sum_l D_PQ[j, l] F_c[l][mu]
 // G part for columns c on atom X in N[P]:
-//   H_c[l][nu] += 2 sum_mu' E_X[(mu', c), l] V_XP[mu', nu].
+//   H_c[l][nu] += g sum_mu' E_X[(mu', c), l] V_XP[mu', nu]   (g = 2 forward).
+// The chain lengths are compile-time per shape class of Q.
 
-constexpr int LDS_PITCH = 17;   // doubles per staged row (16 columns + 1: no bank conflicts)
+constexpr int LDS_PITCH = H_COLS + 1;   // doubles per staged row (one pad column: no bank conflicts)
+constexpr int HQ_CHUNK = 64;            // Q-list entries whose metadata sits in LDS at once
+constexpr int H_WAVES = 4;
+constexpr int H_CPW = H_COLS / H_WAVES;
 
-__global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict__ V,
-                                                         const double* __restrict__ D, DevPlan d,
-                                                         int n_tiles, int n_padded, double gscale,
-                                                         int g_only) {
+__device__ __forceinline__ int h_class(int ns, int nl) {
+  if (ns <= 4 && nl <= 2) return 0;
+  if (ns <= 10) return 1;
+  return 2;
+}
+
+struct HUnits {            // unit table of the group (LDS)
+  int P[GROUP_WAVES], mu0[GROUP_WAVES], slot[GROUP_WAVES], a[GROUP_WAVES], b[GROUP_WAVES], bo[GROUP_WAVES];
+};
+
+template <int NS, int NL, int U>
+__device__ __forceinline__ void h_q(d4 (&Hc)[U][H_CPW], const double* sT, const HUnits& un, int nU,
+                                    const int* qp, const int64_t* qv, const double* V, const double* Ds,
+                                    int64_t ns, int Q, int aQ, int bQ, int boQ, const int* lc_row, int ncols,
+                                    int c0, int lr, int lk) {
+  const bool lv = lr < bQ;
+  const int row0 = lv ? lr * LDS_PITCH : 0;
+  bool cval[H_CPW];
+#pragma unroll
+  for (int cc = 0; cc < H_CPW; ++cc) cval[cc] = (c0 + cc < ncols) && lc_row[c0 + cc] >= 0;
+  bool anyc = false;
+#pragma unroll
+  for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || cval[cc];
+  if (!anyc) return;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (u < nU) {
+      const int p = qp[un.slot[u]];
+      if (p >= 0) {
+        const int P = un.P[u], aP = un.a[u], bP = un.b[u];
+        const int muB = un.mu0[u] + lr;
+        const bool muv = muB < aP;
+        const double* Vp = V + qv[un.slot[u]];
+        double vb[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int nu = 4 * q + lk;
+          vb[q] = (muv && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, muB, nu) : 0.0;
+        }
+        double da[NL];
+        const double* DPQ = Ds + (size_t)un.bo[u] * ns + boQ;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+          const int l = 4 * q + lk;
+          da[q] = (lr < bP && l < bQ) ? DPQ[(size_t)lr * ns + l] : 0.0;
+        }
+#pragma unroll
+        for (int cc = 0; cc < H_CPW; ++cc) {
+          if (cval[cc]) {
+            d4 F = d4{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+              const int nu = 4 * q + lk;
+              const bool ok = lv && nu < aQ;
+              const double t = sT[(ok ? nu * bQ * LDS_PITCH : 0) + row0 + c0 + cc];
+              F = mfma64(ok ? t : 0.0, vb[q], F);
+            }
+#pragma unroll
+            for (int q = 0; q < NL; ++q) Hc[u][cc] = mfma64(da[q], F[q], Hc[u][cc]);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int U>
+__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_H(const double* __restrict__ V, const double* __restrict__ D,
+                                                    DevPlan d, int n_tiles, int n_padded, double gscale,
+                                                    int g_only) {
   extern __shared__ double sT[];
-  __shared__ int sColQ[16];
+  __shared__ HUnits un;
+  __shared__ int qm_atom[HQ_CHUNK], qm_n[HQ_CHUNK], qm_a[HQ_CHUNK], qm_b[HQ_CHUNK], qm_bo[HQ_CHUNK];
+  __shared__ int qm_lc[HQ_CHUNK][H_COLS], qm_p[HQ_CHUNK][GROUP_ATOMS];
+  __shared__ int64_t qm_toff[HQ_CHUNK], qm_voff[HQ_CHUNK][GROUP_ATOMS];
   const int ti = xcd_task(n_padded);
   if (ti >= n_tiles) return;
   const GTile tl = d.g_tiles[ti];
@@ -339,113 +413,126 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void k_H(const double* __restrict
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
   const int u0 = d.grp_unit_ptr[g];
-  const bool active = wv < d.grp_unit_ptr[g + 1] - u0;
-  const Unit un = d.grp_units[active ? u0 + wv : u0];
-  const int P = un.P, mu0 = un.mu0, slot = un.slot;
-  const int aP = d.na[P], bP = d.nb[P], mP = d.m_loc[P];
-  const int s = d.atom_sys[P];
+  const int nU = d.grp_unit_ptr[g + 1] - u0;
+  if (threadIdx.x < nU) {
+    const Unit x = d.grp_units[u0 + threadIdx.x];
+    un.P[threadIdx.x] = x.P;
+    un.mu0[threadIdx.x] = x.mu0;
+    un.slot[threadIdx.x] = x.slot;
+    un.a[threadIdx.x] = d.na[x.P];
+    un.b[threadIdx.x] = d.nb[x.P];
+    un.bo[threadIdx.x] = d.bo[x.P];
+  }
+  const int s = d.atom_sys[d.grp_first[g]];
   const int64_t ns = d.sys_n[s];
   const double* Ds = D + d.sys_d_off[s];
   const int* gcol = d.grp_cols + tl.col_beg;
   const int ncols = tl.ncols;
-  const int muB = mu0 + lr;      // B-operand column (aux of P)
-  const bool muv = muB < aP;
-  d4 Hc[16];
+  const int c0 = wv * H_CPW;
+  d4 Hc[U][H_CPW];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) Hc[c] = d4{0, 0, 0, 0};
-
-  // staging role of this thread: column tc, rows r0, r0 + step, ...
-  const int tc = threadIdx.x & 15;
-  const int tstep = blockDim.x >> 4;
-  const int tgc = tc < ncols ? gcol[tc] : -1;
-
-  for (int e = g_only ? tl.q_end : tl.q_beg; e < tl.q_end; ++e) {
-    const Slot4 qe = d.gq[e];
-    const int Q = qe.atom;
-    const int aQ = d.na[Q], bQ = d.nb[Q], nQ = d.n_loc[Q], sQ = aQ * bQ;
-    const int lcq = tgc >= 0 ? d.map1[d.map_off[Q] + tgc] : -1;
-    const double* TQ = d.T + d.t_off[Q];
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int cc = 0; cc < H_CPW; ++cc) Hc[u][cc] = d4{0, 0, 0, 0};
+  const int tc = threadIdx.x % H_COLS;
+  const int tstep = blockDim.x / H_COLS;
+  for (int e0 = g_only ? tl.q_end : tl.q_beg; e0 < tl.q_end; e0 += HQ_CHUNK) {
+    const int nchunk = min(HQ_CHUNK, tl.q_end - e0);
     __syncthreads();
-    if (threadIdx.x < 16) sColQ[tc] = lcq >= 0;
-    for (int r = threadIdx.x >> 4; r < sQ; r += tstep)
-      sT[r * LDS_PITCH + tc] = lcq >= 0 ? TQ[(size_t)r * nQ + lcq] : 0.0;
-    __syncthreads();
-    const int p = slot == 0 ? qe.p0 : (slot == 1 ? qe.p1 : qe.p2);
-    if (!active || p < 0) continue;
-    const double* Vp = V + d.v_off[p];
-    const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
-    double vb[NA_MAX / 4];
-#pragma unroll
-    for (int q = 0; q < NA_MAX / 4; ++q) {
-      const int nu = 4 * q + lk;
-      vb[q] = (q < nsQ && muv && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, muB, nu) : 0.0;
-    }
-    double da[NB_MAX / 4];
-    const double* DPQ = Ds + (size_t)d.bo[P] * ns + d.bo[Q];
-#pragma unroll
-    for (int q = 0; q < NB_MAX / 4; ++q) {
-      const int l = 4 * q + lk;
-      da[q] = (lr < bP && l < bQ) ? DPQ[(size_t)lr * ns + l] : 0.0;
-    }
-    const bool lv = lr < bQ;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      if (c < ncols && sColQ[c]) {
-        d4 F = d4{0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < NA_MAX / 4; ++q) {
-          if (q < nsQ) {
-            const int nu = 4 * q + lk;
-            const double a = (lv && nu < aQ) ? sT[(nu * bQ + lr) * LDS_PITCH + c] : 0.0;
-            F = mfma64(a, vb[q], F);
-          }
+    for (int t = threadIdx.x; t < nchunk * H_COLS; t += blockDim.x) {
+      const int ei = t / H_COLS, c = t % H_COLS;
+      const Slot4 qe = d.gq[e0 + ei];
+      const int Q = qe.atom;
+      qm_lc[ei][c] = (c < ncols) ? d.map1[d.map_off[Q] + gcol[c]] : -1;
+      if (c == 0) {
+        qm_atom[ei] = Q;
+        qm_n[ei] = d.n_loc[Q];
+        qm_a[ei] = d.na[Q];
+        qm_b[ei] = d.nb[Q];
+        qm_bo[ei] = d.bo[Q];
+        qm_toff[ei] = d.t_off[Q];
+        const int pp[3] = {qe.p0, qe.p1, qe.p2};
+        for (int k = 0; k < GROUP_ATOMS; ++k) {
+          qm_p[ei][k] = pp[k];
+          qm_voff[ei][k] = pp[k] >= 0 ? d.v_off[pp[k]] : 0;
         }
-#pragma unroll
-        for (int q = 0; q < NB_MAX / 4; ++q)
-          if (q < nlQ) Hc[c] = mfma64(da[q], F[q], Hc[c]);
       }
     }
+    __syncthreads();
+    for (int ei = 0; ei < nchunk; ++ei) {
+      const int Q = qm_atom[ei], aQ = qm_a[ei], bQ = qm_b[ei], nQ = qm_n[ei], sQ = aQ * bQ;
+      const int lcq = qm_lc[ei][tc];
+      const double* TQ = d.T + qm_toff[ei] + (lcq >= 0 ? lcq : 0);
+      for (int r = threadIdx.x / H_COLS; r < sQ; r += tstep)
+        sT[r * LDS_PITCH + tc] = lcq >= 0 ? TQ[(size_t)r * nQ] : 0.0;
+      __syncthreads();
+      const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
+      switch (h_class(nsQ, nlQ)) {
+        case 0: h_q<4, 2, U>(Hc, sT, un, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, aQ, bQ, qm_bo[ei], qm_lc[ei], ncols, c0, lr, lk); break;
+        case 1: h_q<10, 4, U>(Hc, sT, un, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, aQ, bQ, qm_bo[ei], qm_lc[ei], ncols, c0, lr, lk); break;
+        default: h_q<16, 4, U>(Hc, sT, un, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, aQ, bQ, qm_bo[ei], qm_lc[ei], ncols, c0, lr, lk); break;
+      }
+      __syncthreads();
+    }
   }
-  if (active) {
-    for (int e = tl.x_beg; e < tl.x_end; ++e) {
-      const Slot4 xe = d.gx[e];
-      const int p = slot == 0 ? xe.p0 : (slot == 1 ? xe.p1 : xe.p2);
-      if (p < 0) continue;
-      const int X = xe.atom;
-      const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
-      const double* Vp = V + d.v_off[p];
-      const int colx = lr < bP ? d.map2[d.map_off[X] + d.bo[P] + lr] : 0;
-      const double* EX = d.E + d.e_off[X] + colx;
-      const int nsX = (aX + 3) >> 2;
+  __syncthreads();
+  // G part (this wavefront's columns)
+  for (int e = tl.x_beg; e < tl.x_end; ++e) {
+    const Slot4 xe = d.gx[e];
+    const int X = xe.atom;
+    const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
+    const int pp[3] = {xe.p0, xe.p1, xe.p2};
+    const double* EX0 = d.E + d.e_off[X];
+    const int* m2X = d.map2 + d.map_off[X];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int ic = (c < ncols) ? gcol[c] - boX : -1;
-        if (ic >= 0 && ic < bX) {
+    for (int cc = 0; cc < H_CPW; ++cc) {
+      const int c = c0 + cc;
+      const int ic = (c < ncols) ? gcol[c] - boX : -1;
+      if (ic >= 0 && ic < bX) {
 #pragma unroll
-          for (int q = 0; q < NA_MAX / 4; ++q) {
-            if (q < nsX) {
-              const int m2 = 4 * q + lk;
-              const bool mv = m2 < aX;
-              const double a = (mv && lr < bP) ? EX[(size_t)(m2 * bX + ic) * mX] : 0.0;
-              const double b = (mv && muv) ? gscale * v_elem(Vp, P, X, aP, aX, muB, m2) : 0.0;
-              Hc[c] = mfma64(a, b, Hc[c]);
+        for (int u = 0; u < U; ++u) {
+          if (u < nU) {
+            const int p = pp[un.slot[u]];
+            if (p >= 0) {
+              const int P = un.P[u], aP = un.a[u], bP = un.b[u];
+              const int muB = un.mu0[u] + lr;
+              const bool muv = muB < aP;
+              const double* Vp = V + d.v_off[p];
+              const int colx = lr < bP ? m2X[un.bo[u] + lr] : 0;
+              const double* EX = EX0 + colx + (size_t)ic * mX;
+              for (int q = 0; q < (aX + 3) / 4; ++q) {
+                const int m2 = 4 * q + lk;
+                const bool mv = m2 < aX;
+                const double a = (mv && lr < bP) ? EX[(size_t)(m2 * bX) * mX] : 0.0;
+                const double b = (mv && muv) ? gscale * v_elem(Vp, P, X, aP, aX, muB, m2) : 0.0;
+                Hc[u][cc] = mfma64(a, b, Hc[u][cc]);
+              }
             }
           }
         }
       }
     }
-    double* HP = d.H + d.e_off[P];
-    const int* m2P = d.map2 + d.map_off[P];
+  }
+  // store (accumulate in G-only mode)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int col = (c < ncols) ? m2P[gcol[c]] : -1;
-      if (col >= 0 && muv) {
+  for (int u = 0; u < U; ++u) {
+    if (u < nU) {
+      const int P = un.P[u], aP = un.a[u], bP = un.b[u], mP = d.m_loc[P];
+      const int muB = un.mu0[u] + lr;
+      double* HP = d.H + d.e_off[P];
+      const int* m2P = d.map2 + d.map_off[P];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = lk + 4 * v;
-          if (j < bP) {
-            double* h = HP + (size_t)(muB * bP + j) * mP + col;
-            *h = g_only ? *h + Hc[c][v] : Hc[c][v];
+      for (int cc = 0; cc < H_CPW; ++cc) {
+        const int c = c0 + cc;
+        const int col = (c < ncols) ? m2P[gcol[c]] : -1;
+        if (col >= 0 && muB < aP) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = lk + 4 * v;
+            if (j < bP) {
+              double* h = HP + (size_t)(muB * bP + j) * mP + col;
+              *h = g_only ? *h + Hc[u][cc][v] : Hc[u][cc][v];
+            }
           }
         }
       }
@@ -1225,8 +1312,14 @@ static void launch_H(exx_plan plan, const double* V, const double* D, double gsc
                      hipStream_t st) {
   const HostPlan& hp = plan->hp;
   const int nH = (int)hp.g_tiles.size(), nHp = (nH + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_H, dim3(nHp), dim3(64 * hp.h_waves), g_only ? 0 : plan->h_lds, st, V, D, plan->d,
-                     nH, nHp, gscale, g_only);
+  const size_t lds = g_only ? 0 : plan->h_lds;
+  const dim3 grid(nHp), blk(64 * H_WAVES);
+  if (hp.h_waves <= 2)
+    hipLaunchKernelGGL(k_H<2>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
+  else if (hp.h_waves <= 5)
+    hipLaunchKernelGGL(k_H<5>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
+  else
+    hipLaunchKernelGGL(k_H<8>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
 }
 
 static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st) {

@@ -28,6 +28,7 @@ struct GTile { int grp, col_beg, ncols, q_beg, q_end, x_beg, x_end, pad; };  // 
 struct Slot4 { int atom, p0, p1, p2; };      // list entry: atom, pair id with group slots 0..2 (-1: none)
 
 constexpr int GROUP_ATOMS = 3;       // atoms per H group (slots)
+constexpr int H_COLS = 8;            // columns per V-stage tile
 constexpr int GROUP_WAVES = 8;       // wavefronts per H workgroup at most
 constexpr double GROUP_RADIUS = 2.5; // A, group atoms lie within this of the first
 struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)

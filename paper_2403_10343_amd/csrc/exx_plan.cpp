@@ -371,8 +371,8 @@ int derive_lists(HostPlan& hp, std::string& err) {
         }
         return e;
       };
-      for (int c0 = 0; c0 < ncol; c0 += 16) {
-        const int c1 = std::min(ncol, c0 + 16);
+      for (int c0 = 0; c0 < ncol; c0 += H_COLS) {
+        const int c1 = std::min(ncol, c0 + H_COLS);
         ++stampv;
         for (int c = c0; c < c1; ++c) stamp2[col_atom[c]] = stampv;
         GTile tl{};
@@ -392,9 +392,12 @@ int derive_lists(HostPlan& hp, std::string& err) {
         for (int e = tl.q_beg; e < tl.q_end; ++e) {
           const int q = hp.gq[e].atom;
           const int* sl = &hp.gq[e].p0;
+          int cq = 0;   // tile columns present in N[Q]
+          for (int c = c0; c < c1; ++c)
+            cq += std::binary_search(nat.begin() + np[q], nat.begin() + np[q + 1], col_atom[c]);
           for (int t = 0; t < n; ++t)
             if (sl[t] >= 0)
-              hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * tl.ncols *
+              hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * cq *
                               (((hp.na[q] + 3) / 4) + ((hp.nb[q] + 3) / 4));
         }
         for (int e = tl.x_beg; e < tl.x_end; ++e) {
