@@ -554,14 +554,14 @@ constexpr int T2_PITCH = T2_COLS + 1;
 
 template <int NT, int NS>
 __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double* __restrict__ K,
-                                            DevPlan d, int n_items, int n_padded) {
+                                            DevPlan d, int n_items, int n_padded, int item_base) {
   extern __shared__ double sm[];
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
-  const int p = d.t2_items[w] >> 1;
-  const bool flip = d.t2_items[w] & 1;
+  const int p = d.t2_items[item_base + w] >> 1;
+  const bool flip = d.t2_items[item_base + w] & 1;
   const int P = flip ? d.pair_b[p] : d.pair_a[p], Q = flip ? d.pair_a[p] : d.pair_b[p];
   const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
   const int sP = aP * bP, sQ = aQ * bQ;
@@ -600,24 +600,26 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
     for (int h = 0; h < T2_COLS / 4; ++h) {
       const int c = wv * (T2_COLS / 4) + h;
       if (l0 + c < nQ) {
+        // straight-line chains: NT aux tiles of P, NS nu steps of Q (compile time)
+        double b[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int nu = 4 * q + lk;
+          const bool ok = kv && nu < aQ;
+          const double t = sT[(ok ? (nu * bQ + lr) * T2_PITCH : 0) + c];
+          b[q] = ok ? t : 0.0;
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          if (t < nt) {
-            d4 F = d4{0, 0, 0, 0};
+          d4 F = d4{0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < NS; ++q) {
-              if (q < nsr) {
-                const int nu = 4 * q + lk;
-                const double b = (kv && nu < aQ) ? sT[(nu * bQ + lr) * T2_PITCH + c] : 0.0;
-                F = mfma64(va[t][q], b, F);
-              }
-            }
+          for (int q = 0; q < NS; ++q) F = mfma64(va[t][q], b[q], F);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int mu = 16 * t + 4 * v + lk;
-              const double a2 = (iv && mu < aP) ? sE[(mu * bP + lr) * T2_PITCH + c] : 0.0;
-              acc = mfma64(a2, F[v], acc);
-            }
+          for (int v = 0; v < 4; ++v) {
+            const int mu = 16 * t + 4 * v + lk;
+            const bool ok = iv && mu < aP;
+            const double x = sE[(ok ? (mu * bP + lr) * T2_PITCH : 0) + c];
+            acc = mfma64(ok ? x : 0.0, F[v], acc);
           }
         }
       }
@@ -1322,15 +1324,35 @@ static void launch_H(exx_plan plan, const double* V, const double* D, double gsc
     hipLaunchKernelGGL(k_H<8>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
 }
 
+extern "C++" {
+template <int NT>
+static void launch_T2_nt(exx_plan plan, int nsc, const double* V, double* K, int beg, int n, hipStream_t st) {
+  const int np_ = (n + 7) / 8 * 8;
+  DevPlan& d = plan->d;
+  const size_t lds = plan->t2_lds;
+  switch (nsc) {
+    case 4: hipLaunchKernelGGL((k_T2<NT, 4>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
+    case 8: hipLaunchKernelGGL((k_T2<NT, 8>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
+    case 10: hipLaunchKernelGGL((k_T2<NT, 10>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
+    case 12: hipLaunchKernelGGL((k_T2<NT, 12>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
+    default: hipLaunchKernelGGL((k_T2<NT, 16>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
+  }
+}
+
+}  // extern "C++"
+
+// one launch per shape class (aux tiles of P, nu steps of Q) of the pairs
 static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st) {
   const HostPlan& hp = plan->hp;
-  DevPlan& d = plan->d;
-  const int nT = (int)hp.t2_items.size(), nTp = (nT + 7) / 8 * 8;
-  switch (plan->t2_nt) {
-    case 1: hipLaunchKernelGGL((k_T2<1, 4>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-    case 2: hipLaunchKernelGGL((k_T2<2, 8>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-    case 3: hipLaunchKernelGGL((k_T2<3, 12>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
-    default: hipLaunchKernelGGL((k_T2<4, 16>), dim3(nTp), dim3(256), plan->t2_lds, st, V, K, d, nT, nTp); break;
+  for (const T2Class& c : hp.t2_classes) {
+    const int n = c.end - c.beg;
+    if (n <= 0) continue;
+    switch (c.nt) {
+      case 1: launch_T2_nt<1>(plan, c.ns, V, K, c.beg, n, st); break;
+      case 2: launch_T2_nt<2>(plan, c.ns, V, K, c.beg, n, st); break;
+      case 3: launch_T2_nt<3>(plan, c.ns, V, K, c.beg, n, st); break;
+      default: launch_T2_nt<4>(plan, c.ns, V, K, c.beg, n, st); break;
+    }
   }
 }
 

@@ -427,6 +427,25 @@ int derive_lists(HostPlan& hp, std::string& err) {
     hp.flops[3] += 2LL * hp.na[a] * hp.na[b] * hp.nb[b] * hp.n_loc[b] + 2LL * hp.na[a] * hp.nb[a] * hp.nb[b] * hp.n_loc[b];
     hp.issued[3] += 2048LL * cost(a, b);
   }
+  // shape classes: aux tiles of 16 of the row atom, nu steps of 4 (rounded up
+  // to a compiled size) of the column atom; stable sort keeps pair order inside
+  {
+    auto ns_class = [](int ns) { return ns <= 4 ? 4 : ns <= 8 ? 8 : ns <= 10 ? 10 : ns <= 12 ? 12 : 16; };
+    auto key = [&](int item) {
+      const int p = item >> 1;
+      const bool flip = item & 1;
+      const int a = flip ? hp.pair_b[p] : hp.pair_a[p], b = flip ? hp.pair_a[p] : hp.pair_b[p];
+      return ((hp.na[a] + 15) / 16) * 64 + ns_class((hp.na[b] + 3) / 4);
+    };
+    std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    hp.t2_classes.clear();
+    for (int i = 0; i < (int)hp.t2_items.size(); ++i) {
+      const int k = key(hp.t2_items[i]);
+      if (hp.t2_classes.empty() || hp.t2_classes.back().nt * 64 + hp.t2_classes.back().ns != k)
+        hp.t2_classes.push_back(T2Class{k / 64, k % 64, i, i});
+      hp.t2_classes.back().end = i + 1;
+    }
+  }
   // ---- final tasks: 32 x 32 tile pairs (upper triangle) with their P-lists
   hp.f_items.clear();
   hp.f_plist.clear();
