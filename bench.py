@@ -21,6 +21,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
+CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
+# HBM bytes per dispatch, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# this script on the 768-atom box, scaled by what the counters read for a 1 GiB
+# device copy in the same runs (read x2.0, write x1.0).  They describe the
+# kernels built from the sources with this fingerprint only; for any other
+# sources the roofline's traffic is reported as null.
+MEASURED_TRAFFIC = {
+    "sources": "9af96e36e2db7b97",
+    "workload": "ice768",
+    "bytes": {"H": 23.905e9 + 3.472e9, "T2": 40.141e9 + 0.025e9, "final": 10.606e9 + 4.290e9,
+              "E": 2.536e9 + 2.632e9},
+}
+
+
+def sources_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("exx_device.hip", "exx_internal.h", "exx_plan.cpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 WORKLOADS = {
     "ice768": (2, "ice_box_4x4x2_768_atoms_6144_basis_rcut6"),
     "water24": (1, "water_cluster_8_24_atoms_192_basis_rcut6"),
@@ -60,6 +81,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--backward-steps", type=int, default=3,
+                    help="also time forward + exchange_backward (dE/dC, dE/dV, dE/dD, forces); 0 = skip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -109,6 +132,10 @@ def main():
     achieved = flops_dom / (avg_ms[dom] * 1e-3) if avg_ms[dom] > 0 else 0.0
     total_flops = plan.flops()
     e_x = float(Ex[0].item())
+    traffic = None
+    if (MEASURED_TRAFFIC["workload"] == args.workload and sources_fingerprint() == MEASURED_TRAFFIC["sources"]
+            and names[dom] in MEASURED_TRAFFIC["bytes"]):
+        traffic = MEASURED_TRAFFIC["bytes"][names[dom]]
 
     out = {
         "metric": "K-matrix builds/s (RI-LVL exchange, FP64 path)",
@@ -128,7 +155,7 @@ def main():
                    "r_cut_A": sysm.r_cut, "precision": args.precision},
         "roofline": {"bound": "mfma", "kernel": f"k_{names[dom]}", "achieved": achieved / 1e12,
                      "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"],
-                     "traffic": None},
+                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM read + write)"},
         "algorithmic_gflop_per_build": total_flops / 1e9,
         "whole_build_tflops": total_flops * builds_per_s / 1e12,
         "whole_build_frac_fp64_peak": total_flops * builds_per_s / PEAK["fp64"],
@@ -140,6 +167,25 @@ def main():
         "E_x": e_x,
         "E_x_per_atom": e_x / sysm.n_atoms,
     }
+    if args.backward_steps > 0:
+        dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D)
+        F = torch.empty(sysm.n_atoms * 3, dtype=torch.float64, device=dev)
+        plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for _ in range(args.backward_steps):
+            plan.build_K(C, V, D, K, Ex, precision=prec)
+            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - tb0) / args.backward_steps
+        Ff = F.view(-1, 3)
+        out["forward_backward"] = {
+            "workload": wname + " (E_x, dE/dC, dE/dV, dE/dD, forces)",
+            "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
+            "net_force_max": float(Ff.sum(0).abs().max().item()),
+            "euler_C": float((dC * C).sum().item() / (2 * e_x)),
+            "euler_V": float((dV * V).sum().item() / e_x),
+        }
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -32,8 +32,8 @@ constexpr int H_COLS = 8;            // columns per V-stage tile
 constexpr int GROUP_WAVES = 8;       // wavefronts per H workgroup at most
 constexpr double GROUP_RADIUS = 2.5; // A, group atoms lie within this of the first
 struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)
-struct YTile { int P, m0, n0, pad; };
-struct T2Class { int nt, ns, beg, end; };        // pairs [beg, end) of t2_items with this shape          // 64 x 64 tile of Y_P = T_P^T H'_P
+struct YTile { int P, m0, n0, pad; };          // 64 x 64 tile of Y_P = T_P^T H'_P
+struct T2Class { int nt, ns, beg, end; };      // pairs [beg, end) of t2_items with this shape
 
 struct HostPlan {
   // system description
