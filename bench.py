@@ -151,7 +151,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "atoms": sysm.n_atoms,
-                   "basis": int(inp.layout.sys_nbas[0]), "aux": int(synth.N_AUX[sysm.species].sum()),
+                   "basis": int(inp.layout.sys_nbas[0]), "aux": int(sysm.naux().sum()),
                    "r_cut_A": sysm.r_cut, "precision": args.precision},
         "roofline": {"bound": "mfma", "kernel": f"k_{names[dom]}", "achieved": achieved / 1e12,
                      "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"],

@@ -73,9 +73,8 @@ class Blocks:
         self.lo, self.hi = int(sysm.sys_off[s]), int(sysm.sys_off[s + 1])
         self.nat = self.hi - self.lo
         sp = sysm.species[self.lo:self.hi]
-        from synth.water import N_AUX, N_BASIS  # species table (input metadata)
-        self.nb = N_BASIS[sp].astype(np.int64)
-        self.na = N_AUX[sp].astype(np.int64)
+        self.nb = sysm.basis_table[sp].astype(np.int64)   # species tables: input metadata
+        self.na = sysm.aux_table[sp].astype(np.int64)
         self.bo = np.concatenate([[0], np.cumsum(self.nb)])
         self.ao = np.concatenate([[0], np.cumsum(self.na)])
         self.n, self.naux = int(self.bo[-1]), int(self.ao[-1])

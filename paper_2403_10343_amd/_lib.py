@@ -131,9 +131,9 @@ class Plan:
 
     @classmethod
     def for_system(cls, system, host_only=False):
-        """Plan for a ``synth.System``-like object (species, pos, r_cut, sys_off)."""
-        from synth.water import N_AUX, N_BASIS
-        return cls(system.species, system.pos, N_BASIS, N_AUX, system.r_cut,
+        """Plan for a ``synth.System``-like object (species, pos, species tables
+        basis_table / aux_table, r_cut, sys_off)."""
+        return cls(system.species, system.pos, system.basis_table, system.aux_table, system.r_cut,
                    system.sys_off if system.n_systems > 1 else None, host_only)
 
     def _info(self):

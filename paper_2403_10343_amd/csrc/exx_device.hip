@@ -1188,6 +1188,15 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
     pl->t2_lds = std::max((size_t)2 * smax * T2_PITCH, (size_t)16 * 64) * sizeof(double);
   }
   if (!pl->host_only) {
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) != hipSuccess) {
+      delete pl;
+      return fail(EXX_EDEVICE, "exx_plan_create: cannot query the LDS size");
+    }
+    if (pl->t2_lds > (size_t)lds_max || pl->h_lds + 8192 > (size_t)lds_max) {
+      delete pl;
+      return fail(EXX_EUNSUPPORTED, "exx_plan_create: the largest n_aux * n_basis needs more LDS than a workgroup has");
+    }
     if ((rc = upload_plan(pl)) != 0) {
       release(pl);
       delete pl;

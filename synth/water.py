@@ -65,6 +65,8 @@ class System:
     labels: np.ndarray = None      # (n_atoms,) int64, persistent ids for RNG keys
     sys_off: np.ndarray = None     # (n_systems + 1,) int32 atom offsets
     name: str = ""
+    basis_table: np.ndarray = None  # per-species basis counts (default N_BASIS)
+    aux_table: np.ndarray = None    # per-species aux counts (default N_AUX)
 
     def __post_init__(self):
         self.species = np.ascontiguousarray(self.species, dtype=np.int32)
@@ -76,6 +78,10 @@ class System:
         if self.sys_off is None:
             self.sys_off = np.array([0, n], dtype=np.int32)
         self.sys_off = np.ascontiguousarray(self.sys_off, dtype=np.int32)
+        self.basis_table = np.ascontiguousarray(N_BASIS if self.basis_table is None else self.basis_table,
+                                                dtype=np.int32)
+        self.aux_table = np.ascontiguousarray(N_AUX if self.aux_table is None else self.aux_table,
+                                              dtype=np.int32)
 
     @property
     def n_atoms(self):
@@ -86,10 +92,10 @@ class System:
         return len(self.sys_off) - 1
 
     def nbas(self):
-        return N_BASIS[self.species]
+        return self.basis_table[self.species]
 
     def naux(self):
-        return N_AUX[self.species]
+        return self.aux_table[self.species]
 
 
 @dataclass
@@ -229,7 +235,8 @@ def permuted(system, perm):
     perm = np.asarray(perm)
     assert system.n_systems == 1
     return System(system.species[perm], system.pos[perm], system.r_cut, system.seed,
-                  labels=system.labels[perm], name=system.name + "_perm")
+                  labels=system.labels[perm], name=system.name + "_perm",
+                  basis_table=system.basis_table, aux_table=system.aux_table)
 
 
 # ----------------------------------------------------------------------------
@@ -281,10 +288,10 @@ def _sym_upper(x):
     return u + np.swapaxes(np.triu(x, 1), -1, -2)
 
 
-def v_factors(seed):
+def v_factors(seed, aux_table=N_AUX):
     rng = _rng(seed, _KIND_V)
-    return [rng.normal(size=(int(N_AUX[s]), L_RANK)) / math.sqrt(L_RANK)
-            for s in range(len(N_AUX))]
+    return [rng.normal(size=(int(aux_table[s]), L_RANK)) / math.sqrt(L_RANK)
+            for s in range(len(aux_table))]
 
 
 def make_inputs(system, layout=None, zero_D=False):
@@ -292,11 +299,11 @@ def make_inputs(system, layout=None, zero_D=False):
     if layout is None:
         layout = make_layout(system)
     sp, lab, pos = system.species, system.labels, system.pos
-    nb, na = N_BASIS, N_AUX
+    nb, na = system.basis_table, system.aux_table
     C = np.empty(int(layout.c_off[-1]))
     V = np.empty(int(layout.v_off[-1]))
     D = np.zeros(layout.d_size)
-    L = v_factors(system.seed)
+    L = v_factors(system.seed, na)
     seeds = getattr(system, "cluster_seeds", None)
     atom_sys = np.zeros(system.n_atoms, dtype=np.int64)
     for s in range(system.n_systems):
@@ -305,7 +312,7 @@ def make_inputs(system, layout=None, zero_D=False):
         A, B = int(layout.pair_a[p]), int(layout.pair_b[p])
         sA, sB = int(sp[A]), int(sp[B])
         seed = system.seed if seeds is None else seeds[atom_sys[A]]
-        Ls = L if seeds is None else v_factors(seed)
+        Ls = L if seeds is None else v_factors(seed, na)
         d = pos[A] - pos[B]
         r = math.sqrt(float(d @ d))
         c0, c1 = int(layout.c_off[p]), int(layout.c_off[p + 1])

@@ -31,8 +31,8 @@ def rel(a, b):
 
 
 def _offsets(sysm):
-    nb = synth.N_BASIS[sysm.species].astype(int)
-    na = synth.N_AUX[sysm.species].astype(int)
+    nb = sysm.nbas().astype(int)
+    na = sysm.naux().astype(int)
     return nb, na, np.concatenate([[0], np.cumsum(nb)]), np.concatenate([[0], np.cumsum(na)])
 
 
@@ -172,7 +172,7 @@ def pin_permutation(route="rows", seed=4):
     inp_p = synth.make_inputs(sp)
     K = _route(inp, route)
     Kp = _route(inp_p, route)
-    nb = synth.N_BASIS[sysm.species]
+    nb = sysm.nbas()
     bo = np.concatenate([[0], np.cumsum(nb)])
     bidx = np.concatenate([np.arange(bo[a], bo[a + 1]) for a in perm])
     r = rel(Kp, K[np.ix_(bidx, bidx)])

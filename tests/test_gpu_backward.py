@@ -51,6 +51,22 @@ def test_gradients_match_oracle(exx, n_mol, seed):
     assert relmax(g["F"], Fo) < 1e-10
 
 
+@pytest.mark.parametrize("tables", [([16, 3], [64, 7]), ([1, 2], [1, 5])])
+def test_gradients_other_species_shapes(exx, tables):
+    nb, na = tables
+    base = synth.water_cluster(3, seed=21)
+    sysm = synth.System(base.species, base.pos, 6.0, seed=21,
+                        basis_table=np.array(nb), aux_table=np.array(na))
+    print("backward species tables", tables, flush=True)
+    inp = synth.make_inputs(sysm)
+    g = backward(exx.Plan.for_system(sysm), inp)
+    go = O.gradients(inp)
+    assert relmax(g["dC"], go["dC"]) < 1e-10
+    assert relmax(g["dV"], go["dV"]) < 1e-10
+    assert relmax(system_block(g["dD"], inp.layout, 0), go["dD"]) < 1e-10
+    assert relmax(g["F"], O.forces(inp, go)) < 1e-10
+
+
 def test_partial_outputs_and_scaling(exx):
     sysm = synth.water_cluster(2, 5)
     inp = synth.make_inputs(sysm)

@@ -111,3 +111,32 @@ def test_config2_sampled_rows(exx):
     assert np.abs(Kg[rows] - Kr).max() < TOL_K * scale
     assert np.array_equal(Kg, Kg.T)
     assert abs(Ex[0] - O.exchange_energy(Kg, blk.D)) < 1e-12 * abs(Ex[0])
+
+
+def test_hand_worked_two_atom_case(exx):
+    """Two one-function atoms; K and E_x worked out by hand (tests/golden)."""
+    from tests.test_oracle import golden_inputs
+    inp, g = golden_inputs("two_atom_hand.json")
+    K, Ex = run_build(_plan(exx, inp.system), inp, torch)
+    assert np.abs(K - np.array(g["K"])).max() < 1e-12
+    assert abs(Ex[0] - g["E_x"]) < 1e-12
+
+
+@pytest.mark.parametrize("tables", [([16, 3], [64, 7]), ([7, 1], [23, 2]), ([1, 2], [1, 5]),
+                                    ([16, 16], [64, 64]), ([12, 9], [33, 17])])
+def test_other_species_shapes(exx, tables):
+    """Basis / aux counts away from the water species, up to the limits
+    (16 basis, 64 aux per atom): every shape class of the kernels, ragged
+    tiles, groups of up to 8 aux tiles."""
+    nb, na = tables
+    base = synth.water_cluster(4, seed=17)
+    sysm = synth.System(base.species, base.pos, 6.0, seed=17,
+                        basis_table=np.array(nb), aux_table=np.array(na))
+    print("species tables", tables, flush=True)
+    inp = synth.make_inputs(sysm)
+    K, Ex = run_build(_plan(exx, sysm), inp, torch)
+    Kg = system_block(K, inp.layout, 0)
+    Ko = O.k_eigen(inp)
+    assert relmax(Kg, Ko) < TOL_K
+    Eo = O.exchange_energy(Ko, O.Blocks(inp).D)
+    assert abs(Ex[0] - Eo) < TOL_E * abs(Eo)

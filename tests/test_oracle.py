@@ -47,3 +47,28 @@ def test_batch_systems_independent():
         K1 = O.k_eigen(inp, s)
         K2 = O.k_eigen(synth.make_inputs(alone))
         assert pins.rel(K1, K2) < 1e-13
+
+
+def golden_inputs(name):
+    """Inputs of a hand-worked fixture in tests/golden (layout from synth)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        g = json.load(fh)
+    sysm = synth.System(np.array(g["species"]), np.array(g["positions"]), g["r_cut"], 0,
+                        basis_table=np.array(g["basis_table"]), aux_table=np.array(g["aux_table"]))
+    lay = synth.make_layout(sysm)
+    inp = synth.Inputs(sysm, lay, np.array(g["C"]), np.array(g["V"]), np.array(g["D"]))
+    return inp, g
+
+
+def test_hand_worked_two_atom_case():
+    inp, g = golden_inputs("two_atom_hand.json")
+    assert len(inp.C) == len(g["C"]) and len(inp.V) == len(g["V"])
+    Kx = np.array(g["K"]).reshape(2, 2)
+    K4, e_k, e_direct = O.k_4index(inp)
+    assert np.abs(K4 - Kx).max() < 1e-12
+    assert np.abs(O.k_eigen(inp) - Kx).max() < 1e-12
+    assert np.abs(O.k_full_rows(inp) - Kx).max() < 1e-12
+    assert abs(e_k - g["E_x"]) < 1e-12 and abs(e_direct - g["E_x"]) < 1e-12
+    assert abs(O.exchange_energy(Kx, inp.D.reshape(2, 2)) - g["E_x"]) < 1e-12
