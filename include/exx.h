@@ -67,8 +67,8 @@ extern "C" {
 #define EXX_EUNSUPPORTED -5   /* option not implemented */
 
 /* arithmetic of the contraction stages */
-#define EXX_PREC_FP64     0   /* binary64 everywhere (FP64 MFMA + FP64 FMA) */
-#define EXX_PREC_FP32     1   /* binary32 operands and MFMA, binary32 accumulation */
+#define EXX_PREC_FP64     0   /* binary64 everywhere (FP64 MFMA) */
+#define EXX_PREC_MIXED    1   /* distance-split mixed precision, see exx_plan_set_mixed_split */
 
 /* plan flags */
 #define EXX_PLAN_HOST_ONLY 1u /* build the lists on the host only; no device use */
@@ -131,16 +131,28 @@ int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom);
 int build_K(exx_plan plan, const double* C, const double* V, const double* D,
             int precision, double* K, double* Ex, void* stream);
 
-/* Capture one build_K (FP64, these exact arrays) on `stream` into a HIP
- * graph owned by the plan, replacing any earlier one; exx_graph_launch()
- * replays it.  The arrays must stay valid while the graph is used.  The
+/* Capture one build_K (these exact arrays, `precision` as in build_K) on
+ * `stream` into a HIP graph owned by the plan, replacing any earlier one;
+ * exx_graph_launch() replays it.  The arrays must stay valid while the graph is used.  The
  * captured work is kernel launches only (buffers are cleared by kernels).
  * `stream` must be a created stream (capture on the default stream is
  * rejected with EXX_EINVAL).  Replays on one plan must not overlap: they
  * share the plan's workspace. */
 int exx_graph_build(exx_plan plan, const double* C, const double* V, const double* D,
-                    double* K, double* Ex, void* stream);
+                    int precision, double* K, double* Ex, void* stream);
 int exx_graph_launch(exx_plan plan, void* stream);
+
+/* Mixed precision (EXX_PREC_MIXED in build_K).  K is linear in V, and every
+ * pair term of the V stage and of the T2 blocks belongs to one aux-atom pair
+ * (P, Q) (Eq. temp_F, temp_G, temp_H and the F-E term of Eq.
+ * ri_lvl_exchange_matrix).  Terms of pairs with |R_P - R_Q| >= r_split (their
+ * V, C and D blocks are the small ones, decaying with distance) run with
+ * binary32 operands on FP32 MFMA with binary32 accumulation; all other terms,
+ * E = M D, the final contraction, K itself and E_x stay binary64.  The
+ * default split is 5.0 A; r_split = 0 puts every pair term in binary32.
+ * Changing the split rebuilds the split lists (a blocking call) and drops a
+ * captured graph.  Returns EXX_EINVAL unless 0 <= r_split <= 1e6. */
+int exx_plan_set_mixed_split(exx_plan plan, double r_split);
 
 /* E_x = -1/4 sum_ik K_ik D_ik for every system (device Ex [n_systems]),
  * a fixed-order binary64 reduction (bitwise reproducible). */
@@ -157,7 +169,8 @@ int exchange_energy(exx_plan plan, const double* K, const double* D,
  *   forces (device [n_atoms][3], may be NULL): -d(gE E_x)/dR for the
  *       synthetic model C_AB ~ exp(-r_AB / c_decay), V_AB ~ exp(-r_AB^2 / v_2s2)
  *       (on-site blocks position independent, D held fixed).
- * Any of dC, dV, dD may be NULL to skip it. */
+ * Any of dC, dV, dD may be NULL to skip it.  precision must be
+ * EXX_PREC_FP64 (EXX_PREC_MIXED returns EXX_EUNSUPPORTED). */
 int exchange_backward(exx_plan plan, const double* C, const double* V,
                       const double* D, double gE, int precision,
                       double* dC, double* dV, double* dD, double* forces,
@@ -167,17 +180,22 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
  * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction:
  * 2*m*n*k summed over the structurally nonzero blocks.  Stages 10..14 give
  * the flops the MFMA instructions of stage 0..4 actually issue (tile padding
- * included). */
+ * included).  For the mixed build at the current split: 20..24 the
+ * algorithmic flops run in binary32, 30..34 the issued binary32 MFMA flops,
+ * 40..44 the issued binary64 MFMA flops. */
 int64_t exx_plan_flops(exx_plan plan, int stage);
 
 /* Instrumentation: when enabled, build_K records HIP events on its stream at
- * the boundaries of its EXX_N_STAGES stages (0 zero-fill + repack of C,
- * 1 E = M D, 2 V stage, 3 T2 blocks, 4 final contraction, 5 energy), for up
- * to 512 builds.  exx_plan_stage_times() waits for the recorded builds, adds
- * their per-stage durations into ms[EXX_N_STAGES] (milliseconds, host
- * array), stores how many builds were recorded in *n_builds and starts a new
- * recording.  Enabling (or re-enabling) clears earlier records. */
-#define EXX_N_STAGES 6
+ * the boundaries of its EXX_N_STAGES stages, for up to 512 builds:
+ *   0 zero-fill + repack of C, 1 E = M D, 2 V stage in binary64 (all pairs,
+ *   or the near pairs of a mixed build), 3 V stage in binary32 (far pairs of
+ *   a mixed build; empty otherwise), 4 T2 in binary64, 5 T2 in binary32
+ *   (mixed only), 6 final contraction, 7 energy.
+ * exx_plan_stage_times() waits for the recorded builds, adds their per-stage
+ * durations into ms[EXX_N_STAGES] (milliseconds, host array), stores how many
+ * builds were recorded in *n_builds and starts a new recording.  Enabling
+ * (or re-enabling) clears earlier records. */
+#define EXX_N_STAGES 8
 int exx_plan_set_profiling(exx_plan plan, int enable);
 int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds);
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libexx.so")
 
 EXX_OK, EXX_EINVAL, EXX_ENOMEM, EXX_EDEVICE, EXX_ESTATE, EXX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
 PLAN_HOST_ONLY = 1
 
 _lib = None
@@ -51,9 +51,9 @@ class _Info(ctypes.Structure):
 EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pairs",
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
-           "exx_graph_build", "exx_graph_launch")
-N_STAGES = 6
-STAGE_NAMES = ("repack", "E", "H", "T2", "final", "energy")
+           "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split")
+N_STAGES = 8
+STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
 
 def lib():
@@ -73,7 +73,8 @@ def lib():
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
-    L.exx_graph_build.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.exx_plan_set_mixed_split.argtypes = [vp, dp]
     L.exx_graph_launch.argtypes = [vp, vp]
     L.exx_plan_set_profiling.argtypes = [vp, ctypes.c_int]
     L.exx_plan_stage_times.argtypes = [vp, vp, vp]
@@ -158,6 +159,18 @@ class Plan:
     def flops(self, stage=-1):
         return int(lib().exx_plan_flops(self._h, stage))
 
+    def stage_flops(self, mixed=False):
+        """Algorithmic and issued MFMA flops of each profiled stage (STAGE_NAMES
+        order) for an FP64 or a mixed build: two lists of N_STAGES ints."""
+        f = [self.flops(i) for i in range(5)]
+        iss = [self.flops(10 + i) for i in range(5)]
+        f32 = [self.flops(20 + i) for i in range(5)] if mixed else [0] * 5
+        i32 = [self.flops(30 + i) for i in range(5)] if mixed else [0] * 5
+        i64 = [self.flops(40 + i) for i in range(5)] if mixed else iss
+        alg = [f[0], f[1], f[2] - f32[2], f32[2], f[3] - f32[3], f32[3], f[4], 0]
+        issued = [i64[0], i64[1], i64[2], i32[2], i64[3], i32[3], i64[4], 0]
+        return alg, issued
+
     def build_K(self, C, V, D, K, Ex=None, precision=PREC_FP64, stream=None):
         _check(lib().build_K(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
                              _stream(stream)))
@@ -171,9 +184,14 @@ class Plan:
                                        _ptr(dC), _ptr(dV), _ptr(dD), _ptr(forces),
                                        float(c_decay), float(v_2s2), _stream(stream)))
 
-    def graph_build(self, C, V, D, K, Ex, stream):
-        """Capture one FP64 build_K on `stream` (a created stream) into a HIP graph."""
-        _check(lib().exx_graph_build(self._h, _ptr(C), _ptr(V), _ptr(D), _ptr(K), _ptr(Ex), _stream(stream)))
+    def graph_build(self, C, V, D, K, Ex, stream, precision=PREC_FP64):
+        """Capture one build_K on `stream` (a created stream) into a HIP graph."""
+        _check(lib().exx_graph_build(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
+                                     _stream(stream)))
+
+    def set_mixed_split(self, r_split):
+        """Distance (A) at and beyond which pair terms run in binary32 (PREC_MIXED)."""
+        _check(lib().exx_plan_set_mixed_split(self._h, float(r_split)))
 
     def graph_launch(self, stream=None):
         _check(lib().exx_graph_launch(self._h, _stream(stream)))

@@ -42,6 +42,29 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Arithmetic of the pair-term kernels (V stage, T2) by element type R.
+// Both 16x16x4 MFMAs take A[L%16][L/16] and B[L/16][L%16]; they differ in
+// where the result lands: accumulator element v of lane L is row
+// row(L/16, v) of the 16 x 16 result (column L%16).  A chained product uses
+// element v as its B operand, i.e. as k-row row(L/16, v).
+template <typename R> struct Mf;
+template <> struct Mf<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mf<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
 static thread_local std::string g_err;
 
 static int fail(int code, const std::string& msg) {
@@ -83,6 +106,9 @@ struct DevPlan {
   GTile* g_tiles;
   Slot4 *gq, *gx;
   int* t2_items;
+  GTile *hm_tiles_near, *hm_tiles_far;
+  Slot4 *hm_q_near, *hm_x_near, *hm_q_far, *hm_x_far;
+  int* t2m_items;
   FItem* f_items;
   int* f_plist;
   int *en_sys, *en_beg, *en_end;
@@ -91,7 +117,7 @@ struct DevPlan {
   double *T, *E, *H, *Y, *GD, *sC, *sV, *epart;
 };
 
-constexpr int N_STAGE_EV = 7;   // boundaries: start, repack, E, H, T2, final, energy
+constexpr int N_STAGE_EV = EXX_N_STAGES + 1;   // stage boundaries, start and end included
 constexpr int MAX_PROFILED = 512;
 
 struct exx_plan_s {
@@ -106,8 +132,13 @@ struct exx_plan_s {
   std::vector<hipEvent_t> events;   // MAX_PROFILED * N_STAGE_EV, created lazily
   int n_recorded = 0;
   int t2_nt = 4;                    // aux tiles of 16 needed by the largest atom
-  size_t h_lds = 0;                 // dynamic LDS bytes of k_H
-  size_t t2_lds = 0;                // dynamic LDS bytes of k_T2
+  size_t h_lds = 0;                 // dynamic LDS bytes of k_H (binary64)
+  size_t t2_lds = 0;                // dynamic LDS bytes of k_T2 (binary64)
+  size_t h_lds32 = 0, t2_lds32 = 0; // the same for the binary32 kernels
+  int h_vbase = 0, h_dbase = 0;     // element offsets of V and D in k_H's LDS
+  std::vector<void*> mixed_allocs;  // device copies of the mixed-precision lists
+  int64_t mixed_bytes = 0;
+  bool mixed_uploaded = false;
   hipGraph_t graph = nullptr;       // captured build_K (exx_graph_build)
   hipGraphExec_t graph_exec = nullptr;
   double* dC_scratch = nullptr;     // gradient buffers used when the caller passes NULL
@@ -115,13 +146,13 @@ struct exx_plan_s {
 };
 
 template <typename X>
-static int upload(exx_plan_s* p, X*& dst, const std::vector<X>& src) {
+static int upload(exx_plan_s* p, X*& dst, const std::vector<X>& src, bool mixed = false) {
   dst = nullptr;
   if (src.empty()) return 0;
   size_t bytes = src.size() * sizeof(X);
   HIP_TRY(hipMalloc((void**)&dst, bytes));
-  p->allocs.push_back(dst);
-  p->dev_bytes += bytes;
+  (mixed ? p->mixed_allocs : p->allocs).push_back(dst);
+  (mixed ? p->mixed_bytes : p->dev_bytes) += bytes;
   HIP_TRY(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
   return 0;
 }
@@ -327,6 +358,7 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
 // The chain lengths are compile-time per shape class of Q.
 
 constexpr int LDS_PITCH = H_COLS + 1;   // doubles per staged row (one pad column: no bank conflicts)
+constexpr int H_DPITCH = 17;            // staged D_PQ blocks: [slot][16 rows][17]
 constexpr int HQ_CHUNK = 64;            // Q-list entries whose metadata sits in LDS at once
 constexpr int H_WAVES = 4;
 constexpr int H_CPW = H_COLS / H_WAVES;
@@ -341,74 +373,125 @@ struct HUnits {            // unit table of the group (LDS)
   int P[GROUP_WAVES], mu0[GROUP_WAVES], slot[GROUP_WAVES], a[GROUP_WAVES], b[GROUP_WAVES], bo[GROUP_WAVES];
 };
 
-template <int NS, int NL, int U>
-__device__ __forceinline__ void h_q(d4 (&Hc)[U][H_CPW], const double* sT, const HUnits& un, int nU,
-                                    const int* qp, const int64_t* qv, const double* V, const double* Ds,
-                                    int64_t ns, int Q, int aQ, int bQ, int boQ, const int* lc_row, int ncols,
-                                    int c0, int lr, int lk) {
-  const bool lv = lr < bQ;
-  const int row0 = lv ? lr * LDS_PITCH : 0;
-  bool cval[H_CPW];
-#pragma unroll
-  for (int cc = 0; cc < H_CPW; ++cc) cval[cc] = (c0 + cc < ncols) && lc_row[c0 + cc] >= 0;
+// The binary32 kernel stages the V_PQ and D_PQ blocks of the group in LDS
+// once per Q; the binary64 kernel (register bound) reads them per unit.
+template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == sizeof(float); };
+
+// One Q of a V-stage tile, both columns of this wavefront.  The staged T_Q
+// rows are read without masks: rows past s_Q (or of lanes past n_b(Q)) hold
+// finite values, and they meet zero V (nu >= n_a(Q)) or zero D (l >= n_b(Q))
+// operands.  A column missing from N[Q] is staged as zeros.
+template <int NS, int NL, int U, typename R>
+__device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R* sT, const R* sV, const R* sD,
+                                    const HUnits& un, const int* roff, int vr, int nU, const int* qp,
+                                    const int64_t* qv, const double* V, const double* Ds, int64_t ns, int Q,
+                                    int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
+                                    int lk) {
+  typedef typename Mf<R>::acc A4;
+  static_assert(H_CPW == 2, "two columns per wavefront");
   bool anyc = false;
 #pragma unroll
-  for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || cval[cc];
+  for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || ((c0 + cc < ncols) && lc_row[c0 + cc] >= 0);
   if (!anyc) return;
+  const R* t0 = sT + lr * LDS_PITCH + c0;
+  const int tstride = 4 * bQ * LDS_PITCH;
+  constexpr int NLR = sizeof(R) == sizeof(double) ? NL : 4;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (u < nU) {
-      const int p = qp[un.slot[u]];
-      if (p >= 0) {
-        const int P = un.P[u], aP = un.a[u], bP = un.b[u];
+      const int sl = un.slot[u];
+      if (qp[sl] >= 0) {
+        const int aP = un.a[u], bP = un.b[u];
         const int muB = un.mu0[u] + lr;
         const bool muv = muB < aP;
-        const double* Vp = V + qv[un.slot[u]];
-        double vb[NS];
+        R vb[NS];
+        R da[NLR];
+        if constexpr (HStage<R>::vd) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            const int nu = 4 * q + lk;
+            const bool ok = muv && nu < aQ;
+            const R x = sV[ok ? nu * vr + roff[sl] + muB : 0];
+            vb[q] = ok ? x : (R)0;
+          }
+#pragma unroll
+          for (int q = 0; q < NLR; ++q) {
+            const int l = Mf<R>::row(lk, q);
+            const bool ok = lr < bP && l < bQ;
+            const R x = sD[ok ? (sl * 16 + lr) * H_DPITCH + l : 0];
+            da[q] = ok ? x : (R)0;
+          }
+        } else {
+          // branch-free: invalid lanes read the block's first element and discard it
+          const int P = un.P[u];
+          const double* Vp = V + qv[sl];
+          const bool pq = P <= Q;
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            const int nu = 4 * q + lk;
+            const bool ok = muv && nu < aQ;
+            const double x = Vp[ok ? (pq ? muB * aQ + nu : nu * aP + muB) : 0];
+            vb[q] = ok ? (R)x : (R)0;
+          }
+          const double* DPQ = Ds + (size_t)un.bo[u] * ns + boQ;
+#pragma unroll
+          for (int q = 0; q < NLR; ++q) {
+            const int l = Mf<R>::row(lk, q);
+            const bool ok = lr < bP && l < bQ;
+            const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
+            da[q] = ok ? (R)x : (R)0;
+          }
+        }
+        // the A operands of both columns first (independent LDS reads), then the chains
+        R ta[NS], tb[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-          const int nu = 4 * q + lk;
-          vb[q] = (muv && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, muB, nu) : 0.0;
+          const R* row = t0 + (q * 4 + lk) * bQ * LDS_PITCH;
+          ta[q] = row[0];
+          tb[q] = row[1];
         }
-        double da[NL];
-        const double* DPQ = Ds + (size_t)un.bo[u] * ns + boQ;
+        A4 Fa = A4{0, 0, 0, 0}, Fb = A4{0, 0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < NL; ++q) {
-          const int l = 4 * q + lk;
-          da[q] = (lr < bP && l < bQ) ? DPQ[(size_t)lr * ns + l] : 0.0;
+        for (int q = 0; q < NS; ++q) {
+          Fa = Mf<R>::mma(ta[q], vb[q], Fa);
+          Fb = Mf<R>::mma(tb[q], vb[q], Fb);
         }
 #pragma unroll
-        for (int cc = 0; cc < H_CPW; ++cc) {
-          if (cval[cc]) {
-            d4 F = d4{0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-              const int nu = 4 * q + lk;
-              const bool ok = lv && nu < aQ;
-              const double t = sT[(ok ? nu * bQ * LDS_PITCH : 0) + row0 + c0 + cc];
-              F = mfma64(ok ? t : 0.0, vb[q], F);
-            }
-#pragma unroll
-            for (int q = 0; q < NL; ++q) Hc[u][cc] = mfma64(da[q], F[q], Hc[u][cc]);
-          }
+        for (int q = 0; q < NLR; ++q) {
+          Hc[u][0] = Mf<R>::mma(da[q], Fa[q], Hc[u][0]);
+          Hc[u][1] = Mf<R>::mma(da[q], Fb[q], Hc[u][1]);
         }
       }
     }
   }
+  (void)tstride;
 }
 
-template <int U>
-__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_H(const double* __restrict__ V, const double* __restrict__ D,
-                                                    DevPlan d, int n_tiles, int n_padded, double gscale,
-                                                    int g_only) {
-  extern __shared__ double sT[];
+// Task lists of one k_H launch: tiles and their Q- and X-lists.
+struct HLists {
+  const GTile* tiles;
+  const Slot4 *gq, *gx;
+  int v_base, d_base;     // element offsets of the staged V and D blocks in LDS
+};
+
+// mode: H_WRITE stores H' = (Q part + G part); H_ADD adds both parts to H';
+// H_G_ADD adds the G part only.
+enum { H_WRITE = 0, H_ADD = 1, H_G_ADD = 2 };
+
+template <int U, typename R>
+__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_H(
+    const double* __restrict__ V, const double* __restrict__ D, DevPlan d, HLists hl, int n_tiles,
+    int n_padded, double gscale, int mode) {
+  typedef typename Mf<R>::acc A4;
+  extern __shared__ double sraw[];
+  R* sT = reinterpret_cast<R*>(sraw);
   __shared__ HUnits un;
   __shared__ int qm_atom[HQ_CHUNK], qm_n[HQ_CHUNK], qm_a[HQ_CHUNK], qm_b[HQ_CHUNK], qm_bo[HQ_CHUNK];
   __shared__ int qm_lc[HQ_CHUNK][H_COLS], qm_p[HQ_CHUNK][GROUP_ATOMS];
   __shared__ int64_t qm_toff[HQ_CHUNK], qm_voff[HQ_CHUNK][GROUP_ATOMS];
   const int ti = xcd_task(n_padded);
   if (ti >= n_tiles) return;
-  const GTile tl = d.g_tiles[ti];
+  const GTile tl = hl.tiles[ti];
   const int g = tl.grp;
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
@@ -429,19 +512,40 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
   const int* gcol = d.grp_cols + tl.col_beg;
   const int ncols = tl.ncols;
   const int c0 = wv * H_CPW;
-  d4 Hc[U][H_CPW];
+  A4 Hc[U][H_CPW];
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int cc = 0; cc < H_CPW; ++cc) Hc[u][cc] = d4{0, 0, 0, 0};
+    for (int cc = 0; cc < H_CPW; ++cc) Hc[u][cc] = A4{0, 0, 0, 0};
   const int tc = threadIdx.x % H_COLS;
   const int tstep = blockDim.x / H_COLS;
-  for (int e0 = g_only ? tl.q_end : tl.q_beg; e0 < tl.q_end; e0 += HQ_CHUNK) {
+  // LDS: T_Q[:, tile columns] | V_PQ of the group's atoms, [nu][group aux row] | D_PQ blocks
+  R* sV = sT + hl.v_base;
+  R* sD = sV + hl.d_base;
+  __shared__ int roff[GROUP_ATOMS + 1], sP_[GROUP_ATOMS], sa_[GROUP_ATOMS], sb_[GROUP_ATOMS], sbo_[GROUP_ATOMS];
+  if (threadIdx.x == 0) {
+    const int a0 = d.grp_first[g];
+    const int nsl = d.grp_units[u0 + nU - 1].slot + 1;
+    roff[0] = 0;
+    for (int t = 0; t < GROUP_ATOMS; ++t) {
+      const int P = a0 + t;
+      const bool in = t < nsl;
+      sP_[t] = in ? P : -1;
+      sa_[t] = in ? d.na[P] : 0;
+      sb_[t] = in ? d.nb[P] : 0;
+      sbo_[t] = in ? d.bo[P] : 0;
+      roff[t + 1] = roff[t] + sa_[t];
+    }
+  }
+  for (int i = threadIdx.x; i < hl.v_base; i += blockDim.x) sT[i] = (R)0;   // rows read past s_Q stay finite
+  __syncthreads();
+  const int vr = roff[GROUP_ATOMS];
+  for (int e0 = mode == H_G_ADD ? tl.q_end : tl.q_beg; e0 < tl.q_end; e0 += HQ_CHUNK) {
     const int nchunk = min(HQ_CHUNK, tl.q_end - e0);
     __syncthreads();
     for (int t = threadIdx.x; t < nchunk * H_COLS; t += blockDim.x) {
       const int ei = t / H_COLS, c = t % H_COLS;
-      const Slot4 qe = d.gq[e0 + ei];
+      const Slot4 qe = hl.gq[e0 + ei];
       const int Q = qe.atom;
       qm_lc[ei][c] = (c < ncols) ? d.map1[d.map_off[Q] + gcol[c]] : -1;
       if (c == 0) {
@@ -464,13 +568,32 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
       const int lcq = qm_lc[ei][tc];
       const double* TQ = d.T + qm_toff[ei] + (lcq >= 0 ? lcq : 0);
       for (int r = threadIdx.x / H_COLS; r < sQ; r += tstep)
-        sT[r * LDS_PITCH + tc] = lcq >= 0 ? TQ[(size_t)r * nQ] : 0.0;
+        sT[r * LDS_PITCH + tc] = (R)(lcq >= 0 ? TQ[(size_t)r * nQ] : 0.0);
+      // V_PQ and D_PQ of every group atom paired with Q (coalesced reads of the
+      // canonical V block, transposed into [nu][row])
+#pragma unroll
+      for (int k = 0; k < GROUP_ATOMS; ++k) {
+        if (HStage<R>::vd && qm_p[ei][k] >= 0) {
+          const int P = sP_[k], aP = sa_[k], bP = sb_[k];
+          const double* Vp = V + qm_voff[ei][k];
+          const bool pq = P <= Q;
+          for (int i = threadIdx.x; i < aP * aQ; i += blockDim.x) {
+            const int mu = pq ? i / aQ : i % aP, nu = pq ? i % aQ : i / aP;
+            sV[nu * vr + roff[k] + mu] = (R)Vp[i];
+          }
+          const double* DPQ = Ds + (size_t)sbo_[k] * ns + qm_bo[ei];
+          for (int i = threadIdx.x; i < bP * bQ; i += blockDim.x) {
+            const int j = i / bQ, l = i % bQ;
+            sD[(k * 16 + j) * H_DPITCH + l] = (R)DPQ[(size_t)j * ns + l];
+          }
+        }
+      }
       __syncthreads();
       const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
       switch (h_class(nsQ, nlQ)) {
-        case 0: h_q<4, 2, U>(Hc, sT, un, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, aQ, bQ, qm_bo[ei], qm_lc[ei], ncols, c0, lr, lk); break;
-        case 1: h_q<10, 4, U>(Hc, sT, un, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, aQ, bQ, qm_bo[ei], qm_lc[ei], ncols, c0, lr, lk); break;
-        default: h_q<16, 4, U>(Hc, sT, un, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, aQ, bQ, qm_bo[ei], qm_lc[ei], ncols, c0, lr, lk); break;
+        case 0: h_q<4, 2, U, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
+        case 1: h_q<10, 4, U, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
+        default: h_q<16, 4, U, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
       }
       __syncthreads();
     }
@@ -478,7 +601,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
   __syncthreads();
   // G part (this wavefront's columns)
   for (int e = tl.x_beg; e < tl.x_end; ++e) {
-    const Slot4 xe = d.gx[e];
+    const Slot4 xe = hl.gx[e];
     const int X = xe.atom;
     const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
     const int pp[3] = {xe.p0, xe.p1, xe.p2};
@@ -500,12 +623,14 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
               const double* Vp = V + d.v_off[p];
               const int colx = lr < bP ? m2X[un.bo[u] + lr] : 0;
               const double* EX = EX0 + colx + (size_t)ic * mX;
+              const bool px = P <= X;
               for (int q = 0; q < (aX + 3) / 4; ++q) {
                 const int m2 = 4 * q + lk;
                 const bool mv = m2 < aX;
-                const double a = (mv && lr < bP) ? EX[(size_t)(m2 * bX) * mX] : 0.0;
-                const double b = (mv && muv) ? gscale * v_elem(Vp, P, X, aP, aX, muB, m2) : 0.0;
-                Hc[u][cc] = mfma64(a, b, Hc[u][cc]);
+                const bool oka = mv && lr < bP, okb = mv && muv;
+                const double a = EX[oka ? (size_t)(m2 * bX) * mX : 0];
+                const double b = Vp[okb ? (px ? muB * aX + m2 : m2 * aP + muB) : 0];
+                Hc[u][cc] = Mf<R>::mma(oka ? (R)a : (R)0, okb ? (R)(gscale * b) : (R)0, Hc[u][cc]);
               }
             }
           }
@@ -513,7 +638,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
       }
     }
   }
-  // store (accumulate in G-only mode)
+  // store, or add to H'
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (u < nU) {
@@ -528,10 +653,10 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
         if (col >= 0 && muB < aP) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int j = lk + 4 * v;
+            const int j = Mf<R>::row(lk, v);
             if (j < bP) {
               double* h = HP + (size_t)(muB * bP + j) * mP + col;
-              *h = g_only ? *h + Hc[u][cc][v] : Hc[u][cc][v];
+              *h = mode == H_WRITE ? (double)Hc[u][cc][v] : *h + (double)Hc[u][cc][v];
             }
           }
         }
@@ -552,16 +677,19 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
 constexpr int T2_COLS = 8;
 constexpr int T2_PITCH = T2_COLS + 1;
 
-template <int NT, int NS>
+template <int NT, int NS, typename R>
 __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double* __restrict__ K,
-                                            DevPlan d, int n_items, int n_padded, int item_base) {
-  extern __shared__ double sm[];
+                                            DevPlan d, const int* __restrict__ items, int n_items,
+                                            int n_padded, int item_base) {
+  typedef typename Mf<R>::acc A4;
+  extern __shared__ double sraw[];
+  R* sm = reinterpret_cast<R*>(sraw);
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
-  const int p = d.t2_items[item_base + w] >> 1;
-  const bool flip = d.t2_items[item_base + w] & 1;
+  const int p = items[item_base + w] >> 1;
+  const bool flip = items[item_base + w] & 1;
   const int P = flip ? d.pair_b[p] : d.pair_a[p], Q = flip ? d.pair_a[p] : d.pair_b[p];
   const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
   const int sP = aP * bP, sQ = aQ * bQ;
@@ -573,78 +701,79 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
   const int* m2P = d.map2 + d.map_off[P];
   const double* TQ = d.T + d.t_off[Q];
   const double* EP = d.E + d.e_off[P];
-  double* sT = sm;                                  // [sQ][T2_PITCH]
-  double* sE = sm + (size_t)sQ * T2_PITCH;          // [sP][T2_PITCH]
-  const int nt = (aP + 15) >> 4, nsr = (aQ + 3) >> 2;
-  double va[NT][NS];
+  R* sT = sm;                                  // [sQ][T2_PITCH]
+  R* sE = sm + (size_t)sQ * T2_PITCH;          // [sP][T2_PITCH]
+  R va[NT][NS];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       const int mu = 16 * t + lr, nu = 4 * q + lk;
-      va[t][q] = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
+      va[t][q] = (R)((mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0);
     }
   const bool kv = lr < bQ, iv = lr < bP;
   // staging role: column tc of the chunk, rows r0, r0 + 32, ...
   const int tc = threadIdx.x & (T2_COLS - 1);
-  d4 acc = d4{0, 0, 0, 0};
+  A4 acc = A4{0, 0, 0, 0};
   for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
     const int l = l0 + tc;
     const bool cvld = l < nQ;
     const int ce = cvld ? m2P[cg[l]] : 0;
     __syncthreads();
-    for (int r = threadIdx.x >> 3; r < sQ; r += 32) sT[r * T2_PITCH + tc] = cvld ? TQ[(size_t)r * nQ + l] : 0.0;
-    for (int r = threadIdx.x >> 3; r < sP; r += 32) sE[r * T2_PITCH + tc] = cvld ? EP[(size_t)r * mP + ce] : 0.0;
+    for (int r = threadIdx.x >> 3; r < sQ; r += 32) sT[r * T2_PITCH + tc] = (R)(cvld ? TQ[(size_t)r * nQ + l] : 0.0);
+    for (int r = threadIdx.x >> 3; r < sP; r += 32) sE[r * T2_PITCH + tc] = (R)(cvld ? EP[(size_t)r * mP + ce] : 0.0);
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < T2_COLS / 4; ++h) {
       const int c = wv * (T2_COLS / 4) + h;
       if (l0 + c < nQ) {
         // straight-line chains: NT aux tiles of P, NS nu steps of Q (compile time)
-        double b[NS];
+        R b[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           const int nu = 4 * q + lk;
           const bool ok = kv && nu < aQ;
-          const double t = sT[(ok ? (nu * bQ + lr) * T2_PITCH : 0) + c];
-          b[q] = ok ? t : 0.0;
+          const R t = sT[(ok ? (nu * bQ + lr) * T2_PITCH : 0) + c];
+          b[q] = ok ? t : (R)0;
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          d4 F = d4{0, 0, 0, 0};
+          A4 F = A4{0, 0, 0, 0};
 #pragma unroll
-          for (int q = 0; q < NS; ++q) F = mfma64(va[t][q], b[q], F);
+          for (int q = 0; q < NS; ++q) F = Mf<R>::mma(va[t][q], b[q], F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int mu = 16 * t + 4 * v + lk;
+            // element v of F holds aux row mu of P; the E operand uses the same mu as k
+            const int mu = 16 * t + Mf<R>::row(lk, v);
             const bool ok = iv && mu < aP;
-            const double x = sE[(ok ? (mu * bP + lr) * T2_PITCH : 0) + c];
-            acc = mfma64(ok ? x : 0.0, F[v], acc);
+            const R x = sE[(ok ? (mu * bP + lr) * T2_PITCH : 0) + c];
+            acc = Mf<R>::mma(ok ? x : (R)0, F[v], acc);
           }
         }
       }
     }
   }
-  // fixed-order reduction of the four wavefront partials
+  // fixed-order reduction of the four wavefront partials (binary64)
   __syncthreads();
-  double* red = sm;
-  for (int v = 0; v < 4; ++v) red[(wv * 4 + v) * 64 + L] = acc[v];
+  double* red = sraw;
+  for (int v = 0; v < 4; ++v) red[(wv * 4 + v) * 64 + L] = (double)acc[v];
   __syncthreads();
   if (wv == 0) {
+    double out[4];
     for (int v = 0; v < 4; ++v) {
       double x = red[v * 64 + L];
       x += red[(4 + v) * 64 + L];
       x += red[(8 + v) * 64 + L];
       x += red[(12 + v) * 64 + L];
-      acc[v] = x;
+      out[v] = x;
     }
     double* Ks = K + d.sys_d_off[s];
     const int bPo = d.bo[P], bQo = d.bo[Q];
     for (int v = 0; v < 4; ++v) {
-      const int i = lk + 4 * v, k = lr;
+      const int i = Mf<R>::row(lk, v), k = lr;
       if (i < bP && k < bQ) {
-        Ks[(size_t)(bPo + i) * ns + bQo + k] = acc[v];
-        if (P != Q) Ks[(size_t)(bQo + k) * ns + bPo + i] = acc[v];
+        Ks[(size_t)(bPo + i) * ns + bQo + k] = out[v];
+        if (P != Q) Ks[(size_t)(bQo + k) * ns + bPo + i] = out[v];
       }
     }
   }
@@ -1126,6 +1255,8 @@ static void release(exx_plan_s* pl) {
   pl->graph = nullptr;
   for (void* p : pl->allocs) hipFree(p);
   pl->allocs.clear();
+  for (void* p : pl->mixed_allocs) hipFree(p);
+  pl->mixed_allocs.clear();
   for (hipEvent_t e : pl->events) hipEventDestroy(e);
   pl->events.clear();
 }
@@ -1184,8 +1315,29 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
     pl->t2_nt = (amax + 15) / 16;
     int smax = 1;
     for (int a = 0; a < pl->hp.n_atoms; ++a) smax = std::max(smax, pl->hp.na[a] * pl->hp.nb[a]);
-    pl->h_lds = (size_t)smax * LDS_PITCH * sizeof(double);
+    // k_H: T_Q tile | V blocks [nu][aux rows of the group] | D blocks
+    int vr_max = 1;
+    const HostPlan& hq = pl->hp;
+    for (size_t g = 0; g + 1 < hq.grp_unit_ptr.size(); ++g) {
+      const int nsl = hq.grp_units[hq.grp_unit_ptr[g + 1] - 1].slot + 1;
+      int vr = 0;
+      for (int t = 0; t < nsl; ++t) vr += hq.na[hq.grp_first[g] + t];
+      vr_max = std::max(vr_max, vr);
+    }
+    // rows of the staged T_Q read by the chains: up to 4 NS * n_b(Q) + 16 (NS of Q's shape class)
+    int h_rows = smax;
+    for (int a = 0; a < pl->hp.n_atoms; ++a) {
+      const int nsq = (pl->hp.na[a] + 3) / 4, nlq = (pl->hp.nb[a] + 3) / 4;
+      const int NS = (nsq <= 4 && nlq <= 2) ? 4 : (nsq <= 10 ? 10 : 16);
+      h_rows = std::max(h_rows, 4 * NS * pl->hp.nb[a] + 16);
+    }
+    pl->h_vbase = h_rows * LDS_PITCH;
+    pl->h_dbase = amax * vr_max;
+    const size_t h_elems = (size_t)pl->h_vbase + pl->h_dbase + GROUP_ATOMS * 16 * H_DPITCH;
+    pl->h_lds = (size_t)pl->h_vbase * sizeof(double);   // the binary64 kernel stages T_Q only
     pl->t2_lds = std::max((size_t)2 * smax * T2_PITCH, (size_t)16 * 64) * sizeof(double);
+    pl->h_lds32 = h_elems * sizeof(float);
+    pl->t2_lds32 = std::max((size_t)2 * smax * T2_PITCH * sizeof(float), (size_t)16 * 64 * sizeof(double));
   }
   if (!pl->host_only) {
     int lds_max = 0;
@@ -1193,7 +1345,7 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
       delete pl;
       return fail(EXX_EDEVICE, "exx_plan_create: cannot query the LDS size");
     }
-    if (pl->t2_lds > (size_t)lds_max || pl->h_lds + 8192 > (size_t)lds_max) {
+    if (pl->t2_lds > (size_t)lds_max || pl->h_lds + 8192 > (size_t)lds_max) {   // static LDS of k_H < 8 KB
       delete pl;
       return fail(EXX_EUNSUPPORTED, "exx_plan_create: the largest n_aux * n_basis needs more LDS than a workgroup has");
     }
@@ -1224,7 +1376,7 @@ int exx_plan_info(exx_plan plan, exx_info* info) {
   info->v_size = hp.v_off.empty() ? 0 : hp.v_off.back();
   info->d_size = hp.d_size;
   info->n_basis_max = hp.n_basis_max;
-  info->workspace_bytes = plan->dev_bytes;
+  info->workspace_bytes = plan->dev_bytes + plan->mixed_bytes;
   info->flops_fp64 = hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
   return EXX_OK;
 }
@@ -1253,6 +1405,12 @@ int64_t exx_plan_flops(exx_plan plan, int stage) {
   const HostPlan& hp = plan->hp;
   if (stage < 0) return hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
   if (stage >= 10 && stage <= 14) return hp.issued[stage - 10];
+  if (stage >= 20 && stage <= 44 && stage % 10 <= 4) {
+    if (!plan->hp.mixed_ready) derive_mixed_lists(plan->hp);
+    if (stage < 30) return hp.flops32[stage - 20];
+    if (stage < 40) return hp.issued32[stage - 30];
+    return hp.issued64m[stage - 40];
+  }
   if (stage > 4) return -1;
   return hp.flops[stage];
 }
@@ -1319,50 +1477,101 @@ static void launch_repack_E(exx_plan plan, const double* C, const double* D, hip
   launch_rowD(plan, D, rowd_E(plan), (int)hp.e_items.size(), st);
 }
 
-static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int g_only,
-                     hipStream_t st) {
+extern "C++" {
+template <typename R>
+static void launch_H_lists(exx_plan plan, const double* V, const double* D, const HLists& hl, int n, double gscale,
+                           int mode, hipStream_t st) {
+  if (n <= 0) return;
   const HostPlan& hp = plan->hp;
-  const int nH = (int)hp.g_tiles.size(), nHp = (nH + 7) / 8 * 8;
-  const size_t lds = g_only ? 0 : plan->h_lds;
-  const dim3 grid(nHp), blk(64 * H_WAVES);
+  const int np_ = (n + 7) / 8 * 8;
+  const size_t lds = mode == H_G_ADD ? 0 : (sizeof(R) == sizeof(double) ? plan->h_lds : plan->h_lds32);
+  const dim3 grid(np_), blk(64 * H_WAVES);
   if (hp.h_waves <= 2)
-    hipLaunchKernelGGL(k_H<2>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
+    hipLaunchKernelGGL((k_H<2, R>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
   else if (hp.h_waves <= 5)
-    hipLaunchKernelGGL(k_H<5>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
+    hipLaunchKernelGGL((k_H<5, R>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
   else
-    hipLaunchKernelGGL(k_H<8>, grid, blk, lds, st, V, D, plan->d, nH, nHp, gscale, g_only);
+    hipLaunchKernelGGL((k_H<8, R>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+}
+}  // extern "C++"
+
+// V stage over the full lists in binary64
+static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int mode, hipStream_t st) {
+  const DevPlan& d = plan->d;
+  launch_H_lists<double>(plan, V, D, HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase},
+                         (int)plan->hp.g_tiles.size(), gscale, mode, st);
+}
+
+// V stage of the mixed build: near pairs stored in binary64, far pairs added in binary32
+static void stage_mark(exx_plan_s* pl, int i, hipStream_t st);
+static void launch_H_mixed(exx_plan plan, const double* V, const double* D, hipStream_t st) {
+  const DevPlan& d = plan->d;
+  const HostPlan& hp = plan->hp;
+  launch_H_lists<double>(plan, V, D, HLists{d.hm_tiles_near, d.hm_q_near, d.hm_x_near, plan->h_vbase, plan->h_dbase},
+                         (int)hp.hm_tiles_near.size(), 2.0, H_WRITE, st);
+  stage_mark(plan, 3, st);
+  launch_H_lists<float>(plan, V, D, HLists{d.hm_tiles_far, d.hm_q_far, d.hm_x_far, plan->h_vbase, plan->h_dbase},
+                        (int)hp.hm_tiles_far.size(), 2.0, H_ADD, st);
 }
 
 extern "C++" {
-template <int NT>
-static void launch_T2_nt(exx_plan plan, int nsc, const double* V, double* K, int beg, int n, hipStream_t st) {
+template <int NT, typename R>
+static void launch_T2_nt(exx_plan plan, int nsc, const double* V, double* K, const int* items, int beg, int n,
+                         hipStream_t st) {
   const int np_ = (n + 7) / 8 * 8;
   DevPlan& d = plan->d;
-  const size_t lds = plan->t2_lds;
+  const size_t lds = sizeof(R) == sizeof(double) ? plan->t2_lds : plan->t2_lds32;
   switch (nsc) {
-    case 4: hipLaunchKernelGGL((k_T2<NT, 4>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
-    case 8: hipLaunchKernelGGL((k_T2<NT, 8>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
-    case 10: hipLaunchKernelGGL((k_T2<NT, 10>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
-    case 12: hipLaunchKernelGGL((k_T2<NT, 12>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
-    default: hipLaunchKernelGGL((k_T2<NT, 16>), dim3(np_), dim3(256), lds, st, V, K, d, n, np_, beg); break;
+    case 4: hipLaunchKernelGGL((k_T2<NT, 4, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 8: hipLaunchKernelGGL((k_T2<NT, 8, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 10: hipLaunchKernelGGL((k_T2<NT, 10, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 12: hipLaunchKernelGGL((k_T2<NT, 12, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    default: hipLaunchKernelGGL((k_T2<NT, 16, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
   }
 }
 
+template <typename R>
+static void launch_T2_class(exx_plan plan, const T2Class& c, const double* V, double* K, const int* items,
+                            hipStream_t st) {
+  const int n = c.end - c.beg;
+  if (n <= 0) return;
+  switch (c.nt) {
+    case 1: launch_T2_nt<1, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 2: launch_T2_nt<2, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 3: launch_T2_nt<3, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    default: launch_T2_nt<4, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
+  }
+}
 }  // extern "C++"
 
-// one launch per shape class (aux tiles of P, nu steps of Q) of the pairs
-static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st) {
+// one launch per shape class (aux tiles of P, nu steps of Q) and precision
+// (mixed: the classes of one precision only)
+static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st, bool mixed = false, int prec = 0) {
   const HostPlan& hp = plan->hp;
-  for (const T2Class& c : hp.t2_classes) {
-    const int n = c.end - c.beg;
-    if (n <= 0) continue;
-    switch (c.nt) {
-      case 1: launch_T2_nt<1>(plan, c.ns, V, K, c.beg, n, st); break;
-      case 2: launch_T2_nt<2>(plan, c.ns, V, K, c.beg, n, st); break;
-      case 3: launch_T2_nt<3>(plan, c.ns, V, K, c.beg, n, st); break;
-      default: launch_T2_nt<4>(plan, c.ns, V, K, c.beg, n, st); break;
-    }
+  const DevPlan& d = plan->d;
+  for (const T2Class& c : mixed ? hp.t2m_classes : hp.t2_classes) {
+    if (mixed && c.prec != prec) continue;
+    if (c.prec) launch_T2_class<float>(plan, c, V, K, d.t2m_items, st);
+    else launch_T2_class<double>(plan, c, V, K, mixed ? d.t2m_items : d.t2_items, st);
   }
+}
+
+// device copies of the near / far lists for the current split distance
+static int prepare_mixed(exx_plan pl) {
+  if (pl->mixed_uploaded) return EXX_OK;
+  HostPlan& hp = pl->hp;
+  if (!hp.mixed_ready) derive_mixed_lists(hp);
+  for (void* p : pl->mixed_allocs) hipFree(p);
+  pl->mixed_allocs.clear();
+  pl->mixed_bytes = 0;
+  DevPlan& d = pl->d;
+  int rc = 0;
+#define UPM(field) if ((rc = upload(pl, d.field, hp.field, true)) != 0) return rc
+  UPM(hm_tiles_near); UPM(hm_tiles_far); UPM(hm_q_near); UPM(hm_x_near); UPM(hm_q_far); UPM(hm_x_far);
+  UPM(t2m_items);
+#undef UPM
+  pl->mixed_uploaded = true;
+  return EXX_OK;
 }
 
 static void launch_final(exx_plan plan, double* K, hipStream_t st) {
@@ -1390,7 +1599,13 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   if (!plan) return fail(EXX_EINVAL, "build_K: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "build_K: host-only plan");
   if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K: NULL array");
-  if (precision != EXX_PREC_FP64) return fail(EXX_EUNSUPPORTED, "build_K: precision not implemented");
+  if (precision != EXX_PREC_FP64 && precision != EXX_PREC_MIXED)
+    return fail(EXX_EINVAL, "build_K: unknown precision");
+  const bool mixed = precision == EXX_PREC_MIXED;
+  if (mixed) {
+    const int rcm = prepare_mixed(plan);
+    if (rcm != EXX_OK) return rcm;
+  }
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
   DevPlan& d = plan->d;
@@ -1398,32 +1613,45 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, hp.d_size);
   launch_repack_E(plan, C, D, st, true);
   stage_mark(plan, 2, st);
-  launch_H(plan, V, D, 2.0, 0, st);
-  stage_mark(plan, 3, st);
-  launch_T2(plan, V, K, st);
+  if (mixed) {
+    launch_H_mixed(plan, V, D, st);   // marks boundary 3 between its binary64 and binary32 parts
+  } else {
+    launch_H(plan, V, D, 2.0, H_WRITE, st);
+    stage_mark(plan, 3, st);
+  }
   stage_mark(plan, 4, st);
-  launch_final(plan, K, st);
+  launch_T2(plan, V, K, st, mixed, 0);
   stage_mark(plan, 5, st);
+  if (mixed) launch_T2(plan, V, K, st, true, 1);
+  stage_mark(plan, 6, st);
+  launch_final(plan, K, st);
+  stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   int rc = EXX_OK;
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
-  stage_mark(plan, 6, st);
+  stage_mark(plan, 8, st);
   return rc;
 }
 
-int exx_graph_build(exx_plan plan, const double* C, const double* V, const double* D, double* K, double* Ex,
-                    void* stream) {
+int exx_graph_build(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
+                    double* Ex, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "exx_graph_build: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "exx_graph_build: host-only plan");
   if (!stream) return fail(EXX_EINVAL, "exx_graph_build: capture needs a created (non-default) stream");
   if (!C || !V || !D || !K) return fail(EXX_EINVAL, "exx_graph_build: NULL array");
+  if (precision != EXX_PREC_FP64 && precision != EXX_PREC_MIXED)
+    return fail(EXX_EINVAL, "exx_graph_build: unknown precision");
+  if (precision == EXX_PREC_MIXED) {
+    const int rcm = prepare_mixed(plan);   // list uploads stay outside the capture
+    if (rcm != EXX_OK) return rcm;
+  }
   hipStream_t st = (hipStream_t)stream;
   if (plan->graph_exec) { hipGraphExecDestroy(plan->graph_exec); plan->graph_exec = nullptr; }
   if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
   const bool prof = plan->profiling;
   plan->profiling = false;
   HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  const int rc = build_K(plan, C, V, D, EXX_PREC_FP64, K, Ex, stream);
+  const int rc = build_K(plan, C, V, D, precision, K, Ex, stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(st, &g);
   plan->profiling = prof;
@@ -1441,6 +1669,21 @@ int exx_graph_launch(exx_plan plan, void* stream) {
   return EXX_OK;
 }
 
+int exx_plan_set_mixed_split(exx_plan plan, double r_split) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_set_mixed_split: NULL plan");
+  if (!(r_split >= 0.0) || r_split > 1e6) return fail(EXX_EINVAL, "exx_plan_set_mixed_split: r_split must be in [0, 1e6]");
+  if (plan->hp.mixed_ready && plan->hp.mixed_split == r_split) return EXX_OK;
+  if (plan->graph_exec) { hipGraphExecDestroy(plan->graph_exec); plan->graph_exec = nullptr; }
+  if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+  plan->hp.mixed_split = r_split;
+  plan->hp.mixed_ready = false;
+  plan->mixed_uploaded = false;
+  derive_mixed_lists(plan->hp);
+  if (plan->host_only) return EXX_OK;
+  HIP_TRY(hipDeviceSynchronize());   // lists of an earlier split may still be in use
+  return prepare_mixed(plan);
+}
+
 int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "exchange_energy: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "exchange_energy: host-only plan");
@@ -1454,7 +1697,9 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
   if (!plan) return fail(EXX_EINVAL, "exchange_backward: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "exchange_backward: host-only plan");
   if (!C || !V || !D) return fail(EXX_EINVAL, "exchange_backward: NULL input array");
-  if (precision != EXX_PREC_FP64) return fail(EXX_EUNSUPPORTED, "exchange_backward: precision not implemented");
+  if (precision == EXX_PREC_MIXED)
+    return fail(EXX_EUNSUPPORTED, "exchange_backward: only the binary64 backward is implemented");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "exchange_backward: unknown precision");
   if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, "exchange_backward: decay lengths must be positive");
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
@@ -1474,13 +1719,13 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
   if (dD) {
     // dE/dD = -1/2 K: the forward build into dD, then scaled
     hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, dD, hp.d_size);
-    launch_H(plan, V, D, 2.0, 0, st);
+    launch_H(plan, V, D, 2.0, H_WRITE, st);
     launch_T2(plan, V, dD, st);
     launch_final(plan, dD, st);
     hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, st, dD, hp.d_size, -0.5 * gE);
-    if (needC) launch_H(plan, V, D, -1.0, 1, st);   // G term taken once
+    if (needC) launch_H(plan, V, D, -1.0, H_G_ADD, st);   // G term taken once
   } else if (needC) {
-    launch_H(plan, V, D, 1.0, 0, st);
+    launch_H(plan, V, D, 1.0, H_WRITE, st);
   }
   if (needC) {
     launch_rowD(plan, D, rowd_GD(plan), (int)hp.gd_items.size(), st);

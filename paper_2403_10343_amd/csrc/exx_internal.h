@@ -33,7 +33,7 @@ constexpr int GROUP_WAVES = 8;       // wavefronts per H workgroup at most
 constexpr double GROUP_RADIUS = 2.5; // A, group atoms lie within this of the first
 struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)
 struct YTile { int P, m0, n0, pad; };          // 64 x 64 tile of Y_P = T_P^T H'_P
-struct T2Class { int nt, ns, beg, end; };      // pairs [beg, end) of t2_items with this shape
+struct T2Class { int nt, ns, beg, end, prec; }; // items [beg, end) with this shape (prec 1: binary32)
 
 struct HostPlan {
   // system description
@@ -83,6 +83,17 @@ struct HostPlan {
   // flop counts: [0] repack (0), [1] E, [2] H, [3] T2, [4] final
   int64_t flops[5] = {0, 0, 0, 0, 0};
   int64_t issued[5] = {0, 0, 0, 0, 0};
+  // mixed precision: pair terms (P, Q) with |R_P - R_Q| >= mixed_split run in
+  // binary32 in the V stage and T2; the near lists keep binary64
+  double mixed_split = 5.0;
+  bool mixed_ready = false;
+  std::vector<GTile> hm_tiles_near, hm_tiles_far;
+  std::vector<Slot4> hm_q_near, hm_x_near, hm_q_far, hm_x_far;
+  std::vector<int> t2m_items;                       // near classes first, then far
+  std::vector<T2Class> t2m_classes;
+  int64_t flops32[5] = {0, 0, 0, 0, 0};             // algorithmic flops run in binary32
+  int64_t issued32[5] = {0, 0, 0, 0, 0};            // issued binary32 MFMA flops
+  int64_t issued64m[5] = {0, 0, 0, 0, 0};           // issued binary64 MFMA flops, mixed build
 };
 
 // Validate a system and fill the description part of a HostPlan.
@@ -98,5 +109,9 @@ void host_neighbors(HostPlan& hp);
 // Everything derived from the neighbour lists: canonical pairs and their
 // storage offsets, N2, maps, workspace layout, all task lists, flop counts.
 int derive_lists(HostPlan& hp, std::string& err);
+
+// Near / far split of the V-stage and T2 lists at hp.mixed_split (after
+// derive_lists), with the binary32 flop counts.
+void derive_mixed_lists(HostPlan& hp);
 
 }  // namespace exx

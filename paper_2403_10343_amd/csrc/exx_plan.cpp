@@ -442,7 +442,7 @@ int derive_lists(HostPlan& hp, std::string& err) {
     for (int i = 0; i < (int)hp.t2_items.size(); ++i) {
       const int k = key(hp.t2_items[i]);
       if (hp.t2_classes.empty() || hp.t2_classes.back().nt * 64 + hp.t2_classes.back().ns != k)
-        hp.t2_classes.push_back(T2Class{k / 64, k % 64, i, i});
+        hp.t2_classes.push_back(T2Class{k / 64, k % 64, i, i, 0});
       hp.t2_classes.back().end = i + 1;
     }
   }
@@ -525,6 +525,133 @@ int derive_lists(HostPlan& hp, std::string& err) {
   }
   for (int i = 1; i < 5; ++i) hp.flops[0] += 0;
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: the V-stage Q- and X-lists and the T2 pairs are split by
+// atom-pair distance.  Pairs at or beyond mixed_split (their V block, C
+// blocks and D blocks all decay with distance) go to the binary32 kernels,
+// the rest stay binary64.  The V stage runs the near lists as the storing
+// launch (every tile, so every H' entry is written) and the far lists as an
+// accumulating launch (tiles with no far pair dropped).
+void derive_mixed_lists(HostPlan& hp) {
+  const int NA = hp.n_atoms;
+  const int64_t npairs = (int64_t)hp.pair_a.size();
+  const std::vector<int>& np = hp.nbr_ptr;
+  const std::vector<int>& nat = hp.nbr_atom;
+  const double s2 = hp.mixed_split * hp.mixed_split;
+  std::vector<char> far(npairs, 0);
+  for (int64_t p = 0; p < npairs; ++p) {
+    const double* pa = &hp.pos[3 * (size_t)hp.pair_a[p]];
+    const double* pb = &hp.pos[3 * (size_t)hp.pair_b[p]];
+    volatile double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
+    volatile double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    volatile double r2 = (xx + yy);
+    r2 = r2 + zz;
+    far[p] = (hp.mixed_split <= 0.0) || (r2 >= s2);
+  }
+  for (int i = 0; i < 5; ++i) hp.flops32[i] = hp.issued32[i] = hp.issued64m[i] = 0;
+  // algorithmic binary32 flops of the V stage (ordered pairs) and T2
+  for (int a = 0; a < NA; ++a) {
+    const int aP = hp.na[a], bP = hp.nb[a];
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      const int q = nat[k];
+      if (!far[hp.nbr_pair[k]]) continue;
+      hp.flops32[2] += 2LL * aP * hp.na[q] * hp.nb[q] * hp.n_loc[q] + 2LL * aP * bP * hp.nb[q] * hp.n_loc[q] +
+                       2LL * aP * hp.na[q] * bP * hp.nb[q];
+    }
+  }
+  // atom of a basis column of a system
+  auto col_atom = [&](int s, int col) {
+    const int lo = hp.sys_atom_off[s], hi = hp.sys_atom_off[s + 1];
+    int l = lo, h = hi - 1;
+    while (l < h) {
+      const int m = (l + h + 1) / 2;
+      if (hp.bo[m] <= col) l = m; else h = m - 1;
+    }
+    return l;
+  };
+  hp.hm_tiles_near.clear();
+  hp.hm_tiles_far.clear();
+  hp.hm_q_near.clear();
+  hp.hm_x_near.clear();
+  hp.hm_q_far.clear();
+  hp.hm_x_far.clear();
+  std::vector<int> catom;
+  for (const GTile& t : hp.g_tiles) {
+    const int a = hp.grp_first[t.grp];
+    const int s = hp.atom_sys[a];
+    catom.resize(t.ncols);
+    for (int c = 0; c < t.ncols; ++c) catom[c] = col_atom(s, hp.grp_cols[t.col_beg + c]);
+    GTile tn = t, tf = t;
+    tn.q_beg = (int)hp.hm_q_near.size();
+    tf.q_beg = (int)hp.hm_q_far.size();
+    tn.x_beg = (int)hp.hm_x_near.size();
+    tf.x_beg = (int)hp.hm_x_far.size();
+    for (int pass = 0; pass < 2; ++pass) {
+      const std::vector<Slot4>& src = pass == 0 ? hp.gq : hp.gx;
+      const int e0 = pass == 0 ? t.q_beg : t.x_beg, e1 = pass == 0 ? t.q_end : t.x_end;
+      for (int e = e0; e < e1; ++e) {
+        const Slot4& x = src[e];
+        const int q = x.atom;
+        int cnt = 0;   // tile columns this entry touches: in N[Q] (Q part) or on X (G part)
+        for (int c = 0; c < t.ncols; ++c)
+          cnt += pass == 0 ? std::binary_search(nat.begin() + np[q], nat.begin() + np[q + 1], catom[c])
+                           : (catom[c] == q);
+        // MFMAs per column and aux tile: F chain + D chain (the binary32 kernel
+        // always runs all four D steps) or the G chain
+        const int per = pass == 0 ? ((hp.na[q] + 3) / 4) + ((hp.nb[q] + 3) / 4) : (hp.na[q] + 3) / 4;
+        const int per32 = pass == 0 ? ((hp.na[q] + 3) / 4) + 4 : per;
+        Slot4 n4{q, -1, -1, -1}, f4{q, -1, -1, -1};
+        const int* sl = &x.p0;
+        int* sn = &n4.p0;
+        int* sf = &f4.p0;
+        bool anyn = false, anyf = false;
+        for (int k = 0; k < GROUP_ATOMS; ++k) {
+          if (sl[k] < 0) continue;
+          const int64_t fl = 2048LL * ((hp.na[a + k] + 15) / 16) * cnt;
+          if (far[sl[k]]) { sf[k] = sl[k]; anyf = true; hp.issued32[2] += fl * per32; }
+          else { sn[k] = sl[k]; anyn = true; hp.issued64m[2] += fl * per; }
+        }
+        if (anyn) (pass == 0 ? hp.hm_q_near : hp.hm_x_near).push_back(n4);
+        if (anyf) (pass == 0 ? hp.hm_q_far : hp.hm_x_far).push_back(f4);
+      }
+    }
+    tn.q_end = (int)hp.hm_q_near.size();
+    tf.q_end = (int)hp.hm_q_far.size();
+    tn.x_end = (int)hp.hm_x_near.size();
+    tf.x_end = (int)hp.hm_x_far.size();
+    hp.hm_tiles_near.push_back(tn);
+    if (tf.q_end > tf.q_beg || tf.x_end > tf.x_beg) hp.hm_tiles_far.push_back(tf);
+  }
+  // T2: the full list's order (shape classes) kept inside each precision
+  hp.t2m_items.clear();
+  hp.t2m_classes.clear();
+  for (int prec = 0; prec < 2; ++prec) {
+    for (const T2Class& c : hp.t2_classes) {
+      const int beg = (int)hp.t2m_items.size();
+      for (int i = c.beg; i < c.end; ++i) {
+        const int item = hp.t2_items[i];
+        const int p = item >> 1;
+        if (far[p] != (prec == 1)) continue;
+        hp.t2m_items.push_back(item);
+        const bool flip = item & 1;
+        const int x = flip ? hp.pair_b[p] : hp.pair_a[p], y = flip ? hp.pair_a[p] : hp.pair_b[p];
+        const int64_t iss = 2048LL * ((hp.na[x] + 15) / 16) * (((hp.na[y] + 3) / 4) + 4) * hp.n_loc[y];
+        if (prec == 1) {
+          hp.flops32[3] += 2LL * hp.na[x] * hp.na[y] * hp.nb[y] * hp.n_loc[y] +
+                           2LL * hp.na[x] * hp.nb[x] * hp.nb[y] * hp.n_loc[y];
+          hp.issued32[3] += iss;
+        } else {
+          hp.issued64m[3] += iss;
+        }
+      }
+      const int end = (int)hp.t2m_items.size();
+      if (end > beg) hp.t2m_classes.push_back(T2Class{c.nt, c.ns, beg, end, prec});
+    }
+  }
+  for (int i : {0, 1, 4}) hp.issued64m[i] = hp.issued[i];
+  hp.mixed_ready = true;
 }
 
 }  // namespace exx

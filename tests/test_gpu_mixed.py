@@ -1,0 +1,148 @@
+"""Distance-split mixed-precision path (pair terms beyond the split in FP32)
+against the FP64 path and the oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exx_oracle as O
+from tests.gpu_util import device_inputs, relmax, run_build, system_block
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BAR_K = 1e-5          # max |dK|, absolute
+BAR_E = 1e-6          # |dE_x| per atom
+
+
+@pytest.fixture(scope="module")
+def exx():
+    import paper_2403_10343_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def integer_inputs(inp, rho=0.3):
+    """The same blocks with values in {-1, 0, 1}: an entry keeps its sign when
+    a digit-derived hash of its value is below rho (equal values, so mirrored
+    on-site entries, get equal results), else it is zero.  Every partial sum
+    of either path is then a multiple of 1/4 bounded by the same sum over
+    absolute values, which the test checks stays below 2^21: FP32 and FP64
+    arithmetic are both exact."""
+    def q(x):
+        keep = np.modf(np.abs(x) * 1000.0)[0] < rho
+        return np.where(keep, np.sign(x), 0.0)
+    out = synth.Inputs(inp.system, inp.layout, q(inp.C), q(inp.V), q(inp.D))
+    absd = synth.Inputs(inp.system, inp.layout, np.abs(out.C), np.abs(out.V), np.abs(out.D))
+    assert np.abs(O.k_full_rows(absd)).max() < 2.0 ** 21
+    return out
+
+
+def test_split_beyond_cutoff_is_the_fp64_build(exx):
+    sysm = synth.water_cluster(8, seed=5)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    K64, E64 = run_build(plan, inp, torch, exx.PREC_FP64)
+    plan.set_mixed_split(1e6)
+    assert plan.flops(22) == 0 and plan.flops(23) == 0
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    assert np.array_equal(Km, K64) and np.array_equal(Em, E64)
+
+
+@pytest.mark.parametrize("tables", [None, ([16, 3], [64, 7]), ([7, 1], [23, 2]), ([12, 9], [33, 17])])
+def test_fp32_kernels_exact_on_integer_inputs(exx, tables):
+    """Split 0 (every pair term in FP32) on integer-valued inputs must give
+    exactly the FP64 result: checks the FP32 kernels' indexing and lane
+    layouts for every shape class, independent of rounding."""
+    base = synth.water_cluster(3, seed=8)
+    if tables is None:
+        sysm = base
+    else:
+        sysm = synth.System(base.species, base.pos, 6.0, seed=8,
+                            basis_table=np.array(tables[0]), aux_table=np.array(tables[1]))
+    print("integer inputs", tables, flush=True)
+    inp = integer_inputs(synth.make_inputs(sysm))
+    plan = exx.Plan.for_system(sysm)
+    K64, E64 = run_build(plan, inp, torch, exx.PREC_FP64)
+    assert np.array_equal(system_block(K64, inp.layout, 0), O.k_full_rows(inp))
+    plan.set_mixed_split(0.0)
+    assert plan.flops(22) == plan.flops(2) and plan.flops(23) == plan.flops(3)
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    assert np.array_equal(Km, K64)
+    assert Em[0] == E64[0]
+
+
+def test_mixed_within_bars_config1(exx):
+    """Config 1 (8 waters) at the default split against the 4-index oracle."""
+    inp = synth.make_inputs(synth.config(1))
+    plan = exx.Plan.for_system(inp.system)
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    K4, _, e_direct = O.k_4index(inp)
+    dK = np.abs(system_block(Km, inp.layout, 0) - K4).max()
+    dE = abs(Em[0] - e_direct) / inp.system.n_atoms
+    print(f"config 1 mixed: max|dK| {dK:.2e}  |dE|/atom {dE:.2e}", flush=True)
+    assert dK <= BAR_K and dE <= BAR_E
+
+
+def test_mixed_within_bars_batch(exx):
+    b = synth.cluster_batch(6, n_min=4, n_max=40)
+    inp = synth.make_inputs(b)
+    plan = exx.Plan.for_system(b)
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    for s in range(b.n_systems):
+        Ko = O.k_eigen(inp, s)
+        Eo = O.exchange_energy(Ko, O.Blocks(inp, s).D)
+        nat = int(b.sys_off[s + 1] - b.sys_off[s])
+        assert np.abs(system_block(Km, inp.layout, s) - Ko).max() <= BAR_K
+        assert abs(Em[s] - Eo) / nat <= BAR_E
+
+
+def test_mixed_768_atom_box(exx):
+    """The benchmark box: mixed against the FP64 path on all of K and E_x, and
+    against the oracle on sampled rows; split 0 (all pair terms FP32) is
+    reported and must stay close."""
+    inp = synth.make_inputs(synth.config(2))
+    plan = exx.Plan.for_system(inp.system)
+    K64, E64 = run_build(plan, inp, torch, exx.PREC_FP64)
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    n_at = inp.system.n_atoms
+    dK = np.abs(Km - K64).max()
+    dE = abs(Em[0] - E64[0]) / n_at
+    print(f"768 box mixed (default split): max|dK| {dK:.2e}  |dE|/atom {dE:.2e}  max|K| {np.abs(K64).max():.1f}", flush=True)
+    assert dK <= BAR_K and dE <= BAR_E
+    rows = np.array([1, 3000, 6143])
+    Kr = O.k_rows(inp, rows)
+    assert np.abs(system_block(Km, inp.layout, 0)[rows] - Kr).max() <= BAR_K
+    plan.set_mixed_split(0.0)
+    K0, E0 = run_build(plan, inp, torch, exx.PREC_MIXED)
+    d0 = np.abs(K0 - K64).max()
+    print(f"768 box all-FP32 pair terms: max|dK| {d0:.2e}  |dE|/atom {abs(E0[0] - E64[0]) / n_at:.2e}", flush=True)
+    assert d0 <= 1e-5 * np.abs(K64).max()
+
+
+def test_mixed_graph_replays_match_eager(exx):
+    b = synth.cluster_batch(4, n_min=6, n_max=20)
+    inp = synth.make_inputs(b)
+    plan = exx.Plan.for_system(b)
+    plan.set_mixed_split(3.0)
+    Ke, Ee = run_build(plan, inp, torch, exx.PREC_MIXED)
+    C, V, D = device_inputs(inp, torch)
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+    Ex = torch.empty(plan.n_systems, dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.Stream()
+    plan.graph_build(C, V, D, K, Ex, stream=s.cuda_stream, precision=exx.PREC_MIXED)
+    for _ in range(3):
+        K.fill_(7.0)
+        torch.cuda.synchronize()
+        plan.graph_launch(stream=s.cuda_stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(K.cpu().numpy(), Ke) and np.array_equal(Ex.cpu().numpy(), Ee)
+
+
+def test_mixed_backward_is_rejected(exx):
+    sysm = synth.water_cluster(2, seed=1)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    C, V, D = device_inputs(inp, torch)
+    with pytest.raises(exx.ExxError) as e:
+        plan.exchange_backward(C, V, D, 1.0, dD=torch.empty_like(D), precision=exx.PREC_MIXED)
+    assert e.value.code == -5

@@ -68,3 +68,27 @@ def test_errors_are_codes_not_aborts():
     rc = L.lib().build_K(None, None, None, None, 0, None, None, None)
     assert rc == L.EXX_EINVAL
     assert L.lib().exx_last_error()
+
+
+def test_mixed_split_flop_accounting():
+    """Host-only plan: the FP32 share of the V-stage and T2 flops is all of
+    them at split 0, none beyond the cutoff, and grows as the split shrinks."""
+    import paper_2403_10343_amd as exx
+    sysm = synth.ice_box(2, 2, 1, seed=0)
+    p = exx.Plan.for_system(sysm, host_only=True)
+    full = [p.flops(i) for i in range(5)]
+    prev = -1
+    for r in (7.0, 5.0, 4.0, 3.0, 1.0, 0.0):
+        p.set_mixed_split(r)
+        f32 = [p.flops(20 + i) for i in range(5)]
+        assert f32[0] == f32[1] == f32[4] == 0
+        assert 0 <= f32[2] <= full[2] and 0 <= f32[3] <= full[3]
+        assert f32[2] + f32[3] >= prev
+        prev = f32[2] + f32[3]
+        alg, issued = p.stage_flops(mixed=True)
+        assert sum(alg) == sum(full)
+    assert f32[2] == full[2] and f32[3] == full[3]
+    p.set_mixed_split(7.0)
+    assert p.flops(22) == 0 and p.flops(23) == 0
+    with pytest.raises(exx.ExxError):
+        p.set_mixed_split(-1.0)
