@@ -712,17 +712,49 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
       va[t][q] = (R)((mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0);
     }
   const bool kv = lr < bQ, iv = lr < bP;
-  // staging role: column tc of the chunk, rows r0, r0 + 32, ...
+  // staging role: column tc of the chunk, rows r0, r0 + 32, ...  The next
+  // chunk is fetched into registers while the current one is computed from
+  // LDS (a single workgroup fits per CU, so registers are plentiful).
   const int tc = threadIdx.x & (T2_COLS - 1);
-  A4 acc = A4{0, 0, 0, 0};
-  for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
+  const int r0 = threadIdx.x >> 3;
+  constexpr int RT = (NS * 4 * NB_MAX + 31) / 32;   // rows of T_Q per thread at most
+  constexpr int RE = (NT * 16 * NB_MAX + 31) / 32;  // rows of E_P per thread at most
+  R pt[RT], pe[RE];
+  auto fetch = [&](int l0) {
     const int l = l0 + tc;
-    const bool cvld = l < nQ;
-    const int ce = cvld ? m2P[cg[l]] : 0;
+    const bool cv = l < nQ;
+    const int ce = cv ? m2P[cg[l]] : 0;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int r = r0 + 32 * i;
+      const bool ok = cv && r < sQ;
+      const double x = TQ[ok ? (size_t)r * nQ + l : 0];
+      pt[i] = ok ? (R)x : (R)0;
+    }
+#pragma unroll
+    for (int i = 0; i < RE; ++i) {
+      const int r = r0 + 32 * i;
+      const bool ok = cv && r < sP;
+      const double x = EP[ok ? (size_t)r * mP + ce : 0];
+      pe[i] = ok ? (R)x : (R)0;
+    }
+  };
+  A4 acc = A4{0, 0, 0, 0};
+  fetch(0);
+  for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
     __syncthreads();
-    for (int r = threadIdx.x >> 3; r < sQ; r += 32) sT[r * T2_PITCH + tc] = (R)(cvld ? TQ[(size_t)r * nQ + l] : 0.0);
-    for (int r = threadIdx.x >> 3; r < sP; r += 32) sE[r * T2_PITCH + tc] = (R)(cvld ? EP[(size_t)r * mP + ce] : 0.0);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int r = r0 + 32 * i;
+      if (r < sQ) sT[r * T2_PITCH + tc] = pt[i];
+    }
+#pragma unroll
+    for (int i = 0; i < RE; ++i) {
+      const int r = r0 + 32 * i;
+      if (r < sP) sE[r * T2_PITCH + tc] = pe[i];
+    }
     __syncthreads();
+    if (l0 + T2_COLS < nQ) fetch(l0 + T2_COLS);
 #pragma unroll
     for (int h = 0; h < T2_COLS / 4; ++h) {
       const int c = wv * (T2_COLS / 4) + h;
