@@ -279,12 +279,18 @@ struct RowD {
   const Run* runs;
 };
 
+// Batched GEMM: 64 x 64 output tile per workgroup of four wavefronts (32 x 32
+// each), k in steps of 16 staged through double-buffered LDS.  The k index
+// runs over the basis functions of the input atoms listed for the tile's
+// column tile (runs of consecutive atoms: column lcol.. of A, row grow.. of D).
+constexpr int ET = 64, EK = 16, EPITCH = ET + 4;
+
 __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
                                               int n_padded) {
-  const int w = xcd_task(n_padded) * 4 + (threadIdx.x >> 6);
+  __shared__ double As[2][EK][EPITCH];
+  __shared__ double Bs[2][EK][EPITCH];
+  const int w = xcd_task(n_padded);
   if (w >= n_items) return;
-  const int L = threadIdx.x & 63;
-  const int lr = L & 15, lk = L >> 4;
   const EItem it = r.items[w];
   const int P = it.P;
   const int sP = d.na[P] * d.nb[P], lda = r.a_ld[P], ldo = r.o_ld[P];
@@ -292,47 +298,84 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   const int64_t ns = d.sys_n[s];
   const double* Ds = D + d.sys_d_off[s];
   const double* AP = r.A + r.a_off[P];
-  int gc[2];
-  for (int h = 0; h < 2; ++h) {
-    const int c = it.c0 + 16 * h + lr;
-    gc[h] = (c < ldo) ? r.ocolg[r.ocolg_off[P] + c] : -1;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  // staging roles: A (rows of A_P) k = t & 15, rows ma + 16 x; B (rows of D) k = t >> 4, columns nb0 + x
+  const int ka = t & 15, ma = t >> 4;
+  const int kb = t >> 4, nb0 = (t & 15) * 4;
+  int gcn[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int n = it.c0 + nb0 + x;
+    gcn[x] = n < ldo ? r.ocolg[r.ocolg_off[P] + n] : -1;
   }
-  const int row0 = it.r0 + lr, row1 = it.r0 + 16 + lr;
-  const bool rv0 = row0 < sP, rv1 = row1 < sP;
-  d4 acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
   const int klen = r.klen[it.ct];
-  int rr0 = r.run_ptr[it.ct], rstart = 0;
-  for (int kb = 0; kb < klen; kb += 4) {
-    while (kb >= rstart + r.runs[rr0].len) { rstart += r.runs[rr0].len; ++rr0; }
-    const int kk = kb + lk;
-    const bool kv = kk < klen;
-    int lc = 0, gr = 0;
-    if (kv) {
-      int q = rr0, off = kk - rstart;
-      const Run R0 = r.runs[rr0];
-      if (off >= R0.len) { off -= R0.len; q = rr0 + 1; }
-      const Run R = (q == rr0) ? R0 : r.runs[q];
-      lc = R.lcol + off;
-      gr = R.grow + off;
+  const Run* runs = r.runs + r.run_ptr[it.ct];
+  int ia = 0, sa = 0, ib = 0, sb = 0;   // run cursors (run index, its first k) of the two roles
+  double va[4], vb[4];
+  auto gload = [&](int k0) {
+    const int k1 = k0 + ka, k2 = k0 + kb;
+    const bool oka = k1 < klen, okb = k2 < klen;
+    if (oka) while (k1 >= sa + runs[ia].len) { sa += runs[ia].len; ++ia; }
+    if (okb) while (k2 >= sb + runs[ib].len) { sb += runs[ib].len; ++ib; }
+    const int lc = oka ? runs[ia].lcol + (k1 - sa) : 0;
+    const int gr = okb ? runs[ib].grow + (k2 - sb) : 0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int m = it.r0 + ma + 16 * x;
+      const bool ok = oka && m < sP;
+      const double y = AP[ok ? (size_t)m * lda + lc : 0];
+      va[x] = ok ? y : 0.0;
+      const bool okd = okb && gcn[x] >= 0;
+      const double z = Ds[okd ? (size_t)gr * ns + gcn[x] : 0];
+      vb[x] = okd ? z : 0.0;
     }
-    const double a0 = (kv && rv0) ? AP[(size_t)row0 * lda + lc] : 0.0;
-    const double a1 = (kv && rv1) ? AP[(size_t)row1 * lda + lc] : 0.0;
-    const double b0 = (kv && gc[0] >= 0) ? Ds[(size_t)gr * ns + gc[0]] : 0.0;
-    const double b1 = (kv && gc[1] >= 0) ? Ds[(size_t)gr * ns + gc[1]] : 0.0;
-    acc[0][0] = mfma64(a0, b0, acc[0][0]);
-    acc[0][1] = mfma64(a0, b1, acc[0][1]);
-    acc[1][0] = mfma64(a1, b0, acc[1][0]);
-    acc[1][1] = mfma64(a1, b1, acc[1][1]);
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      As[buf][ka][ma + 16 * x] = va[x];
+      Bs[buf][kb][nb0 + x] = vb[x];
+    }
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < klen; k0 += EK) {
+    const bool more = k0 + EK < klen;
+    if (more) gload(k0 + EK);
+#pragma unroll
+    for (int ks = 0; ks < EK; ks += 4) {
+      const double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
+      const double b0 = Bs[buf][ks + lk][wn + lr], b1 = Bs[buf][ks + lk][wn + 16 + lr];
+      acc[0][0] = mfma64(a0, b0, acc[0][0]);
+      acc[0][1] = mfma64(a0, b1, acc[0][1]);
+      acc[1][0] = mfma64(a1, b0, acc[1][0]);
+      acc[1][1] = mfma64(a1, b1, acc[1][1]);
+    }
+    if (more) {
+      sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
   double* OP = r.O + r.o_off[P];
+#pragma unroll
   for (int x = 0; x < 2; ++x)
+#pragma unroll
     for (int y = 0; y < 2; ++y) {
-      const int col = it.c0 + 16 * y + lr;
+      const int col = it.c0 + wn + 16 * y + lr;
       if (col >= ldo) continue;
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = it.r0 + 16 * x + lk + 4 * v;
+        const int row = it.r0 + wm + 16 * x + lk + 4 * v;
         if (row < sP) OP[(size_t)row * ldo + col] = acc[x][y][v];
       }
     }
@@ -1497,7 +1540,8 @@ static RowD rowd_GD(exx_plan plan) {
 }
 
 static void launch_rowD(exx_plan plan, const double* D, const RowD& r, int n, hipStream_t st) {
-  const int nwg = (n + 3) / 4, nwgp = (nwg + 7) / 8 * 8;
+  if (n <= 0) return;
+  const int nwgp = (n + 7) / 8 * 8;
   hipLaunchKernelGGL(k_rowD, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
 }
 

@@ -27,6 +27,7 @@ struct Unit { int P, mu0, slot, pad; };        // one wavefront of an H group: a
 struct GTile { int grp, col_beg, ncols, q_beg, q_end, x_beg, x_end, pad; };  // H group x 16 columns
 struct Slot4 { int atom, p0, p1, p2; };      // list entry: atom, pair id with group slots 0..2 (-1: none)
 
+constexpr int E_TILE = 64;           // output tile (rows and columns) of the E = M D GEMM
 constexpr int GROUP_ATOMS = 3;       // atoms per H group (slots)
 constexpr int H_COLS = 8;            // columns per V-stage tile
 constexpr int GROUP_WAVES = 8;       // wavefronts per H workgroup at most

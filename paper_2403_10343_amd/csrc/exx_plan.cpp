@@ -242,9 +242,9 @@ int derive_lists(HostPlan& hp, std::string& err) {
       const int* out_b = grad ? &nat[np[a]] : &hp.n2_atom[hp.n2_ptr[a]];
       const int n_out = grad ? np[a + 1] - np[a] : hp.n2_ptr[a + 1] - hp.n2_ptr[a];
       const int mOut = grad ? hp.n_loc[a] : hp.m_loc[a];
-      for (int c0 = 0; c0 < mOut; c0 += 32) {
+      for (int c0 = 0; c0 < mOut; c0 += E_TILE) {
         ++stampv;
-        const int c1 = std::min(mOut, c0 + 32);
+        const int c1 = std::min(mOut, c0 + E_TILE);
         int c = 0;
         for (int k = 0; k < n_out; ++k) {
           const int l = out_b[k];
@@ -276,9 +276,9 @@ int derive_lists(HostPlan& hp, std::string& err) {
         if (cur.len > 0) runs.push_back(cur);
         run_ptr.push_back((int)runs.size());
         klens.push_back(klen);
-        for (int r0 = 0; r0 < sP; r0 += 32) {
+        for (int r0 = 0; r0 < sP; r0 += E_TILE) {
           items.push_back(EItem{a, r0, c0, ct});
-          issued += 2LL * 32 * 32 * ceil_to(klen, 4);
+          issued += 2LL * E_TILE * E_TILE * ceil_to(klen, 16);
         }
       }
     }
