@@ -139,6 +139,7 @@ def main():
     ap.add_argument("--mixed-split", type=float, default=5.0,
                     help="pair distance (A) at and beyond which the mixed path runs pair terms in FP32")
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--backward-steps", type=int, default=3,
@@ -169,6 +170,9 @@ def main():
     stream = torch.cuda.current_stream()
     names = exx._lib.STAGE_NAMES
 
+    if not args.no_autotune:
+        plan.autotune(C, V, D, K, stream=stream.cuda_stream)
+    tuning = plan.tuning()
     dt64, st64 = time_builds(plan, C, V, D, K, Ex, exx.PREC_FP64, args.steps, args.warmup, stream)
     K64, E64 = K.clone(), float(Ex[0].item())
     rec64 = path_record(plan, dt64, st64, False, names, args.workload)
@@ -212,6 +216,7 @@ def main():
                    "mixed_split_A": args.mixed_split if use_mixed else None},
         "roofline": main_rec["roofline"],
         "algorithmic_gflop_per_build": total_flops / 1e9,
+        "tile_shapes": {k: {"chosen": v[0], "ms": v[1]} for k, v in tuning.items()},
         "fp64": rec64,
         "mixed": recm,
         "mixed_speedup_vs_fp64": (dt64 / recm["ms_per_build"] * 1e3) if recm else None,

@@ -66,6 +66,8 @@ def main():
         alg, _ = plan.stage_flops(prec == exx.PREC_MIXED)
         return dt, {names[i]: float(stage_ms[i]) for i in range(len(names))}, alg
 
+    plan.autotune(C, V, D, K, stream=s.cuda_stream)
+    tuning = plan.tuning()
     dt64, st64, alg64 = run(exx.PREC_FP64)
     K64, E64 = K.clone(), Ex.clone()
     plan.set_mixed_split(args.mixed_split)
@@ -87,6 +89,7 @@ def main():
                    "path": "mixed" if use_mixed else "fp64", "mixed_split_A": args.mixed_split,
                    "sizes_molecules": [int(x) // 3 for x in sizes]},
         "algorithmic_gflop_per_batch": flops / 1e9,
+        "tile_shapes": {k: {"chosen": v[0], "ms": v[1]} for k, v in tuning.items()},
         "fp64": {"K_per_s": b.n_systems / dt64, "ms_per_batch": 1e3 * dt64, "tflops": flops / dt64 / 1e12,
                  "frac_fp64_peak": flops / dt64 / 78.6e12, "eager_stage_ms": st64},
         "mixed": {"K_per_s": b.n_systems / dtm, "ms_per_batch": 1e3 * dtm, "tflops": flops / dtm / 1e12,

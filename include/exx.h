@@ -142,6 +142,25 @@ int exx_graph_build(exx_plan plan, const double* C, const double* V, const doubl
                     int precision, double* K, double* Ex, void* stream);
 int exx_graph_launch(exx_plan plan, void* stream);
 
+/* Autotuner.  Tile shapes of three stages exist as compiled variants:
+ *   choice[0]  E = M D GEMM: k-chunk per LDS stage, 0 -> 16, 1 -> 32;
+ *   choice[1]  T2 pair blocks: columns per staged chunk, 0 -> 4, 1 -> 8;
+ *   choice[2]  Y = T^T H' GEMM: k-chunk per LDS stage, 0 -> 16, 1 -> 32.
+ * exx_plan_autotune() runs one build_K (precision as given), then times
+ * every variant of each stage on these inputs (best of 3, HIP events on
+ * `stream`), keeps the fastest per stage for all later builds of the plan,
+ * and ends with a build_K of the chosen configuration into K (no E_x).  It
+ * blocks until done and must not be captured.  Every variant computes the
+ * same K up to rounding order.  Defaults before tuning: {0, 1, 0}.
+ * exx_plan_tuning() reports the choices (int32 [3]) and, if ms is not NULL
+ * and the plan was tuned, the measured milliseconds (float [3][2]);
+ * exx_plan_set_tuning() sets the choices directly (each 0 or 1, else
+ * EXX_EINVAL). */
+int exx_plan_autotune(exx_plan plan, const double* C, const double* V, const double* D,
+                      int precision, double* K, void* stream);
+int exx_plan_tuning(exx_plan plan, int32_t* choices, float* ms);
+int exx_plan_set_tuning(exx_plan plan, const int32_t* choices);
+
 /* Mixed precision (EXX_PREC_MIXED in build_K).  K is linear in V, and every
  * pair term of the V stage and of the T2 blocks belongs to one aux-atom pair
  * (P, Q) (Eq. temp_F, temp_G, temp_H and the F-E term of Eq.

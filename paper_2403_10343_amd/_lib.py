@@ -51,7 +51,8 @@ class _Info(ctypes.Structure):
 EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pairs",
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
-           "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split")
+           "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
+           "exx_plan_tuning", "exx_plan_set_tuning")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -75,6 +76,9 @@ def lib():
     L.exchange_backward.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
+    L.exx_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp]
+    L.exx_plan_tuning.argtypes = [vp, vp, vp]
+    L.exx_plan_set_tuning.argtypes = [vp, vp]
     L.exx_graph_launch.argtypes = [vp, vp]
     L.exx_plan_set_profiling.argtypes = [vp, ctypes.c_int]
     L.exx_plan_stage_times.argtypes = [vp, vp, vp]
@@ -188,6 +192,30 @@ class Plan:
         """Capture one build_K on `stream` (a created stream) into a HIP graph."""
         _check(lib().exx_graph_build(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
                                      _stream(stream)))
+
+    TUNING_NAMES = (("E k-chunk", (16, 32)), ("T2 columns", (4, 8)), ("Y k-chunk", (16, 32)))
+
+    def autotune(self, C, V, D, K, precision=PREC_FP64, stream=None):
+        """Time the compiled tile variants of the E, T2 and Y stages on these
+        inputs and keep the fastest (blocking); K holds a build afterwards."""
+        _check(lib().exx_plan_autotune(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K),
+                                       _stream(stream)))
+
+    def tuning(self):
+        """{stage: (chosen tile value, {tile value: ms})} (ms empty before tuning)."""
+        ch = np.zeros(3, np.int32)
+        ms = np.zeros(6, np.float32)
+        _check(lib().exx_plan_tuning(self._h, ch.ctypes.data, ms.ctypes.data))
+        out = {}
+        for i, (name, vals) in enumerate(self.TUNING_NAMES):
+            t = {vals[c]: float(ms[2 * i + c]) for c in range(2) if ms[2 * i + c] > 0}
+            out[name] = (vals[int(ch[i])], t)
+        return out
+
+    def set_tuning(self, choices):
+        """Set the three tile choices directly (each 0 or 1)."""
+        ch = np.ascontiguousarray(choices, dtype=np.int32)
+        _check(lib().exx_plan_set_tuning(self._h, ch.ctypes.data))
 
     def set_mixed_split(self, r_split):
         """Distance (A) at and beyond which pair terms run in binary32 (PREC_MIXED)."""

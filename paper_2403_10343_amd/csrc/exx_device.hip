@@ -120,8 +120,19 @@ struct DevPlan {
 constexpr int N_STAGE_EV = EXX_N_STAGES + 1;   // stage boundaries, start and end included
 constexpr int MAX_PROFILED = 512;
 
+// tunable tile choices (exx_plan_autotune): E GEMM k-chunk {16, 32}, T2 column
+// chunk {4, 8}, Y GEMM k-chunk {16, 32}
+enum { TUNE_E = 0, TUNE_T2 = 1, TUNE_Y = 2, N_TUNE = 3, N_CAND = 2 };
+
+static size_t t2_lds_bytes(int smax, size_t esize, int cols) {
+  return std::max((size_t)2 * smax * (cols + 1) * esize, (size_t)16 * 64 * sizeof(double));
+}
+
 struct exx_plan_s {
   HostPlan hp;
+  int tune[N_TUNE] = {0, 1, 0};     // defaults: E 16, T2 8 columns, Y 16
+  float tune_ms[N_TUNE][N_CAND] = {};
+  bool tuned = false;
   bool host_only = false;
   int device = -1;
   DevPlan d{};
@@ -136,6 +147,7 @@ struct exx_plan_s {
   size_t t2_lds = 0;                // dynamic LDS bytes of k_T2 (binary64)
   size_t h_lds32 = 0, t2_lds32 = 0; // the same for the binary32 kernels
   int h_vbase = 0, h_dbase = 0;     // element offsets of V and D in k_H's LDS
+  int h_smax_t2 = 1;                // largest n_aux * n_basis (T2 staging)
   std::vector<void*> mixed_allocs;  // device copies of the mixed-precision lists
   int64_t mixed_bytes = 0;
   bool mixed_uploaded = false;
@@ -283,8 +295,10 @@ struct RowD {
 // each), k in steps of 16 staged through double-buffered LDS.  The k index
 // runs over the basis functions of the input atoms listed for the tile's
 // column tile (runs of consecutive atoms: column lcol.. of A, row grow.. of D).
-constexpr int ET = 64, EK = 16, EPITCH = ET + 4;
+constexpr int ET = 64, EPITCH = ET + 4;
 
+// EK: k-chunk per LDS stage (a tuning choice: 16 or 32)
+template <int EK>
 __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
                                               int n_padded) {
   __shared__ double As[2][EK][EPITCH];
@@ -301,8 +315,10 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   const int t = threadIdx.x;
   const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
   const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
-  // staging roles: A (rows of A_P) k = t & 15, rows ma + 16 x; B (rows of D) k = t >> 4, columns nb0 + x
-  const int ka = t & 15, ma = t >> 4;
+  // staging roles: A (rows of A_P) k = t % EK, rows ma + MS x; B (rows of D) k = t / (256 / EK)... per pass of
+  // 16 k rows: k = pass * 16 + (t >> 4), columns nb0 + x
+  constexpr int MS = 256 / EK, NA_ = ET / MS, NP = EK / 16;
+  const int ka = t % EK, ma = t / EK;
   const int kb = t >> 4, nb0 = (t & 15) * 4;
   int gcn[4];
 #pragma unroll
@@ -312,32 +328,44 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   }
   const int klen = r.klen[it.ct];
   const Run* runs = r.runs + r.run_ptr[it.ct];
-  int ia = 0, sa = 0, ib = 0, sb = 0;   // run cursors (run index, its first k) of the two roles
-  double va[4], vb[4];
-  auto gload = [&](int k0) {
-    const int k1 = k0 + ka, k2 = k0 + kb;
-    const bool oka = k1 < klen, okb = k2 < klen;
-    if (oka) while (k1 >= sa + runs[ia].len) { sa += runs[ia].len; ++ia; }
-    if (okb) while (k2 >= sb + runs[ib].len) { sb += runs[ib].len; ++ib; }
-    const int lc = oka ? runs[ia].lcol + (k1 - sa) : 0;
-    const int gr = okb ? runs[ib].grow + (k2 - sb) : 0;
+  int ia = 0, sa = 0;                   // run cursor (run index, its first k) of the A role
+  int ib[NP], sb[NP];                    // and of each pass of the B role
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int m = it.r0 + ma + 16 * x;
+  for (int pz = 0; pz < NP; ++pz) ib[pz] = sb[pz] = 0;
+  double va[NA_], vb[NP][4];
+  auto gload = [&](int k0) {
+    const int k1 = k0 + ka;
+    const bool oka = k1 < klen;
+    if (oka) while (k1 >= sa + runs[ia].len) { sa += runs[ia].len; ++ia; }
+    const int lc = oka ? runs[ia].lcol + (k1 - sa) : 0;
+#pragma unroll
+    for (int x = 0; x < NA_; ++x) {
+      const int m = it.r0 + ma + MS * x;
       const bool ok = oka && m < sP;
       const double y = AP[ok ? (size_t)m * lda + lc : 0];
       va[x] = ok ? y : 0.0;
-      const bool okd = okb && gcn[x] >= 0;
-      const double z = Ds[okd ? (size_t)gr * ns + gcn[x] : 0];
-      vb[x] = okd ? z : 0.0;
+    }
+#pragma unroll
+    for (int pz = 0; pz < NP; ++pz) {
+      const int k2 = k0 + 16 * pz + kb;
+      const bool okb = k2 < klen;
+      if (okb) while (k2 >= sb[pz] + runs[ib[pz]].len) { sb[pz] += runs[ib[pz]].len; ++ib[pz]; }
+      const int gr = okb ? runs[ib[pz]].grow + (k2 - sb[pz]) : 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const bool okd = okb && gcn[x] >= 0;
+        const double z = Ds[okd ? (size_t)gr * ns + gcn[x] : 0];
+        vb[pz][x] = okd ? z : 0.0;
+      }
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      As[buf][ka][ma + 16 * x] = va[x];
-      Bs[buf][kb][nb0 + x] = vb[x];
-    }
+    for (int x = 0; x < NA_; ++x) As[buf][ka][ma + MS * x] = va[x];
+#pragma unroll
+    for (int pz = 0; pz < NP; ++pz)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) Bs[buf][16 * pz + kb][nb0 + x] = vb[pz][x];
   };
   d4 acc[2][2];
 #pragma unroll
@@ -717,10 +745,11 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
 // columns.  Per column, the stage-one accumulator element v is directly the
 // stage-two B operand.  The four partial sums are added in a fixed order.
 
-constexpr int T2_COLS = 8;
+constexpr int T2_COLS = 8;               // column chunk of the backward pair kernel
 constexpr int T2_PITCH = T2_COLS + 1;
 
-template <int NT, int NS, typename R>
+// COLS: columns per staged chunk (a tuning choice: 4 or 8)
+template <int NT, int NS, typename R, int COLS>
 __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double* __restrict__ K,
                                             DevPlan d, const int* __restrict__ items, int n_items,
                                             int n_padded, int item_base) {
@@ -744,8 +773,9 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
   const int* m2P = d.map2 + d.map_off[P];
   const double* TQ = d.T + d.t_off[Q];
   const double* EP = d.E + d.e_off[P];
-  R* sT = sm;                                  // [sQ][T2_PITCH]
-  R* sE = sm + (size_t)sQ * T2_PITCH;          // [sP][T2_PITCH]
+  constexpr int PITCH = COLS + 1, RSTEP = 256 / COLS;
+  R* sT = sm;                                  // [sQ][PITCH]
+  R* sE = sm + (size_t)sQ * PITCH;             // [sP][PITCH]
   R va[NT][NS];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -758,10 +788,10 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
   // staging role: column tc of the chunk, rows r0, r0 + 32, ...  The next
   // chunk is fetched into registers while the current one is computed from
   // LDS (a single workgroup fits per CU, so registers are plentiful).
-  const int tc = threadIdx.x & (T2_COLS - 1);
-  const int r0 = threadIdx.x >> 3;
-  constexpr int RT = (NS * 4 * NB_MAX + 31) / 32;   // rows of T_Q per thread at most
-  constexpr int RE = (NT * 16 * NB_MAX + 31) / 32;  // rows of E_P per thread at most
+  const int tc = threadIdx.x & (COLS - 1);
+  const int r0 = threadIdx.x / COLS;
+  constexpr int RT = (NS * 4 * NB_MAX + RSTEP - 1) / RSTEP;   // rows of T_Q per thread at most
+  constexpr int RE = (NT * 16 * NB_MAX + RSTEP - 1) / RSTEP;  // rows of E_P per thread at most
   R pt[RT], pe[RE];
   auto fetch = [&](int l0) {
     const int l = l0 + tc;
@@ -769,14 +799,14 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
     const int ce = cv ? m2P[cg[l]] : 0;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-      const int r = r0 + 32 * i;
+      const int r = r0 + RSTEP * i;
       const bool ok = cv && r < sQ;
       const double x = TQ[ok ? (size_t)r * nQ + l : 0];
       pt[i] = ok ? (R)x : (R)0;
     }
 #pragma unroll
     for (int i = 0; i < RE; ++i) {
-      const int r = r0 + 32 * i;
+      const int r = r0 + RSTEP * i;
       const bool ok = cv && r < sP;
       const double x = EP[ok ? (size_t)r * mP + ce : 0];
       pe[i] = ok ? (R)x : (R)0;
@@ -784,23 +814,23 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
   };
   A4 acc = A4{0, 0, 0, 0};
   fetch(0);
-  for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
+  for (int l0 = 0; l0 < nQ; l0 += COLS) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-      const int r = r0 + 32 * i;
-      if (r < sQ) sT[r * T2_PITCH + tc] = pt[i];
+      const int r = r0 + RSTEP * i;
+      if (r < sQ) sT[r * PITCH + tc] = pt[i];
     }
 #pragma unroll
     for (int i = 0; i < RE; ++i) {
-      const int r = r0 + 32 * i;
-      if (r < sP) sE[r * T2_PITCH + tc] = pe[i];
+      const int r = r0 + RSTEP * i;
+      if (r < sP) sE[r * PITCH + tc] = pe[i];
     }
     __syncthreads();
-    if (l0 + T2_COLS < nQ) fetch(l0 + T2_COLS);
+    if (l0 + COLS < nQ) fetch(l0 + COLS);
 #pragma unroll
-    for (int h = 0; h < T2_COLS / 4; ++h) {
-      const int c = wv * (T2_COLS / 4) + h;
+    for (int h = 0; h < COLS / 4; ++h) {
+      const int c = wv * (COLS / 4) + h;
       if (l0 + c < nQ) {
         // straight-line chains: NT aux tiles of P, NS nu steps of Q (compile time)
         R b[NS];
@@ -808,7 +838,7 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
         for (int q = 0; q < NS; ++q) {
           const int nu = 4 * q + lk;
           const bool ok = kv && nu < aQ;
-          const R t = sT[(ok ? (nu * bQ + lr) * T2_PITCH : 0) + c];
+          const R t = sT[(ok ? (nu * bQ + lr) * PITCH : 0) + c];
           b[q] = ok ? t : (R)0;
         }
 #pragma unroll
@@ -821,7 +851,7 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
             // element v of F holds aux row mu of P; the E operand uses the same mu as k
             const int mu = 16 * t + Mf<R>::row(lk, v);
             const bool ok = iv && mu < aP;
-            const R x = sE[(ok ? (mu * bP + lr) * T2_PITCH : 0) + c];
+            const R x = sE[(ok ? (mu * bP + lr) * PITCH : 0) + c];
             acc = Mf<R>::mma(ok ? x : (R)0, F[v], acc);
           }
         }
@@ -860,8 +890,10 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
 // workgroup of four wavefronts (32 x 32 each), k-steps of 16 staged in
 // double-buffered LDS with coalesced row loads.
 
-constexpr int YT = 64, YK = 16, YPITCH = YT + 4;
+constexpr int YT = 64, YPITCH = YT + 4;
 
+// YK: k-chunk per LDS stage (a tuning choice: 16 or 32)
+template <int YK>
 __global__ __launch_bounds__(256) void k_Y(DevPlan d, int n_tiles, int n_padded) {
   __shared__ double As[2][YK][YPITCH];
   __shared__ double Bs[2][YK][YPITCH];
@@ -875,24 +907,33 @@ __global__ __launch_bounds__(256) void k_Y(DevPlan d, int n_tiles, int n_padded)
   const int t = threadIdx.x;
   const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
   const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
-  // global -> LDS staging role: row kr = t / 16 of the k-step, 4 columns
+  // global -> LDS staging role: rows kr + 16 pz of the k-chunk, 4 columns
+  constexpr int NP = YK / 16;
   const int kr = t >> 4, cc = (t & 15) * 4;
-  double ra[4], rb[4];
+  double ra[NP][4], rb[NP][4];
   auto gload = [&](int k0) {
-    const int k = k0 + kr;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int m = yt.m0 + cc + x, n = yt.n0 + cc + x;
-      ra[x] = (k < Kd && m < M) ? A[(size_t)k * M + m] : 0.0;
-      rb[x] = (k < Kd && n < N) ? B[(size_t)k * N + n] : 0.0;
+    for (int pz = 0; pz < NP; ++pz) {
+      const int k = k0 + 16 * pz + kr;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int m = yt.m0 + cc + x, n = yt.n0 + cc + x;
+        const bool oa = k < Kd && m < M, ob = k < Kd && n < N;
+        const double a = A[oa ? (size_t)k * M + m : 0];
+        const double b = B[ob ? (size_t)k * N + n : 0];
+        ra[pz][x] = oa ? a : 0.0;
+        rb[pz][x] = ob ? b : 0.0;
+      }
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      As[buf][kr][cc + x] = ra[x];
-      Bs[buf][kr][cc + x] = rb[x];
-    }
+    for (int pz = 0; pz < NP; ++pz)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        As[buf][16 * pz + kr][cc + x] = ra[pz][x];
+        Bs[buf][16 * pz + kr][cc + x] = rb[pz][x];
+      }
   };
   d4 acc[2][2];
 #pragma unroll
@@ -1411,6 +1452,7 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
     const size_t h_elems = (size_t)pl->h_vbase + pl->h_dbase + GROUP_ATOMS * 16 * H_DPITCH;
     pl->h_lds = (size_t)pl->h_vbase * sizeof(double);   // the binary64 kernel stages T_Q only
     pl->t2_lds = std::max((size_t)2 * smax * T2_PITCH, (size_t)16 * 64) * sizeof(double);
+    pl->h_smax_t2 = smax;
     pl->h_lds32 = h_elems * sizeof(float);
     pl->t2_lds32 = std::max((size_t)2 * smax * T2_PITCH * sizeof(float), (size_t)16 * 64 * sizeof(double));
   }
@@ -1542,7 +1584,8 @@ static RowD rowd_GD(exx_plan plan) {
 static void launch_rowD(exx_plan plan, const double* D, const RowD& r, int n, hipStream_t st) {
   if (n <= 0) return;
   const int nwgp = (n + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_rowD, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
+  if (plan->tune[TUNE_E] == 1) hipLaunchKernelGGL(k_rowD<32>, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
+  else hipLaunchKernelGGL(k_rowD<16>, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
 }
 
 // repack C into T_P, then E_P = T_P D (stage mark 1 in between)
@@ -1591,18 +1634,29 @@ static void launch_H_mixed(exx_plan plan, const double* V, const double* D, hipS
 }
 
 extern "C++" {
-template <int NT, typename R>
+template <int NT, typename R, int COLS>
 static void launch_T2_nt(exx_plan plan, int nsc, const double* V, double* K, const int* items, int beg, int n,
                          hipStream_t st) {
   const int np_ = (n + 7) / 8 * 8;
   DevPlan& d = plan->d;
-  const size_t lds = sizeof(R) == sizeof(double) ? plan->t2_lds : plan->t2_lds32;
+  const size_t lds = t2_lds_bytes(plan->h_smax_t2, sizeof(R), COLS);
   switch (nsc) {
-    case 4: hipLaunchKernelGGL((k_T2<NT, 4, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    case 8: hipLaunchKernelGGL((k_T2<NT, 8, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    case 10: hipLaunchKernelGGL((k_T2<NT, 10, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    case 12: hipLaunchKernelGGL((k_T2<NT, 12, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    default: hipLaunchKernelGGL((k_T2<NT, 16, R>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 4: hipLaunchKernelGGL((k_T2<NT, 4, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 8: hipLaunchKernelGGL((k_T2<NT, 8, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 10: hipLaunchKernelGGL((k_T2<NT, 10, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 12: hipLaunchKernelGGL((k_T2<NT, 12, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    default: hipLaunchKernelGGL((k_T2<NT, 16, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+  }
+}
+
+template <typename R, int COLS>
+static void launch_T2_cols(exx_plan plan, const T2Class& c, const double* V, double* K, const int* items, int n,
+                           hipStream_t st) {
+  switch (c.nt) {
+    case 1: launch_T2_nt<1, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 2: launch_T2_nt<2, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 3: launch_T2_nt<3, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    default: launch_T2_nt<4, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
   }
 }
 
@@ -1611,12 +1665,8 @@ static void launch_T2_class(exx_plan plan, const T2Class& c, const double* V, do
                             hipStream_t st) {
   const int n = c.end - c.beg;
   if (n <= 0) return;
-  switch (c.nt) {
-    case 1: launch_T2_nt<1, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    case 2: launch_T2_nt<2, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    case 3: launch_T2_nt<3, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    default: launch_T2_nt<4, R>(plan, c.ns, V, K, items, c.beg, n, st); break;
-  }
+  if (plan->tune[TUNE_T2] == 0) launch_T2_cols<R, 4>(plan, c, V, K, items, n, st);
+  else launch_T2_cols<R, 8>(plan, c, V, K, items, n, st);
 }
 }  // extern "C++"
 
@@ -1653,7 +1703,8 @@ static int prepare_mixed(exx_plan pl) {
 static void launch_final(exx_plan plan, double* K, hipStream_t st) {
   const HostPlan& hp = plan->hp;
   const int nY = (int)hp.y_tiles.size(), nYp = (nY + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_Y, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+  if (plan->tune[TUNE_Y] == 1) hipLaunchKernelGGL(k_Y<32>, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+  else hipLaunchKernelGGL(k_Y<16>, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
   const int nF = (int)hp.f_items.size(), nFp = (nF + 7) / 8 * 8;
   hipLaunchKernelGGL(k_symreduce, dim3(nFp), dim3(256), 0, st, K, plan->d, nF, nFp);
 }
@@ -1742,6 +1793,95 @@ int exx_graph_launch(exx_plan plan, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "exx_graph_launch: NULL plan");
   if (!plan->graph_exec) return fail(EXX_ESTATE, "exx_graph_launch: no graph built");
   HIP_TRY(hipGraphLaunch(plan->graph_exec, (hipStream_t)stream));
+  return EXX_OK;
+}
+
+// time `launch` (one stage of a build) `reps` times on `st`; returns the fastest, ms
+extern "C++" {
+template <typename F>
+static int time_stage(hipStream_t st, int reps, F launch, float& best) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  best = 1e30f;
+  int rc = EXX_OK;
+  for (int r = 0; r < reps && rc == EXX_OK; ++r) {
+    hipEventRecord(e0, st);
+    launch();
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(EXX_EDEVICE, "exx_plan_autotune: stage failed"); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
+}
+}  // extern "C++"
+
+int exx_plan_autotune(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
+                      void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_autotune: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_plan_autotune: host-only plan");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "exx_plan_autotune: NULL array");
+  if (precision != EXX_PREC_FP64 && precision != EXX_PREC_MIXED)
+    return fail(EXX_EINVAL, "exx_plan_autotune: unknown precision");
+  hipStream_t st = (hipStream_t)stream;
+  const bool mixed = precision == EXX_PREC_MIXED;
+  const bool prof = plan->profiling;
+  plan->profiling = false;
+  // one build fills the workspace the stage kernels read
+  int rc = build_K(plan, C, V, D, precision, K, nullptr, stream);
+  if (rc == EXX_OK) HIP_TRY(hipStreamSynchronize(st));
+  const HostPlan& hp = plan->hp;
+  constexpr int REPS = 3;
+  for (int stage = 0; stage < N_TUNE && rc == EXX_OK; ++stage) {
+    for (int c = 0; c < N_CAND && rc == EXX_OK; ++c) {
+      plan->tune[stage] = c;
+      float ms = 0.f;
+      if (stage == TUNE_E) {
+        rc = time_stage(st, REPS, [&] { launch_rowD(plan, D, rowd_E(plan), (int)hp.e_items.size(), st); }, ms);
+      } else if (stage == TUNE_T2) {
+        rc = time_stage(st, REPS, [&] {
+          launch_T2(plan, V, K, st, mixed, 0);
+          if (mixed) launch_T2(plan, V, K, st, true, 1);
+        }, ms);
+      } else {
+        const int nY = (int)hp.y_tiles.size(), nYp = (nY + 7) / 8 * 8;
+        rc = time_stage(st, REPS, [&] {
+          if (c == 1) hipLaunchKernelGGL(k_Y<32>, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+          else hipLaunchKernelGGL(k_Y<16>, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+        }, ms);
+      }
+      plan->tune_ms[stage][c] = ms;
+    }
+    if (rc == EXX_OK) plan->tune[stage] = plan->tune_ms[stage][1] < plan->tune_ms[stage][0] ? 1 : 0;
+  }
+  plan->profiling = prof;
+  if (rc != EXX_OK) return rc;
+  plan->tuned = true;
+  // leave a K of the chosen configuration behind
+  rc = build_K(plan, C, V, D, precision, K, nullptr, stream);
+  if (rc == EXX_OK) HIP_TRY(hipStreamSynchronize(st));
+  return rc;
+}
+
+int exx_plan_tuning(exx_plan plan, int32_t* choices, float* ms) {
+  if (!plan || !choices) return fail(EXX_EINVAL, "exx_plan_tuning: NULL argument");
+  for (int i = 0; i < N_TUNE; ++i) {
+    choices[i] = plan->tune[i];
+    if (ms)
+      for (int c = 0; c < N_CAND; ++c) ms[i * N_CAND + c] = plan->tuned ? plan->tune_ms[i][c] : 0.f;
+  }
+  return EXX_OK;
+}
+
+int exx_plan_set_tuning(exx_plan plan, const int32_t* choices) {
+  if (!plan || !choices) return fail(EXX_EINVAL, "exx_plan_set_tuning: NULL argument");
+  for (int i = 0; i < N_TUNE; ++i)
+    if (choices[i] < 0 || choices[i] >= N_CAND) return fail(EXX_EINVAL, "exx_plan_set_tuning: choice out of range");
+  for (int i = 0; i < N_TUNE; ++i) plan->tune[i] = choices[i];
   return EXX_OK;
 }
 

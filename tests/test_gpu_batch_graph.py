@@ -99,3 +99,35 @@ def test_full_batch_of_64_clusters_sampled(exx):
         Kc = system_block(K, inp.layout, c)
         assert np.array_equal(Kc, Kc.T)
     assert np.all(np.isfinite(Ex))
+
+
+def test_every_tile_variant_and_the_autotuner(exx):
+    """All 8 combinations of the tuned tile shapes give K equal to the oracle
+    (and to each other up to rounding); the autotuner picks one of them and
+    leaves a correct K behind."""
+    import itertools
+    b = synth.cluster_batch(4, n_min=3, n_max=16)
+    inp = synth.make_inputs(b)
+    plan = exx.Plan.for_system(b)
+    ref = [O.k_eigen(inp, s) for s in range(b.n_systems)]
+    base = None
+    for ch in itertools.product((0, 1), repeat=3):
+        plan.set_tuning(ch)
+        print("tile choices", ch, flush=True)
+        K, _ = run_build(plan, inp, torch)
+        for s in range(b.n_systems):
+            assert relmax(system_block(K, inp.layout, s), ref[s]) < 1e-10
+        if base is None:
+            base = K
+        assert relmax(K, base) < 1e-12
+    C, V, D = device_inputs(inp, torch)
+    Kt = torch.empty(plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+    plan.autotune(C, V, D, Kt)
+    torch.cuda.synchronize()
+    tun = plan.tuning()
+    assert set(tun) == {"E k-chunk", "T2 columns", "Y k-chunk"}
+    for name, (val, ms) in tun.items():
+        assert len(ms) == 2 and all(t > 0 for t in ms.values()) and val == min(ms, key=ms.get)
+    assert relmax(Kt.cpu().numpy(), base) < 1e-12
+    K2, _ = run_build(plan, inp, torch)
+    assert np.array_equal(K2, Kt.cpu().numpy())

@@ -92,3 +92,13 @@ def test_mixed_split_flop_accounting():
     assert p.flops(22) == 0 and p.flops(23) == 0
     with pytest.raises(exx.ExxError):
         p.set_mixed_split(-1.0)
+
+
+def test_tuning_choices_validated_on_host_plan():
+    import paper_2403_10343_amd as exx
+    p = exx.Plan.for_system(synth.water_cluster(2, seed=0), host_only=True)
+    assert {k: v[0] for k, v in p.tuning().items()} == {"E k-chunk": 16, "T2 columns": 8, "Y k-chunk": 16}
+    p.set_tuning([1, 0, 1])
+    assert {k: v[0] for k, v in p.tuning().items()} == {"E k-chunk": 32, "T2 columns": 4, "Y k-chunk": 32}
+    with pytest.raises(exx.ExxError):
+        p.set_tuning([0, 2, 0])
