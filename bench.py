@@ -28,15 +28,16 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # HBM bytes per dispatch, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# this script on the 768-atom box, scaled by what the counters read for a 1 GiB
-# device copy in the same runs (read x2.0, write x1.0).  They describe the
+# this script on the 768-atom box, scaled by what the counters read for kernels
+# of known traffic in the same runs (k_repack reads C once: read x1.94; k_zero
+# writes K once: write x1.00).  They describe the
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "9af96e36e2db7b97",
+    "sources": "984315bff1d49a7c",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 23.905e9 + 3.472e9, ("fp64", "T2"): 40.141e9 + 0.025e9,
-              ("fp64", "final"): 10.606e9 + 4.290e9, ("fp64", "E"): 2.536e9 + 2.632e9},
+    "bytes": {("fp64", "H"): 23.197e9 + 3.507e9, ("fp64", "T2"): 36.882e9 + 0.025e9,
+              ("fp64", "final"): 10.247e9 + 4.280e9, ("fp64", "E"): 2.757e9 + 2.476e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double>", "H32": "k_H<U, float>",
                    "T2": "k_T2<NT, NS, double>", "T2_32": "k_T2<NT, NS, float>",
