@@ -144,7 +144,8 @@ int exx_graph_launch(exx_plan plan, void* stream);
 
 /* Autotuner.  Tile shapes of three stages exist as compiled variants:
  *   choice[0]  E = M D GEMM: k-chunk per LDS stage, 0 -> 16, 1 -> 32;
- *   choice[1]  T2 pair blocks: columns per staged chunk, 0 -> 4, 1 -> 8;
+ *   choice[1]  T2 pair blocks: columns per staged chunk x wavefronts per
+ *              workgroup, 0 -> 4 x 4, 1 -> 8 x 4, 2 -> 8 x 8;
  *   choice[2]  Y = T^T H' GEMM: k-chunk per LDS stage, 0 -> 16, 1 -> 32.
  * exx_plan_autotune() runs one build_K (precision as given), then times
  * every variant of each stage on these inputs (best of 3, HIP events on
@@ -153,9 +154,9 @@ int exx_graph_launch(exx_plan plan, void* stream);
  * blocks until done and must not be captured.  Every variant computes the
  * same K up to rounding order.  Defaults before tuning: {0, 1, 0}.
  * exx_plan_tuning() reports the choices (int32 [3]) and, if ms is not NULL
- * and the plan was tuned, the measured milliseconds (float [3][2]);
- * exx_plan_set_tuning() sets the choices directly (each 0 or 1, else
- * EXX_EINVAL). */
+ * and the plan was tuned, the measured milliseconds (float [3][3], zero for
+ * candidates a stage does not have); exx_plan_set_tuning() sets the choices
+ * directly (in range for each stage, else EXX_EINVAL). */
 int exx_plan_autotune(exx_plan plan, const double* C, const double* V, const double* D,
                       int precision, double* K, void* stream);
 int exx_plan_tuning(exx_plan plan, int32_t* choices, float* ms);

@@ -193,7 +193,7 @@ class Plan:
         _check(lib().exx_graph_build(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
                                      _stream(stream)))
 
-    TUNING_NAMES = (("E k-chunk", (16, 32)), ("T2 columns", (4, 8)), ("Y k-chunk", (16, 32)))
+    TUNING_NAMES = (("E k-chunk", (16, 32)), ("T2 columns x waves", ("4x4", "8x4", "8x8")), ("Y k-chunk", (16, 32)))
 
     def autotune(self, C, V, D, K, precision=PREC_FP64, stream=None):
         """Time the compiled tile variants of the E, T2 and Y stages on these
@@ -204,16 +204,16 @@ class Plan:
     def tuning(self):
         """{stage: (chosen tile value, {tile value: ms})} (ms empty before tuning)."""
         ch = np.zeros(3, np.int32)
-        ms = np.zeros(6, np.float32)
+        ms = np.zeros(9, np.float32)
         _check(lib().exx_plan_tuning(self._h, ch.ctypes.data, ms.ctypes.data))
         out = {}
         for i, (name, vals) in enumerate(self.TUNING_NAMES):
-            t = {vals[c]: float(ms[2 * i + c]) for c in range(2) if ms[2 * i + c] > 0}
+            t = {vals[c]: float(ms[3 * i + c]) for c in range(len(vals)) if ms[3 * i + c] > 0}
             out[name] = (vals[int(ch[i])], t)
         return out
 
     def set_tuning(self, choices):
-        """Set the three tile choices directly (each 0 or 1)."""
+        """Set the three tile choices directly (indices into TUNING_NAMES' values)."""
         ch = np.ascontiguousarray(choices, dtype=np.int32)
         _check(lib().exx_plan_set_tuning(self._h, ch.ctypes.data))
 

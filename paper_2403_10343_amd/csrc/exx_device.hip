@@ -120,12 +120,13 @@ struct DevPlan {
 constexpr int N_STAGE_EV = EXX_N_STAGES + 1;   // stage boundaries, start and end included
 constexpr int MAX_PROFILED = 512;
 
-// tunable tile choices (exx_plan_autotune): E GEMM k-chunk {16, 32}, T2 column
-// chunk {4, 8}, Y GEMM k-chunk {16, 32}
-enum { TUNE_E = 0, TUNE_T2 = 1, TUNE_Y = 2, N_TUNE = 3, N_CAND = 2 };
+// tunable tile choices (exx_plan_autotune): E GEMM k-chunk {16, 32}; T2 column
+// chunk x wavefronts {4 x 4, 8 x 4, 8 x 8}; Y GEMM k-chunk {16, 32}
+enum { TUNE_E = 0, TUNE_T2 = 1, TUNE_Y = 2, N_TUNE = 3, N_CAND = 3 };
+static const int kTuneCands[N_TUNE] = {2, 3, 2};
 
-static size_t t2_lds_bytes(int smax, size_t esize, int cols) {
-  return std::max((size_t)2 * smax * (cols + 1) * esize, (size_t)16 * 64 * sizeof(double));
+static size_t t2_lds_bytes(int smax, size_t esize, int cols, int waves) {
+  return std::max((size_t)2 * smax * (cols + 1) * esize, (size_t)waves * 4 * 64 * sizeof(double));
 }
 
 struct exx_plan_s {
@@ -749,8 +750,8 @@ constexpr int T2_COLS = 8;               // column chunk of the backward pair ke
 constexpr int T2_PITCH = T2_COLS + 1;
 
 // COLS: columns per staged chunk (a tuning choice: 4 or 8)
-template <int NT, int NS, typename R, int COLS>
-__global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double* __restrict__ K,
+template <int NT, int NS, typename R, int COLS, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V, double* __restrict__ K,
                                             DevPlan d, const int* __restrict__ items, int n_items,
                                             int n_padded, int item_base) {
   typedef typename Mf<R>::acc A4;
@@ -773,7 +774,7 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
   const int* m2P = d.map2 + d.map_off[P];
   const double* TQ = d.T + d.t_off[Q];
   const double* EP = d.E + d.e_off[P];
-  constexpr int PITCH = COLS + 1, RSTEP = 256 / COLS;
+  constexpr int PITCH = COLS + 1, RSTEP = 64 * WAVES / COLS, CPW = COLS / WAVES;
   R* sT = sm;                                  // [sQ][PITCH]
   R* sE = sm + (size_t)sQ * PITCH;             // [sP][PITCH]
   R va[NT][NS];
@@ -785,9 +786,8 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
       va[t][q] = (R)((mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0);
     }
   const bool kv = lr < bQ, iv = lr < bP;
-  // staging role: column tc of the chunk, rows r0, r0 + 32, ...  The next
-  // chunk is fetched into registers while the current one is computed from
-  // LDS (a single workgroup fits per CU, so registers are plentiful).
+  // staging role: column tc of the chunk, rows r0, r0 + RSTEP, ...  The next
+  // chunk is fetched into registers while the current one is computed from LDS.
   const int tc = threadIdx.x & (COLS - 1);
   const int r0 = threadIdx.x / COLS;
   constexpr int RT = (NS * 4 * NB_MAX + RSTEP - 1) / RSTEP;   // rows of T_Q per thread at most
@@ -829,8 +829,8 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
     __syncthreads();
     if (l0 + COLS < nQ) fetch(l0 + COLS);
 #pragma unroll
-    for (int h = 0; h < COLS / 4; ++h) {
-      const int c = wv * (COLS / 4) + h;
+    for (int h = 0; h < CPW; ++h) {
+      const int c = wv * CPW + h;
       if (l0 + c < nQ) {
         // straight-line chains: NT aux tiles of P, NS nu steps of Q (compile time)
         R b[NS];
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
       }
     }
   }
-  // fixed-order reduction of the four wavefront partials (binary64)
+  // fixed-order reduction of the wavefront partials (binary64)
   __syncthreads();
   double* red = sraw;
   for (int v = 0; v < 4; ++v) red[(wv * 4 + v) * 64 + L] = (double)acc[v];
@@ -867,9 +867,7 @@ __global__ __launch_bounds__(256) void k_T2(const double* __restrict__ V, double
     double out[4];
     for (int v = 0; v < 4; ++v) {
       double x = red[v * 64 + L];
-      x += red[(4 + v) * 64 + L];
-      x += red[(8 + v) * 64 + L];
-      x += red[(12 + v) * 64 + L];
+      for (int w2 = 1; w2 < WAVES; ++w2) x += red[(w2 * 4 + v) * 64 + L];
       out[v] = x;
     }
     double* Ks = K + d.sys_d_off[s];
@@ -1634,29 +1632,30 @@ static void launch_H_mixed(exx_plan plan, const double* V, const double* D, hipS
 }
 
 extern "C++" {
-template <int NT, typename R, int COLS>
+template <int NT, typename R, int COLS, int WAVES>
 static void launch_T2_nt(exx_plan plan, int nsc, const double* V, double* K, const int* items, int beg, int n,
                          hipStream_t st) {
   const int np_ = (n + 7) / 8 * 8;
   DevPlan& d = plan->d;
-  const size_t lds = t2_lds_bytes(plan->h_smax_t2, sizeof(R), COLS);
+  const size_t lds = t2_lds_bytes(plan->h_smax_t2, sizeof(R), COLS, WAVES);
+  const dim3 g(np_), b(64 * WAVES);
   switch (nsc) {
-    case 4: hipLaunchKernelGGL((k_T2<NT, 4, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    case 8: hipLaunchKernelGGL((k_T2<NT, 8, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    case 10: hipLaunchKernelGGL((k_T2<NT, 10, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    case 12: hipLaunchKernelGGL((k_T2<NT, 12, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
-    default: hipLaunchKernelGGL((k_T2<NT, 16, R, COLS>), dim3(np_), dim3(256), lds, st, V, K, d, items, n, np_, beg); break;
+    case 4: hipLaunchKernelGGL((k_T2<NT, 4, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
+    case 8: hipLaunchKernelGGL((k_T2<NT, 8, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
+    case 10: hipLaunchKernelGGL((k_T2<NT, 10, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
+    case 12: hipLaunchKernelGGL((k_T2<NT, 12, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
+    default: hipLaunchKernelGGL((k_T2<NT, 16, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
   }
 }
 
-template <typename R, int COLS>
+template <typename R, int COLS, int WAVES>
 static void launch_T2_cols(exx_plan plan, const T2Class& c, const double* V, double* K, const int* items, int n,
                            hipStream_t st) {
   switch (c.nt) {
-    case 1: launch_T2_nt<1, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    case 2: launch_T2_nt<2, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    case 3: launch_T2_nt<3, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    default: launch_T2_nt<4, R, COLS>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 1: launch_T2_nt<1, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 2: launch_T2_nt<2, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 3: launch_T2_nt<3, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    default: launch_T2_nt<4, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
   }
 }
 
@@ -1665,8 +1664,11 @@ static void launch_T2_class(exx_plan plan, const T2Class& c, const double* V, do
                             hipStream_t st) {
   const int n = c.end - c.beg;
   if (n <= 0) return;
-  if (plan->tune[TUNE_T2] == 0) launch_T2_cols<R, 4>(plan, c, V, K, items, n, st);
-  else launch_T2_cols<R, 8>(plan, c, V, K, items, n, st);
+  switch (plan->tune[TUNE_T2]) {
+    case 0: launch_T2_cols<R, 4, 4>(plan, c, V, K, items, n, st); break;
+    case 1: launch_T2_cols<R, 8, 4>(plan, c, V, K, items, n, st); break;
+    default: launch_T2_cols<R, 8, 8>(plan, c, V, K, items, n, st); break;
+  }
 }
 }  // extern "C++"
 
@@ -1837,7 +1839,7 @@ int exx_plan_autotune(exx_plan plan, const double* C, const double* V, const dou
   const HostPlan& hp = plan->hp;
   constexpr int REPS = 3;
   for (int stage = 0; stage < N_TUNE && rc == EXX_OK; ++stage) {
-    for (int c = 0; c < N_CAND && rc == EXX_OK; ++c) {
+    for (int c = 0; c < kTuneCands[stage] && rc == EXX_OK; ++c) {
       plan->tune[stage] = c;
       float ms = 0.f;
       if (stage == TUNE_E) {
@@ -1856,7 +1858,12 @@ int exx_plan_autotune(exx_plan plan, const double* C, const double* V, const dou
       }
       plan->tune_ms[stage][c] = ms;
     }
-    if (rc == EXX_OK) plan->tune[stage] = plan->tune_ms[stage][1] < plan->tune_ms[stage][0] ? 1 : 0;
+    if (rc == EXX_OK) {
+      int best = 0;
+      for (int c = 1; c < kTuneCands[stage]; ++c)
+        if (plan->tune_ms[stage][c] < plan->tune_ms[stage][best]) best = c;
+      plan->tune[stage] = best;
+    }
   }
   plan->profiling = prof;
   if (rc != EXX_OK) return rc;
@@ -1872,7 +1879,8 @@ int exx_plan_tuning(exx_plan plan, int32_t* choices, float* ms) {
   for (int i = 0; i < N_TUNE; ++i) {
     choices[i] = plan->tune[i];
     if (ms)
-      for (int c = 0; c < N_CAND; ++c) ms[i * N_CAND + c] = plan->tuned ? plan->tune_ms[i][c] : 0.f;
+      for (int c = 0; c < N_CAND; ++c)
+        ms[i * N_CAND + c] = (plan->tuned && c < kTuneCands[i]) ? plan->tune_ms[i][c] : 0.f;
   }
   return EXX_OK;
 }
@@ -1880,7 +1888,7 @@ int exx_plan_tuning(exx_plan plan, int32_t* choices, float* ms) {
 int exx_plan_set_tuning(exx_plan plan, const int32_t* choices) {
   if (!plan || !choices) return fail(EXX_EINVAL, "exx_plan_set_tuning: NULL argument");
   for (int i = 0; i < N_TUNE; ++i)
-    if (choices[i] < 0 || choices[i] >= N_CAND) return fail(EXX_EINVAL, "exx_plan_set_tuning: choice out of range");
+    if (choices[i] < 0 || choices[i] >= kTuneCands[i]) return fail(EXX_EINVAL, "exx_plan_set_tuning: choice out of range");
   for (int i = 0; i < N_TUNE; ++i) plan->tune[i] = choices[i];
   return EXX_OK;
 }

@@ -97,8 +97,12 @@ def test_mixed_split_flop_accounting():
 def test_tuning_choices_validated_on_host_plan():
     import paper_2403_10343_amd as exx
     p = exx.Plan.for_system(synth.water_cluster(2, seed=0), host_only=True)
-    assert {k: v[0] for k, v in p.tuning().items()} == {"E k-chunk": 16, "T2 columns": 8, "Y k-chunk": 16}
-    p.set_tuning([1, 0, 1])
-    assert {k: v[0] for k, v in p.tuning().items()} == {"E k-chunk": 32, "T2 columns": 4, "Y k-chunk": 32}
+    assert {k: v[0] for k, v in p.tuning().items()} == {"E k-chunk": 16, "T2 columns x waves": "8x4",
+                                                         "Y k-chunk": 16}
+    p.set_tuning([1, 2, 1])
+    assert {k: v[0] for k, v in p.tuning().items()} == {"E k-chunk": 32, "T2 columns x waves": "8x8",
+                                                         "Y k-chunk": 32}
     with pytest.raises(exx.ExxError):
-        p.set_tuning([0, 2, 0])
+        p.set_tuning([0, 3, 0])
+    with pytest.raises(exx.ExxError):
+        p.set_tuning([2, 0, 0])
