@@ -479,11 +479,14 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
         R vb[NS];
         R da[NLR];
         if constexpr (HStage<R>::vd) {
+          const bool pqs = un.P[u] <= Q;
 #pragma unroll
           for (int q = 0; q < NS; ++q) {
             const int nu = 4 * q + lk;
             const bool ok = muv && nu < aQ;
-            const R x = sV[ok ? nu * vr + roff[sl] + muB : 0];
+            // the canonical block as stored: [mu][nu] if P <= Q, else [nu][mu]
+            const int vi = pqs ? muB * aQ + nu : nu * aP + muB;
+            const R x = sV[ok ? roff[sl] * aQ + vi : 0];
             vb[q] = ok ? x : (R)0;
           }
 #pragma unroll
@@ -647,17 +650,16 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2)
       for (int k = 0; k < GROUP_ATOMS; ++k) {
         if (HStage<R>::vd && qm_p[ei][k] >= 0) {
           const int P = sP_[k], aP = sa_[k], bP = sb_[k];
+          // plain copies: the V block as stored, the D block row by row
           const double* Vp = V + qm_voff[ei][k];
-          const bool pq = P <= Q;
-          for (int i = threadIdx.x; i < aP * aQ; i += blockDim.x) {
-            const int mu = pq ? i / aQ : i % aP, nu = pq ? i % aQ : i / aP;
-            sV[nu * vr + roff[k] + mu] = (R)Vp[i];
-          }
+          R* dv = sV + roff[k] * aQ;
+          for (int i = threadIdx.x; i < aP * aQ; i += blockDim.x) dv[i] = (R)Vp[i];
           const double* DPQ = Ds + (size_t)sbo_[k] * ns + qm_bo[ei];
-          for (int i = threadIdx.x; i < bP * bQ; i += blockDim.x) {
-            const int j = i / bQ, l = i % bQ;
-            sD[(k * 16 + j) * H_DPITCH + l] = (R)DPQ[(size_t)j * ns + l];
+          for (int i = threadIdx.x; i < bP * 16; i += blockDim.x) {
+            const int j = i >> 4, l = i & 15;
+            if (l < bQ) sD[(k * 16 + j) * H_DPITCH + l] = (R)DPQ[(size_t)j * ns + l];
           }
+          (void)P;
         }
       }
       __syncthreads();
