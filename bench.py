@@ -227,22 +227,28 @@ def main():
     if args.backward_steps > 0:
         dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D)
         F = torch.empty(sysm.n_atoms * 3, dtype=torch.float64, device=dev)
-        plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F)
-        torch.cuda.synchronize()
-        tb0 = time.perf_counter()
-        for _ in range(args.backward_steps):
-            plan.build_K(C, V, D, K, Ex, precision=exx.PREC_FP64)
-            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - tb0) / args.backward_steps
-        Ff = F.view(-1, 3)
-        out["forward_backward"] = {
-            "workload": wname + " (FP64: E_x, dE/dC, dE/dV, dE/dD, forces)",
-            "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
-            "net_force_max": float(Ff.sum(0).abs().max().item()),
-            "euler_C": float((dC * C).sum().item() / (2 * E64)),
-            "euler_V": float((dV * V).sum().item() / E64),
-        }
+        fb = {}
+        for name, prec in (("fp64", exx.PREC_FP64), ("mixed", exx.PREC_MIXED)):
+            if prec == exx.PREC_MIXED and recm is None:
+                continue
+            plan.build_K(C, V, D, K, Ex, precision=prec)
+            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+            torch.cuda.synchronize()
+            tb0 = time.perf_counter()
+            for _ in range(args.backward_steps):
+                plan.build_K(C, V, D, K, Ex, precision=prec)
+                plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - tb0) / args.backward_steps
+            Ff = F.view(-1, 3)
+            fb[name] = {
+                "workload": wname + f" ({name} forward E_x; FP64 backward: dE/dC, dE/dV, dE/dD, forces)",
+                "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
+                "net_force_max": float(Ff.sum(0).abs().max().item()),
+                "euler_C": float((dC * C).sum().item() / (2 * E64)),
+                "euler_V": float((dV * V).sum().item() / E64),
+            }
+        out["forward_backward"] = fb
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

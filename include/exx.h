@@ -189,10 +189,14 @@ int exchange_energy(exx_plan plan, const double* K, const double* D,
  *   forces (device [n_atoms][3], may be NULL): -d(gE E_x)/dR for the
  *       synthetic model C_AB ~ exp(-r_AB / c_decay), V_AB ~ exp(-r_AB^2 / v_2s2)
  *       (on-site blocks position independent, D held fixed).
- * Any of dC, dV, dD may be NULL to skip it.  precision must be
- * EXX_PREC_FP64 (EXX_PREC_MIXED returns EXX_EUNSUPPORTED). */
+ * Any of dC, dV, dD may be NULL to skip it.  K (device, d_size, may be NULL)
+ * is the exchange matrix of these same C, V, D from build_K (of either
+ * precision): dD is then -1/2 gE K without a rebuild; with K NULL, dD needs a
+ * binary64 rebuild of K inside the call.  The gradient arithmetic is binary64:
+ * precision must be EXX_PREC_FP64 (EXX_PREC_MIXED returns EXX_EUNSUPPORTED;
+ * a mixed forward pass is differentiated by passing its K here). */
 int exchange_backward(exx_plan plan, const double* C, const double* V,
-                      const double* D, double gE, int precision,
+                      const double* D, const double* K, double gE, int precision,
                       double* dC, double* dV, double* dD, double* forces,
                       double c_decay, double v_2s2, void* stream);
 

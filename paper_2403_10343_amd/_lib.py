@@ -73,7 +73,7 @@ def lib():
     L.exx_plan_neighbors.argtypes = [vp, vp, vp]
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
-    L.exchange_backward.argtypes = [vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
     L.exx_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp]
@@ -183,8 +183,10 @@ class Plan:
         _check(lib().exchange_energy(self._h, _ptr(K), _ptr(D), _ptr(Ex), _stream(stream)))
 
     def exchange_backward(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
-                          precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None):
-        _check(lib().exchange_backward(self._h, _ptr(C), _ptr(V), _ptr(D), float(gE), int(precision),
+                          precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):
+        """Gradients of gE * E_x; K (optional) is this input's build_K result,
+        reused for dE/dD = -K/2 instead of a rebuild."""
+        _check(lib().exchange_backward(self._h, _ptr(C), _ptr(V), _ptr(D), _ptr(K), float(gE), int(precision),
                                        _ptr(dC), _ptr(dV), _ptr(dD), _ptr(forces),
                                        float(c_decay), float(v_2s2), _stream(stream)))
 

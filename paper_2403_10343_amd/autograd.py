@@ -1,7 +1,8 @@
 """torch.autograd binding of the exchange energy (argument marshalling only).
 
-``exchange_energy(plan, C, V, D)`` returns E_x per system; its backward calls
-the library's exchange_backward kernels for dE/dC, dE/dV and dE/dD.
+``exchange_energy(plan, C, V, D, precision)`` returns E_x per system (FP64 or
+mixed forward); its backward calls the library's binary64 exchange_backward
+kernels for dE/dC, dE/dV and dE/dD, reusing the forward K for dE/dD.
 ``exchange_forces(plan, C, V, D)`` returns -dE_x/dR for the synthetic
 exp(-r/1.5) / exp(-r^2/8) position dependence of C and V.
 """
@@ -16,13 +17,13 @@ class _ExchangeEnergy(torch.autograd.Function):
         K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=C.device)
         Ex = torch.empty(plan.n_systems, dtype=torch.float64, device=C.device)
         plan.build_K(C, V, D, K, Ex, precision=precision)
-        ctx.save_for_backward(C, V, D)
-        ctx.plan, ctx.precision = plan, precision
+        ctx.save_for_backward(C, V, D, K)
+        ctx.plan = plan
         return Ex
 
     @staticmethod
     def backward(ctx, gEx):
-        C, V, D = ctx.saved_tensors
+        C, V, D, K = ctx.saved_tensors
         g = gEx.detach().cpu()
         if not bool(torch.all(g == g[0])):
             raise NotImplementedError("exchange_energy backward needs the same upstream gradient for every system")
@@ -32,7 +33,8 @@ class _ExchangeEnergy(torch.autograd.Function):
         dV = torch.empty_like(V) if need[1] else None
         dD = torch.empty_like(D) if need[2] else None
         if dC is not None or dV is not None or dD is not None:
-            ctx.plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, precision=ctx.precision)
+            # binary64 gradient kernels; dE/dD = -K/2 reuses the forward K (of either precision)
+            ctx.plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K)
         return dC, dV, dD, None, None
 
 

@@ -1292,6 +1292,11 @@ __global__ void k_forces(const double* __restrict__ pos, const double* __restric
   F[3 * A + 2] = f2;
 }
 
+__global__ void k_scaled_copy(double* __restrict__ y, const double* __restrict__ x, int64_t n, double a) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
 __global__ void k_scale(double* x, int64_t n, double a) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] *= a;
@@ -1917,8 +1922,8 @@ int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex,
   return launch_energy(plan, K, D, Ex, (hipStream_t)stream);
 }
 
-int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, double gE,
-                      int precision, double* dC, double* dV, double* dD, double* forces,
+int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                      double gE, int precision, double* dC, double* dV, double* dD, double* forces,
                       double c_decay, double v_2s2, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "exchange_backward: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "exchange_backward: host-only plan");
@@ -1942,7 +1947,11 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
   double* dCb = dC ? dC : plan->dC_scratch;
   double* dVb = dV ? dV : plan->dV_scratch;
   launch_repack_E(plan, C, D, st, false);
-  if (dD) {
+  if (dD && K) {
+    // dE/dD = -1/2 K from the caller's K
+    hipLaunchKernelGGL(k_scaled_copy, dim3(1024), dim3(256), 0, st, dD, K, hp.d_size, -0.5 * gE);
+    if (needC) launch_H(plan, V, D, 1.0, H_WRITE, st);
+  } else if (dD) {
     // dE/dD = -1/2 K: the forward build into dD, then scaled
     hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, dD, hp.d_size);
     launch_H(plan, V, D, 2.0, H_WRITE, st);

@@ -139,3 +139,42 @@ def test_autograd_function(exx):
     assert relmax(system_block(D.grad.cpu().numpy(), inp.layout, 0), 3.0 * go["dD"]) < 1e-10
     F = exx.exchange_forces(plan, C.detach(), V.detach(), D.detach()).cpu().numpy()
     assert relmax(F, O.forces(inp, go)) < 1e-10
+
+
+def test_backward_with_forward_K(exx):
+    """Passing the forward K: dE/dD is exactly -gE K / 2 and the other
+    gradients agree with the self-contained backward (and the oracle)."""
+    sysm = synth.water_cluster(4, 6)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    C, V, D = device_inputs(inp, torch)
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+    plan.build_K(C, V, D, K)
+    ref = backward(plan, inp, gE=0.7)
+    dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D)
+    F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device="cuda:0")
+    plan.exchange_backward(C, V, D, 0.7, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+    torch.cuda.synchronize()
+    assert np.array_equal(dD.cpu().numpy(), -0.35 * K.cpu().numpy())
+    assert relmax(dC.cpu().numpy(), ref["dC"]) < 1e-12
+    assert np.array_equal(dV.cpu().numpy(), ref["dV"])
+    assert relmax(F.cpu().numpy().reshape(-1, 3), ref["F"]) < 1e-12
+    go = O.gradients(inp)
+    assert relmax(dC.cpu().numpy(), 0.7 * go["dC"]) < 1e-10
+
+
+def test_autograd_mixed_forward(exx):
+    """Mixed-precision forward, binary64 backward: dC and dV match the oracle at
+    the FP64 bar; dD = -K/2 of the mixed K, within the mixed-path bar."""
+    sysm = synth.water_cluster(8, 4)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)   # default split distance
+    C, V, D = (x.clone().requires_grad_(True) for x in device_inputs(inp, torch))
+    E = exx.exchange_energy(plan, C, V, D, precision=exx.PREC_MIXED)
+    E.sum().backward()
+    go = O.gradients(inp)
+    assert relmax(C.grad.cpu().numpy(), go["dC"]) < 1e-10
+    assert relmax(V.grad.cpu().numpy(), go["dV"]) < 1e-10
+    dD = system_block(D.grad.cpu().numpy(), inp.layout, 0)
+    assert np.abs(dD - go["dD"]).max() <= 0.5e-5
+    assert abs(E.item() - go["E"]) / sysm.n_atoms <= 1e-6
