@@ -109,6 +109,7 @@ struct DevPlan {
   GTile *hm_tiles_near, *hm_tiles_far;
   Slot4 *hm_q_near, *hm_x_near, *hm_q_far, *hm_x_far;
   int* t2m_items;
+  int* dv_items;
   FItem* f_items;
   int* f_plist;
   int *en_sys, *en_beg, *en_end;
@@ -1132,16 +1133,22 @@ __global__ __launch_bounds__(256) void k_block_dot(const double* __restrict__ X,
 // Off-site stored entries carry both V_{mu nu} and V_{nu mu}.  Same LDS
 // staging as the T2 kernel (columns j of N[Q] in chunks).
 
-template <int NTP, int NTQ>
-__global__ __launch_bounds__(256) void k_dV(const double* __restrict__ V, const double* __restrict__ D,
-                                            double* __restrict__ dV, DevPlan d, double gE, int n_items,
-                                            int n_padded) {
+// One workgroup of eight wavefronts per canonical pair, one column of each
+// 8-column chunk per wavefront; compile-time shape per pair class (aux tiles
+// of 16 of P and Q, basis steps of 4 of Q and P); the next chunk is fetched
+// into registers while the current one is used from LDS.
+constexpr int DV_WAVES = 8, DV_COLS = 8, DV_PITCH = DV_COLS + 1, DV_RSTEP = 64 * DV_WAVES / DV_COLS;
+
+template <int NTP, int NTQ, int NLQ, int NIP>
+__global__ __launch_bounds__(64 * DV_WAVES) void k_dV(const double* __restrict__ V, const double* __restrict__ D,
+                                                     double* __restrict__ dV, DevPlan d, const int* __restrict__ items,
+                                                     double gE, int n_items, int n_padded, int item_base) {
   extern __shared__ double sm[];
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
-  const int p = w;
+  const int p = items[item_base + w];
   const int P = d.pair_a[p], Q = d.pair_b[p];
   const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];
   const int sP = aP * bP, sQ = aQ * bQ;
@@ -1155,64 +1162,84 @@ __global__ __launch_bounds__(256) void k_dV(const double* __restrict__ V, const 
   const double* EP = d.E + d.e_off[P];
   const double* EQ = d.E + d.e_off[Q];
   double* sT = sm;
-  double* sE = sm + (size_t)sQ * T2_PITCH;
-  const int ntp = (aP + 15) >> 4, ntq = (aQ + 15) >> 4;
+  double* sE = sm + (size_t)sQ * DV_PITCH;
   // D_PQ fragments: A[i][l] with i = lr, l = 4 q + lk
-  double da[NB_MAX / 4];
+  double da[NLQ];
   const double* DPQ = D + d.sys_d_off[s] + (size_t)d.bo[P] * ns + d.bo[Q];
 #pragma unroll
-  for (int q = 0; q < NB_MAX / 4; ++q) {
+  for (int q = 0; q < NLQ; ++q) {
     const int l = 4 * q + lk;
-    da[q] = (lr < bP && l < bQ) ? DPQ[(size_t)lr * ns + l] : 0.0;
+    const bool ok = lr < bP && l < bQ;
+    const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
+    da[q] = ok ? x : 0.0;
   }
-  const int nlq = (bQ + 3) >> 2, nip = (bP + 3) >> 2;
   d4 acc[NTP][NTQ];
 #pragma unroll
   for (int x = 0; x < NTP; ++x)
 #pragma unroll
     for (int y = 0; y < NTQ; ++y) acc[x][y] = d4{0, 0, 0, 0};
-  const int tc = threadIdx.x & (T2_COLS - 1);
-  for (int l0 = 0; l0 < nQ; l0 += T2_COLS) {
+  const int tc = threadIdx.x & (DV_COLS - 1), r0 = threadIdx.x / DV_COLS;
+  constexpr int RT = (NTQ * 16 * NB_MAX + DV_RSTEP - 1) / DV_RSTEP;
+  constexpr int RE = (NTP * 16 * NB_MAX + DV_RSTEP - 1) / DV_RSTEP;
+  double pt[RT], pe[RE];
+  auto fetch = [&](int l0) {
     const int l = l0 + tc;
-    const bool cvld = l < nQ;
-    const int ce = cvld ? m2P[cg[l]] : 0;
+    const bool cv = l < nQ;
+    const int ce = cv ? m2P[cg[l]] : 0;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int r = r0 + DV_RSTEP * i;
+      const bool ok = cv && r < sQ;
+      const double x = TQ[ok ? (size_t)r * nQ + l : 0];
+      pt[i] = ok ? x : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RE; ++i) {
+      const int r = r0 + DV_RSTEP * i;
+      const bool ok = cv && r < sP;
+      const double x = EP[ok ? (size_t)r * mP + ce : 0];
+      pe[i] = ok ? x : 0.0;
+    }
+  };
+  fetch(0);
+  for (int l0 = 0; l0 < nQ; l0 += DV_COLS) {
     __syncthreads();
-    for (int r = threadIdx.x >> 3; r < sQ; r += 32) sT[r * T2_PITCH + tc] = cvld ? TQ[(size_t)r * nQ + l] : 0.0;
-    for (int r = threadIdx.x >> 3; r < sP; r += 32) sE[r * T2_PITCH + tc] = cvld ? EP[(size_t)r * mP + ce] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int r = r0 + DV_RSTEP * i;
+      if (r < sQ) sT[r * DV_PITCH + tc] = pt[i];
+    }
+#pragma unroll
+    for (int i = 0; i < RE; ++i) {
+      const int r = r0 + DV_RSTEP * i;
+      if (r < sP) sE[r * DV_PITCH + tc] = pe[i];
+    }
     __syncthreads();
+    if (l0 + DV_COLS < nQ) fetch(l0 + DV_COLS);
+    const int c = wv;
+    if (l0 + c < nQ) {
 #pragma unroll
-    for (int h = 0; h < T2_COLS / 4; ++h) {
-      const int c = wv * (T2_COLS / 4) + h;
-      if (l0 + c < nQ) {
+      for (int y = 0; y < NTQ; ++y) {
+        // Yt[i][nu] = sum_l D[i, l] T_Q[(nu, l), j]
+        d4 Yt = d4{0, 0, 0, 0};
+        const int nu = 16 * y + lr;
 #pragma unroll
-        for (int y = 0; y < NTQ; ++y) {
-          if (y < ntq) {
-            // Yt[i][nu] = sum_l D[i, l] T_Q[(nu, l), j]
-            d4 Yt = d4{0, 0, 0, 0};
-            const int nu = 16 * y + lr;
+        for (int q = 0; q < NLQ; ++q) {
+          const int lq = 4 * q + lk;
+          const bool ok = nu < aQ && lq < bQ;
+          const double b = sT[(ok ? (nu * bQ + lq) * DV_PITCH : 0) + c];
+          Yt = mfma64(da[q], ok ? b : 0.0, Yt);
+        }
+        // tB[mu][nu] += sum_i E_P[(mu, i), j] Yt[i][nu]
 #pragma unroll
-            for (int q = 0; q < NB_MAX / 4; ++q) {
-              if (q < nlq) {
-                const int lq = 4 * q + lk;
-                const double b = (nu < aQ && lq < bQ) ? sT[(nu * bQ + lq) * T2_PITCH + c] : 0.0;
-                Yt = mfma64(da[q], b, Yt);
-              }
-            }
-            // tB[mu][nu] += sum_i E_P[(mu, i), j] Yt[i][nu]
+        for (int x = 0; x < NTP; ++x) {
+          const int mu = 16 * x + lr;
 #pragma unroll
-            for (int x = 0; x < NTP; ++x) {
-              if (x < ntp) {
-                const int mu = 16 * x + lr;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                  if (v < nip) {
-                    const int i = 4 * v + lk;
-                    const double a = (mu < aP && i < bP) ? sE[(mu * bP + i) * T2_PITCH + c] : 0.0;
-                    acc[x][y] = mfma64(a, Yt[v], acc[x][y]);
-                  }
-                }
-              }
-            }
+          for (int v = 0; v < NIP; ++v) {
+            const int i = 4 * v + lk;
+            const bool ok = mu < aP && i < bP;
+            const double a = sE[(ok ? (mu * bP + i) * DV_PITCH : 0) + c];
+            acc[x][y] = mfma64(ok ? a : 0.0, Yt[v], acc[x][y]);
           }
         }
       }
@@ -1221,48 +1248,42 @@ __global__ __launch_bounds__(256) void k_dV(const double* __restrict__ V, const 
   // tA: k = (i, l) flattened, k-steps dealt round-robin to the wavefronts
   {
     const int K2 = bP * bQ, nk = (K2 + 3) >> 2;
-    for (int q = wv; q < nk; q += 4) {
+    for (int q = wv; q < nk; q += DV_WAVES) {
       const int kf = 4 * q + lk;
       const bool kv = kf < K2;
       const int i = kv ? kf / bQ : 0, l = kv ? kf - i * bQ : 0;
       const int cP = kv ? m2P[d.bo[Q] + l] : 0, cQ = kv ? m2Q[d.bo[P] + i] : 0;
 #pragma unroll
       for (int y = 0; y < NTQ; ++y) {
-        if (y < ntq) {
-          const int nu = 16 * y + lr;
-          const double b = (kv && nu < aQ) ? EQ[(size_t)(nu * bQ + l) * mQ + cQ] : 0.0;
+        const int nu = 16 * y + lr;
+        const bool okb = kv && nu < aQ;
+        const double b = EQ[okb ? (size_t)(nu * bQ + l) * mQ + cQ : 0];
 #pragma unroll
-          for (int x = 0; x < NTP; ++x) {
-            if (x < ntp) {
-              const int mu = 16 * x + lr;
-              const double a = (kv && mu < aP) ? EP[(size_t)(mu * bP + i) * mP + cP] : 0.0;
-              acc[x][y] = mfma64(a, b, acc[x][y]);
-            }
-          }
+        for (int x = 0; x < NTP; ++x) {
+          const int mu = 16 * x + lr;
+          const bool oka = kv && mu < aP;
+          const double a = EP[oka ? (size_t)(mu * bP + i) * mP + cP : 0];
+          acc[x][y] = mfma64(oka ? a : 0.0, okb ? b : 0.0, acc[x][y]);
         }
       }
     }
   }
-  // fixed-order reduction of the four wavefront partials, tile by tile
+  // fixed-order reduction of the wavefront partials, tile by tile
   const double f = -0.5 * gE * (P != Q ? 2.0 : 1.0);
   double* dVp = dV + d.v_off[p];
 #pragma unroll
   for (int x = 0; x < NTP; ++x)
 #pragma unroll
     for (int y = 0; y < NTQ; ++y) {
-      if (x < ntp && y < ntq) {
-        __syncthreads();
-        for (int v = 0; v < 4; ++v) sm[(wv * 4 + v) * 64 + L] = acc[x][y][v];
-        __syncthreads();
-        if (wv == 0) {
-          for (int v = 0; v < 4; ++v) {
-            double t = sm[v * 64 + L];
-            t += sm[(4 + v) * 64 + L];
-            t += sm[(8 + v) * 64 + L];
-            t += sm[(12 + v) * 64 + L];
-            const int mu = 16 * x + lk + 4 * v, nu = 16 * y + lr;
-            if (mu < aP && nu < aQ) dVp[(size_t)mu * aQ + nu] = f * t;
-          }
+      __syncthreads();
+      for (int v = 0; v < 4; ++v) sm[(wv * 4 + v) * 64 + L] = acc[x][y][v];
+      __syncthreads();
+      if (wv == 0) {
+        for (int v = 0; v < 4; ++v) {
+          double t = sm[v * 64 + L];
+          for (int w2 = 1; w2 < DV_WAVES; ++w2) t += sm[(w2 * 4 + v) * 64 + L];
+          const int mu = 16 * x + lk + 4 * v, nu = 16 * y + lr;
+          if (mu < aP && nu < aQ) dVp[(size_t)mu * aQ + nu] = f * t;
         }
       }
     }
@@ -1355,7 +1376,7 @@ static int upload_plan(exx_plan_s* pl) {
   UP(t_off); UP(e_off); UP(e_items); UP(ct_run_ptr); UP(ct_klen); UP(runs);
   UP(gd_items); UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
-  UP(g_tiles); UP(gq); UP(gx); UP(t2_items);
+  UP(g_tiles); UP(gq); UP(gx); UP(t2_items); UP(dv_items);
   UP(f_items); UP(f_plist); UP(en_sys); UP(en_beg); UP(en_end); UP(y_tiles); UP(y_off);
 #undef UP
   if ((rc = alloc_buf(pl, d.T, hp.t_total))) return rc;
@@ -1718,15 +1739,37 @@ static void launch_final(exx_plan plan, double* K, hipStream_t st) {
   hipLaunchKernelGGL(k_symreduce, dim3(nFp), dim3(256), 0, st, K, plan->d, nF, nFp);
 }
 
-static void launch_dV(exx_plan plan, const double* V, const double* D, double* dV, double gE, hipStream_t st) {
-  const HostPlan& hp = plan->hp;
+extern "C++" {
+template <int NTP, int NTQ>
+static void launch_dV_t(exx_plan plan, const DVClass& c, const double* V, const double* D, double* dV, double gE,
+                        hipStream_t st) {
+  const int n = c.end - c.beg, np_ = (n + 7) / 8 * 8;
   DevPlan& d = plan->d;
-  const int nP = (int)hp.pair_a.size(), nPp = (nP + 7) / 8 * 8;
-  switch (plan->t2_nt) {
-    case 1: hipLaunchKernelGGL((k_dV<1, 1>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
-    case 2: hipLaunchKernelGGL((k_dV<2, 2>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
-    case 3: hipLaunchKernelGGL((k_dV<3, 3>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
-    default: hipLaunchKernelGGL((k_dV<4, 4>), dim3(nPp), dim3(256), plan->t2_lds, st, V, D, dV, d, gE, nP, nPp); break;
+  const size_t lds = std::max((size_t)2 * plan->h_smax_t2 * DV_PITCH, (size_t)DV_WAVES * 4 * 64) * sizeof(double);
+  const dim3 g(np_), b(64 * DV_WAVES);
+  const int key = c.nlq * 8 + c.nip;
+  // basis steps of 4 of Q and P: 1..4 each
+  switch (key) {
+#define DVC(NL, NI) case NL * 8 + NI: hipLaunchKernelGGL((k_dV<NTP, NTQ, NL, NI>), g, b, lds, st, V, D, dV, d, d.dv_items, gE, n, np_, c.beg); break;
+    DVC(1, 1) DVC(1, 2) DVC(1, 3) DVC(1, 4) DVC(2, 1) DVC(2, 2) DVC(2, 3) DVC(2, 4)
+    DVC(3, 1) DVC(3, 2) DVC(3, 3) DVC(3, 4) DVC(4, 1) DVC(4, 2) DVC(4, 3) DVC(4, 4)
+#undef DVC
+    default: break;
+  }
+}
+}  // extern "C++"
+
+static void launch_dV(exx_plan plan, const double* V, const double* D, double* dV, double gE, hipStream_t st) {
+  for (const DVClass& c : plan->hp.dv_classes) {
+    if (c.end <= c.beg) continue;
+    const int k = c.ntp * 8 + c.ntq;
+    switch (k) {
+#define DVT(TP, TQ) case TP * 8 + TQ: launch_dV_t<TP, TQ>(plan, c, V, D, dV, gE, st); break;
+      DVT(1, 1) DVT(1, 2) DVT(1, 3) DVT(1, 4) DVT(2, 1) DVT(2, 2) DVT(2, 3) DVT(2, 4)
+      DVT(3, 1) DVT(3, 2) DVT(3, 3) DVT(3, 4) DVT(4, 1) DVT(4, 2) DVT(4, 3) DVT(4, 4)
+#undef DVT
+      default: break;
+    }
   }
 }
 

@@ -35,6 +35,7 @@ constexpr double GROUP_RADIUS = 2.5; // A, group atoms lie within this of the fi
 struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)
 struct YTile { int P, m0, n0, pad; };          // 64 x 64 tile of Y_P = T_P^T H'_P
 struct T2Class { int nt, ns, beg, end, prec; }; // items [beg, end) with this shape (prec 1: binary32)
+struct DVClass { int ntp, ntq, nlq, nip, beg, end; };  // dV pairs [beg, end) of dv_items with this shape
 
 struct HostPlan {
   // system description
@@ -74,6 +75,8 @@ struct HostPlan {
   std::vector<Slot4> gq, gx;
   int h_waves = 1;
   std::vector<int> t2_items;                        // 2 * canonical pair id + orientation bit
+  std::vector<int> dv_items;                        // canonical pair ids sorted by dV shape class
+  std::vector<DVClass> dv_classes;
   std::vector<T2Class> t2_classes;
   std::vector<int64_t> y_off;                       // Y_P = T_P^T H'_P, n_P x m_P row-major
   int64_t y_total = 0;

@@ -446,6 +446,24 @@ int derive_lists(HostPlan& hp, std::string& err) {
       hp.t2_classes.back().end = i + 1;
     }
   }
+  // ---- dV tasks: canonical pairs grouped by shape (aux tiles of 16 of P and
+  // Q, basis steps of 4 of Q and P); stable order inside a class
+  {
+    auto key = [&](int p) {
+      const int a = hp.pair_a[p], b = hp.pair_b[p];
+      return (((hp.na[a] + 15) / 16) * 8 + (hp.na[b] + 15) / 16) * 64 + ((hp.nb[b] + 3) / 4) * 8 + (hp.nb[a] + 3) / 4;
+    };
+    hp.dv_items.resize(npairs);
+    for (int64_t p = 0; p < npairs; ++p) hp.dv_items[p] = (int)p;
+    std::stable_sort(hp.dv_items.begin(), hp.dv_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    hp.dv_classes.clear();
+    for (int i = 0; i < (int)hp.dv_items.size(); ++i) {
+      const int k = key(hp.dv_items[i]);
+      if (hp.dv_classes.empty() || i == 0 || key(hp.dv_items[i - 1]) != k)
+        hp.dv_classes.push_back(DVClass{k / 512, (k / 64) % 8, (k / 8) % 8, k % 8, i, i});
+      hp.dv_classes.back().end = i + 1;
+    }
+  }
   // ---- final tasks: 32 x 32 tile pairs (upper triangle) with their P-lists
   hp.f_items.clear();
   hp.f_plist.clear();
