@@ -79,8 +79,58 @@ def cpu_baseline(inp, seconds=15.0, max_rows=64):
     dt = time.perf_counter() - t0
     rec = {"value": done / dt / n, "unit": "builds/s", "cores": int(threads), "kind": "oracle",
            "sample": f"{done} random rows of K ({n} rows per build) by the oracle's row route, "
-                     f"{dt:.1f} s; builds/s = rows/s / {n}"}
+                     f"{dt:.1f} s; builds/s = rows/s / {n}",
+           "host": host_description()}
     return rec, order[:done], np.array(rows)
+
+
+def host_description():
+    """CPU model, logical CPUs and the BLAS library behind NumPy (for the baseline record)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = ""
+    try:
+        from threadpoolctl import threadpool_info
+        blas = ", ".join(sorted({f"{t.get('internal_api')} {t.get('version')}" for t in threadpool_info()}))
+    except Exception:
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "blas": blas}
+
+
+def small_config_comparison(exx, torch, seconds_cap=60.0):
+    """The 24-atom cluster: one full oracle build (4-index route, which also
+    gives E_x directly from (ij|kl)) against the GPU FP64 build."""
+    import numpy as np
+    import synth
+    from oracle import exx_oracle as O
+    inp = synth.make_inputs(synth.config(1))
+    t0 = time.perf_counter()
+    K4, _, e_direct = O.k_4index(inp)
+    t_cpu = time.perf_counter() - t0
+    plan = exx.Plan.for_system(inp.system)
+    dev = torch.device("cuda:0")
+    C, V, D = (torch.from_numpy(a).to(dev) for a in (inp.C, inp.V, inp.D))
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=dev)
+    Ex = torch.empty(1, dtype=torch.float64, device=dev)
+    plan.build_K(C, V, D, K, Ex)
+    torch.cuda.synchronize()
+    n = 20
+    t0 = time.perf_counter()
+    for _ in range(n):
+        plan.build_K(C, V, D, K, Ex)
+    torch.cuda.synchronize()
+    t_gpu = (time.perf_counter() - t0) / n
+    Kg = K.cpu().numpy().reshape(K4.shape)
+    return {"workload": "water_cluster_8_24_atoms_192_basis", "oracle_4index_s": t_cpu,
+            "gpu_fp64_ms": 1e3 * t_gpu, "max_rel_dK": float(np.abs(Kg - K4).max() / np.abs(K4).max()),
+            "rel_dE_x_direct": float(abs(Ex.item() - e_direct) / abs(e_direct))}
 
 
 def time_builds(plan, C, V, D, K, Ex, prec, steps, warmup, stream):
@@ -258,6 +308,7 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
+        out["config1_oracle_vs_gpu"] = small_config_comparison(exx, torch)
         rec, rows, Krows = cpu_baseline(inp, seconds=args.cpu_seconds)
         out["cpu_baseline"] = rec
         n = int(inp.layout.sys_nbas[0])

@@ -99,9 +99,17 @@ def test_zero_D_and_linearity_and_determinism(exx):
 
 
 def test_config2_sampled_rows(exx):
-    """768-atom box at full size: sampled rows of K against the row oracle."""
+    """768-atom box at full size, in the benchmark's launch configuration (tile
+    shapes chosen by the autotuner on these inputs): sampled rows of K against
+    the row oracle, symmetry, and E_x from K."""
+    from tests.gpu_util import device_inputs
     inp = synth.make_inputs(synth.config(2))
-    K, Ex = run_build(_plan(exx, inp.system), inp, torch)
+    plan = _plan(exx, inp.system)
+    C, V, D = device_inputs(inp, torch)
+    Kt = torch.empty(plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+    plan.autotune(C, V, D, Kt)
+    print("tuned tile shapes", {k: v[0] for k, v in plan.tuning().items()}, flush=True)
+    K, Ex = run_build(plan, inp, torch)
     Kg = system_block(K, inp.layout, 0)
     rng = np.random.default_rng(0)
     rows = np.concatenate([[0, 6143], rng.integers(0, 6144, 4)])
