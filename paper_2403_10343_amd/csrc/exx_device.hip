@@ -986,14 +986,9 @@ __global__ __launch_bounds__(256) void k_Y(DevPlan d, int n_tiles, int n_padded)
 // X[l, i] with i fastest (both coalesced), the two halves are combined in
 // LDS, and every element is written together with its mirror.
 
-constexpr int SR_PB = 8;   // aux atoms whose column maps are staged per barrier pair
-
 __global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPlan d, int n_items,
                                                    int n_padded) {
-  // per staged atom: c1(I rows), c2(I rows), c1(L cols), c2(L cols)
-  __shared__ int cmap[SR_PB][4][32];
-  __shared__ int pm[SR_PB];
-  __shared__ int64_t poff[SR_PB];
+  __shared__ int cmap[4][32];      // c1(I rows), c2(I rows), c1(L cols), c2(L cols)
   __shared__ double xa[32][33], xb[32][33];
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
@@ -1003,40 +998,27 @@ __global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPl
   const int t = threadIdx.x;
   const int ta = t & 31, tb = t >> 5;   // element (tb + 8 r, ta)
   double acc_a[4] = {0, 0, 0, 0}, acc_b[4] = {0, 0, 0, 0};
-  for (int pb = it.pbeg; pb < it.pend; pb += SR_PB) {
-    const int nb = min(SR_PB, it.pend - pb);
+  for (int pi = it.pbeg; pi < it.pend; ++pi) {
+    const int P = d.f_plist[pi];
+    const int nP_ = d.m_loc[P];
+    const double* Y = d.Y + d.y_off[P];
     __syncthreads();
-    for (int idx = t; idx < nb * 128; idx += blockDim.x) {
-      const int k = idx >> 7, which = (idx >> 5) & 3, x = idx & 31;
-      const int P = d.f_plist[pb + k];
+    if (t < 128) {
+      const int which = t >> 5, x = t & 31;
       const int g = ((which < 2) ? it.gI0 : it.gL0) + x;
       const int* mp = ((which & 1) ? d.map2 : d.map1) + d.map_off[P];
-      cmap[k][which][x] = g < ns ? mp[g] : -1;
-      if (idx == k * 128) {
-        pm[k] = d.m_loc[P];
-        poff[k] = d.y_off[P];
-      }
+      cmap[which][x] = g < ns ? mp[g] : -1;
     }
     __syncthreads();
-    // all loads of the batch are independent: branch-free (invalid ones read Y_P[0] and drop it)
-    for (int k = 0; k < nb; ++k) {
-      const int nP_ = pm[k];
-      const double* Y = d.Y + poff[k];
-      const int c2 = cmap[k][3][ta], d2 = cmap[k][1][ta];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ii = tb + 8 * r;
-        // X[i = I0 + ii, l = L0 + ta] = Y_P[c1(i), c2(l)]
-        const int c1 = cmap[k][0][ii];
-        const bool oa = c1 >= 0 && c2 >= 0;
-        const double ya = Y[oa ? (size_t)c1 * nP_ + c2 : 0];
-        acc_a[r] += oa ? ya : 0.0;
-        // X[l = L0 + ii, i = I0 + ta] = Y_P[c1(l), c2(i)], stored at (ta, ii)
-        const int d1 = cmap[k][2][ii];
-        const bool ob = d1 >= 0 && d2 >= 0;
-        const double yb = Y[ob ? (size_t)d1 * nP_ + d2 : 0];
-        acc_b[r] += ob ? yb : 0.0;
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int ii = tb + 8 * r;
+      // X[i = I0 + ii, l = L0 + ta] = Y_P[c1(i), c2(l)]
+      const int c1 = cmap[0][ii], c2 = cmap[3][ta];
+      if (c1 >= 0 && c2 >= 0) acc_a[r] += Y[(size_t)c1 * nP_ + c2];
+      // X[l = L0 + ii, i = I0 + ta] = Y_P[c1(l), c2(i)], stored at (ta, ii)
+      const int d1 = cmap[2][ii], d2 = cmap[1][ta];
+      if (d1 >= 0 && d2 >= 0) acc_b[r] += Y[(size_t)d1 * nP_ + d2];
     }
   }
   __syncthreads();
