@@ -450,7 +450,7 @@ struct HUnits {            // unit table of the group (LDS)
 // once per Q; the binary64 kernel (register bound) reads them per unit.
 template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == sizeof(float); };
 
-// One Q of a V-stage tile, both columns of this wavefront.  The staged T_Q
+// One Q of a V-stage tile, all H_CPW columns of this wavefront.  The staged T_Q
 // rows are read without masks: rows past s_Q (or of lanes past n_b(Q)) hold
 // finite values, and they meet zero V (nu >= n_a(Q)) or zero D (l >= n_b(Q))
 // operands.  A column missing from N[Q] is staged as zeros.
@@ -461,7 +461,6 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
                                     int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
                                     int lk) {
   typedef typename Mf<R>::acc A4;
-  static_assert(H_CPW == 2, "two columns per wavefront");
   bool anyc = false;
 #pragma unroll
   for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || ((c0 + cc < ncols) && lc_row[c0 + cc] >= 0);
@@ -518,25 +517,25 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
             da[q] = ok ? (R)x : (R)0;
           }
         }
-        // the A operands of both columns first (independent LDS reads), then the chains
-        R ta[NS], tb[NS];
+        // the A operands of all columns first (independent LDS reads), then the chains
+        R ta[NS][H_CPW];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
           const R* row = t0 + (q * 4 + lk) * bQ * LDS_PITCH;
-          ta[q] = row[0];
-          tb[q] = row[1];
-        }
-        A4 Fa = A4{0, 0, 0, 0}, Fb = A4{0, 0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < NS; ++q) {
-          Fa = Mf<R>::mma(ta[q], vb[q], Fa);
-          Fb = Mf<R>::mma(tb[q], vb[q], Fb);
+          for (int cc = 0; cc < H_CPW; ++cc) ta[q][cc] = row[cc];
         }
+        A4 F[H_CPW];
 #pragma unroll
-        for (int q = 0; q < NLR; ++q) {
-          Hc[u][0] = Mf<R>::mma(da[q], Fa[q], Hc[u][0]);
-          Hc[u][1] = Mf<R>::mma(da[q], Fb[q], Hc[u][1]);
-        }
+        for (int cc = 0; cc < H_CPW; ++cc) F[cc] = A4{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+          for (int cc = 0; cc < H_CPW; ++cc) F[cc] = Mf<R>::mma(ta[q][cc], vb[q], F[cc]);
+#pragma unroll
+        for (int q = 0; q < NLR; ++q)
+#pragma unroll
+          for (int cc = 0; cc < H_CPW; ++cc) Hc[u][cc] = Mf<R>::mma(da[q], F[cc][q], Hc[u][cc]);
       }
     }
   }
@@ -555,7 +554,7 @@ struct HLists {
 enum { H_WRITE = 0, H_ADD = 1, H_G_ADD = 2 };
 
 template <int U, typename R>
-__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_H(
+__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_H(
     const double* __restrict__ V, const double* __restrict__ D, DevPlan d, HLists hl, int n_tiles,
     int n_padded, double gscale, int mode) {
   typedef typename Mf<R>::acc A4;

@@ -29,7 +29,7 @@ struct Slot4 { int atom, p0, p1, p2; };      // list entry: atom, pair id with g
 
 constexpr int E_TILE = 64;           // output tile (rows and columns) of the E = M D GEMM
 constexpr int GROUP_ATOMS = 3;       // atoms per H group (slots)
-constexpr int H_COLS = 8;            // columns per V-stage tile
+constexpr int H_COLS = 4;            // columns per V-stage tile (one per wavefront)
 constexpr int GROUP_WAVES = 8;       // wavefronts per H workgroup at most
 constexpr double GROUP_RADIUS = 2.5; // A, group atoms lie within this of the first
 struct FItem { int sys, gI0, gL0, pbeg, pend, pad0, pad1, pad2; };  // final tile pair (32 x 32)
