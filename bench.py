@@ -34,10 +34,10 @@ CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "e6ce9496922948e6",
+    "sources": "c5127c6c4c91743c",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 23.192e9 + 3.509e9, ("fp64", "T2"): 35.626e9 + 0.025e9,
-              ("fp64", "final"): 10.245e9 + 4.280e9, ("fp64", "E"): 2.756e9 + 2.477e9},
+    "bytes": {("fp64", "H"): 25.280e9 + 4.150e9, ("fp64", "T2"): 35.342e9 + 0.025e9,
+              ("fp64", "final"): 10.243e9 + 4.280e9, ("fp64", "E"): 2.756e9 + 2.476e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double>", "H32": "k_H<U, float>",
                    "T2": "k_T2<NT, NS, double>", "T2_32": "k_T2<NT, NS, float>",
