@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--backward-steps", type=int, default=3,
                     help="also time forward + exchange_backward (dE/dC, dE/dV, dE/dD, forces); 0 = skip")
+    ap.add_argument("--spin-steps", type=int, default=5,
+                    help="also time the collinear-spin build (two density matrices, FP64); 0 = skip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -299,6 +301,26 @@ def main():
                 "euler_V": float((dV * V).sum().item() / E64),
             }
         out["forward_backward"] = fb
+    if args.spin_steps > 0:
+        Ds = torch.from_numpy(synth.spin_densities(inp).reshape(-1)).to(dev)
+        K2 = torch.empty(2 * plan.info["d_size"], dtype=torch.float64, device=dev)
+        plan.build_K_spin(C, V, Ds, K2, Ex)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        ts0 = time.perf_counter()
+        for _ in range(args.spin_steps):
+            plan.build_K_spin(C, V, Ds, K2, Ex)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - ts0) / args.spin_steps
+        sst, nrec = plan.stage_times()
+        plan.set_profiling(False)
+        out["spin"] = {
+            "workload": wname + " (collinear spin: two density matrices D^0, D^1, FP64)",
+            "ms_per_build": 1e3 * ts, "builds_per_s": 1.0 / ts,
+            "vs_two_one_density_builds": 2 * dt64 / ts,
+            "stage_ms": {n_: float(x) for n_, x in zip(names, sst / max(nrec, 1))},
+            "E_x": float(Ex[0].item()),
+        }
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

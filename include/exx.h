@@ -131,6 +131,21 @@ int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom);
 int build_K(exx_plan plan, const double* C, const double* V, const double* D,
             int precision, double* K, double* Ex, void* stream);
 
+/* Collinear spin: the spin index of Eq. realspace_exchange (Sec. "Description
+ * of the real-space formalism") runs over two values, and each spin has its
+ * own density matrix D^s and exchange matrix K^s = sum C V C D^s (the
+ * definition above with D^s in place of D).
+ * D: device, 2 * d_size doubles, D^0 then D^1, each laid out as D of build_K.
+ * K: device output, 2 * d_size doubles, K^0 then K^1 (each exactly symmetric).
+ * Ex: NULL, or device [n_systems]: E_x = -1/2 sum_s sum_ik K^s_ik D^s_ik
+ * (with D^0 = D^1 = D/2 this is the E_x of build_K for D).
+ * The repack of C and the F = V C part of the V stage (Eq. temp_F) are formed
+ * once for both spins.  precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns
+ * EXX_EUNSUPPORTED).  The first call allocates a second E and H' workspace
+ * (EXX_ENOMEM if that fails); calls on one plan must not overlap. */
+int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D,
+                 int precision, double* K, double* Ex, void* stream);
+
 /* Capture one build_K (these exact arrays, `precision` as in build_K) on
  * `stream` into a HIP graph owned by the plan, replacing any earlier one;
  * exx_graph_launch() replays it.  The arrays must stay valid while the graph is used.  The

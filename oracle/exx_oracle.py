@@ -28,6 +28,12 @@ Routes (three independent evaluations of the same definition):
 * ``k_rows``    evaluates whole rows K[i, :] from the definition with the
   structural zeros of C and V skipped; usable at any system size.
 
+Collinear spin (``k_spin``, ``spin_exchange_energy``): the spin index of
+Eq. (realspace_exchange) only selects the density matrix, so each spin's K^s
+is the definition above with D^s.  The paper does not write the spin energy
+either; the reading used is E_x = -1/2 sum_s sum_ik K^s_ik D^s_ik, which for
+D^0 = D^1 = D/2 is the closed-shell E_x above.
+
 Gradients (``gradients``) follow from E_x being quadratic in C and D and
 linear in V:  dE/dD = -1/2 K,  dE/dC^mu = -1/2 sum_nu V_{mu nu} D C^nu D,
 dE/dV_{mu nu} = -1/4 tr(C^mu D C^nu D); per stored layout entry the mirrored
@@ -37,6 +43,7 @@ the atom positions (C ~ exp(-r/1.5), V ~ exp(-r^2/8)), with D held fixed.
 """
 from __future__ import annotations
 
+import copy
 import math
 
 import numpy as np
@@ -272,6 +279,29 @@ def k_full_rows(inputs, s=0):
     """The whole K of system s via the row route (moderate sizes only)."""
     blk = Blocks(inputs, s)
     return k_rows(inputs, np.arange(blk.n), s, blk)
+
+
+# ----------------------------------------------------------------------------
+# collinear spin
+
+
+def with_density(inputs, D):
+    """A shallow copy of ``inputs`` whose (flat) density matrix is D."""
+    out = copy.copy(inputs)
+    out.D = np.asarray(D, dtype=np.float64)
+    return out
+
+
+def k_spin(inputs, D_spin, s=0, route="eigen"):
+    """[K^0, K^1] of system s: the definition evaluated once per spin density
+    matrix (D_spin: two flat arrays in the layout of inputs.D)."""
+    f = {"eigen": k_eigen, "rows": k_full_rows, "4index": lambda i, s: k_4index(i, s)[0]}[route]
+    return [f(with_density(inputs, D), s) for D in D_spin]
+
+
+def spin_exchange_energy(K_spin, D_spin):
+    """E_x = -1/2 sum_s sum_ik K^s_ik D^s_ik (K^s and D^s dense, one system)."""
+    return -0.5 * sum(float(np.sum(K * D)) for K, D in zip(K_spin, D_spin))
 
 
 # ----------------------------------------------------------------------------

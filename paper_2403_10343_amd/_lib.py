@@ -52,7 +52,7 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pai
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
-           "exx_plan_tuning", "exx_plan_set_tuning")
+           "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -72,6 +72,7 @@ def lib():
     L.exx_plan_pairs.argtypes = [vp, vp, vp, vp, vp]
     L.exx_plan_neighbors.argtypes = [vp, vp, vp]
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.build_K_spin.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
@@ -178,6 +179,12 @@ class Plan:
     def build_K(self, C, V, D, K, Ex=None, precision=PREC_FP64, stream=None):
         _check(lib().build_K(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
                              _stream(stream)))
+
+    def build_K_spin(self, C, V, D, K, Ex=None, precision=PREC_FP64, stream=None):
+        """Collinear spin: D and K hold two d_size blocks (spin 0, then spin 1);
+        Ex (optional) gets -1/2 sum_s sum K^s D^s per system."""
+        _check(lib().build_K_spin(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
+                                  _stream(stream)))
 
     def exchange_energy(self, K, D, Ex, stream=None):
         _check(lib().exchange_energy(self._h, _ptr(K), _ptr(D), _ptr(Ex), _stream(stream)))

@@ -157,6 +157,8 @@ struct exx_plan_s {
   hipGraphExec_t graph_exec = nullptr;
   double* dC_scratch = nullptr;     // gradient buffers used when the caller passes NULL
   double* dV_scratch = nullptr;
+  double* spin_E1 = nullptr;        // E and H' of the second spin (build_K_spin), allocated on first use
+  double* spin_H1 = nullptr;
 };
 
 template <typename X>
@@ -454,13 +456,16 @@ template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == si
 // rows are read without masks: rows past s_Q (or of lanes past n_b(Q)) hold
 // finite values, and they meet zero V (nu >= n_a(Q)) or zero D (l >= n_b(Q))
 // operands.  A column missing from N[Q] is staged as zeros.
-template <int NS, int NL, int U, typename R>
-__device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R* sT, const R* sV, const R* sD,
-                                    const HUnits& un, const int* roff, int vr, int nU, const int* qp,
-                                    const int64_t* qv, const double* V, const double* Ds, int64_t ns, int Q,
-                                    int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
+// NSP density matrices (collinear spin: two, D^s at Ds + s * dsp) share F; each has its own
+// D contraction and accumulators.
+template <int NS, int NL, int U, int NSP, typename R>
+__device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], const R* sT, const R* sV,
+                                    const R* sD, const HUnits& un, const int* roff, int vr, int nU, const int* qp,
+                                    const int64_t* qv, const double* V, const double* Ds, int64_t dsp, int64_t ns,
+                                    int Q, int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
                                     int lk) {
   typedef typename Mf<R>::acc A4;
+  static_assert(NSP == 1 || !HStage<R>::vd, "the LDS-staged binary32 kernel takes one density matrix");
   bool anyc = false;
 #pragma unroll
   for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || ((c0 + cc < ncols) && lc_row[c0 + cc] >= 0);
@@ -477,7 +482,7 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
         const int muB = un.mu0[u] + lr;
         const bool muv = muB < aP;
         R vb[NS];
-        R da[NLR];
+        R da[NSP][NLR];
         if constexpr (HStage<R>::vd) {
           const bool pqs = un.P[u] <= Q;
 #pragma unroll
@@ -494,7 +499,7 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
             const int l = Mf<R>::row(lk, q);
             const bool ok = lr < bP && l < bQ;
             const R x = sD[ok ? (sl * 16 + lr) * H_DPITCH + l : 0];
-            da[q] = ok ? x : (R)0;
+            da[0][q] = ok ? x : (R)0;
           }
         } else {
           // branch-free: invalid lanes read the block's first element and discard it
@@ -508,13 +513,16 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
             const double x = Vp[ok ? (pq ? muB * aQ + nu : nu * aP + muB) : 0];
             vb[q] = ok ? (R)x : (R)0;
           }
-          const double* DPQ = Ds + (size_t)un.bo[u] * ns + boQ;
 #pragma unroll
-          for (int q = 0; q < NLR; ++q) {
-            const int l = Mf<R>::row(lk, q);
-            const bool ok = lr < bP && l < bQ;
-            const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
-            da[q] = ok ? (R)x : (R)0;
+          for (int sp = 0; sp < NSP; ++sp) {
+            const double* DPQ = Ds + sp * dsp + (size_t)un.bo[u] * ns + boQ;
+#pragma unroll
+            for (int q = 0; q < NLR; ++q) {
+              const int l = Mf<R>::row(lk, q);
+              const bool ok = lr < bP && l < bQ;
+              const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
+              da[sp][q] = ok ? (R)x : (R)0;
+            }
           }
         }
         // the A operands of all columns first (independent LDS reads), then the chains
@@ -535,7 +543,9 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[U][H_CPW], const R
 #pragma unroll
         for (int q = 0; q < NLR; ++q)
 #pragma unroll
-          for (int cc = 0; cc < H_CPW; ++cc) Hc[u][cc] = Mf<R>::mma(da[q], F[cc][q], Hc[u][cc]);
+          for (int cc = 0; cc < H_CPW; ++cc)
+#pragma unroll
+            for (int sp = 0; sp < NSP; ++sp) Hc[sp][u][cc] = Mf<R>::mma(da[sp][q], F[cc][q], Hc[sp][u][cc]);
       }
     }
   }
@@ -547,14 +557,21 @@ struct HLists {
   const GTile* tiles;
   const Slot4 *gq, *gx;
   int v_base, d_base;     // element offsets of the staged V and D blocks in LDS
+  // second density matrix (collinear spin): D^1 at D + d_spin, its E and H' workspaces
+  int64_t d_spin;
+  const double* E1;
+  double* H1;
 };
 
 // mode: H_WRITE stores H' = (Q part + G part); H_ADD adds both parts to H';
 // H_G_ADD adds the G part only.
 enum { H_WRITE = 0, H_ADD = 1, H_G_ADD = 2 };
 
-template <int U, typename R>
-__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_H(
+// NSP = 2: the two spin density matrices of a collinear-spin build in one pass (F = V T_Q is
+// formed once); H'^0 goes to d.H, H'^1 to hl.H1.  Three wavefronts per SIMD for one density
+// matrix, two for two (their accumulators double).
+template <int U, typename R, int NSP>
+__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NSP == 1 ? 3 : 2))) void k_H(
     const double* __restrict__ V, const double* __restrict__ D, DevPlan d, HLists hl, int n_tiles,
     int n_padded, double gscale, int mode) {
   typedef typename Mf<R>::acc A4;
@@ -587,11 +604,13 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3)
   const int* gcol = d.grp_cols + tl.col_beg;
   const int ncols = tl.ncols;
   const int c0 = wv * H_CPW;
-  A4 Hc[U][H_CPW];
+  A4 Hc[NSP][U][H_CPW];
 #pragma unroll
-  for (int u = 0; u < U; ++u)
+  for (int sp = 0; sp < NSP; ++sp)
 #pragma unroll
-    for (int cc = 0; cc < H_CPW; ++cc) Hc[u][cc] = A4{0, 0, 0, 0};
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int cc = 0; cc < H_CPW; ++cc) Hc[sp][u][cc] = A4{0, 0, 0, 0};
   const int tc = threadIdx.x % H_COLS;
   const int tstep = blockDim.x / H_COLS;
   // LDS: T_Q[:, tile columns] | V_PQ of the group's atoms, [nu][group aux row] | D_PQ blocks
@@ -612,7 +631,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3)
       roff[t + 1] = roff[t] + sa_[t];
     }
   }
-  for (int i = threadIdx.x; i < hl.v_base; i += blockDim.x) sT[i] = (R)0;   // rows read past s_Q stay finite
+  // rows read past s_Q stay finite (the G-only pass has no Q loop and no dynamic LDS)
+  if (mode != H_G_ADD)
+    for (int i = threadIdx.x; i < hl.v_base; i += blockDim.x) sT[i] = (R)0;
   __syncthreads();
   const int vr = roff[GROUP_ATOMS];
   for (int e0 = mode == H_G_ADD ? tl.q_end : tl.q_beg; e0 < tl.q_end; e0 += HQ_CHUNK) {
@@ -665,9 +686,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3)
       __syncthreads();
       const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
       switch (h_class(nsQ, nlQ)) {
-        case 0: h_q<4, 2, U, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
-        case 1: h_q<10, 4, U, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
-        default: h_q<16, 4, U, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
+        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
+        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
+        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
       }
       __syncthreads();
     }
@@ -679,7 +700,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3)
     const int X = xe.atom;
     const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
     const int pp[3] = {xe.p0, xe.p1, xe.p2};
-    const double* EX0 = d.E + d.e_off[X];
+    const double* EXs[NSP];
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp) EXs[sp] = (sp == 0 ? d.E : hl.E1) + d.e_off[X];
     const int* m2X = d.map2 + d.map_off[X];
 #pragma unroll
     for (int cc = 0; cc < H_CPW; ++cc) {
@@ -696,15 +719,19 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3)
               const bool muv = muB < aP;
               const double* Vp = V + d.v_off[p];
               const int colx = lr < bP ? m2X[un.bo[u] + lr] : 0;
-              const double* EX = EX0 + colx + (size_t)ic * mX;
+              const size_t xo = colx + (size_t)ic * mX;
               const bool px = P <= X;
               for (int q = 0; q < (aX + 3) / 4; ++q) {
                 const int m2 = 4 * q + lk;
                 const bool mv = m2 < aX;
                 const bool oka = mv && lr < bP, okb = mv && muv;
-                const double a = EX[oka ? (size_t)(m2 * bX) * mX : 0];
                 const double b = Vp[okb ? (px ? muB * aX + m2 : m2 * aP + muB) : 0];
-                Hc[u][cc] = Mf<R>::mma(oka ? (R)a : (R)0, okb ? (R)(gscale * b) : (R)0, Hc[u][cc]);
+                const R bv = okb ? (R)(gscale * b) : (R)0;
+#pragma unroll
+                for (int sp = 0; sp < NSP; ++sp) {
+                  const double a = EXs[sp][oka ? xo + (size_t)(m2 * bX) * mX : xo];
+                  Hc[sp][u][cc] = Mf<R>::mma(oka ? (R)a : (R)0, bv, Hc[sp][u][cc]);
+                }
               }
             }
           }
@@ -718,19 +745,22 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(3)
     if (u < nU) {
       const int P = un.P[u], aP = un.a[u], bP = un.b[u], mP = d.m_loc[P];
       const int muB = un.mu0[u] + lr;
-      double* HP = d.H + d.e_off[P];
       const int* m2P = d.map2 + d.map_off[P];
 #pragma unroll
-      for (int cc = 0; cc < H_CPW; ++cc) {
-        const int c = c0 + cc;
-        const int col = (c < ncols) ? m2P[gcol[c]] : -1;
-        if (col >= 0 && muB < aP) {
+      for (int sp = 0; sp < NSP; ++sp) {
+        double* HP = (sp == 0 ? d.H : hl.H1) + d.e_off[P];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int j = Mf<R>::row(lk, v);
-            if (j < bP) {
-              double* h = HP + (size_t)(muB * bP + j) * mP + col;
-              *h = mode == H_WRITE ? (double)Hc[u][cc][v] : *h + (double)Hc[u][cc][v];
+        for (int cc = 0; cc < H_CPW; ++cc) {
+          const int c = c0 + cc;
+          const int col = (c < ncols) ? m2P[gcol[c]] : -1;
+          if (col >= 0 && muB < aP) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int j = Mf<R>::row(lk, v);
+              if (j < bP) {
+                double* h = HP + (size_t)(muB * bP + j) * mP + col;
+                *h = mode == H_WRITE ? (double)Hc[sp][u][cc][v] : *h + (double)Hc[sp][u][cc][v];
+              }
             }
           }
         }
@@ -1042,17 +1072,22 @@ __global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPl
 }
 
 // ---------------------------------------------------------------------------
-// energy: per-chunk tree reduction, then per-system ordered sum.
+// energy: per-chunk tree reduction, then per-system ordered sum.  n_spin density
+// matrices (and their K) are stored spin_stride apart; the chunk sums run over all.
 
 __global__ __launch_bounds__(256) void k_energy_part(const double* K, const double* D, DevPlan d,
-                                                     int n_chunks) {
+                                                     int n_chunks, int n_spin, int64_t spin_stride) {
   const int c = blockIdx.x;
   if (c >= n_chunks) return;
   const int s = d.en_sys[c];
   const int64_t base = d.sys_d_off[s];
   __shared__ double part[256];
   double acc = 0.0;
-  for (int e = d.en_beg[c] + threadIdx.x; e < d.en_end[c]; e += 256) acc += K[base + e] * D[base + e];
+  for (int sp = 0; sp < n_spin; ++sp) {
+    const double* Ks = K + sp * spin_stride;
+    const double* Dsp = D + sp * spin_stride;
+    for (int e = d.en_beg[c] + threadIdx.x; e < d.en_end[c]; e += 256) acc += Ks[base + e] * Dsp[base + e];
+  }
   part[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -1062,13 +1097,14 @@ __global__ __launch_bounds__(256) void k_energy_part(const double* K, const doub
   if (threadIdx.x == 0) d.epart[c] = part[0];
 }
 
-__global__ void k_energy_sum(double* Ex, DevPlan d, int n_chunks) {
+// scale: -1/4 for one (spin-summed) density matrix, -1/2 for the two spin density matrices
+__global__ void k_energy_sum(double* Ex, DevPlan d, int n_chunks, double scale) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.n_sys) return;
   double acc = 0.0;
   for (int c = 0; c < n_chunks; ++c)
     if (d.en_sys[c] == s) acc += d.epart[c];
-  Ex[s] = -0.25 * acc;
+  Ex[s] = scale * acc;
 }
 
 __global__ void k_zero(double* x, int64_t n) {
@@ -1557,10 +1593,12 @@ int64_t exx_plan_flops(exx_plan plan, int stage) {
   return hp.flops[stage];
 }
 
-static int launch_energy(exx_plan plan, const double* K, const double* D, double* Ex, hipStream_t st) {
+static int launch_energy(exx_plan plan, const double* K, const double* D, double* Ex, hipStream_t st,
+                         int n_spin = 1) {
   const int nch = (int)plan->hp.en_sys.size();
-  hipLaunchKernelGGL(k_energy_part, dim3(nch), dim3(256), 0, st, K, D, plan->d, nch);
-  hipLaunchKernelGGL(k_energy_sum, dim3((plan->hp.n_sys + 63) / 64), dim3(64), 0, st, Ex, plan->d, nch);
+  hipLaunchKernelGGL(k_energy_part, dim3(nch), dim3(256), 0, st, K, D, plan->d, nch, n_spin, plan->hp.d_size);
+  hipLaunchKernelGGL(k_energy_sum, dim3((plan->hp.n_sys + 63) / 64), dim3(64), 0, st, Ex, plan->d, nch,
+                     n_spin == 1 ? -0.25 : -0.5);
   HIP_TRY(hipGetLastError());
   return EXX_OK;
 }
@@ -1622,7 +1660,7 @@ static void launch_repack_E(exx_plan plan, const double* C, const double* D, hip
 }
 
 extern "C++" {
-template <typename R>
+template <typename R, int NSP = 1>
 static void launch_H_lists(exx_plan plan, const double* V, const double* D, const HLists& hl, int n, double gscale,
                            int mode, hipStream_t st) {
   if (n <= 0) return;
@@ -1631,11 +1669,11 @@ static void launch_H_lists(exx_plan plan, const double* V, const double* D, cons
   const size_t lds = mode == H_G_ADD ? 0 : (sizeof(R) == sizeof(double) ? plan->h_lds : plan->h_lds32);
   const dim3 grid(np_), blk(64 * H_WAVES);
   if (hp.h_waves <= 2)
-    hipLaunchKernelGGL((k_H<2, R>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+    hipLaunchKernelGGL((k_H<2, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
   else if (hp.h_waves <= 5)
-    hipLaunchKernelGGL((k_H<5, R>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+    hipLaunchKernelGGL((k_H<5, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
   else
-    hipLaunchKernelGGL((k_H<8, R>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+    hipLaunchKernelGGL((k_H<8, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
 }
 }  // extern "C++"
 
@@ -1807,6 +1845,63 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   HIP_TRY(hipGetLastError());
   int rc = EXX_OK;
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
+  stage_mark(plan, 8, st);
+  return rc;
+}
+
+// Collinear spin: E^s = T D^s for both spins, then one V-stage pass for both (F shared), then
+// T2 and the final contraction per spin with E and H' pointed at that spin's workspace.
+int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
+                 double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "build_K_spin: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "build_K_spin: host-only plan");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K_spin: NULL array");
+  if (precision == EXX_PREC_MIXED)
+    return fail(EXX_EUNSUPPORTED, "build_K_spin: only the binary64 build takes two spins");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
+  const HostPlan& hp = plan->hp;
+  const int64_t ds = hp.d_size, ne = std::max<int64_t>(1, hp.e_total);
+  if (!plan->spin_E1) {
+    HIP_TRY(hipMalloc((void**)&plan->spin_E1, sizeof(double) * ne));
+    plan->allocs.push_back(plan->spin_E1);
+    HIP_TRY(hipMalloc((void**)&plan->spin_H1, sizeof(double) * ne));
+    plan->allocs.push_back(plan->spin_H1);
+    plan->dev_bytes += 2 * (int64_t)sizeof(double) * ne;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  DevPlan& d = plan->d;
+  double* const E0 = d.E;
+  double* const H0 = d.H;
+  const int n_e = (int)hp.e_items.size();
+  stage_mark(plan, 0, st);
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
+  hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, plan->d);
+  stage_mark(plan, 1, st);
+  launch_rowD(plan, D, rowd_E(plan), n_e, st);
+  d.E = plan->spin_E1;
+  launch_rowD(plan, D + ds, rowd_E(plan), n_e, st);
+  d.E = E0;
+  stage_mark(plan, 2, st);
+  launch_H_lists<double, 2>(plan, V, D,
+                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, ds, plan->spin_E1,
+                                   plan->spin_H1},
+                            (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
+  stage_mark(plan, 3, st);
+  stage_mark(plan, 4, st);
+  launch_T2(plan, V, K, st);
+  d.E = plan->spin_E1;
+  launch_T2(plan, V, K + ds, st);
+  d.E = E0;
+  stage_mark(plan, 5, st);
+  stage_mark(plan, 6, st);
+  launch_final(plan, K, st);
+  d.H = plan->spin_H1;
+  launch_final(plan, K + ds, st);
+  d.H = H0;
+  stage_mark(plan, 7, st);
+  HIP_TRY(hipGetLastError());
+  int rc = EXX_OK;
+  if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
   stage_mark(plan, 8, st);
   return rc;
 }

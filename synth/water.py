@@ -48,7 +48,8 @@ D_DECAY = 2.0          # A, D ~ exp(-r / D_DECAY)
 V_GAUSS_2S2 = 8.0      # A^2, V ~ exp(-r^2 / V_GAUSS_2S2)  (2 * 2.0^2)
 L_RANK = 40            # inner dimension of the per-species V factors
 
-_KIND_GEOM, _KIND_C, _KIND_D, _KIND_V, _KIND_BATCH = 1, 2, 3, 4, 5
+_KIND_GEOM, _KIND_C, _KIND_D, _KIND_V, _KIND_BATCH, _KIND_SPIN = 1, 2, 3, 4, 5, 6
+SPIN_POLARIZATION = 0.3   # weight m of the spin-difference matrix S in D^0, D^1 = (D +- m S) / 2
 
 OH_BOND = 0.96
 HOH_ANGLE = math.radians(104.5)
@@ -347,6 +348,46 @@ def make_inputs(system, layout=None, zero_D=False):
             Dm[ia:ia + nb[sA], ib:ib + nb[sB]] = dblk
             Dm[ib:ib + nb[sB], ia:ia + nb[sA]] = dblk.T
     return Inputs(system, layout, C, V, D)
+
+
+def spin_densities(inputs, polarization=SPIN_POLARIZATION):
+    """Two collinear-spin density matrices, shape (2, d_size):
+    D^0 = (D + m S) / 2 and D^1 = (D - m S) / 2 with m = polarization.
+
+    S, a spin-difference (magnetisation-like) matrix, follows the D recipe:
+    the same block pattern, symmetry and exp(-r / 2.0) decay, drawn from its
+    own keyed streams, so D^0 + D^1 = D exactly (up to one rounding)."""
+    system, layout = inputs.system, inputs.layout
+    sp, lab, pos = system.species, system.labels, system.pos
+    nb = system.basis_table
+    seeds = getattr(system, "cluster_seeds", None)
+    atom_sys = np.zeros(system.n_atoms, dtype=np.int64)
+    for s in range(system.n_systems):
+        atom_sys[system.sys_off[s]:system.sys_off[s + 1]] = s
+    S = np.zeros(layout.d_size)
+    for p in range(layout.n_pairs):
+        A, B = int(layout.pair_a[p]), int(layout.pair_b[p])
+        sA, sB = int(sp[A]), int(sp[B])
+        seed = system.seed if seeds is None else seeds[atom_sys[A]]
+        so = int(layout.sys_bas_off[atom_sys[A]])
+        n_s = int(layout.sys_nbas[atom_sys[A]])
+        ia, ib = int(layout.bas_off[A]), int(layout.bas_off[B])
+        if A == B:
+            blk = _sym_upper(_rng(seed, _KIND_SPIN, lab[A], lab[A]).normal(size=(nb[sA], nb[sA])))
+        else:
+            d = pos[A] - pos[B]
+            r = math.sqrt(float(d @ d))
+            flip = lab[A] > lab[B]
+            la, lb = (lab[B], lab[A]) if flip else (lab[A], lab[B])
+            s1, s2 = (sB, sA) if flip else (sA, sB)
+            blk = _rng(seed, _KIND_SPIN, la, lb).normal(size=(nb[s1], nb[s2])) * math.exp(-r / D_DECAY)
+            if flip:
+                blk = blk.T
+        Sm = S[so:so + n_s * n_s].reshape(n_s, n_s)
+        Sm[ia:ia + nb[sA], ib:ib + nb[sB]] = blk
+        Sm[ib:ib + nb[sB], ia:ia + nb[sA]] = blk.T
+    m = float(polarization)
+    return np.stack([0.5 * (inputs.D + m * S), 0.5 * (inputs.D - m * S)])
 
 
 # ----------------------------------------------------------------------------

@@ -369,6 +369,33 @@ def pin_screening(seed=13):
     return ok, "screened pair sets equal"
 
 
+def pin_spin(seed=14):
+    """Collinear spin: with D^0 = D^1 = D/2 each K^s is K(D)/2 and the spin
+    energy equals the closed-shell E_x of D; for unequal spins K^0 + K^1 =
+    K(D^0 + D^1) (linearity in D) and the energy is -1/2 sum_s <K^s, D^s>
+    evaluated from the 4-index tensor, without K."""
+    sysm = synth.water_cluster(2, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    K, e_cs, _ = O.k_4index(inp)
+    half = [0.5 * inp.D, 0.5 * inp.D]
+    Kh = O.k_spin(inp, half, route="4index")
+    n = Dd.shape[0]
+    e_half = O.spin_exchange_energy(Kh, [x.reshape(n, n) for x in half])
+    rng = np.random.default_rng(seed)
+    S = rng.normal(size=(n, n))
+    S = (S + S.T) * (np.abs(Dd) > 0)
+    D0 = 0.5 * (Dd + 0.4 * S)
+    D1 = Dd - D0
+    Ku = O.k_spin(inp, [D0.ravel(), D1.ravel()], route="eigen")
+    B = np.einsum("aij,ab->bij", C3, Vd)                 # sum_mu C^mu_ij V_{mu nu}
+    e_direct = sum(-0.5 * float(np.einsum("aij,akl,ik,jl->", C3, B, Dx, Dx, optimize=True))
+                   for Dx in (D0, D1))
+    e_spin = O.spin_exchange_energy(Ku, [D0, D1])
+    r = max(rel(Kh[0], 0.5 * K), rel(Kh[1], 0.5 * K), rel(Ku[0] + Ku[1], K))
+    ok = r < TOL and abs(e_half - e_cs) <= TOL * abs(e_cs) and abs(e_spin - e_direct) <= TOL * abs(e_direct)
+    return ok, f"K {r:.1e}, E(D/2, D/2) {e_half:.12e} vs {e_cs:.12e}, E {e_spin:.12e} vs {e_direct:.12e}"
+
+
 ALL_PINS = {
     "screening": pin_screening,
     "rank1_4index": lambda: pin_rank1_closed_form("4index"),
@@ -387,4 +414,5 @@ ALL_PINS = {
     "dD_minus_half_K": pin_dD_is_minus_half_K,
     "force_invariants": pin_force_invariants,
     "fd_forces": pin_fd_forces,
+    "spin": pin_spin,
 }

@@ -1,0 +1,124 @@
+"""Collinear spin (build_K_spin) against the CPU oracle, and against the
+one-density build on each spin's density matrix."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exx_oracle as O
+from tests.gpu_util import device_inputs, relmax, system_block
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_K = 1e-10
+TOL_E = 1e-10
+
+
+@pytest.fixture(scope="module")
+def exx():
+    import paper_2403_10343_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def spin_build(plan, inp, Ds):
+    dev = "cuda:0"
+    C, V, _ = device_inputs(inp, torch)
+    D2 = torch.from_numpy(np.ascontiguousarray(Ds.reshape(-1))).to(dev)
+    n = plan.info["d_size"]
+    K2 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    Ex = torch.empty(plan.n_systems, dtype=torch.float64, device=dev)
+    plan.build_K_spin(C, V, D2, K2, Ex)
+    torch.cuda.synchronize()
+    return K2.cpu().numpy().reshape(2, n), Ex.cpu().numpy()
+
+
+def one_density_build(plan, inp, D):
+    dev = "cuda:0"
+    C, V, _ = device_inputs(inp, torch)
+    Dd = torch.from_numpy(np.ascontiguousarray(D)).to(dev)
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=dev)
+    plan.build_K(C, V, Dd, K)
+    torch.cuda.synchronize()
+    return K.cpu().numpy()
+
+
+@pytest.mark.parametrize("n_mol,seed", [(1, 3), (2, 4), (8, 5)])
+def test_spin_clusters_match_oracle(exx, n_mol, seed):
+    sysm = synth.water_cluster(n_mol, seed)
+    print("spin cluster", n_mol, flush=True)
+    inp = synth.make_inputs(sysm)
+    Ds = synth.spin_densities(inp)
+    plan = exx.Plan.for_system(sysm)
+    K2, Ex = spin_build(plan, inp, Ds)
+    Ko = O.k_spin(inp, Ds)
+    for s in range(2):
+        Kg = system_block(K2[s], inp.layout, 0)
+        assert relmax(Kg, Ko[s]) < TOL_K
+        assert np.array_equal(Kg, Kg.T)
+    n = Ko[0].shape[0]
+    Eo = O.spin_exchange_energy(Ko, [x.reshape(n, n) for x in Ds])
+    assert abs(Ex[0] - Eo) < TOL_E * abs(Eo)
+
+
+def test_spin_config1_4index(exx):
+    inp = synth.make_inputs(synth.config(1))
+    Ds = synth.spin_densities(inp, polarization=0.7)
+    K2, Ex = spin_build(exx.Plan.for_system(inp.system), inp, Ds)
+    Ko = O.k_spin(inp, Ds, route="4index")
+    for s in range(2):
+        assert relmax(system_block(K2[s], inp.layout, 0), Ko[s]) < TOL_K
+    n = Ko[0].shape[0]
+    Eo = O.spin_exchange_energy(Ko, [x.reshape(n, n) for x in Ds])
+    assert abs(Ex[0] - Eo) < TOL_E * abs(Eo)
+
+
+def test_spin_uneven_batch(exx):
+    """A plan over several clusters of different sizes: every cluster's K^s
+    and E_x against the oracle."""
+    sysm = synth.cluster_batch(4, batch_seed=7, n_min=2, n_max=12)
+    print("spin batch", sysm.n_systems, flush=True)
+    inp = synth.make_inputs(sysm)
+    Ds = synth.spin_densities(inp)
+    K2, Ex = spin_build(exx.Plan.for_system(sysm), inp, Ds)
+    for c in range(sysm.n_systems):
+        Ko = O.k_spin(inp, Ds, s=c)
+        for s in range(2):
+            assert relmax(system_block(K2[s], inp.layout, c), Ko[s]) < TOL_K
+        Db = [system_block(x, inp.layout, c) for x in Ds]
+        Eo = O.spin_exchange_energy(Ko, Db)
+        assert abs(Ex[c] - Eo) < TOL_E * abs(Eo)
+
+
+def test_spin_equals_one_density_builds_768(exx):
+    """On the 768-atom box: K^s of the two-spin build equals build_K on D^s
+    bit for bit (the shared V-stage pass keeps every sum in the same order),
+    and with D^0 = D^1 = D/2 the spin E_x is the one-density E_x of D."""
+    sysm = synth.config(2)
+    print("spin 768 atoms", flush=True)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    Ds = synth.spin_densities(inp)
+    K2, Ex = spin_build(plan, inp, Ds)
+    for s in range(2):
+        assert np.array_equal(K2[s], one_density_build(plan, inp, Ds[s]))
+    half = np.stack([0.5 * inp.D, 0.5 * inp.D])
+    Kh, Eh = spin_build(plan, inp, half)
+    C, V, D = device_inputs(inp, torch)
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+    E1 = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    plan.build_K(C, V, D, K, E1)
+    torch.cuda.synchronize()
+    assert np.array_equal(Kh[0], 0.5 * K.cpu().numpy())
+    assert abs(Eh[0] - E1.item()) <= 1e-13 * abs(E1.item())
+
+
+def test_spin_rejects_mixed(exx):
+    sysm = synth.water_cluster(1, 1)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    with pytest.raises(exx.ExxError):
+        spin_build_mixed = torch.zeros(2 * plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+        C, V, _ = device_inputs(inp, torch)
+        plan.build_K_spin(C, V, spin_build_mixed, torch.empty_like(spin_build_mixed),
+                          precision=exx.PREC_MIXED)

@@ -27,6 +27,9 @@ MUTATIONS = {
     "rows_missing_transpose_term": ('Ki[sj] += np.einsum("nkl,nk->l", part, yQ[:, sq])', "pass"),
     "eigen_missing_lambda": ("Ul = U * lam[None, None, :]", "Ul = U"),
     "screening_strict": ("a, b = np.nonzero(np.triu(r2 <= rc2))", "a, b = np.nonzero(np.triu(r2 < 0.81 * rc2))"),
+    "spin_energy_factor": ("return -0.5 * sum(float(np.sum(K * D))", "return -0.25 * sum(float(np.sum(K * D))"),
+    "spin_ignores_D": ("return [f(with_density(inputs, D), s) for D in D_spin]",
+                       "return [f(inputs, s) for D in D_spin]"),
 }
 
 
