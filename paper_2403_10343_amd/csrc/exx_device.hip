@@ -126,8 +126,9 @@ constexpr int MAX_PROFILED = 512;
 enum { TUNE_E = 0, TUNE_T2 = 1, TUNE_Y = 2, N_TUNE = 3, N_CAND = 3 };
 static const int kTuneCands[N_TUNE] = {2, 3, 2};
 
-static size_t t2_lds_bytes(int smax, size_t esize, int cols, int waves) {
-  return std::max((size_t)2 * smax * (cols + 1) * esize, (size_t)waves * 4 * 64 * sizeof(double));
+// T_Q and nsp E_P column chunks, or the nsp fixed-order reduction buffers
+static size_t t2_lds_bytes(int smax, size_t esize, int cols, int waves, int nsp = 1) {
+  return std::max((size_t)(1 + nsp) * smax * (cols + 1) * esize, (size_t)nsp * waves * 4 * 64 * sizeof(double));
 }
 
 struct exx_plan_s {
@@ -150,6 +151,7 @@ struct exx_plan_s {
   size_t h_lds32 = 0, t2_lds32 = 0; // the same for the binary32 kernels
   int h_vbase = 0, h_dbase = 0;     // element offsets of V and D in k_H's LDS
   int h_smax_t2 = 1;                // largest n_aux * n_basis (T2 staging)
+  int lds_max = 0;                  // LDS bytes a workgroup may use on the plan's device
   std::vector<void*> mixed_allocs;  // device copies of the mixed-precision lists
   int64_t mixed_bytes = 0;
   bool mixed_uploaded = false;
@@ -781,11 +783,14 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
 constexpr int T2_COLS = 8;               // column chunk of the backward pair kernel
 constexpr int T2_PITCH = T2_COLS + 1;
 
-// COLS: columns per staged chunk (a tuning choice: 4 or 8)
-template <int NT, int NS, typename R, int COLS, int WAVES>
+// COLS: columns per staged chunk (a tuning choice: 4 or 8).  NSP = 2 (collinear spin): F is
+// formed once per column and contracted with E_P^0 (d.E) and E_P^1 (E1); K^1 sits d_spin
+// after K^0.
+template <int NT, int NS, typename R, int COLS, int WAVES, int NSP>
 __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V, double* __restrict__ K,
                                             DevPlan d, const int* __restrict__ items, int n_items,
-                                            int n_padded, int item_base) {
+                                            int n_padded, int item_base, const double* __restrict__ E1,
+                                            int64_t d_spin) {
   typedef typename Mf<R>::acc A4;
   extern __shared__ double sraw[];
   R* sm = reinterpret_cast<R*>(sraw);
@@ -805,10 +810,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   const int* cg = d.col1g + d.col1g_off[Q];
   const int* m2P = d.map2 + d.map_off[P];
   const double* TQ = d.T + d.t_off[Q];
-  const double* EP = d.E + d.e_off[P];
+  const double* EPs[NSP];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp) EPs[sp] = (sp == 0 ? d.E : E1) + d.e_off[P];
   constexpr int PITCH = COLS + 1, RSTEP = 64 * WAVES / COLS, CPW = COLS / WAVES;
   R* sT = sm;                                  // [sQ][PITCH]
-  R* sE = sm + (size_t)sQ * PITCH;             // [sP][PITCH]
+  R* sE = sm + (size_t)sQ * PITCH;             // [NSP][sP][PITCH]
+  const size_t espin = (size_t)sP * PITCH;
   R va[NT][NS];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -824,7 +832,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   const int r0 = threadIdx.x / COLS;
   constexpr int RT = (NS * 4 * NB_MAX + RSTEP - 1) / RSTEP;   // rows of T_Q per thread at most
   constexpr int RE = (NT * 16 * NB_MAX + RSTEP - 1) / RSTEP;  // rows of E_P per thread at most
-  R pt[RT], pe[RE];
+  R pt[RT], pe[NSP][RE];
   auto fetch = [&](int l0) {
     const int l = l0 + tc;
     const bool cv = l < nQ;
@@ -837,14 +845,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
       pt[i] = ok ? (R)x : (R)0;
     }
 #pragma unroll
-    for (int i = 0; i < RE; ++i) {
-      const int r = r0 + RSTEP * i;
-      const bool ok = cv && r < sP;
-      const double x = EP[ok ? (size_t)r * mP + ce : 0];
-      pe[i] = ok ? (R)x : (R)0;
-    }
+    for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+      for (int i = 0; i < RE; ++i) {
+        const int r = r0 + RSTEP * i;
+        const bool ok = cv && r < sP;
+        const double x = EPs[sp][ok ? (size_t)r * mP + ce : 0];
+        pe[sp][i] = ok ? (R)x : (R)0;
+      }
   };
-  A4 acc = A4{0, 0, 0, 0};
+  A4 acc[NSP];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp) acc[sp] = A4{0, 0, 0, 0};
   fetch(0);
   for (int l0 = 0; l0 < nQ; l0 += COLS) {
     __syncthreads();
@@ -854,10 +866,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
       if (r < sQ) sT[r * PITCH + tc] = pt[i];
     }
 #pragma unroll
-    for (int i = 0; i < RE; ++i) {
-      const int r = r0 + RSTEP * i;
-      if (r < sP) sE[r * PITCH + tc] = pe[i];
-    }
+    for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+      for (int i = 0; i < RE; ++i) {
+        const int r = r0 + RSTEP * i;
+        if (r < sP) sE[sp * espin + r * PITCH + tc] = pe[sp][i];
+      }
     __syncthreads();
     if (l0 + COLS < nQ) fetch(l0 + COLS);
 #pragma unroll
@@ -883,8 +897,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
             // element v of F holds aux row mu of P; the E operand uses the same mu as k
             const int mu = 16 * t + Mf<R>::row(lk, v);
             const bool ok = iv && mu < aP;
-            const R x = sE[(ok ? (mu * bP + lr) * PITCH : 0) + c];
-            acc = Mf<R>::mma(ok ? x : (R)0, F[v], acc);
+#pragma unroll
+            for (int sp = 0; sp < NSP; ++sp) {
+              const R x = sE[sp * espin + (ok ? (mu * bP + lr) * PITCH : 0) + c];
+              acc[sp] = Mf<R>::mma(ok ? x : (R)0, F[v], acc[sp]);
+            }
           }
         }
       }
@@ -893,16 +910,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   // fixed-order reduction of the wavefront partials (binary64)
   __syncthreads();
   double* red = sraw;
-  for (int v = 0; v < 4; ++v) red[(wv * 4 + v) * 64 + L] = (double)acc[v];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp)
+    for (int v = 0; v < 4; ++v) red[((sp * WAVES + wv) * 4 + v) * 64 + L] = (double)acc[sp][v];
   __syncthreads();
-  if (wv == 0) {
+  if (wv < NSP) {
+    const int sp = wv;   // wavefront sp writes spin sp
     double out[4];
     for (int v = 0; v < 4; ++v) {
-      double x = red[v * 64 + L];
-      for (int w2 = 1; w2 < WAVES; ++w2) x += red[(w2 * 4 + v) * 64 + L];
+      double x = red[((sp * WAVES) * 4 + v) * 64 + L];
+      for (int w2 = 1; w2 < WAVES; ++w2) x += red[((sp * WAVES + w2) * 4 + v) * 64 + L];
       out[v] = x;
     }
-    double* Ks = K + d.sys_d_off[s];
+    double* Ks = K + sp * d_spin + d.sys_d_off[s];
     const int bPo = d.bo[P], bQo = d.bo[Q];
     for (int v = 0; v < 4; ++v) {
       const int i = Mf<R>::row(lk, v), k = lr;
@@ -1523,6 +1543,7 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out) {
       delete pl;
       return fail(EXX_EDEVICE, "exx_plan_create: cannot query the LDS size");
     }
+    pl->lds_max = lds_max;
     if (pl->t2_lds > (size_t)lds_max || pl->h_lds + 8192 > (size_t)lds_max) {   // static LDS of k_H < 8 KB
       delete pl;
       return fail(EXX_EUNSUPPORTED, "exx_plan_create: the largest n_aux * n_basis needs more LDS than a workgroup has");
@@ -1697,48 +1718,54 @@ static void launch_H_mixed(exx_plan plan, const double* V, const double* D, hipS
 }
 
 extern "C++" {
-template <int NT, typename R, int COLS, int WAVES>
+template <int NT, typename R, int COLS, int WAVES, int NSP>
 static void launch_T2_nt(exx_plan plan, int nsc, const double* V, double* K, const int* items, int beg, int n,
                          hipStream_t st) {
   const int np_ = (n + 7) / 8 * 8;
   DevPlan& d = plan->d;
-  const size_t lds = t2_lds_bytes(plan->h_smax_t2, sizeof(R), COLS, WAVES);
+  const size_t lds = t2_lds_bytes(plan->h_smax_t2, sizeof(R), COLS, WAVES, NSP);
   const dim3 g(np_), b(64 * WAVES);
+  const double* E1 = plan->spin_E1;
+  const int64_t ds = plan->hp.d_size;
   switch (nsc) {
-    case 4: hipLaunchKernelGGL((k_T2<NT, 4, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
-    case 8: hipLaunchKernelGGL((k_T2<NT, 8, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
-    case 10: hipLaunchKernelGGL((k_T2<NT, 10, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
-    case 12: hipLaunchKernelGGL((k_T2<NT, 12, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
-    default: hipLaunchKernelGGL((k_T2<NT, 16, R, COLS, WAVES>), g, b, lds, st, V, K, d, items, n, np_, beg); break;
+#define T2NS(NS) case NS: hipLaunchKernelGGL((k_T2<NT, NS, R, COLS, WAVES, NSP>), g, b, lds, st, V, K, d, items, n, np_, beg, E1, ds); break;
+    T2NS(4) T2NS(8) T2NS(10) T2NS(12)
+#undef T2NS
+    default: hipLaunchKernelGGL((k_T2<NT, 16, R, COLS, WAVES, NSP>), g, b, lds, st, V, K, d, items, n, np_, beg, E1, ds); break;
   }
 }
 
-template <typename R, int COLS, int WAVES>
+template <typename R, int COLS, int WAVES, int NSP>
 static void launch_T2_cols(exx_plan plan, const T2Class& c, const double* V, double* K, const int* items, int n,
                            hipStream_t st) {
   switch (c.nt) {
-    case 1: launch_T2_nt<1, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    case 2: launch_T2_nt<2, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    case 3: launch_T2_nt<3, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
-    default: launch_T2_nt<4, R, COLS, WAVES>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 1: launch_T2_nt<1, R, COLS, WAVES, NSP>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 2: launch_T2_nt<2, R, COLS, WAVES, NSP>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    case 3: launch_T2_nt<3, R, COLS, WAVES, NSP>(plan, c.ns, V, K, items, c.beg, n, st); break;
+    default: launch_T2_nt<4, R, COLS, WAVES, NSP>(plan, c.ns, V, K, items, c.beg, n, st); break;
   }
 }
 
-template <typename R>
+template <typename R, int NSP = 1>
 static void launch_T2_class(exx_plan plan, const T2Class& c, const double* V, double* K, const int* items,
                             hipStream_t st) {
   const int n = c.end - c.beg;
   if (n <= 0) return;
   switch (plan->tune[TUNE_T2]) {
-    case 0: launch_T2_cols<R, 4, 4>(plan, c, V, K, items, n, st); break;
-    case 1: launch_T2_cols<R, 8, 4>(plan, c, V, K, items, n, st); break;
-    default: launch_T2_cols<R, 8, 8>(plan, c, V, K, items, n, st); break;
+    case 0: launch_T2_cols<R, 4, 4, NSP>(plan, c, V, K, items, n, st); break;
+    case 1: launch_T2_cols<R, 8, 4, NSP>(plan, c, V, K, items, n, st); break;
+    default: launch_T2_cols<R, 8, 8, NSP>(plan, c, V, K, items, n, st); break;
   }
 }
 }  // extern "C++"
 
 // one launch per shape class (aux tiles of P, nu steps of Q) and precision
 // (mixed: the classes of one precision only)
+// spin: both spin density matrices in one pass (binary64 lists; K holds K^0 then K^1)
+static void launch_T2_spin(exx_plan plan, const double* V, double* K, hipStream_t st) {
+  for (const T2Class& c : plan->hp.t2_classes) launch_T2_class<double, 2>(plan, c, V, K, plan->d.t2_items, st);
+}
+
 static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st, bool mixed = false, int prec = 0) {
   const HostPlan& hp = plan->hp;
   const DevPlan& d = plan->d;
@@ -1861,6 +1888,13 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
   const HostPlan& hp = plan->hp;
   const int64_t ds = hp.d_size, ne = std::max<int64_t>(1, hp.e_total);
+  {
+    static const int t2c[3][2] = {{4, 4}, {8, 4}, {8, 8}};
+    const int* cw = t2c[std::min(std::max(plan->tune[TUNE_T2], 0), 2)];
+    if (t2_lds_bytes(plan->h_smax_t2, sizeof(double), cw[0], cw[1], 2) > (size_t)plan->lds_max)
+      return fail(EXX_EUNSUPPORTED, "build_K_spin: the largest n_aux * n_basis needs more LDS than a workgroup has "
+                                    "for two spins in the T2 tile shape chosen");
+  }
   if (!plan->spin_E1) {
     HIP_TRY(hipMalloc((void**)&plan->spin_E1, sizeof(double) * ne));
     plan->allocs.push_back(plan->spin_E1);
@@ -1888,10 +1922,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
                             (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
   stage_mark(plan, 3, st);
   stage_mark(plan, 4, st);
-  launch_T2(plan, V, K, st);
-  d.E = plan->spin_E1;
-  launch_T2(plan, V, K + ds, st);
-  d.E = E0;
+  launch_T2_spin(plan, V, K, st);
   stage_mark(plan, 5, st);
   stage_mark(plan, 6, st);
   launch_final(plan, K, st);
