@@ -34,13 +34,13 @@ CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "c5127c6c4c91743c",
+    "sources": "6ef0046df050fc25",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 25.280e9 + 4.150e9, ("fp64", "T2"): 35.342e9 + 0.025e9,
-              ("fp64", "final"): 10.243e9 + 4.280e9, ("fp64", "E"): 2.756e9 + 2.476e9},
+    "bytes": {("fp64", "H"): 25.244e9 + 4.147e9, ("fp64", "T2"): 35.724e9 + 0.025e9,
+              ("fp64", "final"): 10.244e9 + 4.280e9, ("fp64", "E"): 2.756e9 + 2.476e9},
 }
-KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double>", "H32": "k_H<U, float>",
-                   "T2": "k_T2<NT, NS, double>", "T2_32": "k_T2<NT, NS, float>",
+KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>", "H32": "k_H<U, float, 1>",
+                   "T2": "k_T2<NT, NS, double, COLS, WAVES, 1>", "T2_32": "k_T2<NT, NS, float, COLS, WAVES, 1>",
                    "final": "k_Y + k_symreduce", "energy": "k_energy_part + k_energy_sum"}
 
 
@@ -197,6 +197,8 @@ def main():
                     help="also time forward + exchange_backward (dE/dC, dE/dV, dE/dD, forces); 0 = skip")
     ap.add_argument("--spin-steps", type=int, default=5,
                     help="also time the collinear-spin build (two density matrices, FP64); 0 = skip")
+    ap.add_argument("--two-kernel-steps", type=int, default=5,
+                    help="also time two Coulomb matrices in one call (FP64); 0 = skip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
@@ -320,6 +322,27 @@ def main():
             "vs_two_one_density_builds": 2 * dt64 / ts,
             "stage_ms": {n_: float(x) for n_, x in zip(names, sst / max(nrec, 1))},
             "E_x": float(Ex[0].item()),
+        }
+    if args.two_kernel_steps > 0:
+        V2 = torch.from_numpy(synth.short_range_V(inp)).to(dev)
+        K2 = torch.empty(2 * plan.info["d_size"], dtype=torch.float64, device=dev)
+        E2 = torch.empty(2 * plan.n_systems, dtype=torch.float64, device=dev)
+        plan.build_K_two_kernels(C, V, V2, D, K2, E2)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        tk0 = time.perf_counter()
+        for _ in range(args.two_kernel_steps):
+            plan.build_K_two_kernels(C, V, V2, D, K2, E2)
+        torch.cuda.synchronize()
+        tk = (time.perf_counter() - tk0) / args.two_kernel_steps
+        kst, nrec = plan.stage_times()
+        plan.set_profiling(False)
+        out["two_kernels"] = {
+            "workload": wname + " (two Coulomb matrices: V and a shorter-range V2, one D, FP64)",
+            "ms_per_build": 1e3 * tk, "builds_per_s": 1.0 / tk,
+            "vs_two_one_kernel_builds": 2 * dt64 / tk,
+            "stage_ms": {n_: float(x) for n_, x in zip(names, kst / max(nrec, 1))},
+            "E_x": [float(x) for x in E2.cpu().numpy()],
         }
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)

@@ -146,6 +146,19 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D,
 int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D,
                  int precision, double* K, double* Ex, void* stream);
 
+/* Two Coulomb kernels in one call (Sec. "Introduction": functionals that mix
+ * a full-range and a screened exchange part need one exchange matrix per
+ * Coulomb kernel): K^a = sum C V^a C D for V^0 = V and V^1 = V2, where V2 is a
+ * second Coulomb matrix in the pair layout of V.
+ * K: device output, 2 * d_size doubles, K^0 then K^1.  Ex: NULL, or device
+ * [2 * n_systems]: E_x of K^0 for every system, then of K^1 (each as in
+ * exchange_energy).  The repack of C and E = M D (Eq. temp_E) are shared by
+ * both kernels; the V stage, T2 and the final contraction run per kernel.
+ * precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns EXX_EUNSUPPORTED).
+ * Uses the second workspace of build_K_spin (allocated on first use). */
+int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2,
+                        const double* D, int precision, double* K, double* Ex, void* stream);
+
 /* Capture one build_K (these exact arrays, `precision` as in build_K) on
  * `stream` into a HIP graph owned by the plan, replacing any earlier one;
  * exx_graph_launch() replays it.  The arrays must stay valid while the graph is used.  The

@@ -34,6 +34,10 @@ is the definition above with D^s.  The paper does not write the spin energy
 either; the reading used is E_x = -1/2 sum_s sum_ik K^s_ik D^s_ik, which for
 D^0 = D^1 = D/2 is the closed-shell E_x above.
 
+Two Coulomb kernels (``k_two_kernels``): one exchange matrix per Coulomb
+matrix, K^a = sum C V^a C D, each by the same definition (Sec.
+"Introduction" motivates computing both in one call).
+
 Gradients (``gradients``) follow from E_x being quadratic in C and D and
 linear in V:  dE/dD = -1/2 K,  dE/dC^mu = -1/2 sum_nu V_{mu nu} D C^nu D,
 dE/dV_{mu nu} = -1/4 tr(C^mu D C^nu D); per stored layout entry the mirrored
@@ -297,6 +301,19 @@ def k_spin(inputs, D_spin, s=0, route="eigen"):
     matrix (D_spin: two flat arrays in the layout of inputs.D)."""
     f = {"eigen": k_eigen, "rows": k_full_rows, "4index": lambda i, s: k_4index(i, s)[0]}[route]
     return [f(with_density(inputs, D), s) for D in D_spin]
+
+
+def with_coulomb(inputs, V):
+    """A shallow copy of ``inputs`` whose (flat, pair-block) Coulomb matrix is V."""
+    out = copy.copy(inputs)
+    out.V = np.asarray(V, dtype=np.float64)
+    return out
+
+
+def k_two_kernels(inputs, V2, s=0, route="eigen"):
+    """[K(V), K(V2)] of system s for a second Coulomb matrix V2 in the layout of inputs.V."""
+    f = {"eigen": k_eigen, "rows": k_full_rows, "4index": lambda i, s: k_4index(i, s)[0]}[route]
+    return [f(inputs, s), f(with_coulomb(inputs, V2), s)]
 
 
 def spin_exchange_energy(K_spin, D_spin):

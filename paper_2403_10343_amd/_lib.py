@@ -52,7 +52,8 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pai
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
-           "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin")
+           "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
+           "build_K_two_kernels")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -73,6 +74,7 @@ def lib():
     L.exx_plan_neighbors.argtypes = [vp, vp, vp]
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.build_K_spin.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.build_K_two_kernels.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
@@ -185,6 +187,12 @@ class Plan:
         Ex (optional) gets -1/2 sum_s sum K^s D^s per system."""
         _check(lib().build_K_spin(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
                                   _stream(stream)))
+
+    def build_K_two_kernels(self, C, V, V2, D, K, Ex=None, precision=PREC_FP64, stream=None):
+        """Two Coulomb matrices V, V2 (same layout): K holds K^0 then K^1 (2 d_size);
+        Ex (optional, 2 n_systems) the E_x of each."""
+        _check(lib().build_K_two_kernels(self._h, _ptr(C), _ptr(V), _ptr(V2), _ptr(D), int(precision), _ptr(K),
+                                         _ptr(Ex), _stream(stream)))
 
     def exchange_energy(self, K, D, Ex, stream=None):
         _check(lib().exchange_energy(self._h, _ptr(K), _ptr(D), _ptr(Ex), _stream(stream)))

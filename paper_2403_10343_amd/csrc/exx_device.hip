@@ -1876,6 +1876,18 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   return rc;
 }
 
+// E and H' workspaces of a second result (build_K_spin, build_K_two_kernels), allocated once
+static int second_workspace(exx_plan plan) {
+  if (plan->spin_E1) return EXX_OK;
+  const int64_t ne = std::max<int64_t>(1, plan->hp.e_total);
+  HIP_TRY(hipMalloc((void**)&plan->spin_E1, sizeof(double) * ne));
+  plan->allocs.push_back(plan->spin_E1);
+  HIP_TRY(hipMalloc((void**)&plan->spin_H1, sizeof(double) * ne));
+  plan->allocs.push_back(plan->spin_H1);
+  plan->dev_bytes += 2 * (int64_t)sizeof(double) * ne;
+  return EXX_OK;
+}
+
 // Collinear spin: E^s = T D^s for both spins, then one V-stage pass for both (F shared), then
 // T2 and the final contraction per spin with E and H' pointed at that spin's workspace.
 int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
@@ -1887,7 +1899,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
     return fail(EXX_EUNSUPPORTED, "build_K_spin: only the binary64 build takes two spins");
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
   const HostPlan& hp = plan->hp;
-  const int64_t ds = hp.d_size, ne = std::max<int64_t>(1, hp.e_total);
+  const int64_t ds = hp.d_size;
   {
     static const int t2c[3][2] = {{4, 4}, {8, 4}, {8, 8}};
     const int* cw = t2c[std::min(std::max(plan->tune[TUNE_T2], 0), 2)];
@@ -1895,13 +1907,8 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
       return fail(EXX_EUNSUPPORTED, "build_K_spin: the largest n_aux * n_basis needs more LDS than a workgroup has "
                                     "for two spins in the T2 tile shape chosen");
   }
-  if (!plan->spin_E1) {
-    HIP_TRY(hipMalloc((void**)&plan->spin_E1, sizeof(double) * ne));
-    plan->allocs.push_back(plan->spin_E1);
-    HIP_TRY(hipMalloc((void**)&plan->spin_H1, sizeof(double) * ne));
-    plan->allocs.push_back(plan->spin_H1);
-    plan->dev_bytes += 2 * (int64_t)sizeof(double) * ne;
-  }
+  const int rcw = second_workspace(plan);
+  if (rcw != EXX_OK) return rcw;
   hipStream_t st = (hipStream_t)stream;
   DevPlan& d = plan->d;
   double* const E0 = d.E;
@@ -1933,6 +1940,53 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   HIP_TRY(hipGetLastError());
   int rc = EXX_OK;
   if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
+  stage_mark(plan, 8, st);
+  return rc;
+}
+
+// Two Coulomb matrices: repack and E = T D once, then the V stage, T2 and the final
+// contraction per Coulomb matrix (H' of the second in the second workspace).  A V-stage pass
+// computing both at once (shared T_Q staging and D operands) measured slower than two passes
+// (49.4 against 2 x 22.0 ms at 768 atoms): the V operands, whose loads bound the stage, are
+// not shared, and the doubled accumulators halve the occupancy.
+int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2, const double* D,
+                        int precision, double* K, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "build_K_two_kernels: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "build_K_two_kernels: host-only plan");
+  if (!C || !V || !V2 || !D || !K) return fail(EXX_EINVAL, "build_K_two_kernels: NULL array");
+  if (precision == EXX_PREC_MIXED)
+    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: only the binary64 build takes two Coulomb matrices");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_two_kernels: unknown precision");
+  const int rcw = second_workspace(plan);
+  if (rcw != EXX_OK) return rcw;
+  const HostPlan& hp = plan->hp;
+  const int64_t ds = hp.d_size;
+  hipStream_t st = (hipStream_t)stream;
+  DevPlan& d = plan->d;
+  double* const H0 = d.H;
+  stage_mark(plan, 0, st);
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
+  launch_repack_E(plan, C, D, st, true);
+  stage_mark(plan, 2, st);
+  launch_H(plan, V, D, 2.0, H_WRITE, st);
+  d.H = plan->spin_H1;
+  launch_H(plan, V2, D, 2.0, H_WRITE, st);
+  d.H = H0;
+  stage_mark(plan, 3, st);
+  stage_mark(plan, 4, st);
+  launch_T2(plan, V, K, st);
+  launch_T2(plan, V2, K + ds, st);
+  stage_mark(plan, 5, st);
+  stage_mark(plan, 6, st);
+  launch_final(plan, K, st);
+  d.H = plan->spin_H1;
+  launch_final(plan, K + ds, st);
+  d.H = H0;
+  stage_mark(plan, 7, st);
+  HIP_TRY(hipGetLastError());
+  int rc = EXX_OK;
+  if (Ex) rc = launch_energy(plan, K, D, Ex, st);
+  if (Ex && rc == EXX_OK) rc = launch_energy(plan, K + ds, D, Ex + hp.n_sys, st);
   stage_mark(plan, 8, st);
   return rc;
 }

@@ -46,6 +46,7 @@ O, H = 0, 1
 C_DECAY = 1.5          # A, C ~ exp(-r / C_DECAY)
 D_DECAY = 2.0          # A, D ~ exp(-r / D_DECAY)
 V_GAUSS_2S2 = 8.0      # A^2, V ~ exp(-r^2 / V_GAUSS_2S2)  (2 * 2.0^2)
+V_SR_2S2 = 2.0         # A^2, the second (shorter-range) Coulomb matrix: exp(-r^2 / V_SR_2S2)
 L_RANK = 40            # inner dimension of the per-species V factors
 
 _KIND_GEOM, _KIND_C, _KIND_D, _KIND_V, _KIND_BATCH, _KIND_SPIN = 1, 2, 3, 4, 5, 6
@@ -348,6 +349,30 @@ def make_inputs(system, layout=None, zero_D=False):
             Dm[ia:ia + nb[sA], ib:ib + nb[sB]] = dblk
             Dm[ib:ib + nb[sB], ia:ia + nb[sA]] = dblk.T
     return Inputs(system, layout, C, V, D)
+
+
+def short_range_V(inputs, two_s2=V_SR_2S2):
+    """A second, shorter-range Coulomb matrix in the layout of inputs.V:
+    block (A, B) = exp(-r_AB^2 / two_s2) * (L_s(A) L_s(B)^T) with the same
+    per-species factors L as V (SPD before screening, like V)."""
+    system, layout = inputs.system, inputs.layout
+    sp, pos = system.species, system.pos
+    na = system.aux_table
+    seeds = getattr(system, "cluster_seeds", None)
+    atom_sys = np.zeros(system.n_atoms, dtype=np.int64)
+    for s in range(system.n_systems):
+        atom_sys[system.sys_off[s]:system.sys_off[s + 1]] = s
+    L = v_factors(system.seed, na)
+    V2 = np.empty(int(layout.v_off[-1]))
+    for p in range(layout.n_pairs):
+        A, B = int(layout.pair_a[p]), int(layout.pair_b[p])
+        sA, sB = int(sp[A]), int(sp[B])
+        Ls = L if seeds is None else v_factors(seeds[atom_sys[A]], na)
+        d = pos[A] - pos[B]
+        r2 = float(d @ d)
+        w = 1.0 if A == B else math.exp(-r2 / two_s2)
+        V2[int(layout.v_off[p]):int(layout.v_off[p + 1])] = (w * (Ls[sA] @ Ls[sB].T)).ravel()
+    return V2
 
 
 def spin_densities(inputs, polarization=SPIN_POLARIZATION):

@@ -396,6 +396,20 @@ def pin_spin(seed=14):
     return ok, f"K {r:.1e}, E(D/2, D/2) {e_half:.12e} vs {e_cs:.12e}, E {e_spin:.12e} vs {e_direct:.12e}"
 
 
+def pin_two_kernels(seed=15):
+    """Two Coulomb matrices: the second K against brute force over dense
+    arrays (C V2 C contracted with D by einsum), the first unchanged, and
+    K(V) + K(V2) = K(V + V2)."""
+    sysm = synth.water_cluster(2, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    inp2, _, Vd2, _ = random_problem(sysm, seed + 100)     # same layout, another V
+    K1, K2 = O.k_two_kernels(inp, inp2.V, route="4index")
+    Kb = np.einsum("aij,ab,bkl,jl->ik", C3, Vd2, C3, Dd, optimize=True)
+    Ks = O.k_two_kernels(inp, inp.V + inp2.V, route="eigen")[1]
+    r = max(rel(K2, Kb), rel(K1, O.k_4index(inp)[0]), rel(K1 + K2, Ks))
+    return r < TOL, f"{r:.1e}"
+
+
 ALL_PINS = {
     "screening": pin_screening,
     "rank1_4index": lambda: pin_rank1_closed_form("4index"),
@@ -415,4 +429,5 @@ ALL_PINS = {
     "force_invariants": pin_force_invariants,
     "fd_forces": pin_fd_forces,
     "spin": pin_spin,
+    "two_kernels": pin_two_kernels,
 }

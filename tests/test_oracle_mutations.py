@@ -28,6 +28,8 @@ MUTATIONS = {
     "eigen_missing_lambda": ("Ul = U * lam[None, None, :]", "Ul = U"),
     "screening_strict": ("a, b = np.nonzero(np.triu(r2 <= rc2))", "a, b = np.nonzero(np.triu(r2 < 0.81 * rc2))"),
     "spin_energy_factor": ("return -0.5 * sum(float(np.sum(K * D))", "return -0.25 * sum(float(np.sum(K * D))"),
+    "two_kernels_same_V": ("return [f(inputs, s), f(with_coulomb(inputs, V2), s)]",
+                           "return [f(inputs, s), f(inputs, s)]"),
     "spin_ignores_D": ("return [f(with_density(inputs, D), s) for D in D_spin]",
                        "return [f(inputs, s) for D in D_spin]"),
 }
