@@ -116,6 +116,14 @@ struct DevPlan {
   YTile* y_tiles;
   int64_t* y_off;
   double *T, *E, *H, *Y, *GD, *sC, *sV, *epart;
+  // The V-stage operands in MFMA lane order, rebuilt from V and D before every V stage:
+  // per canonical pair p and orientation o (0: P = pair_a, Q = pair_b; 1: swapped) at
+  // Vr + vr_off[2 p + o], [16-wide aux tile t of P][4-wide aux step q of Q][lane L] =
+  // V_PQ[16 t + L % 16][4 q + L / 16], and at Dr + dr_off[2 p + o], [basis step q of Q][lane L] =
+  // D_PQ[L % 16][L / 16 + 4 q] (zero outside the blocks).  Each MFMA operand is then one
+  // coalesced 512-byte row instead of a gather over 16 rows of V or D.
+  int64_t *vr_off, *dr_off;
+  double *Vr, *Dr;
 };
 
 constexpr int N_STAGE_EV = EXX_N_STAGES + 1;   // stage boundaries, start and end included
@@ -420,6 +428,37 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
   return (P <= Q) ? Vp[mu * aQ + nu] : Vp[nu * aP + mu];
 }
 
+// The V-stage operands in MFMA lane order (DevPlan::Vr, Dr), one workgroup per canonical
+// pair, both orientations.
+__global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, const double* __restrict__ D,
+                                                 DevPlan d) {
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const double* Vp = V + d.v_off[p];
+  const int s = d.atom_sys[A];
+  const int64_t ns = d.sys_n[s];
+  const double* Ds = D + d.sys_d_off[s];
+  for (int o = 0; o < (A == B ? 1 : 2); ++o) {
+    const int P = o ? B : A, Q = o ? A : B;
+    const int aP = d.na[P], aQ = d.na[Q], bP = d.nb[P], bQ = d.nb[Q];
+    const int nsq = (aQ + 3) / 4;
+    double* vr = d.Vr + d.vr_off[2 * p + o];
+    const int nv = (int)(d.vr_off[2 * p + o + 1] - d.vr_off[2 * p + o]);
+    for (int e = threadIdx.x; e < nv; e += 256) {
+      const int L = e & 63, tq = e >> 6, q = tq % nsq, t = tq / nsq;
+      const int mu = 16 * t + (L & 15), nu = 4 * q + (L >> 4);
+      vr[e] = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
+    }
+    double* dr = d.Dr + d.dr_off[2 * p + o];
+    const int nd = (int)(d.dr_off[2 * p + o + 1] - d.dr_off[2 * p + o]);
+    for (int e = threadIdx.x; e < nd; e += 256) {
+      const int L = e & 63, q = e >> 6;
+      const int j = L & 15, l = (L >> 4) + 4 * q;   // the f64 MFMA A-operand row of lane L, step q
+      dr[e] = (j < bP && l < bQ) ? Ds[(size_t)(d.bo[P] + j) * ns + d.bo[Q] + l] : 0.0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // stage 2: H'_P[(mu, j), c] for a group of consecutive atoms (its "units"
 // are the 16-wide aux tiles of the group atoms) and H_COLS columns c of the
@@ -465,7 +504,7 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
                                     const R* sD, const HUnits& un, const int* roff, int vr, int nU, const int* qp,
                                     const int64_t* qv, const double* V, const double* Ds, int64_t dsp, int64_t ns,
                                     int Q, int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
-                                    int lk) {
+                                    int lk, const DevPlan& d) {
   typedef typename Mf<R>::acc A4;
   static_assert(NSP == 1 || !HStage<R>::vd, "the LDS-staged binary32 kernel takes one density matrix");
   bool anyc = false;
@@ -504,28 +543,32 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
             da[0][q] = ok ? x : (R)0;
           }
         } else {
-          // branch-free: invalid lanes read the block's first element and discard it
-          const int P = un.P[u];
-          const double* Vp = V + qv[sl];
-          const bool pq = P <= Q;
+          // the lane-ordered copies: one coalesced row per MFMA step (steps past the
+          // blocks are zero)
+          const int pp = qp[sl], orient = un.P[u] <= Q ? 0 : 1;
+          const int nsq = (aQ + 3) >> 2, nlq = (bQ + 3) >> 2, L = lk * 16 + lr;
+          const double* vrow = d.Vr + d.vr_off[2 * pp + orient] + (size_t)(un.mu0[u] >> 4) * nsq * 64 + L;
 #pragma unroll
-          for (int q = 0; q < NS; ++q) {
-            const int nu = 4 * q + lk;
-            const bool ok = muv && nu < aQ;
-            const double x = Vp[ok ? (pq ? muB * aQ + nu : nu * aP + muB) : 0];
-            vb[q] = ok ? (R)x : (R)0;
-          }
+          for (int q = 0; q < NS; ++q) vb[q] = q < nsq ? (R)vrow[q * 64] : (R)0;
+          if constexpr (NSP == 1) {
+            const double* dr = d.Dr + d.dr_off[2 * pp + orient] + L;
 #pragma unroll
-          for (int sp = 0; sp < NSP; ++sp) {
-            const double* DPQ = Ds + sp * dsp + (size_t)un.bo[u] * ns + boQ;
+            for (int q = 0; q < NLR; ++q) da[0][q] = q < nlq ? (R)dr[q * 64] : (R)0;
+          } else {
+            // branch-free: invalid lanes read the block's first element and discard it
 #pragma unroll
-            for (int q = 0; q < NLR; ++q) {
-              const int l = Mf<R>::row(lk, q);
-              const bool ok = lr < bP && l < bQ;
-              const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
-              da[sp][q] = ok ? (R)x : (R)0;
+            for (int sp = 0; sp < NSP; ++sp) {
+              const double* DPQ = Ds + sp * dsp + (size_t)un.bo[u] * ns + boQ;
+#pragma unroll
+              for (int q = 0; q < NLR; ++q) {
+                const int l = Mf<R>::row(lk, q);
+                const bool ok = lr < bP && l < bQ;
+                const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
+                da[sp][q] = ok ? (R)x : (R)0;
+              }
             }
           }
+          (void)V; (void)qv; (void)muv;
         }
         // the A operands of all columns first (independent LDS reads), then the chains
         R ta[NS][H_CPW];
@@ -688,9 +731,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       __syncthreads();
       const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
       switch (h_class(nsQ, nlQ)) {
-        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
-        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
-        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk); break;
+        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d); break;
+        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d); break;
+        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d); break;
       }
       __syncthreads();
     }
@@ -719,15 +762,16 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
               const int P = un.P[u], aP = un.a[u], bP = un.b[u];
               const int muB = un.mu0[u] + lr;
               const bool muv = muB < aP;
-              const double* Vp = V + d.v_off[p];
               const int colx = lr < bP ? m2X[un.bo[u] + lr] : 0;
               const size_t xo = colx + (size_t)ic * mX;
-              const bool px = P <= X;
-              for (int q = 0; q < (aX + 3) / 4; ++q) {
+              const int nsx = (aX + 3) / 4;
+              // V_PX[muB][m2] from the lane-ordered copy (zero outside the block)
+              const double* vrx = d.Vr + d.vr_off[2 * p + (P <= X ? 0 : 1)] + (size_t)(un.mu0[u] >> 4) * nsx * 64 + L;
+              for (int q = 0; q < nsx; ++q) {
                 const int m2 = 4 * q + lk;
                 const bool mv = m2 < aX;
                 const bool oka = mv && lr < bP, okb = mv && muv;
-                const double b = Vp[okb ? (px ? muB * aX + m2 : m2 * aP + muB) : 0];
+                const double b = vrx[q * 64];
                 const R bv = okb ? (R)(gscale * b) : (R)0;
 #pragma unroll
                 for (int sp = 0; sp < NSP; ++sp) {
@@ -1442,6 +1486,22 @@ static int upload_plan(exx_plan_s* pl) {
   if ((rc = alloc_buf(pl, d.sC, (int64_t)hp.pair_a.size()))) return rc;
   if ((rc = alloc_buf(pl, d.sV, (int64_t)hp.pair_a.size()))) return rc;
   if ((rc = alloc_buf(pl, d.epart, (int64_t)hp.en_sys.size()))) return rc;
+  const size_t np = hp.pair_a.size();
+  std::vector<int64_t> vro(2 * np + 1, 0), dro(2 * np + 1, 0);
+  for (size_t p = 0; p < np; ++p) {
+    const int A = hp.pair_a[p], B = hp.pair_b[p];
+    const int64_t v0 = (int64_t)((hp.na[A] + 15) / 16) * ((hp.na[B] + 3) / 4) * 64;
+    const int64_t v1 = A == B ? 0 : (int64_t)((hp.na[B] + 15) / 16) * ((hp.na[A] + 3) / 4) * 64;
+    const int64_t d0 = (int64_t)((hp.nb[B] + 3) / 4) * 64, d1 = A == B ? 0 : (int64_t)((hp.nb[A] + 3) / 4) * 64;
+    vro[2 * p + 1] = vro[2 * p] + v0;
+    vro[2 * p + 2] = vro[2 * p + 1] + v1;
+    dro[2 * p + 1] = dro[2 * p] + d0;
+    dro[2 * p + 2] = dro[2 * p + 1] + d1;
+  }
+  if ((rc = upload(pl, d.vr_off, vro))) return rc;
+  if ((rc = upload(pl, d.dr_off, dro))) return rc;
+  if ((rc = alloc_buf(pl, d.Vr, std::max<int64_t>(1, vro.back())))) return rc;
+  if ((rc = alloc_buf(pl, d.Dr, std::max<int64_t>(1, dro.back())))) return rc;
   return 0;
 }
 
@@ -1699,8 +1759,15 @@ static void launch_H_lists(exx_plan plan, const double* V, const double* D, cons
 }  // extern "C++"
 
 // V stage over the full lists in binary64
+// the lane-ordered V and D operands of the V stage (DevPlan::Vr, Dr) for these V and D
+static void launch_vd_operands(exx_plan plan, const double* V, const double* D, hipStream_t st) {
+  const unsigned np = (unsigned)plan->hp.pair_a.size();
+  if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d);
+}
+
 static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int mode, hipStream_t st) {
   const DevPlan& d = plan->d;
+  launch_vd_operands(plan, V, D, st);
   launch_H_lists<double>(plan, V, D, HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase},
                          (int)plan->hp.g_tiles.size(), gscale, mode, st);
 }
@@ -1710,6 +1777,7 @@ static void stage_mark(exx_plan_s* pl, int i, hipStream_t st);
 static void launch_H_mixed(exx_plan plan, const double* V, const double* D, hipStream_t st) {
   const DevPlan& d = plan->d;
   const HostPlan& hp = plan->hp;
+  launch_vd_operands(plan, V, D, st);
   launch_H_lists<double>(plan, V, D, HLists{d.hm_tiles_near, d.hm_q_near, d.hm_x_near, plan->h_vbase, plan->h_dbase},
                          (int)hp.hm_tiles_near.size(), 2.0, H_WRITE, st);
   stage_mark(plan, 3, st);
@@ -1923,6 +1991,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   launch_rowD(plan, D + ds, rowd_E(plan), n_e, st);
   d.E = E0;
   stage_mark(plan, 2, st);
+  launch_vd_operands(plan, V, D, st);   // V operands (the two density matrices are read directly)
   launch_H_lists<double, 2>(plan, V, D,
                             HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, ds, plan->spin_E1,
                                    plan->spin_H1},
