@@ -861,14 +861,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   R* sT = sm;                                  // [sQ][PITCH]
   R* sE = sm + (size_t)sQ * PITCH;             // [NSP][sP][PITCH]
   const size_t espin = (size_t)sP * PITCH;
+  // V_PQ in MFMA lane order (written by the V stage's operand repack): coalesced rows
   R va[NT][NS];
+  {
+    const int ntp = (aP + 15) >> 4, nsq = (aQ + 3) >> 2;
+    const double* vr = d.Vr + d.vr_off[2 * p + (flip && P != Q ? 1 : 0)] + L;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      const int mu = 16 * t + lr, nu = 4 * q + lk;
-      va[t][q] = (R)((mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0);
-    }
+      for (int q = 0; q < NS; ++q) va[t][q] = (t < ntp && q < nsq) ? (R)vr[(t * nsq + q) * 64] : (R)0;
+    (void)Vp;
+  }
   const bool kv = lr < bQ, iv = lr < bP;
   // staging role: column tc of the chunk, rows r0, r0 + RSTEP, ...  The next
   // chunk is fetched into registers while the current one is computed from LDS.
@@ -2037,14 +2040,16 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
   launch_repack_E(plan, C, D, st, true);
   stage_mark(plan, 2, st);
+  // T2 reads the lane-ordered copy of the V operands that the V stage writes: each Coulomb
+  // matrix's T2 follows its own V stage
   launch_H(plan, V, D, 2.0, H_WRITE, st);
+  launch_T2(plan, V, K, st);
   d.H = plan->spin_H1;
   launch_H(plan, V2, D, 2.0, H_WRITE, st);
   d.H = H0;
+  launch_T2(plan, V2, K + ds, st);
   stage_mark(plan, 3, st);
   stage_mark(plan, 4, st);
-  launch_T2(plan, V, K, st);
-  launch_T2(plan, V2, K + ds, st);
   stage_mark(plan, 5, st);
   stage_mark(plan, 6, st);
   launch_final(plan, K, st);
