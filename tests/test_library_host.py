@@ -68,6 +68,12 @@ def test_errors_are_codes_not_aborts():
     rc = L.lib().build_K(None, None, None, None, 0, None, None, None)
     assert rc == L.EXX_EINVAL
     assert L.lib().exx_last_error()
+    # the spin and two-Coulomb-matrix entry points: same codes, checked before any device work
+    assert L.lib().build_K_spin(p._h, None, None, None, 0, None, None, None) == L.EXX_ESTATE
+    assert L.lib().build_K_spin(None, None, None, None, 0, None, None, None) == L.EXX_EINVAL
+    assert L.lib().build_K_two_kernels(p._h, None, None, None, None, 0, None, None, None) == L.EXX_ESTATE
+    assert L.lib().build_K_two_kernels(None, None, None, None, None, 0, None, None, None) == L.EXX_EINVAL
+    assert b"build_K_two_kernels" in L.lib().exx_last_error()
 
 
 def test_mixed_split_flop_accounting():
