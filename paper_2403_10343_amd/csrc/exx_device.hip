@@ -169,6 +169,8 @@ struct exx_plan_s {
   double* dV_scratch = nullptr;
   double* spin_E1 = nullptr;        // E and H' of the second spin (build_K_spin), allocated on first use
   double* spin_H1 = nullptr;
+  double* spin_Dr1 = nullptr;       // lane-ordered D operands of the second spin
+  int64_t dr_total = 0;             // doubles of the lane-ordered D operands (DevPlan::Dr)
 };
 
 template <typename X>
@@ -430,11 +432,12 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
 
 // The V-stage operands in MFMA lane order (DevPlan::Vr, Dr), one workgroup per canonical
 // pair, both orientations.
+// V == nullptr: the D operands only (into Dr)
 __global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, const double* __restrict__ D,
-                                                 DevPlan d) {
+                                                 double* __restrict__ Dr, DevPlan d) {
   const int p = blockIdx.x;
   const int A = d.pair_a[p], B = d.pair_b[p];
-  const double* Vp = V + d.v_off[p];
+  const double* Vp = V ? V + d.v_off[p] : nullptr;
   const int s = d.atom_sys[A];
   const int64_t ns = d.sys_n[s];
   const double* Ds = D + d.sys_d_off[s];
@@ -443,13 +446,13 @@ __global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, 
     const int aP = d.na[P], aQ = d.na[Q], bP = d.nb[P], bQ = d.nb[Q];
     const int nsq = (aQ + 3) / 4;
     double* vr = d.Vr + d.vr_off[2 * p + o];
-    const int nv = (int)(d.vr_off[2 * p + o + 1] - d.vr_off[2 * p + o]);
+    const int nv = V ? (int)(d.vr_off[2 * p + o + 1] - d.vr_off[2 * p + o]) : 0;
     for (int e = threadIdx.x; e < nv; e += 256) {
       const int L = e & 63, tq = e >> 6, q = tq % nsq, t = tq / nsq;
       const int mu = 16 * t + (L & 15), nu = 4 * q + (L >> 4);
       vr[e] = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
     }
-    double* dr = d.Dr + d.dr_off[2 * p + o];
+    double* dr = Dr + d.dr_off[2 * p + o];
     const int nd = (int)(d.dr_off[2 * p + o + 1] - d.dr_off[2 * p + o]);
     for (int e = threadIdx.x; e < nd; e += 256) {
       const int L = e & 63, q = e >> 6;
@@ -504,7 +507,7 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
                                     const R* sD, const HUnits& un, const int* roff, int vr, int nU, const int* qp,
                                     const int64_t* qv, const double* V, const double* Ds, int64_t dsp, int64_t ns,
                                     int Q, int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
-                                    int lk, const DevPlan& d) {
+                                    int lk, const DevPlan& d, const double* Dr1) {
   typedef typename Mf<R>::acc A4;
   static_assert(NSP == 1 || !HStage<R>::vd, "the LDS-staged binary32 kernel takes one density matrix");
   bool anyc = false;
@@ -550,25 +553,13 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
           const double* vrow = d.Vr + d.vr_off[2 * pp + orient] + (size_t)(un.mu0[u] >> 4) * nsq * 64 + L;
 #pragma unroll
           for (int q = 0; q < NS; ++q) vb[q] = q < nsq ? (R)vrow[q * 64] : (R)0;
-          if constexpr (NSP == 1) {
-            const double* dr = d.Dr + d.dr_off[2 * pp + orient] + L;
 #pragma unroll
-            for (int q = 0; q < NLR; ++q) da[0][q] = q < nlq ? (R)dr[q * 64] : (R)0;
-          } else {
-            // branch-free: invalid lanes read the block's first element and discard it
+          for (int sp = 0; sp < NSP; ++sp) {
+            const double* dr = (sp == 0 ? d.Dr : Dr1) + d.dr_off[2 * pp + orient] + L;
 #pragma unroll
-            for (int sp = 0; sp < NSP; ++sp) {
-              const double* DPQ = Ds + sp * dsp + (size_t)un.bo[u] * ns + boQ;
-#pragma unroll
-              for (int q = 0; q < NLR; ++q) {
-                const int l = Mf<R>::row(lk, q);
-                const bool ok = lr < bP && l < bQ;
-                const double x = DPQ[ok ? (size_t)lr * ns + l : 0];
-                da[sp][q] = ok ? (R)x : (R)0;
-              }
-            }
+            for (int q = 0; q < NLR; ++q) da[sp][q] = q < nlq ? (R)dr[q * 64] : (R)0;
           }
-          (void)V; (void)qv; (void)muv;
+          (void)V; (void)qv; (void)muv; (void)Ds; (void)dsp; (void)ns; (void)boQ; (void)bP;
         }
         // the A operands of all columns first (independent LDS reads), then the chains
         R ta[NS][H_CPW];
@@ -606,6 +597,7 @@ struct HLists {
   int64_t d_spin;
   const double* E1;
   double* H1;
+  const double* Dr1;   // lane-ordered D operands of the second density matrix
 };
 
 // mode: H_WRITE stores H' = (Q part + G part); H_ADD adds both parts to H';
@@ -731,9 +723,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       __syncthreads();
       const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
       switch (h_class(nsQ, nlQ)) {
-        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d); break;
-        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d); break;
-        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d); break;
+        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
       }
       __syncthreads();
     }
@@ -1505,6 +1497,7 @@ static int upload_plan(exx_plan_s* pl) {
   if ((rc = upload(pl, d.dr_off, dro))) return rc;
   if ((rc = alloc_buf(pl, d.Vr, std::max<int64_t>(1, vro.back())))) return rc;
   if ((rc = alloc_buf(pl, d.Dr, std::max<int64_t>(1, dro.back())))) return rc;
+  pl->dr_total = dro.back();
   return 0;
 }
 
@@ -1765,7 +1758,7 @@ static void launch_H_lists(exx_plan plan, const double* V, const double* D, cons
 // the lane-ordered V and D operands of the V stage (DevPlan::Vr, Dr) for these V and D
 static void launch_vd_operands(exx_plan plan, const double* V, const double* D, hipStream_t st) {
   const unsigned np = (unsigned)plan->hp.pair_a.size();
-  if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d);
+  if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d.Dr, plan->d);
 }
 
 static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int mode, hipStream_t st) {
@@ -1956,6 +1949,10 @@ static int second_workspace(exx_plan plan) {
   HIP_TRY(hipMalloc((void**)&plan->spin_H1, sizeof(double) * ne));
   plan->allocs.push_back(plan->spin_H1);
   plan->dev_bytes += 2 * (int64_t)sizeof(double) * ne;
+  const int64_t ndr = std::max<int64_t>(1, plan->dr_total);
+  HIP_TRY(hipMalloc((void**)&plan->spin_Dr1, sizeof(double) * ndr));
+  plan->allocs.push_back(plan->spin_Dr1);
+  plan->dev_bytes += (int64_t)sizeof(double) * ndr;
   return EXX_OK;
 }
 
@@ -1994,10 +1991,13 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   launch_rowD(plan, D + ds, rowd_E(plan), n_e, st);
   d.E = E0;
   stage_mark(plan, 2, st);
-  launch_vd_operands(plan, V, D, st);   // V operands (the two density matrices are read directly)
+  launch_vd_operands(plan, V, D, st);   // V and D^0 operands
+  if (!hp.pair_a.empty())
+    hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
+                       plan->spin_Dr1, plan->d);   // D^1 operands
   launch_H_lists<double, 2>(plan, V, D,
                             HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, ds, plan->spin_E1,
-                                   plan->spin_H1},
+                                   plan->spin_H1, plan->spin_Dr1},
                             (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
   stage_mark(plan, 3, st);
   stage_mark(plan, 4, st);
