@@ -500,14 +500,15 @@ template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == si
 // rows are read without masks: rows past s_Q (or of lanes past n_b(Q)) hold
 // finite values, and they meet zero V (nu >= n_a(Q)) or zero D (l >= n_b(Q))
 // operands.  A column missing from N[Q] is staged as zeros.
-// NSP density matrices (collinear spin: two, D^s at Ds + s * dsp) share F; each has its own
-// D contraction and accumulators.
+// The binary64 kernel reads the V and D operands from their lane-ordered copies (d.Vr,
+// d.Dr); NSP density matrices (collinear spin: two, the second's D operands in Dr1) share F,
+// and each has its own D contraction and accumulators.  The binary32 kernel reads them from
+// the blocks it staged in LDS (sV, sD).
 template <int NS, int NL, int U, int NSP, typename R>
 __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], const R* sT, const R* sV,
-                                    const R* sD, const HUnits& un, const int* roff, int vr, int nU, const int* qp,
-                                    const int64_t* qv, const double* V, const double* Ds, int64_t dsp, int64_t ns,
-                                    int Q, int boQ, int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr,
-                                    int lk, const DevPlan& d, const double* Dr1) {
+                                    const R* sD, const HUnits& un, const int* roff, int nU, const int* qp, int Q,
+                                    int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr, int lk,
+                                    const DevPlan& d, const double* Dr1) {
   typedef typename Mf<R>::acc A4;
   static_assert(NSP == 1 || !HStage<R>::vd, "the LDS-staged binary32 kernel takes one density matrix");
   bool anyc = false;
@@ -515,7 +516,6 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
   for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || ((c0 + cc < ncols) && lc_row[c0 + cc] >= 0);
   if (!anyc) return;
   const R* t0 = sT + lr * LDS_PITCH + c0;
-  const int tstride = 4 * bQ * LDS_PITCH;
   constexpr int NLR = sizeof(R) == sizeof(double) ? NL : 4;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -559,7 +559,6 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
 #pragma unroll
             for (int q = 0; q < NLR; ++q) da[sp][q] = q < nlq ? (R)dr[q * 64] : (R)0;
           }
-          (void)V; (void)qv; (void)muv; (void)Ds; (void)dsp; (void)ns; (void)boQ; (void)bP;
         }
         // the A operands of all columns first (independent LDS reads), then the chains
         R ta[NS][H_CPW];
@@ -585,7 +584,6 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
       }
     }
   }
-  (void)tstride;
 }
 
 // Task lists of one k_H launch: tiles and their Q- and X-lists.
@@ -593,11 +591,11 @@ struct HLists {
   const GTile* tiles;
   const Slot4 *gq, *gx;
   int v_base, d_base;     // element offsets of the staged V and D blocks in LDS
-  // second density matrix (collinear spin): D^1 at D + d_spin, its E and H' workspaces
-  int64_t d_spin;
+  // second density matrix (collinear spin): its E and H' workspaces and its lane-ordered
+  // D operands
   const double* E1;
   double* H1;
-  const double* Dr1;   // lane-ordered D operands of the second density matrix
+  const double* Dr1;
 };
 
 // mode: H_WRITE stores H' = (Q part + G part); H_ADD adds both parts to H';
@@ -672,7 +670,6 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
   if (mode != H_G_ADD)
     for (int i = threadIdx.x; i < hl.v_base; i += blockDim.x) sT[i] = (R)0;
   __syncthreads();
-  const int vr = roff[GROUP_ATOMS];
   for (int e0 = mode == H_G_ADD ? tl.q_end : tl.q_beg; e0 < tl.q_end; e0 += HQ_CHUNK) {
     const int nchunk = min(HQ_CHUNK, tl.q_end - e0);
     __syncthreads();
@@ -723,9 +720,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       __syncthreads();
       const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
       switch (h_class(nsQ, nlQ)) {
-        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
-        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
-        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, vr, nU, qm_p[ei], qm_voff[ei], V, Ds, hl.d_spin, ns, Q, qm_bo[ei], aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
       }
       __syncthreads();
     }
@@ -1996,7 +1993,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
     hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
                        plan->spin_Dr1, plan->d);   // D^1 operands
   launch_H_lists<double, 2>(plan, V, D,
-                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, ds, plan->spin_E1,
+                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, plan->spin_E1,
                                    plan->spin_H1, plan->spin_Dr1},
                             (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
   stage_mark(plan, 3, st);
