@@ -603,10 +603,11 @@ struct HLists {
 enum { H_WRITE = 0, H_ADD = 1, H_G_ADD = 2 };
 
 // NSP = 2: the two spin density matrices of a collinear-spin build in one pass (F = V T_Q is
-// formed once); H'^0 goes to d.H, H'^1 to hl.H1.  Three wavefronts per SIMD for one density
-// matrix, two for two (their accumulators double).
+// formed once); H'^0 goes to d.H, H'^1 to hl.H1.  Four wavefronts per SIMD for one density
+// matrix (at most 128 VGPRs: measured faster than three with 168 since the V and D operands
+// are coalesced rows), two for two (their accumulators double).
 template <int U, typename R, int NSP>
-__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NSP == 1 ? 3 : 2))) void k_H(
+__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NSP == 1 ? 4 : 2))) void k_H(
     const double* __restrict__ V, const double* __restrict__ D, DevPlan d, HLists hl, int n_tiles,
     int n_padded, double gscale, int mode) {
   typedef typename Mf<R>::acc A4;
