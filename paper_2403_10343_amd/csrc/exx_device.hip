@@ -313,12 +313,13 @@ struct RowD {
 // column tile (runs of consecutive atoms: column lcol.. of A, row grow.. of D).
 constexpr int ET = 64, EPITCH = ET + 4;
 
-// EK: k-chunk per LDS stage (a tuning choice: 16 or 32)
-template <int EK>
+// EK: k-chunk per LDS stage (a tuning choice: 16 or 32).  NSP = 2 (collinear spin): the
+// products with D (into r.O) and D1 (into O1) in one pass, the A_P tile staged once.
+template <int EK, int NSP>
 __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
-                                              int n_padded) {
+                                              int n_padded, const double* __restrict__ D1, double* __restrict__ O1) {
   __shared__ double As[2][EK][EPITCH];
-  __shared__ double Bs[2][EK][EPITCH];
+  __shared__ double Bs[NSP][2][EK][EPITCH];
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
   const EItem it = r.items[w];
@@ -326,7 +327,9 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   const int sP = d.na[P] * d.nb[P], lda = r.a_ld[P], ldo = r.o_ld[P];
   const int s = d.atom_sys[P];
   const int64_t ns = d.sys_n[s];
-  const double* Ds = D + d.sys_d_off[s];
+  const double* Dsp[NSP];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp) Dsp[sp] = (sp == 0 ? D : D1) + d.sys_d_off[s];
   const double* AP = r.A + r.a_off[P];
   const int t = threadIdx.x;
   const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   int ib[NP], sb[NP];                    // and of each pass of the B role
 #pragma unroll
   for (int pz = 0; pz < NP; ++pz) ib[pz] = sb[pz] = 0;
-  double va[NA_], vb[NP][4];
+  double va[NA_], vb[NSP][NP][4];
   auto gload = [&](int k0) {
     const int k1 = k0 + ka;
     const bool oka = k1 < klen;
@@ -370,8 +373,11 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         const bool okd = okb && gcn[x] >= 0;
-        const double z = Ds[okd ? (size_t)gr * ns + gcn[x] : 0];
-        vb[pz][x] = okd ? z : 0.0;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) {
+          const double z = Dsp[sp][okd ? (size_t)gr * ns + gcn[x] : 0];
+          vb[sp][pz][x] = okd ? z : 0.0;
+        }
       }
     }
   };
@@ -379,15 +385,19 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
 #pragma unroll
     for (int x = 0; x < NA_; ++x) As[buf][ka][ma + MS * x] = va[x];
 #pragma unroll
-    for (int pz = 0; pz < NP; ++pz)
+    for (int sp = 0; sp < NSP; ++sp)
 #pragma unroll
-      for (int x = 0; x < 4; ++x) Bs[buf][16 * pz + kb][nb0 + x] = vb[pz][x];
+      for (int pz = 0; pz < NP; ++pz)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) Bs[sp][buf][16 * pz + kb][nb0 + x] = vb[sp][pz][x];
   };
-  d4 acc[2][2];
+  d4 acc[NSP][2][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int sp = 0; sp < NSP; ++sp)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[sp][x][y] = d4{0, 0, 0, 0};
   gload(0);
   sstore(0);
   __syncthreads();
@@ -398,11 +408,14 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
 #pragma unroll
     for (int ks = 0; ks < EK; ks += 4) {
       const double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
-      const double b0 = Bs[buf][ks + lk][wn + lr], b1 = Bs[buf][ks + lk][wn + 16 + lr];
-      acc[0][0] = mfma64(a0, b0, acc[0][0]);
-      acc[0][1] = mfma64(a0, b1, acc[0][1]);
-      acc[1][0] = mfma64(a1, b0, acc[1][0]);
-      acc[1][1] = mfma64(a1, b1, acc[1][1]);
+#pragma unroll
+      for (int sp = 0; sp < NSP; ++sp) {
+        const double b0 = Bs[sp][buf][ks + lk][wn + lr], b1 = Bs[sp][buf][ks + lk][wn + 16 + lr];
+        acc[sp][0][0] = mfma64(a0, b0, acc[sp][0][0]);
+        acc[sp][0][1] = mfma64(a0, b1, acc[sp][0][1]);
+        acc[sp][1][0] = mfma64(a1, b0, acc[sp][1][0]);
+        acc[sp][1][1] = mfma64(a1, b1, acc[sp][1][1]);
+      }
     }
     if (more) {
       sstore(buf ^ 1);
@@ -410,19 +423,22 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
       buf ^= 1;
     }
   }
-  double* OP = r.O + r.o_off[P];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int sp = 0; sp < NSP; ++sp) {
+    double* OP = (sp == 0 ? r.O : O1) + r.o_off[P];
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      const int col = it.c0 + wn + 16 * y + lr;
-      if (col >= ldo) continue;
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = it.r0 + wm + 16 * x + lk + 4 * v;
-        if (row < sP) OP[(size_t)row * ldo + col] = acc[x][y][v];
+      for (int y = 0; y < 2; ++y) {
+        const int col = it.c0 + wn + 16 * y + lr;
+        if (col >= ldo) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = it.r0 + wm + 16 * x + lk + 4 * v;
+          if (row < sP) OP[(size_t)row * ldo + col] = acc[sp][x][y][v];
+        }
       }
-    }
+  }
 }
 
 // V_PQ[mu][nu] (mu on P, nu on Q) from the canonical V block of pair p.
@@ -1722,8 +1738,21 @@ static RowD rowd_GD(exx_plan plan) {
 static void launch_rowD(exx_plan plan, const double* D, const RowD& r, int n, hipStream_t st) {
   if (n <= 0) return;
   const int nwgp = (n + 7) / 8 * 8;
-  if (plan->tune[TUNE_E] == 1) hipLaunchKernelGGL(k_rowD<32>, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
-  else hipLaunchKernelGGL(k_rowD<16>, dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp);
+  if (plan->tune[TUNE_E] == 1)
+    hipLaunchKernelGGL((k_rowD<32, 1>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_rowD<16, 1>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+}
+
+// the two products of a collinear-spin build: r.O = A D, O1 = A D1
+static void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* O1, const RowD& r, int n,
+                             hipStream_t st) {
+  if (n <= 0) return;
+  const int nwgp = (n + 7) / 8 * 8;
+  if (plan->tune[TUNE_E] == 1)
+    hipLaunchKernelGGL((k_rowD<32, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+  else
+    hipLaunchKernelGGL((k_rowD<16, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
 }
 
 // repack C into T_P, then E_P = T_P D (stage mark 1 in between)
@@ -1977,17 +2006,12 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (rcw != EXX_OK) return rcw;
   hipStream_t st = (hipStream_t)stream;
   DevPlan& d = plan->d;
-  double* const E0 = d.E;
-  double* const H0 = d.H;
   const int n_e = (int)hp.e_items.size();
   stage_mark(plan, 0, st);
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
   hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, plan->d);
   stage_mark(plan, 1, st);
-  launch_rowD(plan, D, rowd_E(plan), n_e, st);
-  d.E = plan->spin_E1;
-  launch_rowD(plan, D + ds, rowd_E(plan), n_e, st);
-  d.E = E0;
+  launch_rowD_spin(plan, D, D + ds, plan->spin_E1, rowd_E(plan), n_e, st);
   stage_mark(plan, 2, st);
   launch_vd_operands(plan, V, D, st);   // V and D^0 operands
   if (!hp.pair_a.empty())
@@ -2002,6 +2026,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   launch_T2_spin(plan, V, K, st);
   stage_mark(plan, 5, st);
   stage_mark(plan, 6, st);
+  double* const H0 = d.H;
   launch_final(plan, K, st);
   d.H = plan->spin_H1;
   launch_final(plan, K + ds, st);
