@@ -34,10 +34,10 @@ CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "50ab156d3d8f294f",
+    "sources": "c7fd1bd8d5a74a5d",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 29.968e9 + 5.236e9, ("fp64", "T2"): 35.714e9 + 0.025e9,
-              ("fp64", "final"): 10.238e9 + 4.280e9, ("fp64", "E"): 2.755e9 + 2.476e9},
+    "bytes": {("fp64", "H"): 30.028e9 + 5.239e9, ("fp64", "T2"): 35.684e9 + 0.025e9,
+              ("fp64", "final"): 10.250e9 + 4.280e9, ("fp64", "E"): 2.756e9 + 2.476e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>", "H32": "k_H<U, float, 1>",
                    "T2": "k_T2<NT, NS, double, COLS, WAVES, 1>", "T2_32": "k_T2<NT, NS, float, COLS, WAVES, 1>",

@@ -14,13 +14,16 @@
 // H'_P = sum_Q (V_PQ (x) D_PQ) T_Q + 2 G, the product X = T^T H' equals
 // T3 + 2 T1^T and K = T2 + (X + X^T) / 2.
 //
-// Kernels (one wavefront per task, four tasks per workgroup):
-//   k_repack  C pair blocks -> row-owned T_P
-//   k_E       E_P = T_P D over N2[P]           (FP64 MFMA 16x16x4)
-//   k_H       H'_P: F = V T_Q (MFMA), D contraction (FMA), G part (MFMA)
-//   k_T2      T2 pair blocks into K            (MFMA, two chained stages)
-//   k_final   K = T2 + sym(T^T H'), owner-computes, atomic-free
-//   k_energy  E_x per system, fixed-order reduction
+// Kernels of a build (all contractions on FP64 MFMA 16x16x4, or FP32 16x16x4 for the
+// far pair terms of a mixed build):
+//   k_repack     C pair blocks -> row-owned T_P
+//   k_rowD       E_P = T_P D over N2[P]              (LDS-tiled GEMM over k-runs)
+//   k_vdrepack   V_PQ and D_PQ in MFMA lane order    (coalesced operand rows)
+//   k_H          H'_P: F = V T_Q, D contraction, G part (chained MFMAs per Q)
+//   k_T2         T2 pair blocks into K               (two chained MFMA stages)
+//   k_Y          Y_P = T_P^T H'_P                    (LDS-tiled batched GEMM)
+//   k_symreduce  K = T2 + (X + X^T)/2 gathered from Y, owner-computes, atomic-free
+//   k_energy_*   E_x per system, fixed-order reduction
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -509,7 +512,7 @@ struct HUnits {            // unit table of the group (LDS)
 };
 
 // The binary32 kernel stages the V_PQ and D_PQ blocks of the group in LDS
-// once per Q; the binary64 kernel (register bound) reads them per unit.
+// once per Q; the binary64 kernel reads them per unit from their lane-ordered copies.
 template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == sizeof(float); };
 
 // One Q of a V-stage tile, all H_CPW columns of this wavefront.  The staged T_Q
@@ -2042,8 +2045,9 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
 // Two Coulomb matrices: repack and E = T D once, then the V stage, T2 and the final
 // contraction per Coulomb matrix (H' of the second in the second workspace).  A V-stage pass
 // computing both at once (shared T_Q staging and D operands) measured slower than two passes
-// (49.4 against 2 x 22.0 ms at 768 atoms): the V operands, whose loads bound the stage, are
-// not shared, and the doubled accumulators halve the occupancy.
+// (49.4 against 2 x 22.0 ms at 768 atoms, with the operands then gathered from V and D): the
+// V operands, whose loads bound the stage, are not shared, and the doubled accumulators
+// halve the occupancy.
 int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2, const double* D,
                         int precision, double* K, double* Ex, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "build_K_two_kernels: NULL plan");
