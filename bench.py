@@ -47,7 +47,7 @@ KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>"
 def sources_fingerprint():
     import hashlib
     h = hashlib.sha256()
-    for f in ("exx_device.hip", "exx_internal.h", "exx_plan.cpp"):
+    for f in sorted(os.listdir(CSRC)):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

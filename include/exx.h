@@ -24,7 +24,7 @@
  * V, and the density-matrix pattern).  Pairs never cross systems.
  *
  * Canonical pairs are (A, B) with A <= B, in lexicographic order; their
- * storage offsets are returned by exx_plan_pairs().
+ * storage offsets are returned by exx_pair_layout().
  *
  *   C (device, read-only): for pair (A, B), A < B, a block
  *       [n_aux(A) + n_aux(B)][n_basis(A)][n_basis(B)]; rows m < n_aux(A) hold
@@ -36,8 +36,9 @@
  *       V_{mu nu} = V_{nu mu}, mu on A, nu on B.  On-site blocks in full.
  *   D, K (device): dense, row-major, symmetric, one n_s x n_s block per
  *       system s (n_s = sum of n_basis over its atoms), blocks concatenated
- *       in system order.  D entries of atom pairs beyond r_cut are not read
- *       (treated as zero).
+ *       in system order.  D entries of atom pairs beyond r_cut are ignored
+ *       (treated as zero): the library contracts a copy of D restricted to the
+ *       screened pair blocks, and E_x sums over those blocks only.
  *
  * Ownership: the caller owns every device array passed in; the plan owns its
  * bookkeeping lists and workspace.  Output arrays are fully overwritten
@@ -69,6 +70,10 @@ extern "C" {
 /* arithmetic of the contraction stages */
 #define EXX_PREC_FP64     0   /* binary64 everywhere (FP64 MFMA) */
 #define EXX_PREC_MIXED    1   /* distance-split mixed precision, see exx_plan_set_mixed_split */
+#define EXX_PREC_FP32     2   /* every pair term of the V stage and of the T2 blocks in binary32
+                                 (the mixed build at split 0, whatever split the plan holds);
+                                 a reported mode: it does not meet the mixed-precision bar */
+#define EXX_PREC_BF16X3   3   /* reserved (bfloat16 hi/lo split products): EXX_EUNSUPPORTED */
 
 /* plan flags */
 #define EXX_PLAN_HOST_ONLY 1u /* build the lists on the host only; no device use */
@@ -86,6 +91,11 @@ typedef struct {
     int32_t n_systems;           /* >= 1 */
     const int32_t* sys_atom_off; /* host [n_systems + 1], increasing, first 0,
                                     last n_atoms; may be NULL if n_systems == 1 */
+    const double* lattice;       /* host [3][3] lattice vectors (rows, Angstrom) of a
+                                    periodic system, or NULL for clusters.  Periodic
+                                    systems (lattice vectors R != 0 of Eq.
+                                    realspace_exchange) are not implemented: a non-NULL
+                                    lattice returns EXX_EUNSUPPORTED. */
 } exx_system;
 
 typedef struct {
@@ -94,6 +104,9 @@ typedef struct {
     int64_t n_basis_max;                /* largest system */
     int64_t workspace_bytes;            /* device bytes held by the plan */
     int64_t flops_fp64;                 /* algorithmic flops of one build_K */
+    int64_t n_chunks;                   /* aux-atom chunks a build runs in (1: everything stored) */
+    int64_t intermediate_bytes;         /* device bytes of the E, H' and Y workspaces */
+    int64_t intermediate_bytes_stored;  /* what they take when nothing is recomputed */
 } exx_info;
 
 /* Build a plan for one geometry: screening, canonical pairs, neighbour
@@ -101,8 +114,21 @@ typedef struct {
  * exchange build.  The bookkeeping runs on the current HIP device unless
  * flags has EXX_PLAN_HOST_ONLY.  The plan keeps copies of everything it needs
  * from *sys.  Returns EXX_EINVAL for malformed systems.  Errors leave *out
- * NULL. */
-int exx_plan_create(const exx_system* sys, uint32_t flags, exx_plan* out);
+ * NULL.
+ *
+ * ws_budget_bytes bounds the device memory of the C.D intermediates of a build
+ * (E = M D of Eq. temp_E, H' of Eqs. temp_F-temp_H, Y = T^T H'; the
+ * memory-driven sizing of Sec. "Initialization" and the force pass split of
+ * Sec. "EXX force and stress contributions"); 0 = no bound.  When storing them
+ * for all aux atoms at once would exceed the bound, builds and backward passes
+ * run over consecutive chunks of aux atoms, and the E blocks of the atoms
+ * neighbouring a chunk are recomputed for every chunk that needs them instead
+ * of being stored.  The result equals the unbounded build up to the rounding
+ * order of the final sum (the per-chunk parts of K are added in chunk order).
+ * EXX_ENOMEM if one V-stage group (at most three neighbouring atoms) alone
+ * needs more than the bound.  Collinear-spin and two-kernel builds need the
+ * unbounded layout (EXX_EUNSUPPORTED on a chunked plan). */
+int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_bytes, exx_plan* out);
 
 /* Release the plan and its device memory (after work on it has finished). */
 int exx_plan_destroy(exx_plan plan);
@@ -113,9 +139,9 @@ int exx_plan_info(exx_plan plan, exx_info* info);
 /* Canonical pair layout, written to caller-owned host arrays: pair_a and
  * pair_b [n_pairs] (int32 atom indices), c_off and v_off [n_pairs + 1]
  * (int64 element offsets of each pair's C and V block).  Any pointer may be
- * NULL to skip that array. */
-int exx_plan_pairs(exx_plan plan, int32_t* pair_a, int32_t* pair_b,
-                   int64_t* c_off, int64_t* v_off);
+ * NULL to skip that array.  n_pairs is in exx_plan_info(). */
+int exx_pair_layout(exx_plan plan, int32_t* pair_a, int32_t* pair_b,
+                    int64_t* c_off, int64_t* v_off);
 
 /* Neighbour lists as built on the device (for inspection and tests):
  * nbr_ptr [n_atoms + 1], nbr_atom [nbr_ptr[n_atoms]], host arrays.  Pass
@@ -203,11 +229,14 @@ int exx_plan_set_tuning(exx_plan plan, const int32_t* choices);
 int exx_plan_set_mixed_split(exx_plan plan, double r_split);
 
 /* E_x = -1/4 sum_ik K_ik D_ik for every system (device Ex [n_systems]),
- * a fixed-order binary64 reduction (bitwise reproducible). */
+ * summed over the screened pair blocks (D beyond r_cut counts as zero), a
+ * fixed-order binary64 reduction (bitwise reproducible).  The per-chunk
+ * partial sums live in a plan-owned device buffer. */
 int exchange_energy(exx_plan plan, const double* K, const double* D,
                     double* Ex, void* stream);
 
-/* Gradients of the scaled energy gE * E_x (gE is dL/dE_x of the caller):
+/* Gradients of the scaled energy sum_s gE[s] * E_x[s] (gE: device [n_systems],
+ * dL/dE_x of every system; each system's blocks are scaled by its own gE):
  *   dD (device, d_size, dense, symmetric): dE/dD_ik = -1/2 K_ik, the
  *       derivative with respect to each stored entry of the dense D;
  *   dC (device, c_size): derivative per stored C entry (the two mirrored
@@ -216,6 +245,9 @@ int exchange_energy(exx_plan plan, const double* K, const double* D,
  *       V_{mu nu} and V_{nu mu};
  *   forces (device [n_atoms][3], may be NULL): -d(gE E_x)/dR for the
  *       synthetic model C_AB ~ exp(-r_AB / c_decay), V_AB ~ exp(-r_AB^2 / v_2s2)
+ *       (the position dependence the inputs are generated with; the paper's
+ *       force terms, Sec. "EXX force and stress contributions", differentiate
+ *       the real integrals instead)
  *       (on-site blocks position independent, D held fixed).
  * Any of dC, dV, dD may be NULL to skip it.  K (device, d_size, may be NULL)
  * is the exchange matrix of these same C, V, D from build_K (of either
@@ -224,7 +256,7 @@ int exchange_energy(exx_plan plan, const double* K, const double* D,
  * precision must be EXX_PREC_FP64 (EXX_PREC_MIXED returns EXX_EUNSUPPORTED;
  * a mixed forward pass is differentiated by passing its K here). */
 int exchange_backward(exx_plan plan, const double* C, const double* V,
-                      const double* D, const double* K, double gE, int precision,
+                      const double* D, const double* K, const double* gE, int precision,
                       double* dC, double* dV, double* dD, double* forces,
                       double c_decay, double v_2s2, void* stream);
 

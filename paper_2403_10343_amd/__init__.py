@@ -1,5 +1,5 @@
 """MI355X RI-LVL exact-exchange build: thin Python layer over libexx.so."""
-from ._lib import (PREC_MIXED, PREC_FP64, ExxError, Plan, lib)  # noqa: F401
+from ._lib import (PREC_BF16X3, PREC_FP32, PREC_MIXED, PREC_FP64, ExxError, Plan, lib)  # noqa: F401
 
 
 def exchange_energy(plan, C, V, D, precision=PREC_FP64):
@@ -13,4 +13,5 @@ def exchange_forces(plan, C, V, D, c_decay=1.5, v_2s2=8.0, gE=1.0):
     return f(plan, C, V, D, c_decay, v_2s2, gE)
 
 
-__all__ = ["Plan", "ExxError", "PREC_FP64", "PREC_MIXED", "lib", "exchange_energy", "exchange_forces"]
+__all__ = ["Plan", "ExxError", "PREC_FP64", "PREC_MIXED", "PREC_FP32", "PREC_BF16X3", "lib", "exchange_energy",
+           "exchange_forces"]

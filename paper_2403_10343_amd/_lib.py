@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libexx.so")
 
 EXX_OK, EXX_EINVAL, EXX_ENOMEM, EXX_EDEVICE, EXX_ESTATE, EXX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_FP32, PREC_BF16X3 = 0, 1, 2, 3
 PLAN_HOST_ONLY = 1
 
 _lib = None
@@ -39,16 +39,18 @@ class _System(ctypes.Structure):
         ("r_cut", ctypes.c_double),
         ("n_systems", ctypes.c_int32),
         ("sys_atom_off", ctypes.POINTER(ctypes.c_int32)),
+        ("lattice", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_atoms", "n_systems", "n_pairs", "c_size", "v_size", "d_size",
-        "n_basis_max", "workspace_bytes", "flops_fp64")]
+        "n_basis_max", "workspace_bytes", "flops_fp64", "n_chunks", "intermediate_bytes",
+        "intermediate_bytes_stored")]
 
 
-EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_plan_pairs",
+EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_layout",
            "exx_plan_neighbors", "build_K", "exchange_energy", "exchange_backward",
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
@@ -67,16 +69,16 @@ def lib():
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2403_10343_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-    L.exx_plan_create.argtypes = [ctypes.POINTER(_System), ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.exx_plan_create.argtypes = [ctypes.POINTER(_System), ctypes.c_uint32, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.exx_plan_destroy.argtypes = [vp]
     L.exx_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
-    L.exx_plan_pairs.argtypes = [vp, vp, vp, vp, vp]
+    L.exx_pair_layout.argtypes = [vp, vp, vp, vp, vp]
     L.exx_plan_neighbors.argtypes = [vp, vp, vp]
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.build_K_spin.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.build_K_two_kernels.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
-    L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, dp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
     L.exx_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp]
@@ -100,10 +102,25 @@ def _check(rc):
         raise ExxError(rc, lib().exx_last_error().decode())
 
 
-def _ptr(x):
-    """Raw device/host pointer of a torch tensor (or None)."""
+def _dev(x, n, name, optional=False):
+    """Pointer of a device array the library reads or writes: a contiguous
+    float64 tensor on a GPU with exactly n elements (checked here, so that a
+    wrong array raises instead of reaching the kernels)."""
     if x is None:
-        return None
+        if optional:
+            return None
+        raise ExxError(EXX_EINVAL, f"{name}: array required")
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise ExxError(EXX_EINVAL, f"{name}: expected a torch.Tensor, got {type(x).__name__}")
+    if x.dtype != torch.float64:
+        raise ExxError(EXX_EINVAL, f"{name}: dtype {x.dtype}, expected torch.float64")
+    if not x.is_cuda:
+        raise ExxError(EXX_EINVAL, f"{name}: tensor on {x.device}, expected a GPU tensor")
+    if not x.is_contiguous():
+        raise ExxError(EXX_EINVAL, f"{name}: tensor is not contiguous")
+    if x.numel() != n:
+        raise ExxError(EXX_EINVAL, f"{name}: {x.numel()} elements, expected {n}")
     return ctypes.c_void_p(x.data_ptr())
 
 
@@ -117,7 +134,8 @@ def _stream(stream):
 class Plan:
     """An exchange plan for one geometry (owns the device task lists)."""
 
-    def __init__(self, species, positions, n_basis, n_aux, r_cut, sys_atom_off=None, host_only=False):
+    def __init__(self, species, positions, n_basis, n_aux, r_cut, sys_atom_off=None, host_only=False,
+                 ws_budget_bytes=0, lattice=None):
         species = np.ascontiguousarray(species, dtype=np.int32)
         positions = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
         n_basis = np.ascontiguousarray(n_basis, dtype=np.int32)
@@ -125,24 +143,27 @@ class Plan:
         n_sys = 1 if sys_atom_off is None else len(sys_atom_off) - 1
         off = None if sys_atom_off is None else np.ascontiguousarray(sys_atom_off, dtype=np.int32)
         i32p, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+        lat = None if lattice is None else np.ascontiguousarray(lattice, dtype=np.float64).reshape(3, 3)
         s = _System(len(species), len(n_basis), species.ctypes.data_as(i32p),
                     positions.ctypes.data_as(dp), n_basis.ctypes.data_as(i32p),
                     n_aux.ctypes.data_as(i32p), float(r_cut), n_sys,
-                    off.ctypes.data_as(i32p) if off is not None else None)
+                    off.ctypes.data_as(i32p) if off is not None else None,
+                    lat.ctypes.data_as(dp) if lat is not None else None)
         h = ctypes.c_void_p()
         self._h = None
-        _check(lib().exx_plan_create(ctypes.byref(s), PLAN_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        _check(lib().exx_plan_create(ctypes.byref(s), PLAN_HOST_ONLY if host_only else 0,
+                                     int(ws_budget_bytes), ctypes.byref(h)))
         self._h = h
         self.n_atoms = len(species)
         self.n_systems = n_sys
         self.info = self._info()
 
     @classmethod
-    def for_system(cls, system, host_only=False):
+    def for_system(cls, system, host_only=False, ws_budget_bytes=0):
         """Plan for a ``synth.System``-like object (species, pos, species tables
         basis_table / aux_table, r_cut, sys_off)."""
         return cls(system.species, system.pos, system.basis_table, system.aux_table, system.r_cut,
-                   system.sys_off if system.n_systems > 1 else None, host_only)
+                   system.sys_off if system.n_systems > 1 else None, host_only, ws_budget_bytes)
 
     def _info(self):
         inf = _Info()
@@ -153,7 +174,7 @@ class Plan:
         n = self.info["n_pairs"]
         pa, pb = np.empty(n, np.int32), np.empty(n, np.int32)
         co, vo = np.empty(n + 1, np.int64), np.empty(n + 1, np.int64)
-        _check(lib().exx_plan_pairs(self._h, pa.ctypes.data, pb.ctypes.data, co.ctypes.data, vo.ctypes.data))
+        _check(lib().exx_pair_layout(self._h, pa.ctypes.data, pb.ctypes.data, co.ctypes.data, vo.ctypes.data))
         return pa, pb, co, vo
 
     def neighbors(self):
@@ -178,44 +199,72 @@ class Plan:
         issued = [i64[0], i64[1], i64[2], i32[2], i64[3], i32[3], i64[4], 0]
         return alg, issued
 
+    def _cvd(self, C, V, D, nd=1):
+        i = self.info
+        return (_dev(C, i["c_size"], "C"), _dev(V, i["v_size"], "V"), _dev(D, nd * i["d_size"], "D"))
+
     def build_K(self, C, V, D, K, Ex=None, precision=PREC_FP64, stream=None):
-        _check(lib().build_K(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
-                             _stream(stream)))
+        c, v, d = self._cvd(C, V, D)
+        _check(lib().build_K(self._h, c, v, d, int(precision), _dev(K, self.info["d_size"], "K"),
+                             _dev(Ex, self.n_systems, "Ex", True), _stream(stream)))
 
     def build_K_spin(self, C, V, D, K, Ex=None, precision=PREC_FP64, stream=None):
         """Collinear spin: D and K hold two d_size blocks (spin 0, then spin 1);
         Ex (optional) gets -1/2 sum_s sum K^s D^s per system."""
-        _check(lib().build_K_spin(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
-                                  _stream(stream)))
+        c, v, d = self._cvd(C, V, D, 2)
+        _check(lib().build_K_spin(self._h, c, v, d, int(precision), _dev(K, 2 * self.info["d_size"], "K"),
+                                  _dev(Ex, self.n_systems, "Ex", True), _stream(stream)))
 
     def build_K_two_kernels(self, C, V, V2, D, K, Ex=None, precision=PREC_FP64, stream=None):
         """Two Coulomb matrices V, V2 (same layout): K holds K^0 then K^1 (2 d_size);
         Ex (optional, 2 n_systems) the E_x of each."""
-        _check(lib().build_K_two_kernels(self._h, _ptr(C), _ptr(V), _ptr(V2), _ptr(D), int(precision), _ptr(K),
-                                         _ptr(Ex), _stream(stream)))
+        c, v, d = self._cvd(C, V, D)
+        _check(lib().build_K_two_kernels(self._h, c, v, _dev(V2, self.info["v_size"], "V2"), d, int(precision),
+                                         _dev(K, 2 * self.info["d_size"], "K"),
+                                         _dev(Ex, 2 * self.n_systems, "Ex", True), _stream(stream)))
 
     def exchange_energy(self, K, D, Ex, stream=None):
-        _check(lib().exchange_energy(self._h, _ptr(K), _ptr(D), _ptr(Ex), _stream(stream)))
+        n = self.info["d_size"]
+        _check(lib().exchange_energy(self._h, _dev(K, n, "K"), _dev(D, n, "D"), _dev(Ex, self.n_systems, "Ex"),
+                                     _stream(stream)))
+
+    def gE_tensor(self, gE, device):
+        """dL/dE_x per system as the device array exchange_backward takes: a
+        scalar is broadcast to every system."""
+        import torch
+        if isinstance(gE, torch.Tensor):
+            return gE.detach().to(device=device, dtype=torch.float64).reshape(-1).contiguous()
+        g = np.broadcast_to(np.asarray(gE, dtype=np.float64), (self.n_systems,))
+        return torch.from_numpy(np.ascontiguousarray(g)).to(device)
 
     def exchange_backward(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
                           precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):
-        """Gradients of gE * E_x; K (optional) is this input's build_K result,
-        reused for dE/dD = -K/2 instead of a rebuild."""
-        _check(lib().exchange_backward(self._h, _ptr(C), _ptr(V), _ptr(D), _ptr(K), float(gE), int(precision),
-                                       _ptr(dC), _ptr(dV), _ptr(dD), _ptr(forces),
+        """Gradients of sum_s gE[s] E_x[s] (gE: a scalar for every system, or one
+        value per system); K (optional) is this input's build_K result, reused
+        for dE/dD = -gE K/2 instead of a rebuild."""
+        i = self.info
+        c, v, d = self._cvd(C, V, D)
+        g = self.gE_tensor(gE, C.device)
+        _check(lib().exchange_backward(self._h, c, v, d, _dev(K, i["d_size"], "K", True),
+                                       _dev(g, self.n_systems, "gE"), int(precision),
+                                       _dev(dC, i["c_size"], "dC", True), _dev(dV, i["v_size"], "dV", True),
+                                       _dev(dD, i["d_size"], "dD", True), _dev(forces, 3 * self.n_atoms, "forces", True),
                                        float(c_decay), float(v_2s2), _stream(stream)))
+        self._last_gE = g   # keeps the per-system array alive while the call may still run
 
     def graph_build(self, C, V, D, K, Ex, stream, precision=PREC_FP64):
         """Capture one build_K on `stream` (a created stream) into a HIP graph."""
-        _check(lib().exx_graph_build(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K), _ptr(Ex),
-                                     _stream(stream)))
+        c, v, d = self._cvd(C, V, D)
+        _check(lib().exx_graph_build(self._h, c, v, d, int(precision), _dev(K, self.info["d_size"], "K"),
+                                     _dev(Ex, self.n_systems, "Ex", True), _stream(stream)))
 
     TUNING_NAMES = (("E k-chunk", (16, 32)), ("T2 columns x waves", ("4x4", "8x4", "8x8")), ("Y k-chunk", (16, 32)))
 
     def autotune(self, C, V, D, K, precision=PREC_FP64, stream=None):
         """Time the compiled tile variants of the E, T2 and Y stages on these
         inputs and keep the fastest (blocking); K holds a build afterwards."""
-        _check(lib().exx_plan_autotune(self._h, _ptr(C), _ptr(V), _ptr(D), int(precision), _ptr(K),
+        c, v, d = self._cvd(C, V, D)
+        _check(lib().exx_plan_autotune(self._h, c, v, d, int(precision), _dev(K, self.info["d_size"], "K"),
                                        _stream(stream)))
 
     def tuning(self):

@@ -2,7 +2,8 @@
 
 ``exchange_energy(plan, C, V, D, precision)`` returns E_x per system (FP64 or
 mixed forward); its backward calls the library's binary64 exchange_backward
-kernels for dE/dC, dE/dV and dE/dD, reusing the forward K for dE/dD.
+kernels for dE/dC, dE/dV and dE/dD with each system's upstream gradient,
+reusing the forward K for dE/dD.
 ``exchange_forces(plan, C, V, D)`` returns -dE_x/dR for the synthetic
 exp(-r/1.5) / exp(-r^2/8) position dependence of C and V.
 """
@@ -24,10 +25,7 @@ class _ExchangeEnergy(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gEx):
         C, V, D, K = ctx.saved_tensors
-        g = gEx.detach().cpu()
-        if not bool(torch.all(g == g[0])):
-            raise NotImplementedError("exchange_energy backward needs the same upstream gradient for every system")
-        gE = float(g[0])
+        gE = gEx.detach().to(torch.float64).contiguous()   # one upstream gradient per system
         need = ctx.needs_input_grad
         dC = torch.empty_like(C) if need[0] else None
         dV = torch.empty_like(V) if need[1] else None

@@ -1,7 +1,11 @@
-"""Compile libexx.so (HIP for gfx950) in-tree with hipcc."""
+"""Compile libexx.so (HIP for gfx950) in-tree with hipcc.
+
+Each translation unit is compiled on its own (in parallel), then linked."""
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -9,21 +13,37 @@ LIB = os.path.join(HERE, "libexx.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-Wno-unused-value",
 ]
-SOURCES = ["exx_device.hip", "exx_plan.cpp"]
+SOURCES = ["exx_api.hip", "exx_k_gemm.hip", "exx_k_h.hip", "exx_k_t2.hip", "exx_k_dv.hip", "exx_plan.cpp"]
 
 
-def build(verbose=False):
-    cmd = [HIPCC, *FLAGS, "-o", LIB + ".tmp", *[os.path.join(CSRC, s) for s in SOURCES]]
+def _compile(src, obj):
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libexx.so")
-    if verbose:
-        sys.stderr.write(r.stderr)
+    return src, r
+
+
+def build(verbose=False, jobs=None):
+    jobs = jobs or min(len(SOURCES), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with tempfile.TemporaryDirectory(prefix="libexx_") as tmp:
+        objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        with ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(_compile, SOURCES, objs))
+        bad = [(s, r) for s, r in results if r.returncode != 0]
+        for s, r in results:
+            if verbose or r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+        if bad:
+            raise RuntimeError("hipcc failed building " + ", ".join(s for s, _ in bad))
+        r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("linking libexx.so failed")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

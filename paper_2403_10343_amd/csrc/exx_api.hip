@@ -1,0 +1,1260 @@
+// libexx: RI-LVL exact-exchange build on MI355X (gfx950).
+//
+// Evaluates K_ik = sum_{jl} sum_{mu nu} C^mu_ij V_{mu nu} C^nu_kl D_jl for
+// non-periodic systems (lattice vector R = 0 of Eq. realspace_exchange) and
+// E_x = -1/4 sum K_ik D_ik.  Writing C^mu = M^mu + M^mu^T with M^mu the rows
+// of C^mu on the atom of mu (on-site block halved), the sum splits into the
+// terms of the paper's pair-grouped form (Eq. ri_lvl_exchange_matrix with the
+// intermediates of Eq. temp):
+//   T2 = sum V M^mu D M^nu^T      (the F*E term)
+//   T1 = sum V M^mu D M^nu        (the G term)
+//   T3 = sum V M^mu^T D M^nu      (the H term)
+//   K  = T2 + T3 + T1 + T1^T.
+// The paper's form carries 2G and is symmetrised here: with
+// H'_P = sum_Q (V_PQ (x) D_PQ) T_Q + 2 G, the product X = T^T H' equals
+// T3 + 2 T1^T and K = T2 + (X + X^T) / 2.
+//
+// Kernels of a build (all contractions on FP64 MFMA 16x16x4, or FP32 16x16x4 for the
+// far pair terms of a mixed build):
+//   k_repack     C pair blocks -> row-owned T_P
+//   k_rowD       E_P = T_P D over N2[P]              (LDS-tiled GEMM over k-runs)
+//   k_vdrepack   V_PQ and D_PQ in MFMA lane order    (coalesced operand rows)
+//   k_H          H'_P: F = V T_Q, D contraction, G part (chained MFMAs per Q)
+//   k_T2         T2 pair blocks into K               (two chained MFMA stages)
+//   k_Y          Y_P = T_P^T H'_P                    (LDS-tiled batched GEMM)
+//   k_symreduce  K = T2 + (X + X^T)/2 gathered from Y, owner-computes, atomic-free
+//   k_energy_*   E_x per system, fixed-order reduction
+#include "exx_dev.h"
+
+using namespace exx;
+
+thread_local std::string g_err;
+
+// Device copy of a host list, owned by the plan (or by mixed set m).
+template <typename X>
+static int upload(exx_plan_s* p, X*& dst, const std::vector<X>& src, MixedDev* m = nullptr) {
+  dst = nullptr;
+  if (src.empty()) return 0;
+  size_t bytes = src.size() * sizeof(X);
+  HIP_TRY(hipMalloc((void**)&dst, bytes));
+  (m ? m->allocs : p->allocs).push_back(dst);
+  (m ? m->bytes : p->dev_bytes) += bytes;
+  HIP_TRY(hipMemcpy(dst, src.data(), bytes, hipMemcpyHostToDevice));
+  return 0;
+}
+
+static int alloc_buf(exx_plan_s* p, double*& dst, int64_t n) {
+  dst = nullptr;
+  if (n <= 0) return 0;
+  HIP_TRY(hipMalloc((void**)&dst, n * sizeof(double)));
+  p->allocs.push_back(dst);
+  p->dev_bytes += n * sizeof(double);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// screening on the device: one workgroup per atom A, all B of its system in
+// chunks of 256, ordered compaction by a workgroup prefix sum.
+
+__device__ __forceinline__ bool within_cut(const double* pos, int a, int b, double rc2) {
+  double dx = __dsub_rn(pos[3 * a], pos[3 * b]);
+  double dy = __dsub_rn(pos[3 * a + 1], pos[3 * b + 1]);
+  double dz = __dsub_rn(pos[3 * a + 2], pos[3 * b + 2]);
+  double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  return r2 <= rc2;
+}
+
+__global__ __launch_bounds__(256) void k_nbr_count(const double* pos, const int* atom_sys,
+                                                   const int* sys_atom_off, double rc2, int* count) {
+  const int a = blockIdx.x;
+  const int s = atom_sys[a];
+  const int lo = sys_atom_off[s], hi = sys_atom_off[s + 1];
+  __shared__ int part[256];
+  int c = 0;
+  for (int b = lo + threadIdx.x; b < hi; b += 256) c += within_cut(pos, a, b, rc2) ? 1 : 0;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[a] = part[0];
+}
+
+__global__ __launch_bounds__(256) void k_nbr_fill(const double* pos, const int* atom_sys,
+                                                  const int* sys_atom_off, double rc2,
+                                                  const int* ptr, int* out) {
+  const int a = blockIdx.x;
+  const int s = atom_sys[a];
+  const int lo = sys_atom_off[s], hi = sys_atom_off[s + 1];
+  __shared__ int scan[256];
+  int base = ptr[a];
+  for (int b0 = lo; b0 < hi; b0 += 256) {
+    const int b = b0 + threadIdx.x;
+    const int f = (b < hi && within_cut(pos, a, b, rc2)) ? 1 : 0;
+    scan[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {  // inclusive Hillis-Steele scan
+      int v = (threadIdx.x >= w) ? scan[threadIdx.x - w] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (f) out[base + scan[threadIdx.x] - 1] = b;
+    base += scan[255];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 0: row-owned coefficients T_P from the canonical C pair blocks.
+// One workgroup per neighbour entry (P, J): the s_P x n_basis(J) sub-block.
+
+__global__ __launch_bounds__(256) void k_repack(const double* __restrict__ C, DevPlan d) {
+  const int k = blockIdx.x;
+  const int P = d.nbr_owner[k], J = d.nbr_atom[k], p = d.nbr_pair[k];
+  const int aP = d.na[P], bP = d.nb[P], bJ = d.nb[J], aJ = d.na[J];
+  const int nP = d.n_loc[P], lc = d.nbr_lcol[k];
+  const int sP = aP * bP;
+  const double* Cp = C + d.c_off[p];
+  double* TP = d.T + d.t_off[P];
+  const int nel = sP * bJ;
+  for (int e = threadIdx.x; e < nel; e += 256) {
+    const int r = e / bJ, j = e - r * bJ;
+    const int mu = r / bP, i = r - mu * bP;
+    double v;
+    if (P < J)
+      v = Cp[(size_t)(mu * bP + i) * bJ + j];
+    else if (P > J)
+      v = Cp[(size_t)((aJ + mu) * bJ + j) * bP + i];
+    else
+      v = 0.5 * Cp[(size_t)(mu * bP + i) * bP + j];
+    TP[(size_t)r * nP + lc + j] = v;
+  }
+}
+
+
+// The V-stage operands in MFMA lane order (DevPlan::Vr, Dr), one workgroup per canonical
+// pair, both orientations.
+// V == nullptr: the D operands only (into Dr)
+__global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, const double* __restrict__ D,
+                                                 double* __restrict__ Dr, DevPlan d) {
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const double* Vp = V ? V + d.v_off[p] : nullptr;
+  const int s = d.atom_sys[A];
+  const int64_t ns = d.sys_n[s];
+  const double* Ds = D + d.sys_d_off[s];
+  for (int o = 0; o < (A == B ? 1 : 2); ++o) {
+    const int P = o ? B : A, Q = o ? A : B;
+    const int aP = d.na[P], aQ = d.na[Q], bP = d.nb[P], bQ = d.nb[Q];
+    const int nsq = (aQ + 3) / 4;
+    double* vr = d.Vr + d.vr_off[2 * p + o];
+    const int nv = V ? (int)(d.vr_off[2 * p + o + 1] - d.vr_off[2 * p + o]) : 0;
+    for (int e = threadIdx.x; e < nv; e += 256) {
+      const int L = e & 63, tq = e >> 6, q = tq % nsq, t = tq / nsq;
+      const int mu = 16 * t + (L & 15), nu = 4 * q + (L >> 4);
+      vr[e] = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
+    }
+    double* dr = Dr + d.dr_off[2 * p + o];
+    const int nd = (int)(d.dr_off[2 * p + o + 1] - d.dr_off[2 * p + o]);
+    for (int e = threadIdx.x; e < nd; e += 256) {
+      const int L = e & 63, q = e >> 6;
+      const int j = L & 15, l = (L >> 4) + 4 * q;   // the f64 MFMA A-operand row of lane L, step q
+      dr[e] = (j < bP && l < bQ) ? Ds[(size_t)(d.bo[P] + j) * ns + d.bo[Q] + l] : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energy: sum_ik K_ik D_ik over the screened pair blocks (D beyond the cutoff
+// counts as zero), per chunk of canonical pairs a workgroup tree reduction,
+// then per system an ordered sum of its chunks.  n_spin density matrices (and
+// their K) are stored spin_stride apart; the chunk sums run over all.
+
+__global__ __launch_bounds__(256) void k_energy_part(const double* __restrict__ K, const double* __restrict__ D,
+                                                     DevPlan d, int n_chunks, int n_spin, int64_t spin_stride,
+                                                     double* __restrict__ part_out) {
+  const int c = blockIdx.x;
+  if (c >= n_chunks) return;
+  const int s = d.en_sys[c];
+  const int64_t base = d.sys_d_off[s], ns = d.sys_n[s];
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int p = d.en_pbeg[c]; p < d.en_pend[c]; ++p) {
+    const int A = d.pair_a[p], B = d.pair_b[p];
+    const int bA = d.nb[A], bB = d.nb[B];
+    const int64_t oA = d.bo[A], oB = d.bo[B];
+    for (int sp = 0; sp < n_spin; ++sp) {
+      const double* Ks = K + sp * spin_stride + base;
+      const double* Ds = D + sp * spin_stride + base;
+      for (int e = threadIdx.x; e < bA * bB; e += 256) {
+        const int i = e / bB, k = e - i * bB;
+        const int64_t x = (oA + i) * ns + oB + k;
+        acc += Ks[x] * Ds[x];
+        if (A != B) {
+          const int64_t y = (oB + k) * ns + oA + i;
+          acc += Ks[y] * Ds[y];
+        }
+      }
+    }
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part_out[c] = part[0];
+}
+
+// scale: -1/4 for one (spin-summed) density matrix, -1/2 for the two spin density matrices
+__global__ void k_energy_sum(double* Ex, DevPlan d, int n_chunks, double scale, const double* __restrict__ part) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n_sys) return;
+  double acc = 0.0;
+  for (int c = 0; c < n_chunks; ++c)
+    if (d.en_sys[c] == s) acc += part[c];
+  Ex[s] = scale * acc;
+}
+
+// Dm = D on the screened pair blocks (one workgroup per canonical pair, both
+// orientations); entries outside them stay zero from the plan's set-up.
+__global__ __launch_bounds__(256) void k_dmask(const double* __restrict__ D, double* __restrict__ Dm, DevPlan d) {
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const int s = d.atom_sys[A];
+  const int64_t base = d.sys_d_off[s], ns = d.sys_n[s];
+  const int bA = d.nb[A], bB = d.nb[B];
+  const int64_t oA = d.bo[A], oB = d.bo[B];
+  for (int e = threadIdx.x; e < bA * bB; e += 256) {
+    const int i = e / bB, k = e - i * bB;
+    const int64_t x = base + (oA + i) * ns + oB + k, y = base + (oB + k) * ns + oA + i;
+    Dm[x] = D[x];
+    Dm[y] = D[y];
+  }
+}
+
+__global__ void k_zero(double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// backward.  dE/dC^mu = -1/2 sum_nu V_{mu nu} D C^nu D.  With the row-owned
+// M^mu, the gradient per row-owned entry is -sum_nu V_{mu nu} (D C^nu D) on
+// rows of P; writing C^nu = M^nu + M^nu^T gives the rows-of-P blocks
+//   G_P = (H_P + Gt_P) D,   H_P = rows of P of D F^mu,  F^mu = sum_nu V M^nu,
+// where Gt_P is exactly the G term of the forward V stage taken once.  The
+// un-repack maps G_P back to the canonical C layout (the on-site halving
+// of the repack appears as a factor 1/2).
+
+__global__ __launch_bounds__(256) void k_unrepack(const double* __restrict__ GD, double* __restrict__ dC,
+                                                  DevPlan d, const double* __restrict__ gE, double a) {
+  const int k = blockIdx.x;
+  const int P = d.nbr_owner[k], J = d.nbr_atom[k], p = d.nbr_pair[k];
+  const int aP = d.na[P], bP = d.nb[P], bJ = d.nb[J], aJ = d.na[J];
+  const int nP = d.n_loc[P], lc = d.nbr_lcol[k];
+  const int sP = aP * bP;
+  double* Cp = dC + d.c_off[p];
+  const double* GP = GD + d.t_off[P];
+  const double scale = a * gE[d.atom_sys[P]];
+  const int nel = sP * bJ;
+  for (int e = threadIdx.x; e < nel; e += 256) {
+    const int r = e / bJ, j = e - r * bJ;
+    const int mu = r / bP, i = r - mu * bP;
+    const double v = scale * GP[(size_t)r * nP + lc + j];
+    if (P < J)
+      Cp[(size_t)(mu * bP + i) * bJ + j] = v;
+    else if (P > J)
+      Cp[(size_t)((aJ + mu) * bJ + j) * bP + i] = v;
+    else
+      Cp[(size_t)(mu * bP + i) * bP + j] = 0.5 * v;
+  }
+}
+
+// <X, Y> over every canonical pair block (offsets off[p]..off[p+1]),
+// fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_block_dot(const double* __restrict__ X, const double* __restrict__ Y,
+                                                   const int64_t* __restrict__ off, double* __restrict__ out) {
+  const int p = blockIdx.x;
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int64_t e = off[p] + threadIdx.x; e < off[p + 1]; e += 256) acc += X[e] * Y[e];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = part[0];
+}
+
+// forces: -dE/dR_A = -sum_{J in N[A], J != A} [sC (-1/c_decay) d/r + sV (-2/v_2s2) d],
+// d = R_A - R_J; sC, sV are the per-pair <gradient, block> sums.
+__global__ void k_forces(const double* __restrict__ pos, const double* __restrict__ sC,
+                         const double* __restrict__ sV, double* __restrict__ F, DevPlan d,
+                         double c_decay, double v_2s2) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= d.n_atoms) return;
+  double f0 = 0, f1 = 0, f2 = 0;
+  for (int k = d.nbr_ptr[A]; k < d.nbr_ptr[A + 1]; ++k) {
+    const int J = d.nbr_atom[k];
+    if (J == A) continue;
+    const int p = d.nbr_pair[k];
+    const double dx = pos[3 * A] - pos[3 * J], dy = pos[3 * A + 1] - pos[3 * J + 1], dz = pos[3 * A + 2] - pos[3 * J + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double gc = sC[p] * (-1.0 / c_decay) / r, gv = sV[p] * (-2.0 / v_2s2);
+    f0 -= (gc + gv) * dx;
+    f1 -= (gc + gv) * dy;
+    f2 -= (gc + gv) * dz;
+  }
+  F[3 * A] = f0;
+  F[3 * A + 1] = f1;
+  F[3 * A + 2] = f2;
+}
+
+// y = a gE[s] x over the dense block of every system s (blockIdx.y = s); y == x scales in place
+__global__ void k_scaled_copy_sys(double* y, const double* x, const double* __restrict__ gE, DevPlan d, double a) {
+  const int s = blockIdx.y;
+  const int64_t b = d.sys_d_off[s], n = d.sys_d_off[s + 1] - b;
+  const double f = a * gE[s];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[b + i] = f * x[b + i];
+}
+
+// ---------------------------------------------------------------------------
+// plan creation
+
+static int device_neighbors(exx_plan_s* pl) {
+  HostPlan& hp = pl->hp;
+  double* dpos = nullptr;
+  int *dsys = nullptr, *doff = nullptr, *dcnt = nullptr, *dptr = nullptr, *dout = nullptr;
+  auto cleanup = [&]() {
+    hipFree(dpos); hipFree(dsys); hipFree(doff); hipFree(dcnt); hipFree(dptr); hipFree(dout);
+  };
+  const int NA = hp.n_atoms;
+  hipError_t e = hipSuccess;
+#define NB_TRY(x) do { e = (x); if (e != hipSuccess) { cleanup(); return fail(EXX_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e)); } } while (0)
+  NB_TRY(hipMalloc((void**)&dpos, sizeof(double) * 3 * NA));
+  NB_TRY(hipMalloc((void**)&dsys, sizeof(int) * NA));
+  NB_TRY(hipMalloc((void**)&doff, sizeof(int) * (hp.n_sys + 1)));
+  NB_TRY(hipMalloc((void**)&dcnt, sizeof(int) * NA));
+  NB_TRY(hipMemcpy(dpos, hp.pos.data(), sizeof(double) * 3 * NA, hipMemcpyHostToDevice));
+  NB_TRY(hipMemcpy(dsys, hp.atom_sys.data(), sizeof(int) * NA, hipMemcpyHostToDevice));
+  NB_TRY(hipMemcpy(doff, hp.sys_atom_off.data(), sizeof(int) * (hp.n_sys + 1), hipMemcpyHostToDevice));
+  const double rc2 = hp.r_cut * hp.r_cut;
+  hipLaunchKernelGGL(k_nbr_count, dim3(NA), dim3(256), 0, 0, dpos, dsys, doff, rc2, dcnt);
+  NB_TRY(hipGetLastError());
+  std::vector<int> cnt(NA);
+  NB_TRY(hipMemcpy(cnt.data(), dcnt, sizeof(int) * NA, hipMemcpyDeviceToHost));
+  hp.nbr_ptr.assign(NA + 1, 0);
+  for (int a = 0; a < NA; ++a) hp.nbr_ptr[a + 1] = hp.nbr_ptr[a] + cnt[a];
+  NB_TRY(hipMalloc((void**)&dptr, sizeof(int) * (NA + 1)));
+  NB_TRY(hipMalloc((void**)&dout, sizeof(int) * std::max(1, hp.nbr_ptr[NA])));
+  NB_TRY(hipMemcpy(dptr, hp.nbr_ptr.data(), sizeof(int) * (NA + 1), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_nbr_fill, dim3(NA), dim3(256), 0, 0, dpos, dsys, doff, rc2, dptr, dout);
+  NB_TRY(hipGetLastError());
+  hp.nbr_atom.resize(hp.nbr_ptr[NA]);
+  NB_TRY(hipMemcpy(hp.nbr_atom.data(), dout, sizeof(int) * hp.nbr_ptr[NA], hipMemcpyDeviceToHost));
+#undef NB_TRY
+  cleanup();
+  return 0;
+}
+
+static int upload_plan(exx_plan_s* pl) {
+  HostPlan& hp = pl->hp;
+  DevPlan& d = pl->d;
+  d.n_atoms = hp.n_atoms;
+  d.n_sys = hp.n_sys;
+  int rc = 0;
+#define UP(field) if ((rc = upload(pl, d.field, hp.field)) != 0) return rc
+  UP(nb); UP(na); UP(atom_sys); UP(bo); UP(sys_n); UP(sys_d_off);
+  UP(nbr_ptr); UP(nbr_atom); UP(nbr_pair); UP(nbr_lcol); UP(nbr_owner);
+  UP(pair_a); UP(pair_b); UP(c_off); UP(v_off); UP(n_loc); UP(m_loc);
+  UP(map_off); UP(col1g_off); UP(col2g_off); UP(map1); UP(map2); UP(col1g); UP(col2g);
+  UP(t_off); UP(ct_run_ptr); UP(ct_klen); UP(runs);
+  UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
+  UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
+  UP(gq); UP(gx); UP(en_sys); UP(en_pbeg); UP(en_pend);
+#undef UP
+  if ((rc = upload(pl, pl->g_tiles_all, hp.g_tiles))) return rc;
+  if ((rc = upload(pl, pl->y_tiles_all, hp.y_tiles))) return rc;
+  if ((rc = upload(pl, pl->gd_items_all, hp.gd_items))) return rc;
+  d.g_tiles = pl->g_tiles_all;
+  // chunk lists: the global lists for an unbounded plan, else one set per chunk
+  if (hp.chunks.empty()) {
+    ChunkDev c;
+    if ((rc = upload(pl, c.e_items, hp.e_items))) return rc;
+    c.n_e = (int)hp.e_items.size();
+    c.gt_end = (int)hp.g_tiles.size();
+    c.y_end = (int)hp.y_tiles.size();
+    c.gd_end = (int)hp.gd_items.size();
+    if ((rc = upload(pl, c.t2_items, hp.t2_items))) return rc;
+    c.t2_classes = hp.t2_classes;
+    if ((rc = upload(pl, c.dv_items, hp.dv_items))) return rc;
+    c.dv_classes = hp.dv_classes;
+    if ((rc = upload(pl, c.f_items, hp.f_items))) return rc;
+    c.n_f = (int)hp.f_items.size();
+    if ((rc = upload(pl, c.f_plist, hp.f_plist))) return rc;
+    if ((rc = upload(pl, c.e_off, hp.e_off))) return rc;
+    c.h_off = c.e_off;   // H'_P and E_P share the layout
+    if ((rc = upload(pl, c.y_off, hp.y_off))) return rc;
+    c.h_base = hp.e_total;
+    c.y_base = 2 * hp.e_total;
+    pl->chunks.push_back(std::move(c));
+  } else {
+    for (const ChunkHost& h : hp.chunks) {
+      ChunkDev c;
+      if ((rc = upload(pl, c.e_items, h.e_items))) return rc;
+      c.n_e = (int)h.e_items.size();
+      c.gt_beg = h.gt_beg; c.gt_end = h.gt_end;
+      c.y_beg = h.y_beg; c.y_end = h.y_end;
+      c.gd_beg = h.gd_beg; c.gd_end = h.gd_end;
+      if ((rc = upload(pl, c.t2_items, h.t2_items))) return rc;
+      c.t2_classes = h.t2_classes;
+      if ((rc = upload(pl, c.dv_items, h.dv_items))) return rc;
+      c.dv_classes = h.dv_classes;
+      if ((rc = upload(pl, c.f_items, h.f_items))) return rc;
+      c.n_f = (int)h.f_items.size();
+      if ((rc = upload(pl, c.f_plist, h.f_plist))) return rc;
+      if ((rc = upload(pl, c.e_off, h.e_off))) return rc;
+      if ((rc = upload(pl, c.h_off, h.h_off))) return rc;
+      if ((rc = upload(pl, c.y_off, h.y_off))) return rc;
+      c.h_base = h.e_total;
+      c.y_base = h.e_total + h.h_total;
+      pl->chunks.push_back(std::move(c));
+    }
+  }
+  if ((rc = alloc_buf(pl, d.T, hp.t_total))) return rc;
+  if ((rc = alloc_buf(pl, pl->W, hp.ws_total))) return rc;
+  if ((rc = alloc_buf(pl, d.GD, hp.t_total))) return rc;
+  if ((rc = alloc_buf(pl, d.sC, (int64_t)hp.pair_a.size()))) return rc;
+  if ((rc = alloc_buf(pl, d.sV, (int64_t)hp.pair_a.size()))) return rc;
+  if ((rc = alloc_buf(pl, d.epart, std::max<int64_t>(1, (int64_t)hp.en_sys.size())))) return rc;
+  if ((rc = alloc_buf(pl, d.Dm, std::max<int64_t>(1, hp.d_size)))) return rc;
+  HIP_TRY(hipMemset(d.Dm, 0, sizeof(double) * std::max<int64_t>(1, hp.d_size)));
+  const size_t np = hp.pair_a.size();
+  std::vector<int64_t> vro(2 * np + 1, 0), dro(2 * np + 1, 0);
+  for (size_t p = 0; p < np; ++p) {
+    const int A = hp.pair_a[p], B = hp.pair_b[p];
+    const int64_t v0 = (int64_t)((hp.na[A] + 15) / 16) * ((hp.na[B] + 3) / 4) * 64;
+    const int64_t v1 = A == B ? 0 : (int64_t)((hp.na[B] + 15) / 16) * ((hp.na[A] + 3) / 4) * 64;
+    const int64_t d0 = (int64_t)((hp.nb[B] + 3) / 4) * 64, d1 = A == B ? 0 : (int64_t)((hp.nb[A] + 3) / 4) * 64;
+    vro[2 * p + 1] = vro[2 * p] + v0;
+    vro[2 * p + 2] = vro[2 * p + 1] + v1;
+    dro[2 * p + 1] = dro[2 * p] + d0;
+    dro[2 * p + 2] = dro[2 * p + 1] + d1;
+  }
+  if ((rc = upload(pl, d.vr_off, vro))) return rc;
+  if ((rc = upload(pl, d.dr_off, dro))) return rc;
+  if ((rc = alloc_buf(pl, d.Vr, std::max<int64_t>(1, vro.back())))) return rc;
+  if ((rc = alloc_buf(pl, d.Dr, std::max<int64_t>(1, dro.back())))) return rc;
+  pl->dr_total = dro.back();
+  set_chunk(pl, 0);
+  return 0;
+}
+
+void set_chunk(exx_plan pl, int c) {
+  ChunkDev& ch = pl->chunks[c];
+  DevPlan& d = pl->d;
+  pl->cur = c;
+  d.e_items = ch.e_items;
+  d.t2_items = ch.t2_items;
+  d.dv_items = ch.dv_items;
+  d.f_items = ch.f_items;
+  d.f_plist = ch.f_plist;
+  d.e_off = ch.e_off;
+  d.h_off = ch.h_off;
+  d.y_off = ch.y_off;
+  d.y_tiles = pl->y_tiles_all + ch.y_beg;
+  d.gd_items = pl->gd_items_all + ch.gd_beg;
+  d.E = pl->W;
+  d.H = pl->W ? pl->W + ch.h_base : nullptr;
+  d.Y = pl->W ? pl->W + ch.y_base : nullptr;
+}
+
+static void free_mixed(MixedDev& m) {
+  for (void* p : m.allocs) hipFree(p);
+  m = MixedDev{};
+}
+
+static void release(exx_plan_s* pl) {
+  if (pl->graph_exec) hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) hipGraphDestroy(pl->graph);
+  pl->graph_exec = nullptr;
+  pl->graph = nullptr;
+  for (void* p : pl->allocs) hipFree(p);
+  pl->allocs.clear();
+  for (MixedDev& m : pl->mdev) free_mixed(m);
+  for (hipEvent_t e : pl->events) hipEventDestroy(e);
+  pl->events.clear();
+}
+
+// Record boundary `i` of the current profiled build (no-op when off or full).
+static void stage_mark(exx_plan_s* pl, int i, hipStream_t st) {
+  if (!pl->profiling || pl->n_recorded >= MAX_PROFILED) return;
+  hipEventRecord(pl->events[(size_t)pl->n_recorded * N_STAGE_EV + i], st);
+  if (i == N_STAGE_EV - 1) ++pl->n_recorded;
+}
+
+extern "C" {
+
+const char* exx_last_error(void) { return g_err.c_str(); }
+
+int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_bytes, exx_plan* out) {
+  g_err.clear();
+  if (!out) return fail(EXX_EINVAL, "exx_plan_create: out is NULL");
+  *out = nullptr;
+  if (!sys) return fail(EXX_EINVAL, "exx_plan_create: sys is NULL");
+  exx_plan_s* pl = new (std::nothrow) exx_plan_s();
+  if (!pl) return fail(EXX_ENOMEM, "exx_plan_create: host allocation");
+  pl->host_only = (flags & EXX_PLAN_HOST_ONLY) != 0;
+  std::string err;
+  int rc = describe_system(sys->n_atoms, sys->n_species, sys->species, sys->positions, sys->n_basis,
+                           sys->n_aux, sys->r_cut, sys->n_systems, sys->sys_atom_off, sys->lattice, pl->hp, err);
+  if (rc != 0) {
+    delete pl;
+    return fail(rc, err);
+  }
+  if (pl->host_only) {
+    host_neighbors(pl->hp);
+  } else {
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+      delete pl;
+      return fail(EXX_EDEVICE, "exx_plan_create: no HIP device");
+    }
+    if ((rc = device_neighbors(pl)) != 0) {
+      delete pl;
+      return rc;
+    }
+  }
+  if (ws_budget_bytes > (size_t)INT64_MAX) ws_budget_bytes = (size_t)INT64_MAX;
+  try {
+    rc = derive_lists(pl->hp, err);
+    if (rc != 0) {
+      delete pl;
+      return fail(EXX_EDEVICE, err);
+    }
+    rc = derive_chunks(pl->hp, (int64_t)ws_budget_bytes, err);
+  } catch (const std::bad_alloc&) {
+    delete pl;
+    return fail(EXX_ENOMEM, "exx_plan_create: host allocation in list building");
+  }
+  if (rc != 0) {
+    delete pl;
+    return fail(EXX_ENOMEM, err);
+  }
+  {
+    int amax = 1;
+    for (int a = 0; a < pl->hp.n_atoms; ++a) amax = std::max(amax, pl->hp.na[a]);
+    pl->t2_nt = (amax + 15) / 16;
+    int smax = 1;
+    for (int a = 0; a < pl->hp.n_atoms; ++a) smax = std::max(smax, pl->hp.na[a] * pl->hp.nb[a]);
+    // k_H: T_Q tile | V blocks [nu][aux rows of the group] | D blocks
+    int vr_max = 1;
+    const HostPlan& hq = pl->hp;
+    for (size_t g = 0; g + 1 < hq.grp_unit_ptr.size(); ++g) {
+      const int nsl = hq.grp_units[hq.grp_unit_ptr[g + 1] - 1].slot + 1;
+      int vr = 0;
+      for (int t = 0; t < nsl; ++t) vr += hq.na[hq.grp_first[g] + t];
+      vr_max = std::max(vr_max, vr);
+    }
+    // rows of the staged T_Q read by the chains: up to 4 NS * n_b(Q) + 16 (NS of Q's shape class)
+    int h_rows = smax;
+    for (int a = 0; a < pl->hp.n_atoms; ++a) {
+      const int nsq = (pl->hp.na[a] + 3) / 4, nlq = (pl->hp.nb[a] + 3) / 4;
+      const int NS = (nsq <= 4 && nlq <= 2) ? 4 : (nsq <= 10 ? 10 : 16);
+      h_rows = std::max(h_rows, 4 * NS * pl->hp.nb[a] + 16);
+    }
+    pl->h_vbase = h_rows * LDS_PITCH;
+    pl->h_dbase = amax * vr_max;
+    const size_t h_elems = (size_t)pl->h_vbase + pl->h_dbase + GROUP_ATOMS * 16 * H_DPITCH;
+    pl->h_lds = (size_t)pl->h_vbase * sizeof(double);   // the binary64 kernel stages T_Q only
+    pl->t2_lds = std::max((size_t)2 * smax * T2_PITCH, (size_t)16 * 64) * sizeof(double);
+    pl->h_smax_t2 = smax;
+    pl->h_lds32 = h_elems * sizeof(float);
+    pl->t2_lds32 = std::max((size_t)2 * smax * T2_PITCH * sizeof(float), (size_t)16 * 64 * sizeof(double));
+  }
+  if (!pl->host_only) {
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) != hipSuccess) {
+      delete pl;
+      return fail(EXX_EDEVICE, "exx_plan_create: cannot query the LDS size");
+    }
+    pl->lds_max = lds_max;
+    if (pl->t2_lds > (size_t)lds_max || pl->h_lds + 8192 > (size_t)lds_max) {   // static LDS of k_H < 8 KB
+      delete pl;
+      return fail(EXX_EUNSUPPORTED, "exx_plan_create: the largest n_aux * n_basis needs more LDS than a workgroup has");
+    }
+    if ((rc = upload_plan(pl)) != 0) {
+      release(pl);
+      delete pl;
+      return rc;
+    }
+  }
+  *out = pl;
+  return EXX_OK;
+}
+
+int exx_plan_destroy(exx_plan plan) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_destroy: NULL plan");
+  release(plan);
+  delete plan;
+  return EXX_OK;
+}
+
+int exx_plan_info(exx_plan plan, exx_info* info) {
+  if (!plan || !info) return fail(EXX_EINVAL, "exx_plan_info: NULL argument");
+  const HostPlan& hp = plan->hp;
+  info->n_atoms = hp.n_atoms;
+  info->n_systems = hp.n_sys;
+  info->n_pairs = (int64_t)hp.pair_a.size();
+  info->c_size = hp.c_off.empty() ? 0 : hp.c_off.back();
+  info->v_size = hp.v_off.empty() ? 0 : hp.v_off.back();
+  info->d_size = hp.d_size;
+  info->n_basis_max = hp.n_basis_max;
+  info->workspace_bytes = plan->dev_bytes + plan->mdev[0].bytes + plan->mdev[1].bytes;
+  info->flops_fp64 = hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
+  info->n_chunks = hp.chunks.empty() ? 1 : (int64_t)hp.chunks.size();
+  info->intermediate_bytes = (int64_t)sizeof(double) * hp.ws_total;
+  info->intermediate_bytes_stored = hp.inter_stored;
+  return EXX_OK;
+}
+
+int exx_pair_layout(exx_plan plan, int32_t* pair_a, int32_t* pair_b, int64_t* c_off, int64_t* v_off) {
+  if (!plan) return fail(EXX_EINVAL, "exx_pair_layout: NULL plan");
+  const HostPlan& hp = plan->hp;
+  const size_t n = hp.pair_a.size();
+  if (pair_a) std::memcpy(pair_a, hp.pair_a.data(), n * sizeof(int32_t));
+  if (pair_b) std::memcpy(pair_b, hp.pair_b.data(), n * sizeof(int32_t));
+  if (c_off) std::memcpy(c_off, hp.c_off.data(), (n + 1) * sizeof(int64_t));
+  if (v_off) std::memcpy(v_off, hp.v_off.data(), (n + 1) * sizeof(int64_t));
+  return EXX_OK;
+}
+
+int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom) {
+  if (!plan || !nbr_ptr) return fail(EXX_EINVAL, "exx_plan_neighbors: NULL argument");
+  const HostPlan& hp = plan->hp;
+  std::memcpy(nbr_ptr, hp.nbr_ptr.data(), hp.nbr_ptr.size() * sizeof(int32_t));
+  if (nbr_atom) std::memcpy(nbr_atom, hp.nbr_atom.data(), hp.nbr_atom.size() * sizeof(int32_t));
+  return EXX_OK;
+}
+
+int64_t exx_plan_flops(exx_plan plan, int stage) {
+  if (!plan) return -1;
+  const HostPlan& hp = plan->hp;
+  if (stage < 0) return hp.flops[0] + hp.flops[1] + hp.flops[2] + hp.flops[3] + hp.flops[4];
+  if (stage >= 10 && stage <= 14) return hp.issued[stage - 10];
+  if (stage >= 20 && stage <= 44 && stage % 10 <= 4) {
+    if (!plan->hp.mixed[0].ready) derive_mixed_lists(plan->hp, 0);
+    const MixedSet& m = hp.mixed[0];
+    if (stage < 30) return m.flops32[stage - 20];
+    if (stage < 40) return m.issued32[stage - 30];
+    return m.issued64[stage - 40];
+  }
+  if (stage > 4) return -1;
+  return hp.flops[stage];
+}
+
+// E_x of every system; part: device buffer of one double per energy chunk
+static int launch_energy(exx_plan plan, const double* K, const double* D, double* Ex, hipStream_t st,
+                         int n_spin = 1, double* part = nullptr) {
+  const int nch = (int)plan->hp.en_sys.size();
+  if (!part) part = plan->d.epart;
+  if (nch > 0)
+    hipLaunchKernelGGL(k_energy_part, dim3(nch), dim3(256), 0, st, K, D, plan->d, nch, n_spin, plan->hp.d_size, part);
+  hipLaunchKernelGGL(k_energy_sum, dim3((plan->hp.n_sys + 63) / 64), dim3(64), 0, st, Ex, plan->d, nch,
+                     n_spin == 1 ? -0.25 : -0.5, (const double*)part);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+int exx_plan_set_profiling(exx_plan plan, int enable) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_set_profiling: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_plan_set_profiling: host-only plan");
+  if (enable && plan->events.empty()) {
+    plan->events.resize((size_t)MAX_PROFILED * N_STAGE_EV);
+    for (auto& e : plan->events) HIP_TRY(hipEventCreate(&e));
+  }
+  plan->profiling = enable != 0;
+  plan->n_recorded = 0;
+  return EXX_OK;
+}
+
+int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds) {
+  if (!plan || !ms || !n_builds) return fail(EXX_EINVAL, "exx_plan_stage_times: NULL argument");
+  for (int i = 0; i < EXX_N_STAGES; ++i) ms[i] = 0.0;
+  *n_builds = plan->n_recorded;
+  for (int b = 0; b < plan->n_recorded; ++b) {
+    hipEvent_t* ev = &plan->events[(size_t)b * N_STAGE_EV];
+    HIP_TRY(hipEventSynchronize(ev[N_STAGE_EV - 1]));
+    for (int i = 0; i < EXX_N_STAGES; ++i) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[i] += t;
+    }
+  }
+  plan->n_recorded = 0;
+  return EXX_OK;
+}
+
+static RowD rowd_E(exx_plan plan) {
+  DevPlan& d = plan->d;
+  return RowD{d.T, d.t_off, d.n_loc, d.E, d.e_off, d.m_loc, d.col2g, d.col2g_off,
+              d.e_items, d.ct_run_ptr, d.ct_klen, d.runs};
+}
+
+static RowD rowd_GD(exx_plan plan) {
+  DevPlan& d = plan->d;
+  return RowD{d.H, d.h_off, d.m_loc, d.GD, d.t_off, d.n_loc, d.col1g, d.col1g_off,
+              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs};
+}
+
+static const ChunkDev& cur_chunk(exx_plan plan) { return plan->chunks[plan->cur]; }
+
+// Dm: the caller's D on the screened pair blocks (everything the E = M D
+// product and the gradient product read of D)
+static void launch_dmask(exx_plan plan, const double* D, double* Dm, hipStream_t st) {
+  const unsigned np = (unsigned)plan->hp.pair_a.size();
+  if (np) hipLaunchKernelGGL(k_dmask, dim3(np), dim3(256), 0, st, D, Dm, plan->d);
+}
+
+static void launch_repack(exx_plan plan, const double* C, hipStream_t st) {
+  const HostPlan& hp = plan->hp;
+  hipLaunchKernelGGL(k_repack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, C, plan->d);
+}
+
+// E_P = T_P Dm for the atoms of the current chunk
+static void launch_E(exx_plan plan, hipStream_t st) {
+  launch_rowD(plan, plan->d.Dm, rowd_E(plan), cur_chunk(plan).n_e, st);
+}
+
+// the lane-ordered V and D operands of the V stage (DevPlan::Vr, Dr) for these V and D
+static void launch_vd_operands(exx_plan plan, const double* V, const double* D, hipStream_t st) {
+  const unsigned np = (unsigned)plan->hp.pair_a.size();
+  if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d.Dr, plan->d);
+}
+
+// V stage (binary64) of the current chunk's groups; the operands must be in place
+static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int mode, hipStream_t st) {
+  const DevPlan& d = plan->d;
+  const ChunkDev& ch = cur_chunk(plan);
+  launch_H_lists<double>(plan, V, D, HLists{d.g_tiles + ch.gt_beg, d.gq, d.gx, plan->h_vbase, plan->h_dbase},
+                         ch.gt_end - ch.gt_beg, gscale, mode, st);
+}
+
+// V stage of a mixed build (list set m): near pairs stored in binary64, far pairs added in binary32
+static void stage_mark(exx_plan_s* pl, int i, hipStream_t st);
+static void launch_H_mixed(exx_plan plan, int m, const double* V, const double* D, hipStream_t st) {
+  const ChunkDev& ch = cur_chunk(plan);
+  const MixedDev& md = plan->mdev[m];
+  const std::vector<int>& src = plan->hp.mixed[m].far_src;
+  const int fb = (int)(std::lower_bound(src.begin(), src.end(), ch.gt_beg) - src.begin());
+  const int fe = (int)(std::lower_bound(src.begin(), src.end(), ch.gt_end) - src.begin());
+  launch_H_lists<double>(plan, V, D, HLists{md.tiles_near + ch.gt_beg, md.q_near, md.x_near, plan->h_vbase, plan->h_dbase},
+                         ch.gt_end - ch.gt_beg, 2.0, H_WRITE, st);
+  stage_mark(plan, 3, st);
+  launch_H_lists<float>(plan, V, D, HLists{md.tiles_far + fb, md.q_far, md.x_far, plan->h_vbase, plan->h_dbase},
+                        fe - fb, 2.0, H_ADD, st);
+}
+
+// one launch per shape class (aux tiles of P, nu steps of Q) and precision
+// spin: both spin density matrices in one pass (binary64 lists; K holds K^0 then K^1)
+static void launch_T2_spin(exx_plan plan, const double* V, double* K, hipStream_t st) {
+  const ChunkDev& ch = cur_chunk(plan);
+  for (const T2Class& c : ch.t2_classes) launch_T2_class<double, 2>(plan, c, V, K, ch.t2_items, st);
+}
+
+// m < 0: the binary64 lists; else the classes of mixed set m in precision prec
+static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st, int m = -1, int prec = 0) {
+  const ChunkDev& ch = cur_chunk(plan);
+  if (m < 0) {
+    for (const T2Class& c : ch.t2_classes) launch_T2_class<double>(plan, c, V, K, ch.t2_items, st);
+    return;
+  }
+  for (const T2Class& c : ch.t2m_classes[m]) {
+    if (c.prec != prec) continue;
+    if (c.prec) launch_T2_class<float>(plan, c, V, K, ch.t2m_items[m], st);
+    else launch_T2_class<double>(plan, c, V, K, ch.t2m_items[m], st);
+  }
+}
+
+// device copies of the near / far lists of mixed set m at its split distance
+static int prepare_mixed(exx_plan pl, int m) {
+  MixedDev& md = pl->mdev[m];
+  if (md.uploaded) return EXX_OK;
+  HostPlan& hp = pl->hp;
+  MixedSet& ms = hp.mixed[m];
+  if (!ms.ready) derive_mixed_lists(hp, m);
+  free_mixed(md);
+  int rc = 0;
+  if ((rc = upload(pl, md.tiles_near, ms.tiles_near, &md))) return rc;
+  if ((rc = upload(pl, md.tiles_far, ms.tiles_far, &md))) return rc;
+  if ((rc = upload(pl, md.q_near, ms.q_near, &md))) return rc;
+  if ((rc = upload(pl, md.x_near, ms.x_near, &md))) return rc;
+  if ((rc = upload(pl, md.q_far, ms.q_far, &md))) return rc;
+  if ((rc = upload(pl, md.x_far, ms.x_far, &md))) return rc;
+  if (hp.chunks.empty()) {
+    if ((rc = upload(pl, md.t2_items, ms.t2_items, &md))) return rc;
+    pl->chunks[0].t2m_items[m] = md.t2_items;
+    pl->chunks[0].t2m_classes[m] = ms.t2_classes;
+  } else {
+    for (size_t c = 0; c < hp.chunks.size(); ++c) {
+      if ((rc = upload(pl, pl->chunks[c].t2m_items[m], ms.chunk_t2_items[c], &md))) return rc;
+      pl->chunks[c].t2m_classes[m] = ms.chunk_t2_classes[c];
+    }
+  }
+  md.uploaded = true;
+  return EXX_OK;
+}
+
+static void launch_final(exx_plan plan, double* K, hipStream_t st) {
+  launch_Y(plan, plan->tune[TUNE_Y], st);
+  launch_symreduce(plan, K, st);
+}
+
+static int n_chunks(exx_plan plan) { return (int)plan->chunks.size(); }
+
+// The chunk loop of one K build (D masked into Dm, C repacked into T, K zeroed
+// before): per chunk E, the V stage, T2 and the final contraction, in this
+// order, every part added into K.  m < 0: binary64; else mixed set m.
+static void build_chunks(exx_plan plan, const double* V, const double* D, double* K, int m, hipStream_t st) {
+  for (int c = 0; c < n_chunks(plan); ++c) {
+    set_chunk(plan, c);
+    launch_E(plan, st);
+    if (c == 0) stage_mark(plan, 2, st);
+    if (m >= 0) {
+      launch_H_mixed(plan, m, V, D, st);   // marks boundary 3 between its binary64 and binary32 parts
+    } else {
+      launch_H(plan, V, D, 2.0, H_WRITE, st);
+      if (c == 0) stage_mark(plan, 3, st);
+    }
+    if (c == 0) stage_mark(plan, 4, st);
+    launch_T2(plan, V, K, st, m, 0);
+    if (c == 0) stage_mark(plan, 5, st);
+    if (m >= 0) launch_T2(plan, V, K, st, m, 1);
+    if (c == 0) stage_mark(plan, 6, st);
+    launch_final(plan, K, st);
+  }
+  set_chunk(plan, 0);
+}
+
+// mixed list set of a precision, or -1 for binary64; -2: unknown, -3: reserved
+static int precision_set(int precision) {
+  switch (precision) {
+    case EXX_PREC_FP64: return -1;
+    case EXX_PREC_MIXED: return 0;
+    case EXX_PREC_FP32: return 1;
+    case EXX_PREC_BF16X3: return -3;
+    default: return -2;
+  }
+}
+
+static int check_precision(const char* who, int precision, int& m) {
+  m = precision_set(precision);
+  if (m == -3) return fail(EXX_EUNSUPPORTED, std::string(who) + ": EXX_PREC_BF16X3 is reserved, not implemented");
+  if (m == -2) return fail(EXX_EINVAL, std::string(who) + ": unknown precision");
+  return EXX_OK;
+}
+
+int build_K(exx_plan plan, const double* C, const double* V, const double* D, int precision,
+            double* K, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "build_K: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "build_K: host-only plan");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K: NULL array");
+  int m = -1;
+  int rc = check_precision("build_K", precision, m);
+  if (rc != EXX_OK) return rc;
+  if (m >= 0 && (rc = prepare_mixed(plan, m)) != EXX_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  stage_mark(plan, 0, st);
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, hp.d_size);
+  launch_dmask(plan, D, plan->d.Dm, st);
+  launch_repack(plan, C, st);
+  launch_vd_operands(plan, V, D, st);
+  stage_mark(plan, 1, st);
+  build_chunks(plan, V, D, K, m, st);
+  stage_mark(plan, 7, st);
+  HIP_TRY(hipGetLastError());
+  if (Ex) rc = launch_energy(plan, K, D, Ex, st);
+  stage_mark(plan, 8, st);
+  return rc;
+}
+
+// E and H' workspaces of a second result (build_K_spin, build_K_two_kernels), allocated once
+static int second_workspace(exx_plan plan) {
+  if (plan->spin_E1) return EXX_OK;
+  const int64_t ne = std::max<int64_t>(1, plan->hp.e_total);
+  HIP_TRY(hipMalloc((void**)&plan->spin_E1, sizeof(double) * ne));
+  plan->allocs.push_back(plan->spin_E1);
+  HIP_TRY(hipMalloc((void**)&plan->spin_H1, sizeof(double) * ne));
+  plan->allocs.push_back(plan->spin_H1);
+  plan->dev_bytes += 2 * (int64_t)sizeof(double) * ne;
+  const int64_t ndr = std::max<int64_t>(1, plan->dr_total);
+  HIP_TRY(hipMalloc((void**)&plan->spin_Dr1, sizeof(double) * ndr));
+  plan->allocs.push_back(plan->spin_Dr1);
+  plan->dev_bytes += (int64_t)sizeof(double) * ndr;
+  const int64_t nd = std::max<int64_t>(1, plan->hp.d_size);
+  HIP_TRY(hipMalloc((void**)&plan->spin_Dm1, sizeof(double) * nd));
+  plan->allocs.push_back(plan->spin_Dm1);
+  plan->dev_bytes += (int64_t)sizeof(double) * nd;
+  HIP_TRY(hipMemset(plan->spin_Dm1, 0, sizeof(double) * nd));
+  return EXX_OK;
+}
+
+// Collinear spin: E^s = T D^s for both spins, then one V-stage pass for both (F shared), then
+// T2 and the final contraction per spin with E and H' pointed at that spin's workspace.
+int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
+                 double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "build_K_spin: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "build_K_spin: host-only plan");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K_spin: NULL array");
+  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
+    return fail(EXX_EUNSUPPORTED, "build_K_spin: only the binary64 build takes two spins");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
+  if (n_chunks(plan) > 1)
+    return fail(EXX_EUNSUPPORTED, "build_K_spin: needs an unbounded workspace (the plan is chunked)");
+  const HostPlan& hp = plan->hp;
+  const int64_t ds = hp.d_size;
+  {
+    static const int t2c[3][2] = {{4, 4}, {8, 4}, {8, 8}};
+    const int* cw = t2c[std::min(std::max(plan->tune[TUNE_T2], 0), 2)];
+    if (t2_lds_bytes(plan->h_smax_t2, sizeof(double), cw[0], cw[1], 2) > (size_t)plan->lds_max)
+      return fail(EXX_EUNSUPPORTED, "build_K_spin: the largest n_aux * n_basis needs more LDS than a workgroup has "
+                                    "for two spins in the T2 tile shape chosen");
+  }
+  const int rcw = second_workspace(plan);
+  if (rcw != EXX_OK) return rcw;
+  hipStream_t st = (hipStream_t)stream;
+  DevPlan& d = plan->d;
+  set_chunk(plan, 0);
+  stage_mark(plan, 0, st);
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
+  launch_dmask(plan, D, d.Dm, st);
+  launch_dmask(plan, D + ds, plan->spin_Dm1, st);
+  launch_repack(plan, C, st);
+  stage_mark(plan, 1, st);
+  launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), cur_chunk(plan).n_e, st);
+  stage_mark(plan, 2, st);
+  launch_vd_operands(plan, V, D, st);   // V and D^0 operands
+  if (!hp.pair_a.empty())
+    hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
+                       plan->spin_Dr1, plan->d);   // D^1 operands
+  launch_H_lists<double, 2>(plan, V, D,
+                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, plan->spin_E1,
+                                   plan->spin_H1, plan->spin_Dr1},
+                            (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
+  stage_mark(plan, 3, st);
+  stage_mark(plan, 4, st);
+  launch_T2_spin(plan, V, K, st);
+  stage_mark(plan, 5, st);
+  stage_mark(plan, 6, st);
+  double* const H0 = d.H;
+  launch_final(plan, K, st);
+  d.H = plan->spin_H1;
+  launch_final(plan, K + ds, st);
+  d.H = H0;
+  stage_mark(plan, 7, st);
+  HIP_TRY(hipGetLastError());
+  int rc = EXX_OK;
+  if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
+  stage_mark(plan, 8, st);
+  return rc;
+}
+
+// Two Coulomb matrices: repack and E = T D once, then the V stage, T2 and the final
+// contraction per Coulomb matrix (H' of the second in the second workspace).  A V-stage pass
+// computing both at once (shared T_Q staging and D operands) measured slower than two passes
+// (49.4 against 2 x 22.0 ms at 768 atoms, with the operands then gathered from V and D): the
+// V operands, whose loads bound the stage, are not shared, and the doubled accumulators
+// halve the occupancy.
+int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2, const double* D,
+                        int precision, double* K, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "build_K_two_kernels: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "build_K_two_kernels: host-only plan");
+  if (!C || !V || !V2 || !D || !K) return fail(EXX_EINVAL, "build_K_two_kernels: NULL array");
+  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
+    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: only the binary64 build takes two Coulomb matrices");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_two_kernels: unknown precision");
+  if (n_chunks(plan) > 1)
+    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: needs an unbounded workspace (the plan is chunked)");
+  const int rcw = second_workspace(plan);
+  if (rcw != EXX_OK) return rcw;
+  const HostPlan& hp = plan->hp;
+  const int64_t ds = hp.d_size;
+  hipStream_t st = (hipStream_t)stream;
+  DevPlan& d = plan->d;
+  set_chunk(plan, 0);
+  double* const H0 = d.H;
+  stage_mark(plan, 0, st);
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
+  launch_dmask(plan, D, d.Dm, st);
+  launch_repack(plan, C, st);
+  stage_mark(plan, 1, st);
+  launch_E(plan, st);
+  stage_mark(plan, 2, st);
+  // T2 reads the lane-ordered copy of the V operands that the V stage reads: each Coulomb
+  // matrix's operands are written before its own V stage
+  launch_vd_operands(plan, V, D, st);
+  launch_H(plan, V, D, 2.0, H_WRITE, st);
+  launch_T2(plan, V, K, st);
+  d.H = plan->spin_H1;
+  launch_vd_operands(plan, V2, D, st);
+  launch_H(plan, V2, D, 2.0, H_WRITE, st);
+  d.H = H0;
+  launch_T2(plan, V2, K + ds, st);
+  stage_mark(plan, 3, st);
+  stage_mark(plan, 4, st);
+  stage_mark(plan, 5, st);
+  stage_mark(plan, 6, st);
+  launch_final(plan, K, st);
+  d.H = plan->spin_H1;
+  launch_final(plan, K + ds, st);
+  d.H = H0;
+  stage_mark(plan, 7, st);
+  HIP_TRY(hipGetLastError());
+  int rc = EXX_OK;
+  if (Ex) rc = launch_energy(plan, K, D, Ex, st);
+  if (Ex && rc == EXX_OK) rc = launch_energy(plan, K + ds, D, Ex + hp.n_sys, st);
+  stage_mark(plan, 8, st);
+  return rc;
+}
+
+int exx_graph_build(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
+                    double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_graph_build: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_graph_build: host-only plan");
+  if (!stream) return fail(EXX_EINVAL, "exx_graph_build: capture needs a created (non-default) stream");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "exx_graph_build: NULL array");
+  int m = -1;
+  int rc0 = check_precision("exx_graph_build", precision, m);
+  if (rc0 != EXX_OK) return rc0;
+  if (m >= 0 && (rc0 = prepare_mixed(plan, m)) != EXX_OK) return rc0;   // list uploads stay outside the capture
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->graph_exec) { hipGraphExecDestroy(plan->graph_exec); plan->graph_exec = nullptr; }
+  if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+  const bool prof = plan->profiling;
+  plan->profiling = false;
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const int rc = build_K(plan, C, V, D, precision, K, Ex, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  plan->profiling = prof;
+  if (rc != EXX_OK) { if (g) hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return fail(EXX_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  plan->graph = g;
+  HIP_TRY(hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0));
+  return EXX_OK;
+}
+
+int exx_graph_launch(exx_plan plan, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_graph_launch: NULL plan");
+  if (!plan->graph_exec) return fail(EXX_ESTATE, "exx_graph_launch: no graph built");
+  HIP_TRY(hipGraphLaunch(plan->graph_exec, (hipStream_t)stream));
+  return EXX_OK;
+}
+
+// time `launch` (one stage of a build) `reps` times on `st`; returns the fastest, ms
+extern "C++" {
+template <typename F>
+static int time_stage(hipStream_t st, int reps, F launch, float& best) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  best = 1e30f;
+  int rc = EXX_OK;
+  for (int r = 0; r < reps && rc == EXX_OK; ++r) {
+    hipEventRecord(e0, st);
+    launch();
+    hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(EXX_EDEVICE, "exx_plan_autotune: stage failed"); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
+}
+}  // extern "C++"
+
+int exx_plan_autotune(exx_plan plan, const double* C, const double* V, const double* D, int precision, double* K,
+                      void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_autotune: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_plan_autotune: host-only plan");
+  if (!C || !V || !D || !K) return fail(EXX_EINVAL, "exx_plan_autotune: NULL array");
+  int m = -1;
+  int rc = check_precision("exx_plan_autotune", precision, m);
+  if (rc != EXX_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const bool prof = plan->profiling;
+  plan->profiling = false;
+  // one build fills the workspace the stage kernels read (the last chunk's, for a chunked
+  // plan: its lists are the ones timed)
+  rc = build_K(plan, C, V, D, precision, K, nullptr, stream);
+  if (rc == EXX_OK) HIP_TRY(hipStreamSynchronize(st));
+  set_chunk(plan, n_chunks(plan) - 1);
+  constexpr int REPS = 3;
+  for (int stage = 0; stage < N_TUNE && rc == EXX_OK; ++stage) {
+    for (int c = 0; c < kTuneCands[stage] && rc == EXX_OK; ++c) {
+      plan->tune[stage] = c;
+      float ms = 0.f;
+      if (stage == TUNE_E) {
+        rc = time_stage(st, REPS, [&] { launch_E(plan, st); }, ms);
+      } else if (stage == TUNE_T2) {
+        rc = time_stage(st, REPS, [&] {
+          launch_T2(plan, V, K, st, m, 0);
+          if (m >= 0) launch_T2(plan, V, K, st, m, 1);
+        }, ms);
+      } else {
+        rc = time_stage(st, REPS, [&] { launch_Y(plan, c, st); }, ms);
+      }
+      plan->tune_ms[stage][c] = ms;
+    }
+    if (rc == EXX_OK) {
+      int best = 0;
+      for (int c = 1; c < kTuneCands[stage]; ++c)
+        if (plan->tune_ms[stage][c] < plan->tune_ms[stage][best]) best = c;
+      plan->tune[stage] = best;
+    }
+  }
+  set_chunk(plan, 0);
+  plan->profiling = prof;
+  if (rc != EXX_OK) return rc;
+  plan->tuned = true;
+  // leave a K of the chosen configuration behind
+  rc = build_K(plan, C, V, D, precision, K, nullptr, stream);
+  if (rc == EXX_OK) HIP_TRY(hipStreamSynchronize(st));
+  return rc;
+}
+
+int exx_plan_tuning(exx_plan plan, int32_t* choices, float* ms) {
+  if (!plan || !choices) return fail(EXX_EINVAL, "exx_plan_tuning: NULL argument");
+  for (int i = 0; i < N_TUNE; ++i) {
+    choices[i] = plan->tune[i];
+    if (ms)
+      for (int c = 0; c < N_CAND; ++c)
+        ms[i * N_CAND + c] = (plan->tuned && c < kTuneCands[i]) ? plan->tune_ms[i][c] : 0.f;
+  }
+  return EXX_OK;
+}
+
+int exx_plan_set_tuning(exx_plan plan, const int32_t* choices) {
+  if (!plan || !choices) return fail(EXX_EINVAL, "exx_plan_set_tuning: NULL argument");
+  for (int i = 0; i < N_TUNE; ++i)
+    if (choices[i] < 0 || choices[i] >= kTuneCands[i]) return fail(EXX_EINVAL, "exx_plan_set_tuning: choice out of range");
+  for (int i = 0; i < N_TUNE; ++i) plan->tune[i] = choices[i];
+  return EXX_OK;
+}
+
+int exx_plan_set_mixed_split(exx_plan plan, double r_split) {
+  if (!plan) return fail(EXX_EINVAL, "exx_plan_set_mixed_split: NULL plan");
+  if (!(r_split >= 0.0) || r_split > 1e6) return fail(EXX_EINVAL, "exx_plan_set_mixed_split: r_split must be in [0, 1e6]");
+  MixedSet& ms = plan->hp.mixed[0];
+  if (ms.ready && ms.split == r_split) return EXX_OK;
+  if (plan->graph_exec) { hipGraphExecDestroy(plan->graph_exec); plan->graph_exec = nullptr; }
+  if (plan->graph) { hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+  ms.split = r_split;
+  ms.ready = false;
+  derive_mixed_lists(plan->hp, 0);
+  if (plan->host_only) return EXX_OK;
+  HIP_TRY(hipDeviceSynchronize());   // lists of an earlier split may still be in use
+  plan->mdev[0].uploaded = false;
+  return prepare_mixed(plan, 0);
+}
+
+int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exchange_energy: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exchange_energy: host-only plan");
+  if (!K || !D || !Ex) return fail(EXX_EINVAL, "exchange_energy: NULL array");
+  return launch_energy(plan, K, D, Ex, (hipStream_t)stream);
+}
+
+// dE/dC and dE/dV of one chunk: E, the V stage with the G term taken once, the
+// gradient product G_P = H_P D and the dV pair blocks.  (Launches only.)
+static void backward_chunk(exx_plan plan, const double* V, const double* D, double* dVb, const double* gE,
+                           bool needC, bool needV, bool h_ready, hipStream_t st) {
+  if (!h_ready) launch_E(plan, st);
+  if (needC) {
+    if (!h_ready) launch_H(plan, V, D, 1.0, H_WRITE, st);
+    const ChunkDev& ch = cur_chunk(plan);
+    launch_rowD(plan, plan->d.Dm, rowd_GD(plan), ch.gd_end - ch.gd_beg, st);
+  }
+  if (needV) launch_dV(plan, V, D, dVb, gE, st);
+}
+
+int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                      const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
+                      double c_decay, double v_2s2, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exchange_backward: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exchange_backward: host-only plan");
+  if (!C || !V || !D || !gE) return fail(EXX_EINVAL, "exchange_backward: NULL input array");
+  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
+    return fail(EXX_EUNSUPPORTED, "exchange_backward: only the binary64 backward is implemented");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "exchange_backward: unknown precision");
+  if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, "exchange_backward: decay lengths must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  const bool needC = dC || forces, needV = dV || forces;
+  if (needC && !dC && !plan->dC_scratch) {
+    HIP_TRY(hipMalloc((void**)&plan->dC_scratch, sizeof(double) * std::max<int64_t>(1, hp.c_off.back())));
+    plan->allocs.push_back(plan->dC_scratch);
+  }
+  if (needV && !dV && !plan->dV_scratch) {
+    HIP_TRY(hipMalloc((void**)&plan->dV_scratch, sizeof(double) * std::max<int64_t>(1, hp.v_off.back())));
+    plan->allocs.push_back(plan->dV_scratch);
+  }
+  double* dCb = dC ? dC : plan->dC_scratch;
+  double* dVb = dV ? dV : plan->dV_scratch;
+  const dim3 gsys(256, hp.n_sys);
+  launch_dmask(plan, D, d.Dm, st);
+  launch_repack(plan, C, st);
+  launch_vd_operands(plan, V, D, st);
+  bool h_ready = false;   // E and H (G taken once) of the only chunk already in place
+  if (dD && K) {
+    // dE/dD = -1/2 gE K from the caller's K
+    hipLaunchKernelGGL(k_scaled_copy_sys, gsys, dim3(256), 0, st, dD, K, gE, d, -0.5);
+  } else if (dD) {
+    // dE/dD = -1/2 gE K: the forward build into dD, then scaled
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, dD, hp.d_size);
+    if (n_chunks(plan) == 1) {
+      set_chunk(plan, 0);
+      launch_E(plan, st);
+      launch_H(plan, V, D, 2.0, H_WRITE, st);
+      launch_T2(plan, V, dD, st);
+      launch_final(plan, dD, st);
+      if (needC) launch_H(plan, V, D, -1.0, H_G_ADD, st);   // G term taken once
+      h_ready = true;
+    } else {
+      const bool prof = plan->profiling;
+      plan->profiling = false;
+      build_chunks(plan, V, D, dD, -1, st);
+      plan->profiling = prof;
+    }
+    hipLaunchKernelGGL(k_scaled_copy_sys, gsys, dim3(256), 0, st, dD, dD, gE, d, -0.5);
+  }
+  if (needC || needV) {
+    for (int c = 0; c < n_chunks(plan); ++c) {
+      set_chunk(plan, c);
+      backward_chunk(plan, V, D, dVb, gE, needC, needV, h_ready && c == 0, st);
+    }
+    set_chunk(plan, 0);
+  }
+  if (needC) {
+    hipLaunchKernelGGL(k_unrepack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, d.GD, dCb, d, gE, -1.0);
+    if (forces)
+      hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dCb, C, d.c_off, d.sC);
+  }
+  if (needV && forces)
+    hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dVb, V, d.v_off, d.sV);
+  if (forces)
+    hipLaunchKernelGGL(k_forces, dim3((hp.n_atoms + 127) / 128), dim3(128), 0, st, d.pos, d.sC, d.sV, forces, d,
+                       c_decay, v_2s2);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+}  // extern "C"

@@ -37,6 +37,43 @@ struct YTile { int P, m0, n0, pad; };          // 64 x 64 tile of Y_P = T_P^T H'
 struct T2Class { int nt, ns, beg, end, prec; }; // items [beg, end) with this shape (prec 1: binary32)
 struct DVClass { int ntp, ntq, nlq, nip, beg, end; };  // dV pairs [beg, end) of dv_items with this shape
 
+// Near / far split of the V-stage and T2 lists at one split distance: pair
+// terms (P, Q) with |R_P - R_Q| >= split run in binary32.
+struct MixedSet {
+  double split = 5.0;
+  bool ready = false;
+  std::vector<GTile> tiles_near, tiles_far;
+  std::vector<int> far_src;                         // g_tiles index of every far tile
+  std::vector<Slot4> q_near, x_near, q_far, x_far;
+  std::vector<int> t2_items;                        // near classes first, then far
+  std::vector<T2Class> t2_classes;
+  // chunked plans: the T2 items of each chunk (rows on the chunk's atoms)
+  std::vector<std::vector<int>> chunk_t2_items;
+  std::vector<std::vector<T2Class>> chunk_t2_classes;
+  int64_t flops32[5] = {0, 0, 0, 0, 0};             // algorithmic flops run in binary32
+  int64_t issued32[5] = {0, 0, 0, 0, 0};            // issued binary32 MFMA flops
+  int64_t issued64[5] = {0, 0, 0, 0, 0};            // issued binary64 MFMA flops
+};
+
+// One chunk of a workspace-bounded plan: the aux atoms [a0, a1) (whole V-stage
+// groups [g0, g1)), whose H' and Y are formed, and the atoms whose E is
+// (re)computed for them: the chunk's atoms and their neighbours.
+struct ChunkHost {
+  int a0 = 0, a1 = 0, g0 = 0, g1 = 0;
+  int gt_beg = 0, gt_end = 0, y_beg = 0, y_end = 0, gd_beg = 0, gd_end = 0;   // ranges of global lists
+  std::vector<EItem> e_items;
+  std::vector<int> t2_items;
+  std::vector<T2Class> t2_classes;
+  std::vector<int> dv_items;
+  std::vector<DVClass> dv_classes;
+  std::vector<FItem> f_items;
+  std::vector<int> f_plist;
+  std::vector<int64_t> e_off, h_off, y_off;         // per atom, element offsets in the chunk buffers
+  int64_t e_total = 0, h_total = 0, y_total = 0;
+};
+
+constexpr int EN_PAIRS = 64;         // canonical pairs per energy chunk
+
 struct HostPlan {
   // system description
   int n_atoms = 0, n_sys = 0;
@@ -83,28 +120,27 @@ struct HostPlan {
   std::vector<YTile> y_tiles;
   std::vector<FItem> f_items;
   std::vector<int> f_plist;
-  std::vector<int> en_sys, en_beg, en_end;          // energy chunks
+  std::vector<int> en_sys;                          // system of each energy chunk
   // flop counts: [0] repack (0), [1] E, [2] H, [3] T2, [4] final
   int64_t flops[5] = {0, 0, 0, 0, 0};
   int64_t issued[5] = {0, 0, 0, 0, 0};
-  // mixed precision: pair terms (P, Q) with |R_P - R_Q| >= mixed_split run in
-  // binary32 in the V stage and T2; the near lists keep binary64
-  double mixed_split = 5.0;
-  bool mixed_ready = false;
-  std::vector<GTile> hm_tiles_near, hm_tiles_far;
-  std::vector<Slot4> hm_q_near, hm_x_near, hm_q_far, hm_x_far;
-  std::vector<int> t2m_items;                       // near classes first, then far
-  std::vector<T2Class> t2m_classes;
-  int64_t flops32[5] = {0, 0, 0, 0, 0};             // algorithmic flops run in binary32
-  int64_t issued32[5] = {0, 0, 0, 0, 0};            // issued binary32 MFMA flops
-  int64_t issued64m[5] = {0, 0, 0, 0, 0};           // issued binary64 MFMA flops, mixed build
+  // mixed precision: one list set per split distance (0: the plan's split,
+  // 1: split 0, i.e. every pair term in binary32)
+  MixedSet mixed[2];
+  // energy reduction: chunks of at most EN_PAIRS canonical pairs of one system
+  std::vector<int> en_pbeg, en_pend;
+  // aux-atom chunks of a workspace-bounded plan (empty: one chunk, the global lists)
+  int64_t ws_budget = 0;                            // bytes, 0 = unbounded
+  int64_t inter_stored = 0;                         // bytes of E, H', Y stored for all atoms
+  std::vector<ChunkHost> chunks;
+  int64_t ws_total = 0;                             // doubles of the E + H' + Y buffer
 };
 
 // Validate a system and fill the description part of a HostPlan.
 int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_t* species,
                     const double* positions, const int32_t* n_basis, const int32_t* n_aux,
                     double r_cut, int32_t n_systems, const int32_t* sys_atom_off,
-                    HostPlan& hp, std::string& err);
+                    const double* lattice, HostPlan& hp, std::string& err);
 
 // Host version of the screened neighbour lists (same arithmetic as the
 // device builder): nbr_ptr / nbr_atom only.
@@ -114,8 +150,13 @@ void host_neighbors(HostPlan& hp);
 // storage offsets, N2, maps, workspace layout, all task lists, flop counts.
 int derive_lists(HostPlan& hp, std::string& err);
 
-// Near / far split of the V-stage and T2 lists at hp.mixed_split (after
-// derive_lists), with the binary32 flop counts.
-void derive_mixed_lists(HostPlan& hp);
+// Near / far split of the V-stage and T2 lists of hp.mixed[set] at its split
+// distance (after derive_lists and derive_chunks), with the binary32 flop counts.
+void derive_mixed_lists(HostPlan& hp, int set);
+
+// Aux-atom chunks whose E, H' and Y workspaces fit in budget bytes (0 = no
+// bound).  Leaves hp.chunks empty when everything fits at once.  Returns 0,
+// or -2 (with err) when a single V-stage group does not fit.
+int derive_chunks(HostPlan& hp, int64_t budget, std::string& err);
 
 }  // namespace exx

@@ -1,0 +1,328 @@
+// libexx kernels: the block-sparse GEMM E_P = T_P D (and its adjoint), the
+// batched GEMM Y_P = T_P^T H'_P and the owner-computes gather of K.
+
+#include "exx_dev.h"
+
+using namespace exx;
+
+
+// EK: k-chunk per LDS stage (a tuning choice: 16 or 32).  NSP = 2 (collinear spin): the
+// products with D (into r.O) and D1 (into O1) in one pass, the A_P tile staged once.
+template <int EK, int NSP>
+__global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
+                                              int n_padded, const double* __restrict__ D1, double* __restrict__ O1) {
+  __shared__ double As[2][EK][EPITCH];
+  __shared__ double Bs[NSP][2][EK][EPITCH];
+  const int w = xcd_task(n_padded);
+  if (w >= n_items) return;
+  const EItem it = r.items[w];
+  const int P = it.P;
+  const int sP = d.na[P] * d.nb[P], lda = r.a_ld[P], ldo = r.o_ld[P];
+  const int s = d.atom_sys[P];
+  const int64_t ns = d.sys_n[s];
+  const double* Dsp[NSP];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp) Dsp[sp] = (sp == 0 ? D : D1) + d.sys_d_off[s];
+  const double* AP = r.A + r.a_off[P];
+  const int t = threadIdx.x;
+  const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  // staging roles: A (rows of A_P) k = t % EK, rows ma + MS x; B (rows of D) k = t / (256 / EK)... per pass of
+  // 16 k rows: k = pass * 16 + (t >> 4), columns nb0 + x
+  constexpr int MS = 256 / EK, NA_ = ET / MS, NP = EK / 16;
+  const int ka = t % EK, ma = t / EK;
+  const int kb = t >> 4, nb0 = (t & 15) * 4;
+  int gcn[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int n = it.c0 + nb0 + x;
+    gcn[x] = n < ldo ? r.ocolg[r.ocolg_off[P] + n] : -1;
+  }
+  const int klen = r.klen[it.ct];
+  const Run* runs = r.runs + r.run_ptr[it.ct];
+  int ia = 0, sa = 0;                   // run cursor (run index, its first k) of the A role
+  int ib[NP], sb[NP];                    // and of each pass of the B role
+#pragma unroll
+  for (int pz = 0; pz < NP; ++pz) ib[pz] = sb[pz] = 0;
+  double va[NA_], vb[NSP][NP][4];
+  auto gload = [&](int k0) {
+    const int k1 = k0 + ka;
+    const bool oka = k1 < klen;
+    if (oka) while (k1 >= sa + runs[ia].len) { sa += runs[ia].len; ++ia; }
+    const int lc = oka ? runs[ia].lcol + (k1 - sa) : 0;
+#pragma unroll
+    for (int x = 0; x < NA_; ++x) {
+      const int m = it.r0 + ma + MS * x;
+      const bool ok = oka && m < sP;
+      const double y = AP[ok ? (size_t)m * lda + lc : 0];
+      va[x] = ok ? y : 0.0;
+    }
+#pragma unroll
+    for (int pz = 0; pz < NP; ++pz) {
+      const int k2 = k0 + 16 * pz + kb;
+      const bool okb = k2 < klen;
+      if (okb) while (k2 >= sb[pz] + runs[ib[pz]].len) { sb[pz] += runs[ib[pz]].len; ++ib[pz]; }
+      const int gr = okb ? runs[ib[pz]].grow + (k2 - sb[pz]) : 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const bool okd = okb && gcn[x] >= 0;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) {
+          const double z = Dsp[sp][okd ? (size_t)gr * ns + gcn[x] : 0];
+          vb[sp][pz][x] = okd ? z : 0.0;
+        }
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int x = 0; x < NA_; ++x) As[buf][ka][ma + MS * x] = va[x];
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+      for (int pz = 0; pz < NP; ++pz)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) Bs[sp][buf][16 * pz + kb][nb0 + x] = vb[sp][pz][x];
+  };
+  d4 acc[NSP][2][2];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[sp][x][y] = d4{0, 0, 0, 0};
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < klen; k0 += EK) {
+    const bool more = k0 + EK < klen;
+    if (more) gload(k0 + EK);
+#pragma unroll
+    for (int ks = 0; ks < EK; ks += 4) {
+      const double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
+#pragma unroll
+      for (int sp = 0; sp < NSP; ++sp) {
+        const double b0 = Bs[sp][buf][ks + lk][wn + lr], b1 = Bs[sp][buf][ks + lk][wn + 16 + lr];
+        acc[sp][0][0] = mfma64(a0, b0, acc[sp][0][0]);
+        acc[sp][0][1] = mfma64(a0, b1, acc[sp][0][1]);
+        acc[sp][1][0] = mfma64(a1, b0, acc[sp][1][0]);
+        acc[sp][1][1] = mfma64(a1, b1, acc[sp][1][1]);
+      }
+    }
+    if (more) {
+      sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp) {
+    double* OP = (sp == 0 ? r.O : O1) + r.o_off[P];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int col = it.c0 + wn + 16 * y + lr;
+        if (col >= ldo) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = it.r0 + wm + 16 * x + lk + 4 * v;
+          if (row < sP) OP[(size_t)row * ldo + col] = acc[sp][x][y][v];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 4a: Y_P = T_P^T H'_P for every aux atom P (n_P x m_P, K = s_P), a
+// batched GEMM with both operands stored k-major.  64 x 64 tile per
+// workgroup of four wavefronts (32 x 32 each), k-steps of 16 staged in
+// double-buffered LDS with coalesced row loads.
+
+
+constexpr int YT = 64, YPITCH = YT + 4;
+
+// YK: k-chunk per LDS stage (a tuning choice: 16 or 32)
+template <int YK>
+__global__ __launch_bounds__(256) void k_Y(DevPlan d, int n_tiles, int n_padded) {
+  __shared__ double As[2][YK][YPITCH];
+  __shared__ double Bs[2][YK][YPITCH];
+  const int ti = xcd_task(n_padded);
+  if (ti >= n_tiles) return;
+  const YTile yt = d.y_tiles[ti];
+  const int P = yt.P;
+  const int Kd = d.na[P] * d.nb[P], M = d.n_loc[P], N = d.m_loc[P];
+  const double* A = d.T + d.t_off[P];   // A(m, k) = T_P[k * M + m]
+  const double* B = d.H + d.h_off[P];   // B(k, n) = H'_P[k * N + n]
+  const int t = threadIdx.x;
+  const int wv = t >> 6, L = t & 63, lr = L & 15, lk = L >> 4;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  // global -> LDS staging role: rows kr + 16 pz of the k-chunk, 4 columns
+  constexpr int NP = YK / 16;
+  const int kr = t >> 4, cc = (t & 15) * 4;
+  double ra[NP][4], rb[NP][4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int pz = 0; pz < NP; ++pz) {
+      const int k = k0 + 16 * pz + kr;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int m = yt.m0 + cc + x, n = yt.n0 + cc + x;
+        const bool oa = k < Kd && m < M, ob = k < Kd && n < N;
+        const double a = A[oa ? (size_t)k * M + m : 0];
+        const double b = B[ob ? (size_t)k * N + n : 0];
+        ra[pz][x] = oa ? a : 0.0;
+        rb[pz][x] = ob ? b : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int pz = 0; pz < NP; ++pz)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        As[buf][16 * pz + kr][cc + x] = ra[pz][x];
+        Bs[buf][16 * pz + kr][cc + x] = rb[pz][x];
+      }
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0, 0, 0, 0};
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < Kd; k0 += YK) {
+    const bool more = k0 + YK < Kd;
+    if (more) gload(k0 + YK);
+#pragma unroll
+    for (int ks = 0; ks < YK; ks += 4) {
+      double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
+      double b0 = Bs[buf][ks + lk][wn + lr], b1 = Bs[buf][ks + lk][wn + 16 + lr];
+      acc[0][0] = mfma64(a0, b0, acc[0][0]);
+      acc[0][1] = mfma64(a0, b1, acc[0][1]);
+      acc[1][0] = mfma64(a1, b0, acc[1][0]);
+      acc[1][1] = mfma64(a1, b1, acc[1][1]);
+    }
+    if (more) {
+      sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  double* Y = d.Y + d.y_off[P];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int n = yt.n0 + wn + 16 * y + lr;
+      if (n >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = yt.m0 + wm + 16 * x + lk + 4 * v;
+        if (m < M) Y[(size_t)m * N + n] = acc[x][y][v];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage 4b: K = T2 + (X + X^T)/2 with X[i, l] = sum_P Y_P[c1_P(i), c2_P(l)]
+// (c1: column of T_P, c2: column of H'_P).  One workgroup per 32 x 32 tile
+// pair of the upper triangle; the aux atoms of its list are visited in a
+// fixed order.  X[i, l] is gathered with l fastest across threads and
+// X[l, i] with i fastest (both coalesced), the two halves are combined in
+// LDS, and every element is written together with its mirror.
+
+__global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPlan d, int n_items,
+                                                   int n_padded) {
+  __shared__ int cmap[4][32];      // c1(I rows), c2(I rows), c1(L cols), c2(L cols)
+  __shared__ double xa[32][33], xb[32][33];
+  const int w = xcd_task(n_padded);
+  if (w >= n_items) return;
+  const FItem it = d.f_items[w];
+  const int s = it.sys;
+  const int64_t ns = d.sys_n[s];
+  const int t = threadIdx.x;
+  const int ta = t & 31, tb = t >> 5;   // element (tb + 8 r, ta)
+  double acc_a[4] = {0, 0, 0, 0}, acc_b[4] = {0, 0, 0, 0};
+  for (int pi = it.pbeg; pi < it.pend; ++pi) {
+    const int P = d.f_plist[pi];
+    const int nP_ = d.m_loc[P];
+    const double* Y = d.Y + d.y_off[P];
+    __syncthreads();
+    if (t < 128) {
+      const int which = t >> 5, x = t & 31;
+      const int g = ((which < 2) ? it.gI0 : it.gL0) + x;
+      const int* mp = ((which & 1) ? d.map2 : d.map1) + d.map_off[P];
+      cmap[which][x] = g < ns ? mp[g] : -1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = tb + 8 * r;
+      // X[i = I0 + ii, l = L0 + ta] = Y_P[c1(i), c2(l)]
+      const int c1 = cmap[0][ii], c2 = cmap[3][ta];
+      if (c1 >= 0 && c2 >= 0) acc_a[r] += Y[(size_t)c1 * nP_ + c2];
+      // X[l = L0 + ii, i = I0 + ta] = Y_P[c1(l), c2(i)], stored at (ta, ii)
+      const int d1 = cmap[2][ii], d2 = cmap[1][ta];
+      if (d1 >= 0 && d2 >= 0) acc_b[r] += Y[(size_t)d1 * nP_ + d2];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    xa[tb + 8 * r][ta] = acc_a[r];
+    xb[ta][tb + 8 * r] = acc_b[r];
+  }
+  __syncthreads();
+  double* Ks = K + d.sys_d_off[s];
+  const bool diag = it.gI0 == it.gL0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ii = tb + 8 * r, ll = ta;
+    const int i = it.gI0 + ii, l = it.gL0 + ll;
+    if (i >= ns || l >= ns) continue;
+    if (diag && i > l) continue;
+    const double val = Ks[(size_t)i * ns + l] + 0.5 * (xa[ii][ll] + xb[ii][ll]);
+    Ks[(size_t)i * ns + l] = val;
+    if (i != l) Ks[(size_t)l * ns + i] = val;
+  }
+}
+
+
+void launch_rowD(exx_plan plan, const double* D, const RowD& r, int n, hipStream_t st) {
+  if (n <= 0) return;
+  const int nwgp = (n + 7) / 8 * 8;
+  if (plan->tune[TUNE_E] == 1)
+    hipLaunchKernelGGL((k_rowD<32, 1>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_rowD<16, 1>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+}
+
+// the two products of a collinear-spin build: r.O = A D, O1 = A D1
+void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* O1, const RowD& r, int n,
+                             hipStream_t st) {
+  if (n <= 0) return;
+  const int nwgp = (n + 7) / 8 * 8;
+  if (plan->tune[TUNE_E] == 1)
+    hipLaunchKernelGGL((k_rowD<32, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+  else
+    hipLaunchKernelGGL((k_rowD<16, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+}
+
+void launch_Y(exx_plan plan, int choice, hipStream_t st) {
+  const ChunkDev& ch = plan->chunks[plan->cur];
+  const int nY = ch.y_end - ch.y_beg, nYp = (nY + 7) / 8 * 8;
+  if (nY <= 0) return;
+  if (choice == 1) hipLaunchKernelGGL(k_Y<32>, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+  else hipLaunchKernelGGL(k_Y<16>, dim3(nYp), dim3(256), 0, st, plan->d, nY, nYp);
+}
+
+void launch_symreduce(exx_plan plan, double* K, hipStream_t st) {
+  const int nF = plan->chunks[plan->cur].n_f, nFp = (nF + 7) / 8 * 8;
+  if (nF <= 0) return;
+  hipLaunchKernelGGL(k_symreduce, dim3(nFp), dim3(256), 0, st, K, plan->d, nF, nFp);
+}

@@ -1,0 +1,351 @@
+// libexx kernel: the V stage of the exchange build (k_H).
+
+#include "exx_dev.h"
+
+using namespace exx;
+
+// ---------------------------------------------------------------------------
+// stage 2: H'_P[(mu, j), c] for a group of consecutive atoms (its "units"
+// are the 16-wide aux tiles of the group atoms) and H_COLS columns c of the
+// group's second neighbourhood.  Four wavefronts per workgroup, each owning
+// H_CPW of the columns and looping over all units, so the SIMDs carry equal
+// work.  For every Q of the tile's Q-list, T_Q[:, columns] is staged once in
+// LDS, then per (unit, column) two chained MFMAs (the first result feeding
+// the second as its B operand):
+//   F_c[l][mu] = sum_nu T_Q[(nu, l), c] V_PQ[mu, nu]
+//   H_c[j][mu] += sum_l D_PQ[j, l] F_c[l][mu]
+// G part for columns c on atom X in N[P]:
+//   H_c[l][nu] += g sum_mu' E_X[(mu', c), l] V_XP[mu', nu]   (g = 2 forward).
+// The chain lengths are compile-time per shape class of Q.
+
+
+__device__ __forceinline__ int h_class(int ns, int nl) {
+  if (ns <= 4 && nl <= 2) return 0;
+  if (ns <= 10) return 1;
+  return 2;
+}
+
+struct HUnits {            // unit table of the group (LDS)
+  int P[GROUP_WAVES], mu0[GROUP_WAVES], slot[GROUP_WAVES], a[GROUP_WAVES], b[GROUP_WAVES], bo[GROUP_WAVES];
+};
+
+// The binary32 kernel stages the V_PQ and D_PQ blocks of the group in LDS
+// once per Q; the binary64 kernel reads them per unit from their lane-ordered copies.
+template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == sizeof(float); };
+
+// One Q of a V-stage tile, all H_CPW columns of this wavefront.  The staged T_Q
+// rows are read without masks: rows past s_Q (or of lanes past n_b(Q)) hold
+// finite values, and they meet zero V (nu >= n_a(Q)) or zero D (l >= n_b(Q))
+// operands.  A column missing from N[Q] is staged as zeros.
+// The binary64 kernel reads the V and D operands from their lane-ordered copies (d.Vr,
+// d.Dr); NSP density matrices (collinear spin: two, the second's D operands in Dr1) share F,
+// and each has its own D contraction and accumulators.  The binary32 kernel reads them from
+// the blocks it staged in LDS (sV, sD).
+template <int NS, int NL, int U, int NSP, typename R>
+__device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], const R* sT, const R* sV,
+                                    const R* sD, const HUnits& un, const int* roff, int nU, const int* qp, int Q,
+                                    int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr, int lk,
+                                    const DevPlan& d, const double* Dr1) {
+  typedef typename Mf<R>::acc A4;
+  static_assert(NSP == 1 || !HStage<R>::vd, "the LDS-staged binary32 kernel takes one density matrix");
+  bool anyc = false;
+#pragma unroll
+  for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || ((c0 + cc < ncols) && lc_row[c0 + cc] >= 0);
+  if (!anyc) return;
+  const R* t0 = sT + lr * LDS_PITCH + c0;
+  constexpr int NLR = sizeof(R) == sizeof(double) ? NL : 4;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (u < nU) {
+      const int sl = un.slot[u];
+      if (qp[sl] >= 0) {
+        const int aP = un.a[u], bP = un.b[u];
+        const int muB = un.mu0[u] + lr;
+        const bool muv = muB < aP;
+        R vb[NS];
+        R da[NSP][NLR];
+        if constexpr (HStage<R>::vd) {
+          const bool pqs = un.P[u] <= Q;
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            const int nu = 4 * q + lk;
+            const bool ok = muv && nu < aQ;
+            // the canonical block as stored: [mu][nu] if P <= Q, else [nu][mu]
+            const int vi = pqs ? muB * aQ + nu : nu * aP + muB;
+            const R x = sV[ok ? roff[sl] * aQ + vi : 0];
+            vb[q] = ok ? x : (R)0;
+          }
+#pragma unroll
+          for (int q = 0; q < NLR; ++q) {
+            const int l = Mf<R>::row(lk, q);
+            const bool ok = lr < bP && l < bQ;
+            const R x = sD[ok ? (sl * 16 + lr) * H_DPITCH + l : 0];
+            da[0][q] = ok ? x : (R)0;
+          }
+        } else {
+          // the lane-ordered copies: one coalesced row per MFMA step (steps past the
+          // blocks are zero)
+          const int pp = qp[sl], orient = un.P[u] <= Q ? 0 : 1;
+          const int nsq = (aQ + 3) >> 2, nlq = (bQ + 3) >> 2, L = lk * 16 + lr;
+          const double* vrow = d.Vr + d.vr_off[2 * pp + orient] + (size_t)(un.mu0[u] >> 4) * nsq * 64 + L;
+#pragma unroll
+          for (int q = 0; q < NS; ++q) vb[q] = q < nsq ? (R)vrow[q * 64] : (R)0;
+#pragma unroll
+          for (int sp = 0; sp < NSP; ++sp) {
+            const double* dr = (sp == 0 ? d.Dr : Dr1) + d.dr_off[2 * pp + orient] + L;
+#pragma unroll
+            for (int q = 0; q < NLR; ++q) da[sp][q] = q < nlq ? (R)dr[q * 64] : (R)0;
+          }
+        }
+        // the A operands of all columns first (independent LDS reads), then the chains
+        R ta[NS][H_CPW];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const R* row = t0 + (q * 4 + lk) * bQ * LDS_PITCH;
+#pragma unroll
+          for (int cc = 0; cc < H_CPW; ++cc) ta[q][cc] = row[cc];
+        }
+        A4 F[H_CPW];
+#pragma unroll
+        for (int cc = 0; cc < H_CPW; ++cc) F[cc] = A4{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+          for (int cc = 0; cc < H_CPW; ++cc) F[cc] = Mf<R>::mma(ta[q][cc], vb[q], F[cc]);
+#pragma unroll
+        for (int q = 0; q < NLR; ++q)
+#pragma unroll
+          for (int cc = 0; cc < H_CPW; ++cc)
+#pragma unroll
+            for (int sp = 0; sp < NSP; ++sp) Hc[sp][u][cc] = Mf<R>::mma(da[sp][q], F[cc][q], Hc[sp][u][cc]);
+      }
+    }
+  }
+}
+
+
+// NSP = 2: the two spin density matrices of a collinear-spin build in one pass (F = V T_Q is
+// formed once); H'^0 goes to d.H, H'^1 to hl.H1.  Four wavefronts per SIMD for one density
+// matrix (at most 128 VGPRs: measured faster than three with 168 since the V and D operands
+// are coalesced rows), two for two (their accumulators double).
+template <int U, typename R, int NSP>
+__global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NSP == 1 ? 4 : 2))) void k_H(
+    const double* __restrict__ V, const double* __restrict__ D, DevPlan d, HLists hl, int n_tiles,
+    int n_padded, double gscale, int mode) {
+  typedef typename Mf<R>::acc A4;
+  extern __shared__ double sraw[];
+  R* sT = reinterpret_cast<R*>(sraw);
+  __shared__ HUnits un;
+  __shared__ int qm_atom[HQ_CHUNK], qm_n[HQ_CHUNK], qm_a[HQ_CHUNK], qm_b[HQ_CHUNK], qm_bo[HQ_CHUNK];
+  __shared__ int qm_lc[HQ_CHUNK][H_COLS], qm_p[HQ_CHUNK][GROUP_ATOMS];
+  __shared__ int64_t qm_toff[HQ_CHUNK], qm_voff[HQ_CHUNK][GROUP_ATOMS];
+  const int ti = xcd_task(n_padded);
+  if (ti >= n_tiles) return;
+  const GTile tl = hl.tiles[ti];
+  const int g = tl.grp;
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  const int lr = L & 15, lk = L >> 4;
+  const int u0 = d.grp_unit_ptr[g];
+  const int nU = d.grp_unit_ptr[g + 1] - u0;
+  if (threadIdx.x < nU) {
+    const Unit x = d.grp_units[u0 + threadIdx.x];
+    un.P[threadIdx.x] = x.P;
+    un.mu0[threadIdx.x] = x.mu0;
+    un.slot[threadIdx.x] = x.slot;
+    un.a[threadIdx.x] = d.na[x.P];
+    un.b[threadIdx.x] = d.nb[x.P];
+    un.bo[threadIdx.x] = d.bo[x.P];
+  }
+  const int s = d.atom_sys[d.grp_first[g]];
+  const int64_t ns = d.sys_n[s];
+  const double* Ds = D + d.sys_d_off[s];
+  const int* gcol = d.grp_cols + tl.col_beg;
+  const int ncols = tl.ncols;
+  const int c0 = wv * H_CPW;
+  A4 Hc[NSP][U][H_CPW];
+#pragma unroll
+  for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int cc = 0; cc < H_CPW; ++cc) Hc[sp][u][cc] = A4{0, 0, 0, 0};
+  const int tc = threadIdx.x % H_COLS;
+  const int tstep = blockDim.x / H_COLS;
+  // LDS: T_Q[:, tile columns] | V_PQ of the group's atoms, [nu][group aux row] | D_PQ blocks
+  R* sV = sT + hl.v_base;
+  R* sD = sV + hl.d_base;
+  __shared__ int roff[GROUP_ATOMS + 1], sP_[GROUP_ATOMS], sa_[GROUP_ATOMS], sb_[GROUP_ATOMS], sbo_[GROUP_ATOMS];
+  if (threadIdx.x == 0) {
+    const int a0 = d.grp_first[g];
+    const int nsl = d.grp_units[u0 + nU - 1].slot + 1;
+    roff[0] = 0;
+    for (int t = 0; t < GROUP_ATOMS; ++t) {
+      const int P = a0 + t;
+      const bool in = t < nsl;
+      sP_[t] = in ? P : -1;
+      sa_[t] = in ? d.na[P] : 0;
+      sb_[t] = in ? d.nb[P] : 0;
+      sbo_[t] = in ? d.bo[P] : 0;
+      roff[t + 1] = roff[t] + sa_[t];
+    }
+  }
+  // rows read past s_Q stay finite (the G-only pass has no Q loop and no dynamic LDS)
+  if (mode != H_G_ADD)
+    for (int i = threadIdx.x; i < hl.v_base; i += blockDim.x) sT[i] = (R)0;
+  __syncthreads();
+  for (int e0 = mode == H_G_ADD ? tl.q_end : tl.q_beg; e0 < tl.q_end; e0 += HQ_CHUNK) {
+    const int nchunk = min(HQ_CHUNK, tl.q_end - e0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nchunk * H_COLS; t += blockDim.x) {
+      const int ei = t / H_COLS, c = t % H_COLS;
+      const Slot4 qe = hl.gq[e0 + ei];
+      const int Q = qe.atom;
+      qm_lc[ei][c] = (c < ncols) ? d.map1[d.map_off[Q] + gcol[c]] : -1;
+      if (c == 0) {
+        qm_atom[ei] = Q;
+        qm_n[ei] = d.n_loc[Q];
+        qm_a[ei] = d.na[Q];
+        qm_b[ei] = d.nb[Q];
+        qm_bo[ei] = d.bo[Q];
+        qm_toff[ei] = d.t_off[Q];
+        const int pp[3] = {qe.p0, qe.p1, qe.p2};
+        for (int k = 0; k < GROUP_ATOMS; ++k) {
+          qm_p[ei][k] = pp[k];
+          qm_voff[ei][k] = pp[k] >= 0 ? d.v_off[pp[k]] : 0;
+        }
+      }
+    }
+    __syncthreads();
+    for (int ei = 0; ei < nchunk; ++ei) {
+      const int Q = qm_atom[ei], aQ = qm_a[ei], bQ = qm_b[ei], nQ = qm_n[ei], sQ = aQ * bQ;
+      const int lcq = qm_lc[ei][tc];
+      const double* TQ = d.T + qm_toff[ei] + (lcq >= 0 ? lcq : 0);
+      for (int r = threadIdx.x / H_COLS; r < sQ; r += tstep)
+        sT[r * LDS_PITCH + tc] = (R)(lcq >= 0 ? TQ[(size_t)r * nQ] : 0.0);
+      // V_PQ and D_PQ of every group atom paired with Q (coalesced reads of the
+      // canonical V block, transposed into [nu][row])
+#pragma unroll
+      for (int k = 0; k < GROUP_ATOMS; ++k) {
+        if (HStage<R>::vd && qm_p[ei][k] >= 0) {
+          const int P = sP_[k], aP = sa_[k], bP = sb_[k];
+          // plain copies: the V block as stored, the D block row by row
+          const double* Vp = V + qm_voff[ei][k];
+          R* dv = sV + roff[k] * aQ;
+          for (int i = threadIdx.x; i < aP * aQ; i += blockDim.x) dv[i] = (R)Vp[i];
+          const double* DPQ = Ds + (size_t)sbo_[k] * ns + qm_bo[ei];
+          for (int i = threadIdx.x; i < bP * 16; i += blockDim.x) {
+            const int j = i >> 4, l = i & 15;
+            if (l < bQ) sD[(k * 16 + j) * H_DPITCH + l] = (R)DPQ[(size_t)j * ns + l];
+          }
+          (void)P;
+        }
+      }
+      __syncthreads();
+      const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
+      switch (h_class(nsQ, nlQ)) {
+        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // G part (this wavefront's columns)
+  for (int e = tl.x_beg; e < tl.x_end; ++e) {
+    const Slot4 xe = hl.gx[e];
+    const int X = xe.atom;
+    const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
+    const int pp[3] = {xe.p0, xe.p1, xe.p2};
+    const double* EXs[NSP];
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp) EXs[sp] = (sp == 0 ? d.E : hl.E1) + d.e_off[X];
+    const int* m2X = d.map2 + d.map_off[X];
+#pragma unroll
+    for (int cc = 0; cc < H_CPW; ++cc) {
+      const int c = c0 + cc;
+      const int ic = (c < ncols) ? gcol[c] - boX : -1;
+      if (ic >= 0 && ic < bX) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (u < nU) {
+            const int p = pp[un.slot[u]];
+            if (p >= 0) {
+              const int P = un.P[u], aP = un.a[u], bP = un.b[u];
+              const int muB = un.mu0[u] + lr;
+              const bool muv = muB < aP;
+              const int colx = lr < bP ? m2X[un.bo[u] + lr] : 0;
+              const size_t xo = colx + (size_t)ic * mX;
+              const int nsx = (aX + 3) / 4;
+              // V_PX[muB][m2] from the lane-ordered copy (zero outside the block)
+              const double* vrx = d.Vr + d.vr_off[2 * p + (P <= X ? 0 : 1)] + (size_t)(un.mu0[u] >> 4) * nsx * 64 + L;
+              for (int q = 0; q < nsx; ++q) {
+                const int m2 = 4 * q + lk;
+                const bool mv = m2 < aX;
+                const bool oka = mv && lr < bP, okb = mv && muv;
+                const double b = vrx[q * 64];
+                const R bv = okb ? (R)(gscale * b) : (R)0;
+#pragma unroll
+                for (int sp = 0; sp < NSP; ++sp) {
+                  const double a = EXs[sp][oka ? xo + (size_t)(m2 * bX) * mX : xo];
+                  Hc[sp][u][cc] = Mf<R>::mma(oka ? (R)a : (R)0, bv, Hc[sp][u][cc]);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  // store, or add to H'
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (u < nU) {
+      const int P = un.P[u], aP = un.a[u], bP = un.b[u], mP = d.m_loc[P];
+      const int muB = un.mu0[u] + lr;
+      const int* m2P = d.map2 + d.map_off[P];
+#pragma unroll
+      for (int sp = 0; sp < NSP; ++sp) {
+        double* HP = (sp == 0 ? d.H : hl.H1) + d.h_off[P];
+#pragma unroll
+        for (int cc = 0; cc < H_CPW; ++cc) {
+          const int c = c0 + cc;
+          const int col = (c < ncols) ? m2P[gcol[c]] : -1;
+          if (col >= 0 && muB < aP) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int j = Mf<R>::row(lk, v);
+              if (j < bP) {
+                double* h = HP + (size_t)(muB * bP + j) * mP + col;
+                *h = mode == H_WRITE ? (double)Hc[sp][u][cc][v] : *h + (double)Hc[sp][u][cc][v];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+
+template <typename R, int NSP>
+void launch_H_lists(exx_plan plan, const double* V, const double* D, const HLists& hl, int n, double gscale,
+                           int mode, hipStream_t st) {
+  if (n <= 0) return;
+  const HostPlan& hp = plan->hp;
+  const int np_ = (n + 7) / 8 * 8;
+  const size_t lds = mode == H_G_ADD ? 0 : (sizeof(R) == sizeof(double) ? plan->h_lds : plan->h_lds32);
+  const dim3 grid(np_), blk(64 * H_WAVES);
+  if (hp.h_waves <= 2)
+    hipLaunchKernelGGL((k_H<2, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+  else if (hp.h_waves <= 5)
+    hipLaunchKernelGGL((k_H<5, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+  else
+    hipLaunchKernelGGL((k_H<8, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+}
+template void launch_H_lists<double, 1>(exx_plan, const double*, const double*, const HLists&, int, double, int,
+                                        hipStream_t);
+template void launch_H_lists<float, 1>(exx_plan, const double*, const double*, const HLists&, int, double, int,
+                                       hipStream_t);
+template void launch_H_lists<double, 2>(exx_plan, const double*, const double*, const HLists&, int, double, int,
+                                        hipStream_t);

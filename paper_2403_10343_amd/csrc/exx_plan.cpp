@@ -18,7 +18,11 @@ namespace exx {
 int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_t* species,
                     const double* positions, const int32_t* n_basis, const int32_t* n_aux,
                     double r_cut, int32_t n_systems, const int32_t* sys_atom_off,
-                    HostPlan& hp, std::string& err) {
+                    const double* lattice, HostPlan& hp, std::string& err) {
+  if (lattice) {
+    err = "exx_system: periodic systems (a lattice) are not implemented";
+    return -5;
+  }
   if (n_atoms <= 0 || n_species <= 0 || !species || !positions || !n_basis || !n_aux) {
     err = "exx_system: null array or non-positive count";
     return -1;
@@ -34,6 +38,8 @@ int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_
   }
   hp.n_atoms = n_atoms;
   hp.n_sys = n_systems;
+  hp.mixed[0].split = 5.0;
+  hp.mixed[1].split = 0.0;
   hp.r_cut = r_cut;
   hp.species.assign(species, species + n_atoms);
   hp.pos.assign(positions, positions + 3 * (size_t)n_atoms);
@@ -528,36 +534,36 @@ int derive_lists(HostPlan& hp, std::string& err) {
   hp.y_total = hp.y_off[NA];
   hp.issued[4] = 0;
   for (const auto& t : hp.y_tiles) hp.issued[4] += 2LL * 64 * 64 * ceil_to((int64_t)hp.na[t.P] * hp.nb[t.P], 16);
-  // ---- energy chunks
+  // ---- energy chunks: runs of at most EN_PAIRS canonical pairs of one system
   hp.en_sys.clear();
-  hp.en_beg.clear();
-  hp.en_end.clear();
-  const int64_t CH = 1 << 16;
-  for (int s = 0; s < hp.n_sys; ++s) {
-    int64_t n2 = hp.sys_n[s] * hp.sys_n[s];
-    for (int64_t b = 0; b < n2; b += CH) {
-      hp.en_sys.push_back(s);
-      hp.en_beg.push_back((int)b);
-      hp.en_end.push_back((int)std::min(n2, b + CH));
-    }
+  hp.en_pbeg.clear();
+  hp.en_pend.clear();
+  for (int64_t p = 0; p < npairs;) {
+    const int s = hp.atom_sys[hp.pair_a[p]];
+    int64_t q = p + 1;
+    while (q < npairs && q - p < EN_PAIRS && hp.atom_sys[hp.pair_a[q]] == s) ++q;
+    hp.en_sys.push_back(s);
+    hp.en_pbeg.push_back((int)p);
+    hp.en_pend.push_back((int)q);
+    p = q;
   }
-  for (int i = 1; i < 5; ++i) hp.flops[0] += 0;
   return 0;
 }
 
 // ---------------------------------------------------------------------------
 // Mixed precision: the V-stage Q- and X-lists and the T2 pairs are split by
-// atom-pair distance.  Pairs at or beyond mixed_split (their V block, C
-// blocks and D blocks all decay with distance) go to the binary32 kernels,
-// the rest stay binary64.  The V stage runs the near lists as the storing
-// launch (every tile, so every H' entry is written) and the far lists as an
-// accumulating launch (tiles with no far pair dropped).
-void derive_mixed_lists(HostPlan& hp) {
+// atom-pair distance.  Pairs at or beyond the split (their V block, C blocks
+// and D blocks all decay with distance) go to the binary32 kernels, the rest
+// stay binary64.  The V stage runs the near lists as the storing launch (every
+// tile, so every H' entry is written) and the far lists as an accumulating
+// launch (tiles with no far pair dropped).
+void derive_mixed_lists(HostPlan& hp, int set) {
+  MixedSet& m = hp.mixed[set];
   const int NA = hp.n_atoms;
   const int64_t npairs = (int64_t)hp.pair_a.size();
   const std::vector<int>& np = hp.nbr_ptr;
   const std::vector<int>& nat = hp.nbr_atom;
-  const double s2 = hp.mixed_split * hp.mixed_split;
+  const double s2 = m.split * m.split;
   std::vector<char> far(npairs, 0);
   for (int64_t p = 0; p < npairs; ++p) {
     const double* pa = &hp.pos[3 * (size_t)hp.pair_a[p]];
@@ -566,17 +572,17 @@ void derive_mixed_lists(HostPlan& hp) {
     volatile double xx = dx * dx, yy = dy * dy, zz = dz * dz;
     volatile double r2 = (xx + yy);
     r2 = r2 + zz;
-    far[p] = (hp.mixed_split <= 0.0) || (r2 >= s2);
+    far[p] = (m.split <= 0.0) || (r2 >= s2);
   }
-  for (int i = 0; i < 5; ++i) hp.flops32[i] = hp.issued32[i] = hp.issued64m[i] = 0;
+  for (int i = 0; i < 5; ++i) m.flops32[i] = m.issued32[i] = m.issued64[i] = 0;
   // algorithmic binary32 flops of the V stage (ordered pairs) and T2
   for (int a = 0; a < NA; ++a) {
     const int aP = hp.na[a], bP = hp.nb[a];
     for (int k = np[a]; k < np[a + 1]; ++k) {
       const int q = nat[k];
       if (!far[hp.nbr_pair[k]]) continue;
-      hp.flops32[2] += 2LL * aP * hp.na[q] * hp.nb[q] * hp.n_loc[q] + 2LL * aP * bP * hp.nb[q] * hp.n_loc[q] +
-                       2LL * aP * hp.na[q] * bP * hp.nb[q];
+      m.flops32[2] += 2LL * aP * hp.na[q] * hp.nb[q] * hp.n_loc[q] + 2LL * aP * bP * hp.nb[q] * hp.n_loc[q] +
+                      2LL * aP * hp.na[q] * bP * hp.nb[q];
     }
   }
   // atom of a basis column of a system
@@ -584,28 +590,30 @@ void derive_mixed_lists(HostPlan& hp) {
     const int lo = hp.sys_atom_off[s], hi = hp.sys_atom_off[s + 1];
     int l = lo, h = hi - 1;
     while (l < h) {
-      const int m = (l + h + 1) / 2;
-      if (hp.bo[m] <= col) l = m; else h = m - 1;
+      const int mm = (l + h + 1) / 2;
+      if (hp.bo[mm] <= col) l = mm; else h = mm - 1;
     }
     return l;
   };
-  hp.hm_tiles_near.clear();
-  hp.hm_tiles_far.clear();
-  hp.hm_q_near.clear();
-  hp.hm_x_near.clear();
-  hp.hm_q_far.clear();
-  hp.hm_x_far.clear();
+  m.tiles_near.clear();
+  m.tiles_far.clear();
+  m.far_src.clear();
+  m.q_near.clear();
+  m.x_near.clear();
+  m.q_far.clear();
+  m.x_far.clear();
   std::vector<int> catom;
-  for (const GTile& t : hp.g_tiles) {
+  for (size_t ti = 0; ti < hp.g_tiles.size(); ++ti) {
+    const GTile& t = hp.g_tiles[ti];
     const int a = hp.grp_first[t.grp];
     const int s = hp.atom_sys[a];
     catom.resize(t.ncols);
     for (int c = 0; c < t.ncols; ++c) catom[c] = col_atom(s, hp.grp_cols[t.col_beg + c]);
     GTile tn = t, tf = t;
-    tn.q_beg = (int)hp.hm_q_near.size();
-    tf.q_beg = (int)hp.hm_q_far.size();
-    tn.x_beg = (int)hp.hm_x_near.size();
-    tf.x_beg = (int)hp.hm_x_far.size();
+    tn.q_beg = (int)m.q_near.size();
+    tf.q_beg = (int)m.q_far.size();
+    tn.x_beg = (int)m.x_near.size();
+    tf.x_beg = (int)m.x_far.size();
     for (int pass = 0; pass < 2; ++pass) {
       const std::vector<Slot4>& src = pass == 0 ? hp.gq : hp.gx;
       const int e0 = pass == 0 ? t.q_beg : t.x_beg, e1 = pass == 0 ? t.q_end : t.x_end;
@@ -628,48 +636,192 @@ void derive_mixed_lists(HostPlan& hp) {
         for (int k = 0; k < GROUP_ATOMS; ++k) {
           if (sl[k] < 0) continue;
           const int64_t fl = 2048LL * ((hp.na[a + k] + 15) / 16) * cnt;
-          if (far[sl[k]]) { sf[k] = sl[k]; anyf = true; hp.issued32[2] += fl * per32; }
-          else { sn[k] = sl[k]; anyn = true; hp.issued64m[2] += fl * per; }
+          if (far[sl[k]]) { sf[k] = sl[k]; anyf = true; m.issued32[2] += fl * per32; }
+          else { sn[k] = sl[k]; anyn = true; m.issued64[2] += fl * per; }
         }
-        if (anyn) (pass == 0 ? hp.hm_q_near : hp.hm_x_near).push_back(n4);
-        if (anyf) (pass == 0 ? hp.hm_q_far : hp.hm_x_far).push_back(f4);
+        if (anyn) (pass == 0 ? m.q_near : m.x_near).push_back(n4);
+        if (anyf) (pass == 0 ? m.q_far : m.x_far).push_back(f4);
       }
     }
-    tn.q_end = (int)hp.hm_q_near.size();
-    tf.q_end = (int)hp.hm_q_far.size();
-    tn.x_end = (int)hp.hm_x_near.size();
-    tf.x_end = (int)hp.hm_x_far.size();
-    hp.hm_tiles_near.push_back(tn);
-    if (tf.q_end > tf.q_beg || tf.x_end > tf.x_beg) hp.hm_tiles_far.push_back(tf);
+    tn.q_end = (int)m.q_near.size();
+    tf.q_end = (int)m.q_far.size();
+    tn.x_end = (int)m.x_near.size();
+    tf.x_end = (int)m.x_far.size();
+    m.tiles_near.push_back(tn);
+    if (tf.q_end > tf.q_beg || tf.x_end > tf.x_beg) {
+      m.tiles_far.push_back(tf);
+      m.far_src.push_back((int)ti);
+    }
   }
   // T2: the full list's order (shape classes) kept inside each precision
-  hp.t2m_items.clear();
-  hp.t2m_classes.clear();
+  m.t2_items.clear();
+  m.t2_classes.clear();
   for (int prec = 0; prec < 2; ++prec) {
     for (const T2Class& c : hp.t2_classes) {
-      const int beg = (int)hp.t2m_items.size();
+      const int beg = (int)m.t2_items.size();
       for (int i = c.beg; i < c.end; ++i) {
         const int item = hp.t2_items[i];
         const int p = item >> 1;
         if (far[p] != (prec == 1)) continue;
-        hp.t2m_items.push_back(item);
+        m.t2_items.push_back(item);
         const bool flip = item & 1;
         const int x = flip ? hp.pair_b[p] : hp.pair_a[p], y = flip ? hp.pair_a[p] : hp.pair_b[p];
         const int64_t iss = 2048LL * ((hp.na[x] + 15) / 16) * (((hp.na[y] + 3) / 4) + 4) * hp.n_loc[y];
         if (prec == 1) {
-          hp.flops32[3] += 2LL * hp.na[x] * hp.na[y] * hp.nb[y] * hp.n_loc[y] +
-                           2LL * hp.na[x] * hp.nb[x] * hp.nb[y] * hp.n_loc[y];
-          hp.issued32[3] += iss;
+          m.flops32[3] += 2LL * hp.na[x] * hp.na[y] * hp.nb[y] * hp.n_loc[y] +
+                          2LL * hp.na[x] * hp.nb[x] * hp.nb[y] * hp.n_loc[y];
+          m.issued32[3] += iss;
         } else {
-          hp.issued64m[3] += iss;
+          m.issued64[3] += iss;
         }
       }
-      const int end = (int)hp.t2m_items.size();
-      if (end > beg) hp.t2m_classes.push_back(T2Class{c.nt, c.ns, beg, end, prec});
+      const int end = (int)m.t2_items.size();
+      if (end > beg) m.t2_classes.push_back(T2Class{c.nt, c.ns, beg, end, prec});
     }
   }
-  for (int i : {0, 1, 4}) hp.issued64m[i] = hp.issued[i];
-  hp.mixed_ready = true;
+  // per chunk: the items whose row atom the chunk owns, class by class
+  m.chunk_t2_items.assign(hp.chunks.size(), {});
+  m.chunk_t2_classes.assign(hp.chunks.size(), {});
+  for (size_t ci = 0; ci < hp.chunks.size(); ++ci) {
+    const ChunkHost& ch = hp.chunks[ci];
+    auto& items = m.chunk_t2_items[ci];
+    auto& cls = m.chunk_t2_classes[ci];
+    for (const T2Class& c : m.t2_classes) {
+      const int beg = (int)items.size();
+      for (int i = c.beg; i < c.end; ++i) {
+        const int item = m.t2_items[i], p = item >> 1;
+        const int row = (item & 1) ? hp.pair_b[p] : hp.pair_a[p];
+        if (row >= ch.a0 && row < ch.a1) items.push_back(item);
+      }
+      if ((int)items.size() > beg) cls.push_back(T2Class{c.nt, c.ns, beg, (int)items.size(), c.prec});
+    }
+  }
+  for (int i : {0, 1, 4}) m.issued64[i] = hp.issued[i];
+  m.ready = true;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace-bounded plans.  A chunk owns whole V-stage groups, i.e. a range
+// [a0, a1) of consecutive aux atoms P: their H'_P (V stage) and Y_P (final
+// product) are formed in the chunk, and their T2 blocks (row atom P) and dV
+// pairs (first atom P) are computed there.  The V stage's G part reads E_X of
+// the neighbours X of P and the dV pairs read E_Q, so each chunk computes E for
+// its atoms and their neighbours: E of an atom near a chunk boundary is
+// recomputed by every chunk that needs it.
+int derive_chunks(HostPlan& hp, int64_t budget, std::string& err) {
+  const int NA = hp.n_atoms;
+  hp.chunks.clear();
+  hp.ws_budget = budget;
+  const int64_t stored = (int64_t)sizeof(double) * (2 * hp.e_total + hp.y_total);
+  hp.inter_stored = stored;
+  hp.ws_total = 2 * hp.e_total + hp.y_total;
+  if (budget <= 0 || stored <= budget) return 0;
+  const auto& np = hp.nbr_ptr;
+  const auto& nat = hp.nbr_atom;
+  auto esz = [&](int a) { return hp.e_off[a + 1] - hp.e_off[a]; };
+  auto ysz = [&](int a) { return hp.y_off[a + 1] - hp.y_off[a]; };
+  const int NG = (int)hp.grp_first.size();
+  auto grp_end = [&](int g) { return g + 1 < NG ? hp.grp_first[g + 1] : NA; };
+  std::vector<int> stamp(NA, -1);
+  std::vector<std::pair<int, int>> ranges;   // groups [g0, g1)
+  int g = 0;
+  while (g < NG) {
+    const int tag = (int)ranges.size();
+    int64_t e_d = 0, hy_d = 0;   // doubles: E of the E atoms, H' + Y of the owned atoms
+    int g1 = g;
+    while (g1 < NG) {
+      int64_t de = 0, dhy = 0;
+      std::vector<int> added;
+      for (int a = hp.grp_first[g1]; a < grp_end(g1); ++a) {
+        dhy += esz(a) + ysz(a);
+        for (int k = np[a]; k < np[a + 1]; ++k)
+          if (stamp[nat[k]] != tag) { stamp[nat[k]] = tag; added.push_back(nat[k]); de += esz(nat[k]); }
+      }
+      if ((int64_t)sizeof(double) * (e_d + de + hy_d + dhy) > budget && g1 > g) {
+        for (int x : added) stamp[x] = -1;   // not taken: undo
+        break;
+      }
+      if ((int64_t)sizeof(double) * (e_d + de + hy_d + dhy) > budget) {
+        err = "exx_plan_create: ws_budget_bytes is smaller than the workspace of one V-stage group (" +
+              std::to_string((int64_t)sizeof(double) * (e_d + de + hy_d + dhy)) + " bytes)";
+        hp.chunks.clear();
+        return -2;
+      }
+      e_d += de;
+      hy_d += dhy;
+      ++g1;
+    }
+    ranges.push_back({g, g1});
+    g = g1;
+  }
+  hp.ws_total = 0;
+  std::vector<char> in_e(NA);
+  for (const auto& r : ranges) {
+    ChunkHost ch;
+    ch.g0 = r.first;
+    ch.g1 = r.second;
+    ch.a0 = hp.grp_first[ch.g0];
+    ch.a1 = grp_end(ch.g1 - 1);
+    std::fill(in_e.begin(), in_e.end(), 0);
+    for (int a = ch.a0; a < ch.a1; ++a)
+      for (int k = np[a]; k < np[a + 1]; ++k) in_e[nat[k]] = 1;
+    ch.e_off.assign(NA + 1, 0);
+    ch.h_off.assign(NA + 1, 0);
+    ch.y_off.assign(NA + 1, 0);
+    for (int a = 0; a < NA; ++a) {
+      if (in_e[a]) { ch.e_off[a] = ch.e_total; ch.e_total += esz(a); }
+      if (a >= ch.a0 && a < ch.a1) {
+        ch.h_off[a] = ch.h_total; ch.h_total += esz(a);
+        ch.y_off[a] = ch.y_total; ch.y_total += ysz(a);
+      }
+    }
+    for (const EItem& it : hp.e_items)
+      if (in_e[it.P]) ch.e_items.push_back(it);
+    // ranges of the lists kept in group / atom order
+    ch.gt_beg = (int)(std::lower_bound(hp.g_tiles.begin(), hp.g_tiles.end(), ch.g0,
+                                       [](const GTile& t, int x) { return t.grp < x; }) - hp.g_tiles.begin());
+    ch.gt_end = (int)(std::lower_bound(hp.g_tiles.begin(), hp.g_tiles.end(), ch.g1,
+                                       [](const GTile& t, int x) { return t.grp < x; }) - hp.g_tiles.begin());
+    auto atom_range = [&](const auto& v, int& b, int& e) {
+      b = (int)(std::lower_bound(v.begin(), v.end(), ch.a0, [](const auto& t, int x) { return t.P < x; }) - v.begin());
+      e = (int)(std::lower_bound(v.begin(), v.end(), ch.a1, [](const auto& t, int x) { return t.P < x; }) - v.begin());
+    };
+    atom_range(hp.y_tiles, ch.y_beg, ch.y_end);
+    atom_range(hp.gd_items, ch.gd_beg, ch.gd_end);
+    // T2 items with their row atom in the chunk, class by class
+    for (const T2Class& c : hp.t2_classes) {
+      const int beg = (int)ch.t2_items.size();
+      for (int i = c.beg; i < c.end; ++i) {
+        const int item = hp.t2_items[i], p = item >> 1;
+        const int row = (item & 1) ? hp.pair_b[p] : hp.pair_a[p];
+        if (row >= ch.a0 && row < ch.a1) ch.t2_items.push_back(item);
+      }
+      if ((int)ch.t2_items.size() > beg) ch.t2_classes.push_back(T2Class{c.nt, c.ns, beg, (int)ch.t2_items.size(), 0});
+    }
+    for (const DVClass& c : hp.dv_classes) {
+      const int beg = (int)ch.dv_items.size();
+      for (int i = c.beg; i < c.end; ++i)
+        if (hp.pair_a[hp.dv_items[i]] >= ch.a0 && hp.pair_a[hp.dv_items[i]] < ch.a1) ch.dv_items.push_back(hp.dv_items[i]);
+      if ((int)ch.dv_items.size() > beg) {
+        DVClass d = c;
+        d.beg = beg;
+        d.end = (int)ch.dv_items.size();
+        ch.dv_classes.push_back(d);
+      }
+    }
+    // gather tiles: the P-lists restricted to the chunk's atoms
+    for (const FItem& f : hp.f_items) {
+      FItem x = f;
+      x.pbeg = (int)ch.f_plist.size();
+      for (int i = f.pbeg; i < f.pend; ++i)
+        if (hp.f_plist[i] >= ch.a0 && hp.f_plist[i] < ch.a1) ch.f_plist.push_back(hp.f_plist[i]);
+      x.pend = (int)ch.f_plist.size();
+      if (x.pend > x.pbeg) ch.f_items.push_back(x);
+    }
+    hp.ws_total = std::max(hp.ws_total, ch.e_total + ch.h_total + ch.y_total);
+    hp.chunks.push_back(std::move(ch));
+  }
+  return 0;
 }
 
 }  // namespace exx

@@ -178,3 +178,53 @@ def test_autograd_mixed_forward(exx):
     dD = system_block(D.grad.cpu().numpy(), inp.layout, 0)
     assert np.abs(dD - go["dD"]).max() <= 0.5e-5
     assert abs(E.item() - go["E"]) / sysm.n_atoms <= 1e-6
+
+
+def _moved(inp, A, axis, h, c_decay=1.5, v_2s2=8.0):
+    """Inputs with atom A moved by h along axis and the pair lists frozen: the
+    blocks of every pair (A, B) rescaled by the generator's distance model
+    (C ~ exp(-r / c_decay), V ~ exp(-r^2 / v_2s2); D held fixed)."""
+    lay = inp.layout
+    pos = inp.system.pos.copy()
+    pos[A, axis] += h
+    C, V = inp.C.copy(), inp.V.copy()
+    for p in np.nonzero((lay.pair_a == A) ^ (lay.pair_b == A))[0]:
+        a, b = int(lay.pair_a[p]), int(lay.pair_b[p])
+        r0 = float(np.linalg.norm(inp.system.pos[a] - inp.system.pos[b]))
+        r1 = float(np.linalg.norm(pos[a] - pos[b]))
+        C[lay.c_off[p]:lay.c_off[p + 1]] *= np.exp(-(r1 - r0) / c_decay)
+        V[lay.v_off[p]:lay.v_off[p + 1]] *= np.exp(-(r1 * r1 - r0 * r0) / v_2s2)
+    return synth.Inputs(inp.system, lay, C, V, inp.D)
+
+
+def test_forces_fd_on_24_atoms_of_the_768_box(exx):
+    """Forces on a 24-atom subset (8 molecules around the box centre) of the
+    768-atom box: central differences (h = 1e-4 A) of the GPU FP64 E_x with the
+    pair lists frozen, on six coordinates; and the same 8 molecules cut out as
+    a cluster against the oracle's FP64 gradient and forces."""
+    inp = synth.make_inputs(synth.config(4))
+    sysm = inp.system
+    plan = exx.Plan.for_system(sysm)
+    g = backward(plan, inp, want=("F",))
+    F = g["F"]
+    centre = sysm.pos.mean(0)
+    o_atoms = np.nonzero(sysm.species == synth.O)[0]
+    near = o_atoms[np.argsort(np.linalg.norm(sysm.pos[o_atoms] - centre, axis=1), kind="stable")[:8]]
+    subset = np.sort(np.concatenate([near, near + 1, near + 2]))
+    assert len(subset) == 24
+    h = 1e-4
+    picks = [(subset[0], 0), (subset[4], 1), (subset[8], 2), (subset[13], 0), (subset[17], 1), (subset[23], 2)]
+    for A, ax in picks:
+        es = [run_build(plan, _moved(inp, int(A), ax, s * h), torch)[1][0] for s in (1, -1)]
+        fd = -(es[0] - es[1]) / (2 * h)
+        print(f"atom {A} axis {ax}: FD {fd:.9f}  analytic {F[A, ax]:.9f}", flush=True)
+        assert abs(fd - F[A, ax]) < 1e-6 * np.abs(F).max() + 1e-5, (A, ax, fd, F[A, ax])
+    # the 8 molecules as a standalone cluster: GPU gradients against the oracle's
+    cut = synth.System(sysm.species[subset], sysm.pos[subset], sysm.r_cut, seed=sysm.seed,
+                       labels=sysm.labels[subset], name="ice768_cut24")
+    ci = synth.make_inputs(cut)
+    cp = exx.Plan.for_system(cut)
+    gc = backward(cp, ci)
+    go = O.gradients(ci)
+    assert relmax(gc["dC"], go["dC"]) < 1e-10 and relmax(gc["dV"], go["dV"]) < 1e-10
+    assert relmax(gc["F"], O.forces(ci, go)) < 1e-10

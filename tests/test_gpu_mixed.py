@@ -146,3 +146,29 @@ def test_mixed_backward_is_rejected(exx):
     with pytest.raises(exx.ExxError) as e:
         plan.exchange_backward(C, V, D, 1.0, dD=torch.empty_like(D), precision=exx.PREC_MIXED)
     assert e.value.code == -5
+
+
+def test_mixed_full_64_cluster_batch(exx):
+    """The full 64-cluster batch: the mixed build against the FP64 build on every
+    cluster (max|dK| <= 1e-5, |dE_x|/atom <= 1e-6) and against the oracle on the
+    four smallest clusters."""
+    b = synth.config(3)
+    inp = synth.make_inputs(b)
+    plan = exx.Plan.for_system(b)
+    K64, E64 = run_build(plan, inp, torch, exx.PREC_FP64)
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    worst_k = worst_e = 0.0
+    for s in range(b.n_systems):
+        nat = int(b.sys_off[s + 1] - b.sys_off[s])
+        dk = np.abs(system_block(Km, inp.layout, s) - system_block(K64, inp.layout, s)).max()
+        de = abs(Em[s] - E64[s]) / nat
+        worst_k, worst_e = max(worst_k, dk), max(worst_e, de)
+    print(f"64 clusters mixed vs FP64: worst max|dK| {worst_k:.2e}, worst |dE|/atom {worst_e:.2e}", flush=True)
+    assert worst_k <= BAR_K and worst_e <= BAR_E
+    sizes = np.diff(b.sys_off)
+    for s in np.argsort(sizes, kind="stable")[:4]:
+        Ko = O.k_eigen(inp, int(s))
+        Eo = O.exchange_energy(Ko, O.Blocks(inp, int(s)).D)
+        assert np.abs(system_block(Km, inp.layout, int(s)) - Ko).max() <= BAR_K
+        assert abs(Em[s] - Eo) / sizes[s] <= BAR_E
+        assert relmax(system_block(K64, inp.layout, int(s)), Ko) < 1e-10

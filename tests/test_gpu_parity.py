@@ -148,3 +148,42 @@ def test_other_species_shapes(exx, tables):
     assert relmax(Kg, Ko) < TOL_K
     Eo = O.exchange_energy(Ko, O.Blocks(inp).D)
     assert abs(Ex[0] - Eo) < TOL_E * abs(Eo)
+
+
+def _row_sample(inp, n_atoms_each=3, rows_per_atom=4, seed=1):
+    """Rows of K on O and H atoms at the surface (fewest neighbours) and in the
+    interior (most neighbours) of a box: n_atoms_each atoms of each kind, the
+    first, last and random basis rows of each."""
+    blk = O.Blocks(inp)
+    deg = np.array([len(x) for x in blk.nbrs])
+    sp = inp.system.species
+    rng = np.random.default_rng(seed)
+    rows = []
+    for s in (synth.O, synth.H):
+        atoms = np.nonzero(sp == s)[0]
+        order = atoms[np.argsort(deg[atoms], kind="stable")]
+        for a in list(order[:n_atoms_each]) + list(order[-n_atoms_each:]):
+            b0, nb = int(blk.bo[a]), int(blk.nb[a])
+            pick = [b0, b0 + nb - 1] + list(b0 + rng.choice(np.arange(1, nb - 1), rows_per_atom - 2, replace=False))
+            rows += pick
+    return np.array(rows), blk
+
+
+def test_config2_48_oracle_rows_fp64_and_mixed(exx):
+    """48 rows of K of the 768-atom box (O and H rows of surface and interior
+    atoms) against the oracle's row route: FP64 at 1e-10 relative, the mixed
+    build (default split) at the 1e-5 absolute bar."""
+    inp = synth.make_inputs(synth.config(2))
+    plan = _plan(exx, inp.system)
+    rows, blk = _row_sample(inp)
+    assert len(rows) == 48 and len(set(rows.tolist())) == 48
+    K, _ = run_build(plan, inp, torch)
+    Km, _ = run_build(plan, inp, torch, exx.PREC_MIXED)
+    print("oracle rows:", rows.tolist(), flush=True)
+    Kr = O.k_rows(inp, rows, blk=blk)
+    Kg = system_block(K, inp.layout, 0)[rows]
+    Kmg = system_block(Km, inp.layout, 0)[rows]
+    scale = np.abs(Kr).max()
+    print(f"48 rows: fp64 rel {np.abs(Kg - Kr).max() / scale:.2e}, mixed abs {np.abs(Kmg - Kr).max():.2e}", flush=True)
+    assert np.abs(Kg - Kr).max() < TOL_K * scale
+    assert np.abs(Kmg - Kr).max() <= 1e-5

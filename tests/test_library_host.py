@@ -112,3 +112,51 @@ def test_tuning_choices_validated_on_host_plan():
         p.set_tuning([0, 3, 0])
     with pytest.raises(exx.ExxError):
         p.set_tuning([2, 0, 0])
+
+
+def test_lattice_is_rejected_as_unsupported():
+    from paper_2403_10343_amd import ExxError, Plan
+    sysm = synth.config(1)
+    with pytest.raises(ExxError) as e:
+        Plan(sysm.species, sysm.pos, synth.N_BASIS, synth.N_AUX, 6.0, host_only=True, lattice=np.eye(3) * 30.0)
+    assert e.value.code == -5
+
+
+def test_workspace_budget_chunks_on_host_plan():
+    """A budget below the stored E, H' and Y splits the plan into chunks that
+    each fit; no budget (or a large one) keeps one chunk; a budget below one
+    V-stage group's needs is EXX_ENOMEM."""
+    from paper_2403_10343_amd import ExxError, Plan
+    sysm = synth.ice_box(2, 2, 2, seed=0)
+    full = Plan.for_system(sysm, host_only=True)
+    stored = full.info["intermediate_bytes_stored"]
+    assert full.info["n_chunks"] == 1 and full.info["intermediate_bytes"] == stored
+    assert Plan.for_system(sysm, host_only=True, ws_budget_bytes=2 * stored).info["n_chunks"] == 1
+    prev = 1
+    for frac in (2, 3, 5):
+        p = Plan.for_system(sysm, host_only=True, ws_budget_bytes=stored // frac)
+        assert p.info["n_chunks"] >= prev and p.info["n_chunks"] >= 2
+        assert p.info["intermediate_bytes"] <= stored // frac
+        assert p.info["intermediate_bytes_stored"] == stored
+        prev = p.info["n_chunks"]
+    with pytest.raises(ExxError) as e:
+        Plan.for_system(sysm, host_only=True, ws_budget_bytes=4096)
+    assert e.value.code == -2
+
+
+def test_binding_rejects_arrays_before_the_library():
+    """Arrays of the wrong type, device, layout or size raise EXX_EINVAL in the
+    binding (they never reach a kernel)."""
+    import torch
+    from paper_2403_10343_amd import ExxError, Plan
+    sysm = synth.water_cluster(2, seed=0)
+    inp = synth.make_inputs(sysm)
+    p = Plan.for_system(sysm, host_only=True)
+    C, V, D = (torch.from_numpy(a) for a in (inp.C, inp.V, inp.D))
+    K = torch.empty(p.info["d_size"], dtype=torch.float64)
+    for args in ((C, V, D, K), (C.float(), V, D, K), (C, V[:-1], D, K), (C.numpy(), V, D, K)):
+        with pytest.raises(ExxError) as e:
+            p.build_K(*args)
+        assert e.value.code == -1
+    with pytest.raises(ExxError):
+        p.exchange_backward(C, V, D, 1.0, dC=torch.empty_like(C))
