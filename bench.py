@@ -12,7 +12,7 @@ path (the FP64 path itself always does); "config.path" names it.
 
 Prints ONE JSON line (rank 0).  The "roofline" object describes the dominant
 kernel, timed with HIP events recorded by the library on its launch stream
-during the timed steps; "cpu_baseline" times the CPU oracle (row route) on a
+during the timed steps; "cpu_baseline" times the CPU oracle (block route) on a
 bounded sample of rows of the same workload, scaled to builds/s, and the rows
 it computes give the error of both GPU paths against the oracle.
 """
@@ -57,31 +57,60 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(inp, seconds=15.0, max_rows=64):
-    """Time the oracle's row route on a bounded sample of rows; returns the
-    baseline record and the rows it computed (for the error report)."""
-    import numpy as np
-    from oracle import exx_oracle as O
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        return max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count()
+        return os.cpu_count()
+
+
+def cpu_baseline(inp, flops_per_build, repeats=3):
+    """Time the oracle's block route (rows of K atom by atom, every step a BLAS
+    product over structural blocks) on the rows of one interior water molecule:
+    one warm-up, then the median of `repeats` runs on all BLAS threads, and one
+    run on a single thread (one H atom's rows).  Rates are scaled to whole
+    builds by the fraction of K's rows computed; GFLOP/s use the library's
+    algorithmic flop count of a build times the same fraction.  Returns the
+    record and the rows computed (for the error report)."""
+    import numpy as np
+    from oracle import exx_oracle as O
     blk = O.Blocks(inp)
     n = blk.n
-    rng = np.random.default_rng(0)
-    order = rng.permutation(n)
-    done, t0 = 0, time.perf_counter()
-    rows = []
-    while done < max_rows and time.perf_counter() - t0 < seconds:
-        rows.append(O.k_rows(inp, order[done:done + 1], blk=blk)[0])
-        done += 1
-    dt = time.perf_counter() - t0
-    rec = {"value": done / dt / n, "unit": "builds/s", "cores": int(threads), "kind": "oracle",
-           "sample": f"{done} random rows of K ({n} rows per build) by the oracle's row route, "
-                     f"{dt:.1f} s; builds/s = rows/s / {n}",
-           "host": host_description()}
-    return rec, order[:done], np.array(rows)
+    deg = np.array([len(x) for x in blk.nbrs])
+    o_atoms = np.nonzero(inp.system.species[:blk.nat] == 0)[0]
+    o = int(o_atoms[np.argmax(deg[o_atoms])])           # most-connected O: an interior molecule
+    mol = [o, o + 1, o + 2]
+    rows = np.concatenate([np.arange(blk.bo[a], blk.bo[a + 1]) for a in mol])
+    O.k_atom_rows(inp, [o + 1], blk=blk)                # warm-up
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        Krows = O.k_atom_rows(inp, mol, blk=blk)
+        times.append(time.perf_counter() - t0)
+    t_med = float(np.median(times))
+    frac = len(rows) / n
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        h_rows = int(blk.nb[o + 1])
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            O.k_atom_rows(inp, [o + 1], blk=blk)
+            t1 = time.perf_counter() - t0
+        one = {"builds_per_s": (h_rows / n) / t1, "gflops": (h_rows / n) * flops_per_build / t1 / 1e9,
+               "sample": f"the {h_rows} rows of one H atom, one run, {t1:.2f} s", "cores": 1}
+    except Exception as e:   # threadpoolctl missing: report the multi-threaded rate only
+        one = {"error": str(e)}
+    rec = {"value": frac / t_med, "unit": "builds/s", "cores": int(_blas_threads()), "kind": "oracle",
+           "route": "block route (oracle.k_atom_rows): the definition over structural blocks, atom by atom",
+           "sample": f"the {len(rows)} rows of one interior water molecule ({len(rows)} of {n} rows of K), "
+                     f"median of {repeats} runs after one warm-up: {t_med:.2f} s "
+                     f"(runs {', '.join(f'{t:.2f}' for t in times)} s); builds/s = {len(rows)}/{n} / time",
+           "gflops": frac * flops_per_build / t_med / 1e9,
+           "gflop_note": "library algorithmic flop count of a build times the fraction of rows computed",
+           "one_thread": one, "host": host_description()}
+    return rec, rows, Krows
 
 
 def host_description():
@@ -104,16 +133,21 @@ def host_description():
     return {"cpu": model, "logical_cpus": os.cpu_count(), "blas": blas}
 
 
-def small_config_comparison(exx, torch, seconds_cap=60.0):
-    """The 24-atom cluster: one full oracle build (4-index route, which also
-    gives E_x directly from (ij|kl)) against the GPU FP64 build."""
+def small_config_comparison(exx, torch, repeats=3):
+    """The 24-atom cluster: full oracle builds (4-index route, which also gives
+    E_x directly from (ij|kl); one warm-up, median of `repeats`) against the
+    GPU FP64 build."""
     import numpy as np
     import synth
     from oracle import exx_oracle as O
     inp = synth.make_inputs(synth.config(1))
-    t0 = time.perf_counter()
-    K4, _, e_direct = O.k_4index(inp)
-    t_cpu = time.perf_counter() - t0
+    O.k_4index(inp)
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        K4, _, e_direct = O.k_4index(inp)
+        ts.append(time.perf_counter() - t0)
+    t_cpu = float(np.median(ts))
     plan = exx.Plan.for_system(inp.system)
     dev = torch.device("cuda:0")
     C, V, D = (torch.from_numpy(a).to(dev) for a in (inp.C, inp.V, inp.D))
@@ -129,6 +163,7 @@ def small_config_comparison(exx, torch, seconds_cap=60.0):
     t_gpu = (time.perf_counter() - t0) / n
     Kg = K.cpu().numpy().reshape(K4.shape)
     return {"workload": "water_cluster_8_24_atoms_192_basis", "oracle_4index_s": t_cpu,
+            "oracle_4index_runs_s": ts, "oracle_cores": int(_blas_threads()),
             "gpu_fp64_ms": 1e3 * t_gpu, "max_rel_dK": float(np.abs(Kg - K4).max() / np.abs(K4).max()),
             "rel_dE_x_direct": float(abs(Ex.item() - e_direct) / abs(e_direct))}
 
@@ -191,7 +226,6 @@ def main():
                     help="pair distance (A) at and beyond which the mixed path runs pair terms in FP32")
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--backward-steps", type=int, default=3,
                     help="also time forward + exchange_backward (dE/dC, dE/dV, dE/dD, forces); 0 = skip")
@@ -354,7 +388,7 @@ def main():
         out["calibration_copy_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
         out["config1_oracle_vs_gpu"] = small_config_comparison(exx, torch)
-        rec, rows, Krows = cpu_baseline(inp, seconds=args.cpu_seconds)
+        rec, rows, Krows = cpu_baseline(inp, total_flops)
         out["cpu_baseline"] = rec
         n = int(inp.layout.sys_nbas[0])
         ridx = torch.as_tensor(rows, device=dev)

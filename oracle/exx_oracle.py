@@ -27,6 +27,9 @@ Routes (three independent evaluations of the same definition):
   K = sum_m lambda_m U_m V U_m^T with U_m[:, mu] = C^mu v_m.
 * ``k_rows``    evaluates whole rows K[i, :] from the definition with the
   structural zeros of C and V skipped; usable at any system size.
+* ``k_atom_rows`` (the block route) evaluates the same rows for all basis
+  functions of one atom at once, so that every step is a matrix product over
+  structural blocks; it is the route the CPU baseline times.
 
 Collinear spin (``k_spin``, ``spin_exchange_energy``): the spin index of
 Eq. (realspace_exchange) only selects the density matrix, so each spin's K^s
@@ -279,6 +282,90 @@ def k_rows(inputs, rows, s=0, blk=None):
     return out
 
 
+def _c_row_parts(blk, I, J):
+    """Parts of C^mu restricted to rows on atom I and columns on atom J, for
+    every mu whose C^mu has such a block: a list of (aux atom P, array
+    [n_aux(P), n_basis(I), n_basis(J)])."""
+    a, b = (I, J) if I <= J else (J, I)
+    cb = blk.c_block(blk.pair_of[(a, b)])
+    if I == J:
+        return [(I, cb)]
+    na_a = blk.na[a]
+    out = []
+    for owner, part in ((a, cb[:na_a]), (b, cb[na_a:])):
+        out.append((owner, part if I < J else part.transpose(0, 2, 1)))
+    return out
+
+
+def k_atom_rows(inputs, atoms, s=0, blk=None):
+    """K[rows of the given atoms, :] of system s (rows in the order of atoms).
+
+    The definition K_ik = sum_mu sum_nu V_{mu nu} (C^mu D C^nu)_ik taken for
+    all rows i of one atom I at once, each step a matrix product over
+    structural blocks only:
+      U^mu[i, j]  = C^mu_ij        (mu on I or on a neighbour of I; j near I)
+      T^mu        = U^mu D         (on the columns the C^nu below can reach)
+      Y^nu        = sum_mu V_{nu mu} T^mu      (nu on a neighbour Q of mu's atom)
+      K[i, k]     = sum_nu sum_l C^nu_kl Y^nu[i, l]."""
+    if blk is None:
+        blk = Blocks(inputs, s)
+    D = blk.D
+    cols_of = lambda atoms_: np.concatenate([np.arange(blk.bo[J], blk.bo[J + 1]) for J in atoms_])
+    c1 = [cols_of(blk.nbrs[A]) for A in range(blk.nat)]                       # basis of N[A]
+    n2 = [sorted(set(L for J in blk.nbrs[A] for L in blk.nbrs[J])) for A in range(blk.nat)]
+    c2 = [cols_of(x) for x in n2]                                              # basis of N2[A]
+    out = []
+    for I in atoms:
+        I = int(I)
+        bI = int(blk.nb[I])
+        loc1 = {}
+        c = 0
+        for J in blk.nbrs[I]:
+            loc1[J] = c
+            c += blk.nb[J]
+        U = {}
+        for J in blk.nbrs[I]:
+            for P, part in _c_row_parts(blk, I, J):
+                if P not in U:
+                    U[P] = np.zeros((blk.na[P], bI, len(c1[I])))
+                U[P][:, :, loc1[J]:loc1[J] + blk.nb[J]] += part
+        Y = {}
+        DI = D[c1[I]]
+        for P, UP in U.items():
+            pos2 = {int(x): k for k, x in enumerate(c2[P])}
+            TP = (UP.reshape(-1, len(c1[I])) @ DI[:, c2[P]]).reshape(blk.na[P], bI, len(c2[P]))
+            for Q in blk.nbrs[P]:
+                idx = np.array([pos2[int(x)] for x in c1[Q]])
+                a, b = (P, Q) if P <= Q else (Q, P)
+                vb = blk.v_block(blk.pair_of[(a, b)])
+                VPQ = vb if P <= Q else vb.T                   # [mu on P, nu on Q]
+                contrib = (VPQ.T @ TP[:, :, idx].reshape(blk.na[P], -1)).reshape(blk.na[Q], bI, len(idx))
+                if Q in Y:
+                    Y[Q] += contrib
+                else:
+                    Y[Q] = contrib
+        KI = np.zeros((bI, blk.n))
+        for Q, YQ in Y.items():
+            pos = {}
+            c = 0
+            for J in blk.nbrs[Q]:
+                pos[J] = c
+                c += blk.nb[J]
+            for J in blk.nbrs[Q]:
+                # C^nu (nu on Q) on rows of Q and columns of J, and its mirror
+                for P, part in _c_row_parts(blk, Q, J):
+                    if P != Q:
+                        continue
+                    sq, sj = slice(blk.bo[Q], blk.bo[Q + 1]), slice(blk.bo[J], blk.bo[J + 1])
+                    yJ = YQ[:, :, pos[J]:pos[J] + blk.nb[J]]          # [nu, i, l on J]
+                    KI[:, sq] += np.einsum("nkl,nil->ik", part, yJ, optimize=True)
+                    if J != Q:
+                        yQ = YQ[:, :, pos[Q]:pos[Q] + blk.nb[Q]]      # [nu, i, l on Q]
+                        KI[:, sj] += np.einsum("nkl,nik->il", part, yQ, optimize=True)
+        out.append(KI)
+    return np.concatenate(out) if out else np.zeros((0, blk.n))
+
+
 def k_full_rows(inputs, s=0):
     """The whole K of system s via the row route (moderate sizes only)."""
     blk = Blocks(inputs, s)
@@ -379,10 +466,3 @@ def forces(inputs, grads, c_decay=1.5, v_2s2=8.0):
         F[a] -= g
         F[b] += g
     return F
-
-
-def energy_at(inputs_fn, pos):
-    """E_x of the inputs regenerated at positions pos (helper for FD tests)."""
-    inp = inputs_fn(pos)
-    K = k_eigen(inp)
-    return exchange_energy(K, Blocks(inp).D)

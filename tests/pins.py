@@ -114,6 +114,9 @@ def _route(inp, route):
         return O.k_eigen(inp)
     if route == "rows":
         return O.k_full_rows(inp)
+    if route == "block":
+        blk = O.Blocks(inp)
+        return O.k_atom_rows(inp, range(blk.nat), blk=blk)
     raise ValueError(route)
 
 
@@ -188,12 +191,25 @@ def pin_energy_direct(seed=5):
 
 
 def pin_routes_agree(seed=6):
-    """The 4-index, eigen and row routes give the same K."""
+    """The 4-index, eigen, row and block routes give the same K."""
     sysm = synth.water_cluster(2, seed)
     inp, *_ = random_problem(sysm, seed)
     K4 = O.k_4index(inp)[0]
-    r1, r2 = rel(K4, O.k_eigen(inp)), rel(K4, O.k_full_rows(inp))
-    return max(r1, r2) < TOL, f"eigen {r1:.1e} rows {r2:.1e}"
+    r1, r2, r3 = rel(K4, O.k_eigen(inp)), rel(K4, O.k_full_rows(inp)), rel(K4, _route(inp, "block"))
+    return max(r1, r2, r3) < TOL, f"eigen {r1:.1e} rows {r2:.1e} block {r3:.1e}"
+
+
+def pin_block_route(seed=16):
+    """The block route (the CPU baseline's) on its own: the rank-1 closed form,
+    the invariants, and a three-molecule cluster with atoms of uneven
+    neighbourhoods against the 4-index route."""
+    ok1, m1 = pin_rank1_closed_form(route="block", seed=seed)
+    ok2, m2 = pin_invariants(route="block", seed=seed + 1)
+    sysm = synth.water_cluster(3, seed)
+    sysm.r_cut = 3.2
+    inp, *_ = random_problem(sysm, seed)
+    r = rel(_route(inp, "block"), O.k_4index(inp)[0])
+    return ok1 and ok2 and r < TOL, f"{m1}; {m2}; cut 3.2 A vs 4-index {r:.1e}"
 
 
 def paper_regrouped_X(C3, Vd, Dd, aux_atom, bas_atom):
@@ -411,6 +427,7 @@ def pin_two_kernels(seed=15):
 
 
 ALL_PINS = {
+    "block_route": pin_block_route,
     "screening": pin_screening,
     "rank1_4index": lambda: pin_rank1_closed_form("4index"),
     "rank1_rows": lambda: pin_rank1_closed_form("rows"),

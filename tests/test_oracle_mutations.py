@@ -30,6 +30,9 @@ MUTATIONS = {
     "spin_energy_factor": ("return -0.5 * sum(float(np.sum(K * D))", "return -0.25 * sum(float(np.sum(K * D))"),
     "two_kernels_same_V": ("return [f(inputs, s), f(with_coulomb(inputs, V2), s)]",
                            "return [f(inputs, s), f(inputs, s)]"),
+    "block_missing_mirror_term": ('KI[:, sj] += np.einsum("nkl,nik->il", part, yQ, optimize=True)', "pass"),
+    "block_V_not_transposed": ("VPQ = vb if P <= Q else vb.T                   # [mu on P, nu on Q]",
+                               "VPQ = vb if P <= Q else vb                     # [mu on P, nu on Q]"),
     "spin_ignores_D": ("return [f(with_density(inputs, D), s) for D in D_spin]",
                        "return [f(inputs, s) for D in D_spin]"),
 }
