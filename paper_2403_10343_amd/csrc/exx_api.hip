@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_repack(const double* __restrict__ C, De
 // pair, both orientations.
 // V == nullptr: the D operands only (into Dr)
 __global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, const double* __restrict__ D,
-                                                 double* __restrict__ Dr, DevPlan d) {
+                                                 double* __restrict__ Dr, DevPlan d, int fp32) {
   const int p = blockIdx.x;
   const int A = d.pair_a[p], B = d.pair_b[p];
   const double* Vp = V ? V + d.v_off[p] : nullptr;
@@ -150,11 +150,14 @@ __global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, 
     const int aP = d.na[P], aQ = d.na[Q], bP = d.nb[P], bQ = d.nb[Q];
     const int nsq = (aQ + 3) / 4;
     double* vr = d.Vr + d.vr_off[2 * p + o];
+    float* vr32 = fp32 ? d.Vr32 + d.vr_off[2 * p + o] : nullptr;
     const int nv = V ? (int)(d.vr_off[2 * p + o + 1] - d.vr_off[2 * p + o]) : 0;
     for (int e = threadIdx.x; e < nv; e += 256) {
       const int L = e & 63, tq = e >> 6, q = tq % nsq, t = tq / nsq;
       const int mu = 16 * t + (L & 15), nu = 4 * q + (L >> 4);
-      vr[e] = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
+      const double x = (mu < aP && nu < aQ) ? v_elem(Vp, P, Q, aP, aQ, mu, nu) : 0.0;
+      vr[e] = x;
+      if (fp32) vr32[e] = (float)x;
     }
     double* dr = Dr + d.dr_off[2 * p + o];
     const int nd = (int)(d.dr_off[2 * p + o + 1] - d.dr_off[2 * p + o]);
@@ -162,6 +165,14 @@ __global__ __launch_bounds__(256) void k_vdrepack(const double* __restrict__ V, 
       const int L = e & 63, q = e >> 6;
       const int j = L & 15, l = (L >> 4) + 4 * q;   // the f64 MFMA A-operand row of lane L, step q
       dr[e] = (j < bP && l < bQ) ? Ds[(size_t)(d.bo[P] + j) * ns + d.bo[Q] + l] : 0.0;
+    }
+    if (fp32) {
+      float* dr32 = d.Dr32 + (size_t)(2 * p + o) * 256;
+      for (int e = threadIdx.x; e < 256; e += 256) {
+        const int L = e & 63, q = e >> 6;
+        const int j = L & 15, l = 4 * (L >> 4) + q;   // binary32 accumulator row 4 (L / 16) + q
+        dr32[e] = (j < bP && l < bQ) ? (float)Ds[(size_t)(d.bo[P] + j) * ns + d.bo[Q] + l] : 0.f;
+      }
     }
   }
 }
@@ -552,14 +563,6 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_byte
     int smax = 1;
     for (int a = 0; a < pl->hp.n_atoms; ++a) smax = std::max(smax, pl->hp.na[a] * pl->hp.nb[a]);
     // k_H: T_Q tile | V blocks [nu][aux rows of the group] | D blocks
-    int vr_max = 1;
-    const HostPlan& hq = pl->hp;
-    for (size_t g = 0; g + 1 < hq.grp_unit_ptr.size(); ++g) {
-      const int nsl = hq.grp_units[hq.grp_unit_ptr[g + 1] - 1].slot + 1;
-      int vr = 0;
-      for (int t = 0; t < nsl; ++t) vr += hq.na[hq.grp_first[g] + t];
-      vr_max = std::max(vr_max, vr);
-    }
     // rows of the staged T_Q read by the chains: up to 4 NS * n_b(Q) + 16 (NS of Q's shape class)
     int h_rows = smax;
     for (int a = 0; a < pl->hp.n_atoms; ++a) {
@@ -568,12 +571,10 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_byte
       h_rows = std::max(h_rows, 4 * NS * pl->hp.nb[a] + 16);
     }
     pl->h_vbase = h_rows * LDS_PITCH;
-    pl->h_dbase = amax * vr_max;
-    const size_t h_elems = (size_t)pl->h_vbase + pl->h_dbase + GROUP_ATOMS * 16 * H_DPITCH;
-    pl->h_lds = (size_t)pl->h_vbase * sizeof(double);   // the binary64 kernel stages T_Q only
+    pl->h_lds = (size_t)pl->h_vbase * sizeof(double);   // k_H stages T_Q only
     pl->t2_lds = std::max((size_t)2 * smax * T2_PITCH, (size_t)16 * 64) * sizeof(double);
     pl->h_smax_t2 = smax;
-    pl->h_lds32 = h_elems * sizeof(float);
+    pl->h_lds32 = (size_t)pl->h_vbase * sizeof(float);
     pl->t2_lds32 = std::max((size_t)2 * smax * T2_PITCH * sizeof(float), (size_t)16 * 64 * sizeof(double));
   }
   if (!pl->host_only) {
@@ -730,17 +731,18 @@ static void launch_E(exx_plan plan, hipStream_t st) {
   launch_rowD(plan, plan->d.Dm, rowd_E(plan), cur_chunk(plan).n_e, st);
 }
 
-// the lane-ordered V and D operands of the V stage (DevPlan::Vr, Dr) for these V and D
-static void launch_vd_operands(exx_plan plan, const double* V, const double* D, hipStream_t st) {
+// the lane-ordered V and D operands of the V stage (DevPlan::Vr, Dr; with fp32 also the
+// binary32 copies Vr32, Dr32) for these V and D
+static void launch_vd_operands(exx_plan plan, const double* V, const double* D, hipStream_t st, bool fp32 = false) {
   const unsigned np = (unsigned)plan->hp.pair_a.size();
-  if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d.Dr, plan->d);
+  if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d.Dr, plan->d, fp32 ? 1 : 0);
 }
 
 // V stage (binary64) of the current chunk's groups; the operands must be in place
 static void launch_H(exx_plan plan, const double* V, const double* D, double gscale, int mode, hipStream_t st) {
   const DevPlan& d = plan->d;
   const ChunkDev& ch = cur_chunk(plan);
-  launch_H_lists<double>(plan, V, D, HLists{d.g_tiles + ch.gt_beg, d.gq, d.gx, plan->h_vbase, plan->h_dbase},
+  launch_H_lists<double>(plan, V, D, HLists{d.g_tiles + ch.gt_beg, d.gq, d.gx, plan->h_vbase},
                          ch.gt_end - ch.gt_beg, gscale, mode, st);
 }
 
@@ -752,10 +754,10 @@ static void launch_H_mixed(exx_plan plan, int m, const double* V, const double* 
   const std::vector<int>& src = plan->hp.mixed[m].far_src;
   const int fb = (int)(std::lower_bound(src.begin(), src.end(), ch.gt_beg) - src.begin());
   const int fe = (int)(std::lower_bound(src.begin(), src.end(), ch.gt_end) - src.begin());
-  launch_H_lists<double>(plan, V, D, HLists{md.tiles_near + ch.gt_beg, md.q_near, md.x_near, plan->h_vbase, plan->h_dbase},
+  launch_H_lists<double>(plan, V, D, HLists{md.tiles_near + ch.gt_beg, md.q_near, md.x_near, plan->h_vbase},
                          ch.gt_end - ch.gt_beg, 2.0, H_WRITE, st);
   stage_mark(plan, 3, st);
-  launch_H_lists<float>(plan, V, D, HLists{md.tiles_far + fb, md.q_far, md.x_far, plan->h_vbase, plan->h_dbase},
+  launch_H_lists<float>(plan, V, D, HLists{md.tiles_far + fb, md.q_far, md.x_far, plan->h_vbase},
                         fe - fb, 2.0, H_ADD, st);
 }
 
@@ -784,6 +786,20 @@ static void launch_T2(exx_plan plan, const double* V, double* K, hipStream_t st,
 static int prepare_mixed(exx_plan pl, int m) {
   MixedDev& md = pl->mdev[m];
   if (md.uploaded) return EXX_OK;
+  if (!pl->d.Vr32) {
+    const size_t np = pl->hp.pair_a.size();
+    int64_t nvr = 0;
+    for (size_t p = 0; p < np; ++p) {
+      const int A = pl->hp.pair_a[p], B = pl->hp.pair_b[p];
+      nvr += (int64_t)((pl->hp.na[A] + 15) / 16) * ((pl->hp.na[B] + 3) / 4) * 64;
+      if (A != B) nvr += (int64_t)((pl->hp.na[B] + 15) / 16) * ((pl->hp.na[A] + 3) / 4) * 64;
+    }
+    HIP_TRY(hipMalloc((void**)&pl->d.Vr32, sizeof(float) * std::max<int64_t>(1, nvr)));
+    pl->allocs.push_back(pl->d.Vr32);
+    HIP_TRY(hipMalloc((void**)&pl->d.Dr32, sizeof(float) * 256 * std::max<size_t>(1, 2 * np)));
+    pl->allocs.push_back(pl->d.Dr32);
+    pl->dev_bytes += (int64_t)sizeof(float) * (nvr + 512 * (int64_t)np);
+  }
   HostPlan& hp = pl->hp;
   MixedSet& ms = hp.mixed[m];
   if (!ms.ready) derive_mixed_lists(hp, m);
@@ -873,7 +889,7 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, hp.d_size);
   launch_dmask(plan, D, plan->d.Dm, st);
   launch_repack(plan, C, st);
-  launch_vd_operands(plan, V, D, st);
+  launch_vd_operands(plan, V, D, st, m >= 0);
   stage_mark(plan, 1, st);
   build_chunks(plan, V, D, K, m, st);
   stage_mark(plan, 7, st);
@@ -941,9 +957,9 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   launch_vd_operands(plan, V, D, st);   // V and D^0 operands
   if (!hp.pair_a.empty())
     hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
-                       plan->spin_Dr1, plan->d);   // D^1 operands
+                       plan->spin_Dr1, plan->d, 0);   // D^1 operands
   launch_H_lists<double, 2>(plan, V, D,
-                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->h_dbase, plan->spin_E1,
+                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
                                    plan->spin_H1, plan->spin_Dr1},
                             (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
   stage_mark(plan, 3, st);

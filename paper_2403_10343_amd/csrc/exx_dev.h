@@ -129,6 +129,10 @@ struct DevPlan {
   // coalesced 512-byte row instead of a gather over 16 rows of V or D.
   int64_t *vr_off, *dr_off;
   double *Vr, *Dr;
+  // binary32 copies for the far pair terms of a mixed build: Vr32 in the layout of Vr; Dr32 at
+  // (2 p + o) * 256, [k-step q < 4][lane L] = D_PQ[L % 16][4 (L / 16) + q] (the binary32 MFMA
+  // accumulator puts rows 4 (L / 16) + v in lane L, so its D chain runs four k-steps)
+  float *Vr32, *Dr32;
 };
 
 constexpr int N_STAGE_EV = EXX_N_STAGES + 1;   // stage boundaries, start and end included
@@ -192,7 +196,7 @@ struct exx_plan_s {
   size_t h_lds = 0;                 // dynamic LDS bytes of k_H (binary64)
   size_t t2_lds = 0;                // dynamic LDS bytes of k_T2 (binary64)
   size_t h_lds32 = 0, t2_lds32 = 0; // the same for the binary32 kernels
-  int h_vbase = 0, h_dbase = 0;     // element offsets of V and D in k_H's LDS
+  int h_vbase = 0;                  // elements of the T_Q tile k_H stages in LDS
   int h_smax_t2 = 1;                // largest n_aux * n_basis (T2 staging)
   int lds_max = 0;                  // LDS bytes a workgroup may use on the plan's device
   MixedDev mdev[2];                 // device copies of hp.mixed[0], hp.mixed[1]
@@ -263,7 +267,6 @@ __device__ __forceinline__ double v_elem(const double* Vp, int P, int Q, int aP,
 
 // V stage (k_H)
 constexpr int LDS_PITCH = H_COLS + 1;   // doubles per staged row (one pad column: no bank conflicts)
-constexpr int H_DPITCH = 17;            // staged D_PQ blocks: [slot][16 rows][17]
 constexpr int HQ_CHUNK = 64;            // Q-list entries whose metadata sits in LDS at once
 constexpr int H_WAVES = 4;
 constexpr int H_CPW = H_COLS / H_WAVES;
@@ -272,7 +275,7 @@ constexpr int H_CPW = H_COLS / H_WAVES;
 struct HLists {
   const GTile* tiles;
   const Slot4 *gq, *gx;
-  int v_base, d_base;     // element offsets of the staged V and D blocks in LDS
+  int v_base;             // elements of the staged T_Q tile (cleared before the Q loop)
   // second density matrix (collinear spin): its E and H' workspaces and its lane-ordered
   // D operands
   const double* E1;

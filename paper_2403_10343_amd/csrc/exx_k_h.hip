@@ -29,25 +29,54 @@ struct HUnits {            // unit table of the group (LDS)
   int P[GROUP_WAVES], mu0[GROUP_WAVES], slot[GROUP_WAVES], a[GROUP_WAVES], b[GROUP_WAVES], bo[GROUP_WAVES];
 };
 
-// The binary32 kernel stages the V_PQ and D_PQ blocks of the group in LDS
-// once per Q; the binary64 kernel reads them per unit from their lane-ordered copies.
-template <typename R> struct HStage { static constexpr bool vd = sizeof(R) == sizeof(float); };
+// The V and D operands of one unit and Q, read from their lane-ordered copies: one
+// coalesced row per MFMA step (steps past the blocks are zero).  Binary64 reads d.Vr and
+// d.Dr (second density matrix: Dr1); binary32 reads the binary32 copies d.Vr32 and d.Dr32,
+// whose D rows follow the binary32 accumulator layout (all four k-steps).
+template <typename R> struct HOperands;
+template <> struct HOperands<double> {
+  template <int NS, int NLR, int NSP>
+  static __device__ __forceinline__ void load(double (&vb)[NS], double (&da)[NSP][NLR], const DevPlan& d,
+                                              const double* Dr1, int pp, int orient, int mu_tile, int aQ, int bQ,
+                                              int L) {
+    const int nsq = (aQ + 3) >> 2, nlq = (bQ + 3) >> 2;
+    const double* vrow = d.Vr + d.vr_off[2 * pp + orient] + (size_t)mu_tile * nsq * 64 + L;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) vb[q] = q < nsq ? vrow[q * 64] : 0.0;
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp) {
+      const double* dr = (sp == 0 ? d.Dr : Dr1) + d.dr_off[2 * pp + orient] + L;
+#pragma unroll
+      for (int q = 0; q < NLR; ++q) da[sp][q] = q < nlq ? dr[q * 64] : 0.0;
+    }
+  }
+};
+template <> struct HOperands<float> {
+  template <int NS, int NLR, int NSP>
+  static __device__ __forceinline__ void load(float (&vb)[NS], float (&da)[NSP][NLR], const DevPlan& d,
+                                              const double*, int pp, int orient, int mu_tile, int aQ, int, int L) {
+    static_assert(NSP == 1 && NLR == 4, "binary32: one density matrix, four D steps");
+    const int nsq = (aQ + 3) >> 2;
+    const float* vrow = d.Vr32 + d.vr_off[2 * pp + orient] + (size_t)mu_tile * nsq * 64 + L;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) vb[q] = q < nsq ? vrow[q * 64] : 0.f;
+    const float* dr = d.Dr32 + (size_t)(2 * pp + orient) * 256 + L;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) da[0][q] = dr[q * 64];
+  }
+};
 
 // One Q of a V-stage tile, all H_CPW columns of this wavefront.  The staged T_Q
 // rows are read without masks: rows past s_Q (or of lanes past n_b(Q)) hold
 // finite values, and they meet zero V (nu >= n_a(Q)) or zero D (l >= n_b(Q))
-// operands.  A column missing from N[Q] is staged as zeros.
-// The binary64 kernel reads the V and D operands from their lane-ordered copies (d.Vr,
-// d.Dr); NSP density matrices (collinear spin: two, the second's D operands in Dr1) share F,
-// and each has its own D contraction and accumulators.  The binary32 kernel reads them from
-// the blocks it staged in LDS (sV, sD).
+// operands.  A column missing from N[Q] is staged as zeros.  NSP density
+// matrices (collinear spin: two, the second's D operands in Dr1) share F, and
+// each has its own D contraction and accumulators.
 template <int NS, int NL, int U, int NSP, typename R>
-__device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], const R* sT, const R* sV,
-                                    const R* sD, const HUnits& un, const int* roff, int nU, const int* qp, int Q,
-                                    int aQ, int bQ, const int* lc_row, int ncols, int c0, int lr, int lk,
-                                    const DevPlan& d, const double* Dr1) {
+__device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], const R* sT, const HUnits& un,
+                                    int nU, const int* qp, int Q, int aQ, int bQ, const int* lc_row, int ncols,
+                                    int c0, int lr, int lk, const DevPlan& d, const double* Dr1) {
   typedef typename Mf<R>::acc A4;
-  static_assert(NSP == 1 || !HStage<R>::vd, "the LDS-staged binary32 kernel takes one density matrix");
   bool anyc = false;
 #pragma unroll
   for (int cc = 0; cc < H_CPW; ++cc) anyc = anyc || ((c0 + cc < ncols) && lc_row[c0 + cc] >= 0);
@@ -59,44 +88,10 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
     if (u < nU) {
       const int sl = un.slot[u];
       if (qp[sl] >= 0) {
-        const int aP = un.a[u], bP = un.b[u];
-        const int muB = un.mu0[u] + lr;
-        const bool muv = muB < aP;
         R vb[NS];
         R da[NSP][NLR];
-        if constexpr (HStage<R>::vd) {
-          const bool pqs = un.P[u] <= Q;
-#pragma unroll
-          for (int q = 0; q < NS; ++q) {
-            const int nu = 4 * q + lk;
-            const bool ok = muv && nu < aQ;
-            // the canonical block as stored: [mu][nu] if P <= Q, else [nu][mu]
-            const int vi = pqs ? muB * aQ + nu : nu * aP + muB;
-            const R x = sV[ok ? roff[sl] * aQ + vi : 0];
-            vb[q] = ok ? x : (R)0;
-          }
-#pragma unroll
-          for (int q = 0; q < NLR; ++q) {
-            const int l = Mf<R>::row(lk, q);
-            const bool ok = lr < bP && l < bQ;
-            const R x = sD[ok ? (sl * 16 + lr) * H_DPITCH + l : 0];
-            da[0][q] = ok ? x : (R)0;
-          }
-        } else {
-          // the lane-ordered copies: one coalesced row per MFMA step (steps past the
-          // blocks are zero)
-          const int pp = qp[sl], orient = un.P[u] <= Q ? 0 : 1;
-          const int nsq = (aQ + 3) >> 2, nlq = (bQ + 3) >> 2, L = lk * 16 + lr;
-          const double* vrow = d.Vr + d.vr_off[2 * pp + orient] + (size_t)(un.mu0[u] >> 4) * nsq * 64 + L;
-#pragma unroll
-          for (int q = 0; q < NS; ++q) vb[q] = q < nsq ? (R)vrow[q * 64] : (R)0;
-#pragma unroll
-          for (int sp = 0; sp < NSP; ++sp) {
-            const double* dr = (sp == 0 ? d.Dr : Dr1) + d.dr_off[2 * pp + orient] + L;
-#pragma unroll
-            for (int q = 0; q < NLR; ++q) da[sp][q] = q < nlq ? (R)dr[q * 64] : (R)0;
-          }
-        }
+        HOperands<R>::template load<NS, NLR, NSP>(vb, da, d, Dr1, qp[sl], un.P[u] <= Q ? 0 : 1, un.mu0[u] >> 4,
+                                                  aQ, bQ, lk * 16 + lr);
         // the A operands of all columns first (independent LDS reads), then the chains
         R ta[NS][H_CPW];
 #pragma unroll
@@ -138,7 +133,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
   __shared__ HUnits un;
   __shared__ int qm_atom[HQ_CHUNK], qm_n[HQ_CHUNK], qm_a[HQ_CHUNK], qm_b[HQ_CHUNK], qm_bo[HQ_CHUNK];
   __shared__ int qm_lc[HQ_CHUNK][H_COLS], qm_p[HQ_CHUNK][GROUP_ATOMS];
-  __shared__ int64_t qm_toff[HQ_CHUNK], qm_voff[HQ_CHUNK][GROUP_ATOMS];
+  __shared__ int64_t qm_toff[HQ_CHUNK];
   const int ti = xcd_task(n_padded);
   if (ti >= n_tiles) return;
   const GTile tl = hl.tiles[ti];
@@ -156,9 +151,6 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
     un.b[threadIdx.x] = d.nb[x.P];
     un.bo[threadIdx.x] = d.bo[x.P];
   }
-  const int s = d.atom_sys[d.grp_first[g]];
-  const int64_t ns = d.sys_n[s];
-  const double* Ds = D + d.sys_d_off[s];
   const int* gcol = d.grp_cols + tl.col_beg;
   const int ncols = tl.ncols;
   const int c0 = wv * H_CPW;
@@ -171,24 +163,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       for (int cc = 0; cc < H_CPW; ++cc) Hc[sp][u][cc] = A4{0, 0, 0, 0};
   const int tc = threadIdx.x % H_COLS;
   const int tstep = blockDim.x / H_COLS;
-  // LDS: T_Q[:, tile columns] | V_PQ of the group's atoms, [nu][group aux row] | D_PQ blocks
-  R* sV = sT + hl.v_base;
-  R* sD = sV + hl.d_base;
-  __shared__ int roff[GROUP_ATOMS + 1], sP_[GROUP_ATOMS], sa_[GROUP_ATOMS], sb_[GROUP_ATOMS], sbo_[GROUP_ATOMS];
-  if (threadIdx.x == 0) {
-    const int a0 = d.grp_first[g];
-    const int nsl = d.grp_units[u0 + nU - 1].slot + 1;
-    roff[0] = 0;
-    for (int t = 0; t < GROUP_ATOMS; ++t) {
-      const int P = a0 + t;
-      const bool in = t < nsl;
-      sP_[t] = in ? P : -1;
-      sa_[t] = in ? d.na[P] : 0;
-      sb_[t] = in ? d.nb[P] : 0;
-      sbo_[t] = in ? d.bo[P] : 0;
-      roff[t + 1] = roff[t] + sa_[t];
-    }
-  }
+  // LDS: T_Q[:, tile columns]
   // rows read past s_Q stay finite (the G-only pass has no Q loop and no dynamic LDS)
   if (mode != H_G_ADD)
     for (int i = threadIdx.x; i < hl.v_base; i += blockDim.x) sT[i] = (R)0;
@@ -209,10 +184,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
         qm_bo[ei] = d.bo[Q];
         qm_toff[ei] = d.t_off[Q];
         const int pp[3] = {qe.p0, qe.p1, qe.p2};
-        for (int k = 0; k < GROUP_ATOMS; ++k) {
-          qm_p[ei][k] = pp[k];
-          qm_voff[ei][k] = pp[k] >= 0 ? d.v_off[pp[k]] : 0;
-        }
+        for (int k = 0; k < GROUP_ATOMS; ++k) qm_p[ei][k] = pp[k];
       }
     }
     __syncthreads();
@@ -222,30 +194,12 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       const double* TQ = d.T + qm_toff[ei] + (lcq >= 0 ? lcq : 0);
       for (int r = threadIdx.x / H_COLS; r < sQ; r += tstep)
         sT[r * LDS_PITCH + tc] = (R)(lcq >= 0 ? TQ[(size_t)r * nQ] : 0.0);
-      // V_PQ and D_PQ of every group atom paired with Q (coalesced reads of the
-      // canonical V block, transposed into [nu][row])
-#pragma unroll
-      for (int k = 0; k < GROUP_ATOMS; ++k) {
-        if (HStage<R>::vd && qm_p[ei][k] >= 0) {
-          const int P = sP_[k], aP = sa_[k], bP = sb_[k];
-          // plain copies: the V block as stored, the D block row by row
-          const double* Vp = V + qm_voff[ei][k];
-          R* dv = sV + roff[k] * aQ;
-          for (int i = threadIdx.x; i < aP * aQ; i += blockDim.x) dv[i] = (R)Vp[i];
-          const double* DPQ = Ds + (size_t)sbo_[k] * ns + qm_bo[ei];
-          for (int i = threadIdx.x; i < bP * 16; i += blockDim.x) {
-            const int j = i >> 4, l = i & 15;
-            if (l < bQ) sD[(k * 16 + j) * H_DPITCH + l] = (R)DPQ[(size_t)j * ns + l];
-          }
-          (void)P;
-        }
-      }
       __syncthreads();
       const int nsQ = (aQ + 3) >> 2, nlQ = (bQ + 3) >> 2;
       switch (h_class(nsQ, nlQ)) {
-        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
-        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
-        default: h_q<16, 4, U, NSP, R>(Hc, sT, sV, sD, un, roff, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        case 0: h_q<4, 2, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        case 1: h_q<10, 4, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        default: h_q<16, 4, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
       }
       __syncthreads();
     }
