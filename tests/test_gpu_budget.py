@@ -31,9 +31,11 @@ def grads(plan, inp, gE=1.0, K=None):
 @pytest.mark.parametrize("which", ["ice192", "ice768"])
 def test_chunked_plan_equals_stored(exx, which):
     """A budget a quarter of the stored intermediates forces several chunks; K,
-    E_x and every gradient agree with the unbounded plan (dC and dV bit for
-    bit: the same blocks in the same order; K and E_x up to the order in which
-    the chunks' parts of the final sum are added)."""
+    E_x and every gradient agree with the unbounded plan (dV bit for bit: the
+    same blocks in the same order; K and E_x up to the order in which the
+    chunks' parts of the final sum are added; dC up to the unbounded plan's
+    reuse of its forward V stage, whose G term is taken twice and once
+    subtracted)."""
     sysm = synth.ice_box(2, 2, 2, seed=3) if which == "ice192" else synth.config(2)
     inp = synth.make_inputs(sysm)
     full = exx.Plan.for_system(sysm)
@@ -54,7 +56,7 @@ def test_chunked_plan_equals_stored(exx, which):
         Km2, Em2 = run_build(part, inp, torch, prec)
         assert relmax(Km2, Km1) < 1e-12 and abs(Em2[0] - Em1[0]) < 1e-12 * abs(Em1[0])
     g1, g2 = grads(full, inp), grads(part, inp)
-    assert np.array_equal(g1["dC"], g2["dC"]) and np.array_equal(g1["dV"], g2["dV"])
+    assert relmax(g2["dC"], g1["dC"]) < 1e-12 and np.array_equal(g1["dV"], g2["dV"])
     assert relmax(g2["dD"], g1["dD"]) < 1e-12
     assert relmax(g2["F"], g1["F"]) < 1e-12
 
@@ -73,7 +75,7 @@ def test_chunked_batch_and_forward_K(exx):
     g1 = grads(full, inp, 0.5)
     g2 = grads(part, inp, 0.5, K=K)
     assert np.array_equal(g2["dD"], -0.25 * K2)
-    assert np.array_equal(g1["dC"], g2["dC"]) and np.array_equal(g1["dV"], g2["dV"])
+    assert relmax(g2["dC"], g1["dC"]) < 1e-12 and np.array_equal(g1["dV"], g2["dV"])
     for s in range(b.n_systems):
         Ko = O.k_eigen(inp, s)
         assert relmax(system_block(K2, inp.layout, s), Ko) < 1e-10
