@@ -234,8 +234,9 @@ class Plan:
         import torch
         if isinstance(gE, torch.Tensor):
             return gE.detach().to(device=device, dtype=torch.float64).reshape(-1).contiguous()
-        g = np.broadcast_to(np.asarray(gE, dtype=np.float64), (self.n_systems,))
-        return torch.from_numpy(np.ascontiguousarray(g)).to(device)
+        g = np.full(self.n_systems, 0.0)
+        g[:] = np.asarray(gE, dtype=np.float64)
+        return torch.from_numpy(g).to(device)
 
     def exchange_backward(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
                           precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):
