@@ -235,6 +235,21 @@ int exx_plan_set_mixed_split(exx_plan plan, double r_split);
 int exchange_energy(exx_plan plan, const double* K, const double* D,
                     double* Ex, void* stream);
 
+/* exchange_energy for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * result, bit for bit, with the partial sums in a static device array of
+ * EXX_NOALLOC_MAX_CHUNKS doubles (512 KiB per GPU, held until the process
+ * ends) instead of the plan's buffer.  The call allocates nothing.
+ * EXX_EINVAL if the plan's energy reduction has more chunks than that (the
+ * count is n_pairs / 64 rounded up per system, about 4 million canonical
+ * pairs at most).  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (different streams, threads or plans) race, and
+ * must be ordered by the caller.  The array's device address is looked up
+ * once per device on the first call. */
+#define EXX_NOALLOC_MAX_CHUNKS 65536
+int exchange_energy_noalloc(exx_plan plan, const double* K, const double* D,
+                            double* Ex, void* stream);
+
 /* Gradients of the scaled energy sum_s gE[s] * E_x[s] (gE: device [n_systems],
  * dL/dE_x of every system; each system's blocks are scaled by its own gE):
  *   dD (device, d_size, dense, symmetric): dE/dD_ik = -1/2 K_ik, the

@@ -55,7 +55,7 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
            "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
-           "build_K_two_kernels")
+           "build_K_two_kernels", "exchange_energy_noalloc")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -78,6 +78,7 @@ def lib():
     L.build_K_spin.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.build_K_two_kernels.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
+    L.exchange_energy_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
@@ -227,6 +228,14 @@ class Plan:
         n = self.info["d_size"]
         _check(lib().exchange_energy(self._h, _dev(K, n, "K"), _dev(D, n, "D"), _dev(Ex, self.n_systems, "Ex"),
                                      _stream(stream)))
+
+    def exchange_energy_noalloc(self, K, D, Ex, stream=None):
+        """exchange_energy with its partial sums in the library's static device
+        buffer: the call allocates no device memory (calls on one GPU must not
+        overlap)."""
+        n = self.info["d_size"]
+        _check(lib().exchange_energy_noalloc(self._h, _dev(K, n, "K"), _dev(D, n, "D"),
+                                             _dev(Ex, self.n_systems, "Ex"), _stream(stream)))
 
     def gE_tensor(self, gE, device):
         """dL/dE_x per system as the device array exchange_backward takes: a

@@ -26,9 +26,33 @@
 //   k_energy_*   E_x per system, fixed-order reduction
 #include "exx_dev.h"
 
+#include <mutex>
+
 using namespace exx;
 
 thread_local std::string g_err;
+
+// Partial sums of exchange_energy_noalloc: a fixed array in device memory (one copy per
+// GPU, held until the process ends), so that the call allocates nothing.  Host code never
+// uses the array's name as an address: its device address is looked up once per device
+// at plan creation (hipGetSymbolAddress with that device current) and kept per device.
+static __device__ __align__(256) double scratch[EXX_NOALLOC_MAX_CHUNKS];
+constexpr int MAX_DEVICES = 64;
+static double* g_scratch_dev[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device `dev` (looked up once)
+static int scratch_lookup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(EXX_EDEVICE, "libexx: device index beyond the supported 64");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return EXX_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(EXX_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_dev[dev] = static_cast<double*>(p);
+  return EXX_OK;
+}
 
 // Device copy of a host list, owned by the plan (or by mixed set m).
 template <typename X>
@@ -584,6 +608,10 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_byte
       return fail(EXX_EDEVICE, "exx_plan_create: cannot query the LDS size");
     }
     pl->lds_max = lds_max;
+    if ((rc = scratch_lookup(pl->device)) != EXX_OK) {
+      delete pl;
+      return rc;
+    }
     if (pl->t2_lds > (size_t)lds_max || pl->h_lds + 8192 > (size_t)lds_max) {   // static LDS of k_H < 8 KB
       delete pl;
       return fail(EXX_EUNSUPPORTED, "exx_plan_create: the largest n_aux * n_basis needs more LDS than a workgroup has");
@@ -1186,6 +1214,19 @@ int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex,
   if (plan->host_only) return fail(EXX_ESTATE, "exchange_energy: host-only plan");
   if (!K || !D || !Ex) return fail(EXX_EINVAL, "exchange_energy: NULL array");
   return launch_energy(plan, K, D, Ex, (hipStream_t)stream);
+}
+
+int exchange_energy_noalloc(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exchange_energy_noalloc: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exchange_energy_noalloc: host-only plan");
+  if (!K || !D || !Ex) return fail(EXX_EINVAL, "exchange_energy_noalloc: NULL array");
+  const size_t nch = plan->hp.en_sys.size();
+  if (nch > (size_t)EXX_NOALLOC_MAX_CHUNKS)
+    return fail(EXX_EINVAL, "exchange_energy_noalloc: " + std::to_string(nch) + " energy chunks exceed the static "
+                            "buffer of " + std::to_string(EXX_NOALLOC_MAX_CHUNKS));
+  double* part = plan->device >= 0 && plan->device < MAX_DEVICES ? g_scratch_dev[plan->device] : nullptr;
+  if (!part) return fail(EXX_ESTATE, "exchange_energy_noalloc: static buffer not set up for the plan's device");
+  return launch_energy(plan, K, D, Ex, (hipStream_t)stream, 1, part);
 }
 
 // dE/dC and dE/dV of one chunk: E, the V stage with the G term taken once, the
