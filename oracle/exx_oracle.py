@@ -466,3 +466,262 @@ def forces(inputs, grads, c_decay=1.5, v_2s2=8.0):
         F[a] -= g
         F[b] += g
     return F
+
+
+# ----------------------------------------------------------------------------
+# periodic systems (lattice vectors R != 0 of Eq. (realspace_exchange))
+#
+# Atoms of the home cell carry functions phi(r - R_A); their images in cell n
+# are phi(r - R_A - n.L).  The real-space exchange matrix X_ik(n) couples a
+# function i in the home cell with a function k in cell n; by translation
+# symmetry every block depends on relative images only, so the C, V and D
+# blocks of a pair of home-cell atoms (A, B) serve every pair of their images
+# with the same relative image.  With the cutoff below half the cell width a
+# pair of atoms has at most one image within the cutoff, and X is returned on
+# that pattern: the dense home-cell block (A, B) holds X_AB(n_AB) for the image
+# n_AB of B within the cutoff of A (zero if there is none).  D is given the same
+# way.  E_x = -1/4 sum over those blocks of X o D, the energy per cell.
+
+
+def _shift(lat, n):
+    return np.array([(n[0] * lat[0, c] + n[1] * lat[1, c]) + n[2] * lat[2, c] for c in range(3)])
+
+
+def periodic_pairs(pos, lat, r_cut):
+    """Canonical pairs (A <= B) with the image n of B within r_cut of A, in
+    lexicographic order of (A, B): squared distance ((x_B + s_x) - x_A)^2 + ...
+    summed as (dx*dx + dy*dy) + dz*dz, s the image shift."""
+    rc2 = r_cut * r_cut
+    imgs = [(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]
+    out = []
+    for a in range(len(pos)):
+        for b in range(a, len(pos)):
+            for n in imgs:
+                if a == b and n != (0, 0, 0):
+                    continue
+                s = _shift(lat, n)
+                dx, dy, dz = (pos[b, 0] + s[0]) - pos[a, 0], (pos[b, 1] + s[1]) - pos[a, 1], (pos[b, 2] + s[2]) - pos[a, 2]
+                if (dx * dx + dy * dy) + dz * dz <= rc2:
+                    out.append((a, b, n))
+    return out
+
+
+class PBlocks:
+    """Read access to the C / V / D inputs of a periodic system, blocks keyed
+    by atom pairs and relative lattice images."""
+
+    def __init__(self, inputs):
+        sysm, lay = inputs.system, inputs.layout
+        self.lat = sysm.lattice
+        self.nat = sysm.n_atoms
+        self.nb = sysm.basis_table[sysm.species].astype(np.int64)
+        self.na = sysm.aux_table[sysm.species].astype(np.int64)
+        self.bo = np.concatenate([[0], np.cumsum(self.nb)])
+        self.n = int(self.bo[-1])
+        pairs = periodic_pairs(sysm.pos, self.lat, sysm.r_cut)
+        mine = [(int(a), int(b), tuple(int(x) for x in n)) for a, b, n in zip(lay.pair_a, lay.pair_b, lay.pair_img)]
+        if mine != pairs:
+            raise ValueError("input layout does not match the oracle's periodic screening")
+        self.C, self.V = inputs.C, inputs.V
+        self.c_off, self.v_off = lay.c_off, lay.v_off
+        self.D = inputs.D[:self.n * self.n].reshape(self.n, self.n)
+        self.pair = {}                                  # (A, B, n) -> canonical index, A <= B
+        self.nbrs = [[] for _ in range(self.nat)]       # entries (B, n): B + n within r_cut of A
+        for q, (a, b, n) in enumerate(pairs):
+            self.pair[(a, b, n)] = q
+            self.nbrs[a].append((b, n))
+            if a != b:
+                self.nbrs[b].append((a, tuple(-x for x in n)))
+        for lst in self.nbrs:
+            lst.sort()
+        self.img_of = [dict(lst) for lst in self.nbrs]  # B -> its image within r_cut of A
+
+    def _canon(self, A, B, n):
+        """(canonical pair index, whether (A, B) is stored as (B, A))."""
+        if A < B or (A == B and n == (0, 0, 0)):
+            return self.pair.get((A, B, n)), False
+        return self.pair.get((B, A, tuple(-x for x in n))), True
+
+    def c_rows(self, I, J, m):
+        """C^mu restricted to rows on I (home cell) and columns on J + m, for
+        every mu with such a block: list of ((aux atom, image), [a, b_I, b_J])."""
+        q, flip = self._canon(I, J, m)
+        if q is None:
+            return []
+        blk = self.C[self.c_off[q]:self.c_off[q + 1]]
+        if I == J:
+            return [((I, (0, 0, 0)), blk.reshape(self.na[I], self.nb[I], self.nb[I]))]
+        if not flip:    # pair (I, J + m): rows aux of I, then aux of J + m
+            blk = blk.reshape(self.na[I] + self.na[J], self.nb[I], self.nb[J])
+            return [((I, (0, 0, 0)), blk[:self.na[I]]), ((J, m), blk[self.na[I]:])]
+        # stored as (J, I - m): aux of J first; translated by m it is the pair (J + m, I)
+        blk = blk.reshape(self.na[J] + self.na[I], self.nb[J], self.nb[I])
+        return [((J, m), blk[:self.na[J]].transpose(0, 2, 1)), ((I, (0, 0, 0)), blk[self.na[J]:].transpose(0, 2, 1))]
+
+    def v(self, P, p, Q, q):
+        """V_{mu nu}, mu on P + p, nu on Q + q (None beyond the cutoff)."""
+        r = tuple(b - a for a, b in zip(p, q))
+        k, flip = self._canon(P, Q, r)
+        if k is None:
+            return None
+        blk = self.V[self.v_off[k]:self.v_off[k + 1]]
+        return blk.reshape(self.na[Q], self.na[P]).T if flip else blk.reshape(self.na[P], self.na[Q])
+
+    def d(self, J, m, L, b):
+        """D between J + m and L + b (zeros beyond the cutoff)."""
+        r = tuple(y - x for x, y in zip(m, b))
+        if self.img_of[J].get(L) != r:
+            return np.zeros((self.nb[J], self.nb[L]))
+        return self.D[self.bo[J]:self.bo[J + 1], self.bo[L]:self.bo[L + 1]]
+
+    def entries(self, A, a):
+        """The neighbour entries of atom A placed at image a: (B, a + n)."""
+        return [(B, tuple(x + y for x, y in zip(a, n))) for B, n in self.nbrs[A]]
+
+
+def _add(a, b):
+    return tuple(x + y for x, y in zip(a, b))
+
+
+def _sub(a, b):
+    return tuple(x - y for x, y in zip(a, b))
+
+
+def x_atom_rows_periodic(inputs, atoms, pb=None):
+    """Rows of the folded X (see above) for all basis functions of the given
+    home-cell atoms: the definition X_ik(n) = sum_mu sum_nu V_{mu nu}
+    (C^mu D C^nu)_{i, k(n)} over all images, taken atom by atom as in
+    k_atom_rows with every atom labelled by its image, and kept on the pattern."""
+    if pb is None:
+        pb = PBlocks(inputs)
+    zero = (0, 0, 0)
+    out = []
+    for I in atoms:
+        I = int(I)
+        bI = int(pb.nb[I])
+        ent1 = pb.entries(I, zero)                               # N[I]
+        loc1, c = {}, 0
+        for e in ent1:
+            loc1[e] = c
+            c += pb.nb[e[0]]
+        n1 = c
+        U = {}
+        for (J, m) in ent1:
+            for key, part in pb.c_rows(I, J, m):
+                if key not in U:
+                    U[key] = np.zeros((pb.na[key[0]], bI, n1))
+                U[key][:, :, loc1[(J, m)]:loc1[(J, m)] + pb.nb[J]] += part
+        Y = {}
+        for (P, p), UP in U.items():
+            nq = pb.entries(P, p)                                # the nu atoms Q + q coupled to P + p
+            cols = []                                            # union of the neighbourhoods of those
+            for (Q, q) in nq:
+                for e in pb.entries(Q, q):
+                    if e not in cols:
+                        cols.append(e)
+            loc2, c = {}, 0
+            for e in cols:
+                loc2[e] = c
+                c += pb.nb[e[0]]
+            Dsub = np.zeros((n1, c))
+            for (J, m) in ent1:
+                for (L, b) in cols:
+                    Dsub[loc1[(J, m)]:loc1[(J, m)] + pb.nb[J], loc2[(L, b)]:loc2[(L, b)] + pb.nb[L]] = pb.d(J, m, L, b)
+            TP = (UP.reshape(-1, n1) @ Dsub).reshape(pb.na[P], bI, c)
+            for (Q, q) in nq:
+                VPQ = pb.v(P, p, Q, q)
+                ents = pb.entries(Q, q)
+                idx = np.concatenate([np.arange(loc2[e], loc2[e] + pb.nb[e[0]]) for e in ents])
+                contrib = (VPQ.T @ TP[:, :, idx].reshape(pb.na[P], -1)).reshape(pb.na[Q], bI, len(idx))
+                if (Q, q) in Y:
+                    Y[(Q, q)] += contrib
+                else:
+                    Y[(Q, q)] = contrib
+        XI = np.zeros((bI, pb.n))
+        pattern = dict(ent1)                                     # B -> the image kept for row atom I
+        for (Q, q), YQ in Y.items():
+            pos, c = {}, 0
+            for e in pb.entries(Q, q):
+                pos[e] = c
+                c += pb.nb[e[0]]
+            for (J, b) in pb.entries(Q, q):
+                # C^nu (nu on Q + q) on rows of Q + q and columns of J + b, and its mirror
+                for key, part in pb.c_rows(Q, J, _sub(b, q)):
+                    if key != (Q, zero):
+                        continue
+                    if pattern.get(Q) == q:
+                        yJ = YQ[:, :, pos[(J, b)]:pos[(J, b)] + pb.nb[J]]
+                        XI[:, pb.bo[Q]:pb.bo[Q + 1]] += np.einsum("nkl,nil->ik", part, yJ, optimize=True)
+                    if (J, b) != (Q, q) and pattern.get(J) == b:
+                        yQ = YQ[:, :, pos[(Q, q)]:pos[(Q, q)] + pb.nb[Q]]
+                        XI[:, pb.bo[J]:pb.bo[J + 1]] += np.einsum("nkl,nik->il", part, yQ, optimize=True)
+        out.append(XI)
+    return np.concatenate(out) if out else np.zeros((0, pb.n))
+
+
+def x_periodic(inputs):
+    """The folded X of the whole home cell (moderate sizes only)."""
+    pb = PBlocks(inputs)
+    return x_atom_rows_periodic(inputs, range(pb.nat), pb)
+
+
+def x_unfolded(inputs, reach=2.0):
+    """The folded X by a second, independent route: an explicit cluster of the
+    home cell's atoms and of every image within reach * r_cut of a home atom,
+    with each pair block copied from its home-cell pair at the same relative
+    image, evaluated with the 4-index route; rows of home atoms, kept on the
+    pattern.  (A pattern entry X_AB(n) involves only atoms within two cutoffs
+    of A, so reach 2 is exact.)  Small systems only."""
+    sysm, lay = inputs.system, inputs.layout
+    pb = PBlocks(inputs)
+    lat = sysm.lattice
+    reach_r = reach * sysm.r_cut
+    cands = []
+    rng3 = range(-3, 4)
+    for a in range(pb.nat):
+        for n in ((i, j, k) for i in rng3 for j in rng3 for k in rng3):
+            p = sysm.pos[a] + _shift(lat, n)
+            dmin = np.sqrt(((sysm.pos - p) ** 2).sum(1)).min()
+            if n == (0, 0, 0) or dmin <= reach_r + 1e-9:
+                cands.append((a, n))
+    cands.sort(key=lambda x: (x[1] != (0, 0, 0), x[1], x[0]))   # home cell first, in atom order
+    species = np.array([sysm.species[a] for a, _ in cands])
+    pos = np.array([sysm.pos[a] + _shift(lat, n) for a, n in cands])
+    import synth
+    ext = synth.System(species, pos, sysm.r_cut, sysm.seed, basis_table=sysm.basis_table,
+                       aux_table=sysm.aux_table, name="unfolded")
+    el = synth.make_layout(ext)
+    C = np.empty(int(el.c_off[-1]))
+    V = np.empty(int(el.v_off[-1]))
+    nbx = sysm.basis_table[species].astype(np.int64)
+    box = np.concatenate([[0], np.cumsum(nbx)])
+    nx = int(box[-1])
+    Dx = np.zeros((nx, nx))
+    for q, (A2, B2) in enumerate(zip(el.pair_a, el.pair_b)):
+        (A, a), (B, b) = cands[A2], cands[B2]
+        r = _sub(b, a)
+        if A2 == B2:
+            blk = pb.c_rows(A, A, (0, 0, 0))[0][1]
+            C[el.c_off[q]:el.c_off[q + 1]] = blk.ravel()
+        else:
+            parts = dict(pb.c_rows(A, B, r))
+            C[el.c_off[q]:el.c_off[q + 1]] = np.concatenate([parts[(A, (0, 0, 0))], parts[(B, r)]]).ravel()
+        V[el.v_off[q]:el.v_off[q + 1]] = pb.v(A, (0, 0, 0), B, r).ravel()
+        blkD = pb.d(A, (0, 0, 0), B, r)
+        Dx[box[A2]:box[A2 + 1], box[B2]:box[B2 + 1]] = blkD
+        Dx[box[B2]:box[B2 + 1], box[A2]:box[A2 + 1]] = blkD.T
+    ei = synth.Inputs(ext, el, C, V, Dx.ravel())
+    Kx = k_4index(ei)[0]
+    X = np.zeros((pb.n, pb.n))
+    for i2, (A, a) in enumerate(cands):
+        if a != (0, 0, 0):
+            continue
+        for j2, (B, b) in enumerate(cands):
+            if pb.img_of[A].get(B) == b:
+                X[pb.bo[A]:pb.bo[A + 1], pb.bo[B]:pb.bo[B + 1]] = Kx[box[i2]:box[i2 + 1], box[j2]:box[j2 + 1]]
+    return X
+
+
+def periodic_energy(X, D):
+    """E_x per cell: -1/4 sum over the pattern blocks of X o D (D is zero off the pattern)."""
+    return -0.25 * float(np.sum(X * D))

@@ -29,6 +29,9 @@ distributions are synthetic stand-ins):
 
 Random numbers come from per-block keyed streams (seed, kind, label_a,
 label_b), so values follow atoms under any permutation of the atom order.
+Periodic systems add the pair's lattice image (in cells of the generating
+lattice) to the key when it is not zero, so a cluster in a large box has the
+cluster's values and a supercell repeats its cell's values.
 """
 from __future__ import annotations
 
@@ -69,6 +72,9 @@ class System:
     name: str = ""
     basis_table: np.ndarray = None  # per-species basis counts (default N_BASIS)
     aux_table: np.ndarray = None    # per-species aux counts (default N_AUX)
+    lattice: np.ndarray = None      # (3, 3) lattice vectors (rows, A) of a periodic system, or None
+    cell_index: np.ndarray = None   # (n_atoms, 3) int: copy of the generating cell an atom sits in
+    cell_mult: np.ndarray = None    # (3,) int: cells of the generating lattice per lattice vector
 
     def __post_init__(self):
         self.species = np.ascontiguousarray(self.species, dtype=np.int32)
@@ -84,6 +90,18 @@ class System:
                                                 dtype=np.int32)
         self.aux_table = np.ascontiguousarray(N_AUX if self.aux_table is None else self.aux_table,
                                               dtype=np.int32)
+        if self.lattice is not None:
+            self.lattice = np.ascontiguousarray(self.lattice, dtype=np.float64).reshape(3, 3)
+            if self.cell_index is None:
+                self.cell_index = np.zeros((n, 3), dtype=np.int64)
+            if self.cell_mult is None:
+                self.cell_mult = np.ones(3, dtype=np.int64)
+            self.cell_index = np.ascontiguousarray(self.cell_index, dtype=np.int64).reshape(n, 3)
+            self.cell_mult = np.asarray(self.cell_mult, dtype=np.int64).reshape(3)
+
+    @property
+    def periodic(self):
+        return self.lattice is not None
 
     @property
     def n_atoms(self):
@@ -110,6 +128,7 @@ class Layout:
     bas_off: np.ndarray            # (n_atoms,) basis offset within its system
     sys_bas_off: np.ndarray        # (n_systems + 1,) int64, offsets of dense blocks in D/K
     sys_nbas: np.ndarray           # (n_systems,) int64
+    pair_img: np.ndarray = None    # (n_pairs, 3) int: lattice image n of B in pair (A, B + n)
 
     @property
     def n_pairs(self):
@@ -210,6 +229,36 @@ def ice_box(nx, ny, nz, seed, r_cut=6.0):
     return System(species, pos, r_cut, seed, name=f"ice_box_{nx}x{ny}x{nz}")
 
 
+def ice_box_periodic(nx, ny, nz, seed, r_cut=8.0):
+    """Periodic ice-like box of 8*nx*ny*nz water molecules: the sites and
+    jitter of ice_box, with the box edges as lattice vectors."""
+    sysm = ice_box(nx, ny, nz, seed, r_cut)
+    a = 4.0 * ICE_NN / math.sqrt(3.0)
+    return System(sysm.species, sysm.pos, r_cut, seed, name=f"ice_box_periodic_{nx}x{ny}x{nz}",
+                  lattice=np.diag([nx * a, ny * a, nz * a]))
+
+
+def supercell(system, mult):
+    """The periodic system repeated mult[0] x mult[1] x mult[2] times: copies
+    keep their atom labels and record the copy they sit in, so every pair block
+    of the supercell carries the values of the same pair of the cell."""
+    mult = np.asarray(mult, dtype=np.int64)
+    lat = system.lattice
+    species, pos, labels, cells = [], [], [], []
+    for i in range(mult[0]):
+        for j in range(mult[1]):
+            for k in range(mult[2]):
+                c = np.array([i, j, k])
+                species.append(system.species)
+                pos.append(system.pos + image_shift(lat, c))
+                labels.append(system.labels)
+                cells.append(np.tile(c, (system.n_atoms, 1)))
+    return System(np.concatenate(species), np.concatenate(pos), system.r_cut, system.seed,
+                  labels=np.concatenate(labels), name=system.name + "_super",
+                  basis_table=system.basis_table, aux_table=system.aux_table,
+                  lattice=lat * mult[:, None], cell_index=np.concatenate(cells), cell_mult=mult)
+
+
 def cluster_batch(n_clusters=64, batch_seed=123, n_min=8, n_max=128, r_cut=6.0):
     """Independent water clusters of uneven sizes, concatenated as one batch.
 
@@ -244,13 +293,57 @@ def permuted(system, perm):
 # ----------------------------------------------------------------------------
 # block layout
 
+def image_shift(lattice, n):
+    """n[0] a_0 + n[1] a_1 + n[2] a_2 per component, summed in that order."""
+    a = lattice
+    return np.array([(n[0] * a[0, c] + n[1] * a[1, c]) + n[2] * a[2, c] for c in range(3)])
+
+
+def half_width(lattice):
+    """Half the smallest distance between opposite faces of the cell."""
+    a = lattice
+    vol = abs(float(np.linalg.det(a)))
+    return 0.5 * min(vol / float(np.linalg.norm(np.cross(a[(i + 1) % 3], a[(i + 2) % 3]))) for i in range(3))
+
+
+IMAGES = [np.array((i, j, k)) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]
+
+
 def canonical_pairs(system):
     """All (A, B), A <= B, same system, |R_A - R_B|^2 <= r_cut^2, lexicographic.
 
     The squared distance is formed as dx*dx + dy*dy + dz*dz in float64,
-    left to right, without fused multiply-add."""
+    left to right, without fused multiply-add.  Periodic systems: B is taken
+    at the one lattice image R_B + n (n in {-1, 0, 1}^3, d = (R_B + shift) -
+    R_A) within the cutoff, which is unique because the cutoff is below half
+    the cell width; returns (pair_a, pair_b, pair_img)."""
     pa, pb = [], []
     rc2 = system.r_cut * system.r_cut
+    if system.periodic:
+        if system.r_cut >= half_width(system.lattice):
+            raise ValueError("r_cut must be below half the cell width")
+        shifts = [image_shift(system.lattice, n) for n in IMAGES]
+        P = system.pos
+        out_b, out_n = [], []
+        for a in range(system.n_atoms):
+            Pb = P[a:]
+            bs, ns = [], []
+            for k, sh in enumerate(shifts):
+                dx = (Pb[:, 0] + sh[0]) - P[a, 0]
+                dy = (Pb[:, 1] + sh[1]) - P[a, 1]
+                dz = (Pb[:, 2] + sh[2]) - P[a, 2]
+                hit = np.nonzero((dx * dx + dy * dy) + dz * dz <= rc2)[0]
+                if IMAGES[k].any():
+                    hit = hit[hit > 0]          # an atom is never paired with its own image
+                bs.append(hit + a)
+                ns.append(np.full(len(hit), k))
+            b = np.concatenate(bs)
+            k = np.concatenate(ns)
+            order = np.argsort(b, kind="stable")
+            pa.append(np.full(len(b), a, dtype=np.int32))
+            out_b.append(b[order].astype(np.int32))
+            out_n.append(np.array(IMAGES)[k[order]])
+        return np.concatenate(pa), np.concatenate(out_b), np.concatenate(out_n).astype(np.int64).reshape(-1, 3)
     for s in range(system.n_systems):
         lo, hi = int(system.sys_off[s]), int(system.sys_off[s + 1])
         P = system.pos[lo:hi]
@@ -265,7 +358,11 @@ def canonical_pairs(system):
 
 
 def make_layout(system):
-    pa, pb = canonical_pairs(system)
+    if system.periodic:
+        pa, pb, pimg = canonical_pairs(system)
+    else:
+        pa, pb = canonical_pairs(system)
+        pimg = np.zeros((len(pa), 3), dtype=np.int64)
     nb, na = system.nbas().astype(np.int64), system.naux().astype(np.int64)
     csz = np.where(pa == pb, na[pa] * nb[pa] * nb[pa], (na[pa] + na[pb]) * nb[pa] * nb[pb])
     vsz = na[pa] * na[pb]
@@ -278,7 +375,7 @@ def make_layout(system):
         bas_off[lo:hi] = np.concatenate([[0], np.cumsum(nb[lo:hi])[:-1]])
         sys_nbas[s] = nb[lo:hi].sum()
     sys_bas_off = np.concatenate([[0], np.cumsum(sys_nbas ** 2)]).astype(np.int64)
-    return Layout(pa, pb, c_off, v_off, bas_off, sys_bas_off, sys_nbas)
+    return Layout(pa, pb, c_off, v_off, bas_off, sys_bas_off, sys_nbas, pimg)
 
 
 # ----------------------------------------------------------------------------
@@ -296,8 +393,26 @@ def v_factors(seed, aux_table=N_AUX):
             for s in range(len(aux_table))]
 
 
+def _pair_geometry(system, layout, p):
+    """Separation vector R_A - (R_B + shift) of canonical pair p (shift: the
+    pair's lattice image for periodic systems) and the RNG image key: None for
+    clusters, else the image in units of the generating cell, so that a
+    supercell repeats its cell's values."""
+    A, B = int(layout.pair_a[p]), int(layout.pair_b[p])
+    if not system.periodic:
+        return system.pos[A] - system.pos[B], None
+    n = layout.pair_img[p]
+    d = system.pos[A] - (system.pos[B] + image_shift(system.lattice, n))
+    key = system.cell_index[B] - system.cell_index[A] + system.cell_mult * n
+    return d, np.asarray(key, dtype=np.int64)
+
+
 def make_inputs(system, layout=None, zero_D=False):
-    """Generate C, V, D for a system in the library's block layouts."""
+    """Generate C, V, D for a system in the library's block layouts.
+
+    Periodic systems: the blocks of pair (A, B) belong to B's lattice image
+    within the cutoff, and D holds, in its dense (A, B) block, D_AB at that
+    image (the only one inside the cutoff)."""
     if layout is None:
         layout = make_layout(system)
     sp, lab, pos = system.species, system.labels, system.pos
@@ -315,7 +430,7 @@ def make_inputs(system, layout=None, zero_D=False):
         sA, sB = int(sp[A]), int(sp[B])
         seed = system.seed if seeds is None else seeds[atom_sys[A]]
         Ls = L if seeds is None else v_factors(seed, na)
-        d = pos[A] - pos[B]
+        d, key = _pair_geometry(system, layout, p)
         r = math.sqrt(float(d @ d))
         c0, c1 = int(layout.c_off[p]), int(layout.c_off[p + 1])
         v0, v1 = int(layout.v_off[p]), int(layout.v_off[p + 1])
@@ -331,16 +446,17 @@ def make_inputs(system, layout=None, zero_D=False):
             dblk = _sym_upper(rng_d.normal(size=(nb[sA], nb[sA])))
         else:
             # generate in label orientation (lower label first), then map
-            flip = lab[A] > lab[B]
+            flip = lab[A] > lab[B] or (lab[A] == lab[B] and tuple(key) < (0, 0, 0))
             la, lb = (lab[B], lab[A]) if flip else (lab[A], lab[B])
             s1, s2 = (sB, sA) if flip else (sA, sB)
-            rng_c = _rng(seed, _KIND_C, la, lb)
+            img = [] if key is None or not key.any() else [int(x) + 8 for x in (-key if flip else key)]
+            rng_c = _rng(seed, _KIND_C, la, lb, *img)
             blk = rng_c.normal(size=(na[s1] + na[s2], nb[s1], nb[s2])) * math.exp(-r / C_DECAY)
             if flip:  # label order (B, A) -> index order (A, B)
                 blk = np.concatenate([blk[na[s1]:], blk[:na[s1]]], axis=0).transpose(0, 2, 1)
             C[c0:c1] = np.ascontiguousarray(blk).ravel()
             V[v0:v1] = (math.exp(-r * r / V_GAUSS_2S2) * (Ls[sA] @ Ls[sB].T)).ravel()
-            rng_d = _rng(seed, _KIND_D, la, lb)
+            rng_d = _rng(seed, _KIND_D, la, lb, *img)
             dblk = rng_d.normal(size=(nb[s1], nb[s2])) * math.exp(-r / D_DECAY)
             if flip:
                 dblk = dblk.T
@@ -368,7 +484,7 @@ def short_range_V(inputs, two_s2=V_SR_2S2):
         A, B = int(layout.pair_a[p]), int(layout.pair_b[p])
         sA, sB = int(sp[A]), int(sp[B])
         Ls = L if seeds is None else v_factors(seeds[atom_sys[A]], na)
-        d = pos[A] - pos[B]
+        d, _ = _pair_geometry(system, layout, p)
         r2 = float(d @ d)
         w = 1.0 if A == B else math.exp(-r2 / two_s2)
         V2[int(layout.v_off[p]):int(layout.v_off[p + 1])] = (w * (Ls[sA] @ Ls[sB].T)).ravel()
@@ -400,12 +516,13 @@ def spin_densities(inputs, polarization=SPIN_POLARIZATION):
         if A == B:
             blk = _sym_upper(_rng(seed, _KIND_SPIN, lab[A], lab[A]).normal(size=(nb[sA], nb[sA])))
         else:
-            d = pos[A] - pos[B]
+            d, key = _pair_geometry(system, layout, p)
             r = math.sqrt(float(d @ d))
-            flip = lab[A] > lab[B]
+            flip = lab[A] > lab[B] or (lab[A] == lab[B] and key is not None and tuple(key) < (0, 0, 0))
             la, lb = (lab[B], lab[A]) if flip else (lab[A], lab[B])
             s1, s2 = (sB, sA) if flip else (sA, sB)
-            blk = _rng(seed, _KIND_SPIN, la, lb).normal(size=(nb[s1], nb[s2])) * math.exp(-r / D_DECAY)
+            img = [] if key is None or not key.any() else [int(x) + 8 for x in (-key if flip else key)]
+            blk = _rng(seed, _KIND_SPIN, la, lb, *img).normal(size=(nb[s1], nb[s2])) * math.exp(-r / D_DECAY)
             if flip:
                 blk = blk.T
         Sm = S[so:so + n_s * n_s].reshape(n_s, n_s)
@@ -425,8 +542,8 @@ def config(n, seed=0):
     2: 256-molecule open ice box (768 atoms), r_cut 6 A.
     3: batch of 64 clusters of 8..128 molecules, r_cut 6 A.
     4: the 768-atom box again (differentiation workload).
-    5: 1024-molecule ice box (3072 atoms), r_cut 8 A (periodic in the paper's
-       sense; handled as the open box here when periodic images are off)."""
+    5: 1024-molecule periodic ice box (3072 atoms, 57.3 x 28.6 x 28.6 A
+       cell), r_cut 8 A."""
     if n == 1:
         return water_cluster(8, seed)
     if n in (2, 4):
@@ -434,5 +551,5 @@ def config(n, seed=0):
     if n == 3:
         return cluster_batch()
     if n == 5:
-        return ice_box(8, 4, 4, seed, r_cut=8.0)
+        return ice_box_periodic(8, 4, 4, seed, r_cut=8.0)
     raise ValueError(n)

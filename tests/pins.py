@@ -426,6 +426,61 @@ def pin_two_kernels(seed=15):
     return r < TOL, f"{r:.1e}"
 
 
+def _tiny_periodic(seed):
+    lat = np.array([[3.0, 0.0, 0.0], [0.4, 3.2, 0.0], [0.2, -0.3, 3.4]])
+    pos = np.array([[0.2, 0.3, 0.1], [2.6, 0.5, 0.4], [1.3, 2.9, 3.0], [1.5, 1.6, 1.7], [0.5, 2.8, 3.2]])
+    return synth.System(np.array([0, 1, 1, 0, 1]), pos, 1.45, seed, lattice=lat,
+                        basis_table=np.array([2, 1]), aux_table=np.array([3, 2]))
+
+
+def pin_periodic_unfolded(seed=17):
+    """Periodic route against an explicit cluster of the home cell and its
+    images (copied blocks, 4-index route), on a skewed cell whose atoms pair
+    with images across faces, edges and corners."""
+    sysm = _tiny_periodic(seed)
+    inp = synth.make_inputs(sysm)
+    imgs = np.abs(inp.layout.pair_img).sum(1)
+    Xp, Xu = O.x_periodic(inp), O.x_unfolded(inp)
+    r = rel(Xp, Xu)
+    n = Xp.shape[0]
+    e = abs(O.periodic_energy(Xp, inp.D.reshape(n, n)) - O.periodic_energy(Xu, inp.D.reshape(n, n)))
+    ok = r < TOL and (imgs > 1).any() and e <= TOL * abs(O.periodic_energy(Xu, inp.D.reshape(n, n)))
+    return ok, f"rel {r:.1e}, pairs with images {(imgs > 0).sum()} of {len(imgs)}"
+
+
+def pin_periodic_vacuum(seed=18):
+    """A cluster in a cell far larger than its reach: the periodic route gives
+    the cluster's K on the pair pattern (and the same E_x)."""
+    cl = synth.water_cluster(3, seed)
+    vb = synth.System(cl.species, cl.pos, cl.r_cut, cl.seed, lattice=np.diag([60.0, 61.0, 62.0]))
+    iv, ic = synth.make_inputs(vb), synth.make_inputs(cl)
+    Xv, Kc = O.x_periodic(iv), O.k_4index(ic)[0]
+    blk = O.Blocks(ic)
+    mask = np.zeros((blk.nat, blk.nat), bool)
+    mask[blk.pa, blk.pb] = mask[blk.pb, blk.pa] = True
+    atom = np.repeat(np.arange(blk.nat), blk.nb)
+    M = mask[atom][:, atom]
+    r = rel(Xv, np.where(M, Kc, 0.0))
+    Ev, Ec = O.periodic_energy(Xv, blk.D), O.exchange_energy(Kc, blk.D)
+    return r < TOL and abs(Ev - Ec) <= TOL * abs(Ec), f"rel {r:.1e}, E {Ev:.10e} vs {Ec:.10e}"
+
+
+def pin_periodic_supercell(seed=19):
+    """E_x per cell is extensive: a 2x1x1 and a 1x1x2 supercell (copies keep
+    their values) give twice the cell's E_x."""
+    cell = synth.ice_box_periodic(1, 1, 1, seed, r_cut=3.4)
+    ic = synth.make_inputs(cell)
+    n = int(ic.layout.sys_nbas[0])
+    Ec = O.periodic_energy(O.x_periodic(ic), ic.D.reshape(n, n))
+    worst = 0.0
+    for mult in ([2, 1, 1], [1, 1, 2]):
+        sup = synth.supercell(cell, mult)
+        isup = synth.make_inputs(sup)
+        Es = O.periodic_energy(O.x_periodic(isup), isup.D.reshape(2 * n, 2 * n))
+        worst = max(worst, abs(Es - 2 * Ec) / abs(Ec))
+    return worst < TOL, f"E cell {Ec:.10e}, worst rel deviation of E(super)/2 {worst:.1e}"
+
+
 ALL_PINS = {
     "block_route": pin_block_route,
     "screening": pin_screening,
@@ -447,4 +502,7 @@ ALL_PINS = {
     "fd_forces": pin_fd_forces,
     "spin": pin_spin,
     "two_kernels": pin_two_kernels,
+    "periodic_unfolded": pin_periodic_unfolded,
+    "periodic_vacuum": pin_periodic_vacuum,
+    "periodic_supercell": pin_periodic_supercell,
 }

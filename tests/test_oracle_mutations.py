@@ -33,6 +33,10 @@ MUTATIONS = {
     "block_missing_mirror_term": ('KI[:, sj] += np.einsum("nkl,nik->il", part, yQ, optimize=True)', "pass"),
     "block_V_not_transposed": ("VPQ = vb if P <= Q else vb.T                   # [mu on P, nu on Q]",
                                "VPQ = vb if P <= Q else vb                     # [mu on P, nu on Q]"),
+    "periodic_flip_image_sign": ("return [((J, m), blk[:self.na[J]].transpose(0, 2, 1)), ((I, (0, 0, 0)), blk[self.na[J]:].transpose(0, 2, 1))]",
+                                 "return [((J, m), blk[self.na[J]:].transpose(0, 2, 1)), ((I, (0, 0, 0)), blk[:self.na[J]].transpose(0, 2, 1))]"),
+    "periodic_D_any_image": ("        if self.img_of[J].get(L) != r:", "        if L not in self.img_of[J]:"),
+    "periodic_V_relative_image": ("        r = tuple(b - a for a, b in zip(p, q))", "        r = q"),
     "spin_ignores_D": ("return [f(with_density(inputs, D), s) for D in D_spin]",
                        "return [f(inputs, s) for D in D_spin]"),
 }
@@ -58,4 +62,5 @@ def test_mutation_is_caught(name, monkeypatch):
             ok = False
         if not ok:
             failed.append(pin_name)
+            break
     assert failed, f"mutation {name} was not caught by any pin"
