@@ -1,16 +1,17 @@
 /*
  * exx.h -- C ABI of the MI355X RI-LVL exact-exchange library (libexx.so).
  *
- * The library evaluates the non-periodic (lattice vector R = 0) real-space
- * exchange matrix of the localized resolution-of-identity method
- * (Kokott et al., Sec. "Description of the real-space formalism",
- * Eq. realspace_exchange at R = 0, with the RI-LVL pair restriction
- * C^mu_ij = 0 unless the auxiliary function mu sits on the atom of i or j):
+ * The library evaluates the real-space exchange matrix of the localized
+ * resolution-of-identity method (Kokott et al., Sec. "Description of the
+ * real-space formalism", Eq. realspace_exchange, with the RI-LVL pair
+ * restriction C^mu_ij = 0 unless the auxiliary function mu sits on the atom of
+ * i or j), for clusters (lattice vector R = 0 only):
  *
  *     K_ik = sum_{j,l} sum_{mu,nu} C^mu_ij V_{mu nu} C^nu_kl D_jl
  *     E_x  = -1/4 sum_{i,k} K_ik D_ik
  *
- * and the derivatives of E_x.  All floating-point arrays are IEEE binary64.
+ * and the derivatives of E_x, and for periodic systems (see "Periodic systems"
+ * below).  All floating-point arrays are IEEE binary64.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -39,6 +40,23 @@
  *       in system order.  D entries of atom pairs beyond r_cut are ignored
  *       (treated as zero): the library contracts a copy of D restricted to the
  *       screened pair blocks, and E_x sums over those blocks only.
+ *
+ * Periodic systems (exx_system.lattice != NULL; one system per plan): every
+ * atom A of the home cell has images A + n.L in all cells n.  The cutoff must
+ * be below half the distance between opposite cell faces, so an atom pair
+ * (A, B) has at most one image n_AB of B within r_cut of A: the pair is screened
+ * as ((x_B + s_x) - x_A)^2 + ... (summed (dx*dx + dy*dy) + dz*dz, binary64,
+ * s = (n0 a0 + n1 a1) + n2 a2 per component, n in {-1, 0, 1}^3) and its C, V and
+ * D blocks are those of B at that image: C^mu_{i(A) j(B + n_AB)} for mu on A or
+ * on B + n_AB, V_{mu(A) nu(B + n_AB)}, D_{A, B + n_AB}.  D and the output X keep
+ * the dense layout: block (A, B) holds the pair's block at n_AB, zero for pairs
+ * beyond the cutoff.  The output is the real-space X_ik(n) of Eq.
+ * realspace_exchange restricted to that pattern (i on A in the home cell, k on
+ * B at n_AB), and E_x = -1/4 sum over those blocks of X o D is the exchange
+ * energy per cell.  exx_pair_images() returns n_AB.  Periodic plans take
+ * build_K (every precision), graphs, the autotuner and the energy entry
+ * points; spin, two-kernel and backward calls return EXX_EUNSUPPORTED, and so
+ * does a workspace budget that would need chunks.
  *
  * Ownership: the caller owns every device array passed in; the plan owns its
  * bookkeeping lists and workspace.  Output arrays are fully overwritten
@@ -92,10 +110,9 @@ typedef struct {
     const int32_t* sys_atom_off; /* host [n_systems + 1], increasing, first 0,
                                     last n_atoms; may be NULL if n_systems == 1 */
     const double* lattice;       /* host [3][3] lattice vectors (rows, Angstrom) of a
-                                    periodic system, or NULL for clusters.  Periodic
-                                    systems (lattice vectors R != 0 of Eq.
-                                    realspace_exchange) are not implemented: a non-NULL
-                                    lattice returns EXX_EUNSUPPORTED. */
+                                    periodic system (n_systems must be 1; r_cut below
+                                    half the cell width, else EXX_EINVAL), or NULL for
+                                    clusters */
 } exx_system;
 
 typedef struct {
@@ -142,6 +159,10 @@ int exx_plan_info(exx_plan plan, exx_info* info);
  * NULL to skip that array.  n_pairs is in exx_plan_info(). */
 int exx_pair_layout(exx_plan plan, int32_t* pair_a, int32_t* pair_b,
                     int64_t* c_off, int64_t* v_off);
+
+/* Lattice image n_AB of every canonical pair (periodic plans; zeros for
+ * clusters): host int32 [n_pairs][3]. */
+int exx_pair_images(exx_plan plan, int32_t* images);
 
 /* Neighbour lists as built on the device (for inspection and tests):
  * nbr_ptr [n_atoms + 1], nbr_atom [nbr_ptr[n_atoms]], host arrays.  Pass

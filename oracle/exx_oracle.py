@@ -493,16 +493,20 @@ def periodic_pairs(pos, lat, r_cut):
     summed as (dx*dx + dy*dy) + dz*dz, s the image shift."""
     rc2 = r_cut * r_cut
     imgs = [(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]
+    shifts = [_shift(lat, n) for n in imgs]
     out = []
     for a in range(len(pos)):
-        for b in range(a, len(pos)):
-            for n in imgs:
-                if a == b and n != (0, 0, 0):
+        found = {}
+        for n, sft in zip(imgs, shifts):
+            b = np.arange(a, len(pos))
+            dx = (pos[b, 0] + sft[0]) - pos[a, 0]
+            dy = (pos[b, 1] + sft[1]) - pos[a, 1]
+            dz = (pos[b, 2] + sft[2]) - pos[a, 2]
+            for bb in b[(dx * dx + dy * dy) + dz * dz <= rc2]:
+                if bb == a and n != (0, 0, 0):
                     continue
-                s = _shift(lat, n)
-                dx, dy, dz = (pos[b, 0] + s[0]) - pos[a, 0], (pos[b, 1] + s[1]) - pos[a, 1], (pos[b, 2] + s[2]) - pos[a, 2]
-                if (dx * dx + dy * dy) + dz * dz <= rc2:
-                    out.append((a, b, n))
+                found[int(bb)] = n
+        out.extend((a, b, found[b]) for b in sorted(found))
     return out
 
 
@@ -595,6 +599,30 @@ def x_atom_rows_periodic(inputs, atoms, pb=None):
     if pb is None:
         pb = PBlocks(inputs)
     zero = (0, 0, 0)
+    nat = pb.nat
+    # image of B within r_cut of A as a dense table (codes; -1: none), for the D blocks
+    code = lambda n: (n[0] + 8) + 16 * (n[1] + 8) + 256 * (n[2] + 8)
+    if not hasattr(pb, "_img_tab"):
+        tab = np.full((nat, nat), -1, dtype=np.int64)
+        for A in range(nat):
+            for B, n in pb.nbrs[A]:
+                tab[A, B] = code(n)
+        pb._img_tab = tab
+    tab = pb._img_tab
+
+    def d_rows_cols(rows, cols):
+        """D between the row entries (J, m) and column entries (L, b): the folded
+        D block of (J, L) where n_JL = b - m, zero elsewhere."""
+        rj = np.array([J for J, _ in rows])
+        rm = np.array([code(m) for _, m in rows])
+        cl = np.array([L for L, _ in cols])
+        cb = np.array([code(b) for _, b in cols])
+        ok = (tab[np.ix_(rj, cl)] >= 0) & (tab[np.ix_(rj, cl)] + rm[:, None] - code(zero) == cb[None, :])
+        rb = np.concatenate([np.arange(pb.bo[J], pb.bo[J + 1]) for J in rj])
+        cbas = np.concatenate([np.arange(pb.bo[L], pb.bo[L + 1]) for L in cl])
+        okb = np.repeat(np.repeat(ok, pb.nb[rj], axis=0), pb.nb[cl], axis=1)
+        return np.where(okb, pb.D[np.ix_(rb, cbas)], 0.0)
+
     out = []
     for I in atoms:
         I = int(I)
@@ -614,20 +642,12 @@ def x_atom_rows_periodic(inputs, atoms, pb=None):
         Y = {}
         for (P, p), UP in U.items():
             nq = pb.entries(P, p)                                # the nu atoms Q + q coupled to P + p
-            cols = []                                            # union of the neighbourhoods of those
-            for (Q, q) in nq:
-                for e in pb.entries(Q, q):
-                    if e not in cols:
-                        cols.append(e)
+            cols = sorted({e for (Q, q) in nq for e in pb.entries(Q, q)})   # their neighbourhoods
             loc2, c = {}, 0
             for e in cols:
                 loc2[e] = c
                 c += pb.nb[e[0]]
-            Dsub = np.zeros((n1, c))
-            for (J, m) in ent1:
-                for (L, b) in cols:
-                    Dsub[loc1[(J, m)]:loc1[(J, m)] + pb.nb[J], loc2[(L, b)]:loc2[(L, b)] + pb.nb[L]] = pb.d(J, m, L, b)
-            TP = (UP.reshape(-1, n1) @ Dsub).reshape(pb.na[P], bI, c)
+            TP = (UP.reshape(-1, n1) @ d_rows_cols(ent1, cols)).reshape(pb.na[P], bI, c)
             for (Q, q) in nq:
                 VPQ = pb.v(P, p, Q, q)
                 ents = pb.entries(Q, q)
@@ -640,19 +660,26 @@ def x_atom_rows_periodic(inputs, atoms, pb=None):
         XI = np.zeros((bI, pb.n))
         pattern = dict(ent1)                                     # B -> the image kept for row atom I
         for (Q, q), YQ in Y.items():
+            ents = pb.entries(Q, q)
+            on_q = pattern.get(Q) == q
+            if not on_q and not any(pattern.get(J) == b for J, b in ents):
+                continue
             pos, c = {}, 0
-            for e in pb.entries(Q, q):
+            for e in ents:
                 pos[e] = c
                 c += pb.nb[e[0]]
-            for (J, b) in pb.entries(Q, q):
+            for (J, b) in ents:
+                mirror = (J, b) != (Q, q) and pattern.get(J) == b
+                if not (on_q or mirror):
+                    continue
                 # C^nu (nu on Q + q) on rows of Q + q and columns of J + b, and its mirror
                 for key, part in pb.c_rows(Q, J, _sub(b, q)):
                     if key != (Q, zero):
                         continue
-                    if pattern.get(Q) == q:
+                    if on_q:
                         yJ = YQ[:, :, pos[(J, b)]:pos[(J, b)] + pb.nb[J]]
                         XI[:, pb.bo[Q]:pb.bo[Q + 1]] += np.einsum("nkl,nil->ik", part, yJ, optimize=True)
-                    if (J, b) != (Q, q) and pattern.get(J) == b:
+                    if mirror:
                         yQ = YQ[:, :, pos[(Q, q)]:pos[(Q, q)] + pb.nb[Q]]
                         XI[:, pb.bo[J]:pb.bo[J + 1]] += np.einsum("nkl,nik->il", part, yQ, optimize=True)
         out.append(XI)

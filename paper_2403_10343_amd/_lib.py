@@ -55,7 +55,7 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
            "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
-           "build_K_two_kernels", "exchange_energy_noalloc")
+           "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -73,6 +73,7 @@ def lib():
     L.exx_plan_destroy.argtypes = [vp]
     L.exx_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
     L.exx_pair_layout.argtypes = [vp, vp, vp, vp, vp]
+    L.exx_pair_images.argtypes = [vp, vp]
     L.exx_plan_neighbors.argtypes = [vp, vp, vp]
     L.build_K.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.build_K_spin.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
@@ -164,7 +165,8 @@ class Plan:
         """Plan for a ``synth.System``-like object (species, pos, species tables
         basis_table / aux_table, r_cut, sys_off)."""
         return cls(system.species, system.pos, system.basis_table, system.aux_table, system.r_cut,
-                   system.sys_off if system.n_systems > 1 else None, host_only, ws_budget_bytes)
+                   system.sys_off if system.n_systems > 1 else None, host_only, ws_budget_bytes,
+                   getattr(system, "lattice", None))
 
     def _info(self):
         inf = _Info()
@@ -177,6 +179,12 @@ class Plan:
         co, vo = np.empty(n + 1, np.int64), np.empty(n + 1, np.int64)
         _check(lib().exx_pair_layout(self._h, pa.ctypes.data, pb.ctypes.data, co.ctypes.data, vo.ctypes.data))
         return pa, pb, co, vo
+
+    def pair_images(self):
+        """Lattice image of B for every canonical pair (A, B): int32 [n_pairs, 3]."""
+        img = np.empty((self.info["n_pairs"], 3), np.int32)
+        _check(lib().exx_pair_images(self._h, img.ctypes.data))
+        return img
 
     def neighbors(self):
         ptr = np.empty(self.n_atoms + 1, np.int32)

@@ -17,7 +17,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-value",
 ]
-SOURCES = ["exx_api.hip", "exx_k_gemm.hip", "exx_k_h.hip", "exx_k_t2.hip", "exx_k_dv.hip", "exx_plan.cpp"]
+SOURCES = ["exx_api.hip", "exx_k_gemm.hip", "exx_k_h.hip", "exx_k_t2.hip", "exx_k_dv.hip", "exx_plan.cpp",
+           "exx_plan_periodic.cpp"]
 
 
 def _compile(src, obj):
@@ -39,7 +40,8 @@ def build(verbose=False, jobs=None):
                 sys.stderr.write(r.stdout + r.stderr)
         if bad:
             raise RuntimeError("hipcc failed building " + ", ".join(s for s, _ in bad))
-        r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs],
+        r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined",
+                            "-o", LIB + ".tmp", *objs],
                            capture_output=True, text=True)
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)

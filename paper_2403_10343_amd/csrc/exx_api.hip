@@ -130,6 +130,63 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const double* pos, const int* 
   }
 }
 
+// Periodic screening: atom b pairs with a at the one image (of the 27 around the home
+// cell, shifts sh[t] computed on the host) within the cutoff; the atom itself only at
+// image 0.  Same arithmetic as the host builder: ((x_b + s) - x_a)^2 ... summed (xx + yy) + zz.
+__device__ __forceinline__ int periodic_image(const double* pos, const double* sh, const int* codes, int a, int b,
+                                              double rc2) {
+  for (int t = 0; t < 27; ++t) {
+    if (a == b && codes[t] != IMG0) continue;
+    const double dx = __dsub_rn(__dadd_rn(pos[3 * b], sh[3 * t]), pos[3 * a]);
+    const double dy = __dsub_rn(__dadd_rn(pos[3 * b + 1], sh[3 * t + 1]), pos[3 * a + 1]);
+    const double dz = __dsub_rn(__dadd_rn(pos[3 * b + 2], sh[3 * t + 2]), pos[3 * a + 2]);
+    const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    if (r2 <= rc2) return codes[t];
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void k_nbr_count_p(const double* pos, const double* sh, const int* codes, int n,
+                                                     double rc2, int* count) {
+  const int a = blockIdx.x;
+  __shared__ int part[256];
+  int c = 0;
+  for (int b = threadIdx.x; b < n; b += 256) c += periodic_image(pos, sh, codes, a, b, rc2) >= 0 ? 1 : 0;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[a] = part[0];
+}
+
+__global__ __launch_bounds__(256) void k_nbr_fill_p(const double* pos, const double* sh, const int* codes, int n,
+                                                    double rc2, const int* ptr, int* out, int* out_img) {
+  const int a = blockIdx.x;
+  __shared__ int scan[256];
+  int base = ptr[a];
+  for (int b0 = 0; b0 < n; b0 += 256) {
+    const int b = b0 + threadIdx.x;
+    const int im = b < n ? periodic_image(pos, sh, codes, a, b, rc2) : -1;
+    const int f = im >= 0 ? 1 : 0;
+    scan[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {  // inclusive Hillis-Steele scan
+      int v = (threadIdx.x >= w) ? scan[threadIdx.x - w] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (f) {
+      out[base + scan[threadIdx.x] - 1] = b;
+      out_img[base + scan[threadIdx.x] - 1] = im;
+    }
+    base += scan[255];
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // stage 0: row-owned coefficients T_P from the canonical C pair blocks.
 // One workgroup per neighbour entry (P, J): the s_P x n_basis(J) sub-block.
@@ -361,8 +418,54 @@ __global__ void k_scaled_copy_sys(double* y, const double* x, const double* __re
 // ---------------------------------------------------------------------------
 // plan creation
 
+static int device_neighbors_periodic(exx_plan_s* pl) {
+  HostPlan& hp = pl->hp;
+  const int NA = hp.n_atoms;
+  double sh[27 * 3];
+  int codes[27];
+  for (int t = 0; t < 27; ++t) {
+    codes[t] = img_code(t / 9 - 1, (t / 3) % 3 - 1, t % 3 - 1);
+    image_shift(hp.lat, codes[t], sh + 3 * t);
+  }
+  double *dpos = nullptr, *dsh = nullptr;
+  int *dcodes = nullptr, *dcnt = nullptr, *dptr = nullptr, *dout = nullptr, *dimg = nullptr;
+  auto cleanup = [&]() {
+    hipFree(dpos); hipFree(dsh); hipFree(dcodes); hipFree(dcnt); hipFree(dptr); hipFree(dout); hipFree(dimg);
+  };
+  hipError_t e = hipSuccess;
+#define NB_TRY(x) do { e = (x); if (e != hipSuccess) { cleanup(); return fail(EXX_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e)); } } while (0)
+  NB_TRY(hipMalloc((void**)&dpos, sizeof(double) * 3 * NA));
+  NB_TRY(hipMalloc((void**)&dsh, sizeof(sh)));
+  NB_TRY(hipMalloc((void**)&dcodes, sizeof(codes)));
+  NB_TRY(hipMalloc((void**)&dcnt, sizeof(int) * NA));
+  NB_TRY(hipMemcpy(dpos, hp.pos.data(), sizeof(double) * 3 * NA, hipMemcpyHostToDevice));
+  NB_TRY(hipMemcpy(dsh, sh, sizeof(sh), hipMemcpyHostToDevice));
+  NB_TRY(hipMemcpy(dcodes, codes, sizeof(codes), hipMemcpyHostToDevice));
+  const double rc2 = hp.r_cut * hp.r_cut;
+  hipLaunchKernelGGL(k_nbr_count_p, dim3(NA), dim3(256), 0, 0, dpos, dsh, dcodes, NA, rc2, dcnt);
+  NB_TRY(hipGetLastError());
+  std::vector<int> cnt(NA);
+  NB_TRY(hipMemcpy(cnt.data(), dcnt, sizeof(int) * NA, hipMemcpyDeviceToHost));
+  hp.nbr_ptr.assign(NA + 1, 0);
+  for (int a = 0; a < NA; ++a) hp.nbr_ptr[a + 1] = hp.nbr_ptr[a] + cnt[a];
+  NB_TRY(hipMalloc((void**)&dptr, sizeof(int) * (NA + 1)));
+  NB_TRY(hipMalloc((void**)&dout, sizeof(int) * std::max(1, hp.nbr_ptr[NA])));
+  NB_TRY(hipMalloc((void**)&dimg, sizeof(int) * std::max(1, hp.nbr_ptr[NA])));
+  NB_TRY(hipMemcpy(dptr, hp.nbr_ptr.data(), sizeof(int) * (NA + 1), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_nbr_fill_p, dim3(NA), dim3(256), 0, 0, dpos, dsh, dcodes, NA, rc2, dptr, dout, dimg);
+  NB_TRY(hipGetLastError());
+  hp.nbr_atom.resize(hp.nbr_ptr[NA]);
+  hp.nbr_img.resize(hp.nbr_ptr[NA]);
+  NB_TRY(hipMemcpy(hp.nbr_atom.data(), dout, sizeof(int) * hp.nbr_ptr[NA], hipMemcpyDeviceToHost));
+  NB_TRY(hipMemcpy(hp.nbr_img.data(), dimg, sizeof(int) * hp.nbr_ptr[NA], hipMemcpyDeviceToHost));
+#undef NB_TRY
+  cleanup();
+  return 0;
+}
+
 static int device_neighbors(exx_plan_s* pl) {
   HostPlan& hp = pl->hp;
+  if (hp.periodic) return device_neighbors_periodic(pl);
   double* dpos = nullptr;
   int *dsys = nullptr, *doff = nullptr, *dcnt = nullptr, *dptr = nullptr, *dout = nullptr;
   auto cleanup = [&]() {
@@ -412,7 +515,10 @@ static int upload_plan(exx_plan_s* pl) {
   UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
   UP(gq); UP(gx); UP(en_sys); UP(en_pbeg); UP(en_pend);
+  UP(pimg); UP(col2img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2c_off); UP(t2c); UP(c1ent);
+  UP(pg_beg); UP(pg_mid); UP(pg_end); UP(pg_ent);
 #undef UP
+  d.periodic = hp.periodic ? 1 : 0;
   if ((rc = upload(pl, pl->g_tiles_all, hp.g_tiles))) return rc;
   if ((rc = upload(pl, pl->y_tiles_all, hp.y_tiles))) return rc;
   if ((rc = upload(pl, pl->gd_items_all, hp.gd_items))) return rc;
@@ -553,7 +659,8 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_byte
     return fail(rc, err);
   }
   if (pl->host_only) {
-    host_neighbors(pl->hp);
+    if (pl->hp.periodic) host_neighbors_periodic(pl->hp);
+    else host_neighbors(pl->hp);
   } else {
     if (hipGetDevice(&pl->device) != hipSuccess) {
       delete pl;
@@ -566,10 +673,10 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_byte
   }
   if (ws_budget_bytes > (size_t)INT64_MAX) ws_budget_bytes = (size_t)INT64_MAX;
   try {
-    rc = derive_lists(pl->hp, err);
+    rc = pl->hp.periodic ? derive_lists_periodic(pl->hp, err) : derive_lists(pl->hp, err);
     if (rc != 0) {
       delete pl;
-      return fail(EXX_EDEVICE, err);
+      return fail(rc == -5 ? EXX_EUNSUPPORTED : EXX_EDEVICE, err);
     }
     rc = derive_chunks(pl->hp, (int64_t)ws_budget_bytes, err);
   } catch (const std::bad_alloc&) {
@@ -578,7 +685,7 @@ int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_byte
   }
   if (rc != 0) {
     delete pl;
-    return fail(EXX_ENOMEM, err);
+    return fail(rc == -5 ? EXX_EUNSUPPORTED : EXX_ENOMEM, err);
   }
   {
     int amax = 1;
@@ -662,6 +769,19 @@ int exx_pair_layout(exx_plan plan, int32_t* pair_a, int32_t* pair_b, int64_t* c_
   return EXX_OK;
 }
 
+int exx_pair_images(exx_plan plan, int32_t* images) {
+  if (!plan || !images) return fail(EXX_EINVAL, "exx_pair_images: NULL argument");
+  const HostPlan& hp = plan->hp;
+  const size_t n = hp.pair_a.size();
+  for (size_t p = 0; p < n; ++p) {
+    const int code = hp.periodic ? hp.pair_img[p] : IMG0;
+    images[3 * p] = code % IMG_S - IMG_OFF;
+    images[3 * p + 1] = (code / IMG_S) % IMG_S - IMG_OFF;
+    images[3 * p + 2] = code / (IMG_S * IMG_S) - IMG_OFF;
+  }
+  return EXX_OK;
+}
+
 int exx_plan_neighbors(exx_plan plan, int32_t* nbr_ptr, int32_t* nbr_atom) {
   if (!plan || !nbr_ptr) return fail(EXX_EINVAL, "exx_plan_neighbors: NULL argument");
   const HostPlan& hp = plan->hp;
@@ -731,13 +851,13 @@ int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds) {
 static RowD rowd_E(exx_plan plan) {
   DevPlan& d = plan->d;
   return RowD{d.T, d.t_off, d.n_loc, d.E, d.e_off, d.m_loc, d.col2g, d.col2g_off,
-              d.e_items, d.ct_run_ptr, d.ct_klen, d.runs};
+              d.e_items, d.ct_run_ptr, d.ct_klen, d.runs, plan->hp.periodic ? d.col2img : nullptr};
 }
 
 static RowD rowd_GD(exx_plan plan) {
   DevPlan& d = plan->d;
   return RowD{d.H, d.h_off, d.m_loc, d.GD, d.t_off, d.n_loc, d.col1g, d.col1g_off,
-              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs};
+              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs, nullptr};
 }
 
 static const ChunkDev& cur_chunk(exx_plan plan) { return plan->chunks[plan->cur]; }
@@ -854,6 +974,10 @@ static int prepare_mixed(exx_plan pl, int m) {
 }
 
 static void launch_final(exx_plan plan, double* K, hipStream_t st) {
+  if (plan->hp.periodic) {   // X on the pair pattern only
+    launch_pgather(plan, K, st);
+    return;
+  }
   launch_Y(plan, plan->tune[TUNE_Y], st);
   launch_symreduce(plan, K, st);
 }
@@ -960,6 +1084,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
   if (n_chunks(plan) > 1)
     return fail(EXX_EUNSUPPORTED, "build_K_spin: needs an unbounded workspace (the plan is chunked)");
+  if (plan->hp.periodic) return fail(EXX_EUNSUPPORTED, "build_K_spin: not implemented for periodic plans");
   const HostPlan& hp = plan->hp;
   const int64_t ds = hp.d_size;
   {
@@ -1024,6 +1149,7 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_two_kernels: unknown precision");
   if (n_chunks(plan) > 1)
     return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: needs an unbounded workspace (the plan is chunked)");
+  if (plan->hp.periodic) return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: not implemented for periodic plans");
   const int rcw = second_workspace(plan);
   if (rcw != EXX_OK) return rcw;
   const HostPlan& hp = plan->hp;
@@ -1252,6 +1378,7 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
     return fail(EXX_EUNSUPPORTED, "exchange_backward: only the binary64 backward is implemented");
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "exchange_backward: unknown precision");
   if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, "exchange_backward: decay lengths must be positive");
+  if (plan->hp.periodic) return fail(EXX_EUNSUPPORTED, "exchange_backward: not implemented for periodic plans");
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
   DevPlan& d = plan->d;

@@ -129,6 +129,12 @@ struct DevPlan {
   // coalesced 512-byte row instead of a gather over 16 rows of V or D.
   int64_t *vr_off, *dr_off;
   double *Vr, *Dr;
+  // periodic plans (HostPlan): image codes and image-keyed column maps
+  int periodic;
+  int *pimg, *col2img, *atom_of_col, *grp_colimg, *grp_cmap, *t2c, *c1ent;
+  int64_t* t2c_off;
+  int *pg_beg, *pg_mid, *pg_end;
+  PGEnt* pg_ent;
   // binary32 copies for the far pair terms of a mixed build: Vr32 in the layout of Vr; Dr32 at
   // (2 p + o) * 256, [k-step q < 4][lane L] = D_PQ[L % 16][4 (L / 16) + q] (the binary32 MFMA
   // accumulator puts rows 4 (L / 16) + v in lane L, so its D chain runs four k-steps)
@@ -252,6 +258,10 @@ struct RowD {
   const int* run_ptr;
   const int* klen;
   const Run* runs;
+  // periodic plans (E only, else nullptr): the image code of every output column; a D
+  // element between the k-row atom J (at its image m within r_cut of P) and the column's
+  // atom L at image b is used only if n_JL = b - m (everything else is beyond the cutoff)
+  const int* ocolimg;
 };
 
 // Batched GEMM: 64 x 64 output tile per workgroup of four wavefronts (32 x 32
@@ -300,6 +310,7 @@ void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* 
                       hipStream_t st);
 void launch_Y(exx_plan plan, int choice, hipStream_t st);
 void launch_symreduce(exx_plan plan, double* K, hipStream_t st);
+void launch_pgather(exx_plan plan, double* K, hipStream_t st);
 template <typename R, int NSP = 1>
 void launch_H_lists(exx_plan plan, const double* V, const double* D, const HLists& hl, int n, double gscale,
                     int mode, hipStream_t st);

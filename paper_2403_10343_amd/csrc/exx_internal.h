@@ -25,7 +25,18 @@ struct Run { int lcol, grow, len; };           // k-range of the E GEMM
 struct EItem { int P, r0, c0, ct; };           // E tile: rows r0.., cols c0.., column tile ct
 struct Unit { int P, mu0, slot, pad; };        // one wavefront of an H group: atom, aux tile, slot
 struct GTile { int grp, col_beg, ncols, q_beg, q_end, x_beg, x_end, pad; };  // H group x 16 columns
-struct Slot4 { int atom, p0, p1, p2; };      // list entry: atom, pair id with group slots 0..2 (-1: none)
+// V-stage list entry: atom, pair id with group slots 0..2 (-1: none); periodic plans also
+// the entry's lattice image (code) and, in G-part lists, per slot the column of E_X where
+// the slot atom's basis starts
+struct Slot4 { int atom, p0, p1, p2, img, e0, e1, e2; };
+
+// Lattice images n (components in [-8, 8)) as one int: the sum of two codes minus
+// IMG0 is the code of the sum of the images.
+constexpr int IMG_OFF = 8, IMG_S = 16;
+constexpr int img_code(int a, int b, int c) { return (a + IMG_OFF) + (b + IMG_OFF) * IMG_S + (c + IMG_OFF) * IMG_S * IMG_S; }
+constexpr int IMG0 = img_code(0, 0, 0);
+inline int img_add(int x, int y) { return x + y - IMG0; }
+inline int img_neg(int x) { return 2 * IMG0 - x; }
 
 constexpr int E_TILE = 64;           // output tile (rows and columns) of the E = M D GEMM
 constexpr int GROUP_ATOMS = 3;       // atoms per H group (slots)
@@ -74,10 +85,29 @@ struct ChunkHost {
 
 constexpr int EN_PAIRS = 64;         // canonical pairs per energy chunk
 
+struct PGEnt { int P, tcol, hcol, pad; };       // pattern gather: T_P column, H'_P column
+
 struct HostPlan {
   // system description
   int n_atoms = 0, n_sys = 0;
   double r_cut = 0;
+  // periodic systems (one system, lattice vectors as rows); entries of the
+  // neighbour lists carry the image of the neighbour within the cutoff
+  bool periodic = false;
+  double lat[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<int> nbr_img;                         // image code per neighbour entry
+  std::vector<int> pair_img;                        // image code of B per canonical pair (A, B)
+  std::vector<int> pimg;                            // [A * n_atoms + B]: image of B within r_cut of A, or -1
+  std::vector<int> n2_img;                          // image code per N2 entry
+  std::vector<int> col2img;                         // image code per E_P column
+  std::vector<int> atom_of_col;                     // atom of every basis function
+  std::vector<int> grp_colimg;                      // image code per V-stage group column
+  std::vector<int> grp_cmap;                        // [group column * 3 + slot]: H' column of the slot atom, or -1
+  std::vector<int64_t> t2c_off;                     // per canonical pair: T2 column maps ...
+  std::vector<int> t2c;                             // ... E_P column start of every N[Q] entry
+  std::vector<int> c1ent;                           // per T_P column: N[P] entry index * 16 + offset
+  std::vector<int> pg_beg, pg_mid, pg_end;          // per canonical pair: X'_AB terms [beg, mid), X'_BA [mid, end)
+  std::vector<PGEnt> pg_ent;
   std::vector<int> species, nb, na, atom_sys, bo;   // per atom
   std::vector<double> pos;                          // 3 * n_atoms
   std::vector<int> sys_atom_off;                    // n_sys + 1
@@ -149,6 +179,18 @@ void host_neighbors(HostPlan& hp);
 // Everything derived from the neighbour lists: canonical pairs and their
 // storage offsets, N2, maps, workspace layout, all task lists, flop counts.
 int derive_lists(HostPlan& hp, std::string& err);
+
+// Periodic plans: the same lists with image-labelled entries (after the
+// neighbour lists with their images; see exx_plan_periodic.cpp).
+int derive_lists_periodic(HostPlan& hp, std::string& err);
+
+// Host version of the periodic screening (the device builder's arithmetic):
+// nbr_ptr / nbr_atom / nbr_img.
+void host_neighbors_periodic(HostPlan& hp);
+
+// Separation (R_B + image shift) - R_A of an image code, the shift summed as
+// (n0 a0 + n1 a1) + n2 a2 per component.
+void image_shift(const double* lat, int code, double* s);
 
 // Near / far split of the V-stage and T2 lists of hp.mixed[set] at its split
 // distance (after derive_lists and derive_chunks), with the binary32 flop counts.

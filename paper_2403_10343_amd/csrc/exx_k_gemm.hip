@@ -33,10 +33,17 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   const int ka = t % EK, ma = t / EK;
   const int kb = t >> 4, nb0 = (t & 15) * 4;
   int gcn[4];
+  int gat[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};   // periodic: atom and image code of the column
+  const bool per = r.ocolimg != nullptr;
+  const int NAt = d.n_atoms;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int n = it.c0 + nb0 + x;
     gcn[x] = n < ldo ? r.ocolg[r.ocolg_off[P] + n] : -1;
+    if (per && gcn[x] >= 0) {
+      gat[x] = d.atom_of_col[gcn[x]];
+      gim[x] = r.ocolimg[r.ocolg_off[P] + n];
+    }
   }
   const int klen = r.klen[it.ct];
   const Run* runs = r.runs + r.run_ptr[it.ct];
@@ -63,9 +70,18 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
       const bool okb = k2 < klen;
       if (okb) while (k2 >= sb[pz] + runs[ib[pz]].len) { sb[pz] += runs[ib[pz]].len; ++ib[pz]; }
       const int gr = okb ? runs[ib[pz]].grow + (k2 - sb[pz]) : 0;
+      int jrow = 0, mimg = 0;
+      if (per && okb) {
+        jrow = d.atom_of_col[gr];
+        mimg = d.pimg[(size_t)P * NAt + jrow];
+      }
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        const bool okd = okb && gcn[x] >= 0;
+        bool okd = okb && gcn[x] >= 0;
+        if (per && okd) {
+          const int nJL = d.pimg[(size_t)jrow * NAt + gat[x]];
+          okd = nJL >= 0 && nJL + mimg - IMG0 == gim[x];
+        }
 #pragma unroll
         for (int sp = 0; sp < NSP; ++sp) {
           const double z = Dsp[sp][okd ? (size_t)gr * ns + gcn[x] : 0];
@@ -311,6 +327,79 @@ void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* 
     hipLaunchKernelGGL((k_rowD<32, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
   else
     hipLaunchKernelGGL((k_rowD<16, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+}
+
+// ---------------------------------------------------------------------------
+// Periodic plans: the final contraction on the pair pattern.  Per canonical
+// pair (A, B) (B at its image n within r_cut of A) one workgroup of four
+// wavefronts forms X'_AB = sum_P T_P[:, A]^T H'_P[:, (B, a + n)] (P over the
+// atoms with A in N[P] at image a) and likewise X'_BA, each term a chain of
+// 16x16x4 MFMAs over the s_P rows of P; the terms are dealt to the wavefronts
+// in turn and the four partial sums added in a fixed order.  Then, with T2
+// already in K, K_AB = K_AB + (X'_AB + X'_BA^T) / 2 and K_BA = K_AB^T (for
+// A = B, K_AA + (X' + X'^T) / 2 from its upper triangle).
+__global__ __launch_bounds__(256) void k_pgather(double* __restrict__ K, DevPlan d, int n_pairs, int n_padded) {
+  __shared__ double red[4][2][4][64];
+  __shared__ double xs[2][16][17];
+  const int p = xcd_task(n_padded);
+  if (p >= n_pairs) return;
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63, lr = L & 15, lk = L >> 4;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const int bA = d.nb[A], bB = d.nb[B];
+  const int64_t ns = d.sys_n[0];
+  d4 acc[2];
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    const int beg = dir == 0 ? d.pg_beg[p] : d.pg_mid[p], end = dir == 0 ? d.pg_mid[p] : d.pg_end[p];
+    const bool ia = lr < (dir == 0 ? bA : bB), kb = lr < (dir == 0 ? bB : bA);
+    d4 a4 = d4{0, 0, 0, 0};
+    for (int e = beg + wv; e < end; e += 4) {
+      const PGEnt pe = d.pg_ent[e];
+      const int P = pe.P;
+      const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
+      const double* TP = d.T + d.t_off[P] + pe.tcol + lr;   // A[i][r] = T_P[r][tcol + i]
+      const double* HP = d.H + d.h_off[P] + pe.hcol + lr;   // B[r][k] = H'_P[r][hcol + k]
+      for (int r0 = 0; r0 < sP; r0 += 4) {
+        const int r = r0 + lk;
+        const bool ok = r < sP;
+        const double a = TP[(ok && ia) ? (size_t)r * nP : 0];
+        const double b = HP[(ok && kb) ? (size_t)r * mP : 0];
+        a4 = mfma64((ok && ia) ? a : 0.0, (ok && kb) ? b : 0.0, a4);
+      }
+    }
+    acc[dir] = a4;
+  }
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][dir][v][L] = acc[dir][v];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double x = red[0][dir][v][L];
+        for (int w2 = 1; w2 < 4; ++w2) x += red[w2][dir][v][L];
+        xs[dir][lk + 4 * v][lr] = x;
+      }
+  }
+  __syncthreads();
+  const int i = threadIdx.x >> 4, k = threadIdx.x & 15;
+  if (i < bA && k < bB && (A != B || i <= k)) {
+    double* Kp = K + d.sys_d_off[0];
+    const size_t ab = (size_t)(d.bo[A] + i) * ns + d.bo[B] + k;
+    const double x = 0.5 * (xs[0][i][k] + (A == B ? xs[0][k][i] : xs[1][k][i]));
+    const double val = Kp[ab] + x;
+    Kp[ab] = val;
+    if (A != B || i != k) Kp[(size_t)(d.bo[B] + k) * ns + d.bo[A] + i] = val;
+  }
+}
+
+void launch_pgather(exx_plan plan, double* K, hipStream_t st) {
+  const int n = (int)plan->hp.pair_a.size(), np_ = (n + 7) / 8 * 8;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pgather, dim3(np_), dim3(256), 0, st, K, plan->d, n, np_);
 }
 
 void launch_Y(exx_plan plan, int choice, hipStream_t st) {

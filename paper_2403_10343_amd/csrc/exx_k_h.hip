@@ -175,7 +175,12 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       const int ei = t / H_COLS, c = t % H_COLS;
       const Slot4 qe = hl.gq[e0 + ei];
       const int Q = qe.atom;
-      qm_lc[ei][c] = (c < ncols) ? d.map1[d.map_off[Q] + gcol[c]] : -1;
+      int lc = (c < ncols) ? d.map1[d.map_off[Q] + gcol[c]] : -1;
+      // periodic: the column's atom L at image b lies in N[Q + q] only if n_QL = b - q
+      if (d.periodic && lc >= 0 &&
+          d.pimg[(size_t)Q * d.n_atoms + d.atom_of_col[gcol[c]]] + qe.img - IMG0 != d.grp_colimg[tl.col_beg + c])
+        lc = -1;
+      qm_lc[ei][c] = lc;
       if (c == 0) {
         qm_atom[ei] = Q;
         qm_n[ei] = d.n_loc[Q];
@@ -211,15 +216,17 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
     const int X = xe.atom;
     const int aX = d.na[X], bX = d.nb[X], mX = d.m_loc[X], boX = d.bo[X];
     const int pp[3] = {xe.p0, xe.p1, xe.p2};
+    const int ecol[3] = {xe.e0, xe.e1, xe.e2};   // periodic: E_X column of each slot atom's basis
     const double* EXs[NSP];
 #pragma unroll
     for (int sp = 0; sp < NSP; ++sp) EXs[sp] = (sp == 0 ? d.E : hl.E1) + d.e_off[X];
-    const int* m2X = d.map2 + d.map_off[X];
+    const int* m2X = d.periodic ? nullptr : d.map2 + d.map_off[X];
 #pragma unroll
     for (int cc = 0; cc < H_CPW; ++cc) {
       const int c = c0 + cc;
       const int ic = (c < ncols) ? gcol[c] - boX : -1;
-      if (ic >= 0 && ic < bX) {
+      // periodic: the column must be on X at the image of this entry
+      if (ic >= 0 && ic < bX && (!d.periodic || d.grp_colimg[tl.col_beg + c] == xe.img)) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (u < nU) {
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
               const int P = un.P[u], aP = un.a[u], bP = un.b[u];
               const int muB = un.mu0[u] + lr;
               const bool muv = muB < aP;
-              const int colx = lr < bP ? m2X[un.bo[u] + lr] : 0;
+              const int colx = lr < bP ? (d.periodic ? ecol[un.slot[u]] + lr : m2X[un.bo[u] + lr]) : 0;
               const size_t xo = colx + (size_t)ic * mX;
               const int nsx = (aX + 3) / 4;
               // V_PX[muB][m2] from the lane-ordered copy (zero outside the block)
@@ -257,14 +264,16 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
     if (u < nU) {
       const int P = un.P[u], aP = un.a[u], bP = un.b[u], mP = d.m_loc[P];
       const int muB = un.mu0[u] + lr;
-      const int* m2P = d.map2 + d.map_off[P];
+      const int* m2P = d.periodic ? nullptr : d.map2 + d.map_off[P];
 #pragma unroll
       for (int sp = 0; sp < NSP; ++sp) {
         double* HP = (sp == 0 ? d.H : hl.H1) + d.h_off[P];
 #pragma unroll
         for (int cc = 0; cc < H_CPW; ++cc) {
           const int c = c0 + cc;
-          const int col = (c < ncols) ? m2P[gcol[c]] : -1;
+          const int col = (c < ncols) ? (d.periodic ? d.grp_cmap[(size_t)(tl.col_beg + c) * 3 + un.slot[u]]
+                                                    : m2P[gcol[c]])
+                                      : -1;
           if (col >= 0 && muB < aP) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   const int64_t ns = d.sys_n[s];
   const double* Vp = V + d.v_off[p];
   const int* cg = d.col1g + d.col1g_off[Q];
-  const int* m2P = d.map2 + d.map_off[P];
+  const int* m2P = d.periodic ? nullptr : d.map2 + d.map_off[P];
   const double* TQ = d.T + d.t_off[Q];
   const double* EPs[NSP];
 #pragma unroll
@@ -70,7 +70,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   auto fetch = [&](int l0) {
     const int l = l0 + tc;
     const bool cv = l < nQ;
-    const int ce = cv ? m2P[cg[l]] : 0;
+    int ce = 0;
+    if (cv) {
+      if (d.periodic) {   // the E_P column of T_Q's column l (its N[Q] entry at Q's image)
+        const int en = d.c1ent[d.col1g_off[Q] + l];
+        ce = d.t2c[d.t2c_off[p] + (en >> 4)] + (en & 15);
+      } else {
+        ce = m2P[cg[l]];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       const int r = r0 + RSTEP * i;

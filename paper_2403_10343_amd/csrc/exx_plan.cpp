@@ -19,10 +19,6 @@ int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_
                     const double* positions, const int32_t* n_basis, const int32_t* n_aux,
                     double r_cut, int32_t n_systems, const int32_t* sys_atom_off,
                     const double* lattice, HostPlan& hp, std::string& err) {
-  if (lattice) {
-    err = "exx_system: periodic systems (a lattice) are not implemented";
-    return -5;
-  }
   if (n_atoms <= 0 || n_species <= 0 || !species || !positions || !n_basis || !n_aux) {
     err = "exx_system: null array or non-positive count";
     return -1;
@@ -80,6 +76,36 @@ int describe_system(const int32_t n_atoms, const int32_t n_species, const int32_
     hp.n_basis_max = std::max(hp.n_basis_max, off);
   }
   hp.d_size = hp.sys_d_off[n_systems];
+  hp.periodic = lattice != nullptr;
+  if (hp.periodic) {
+    if (n_systems != 1) { err = "exx_system: a periodic plan holds one system"; return -5; }
+    for (int i = 0; i < 9; ++i) {
+      if (!std::isfinite(lattice[i])) { err = "exx_system: non-finite lattice vector"; return -1; }
+      hp.lat[i] = lattice[i];
+    }
+    // the cutoff must be below half the distance between opposite cell faces, so that an
+    // atom pair has at most one image within it
+    const double* a = hp.lat;
+    const double vol = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                                 a[2] * (a[3] * a[7] - a[4] * a[6]));
+    double hw = 1e300;
+    for (int i = 0; i < 3; ++i) {
+      const double* u = a + 3 * ((i + 1) % 3);
+      const double* v = a + 3 * ((i + 2) % 3);
+      const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+      hw = std::min(hw, 0.5 * vol / std::sqrt(cx * cx + cy * cy + cz * cz));
+    }
+    if (!(vol > 0) || !(r_cut < hw)) {
+      err = "exx_system: r_cut must be below half the cell width (" + std::to_string(hw) + " A)";
+      return -1;
+    }
+    // image components of N2 entries stay within [-8, 8) when the positions lie within two
+    // cell widths of the home cell
+    if (hp.n_atoms > 0 && hp.n_atoms * (int64_t)hp.n_atoms > (int64_t)1 << 31) {
+      err = "exx_system: periodic plans hold at most 46340 atoms";
+      return -5;
+    }
+  }
   return 0;
 }
 
@@ -567,7 +593,13 @@ void derive_mixed_lists(HostPlan& hp, int set) {
   std::vector<char> far(npairs, 0);
   for (int64_t p = 0; p < npairs; ++p) {
     const double* pa = &hp.pos[3 * (size_t)hp.pair_a[p]];
-    const double* pb = &hp.pos[3 * (size_t)hp.pair_b[p]];
+    double pb[3] = {hp.pos[3 * (size_t)hp.pair_b[p]], hp.pos[3 * (size_t)hp.pair_b[p] + 1],
+                    hp.pos[3 * (size_t)hp.pair_b[p] + 2]};
+    if (hp.periodic) {
+      double sh[3];
+      image_shift(hp.lat, hp.pair_img[p], sh);
+      for (int c = 0; c < 3; ++c) pb[c] += sh[c];
+    }
     volatile double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
     volatile double xx = dx * dx, yy = dy * dy, zz = dz * dz;
     volatile double r2 = (xx + yy);
@@ -716,6 +748,11 @@ int derive_chunks(HostPlan& hp, int64_t budget, std::string& err) {
   hp.inter_stored = stored;
   hp.ws_total = 2 * hp.e_total + hp.y_total;
   if (budget <= 0 || stored <= budget) return 0;
+  if (hp.periodic) {
+    err = "exx_plan_create: a periodic plan needs room for all its intermediates (" + std::to_string(stored) +
+          " bytes); chunked builds are not implemented for it";
+    return -5;
+  }
   const auto& np = hp.nbr_ptr;
   const auto& nat = hp.nbr_atom;
   auto esz = [&](int a) { return hp.e_off[a + 1] - hp.e_off[a]; };

@@ -1,0 +1,138 @@
+"""Periodic systems (lattice images, the pattern-folded X of the real-space
+exchange) on the GPU against the periodic oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import exx_oracle as O
+from tests.gpu_util import device_inputs, relmax, run_build
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def exx():
+    import paper_2403_10343_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _tiny(seed, species=(0, 1, 1, 0, 1)):
+    lat = np.array([[3.0, 0.0, 0.0], [0.4, 3.2, 0.0], [0.2, -0.3, 3.4]])
+    pos = np.array([[0.2, 0.3, 0.1], [2.6, 0.5, 0.4], [1.3, 2.9, 3.0], [1.5, 1.6, 1.7], [0.5, 2.8, 3.2]])
+    return synth.System(np.array(species), pos, 1.45, seed, lattice=lat)
+
+
+def _check_full(exx, sysm, tol=TOL):
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    assert np.array_equal(plan.pair_images(), inp.layout.pair_img)
+    K, Ex = run_build(plan, inp, torch)
+    n = int(inp.layout.sys_nbas[0])
+    Kg = K.reshape(n, n)
+    Xo = O.x_periodic(inp)
+    Eo = O.periodic_energy(Xo, inp.D.reshape(n, n))
+    print(f"{sysm.name}: rel {relmax(Kg, Xo):.2e}, E {Ex[0]:.10e} vs {Eo:.10e}", flush=True)
+    assert relmax(Kg, Xo) < tol
+    assert abs(Ex[0] - Eo) < tol * abs(Eo)
+    assert np.array_equal(Kg, Kg.T)
+    return plan, inp, K, Ex
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tiny_skewed_cell_matches_oracle(exx, seed):
+    """A skewed cell with water species whose atoms pair with images across
+    faces, edges and corners: the whole folded X and E_x."""
+    _check_full(exx, _tiny(seed))
+
+
+def test_one_cell_ice_matches_oracle(exx):
+    """One diamond-like cell of 8 waters, r_cut 3.4 A (below half the 7.16 A
+    edge): the whole folded X and E_x."""
+    _check_full(exx, synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4))
+
+
+def test_vacuum_box_equals_cluster(exx):
+    """A cluster in a cell far wider than its reach: the periodic build gives
+    the cluster build's K on the pair pattern and the same E_x."""
+    cl = synth.water_cluster(8, seed=6)
+    vb = synth.System(cl.species, cl.pos, cl.r_cut, cl.seed, lattice=np.diag([60.0, 61.0, 62.0]), name="vacuum")
+    ic, iv = synth.make_inputs(cl), synth.make_inputs(vb)
+    Kc, Ec = run_build(exx.Plan.for_system(cl), ic, torch)
+    Kv, Ev = run_build(exx.Plan.for_system(vb), iv, torch)
+    n = int(ic.layout.sys_nbas[0])
+    blk = O.Blocks(ic)
+    mask = np.zeros((blk.nat, blk.nat), bool)
+    mask[blk.pa, blk.pb] = mask[blk.pb, blk.pa] = True
+    atom = np.repeat(np.arange(blk.nat), blk.nb)
+    M = mask[atom][:, atom]
+    assert relmax(Kv.reshape(n, n), np.where(M, Kc.reshape(n, n), 0.0)) < 1e-12
+    assert np.all(Kv.reshape(n, n)[~M] == 0.0)
+    assert abs(Ev[0] - Ec[0]) < 1e-12 * abs(Ec[0])
+
+
+def test_supercell_is_extensive(exx):
+    """E_x per cell of a 2x1x1 and a 1x2x1 supercell is twice the cell's."""
+    cell = synth.ice_box_periodic(1, 1, 1, seed=7, r_cut=3.4)
+    _, Ec = run_build(exx.Plan.for_system(cell), synth.make_inputs(cell), torch)
+    for mult in ([2, 1, 1], [1, 2, 1]):
+        sup = synth.supercell(cell, mult)
+        _, Es = run_build(exx.Plan.for_system(sup), synth.make_inputs(sup), torch)
+        assert abs(Es[0] - 2 * Ec[0]) < 1e-12 * abs(Ec[0]), (mult, Es[0], 2 * Ec[0])
+
+
+def test_2x2x2_box_sampled_rows_and_mixed(exx):
+    """64 waters, r_cut 6 A: rows of an O and an H atom against the oracle;
+    the mixed build (default split) within the mixed bar of the FP64 build;
+    the FP64 build bitwise run to run; graph replays equal the eager build."""
+    sysm = synth.ice_box_periodic(2, 2, 2, seed=8, r_cut=6.0)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    K, Ex = run_build(plan, inp, torch)
+    K2, Ex2 = run_build(plan, inp, torch)
+    assert np.array_equal(K, K2) and np.array_equal(Ex, Ex2)
+    n = int(inp.layout.sys_nbas[0])
+    Kg = K.reshape(n, n)
+    pb = O.PBlocks(inp)
+    for a in (30, 31):
+        rows = np.arange(pb.bo[a], pb.bo[a + 1])
+        Xr = O.x_atom_rows_periodic(inp, [a], pb)
+        print(f"atom {a}: rel {np.abs(Kg[rows] - Xr).max() / np.abs(Xr).max():.2e}", flush=True)
+        assert np.abs(Kg[rows] - Xr).max() < TOL * np.abs(Xr).max()
+    Km, Em = run_build(plan, inp, torch, exx.PREC_MIXED)
+    dK, dE = np.abs(Km - K).max(), abs(Em[0] - Ex[0]) / sysm.n_atoms
+    print(f"mixed: max|dK| {dK:.2e}, |dE|/atom {dE:.2e}", flush=True)
+    assert dK <= 1e-5 and dE <= 1e-6
+    C, V, D = device_inputs(inp, torch)
+    Kd = torch.empty_like(D)
+    Ed = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.Stream()
+    plan.graph_build(C, V, D, Kd, Ed, stream=s.cuda_stream)
+    for _ in range(2):
+        Kd.fill_(3.0)
+        torch.cuda.synchronize()
+        plan.graph_launch(stream=s.cuda_stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(Kd.cpu().numpy(), K) and Ed.item() == Ex[0]
+
+
+def test_periodic_unsupported_calls(exx):
+    sysm = synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    C, V, D = device_inputs(inp, torch)
+    with pytest.raises(exx.ExxError) as e:
+        plan.exchange_backward(C, V, D, 1.0, dC=torch.empty_like(C))
+    assert e.value.code == -5
+    with pytest.raises(exx.ExxError) as e:
+        plan.build_K_spin(C, V, torch.cat([D, D]), torch.empty(2 * D.numel(), dtype=torch.float64, device="cuda:0"))
+    assert e.value.code == -5
+    with pytest.raises(exx.ExxError) as e:
+        exx.Plan.for_system(sysm, ws_budget_bytes=1 << 20)
+    assert e.value.code == -5
+    with pytest.raises(exx.ExxError) as e:   # cutoff not below half the cell width
+        exx.Plan(sysm.species, sysm.pos, sysm.basis_table, sysm.aux_table, 3.7, lattice=sysm.lattice)
+    assert e.value.code == -1
