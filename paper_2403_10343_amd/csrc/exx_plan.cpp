@@ -660,7 +660,8 @@ void derive_mixed_lists(HostPlan& hp, int set) {
         // always runs all four D steps) or the G chain
         const int per = pass == 0 ? ((hp.na[q] + 3) / 4) + ((hp.nb[q] + 3) / 4) : (hp.na[q] + 3) / 4;
         const int per32 = pass == 0 ? ((hp.na[q] + 3) / 4) + 4 : per;
-        Slot4 n4{q, -1, -1, -1}, f4{q, -1, -1, -1};
+        Slot4 n4 = x, f4 = x;   // keeps the entry's image and E columns (periodic plans)
+        n4.p0 = n4.p1 = n4.p2 = f4.p0 = f4.p1 = f4.p2 = -1;
         const int* sl = &x.p0;
         int* sn = &n4.p0;
         int* sf = &f4.p0;
