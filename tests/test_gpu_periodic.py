@@ -136,3 +136,46 @@ def test_periodic_unsupported_calls(exx):
     with pytest.raises(exx.ExxError) as e:   # cutoff not below half the cell width
         exx.Plan(sysm.species, sysm.pos, sysm.basis_table, sysm.aux_table, 3.7, lattice=sysm.lattice)
     assert e.value.code == -1
+
+
+def test_config5_full_size(exx):
+    """The periodic 3072-atom ice box (1024 waters, r_cut 8 A), in the launch
+    configuration the benchmark times: the FP64 build is exactly symmetric and
+    bitwise reproducible, matches the oracle on the rows of one H atom, and the
+    mixed build stays within the mixed bar of it."""
+    import time
+    t0 = time.time()
+    sysm = synth.config(5)
+    inp = synth.make_inputs(sysm)
+    print(f"config 5 inputs: {time.time() - t0:.1f} s, {inp.layout.n_pairs} pairs", flush=True)
+    plan = exx.Plan.for_system(sysm)
+    print(f"plan: {time.time() - t0:.1f} s, {plan.info['flops_fp64'] / 1e12:.2f} TFLOP per build, "
+          f"workspace {plan.info['workspace_bytes'] / 1e9:.1f} GB", flush=True)
+    assert np.array_equal(plan.pair_images(), inp.layout.pair_img)
+    C, V, D = device_inputs(inp, torch)
+    K = torch.empty_like(D)
+    Ex = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    plan.autotune(C, V, D, K)
+    plan.build_K(C, V, D, K, Ex)
+    torch.cuda.synchronize()
+    K1, E1 = K.clone(), Ex.item()
+    plan.build_K(C, V, D, K, Ex)
+    torch.cuda.synchronize()
+    assert torch.equal(K, K1) and Ex.item() == E1
+    n = int(inp.layout.sys_nbas[0])
+    Km = K1.view(n, n)
+    assert torch.equal(Km, Km.T)
+    print(f"builds: {time.time() - t0:.1f} s, E_x per atom {E1 / sysm.n_atoms:.6f}", flush=True)
+    pb = O.PBlocks(inp)
+    rows = np.arange(pb.bo[1], pb.bo[2])
+    Xr = O.x_atom_rows_periodic(inp, [1], pb)
+    Kr = Km[torch.as_tensor(rows, device="cuda:0")].cpu().numpy()
+    rel = np.abs(Kr - Xr).max() / np.abs(Xr).max()
+    print(f"oracle rows of atom 1: rel {rel:.2e} ({time.time() - t0:.1f} s)", flush=True)
+    assert rel < TOL
+    plan.build_K(C, V, D, K, Ex, precision=exx.PREC_MIXED)
+    torch.cuda.synchronize()
+    dK = (K - K1).abs().max().item()
+    dE = abs(Ex.item() - E1) / sysm.n_atoms
+    print(f"mixed: max|dK| {dK:.2e}, |dE|/atom {dE:.2e}", flush=True)
+    assert dK <= 1e-5 and dE <= 1e-6
