@@ -515,7 +515,7 @@ static int upload_plan(exx_plan_s* pl) {
   UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
   UP(gq); UP(gx); UP(en_sys); UP(en_pbeg); UP(en_pend);
-  UP(pimg); UP(col2img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2c_off); UP(t2c); UP(c1ent);
+  UP(pimg); UP(col2img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2col_off); UP(t2col);
   UP(pg_beg); UP(pg_mid); UP(pg_end); UP(pg_ent);
 #undef UP
   d.periodic = hp.periodic ? 1 : 0;

@@ -111,6 +111,8 @@ struct DevPlan {
   GTile* g_tiles;
   Slot4 *gq, *gx;
   int* t2_items;
+  int* t2col;           // E_P column of every T_Q column of a T2 pair (HostPlan::t2col)
+  int64_t* t2col_off;
   int* dv_items;
   FItem* f_items;
   int* f_plist;
@@ -131,8 +133,7 @@ struct DevPlan {
   double *Vr, *Dr;
   // periodic plans (HostPlan): image codes and image-keyed column maps
   int periodic;
-  int *pimg, *col2img, *atom_of_col, *grp_colimg, *grp_cmap, *t2c, *c1ent;
-  int64_t* t2c_off;
+  int *pimg, *col2img, *atom_of_col, *grp_colimg, *grp_cmap;
   int *pg_beg, *pg_mid, *pg_end;
   PGEnt* pg_ent;
   // binary32 copies for the far pair terms of a mixed build: Vr32 in the layout of Vr; Dr32 at

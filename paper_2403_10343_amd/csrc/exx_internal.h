@@ -103,9 +103,6 @@ struct HostPlan {
   std::vector<int> atom_of_col;                     // atom of every basis function
   std::vector<int> grp_colimg;                      // image code per V-stage group column
   std::vector<int> grp_cmap;                        // [group column * 3 + slot]: H' column of the slot atom, or -1
-  std::vector<int64_t> t2c_off;                     // per canonical pair: T2 column maps ...
-  std::vector<int> t2c;                             // ... E_P column start of every N[Q] entry
-  std::vector<int> c1ent;                           // per T_P column: N[P] entry index * 16 + offset
   std::vector<int> pg_beg, pg_mid, pg_end;          // per canonical pair: X'_AB terms [beg, mid), X'_BA [mid, end)
   std::vector<PGEnt> pg_ent;
   std::vector<int> species, nb, na, atom_sys, bo;   // per atom
@@ -142,6 +139,10 @@ struct HostPlan {
   std::vector<Slot4> gq, gx;
   int h_waves = 1;
   std::vector<int> t2_items;                        // 2 * canonical pair id + orientation bit
+  // per canonical pair (in the orientation of its T2 item: rows P, columns Q), the E_P
+  // column of every column of T_Q (columns N[Q]) at t2col[t2col_off[p] + l]
+  std::vector<int64_t> t2col_off;
+  std::vector<int> t2col;
   std::vector<int> dv_items;                        // canonical pair ids sorted by dV shape class
   std::vector<DVClass> dv_classes;
   std::vector<T2Class> t2_classes;

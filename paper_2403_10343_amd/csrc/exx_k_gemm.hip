@@ -8,7 +8,8 @@ using namespace exx;
 
 // EK: k-chunk per LDS stage (a tuning choice: 16 or 32).  NSP = 2 (collinear spin): the
 // products with D (into r.O) and D1 (into O1) in one pass, the A_P tile staged once.
-template <int EK, int NSP>
+// PER: periodic plans (image check on every D element, see RowD::ocolimg)
+template <int EK, int NSP, bool PER>
 __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
                                               int n_padded, const double* __restrict__ D1, double* __restrict__ O1) {
   __shared__ double As[2][EK][EPITCH];
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   const int kb = t >> 4, nb0 = (t & 15) * 4;
   int gcn[4];
   int gat[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};   // periodic: atom and image code of the column
-  const bool per = r.ocolimg != nullptr;
+  constexpr bool per = PER;
   const int NAt = d.n_atoms;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
@@ -312,21 +313,25 @@ __global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPl
 void launch_rowD(exx_plan plan, const double* D, const RowD& r, int n, hipStream_t st) {
   if (n <= 0) return;
   const int nwgp = (n + 7) / 8 * 8;
-  if (plan->tune[TUNE_E] == 1)
-    hipLaunchKernelGGL((k_rowD<32, 1>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((k_rowD<16, 1>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+  const bool per = r.ocolimg != nullptr;
+  if (plan->tune[TUNE_E] == 1) {
+    if (per) hipLaunchKernelGGL((k_rowD<32, 1, true>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+    else hipLaunchKernelGGL((k_rowD<32, 1, false>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+  } else {
+    if (per) hipLaunchKernelGGL((k_rowD<16, 1, true>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+    else hipLaunchKernelGGL((k_rowD<16, 1, false>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, nullptr, nullptr);
+  }
 }
 
-// the two products of a collinear-spin build: r.O = A D, O1 = A D1
+// the two products of a collinear-spin build (clusters): r.O = A D, O1 = A D1
 void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* O1, const RowD& r, int n,
-                             hipStream_t st) {
+                      hipStream_t st) {
   if (n <= 0) return;
   const int nwgp = (n + 7) / 8 * 8;
   if (plan->tune[TUNE_E] == 1)
-    hipLaunchKernelGGL((k_rowD<32, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+    hipLaunchKernelGGL((k_rowD<32, 2, false>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
   else
-    hipLaunchKernelGGL((k_rowD<16, 2>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+    hipLaunchKernelGGL((k_rowD<16, 2, false>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,7 +342,8 @@ void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* 
 // 16x16x4 MFMAs over the s_P rows of P; the terms are dealt to the wavefronts
 // in turn and the four partial sums added in a fixed order.  Then, with T2
 // already in K, K_AB = K_AB + (X'_AB + X'_BA^T) / 2 and K_BA = K_AB^T (for
-// A = B, K_AA + (X' + X'^T) / 2 from its upper triangle).
+// A = B, K_AA + (X' + X'^T) / 2 from its upper triangle).  Each term runs as four
+// independent MFMA chains (interleaved k-steps) added in a fixed order.
 __global__ __launch_bounds__(256) void k_pgather(double* __restrict__ K, DevPlan d, int n_pairs, int n_padded) {
   __shared__ double red[4][2][4][64];
   __shared__ double xs[2][16][17];
@@ -359,13 +365,23 @@ __global__ __launch_bounds__(256) void k_pgather(double* __restrict__ K, DevPlan
       const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
       const double* TP = d.T + d.t_off[P] + pe.tcol + lr;   // A[i][r] = T_P[r][tcol + i]
       const double* HP = d.H + d.h_off[P] + pe.hcol + lr;   // B[r][k] = H'_P[r][hcol + k]
-      for (int r0 = 0; r0 < sP; r0 += 4) {
-        const int r = r0 + lk;
-        const bool ok = r < sP;
-        const double a = TP[(ok && ia) ? (size_t)r * nP : 0];
-        const double b = HP[(ok && kb) ? (size_t)r * mP : 0];
-        a4 = mfma64((ok && ia) ? a : 0.0, (ok && kb) ? b : 0.0, a4);
+      // four independent chains over k-steps r0 + 4 u (loads of a round issued together)
+      d4 c4[4] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}, d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+      for (int r0 = 0; r0 < sP; r0 += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + 4 * u + lk;
+          const bool ok = r < sP;
+          const double x = TP[(ok && ia) ? (size_t)r * nP : 0];
+          const double y = HP[(ok && kb) ? (size_t)r * mP : 0];
+          a[u] = (ok && ia) ? x : 0.0;
+          b[u] = (ok && kb) ? y : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c4[u] = mfma64(a[u], b[u], c4[u]);
       }
+      a4 += (c4[0] + c4[1]) + (c4[2] + c4[3]);
     }
     acc[dir] = a4;
   }

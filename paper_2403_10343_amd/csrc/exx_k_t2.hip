@@ -38,8 +38,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   const int s = d.atom_sys[P];
   const int64_t ns = d.sys_n[s];
   const double* Vp = V + d.v_off[p];
-  const int* cg = d.col1g + d.col1g_off[Q];
-  const int* m2P = d.periodic ? nullptr : d.map2 + d.map_off[P];
+  const int* t2c = d.t2col + d.t2col_off[p];   // E_P column of every column of T_Q
   const double* TQ = d.T + d.t_off[Q];
   const double* EPs[NSP];
 #pragma unroll
@@ -70,15 +69,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   auto fetch = [&](int l0) {
     const int l = l0 + tc;
     const bool cv = l < nQ;
-    int ce = 0;
-    if (cv) {
-      if (d.periodic) {   // the E_P column of T_Q's column l (its N[Q] entry at Q's image)
-        const int en = d.c1ent[d.col1g_off[Q] + l];
-        ce = d.t2c[d.t2c_off[p] + (en >> 4)] + (en & 15);
-      } else {
-        ce = m2P[cg[l]];
-      }
-    }
+    const int ce = cv ? t2c[l] : 0;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       const int r = r0 + RSTEP * i;

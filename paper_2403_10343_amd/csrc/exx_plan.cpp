@@ -459,6 +459,15 @@ int derive_lists(HostPlan& hp, std::string& err) {
     hp.flops[3] += 2LL * hp.na[a] * hp.na[b] * hp.nb[b] * hp.n_loc[b] + 2LL * hp.na[a] * hp.nb[a] * hp.nb[b] * hp.n_loc[b];
     hp.issued[3] += 2048LL * cost(a, b);
   }
+  hp.t2col_off.assign(npairs + 1, 0);
+  hp.t2col.clear();
+  for (int64_t p = 0; p < npairs; ++p) {
+    const int item = hp.t2_items[p];
+    const int a = (item & 1) ? hp.pair_b[p] : hp.pair_a[p], b = (item & 1) ? hp.pair_a[p] : hp.pair_b[p];
+    for (int l = 0; l < hp.n_loc[b]; ++l)
+      hp.t2col.push_back(hp.map2[hp.map_off[a] + hp.col1g[hp.col1g_off[b] + l]]);
+    hp.t2col_off[p + 1] = (int64_t)hp.t2col.size();
+  }
   // shape classes: aux tiles of 16 of the row atom, nu steps of 4 (rounded up
   // to a compiled size) of the column atom; stable sort keeps pair order inside
   {

@@ -176,7 +176,6 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
     hp.col2g_off[a + 1] = hp.col2g_off[a] + hp.m_loc[a];
   }
   hp.col1g.assign(hp.col1g_off[NA], 0);
-  hp.c1ent.assign(hp.col1g_off[NA], 0);
   hp.col2g.assign(hp.col2g_off[NA], 0);
   hp.col2img.assign(hp.col2g_off[NA], 0);
   hp.atom_of_col.assign(hp.sys_n[0], 0);
@@ -189,7 +188,6 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
       for (int x = 0; x < hp.nb[j]; ++x, ++c) {
         hp.map1[hp.map_off[a] + hp.bo[j] + x] = c;
         hp.col1g[hp.col1g_off[a] + c] = hp.bo[j] + x;
-        hp.c1ent[hp.col1g_off[a] + c] = (k - np[a]) * 16 + x;
       }
     }
     c = 0;
@@ -433,10 +431,11 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
     }
   }
   // ---- T2 pairs: every canonical pair, oriented by cost as for clusters; per pair the E_P
-  // column start of each N[Q] entry (L, q + n_QL), q the image of Q within r_cut of P
+  // column of each column of T_Q: entry (L, n_QL) of N[Q] meets E_P at (L, q + n_QL), q the
+  // image of Q within r_cut of P
   hp.t2_items.resize(npairs);
-  hp.t2c_off.assign(npairs + 1, 0);
-  hp.t2c.clear();
+  hp.t2col_off.assign(npairs + 1, 0);
+  hp.t2col.clear();
   for (int64_t p = 0; p < npairs; ++p) {
     int a = hp.pair_a[p], b = hp.pair_b[p];
     auto cost = [&](int x, int y) {
@@ -451,9 +450,9 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
     for (int k = np[b]; k < np[b + 1]; ++k) {
       const int c = n2col(a, nat[k], img_add(q, nim[k]));
       if (c < 0) { err = "periodic T2 column outside N2"; return -3; }
-      hp.t2c.push_back(c);
+      for (int x = 0; x < hp.nb[nat[k]]; ++x) hp.t2col.push_back(c + x);
     }
-    hp.t2c_off[p + 1] = (int64_t)hp.t2c.size();
+    hp.t2col_off[p + 1] = (int64_t)hp.t2col.size();
   }
   {
     auto ns_class = [](int ns) { return ns <= 4 ? 4 : ns <= 8 ? 8 : ns <= 10 ? 10 : ns <= 12 ? 12 : 16; };

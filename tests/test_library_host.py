@@ -114,11 +114,31 @@ def test_tuning_choices_validated_on_host_plan():
         p.set_tuning([2, 0, 0])
 
 
-def test_lattice_is_rejected_as_unsupported():
+def test_periodic_host_plan_layout_matches_generator():
+    """Periodic host plans: canonical pairs, their lattice images and block
+    offsets equal the generator's and the oracle's screening; a cutoff not below
+    half the cell width is EXX_EINVAL; a budget that would chunk a periodic plan
+    is EXX_EUNSUPPORTED."""
     from paper_2403_10343_amd import ExxError, Plan
-    sysm = synth.config(1)
+    lat = np.array([[3.0, 0.0, 0.0], [0.4, 3.2, 0.0], [0.2, -0.3, 3.4]])
+    pos = np.array([[0.2, 0.3, 0.1], [2.6, 0.5, 0.4], [1.3, 2.9, 3.0], [1.5, 1.6, 1.7], [0.5, 2.8, 3.2]])
+    tiny = synth.System(np.array([0, 1, 1, 0, 1]), pos, 1.45, 3, lattice=lat)
+    for sysm in (tiny, synth.ice_box_periodic(2, 2, 2, seed=0, r_cut=6.0)):
+        p = Plan.for_system(sysm, host_only=True)
+        lay = synth.make_layout(sysm)
+        pa, pb, co, vo = p.pairs()
+        assert np.array_equal(pa, lay.pair_a) and np.array_equal(pb, lay.pair_b)
+        assert np.array_equal(p.pair_images(), lay.pair_img)
+        assert np.array_equal(co, lay.c_off) and np.array_equal(vo, lay.v_off)
+        mine = [(int(a), int(b), tuple(int(x) for x in n)) for a, b, n in zip(pa, pb, p.pair_images())]
+        assert mine == O.periodic_pairs(sysm.pos, sysm.lattice, sysm.r_cut)
+    assert (np.abs(Plan.for_system(tiny, host_only=True).pair_images()).sum(1) > 1).any()
     with pytest.raises(ExxError) as e:
-        Plan(sysm.species, sysm.pos, synth.N_BASIS, synth.N_AUX, 6.0, host_only=True, lattice=np.eye(3) * 30.0)
+        Plan(tiny.species, tiny.pos, synth.N_BASIS, synth.N_AUX, 1.6, host_only=True, lattice=lat)
+    assert e.value.code == -1
+    big = synth.ice_box_periodic(2, 2, 2, seed=0, r_cut=6.0)
+    with pytest.raises(ExxError) as e:
+        Plan.for_system(big, host_only=True, ws_budget_bytes=1 << 20)
     assert e.value.code == -5
 
 

@@ -35,7 +35,8 @@ MUTATIONS = {
                                "VPQ = vb if P <= Q else vb                     # [mu on P, nu on Q]"),
     "periodic_flip_image_sign": ("return [((J, m), blk[:self.na[J]].transpose(0, 2, 1)), ((I, (0, 0, 0)), blk[self.na[J]:].transpose(0, 2, 1))]",
                                  "return [((J, m), blk[self.na[J]:].transpose(0, 2, 1)), ((I, (0, 0, 0)), blk[:self.na[J]].transpose(0, 2, 1))]"),
-    "periodic_D_any_image": ("        if self.img_of[J].get(L) != r:", "        if L not in self.img_of[J]:"),
+    "periodic_D_any_image": ("ok = (tab[np.ix_(rj, cl)] >= 0) & (tab[np.ix_(rj, cl)] + rm[:, None] - code(zero) == cb[None, :])",
+                             "ok = tab[np.ix_(rj, cl)] >= 0"),
     "periodic_V_relative_image": ("        r = tuple(b - a for a, b in zip(p, q))", "        r = q"),
     "spin_ignores_D": ("return [f(with_density(inputs, D), s) for D in D_spin]",
                        "return [f(inputs, s) for D in D_spin]"),
