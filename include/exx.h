@@ -54,9 +54,12 @@
  * realspace_exchange restricted to that pattern (i on A in the home cell, k on
  * B at n_AB), and E_x = -1/4 sum over those blocks of X o D is the exchange
  * energy per cell.  exx_pair_images() returns n_AB.  Periodic plans take
- * build_K (every precision), graphs, the autotuner and the energy entry
- * points; spin, two-kernel and backward calls return EXX_EUNSUPPORTED, and so
- * does a workspace budget that would need chunks.
+ * build_K (every precision), graphs, the autotuner, the energy entry points
+ * and exchange_backward (gradients per stored entry of the home-cell blocks:
+ * E_x per cell differentiated with every image of a block moving with it;
+ * forces use the image separation x_A - (x_B + n_AB.L)); spin and two-kernel
+ * calls return EXX_EUNSUPPORTED, and so does a workspace budget that would
+ * need chunks.
  *
  * Ownership: the caller owns every device array passed in; the plan owns its
  * bookkeeping lists and workspace.  Output arrays are fully overwritten

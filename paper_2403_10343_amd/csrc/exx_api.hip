@@ -394,7 +394,10 @@ __global__ void k_forces(const double* __restrict__ pos, const double* __restric
     const int J = d.nbr_atom[k];
     if (J == A) continue;
     const int p = d.nbr_pair[k];
-    const double dx = pos[3 * A] - pos[3 * J], dy = pos[3 * A + 1] - pos[3 * J + 1], dz = pos[3 * A + 2] - pos[3 * J + 2];
+    // separation R_A - R_J (periodic: to J's image within the cutoff)
+    const double dx = d.periodic ? d.nbr_sep[3 * (size_t)k] : pos[3 * A] - pos[3 * J];
+    const double dy = d.periodic ? d.nbr_sep[3 * (size_t)k + 1] : pos[3 * A + 1] - pos[3 * J + 1];
+    const double dz = d.periodic ? d.nbr_sep[3 * (size_t)k + 2] : pos[3 * A + 2] - pos[3 * J + 2];
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double gc = sC[p] * (-1.0 / c_decay) / r, gv = sV[p] * (-2.0 / v_2s2);
     f0 -= (gc + gv) * dx;
@@ -515,7 +518,8 @@ static int upload_plan(exx_plan_s* pl) {
   UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
   UP(gq); UP(gx); UP(en_sys); UP(en_pbeg); UP(en_pend);
-  UP(pimg); UP(col2img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2col_off); UP(t2col);
+  UP(pimg); UP(col2img); UP(col1img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2col_off); UP(t2col);
+  UP(nbr_sep); UP(dvcol_off); UP(dvcol); UP(dv_cp); UP(dv_cq);
   UP(pg_beg); UP(pg_mid); UP(pg_end); UP(pg_ent);
 #undef UP
   d.periodic = hp.periodic ? 1 : 0;
@@ -857,7 +861,7 @@ static RowD rowd_E(exx_plan plan) {
 static RowD rowd_GD(exx_plan plan) {
   DevPlan& d = plan->d;
   return RowD{d.H, d.h_off, d.m_loc, d.GD, d.t_off, d.n_loc, d.col1g, d.col1g_off,
-              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs, nullptr};
+              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs, plan->hp.periodic ? d.col1img : nullptr};
 }
 
 static const ChunkDev& cur_chunk(exx_plan plan) { return plan->chunks[plan->cur]; }
@@ -1378,7 +1382,6 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
     return fail(EXX_EUNSUPPORTED, "exchange_backward: only the binary64 backward is implemented");
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "exchange_backward: unknown precision");
   if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, "exchange_backward: decay lengths must be positive");
-  if (plan->hp.periodic) return fail(EXX_EUNSUPPORTED, "exchange_backward: not implemented for periodic plans");
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
   DevPlan& d = plan->d;

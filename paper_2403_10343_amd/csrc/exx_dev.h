@@ -133,7 +133,10 @@ struct DevPlan {
   double *Vr, *Dr;
   // periodic plans (HostPlan): image codes and image-keyed column maps
   int periodic;
-  int *pimg, *col2img, *atom_of_col, *grp_colimg, *grp_cmap;
+  int *pimg, *col2img, *col1img, *atom_of_col, *grp_colimg, *grp_cmap;
+  double* nbr_sep;      // periodic: R_A - (R_J + image shift) per neighbour entry
+  int64_t* dvcol_off;   // dV column maps (HostPlan::dvcol)
+  int *dvcol, *dv_cp, *dv_cq;
   int *pg_beg, *pg_mid, *pg_end;
   PGEnt* pg_ent;
   // binary32 copies for the far pair terms of a mixed build: Vr32 in the layout of Vr; Dr32 at
@@ -259,9 +262,9 @@ struct RowD {
   const int* run_ptr;
   const int* klen;
   const Run* runs;
-  // periodic plans (E only, else nullptr): the image code of every output column; a D
-  // element between the k-row atom J (at its image m within r_cut of P) and the column's
-  // atom L at image b is used only if n_JL = b - m (everything else is beyond the cutoff)
+  // periodic plans (else nullptr): the image code of every output column; a D element
+  // between a k-row atom J at image m (that of its run) and the column's atom L at image b
+  // is used only if n_JL = b - m (everything else is beyond the cutoff)
   const int* ocolimg;
 };
 

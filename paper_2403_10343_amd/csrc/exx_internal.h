@@ -21,7 +21,7 @@ namespace exx {
 constexpr int NB_MAX = 16;   // basis functions per atom supported by the kernels
 constexpr int NA_MAX = 64;   // auxiliary functions per atom supported by the kernels
 
-struct Run { int lcol, grow, len; };           // k-range of the E GEMM
+struct Run { int lcol, grow, len, img; };      // k-range of the E GEMM (img: periodic image code of its rows)
 struct EItem { int P, r0, c0, ct; };           // E tile: rows r0.., cols c0.., column tile ct
 struct Unit { int P, mu0, slot, pad; };        // one wavefront of an H group: atom, aux tile, slot
 struct GTile { int grp, col_beg, ncols, q_beg, q_end, x_beg, x_end, pad; };  // H group x 16 columns
@@ -100,6 +100,8 @@ struct HostPlan {
   std::vector<int> pimg;                            // [A * n_atoms + B]: image of B within r_cut of A, or -1
   std::vector<int> n2_img;                          // image code per N2 entry
   std::vector<int> col2img;                         // image code per E_P column
+  std::vector<int> col1img;                         // image code per T_P column
+  std::vector<double> nbr_sep;                      // per neighbour entry (A, J): R_A - (R_J + shift), 3 doubles
   std::vector<int> atom_of_col;                     // atom of every basis function
   std::vector<int> grp_colimg;                      // image code per V-stage group column
   std::vector<int> grp_cmap;                        // [group column * 3 + slot]: H' column of the slot atom, or -1
@@ -144,6 +146,10 @@ struct HostPlan {
   std::vector<int64_t> t2col_off;
   std::vector<int> t2col;
   std::vector<int> dv_items;                        // canonical pair ids sorted by dV shape class
+  // per canonical pair p = (P, Q) = (pair_a, pair_b): the E_P column of every column of T_Q,
+  // and the E_P column where Q's basis starts / the E_Q column where P's basis starts
+  std::vector<int64_t> dvcol_off;
+  std::vector<int> dvcol, dv_cp, dv_cq;
   std::vector<DVClass> dv_classes;
   std::vector<T2Class> t2_classes;
   std::vector<int64_t> y_off;                       // Y_P = T_P^T H'_P, n_P x m_P row-major

@@ -32,9 +32,8 @@ __global__ __launch_bounds__(64 * DV_WAVES) void k_dV(const double* __restrict__
   const int nQ = d.n_loc[Q], mP = d.m_loc[P], mQ = d.m_loc[Q];
   const int s = d.atom_sys[P];
   const int64_t ns = d.sys_n[s];
-  const int* cg = d.col1g + d.col1g_off[Q];
-  const int* m2P = d.map2 + d.map_off[P];
-  const int* m2Q = d.map2 + d.map_off[Q];
+  const int* colP = d.dvcol + d.dvcol_off[p];   // E_P column of every column of T_Q
+  const int cPQ = d.dv_cp[p], cQP = d.dv_cq[p];   // E_P column of Q's basis, E_Q column of P's
   const double* TQ = d.T + d.t_off[Q];
   const double* EP = d.E + d.e_off[P];
   const double* EQ = d.E + d.e_off[Q];
@@ -62,7 +61,7 @@ __global__ __launch_bounds__(64 * DV_WAVES) void k_dV(const double* __restrict__
   auto fetch = [&](int l0) {
     const int l = l0 + tc;
     const bool cv = l < nQ;
-    const int ce = cv ? m2P[cg[l]] : 0;
+    const int ce = cv ? colP[l] : 0;
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       const int r = r0 + DV_RSTEP * i;
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(64 * DV_WAVES) void k_dV(const double* __restrict__
       const int kf = 4 * q + lk;
       const bool kv = kf < K2;
       const int i = kv ? kf / bQ : 0, l = kv ? kf - i * bQ : 0;
-      const int cP = kv ? m2P[d.bo[Q] + l] : 0, cQ = kv ? m2Q[d.bo[P] + i] : 0;
+      const int cP = kv ? cPQ + l : 0, cQ = kv ? cQP + i : 0;
 #pragma unroll
       for (int y = 0; y < NTQ; ++y) {
         const int nu = 16 * y + lr;

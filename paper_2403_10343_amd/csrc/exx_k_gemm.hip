@@ -71,10 +71,10 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
       const bool okb = k2 < klen;
       if (okb) while (k2 >= sb[pz] + runs[ib[pz]].len) { sb[pz] += runs[ib[pz]].len; ++ib[pz]; }
       const int gr = okb ? runs[ib[pz]].grow + (k2 - sb[pz]) : 0;
-      int jrow = 0, mimg = 0;
+      int jrow = 0, mimg = 0;   // periodic: the row's atom and its image (that of its run)
       if (per && okb) {
         jrow = d.atom_of_col[gr];
-        mimg = d.pimg[(size_t)P * NAt + jrow];
+        mimg = runs[ib[pz]].img;
       }
 #pragma unroll
       for (int x = 0; x < 4; ++x) {

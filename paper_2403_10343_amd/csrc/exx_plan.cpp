@@ -286,7 +286,7 @@ int derive_lists(HostPlan& hp, std::string& err) {
         }
         const int ct = (int)klens.size();
         int klen = 0, lcol = 0, prevJ = -2;
-        Run cur{-1, -1, 0};
+        Run cur{-1, -1, 0, 0};
         for (int k = 0; k < n_in; ++k) {
           const int j = in_b[k];
           bool rel = false;
@@ -296,7 +296,7 @@ int derive_lists(HostPlan& hp, std::string& err) {
               cur.len += hp.nb[j];
             } else {
               if (cur.len > 0) runs.push_back(cur);
-              cur = Run{lcol, hp.bo[j], hp.nb[j]};
+              cur = Run{lcol, hp.bo[j], hp.nb[j], 0};
             }
             prevJ = j;
             klen += hp.nb[j];
@@ -504,6 +504,17 @@ int derive_lists(HostPlan& hp, std::string& err) {
         hp.dv_classes.push_back(DVClass{k / 512, (k / 64) % 8, (k / 8) % 8, k % 8, i, i});
       hp.dv_classes.back().end = i + 1;
     }
+  }
+  hp.dvcol_off.assign(npairs + 1, 0);
+  hp.dvcol.clear();
+  hp.dv_cp.assign(npairs, 0);
+  hp.dv_cq.assign(npairs, 0);
+  for (int64_t p = 0; p < npairs; ++p) {
+    const int a = hp.pair_a[p], b = hp.pair_b[p];
+    for (int l = 0; l < hp.n_loc[b]; ++l) hp.dvcol.push_back(hp.map2[hp.map_off[a] + hp.col1g[hp.col1g_off[b] + l]]);
+    hp.dvcol_off[p + 1] = (int64_t)hp.dvcol.size();
+    hp.dv_cp[p] = hp.map2[hp.map_off[a] + hp.bo[b]];
+    hp.dv_cq[p] = hp.map2[hp.map_off[b] + hp.bo[a]];
   }
   // ---- final tasks: 32 x 32 tile pairs (upper triangle) with their P-lists
   hp.f_items.clear();

@@ -178,6 +178,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
   hp.col1g.assign(hp.col1g_off[NA], 0);
   hp.col2g.assign(hp.col2g_off[NA], 0);
   hp.col2img.assign(hp.col2g_off[NA], 0);
+  hp.col1img.assign(hp.col1g_off[NA], 0);
   hp.atom_of_col.assign(hp.sys_n[0], 0);
   for (int a = 0; a < NA; ++a)
     for (int x = 0; x < hp.nb[a]; ++x) hp.atom_of_col[hp.bo[a] + x] = a;
@@ -188,6 +189,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
       for (int x = 0; x < hp.nb[j]; ++x, ++c) {
         hp.map1[hp.map_off[a] + hp.bo[j] + x] = c;
         hp.col1g[hp.col1g_off[a] + c] = hp.bo[j] + x;
+        hp.col1img[hp.col1g_off[a] + c] = nim[k];
       }
     }
     c = 0;
@@ -199,6 +201,17 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
       }
     }
   }
+  // separation of every neighbour entry (forces): R_A - (R_J + shift of its image)
+  hp.nbr_sep.assign(3 * (size_t)nn, 0.0);
+  for (int a = 0; a < NA; ++a)
+    for (int k = np[a]; k < np[a + 1]; ++k) {
+      double sh[3];
+      image_shift(hp.lat, nim[k], sh);
+      for (int c = 0; c < 3; ++c) {
+        volatile double pj = hp.pos[3 * (size_t)nat[k] + c] + sh[c];
+        hp.nbr_sep[3 * (size_t)k + c] = hp.pos[3 * (size_t)a + c] - pj;
+      }
+    }
   // ---- workspace layout
   hp.t_off.assign(NA + 1, 0);
   hp.e_off.assign(NA + 1, 0);
@@ -213,7 +226,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
   for (auto& f : hp.issued) f = 0;
   // ---- E_P = T_P D: 64-column tiles of the N2 entries; the k-range of a tile is the runs of
   // entries (J, m) of N[P] whose neighbourhood meets the tile (J's row of D at image
-  // n_JL = b - m for a tile column (L, b))
+  // n_JL = b - m for a tile column (L, b)), runs of consecutive atoms at one image
   hp.e_items.clear();
   hp.ct_run_ptr.assign(1, 0);
   hp.ct_klen.clear();
@@ -244,18 +257,19 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
           }
         }
         const int ct = (int)hp.ct_klen.size();
-        int klen = 0, lcol = 0, prevJ = -2;
-        Run cur{-1, -1, 0};
+        int klen = 0, lcol = 0, prevJ = -2, prevImg = -1;
+        Run cur{-1, -1, 0, 0};
         for (int k = np[a]; k < np[a + 1]; ++k) {
           const int j = nat[k];
           if (mark[j] == stamp) {
-            if (cur.len > 0 && j == prevJ + 1) {
+            if (cur.len > 0 && j == prevJ + 1 && nim[k] == prevImg) {
               cur.len += hp.nb[j];
             } else {
               if (cur.len > 0) hp.runs.push_back(cur);
-              cur = Run{lcol, hp.bo[j], hp.nb[j]};
+              cur = Run{lcol, hp.bo[j], hp.nb[j], nim[k]};
             }
             prevJ = j;
+            prevImg = nim[k];
             klen += hp.nb[j];
           } else {
             prevJ = -2;
@@ -268,6 +282,59 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         for (int r0 = 0; r0 < sP; r0 += E_TILE) {
           hp.e_items.push_back(EItem{a, r0, c0, ct});
           hp.issued[1] += 2LL * E_TILE * E_TILE * ceil_to(klen, 16);
+        }
+      }
+    }
+  }
+  // ---- the gradient product G_P = H_P D: 64-column tiles of the N[P] entries (J, m); its
+  // k-range is the runs of N2[P] entries (L, b) with J in N[L] at image m - b (runs of
+  // consecutive atoms at one image)
+  {
+    std::vector<int> mark(hp.n2_atom.size(), -1);
+    int stamp = 0;
+    int64_t gd_issued = 0;
+    for (int a = 0; a < NA; ++a) {
+      const int sP = hp.na[a] * hp.nb[a];
+      const int nOut = hp.n_loc[a];
+      int kstart = np[a], cstart = 0;
+      for (int c0 = 0; c0 < nOut; c0 += E_TILE) {
+        const int c1 = std::min(nOut, c0 + E_TILE);
+        ++stamp;
+        while (kstart < np[a + 1] && cstart + hp.nb[nat[kstart]] <= c0) { cstart += hp.nb[nat[kstart]]; ++kstart; }
+        for (int k = kstart, c = cstart; k < np[a + 1] && c < c1; c += hp.nb[nat[k]], ++k) {
+          const int j = nat[k], m = nim[k];
+          for (int k2 = np[j]; k2 < np[j + 1]; ++k2) {
+            const int l = nat[k2], b = img_add(m, nim[k2]);   // L = nat[k2] at image m + n_JL
+            for (int e = n2first[(size_t)a * NA + l]; e >= 0 && e < hp.n2_ptr[a + 1] && hp.n2_atom[e] == l; ++e)
+              if (hp.n2_img[e] == b) mark[e] = stamp;
+          }
+        }
+        const int ct = (int)hp.gd_klen.size();
+        int klen = 0, lcol = 0, prevL = -2, prevImg = -1;
+        Run cur{-1, -1, 0, 0};
+        for (int e = hp.n2_ptr[a]; e < hp.n2_ptr[a + 1]; ++e) {
+          const int l = hp.n2_atom[e], b = hp.n2_img[e];
+          if (mark[e] == stamp) {
+            if (cur.len > 0 && l == prevL + 1 && b == prevImg) {
+              cur.len += hp.nb[l];
+            } else {
+              if (cur.len > 0) hp.gd_runs.push_back(cur);
+              cur = Run{lcol, hp.bo[l], hp.nb[l], b};
+            }
+            prevL = l;
+            prevImg = b;
+            klen += hp.nb[l];
+          } else {
+            prevL = -2;
+          }
+          lcol += hp.nb[l];
+        }
+        if (cur.len > 0) hp.gd_runs.push_back(cur);
+        hp.gd_run_ptr.push_back((int)hp.gd_runs.size());
+        hp.gd_klen.push_back(klen);
+        for (int r0 = 0; r0 < sP; r0 += E_TILE) {
+          hp.gd_items.push_back(EItem{a, r0, c0, ct});
+          gd_issued += 2LL * E_TILE * E_TILE * ceil_to(klen, 16);
         }
       }
     }
@@ -471,8 +538,39 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
       hp.t2_classes.back().end = i + 1;
     }
   }
-  hp.dv_items.clear();
-  hp.dv_classes.clear();
+  // ---- dV pairs: grouped by shape as for clusters; per pair (P, Q) = (pair_a, pair_b) the
+  // E_P column of every column of T_Q and the E columns of each other's basis
+  {
+    auto key = [&](int p) {
+      const int a = hp.pair_a[p], b = hp.pair_b[p];
+      return (((hp.na[a] + 15) / 16) * 8 + (hp.na[b] + 15) / 16) * 64 + ((hp.nb[b] + 3) / 4) * 8 + (hp.nb[a] + 3) / 4;
+    };
+    hp.dv_items.resize(npairs);
+    for (int64_t p = 0; p < npairs; ++p) hp.dv_items[p] = (int)p;
+    std::stable_sort(hp.dv_items.begin(), hp.dv_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    hp.dv_classes.clear();
+    for (int i = 0; i < (int)hp.dv_items.size(); ++i) {
+      const int k = key(hp.dv_items[i]);
+      if (hp.dv_classes.empty() || i == 0 || key(hp.dv_items[i - 1]) != k)
+        hp.dv_classes.push_back(DVClass{k / 512, (k / 64) % 8, (k / 8) % 8, k % 8, i, i});
+      hp.dv_classes.back().end = i + 1;
+    }
+    hp.dvcol_off.assign(npairs + 1, 0);
+    hp.dvcol.clear();
+    hp.dv_cp.assign(npairs, 0);
+    hp.dv_cq.assign(npairs, 0);
+    for (int64_t p = 0; p < npairs; ++p) {
+      const int a = hp.pair_a[p], b = hp.pair_b[p], q = hp.pair_img[p];
+      for (int k = np[b]; k < np[b + 1]; ++k) {
+        const int c = n2col(a, nat[k], img_add(q, nim[k]));
+        if (c < 0) { err = "periodic dV column outside N2"; return -3; }
+        for (int x = 0; x < hp.nb[nat[k]]; ++x) hp.dvcol.push_back(c + x);
+      }
+      hp.dvcol_off[p + 1] = (int64_t)hp.dvcol.size();
+      hp.dv_cp[p] = n2col(a, b, q);
+      hp.dv_cq[p] = n2col(b, a, img_neg(q));
+    }
+  }
   hp.f_items.clear();
   hp.f_plist.clear();
   hp.y_tiles.clear();
