@@ -216,10 +216,11 @@ def path_record(plan, dt, stage_ms, mixed, names, workload):
     }
 
 
-def periodic_record(exx, torch, steps):
+def periodic_record(exx, torch, steps, backward_steps=1):
     """The periodic 1024-water box (3072 atoms, 24576 basis, r_cut 8 A): FP64 and
     mixed K builds per second (the pattern-folded real-space X), stage times,
-    and the mixed error against the FP64 build."""
+    the mixed error against the FP64 build, and forward (FP64 or mixed) plus FP64
+    backward with forces."""
     import synth
     t0 = time.perf_counter()
     sysm = synth.config(5)
@@ -253,6 +254,27 @@ def periodic_record(exx, torch, steps):
                     "dE_x_per_atom_vs_fp64": abs(float(Ex.item()) - E64) / sysm.n_atoms}
     rec["mixed"]["within_bar"] = rec["mixed"]["max_abs_dK_vs_fp64"] <= 1e-5 and rec["mixed"]["dE_x_per_atom_vs_fp64"] <= 1e-6
     rec["E_x_per_atom"] = E64 / sysm.n_atoms
+    if backward_steps > 0:
+        dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D)
+        F = torch.empty(sysm.n_atoms * 3, dtype=torch.float64, device=dev)
+        fb = {}
+        for name, prec in (("fp64", exx.PREC_FP64), ("mixed", exx.PREC_MIXED)):
+            plan.build_K(C, V, D, K, Ex, precision=prec)
+            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(backward_steps):
+                plan.build_K(C, V, D, K, Ex, precision=prec)
+                plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / backward_steps
+            fb[name] = {"workload": f"{name} forward E_x; FP64 backward: dE/dC, dE/dV, dE/dD, forces",
+                        "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
+                        "net_force_max": float(F.view(-1, 3).sum(0).abs().max().item()),
+                        "euler_C": float((dC * C).sum().item() / (2 * E64)),
+                        "euler_V": float((dV * V).sum().item() / E64)}
+        rec["forward_backward"] = fb
+        del dC, dV, dD, F
     del C, V, D, K, K64
     plan.close()
     torch.cuda.empty_cache()
@@ -276,14 +298,16 @@ def main():
                     help="also time the collinear-spin build (two density matrices, FP64); 0 = skip")
     ap.add_argument("--two-kernel-steps", type=int, default=5,
                     help="also time two Coulomb matrices in one call (FP64); 0 = skip")
+    ap.add_argument("--periodic-only", action="store_true",
+                    help="time only the periodic 3072-atom box (its record as the JSON line)")
     ap.add_argument("--periodic-steps", type=int, default=2,
                     help="also time the periodic 3072-atom box (FP64 and mixed builds); 0 = skip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the exchange build here runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build). Use --gpus 1.",
+        print("bench.py measures one GPU only: the exchange build runs on a single MI355X "
+              "(sharding over several GPUs is not implemented). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -293,6 +317,10 @@ def main():
     import synth
     import paper_2403_10343_amd as exx
 
+    if args.periodic_only:
+        print(json.dumps({"periodic": periodic_record(exx, torch, max(args.periodic_steps, 1),
+                                                      min(args.backward_steps, 1))}), flush=True)
+        return
     cfg, wname = WORKLOADS[args.workload]
     sysm = synth.config(cfg)
     inp = synth.make_inputs(sysm)
@@ -424,7 +452,7 @@ def main():
             "E_x": [float(x) for x in E2.cpu().numpy()],
         }
     if args.periodic_steps > 0:
-        out["periodic"] = periodic_record(exx, torch, args.periodic_steps)
+        out["periodic"] = periodic_record(exx, torch, args.periodic_steps, min(args.backward_steps, 1))
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -520,7 +520,7 @@ static int upload_plan(exx_plan_s* pl) {
   UP(gq); UP(gx); UP(en_sys); UP(en_pbeg); UP(en_pend);
   UP(pimg); UP(col2img); UP(col1img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2col_off); UP(t2col);
   UP(nbr_sep); UP(dvcol_off); UP(dvcol); UP(dv_cp); UP(dv_cq);
-  UP(pg_beg); UP(pg_mid); UP(pg_end); UP(pg_ent);
+  UP(pg_beg); UP(pg_mid); UP(pg_end); UP(pg_ent); UP(pt_tiles); UP(pt_ent); UP(pg_pairs);
 #undef UP
   d.periodic = hp.periodic ? 1 : 0;
   if ((rc = upload(pl, pl->g_tiles_all, hp.g_tiles))) return rc;

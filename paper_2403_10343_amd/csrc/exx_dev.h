@@ -139,6 +139,9 @@ struct DevPlan {
   int *dvcol, *dv_cp, *dv_cq;
   int *pg_beg, *pg_mid, *pg_end;
   PGEnt* pg_ent;
+  PTile* pt_tiles;
+  PTEnt* pt_ent;
+  int* pg_pairs;
   // binary32 copies for the far pair terms of a mixed build: Vr32 in the layout of Vr; Dr32 at
   // (2 p + o) * 256, [k-step q < 4][lane L] = D_PQ[L % 16][4 (L / 16) + q] (the binary32 MFMA
   // accumulator puts rows 4 (L / 16) + v in lane L, so its D chain runs four k-steps)

@@ -86,6 +86,13 @@ struct ChunkHost {
 constexpr int EN_PAIRS = 64;         // canonical pairs per energy chunk
 
 struct PGEnt { int P, tcol, hcol, pad; };       // pattern gather: T_P column, H'_P column
+// Tiled pattern contraction: a tile is a pair of V-stage groups (ga <= gb); an entry is one
+// P and one part (0: rows of T_P on the ga atoms times columns of H'_P on the gb atoms;
+// 1: rows of H'_P on the ga atoms times columns of T_P on the gb atoms), with the first
+// column of each group atom in the row and column matrices, or -1.
+struct PTEnt { int P, part, rc[3], cc[3]; };
+struct PTile { int a0, na, b0, nbt, e_beg, e_end, mask, pad; };   // mask bit 3 sa + sb: pair in the pattern
+struct PTClass { int ta, tb, beg, end; };        // tiles with ta x tb 16 x 16 output tiles
 
 struct HostPlan {
   // system description
@@ -107,6 +114,10 @@ struct HostPlan {
   std::vector<int> grp_cmap;                        // [group column * 3 + slot]: H' column of the slot atom, or -1
   std::vector<int> pg_beg, pg_mid, pg_end;          // per canonical pair: X'_AB terms [beg, mid), X'_BA [mid, end)
   std::vector<PGEnt> pg_ent;
+  std::vector<PTile> pt_tiles;                      // tiled pattern contraction, sorted by class
+  std::vector<PTEnt> pt_ent;
+  std::vector<PTClass> pt_classes;
+  std::vector<int> pg_pairs;                        // canonical pairs left to the per-pair gather
   std::vector<int> species, nb, na, atom_sys, bo;   // per atom
   std::vector<double> pos;                          // 3 * n_atoms
   std::vector<int> sys_atom_off;                    // n_sys + 1

@@ -335,8 +335,9 @@ void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* 
 }
 
 // ---------------------------------------------------------------------------
-// Periodic plans: the final contraction on the pair pattern.  Per canonical
-// pair (A, B) (B at its image n within r_cut of A) one workgroup of four
+// Periodic plans: the final contraction on the pair pattern, per canonical pair
+// for the pairs whose group tile has no single image (the rest run in k_ptile
+// below).  Per such pair (A, B) (B at its image n within r_cut of A) one workgroup of four
 // wavefronts forms X'_AB = sum_P T_P[:, A]^T H'_P[:, (B, a + n)] (P over the
 // atoms with A in N[P] at image a) and likewise X'_BA, each term a chain of
 // 16x16x4 MFMAs over the s_P rows of P; the terms are dealt to the wavefronts
@@ -347,8 +348,9 @@ void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* 
 __global__ __launch_bounds__(256) void k_pgather(double* __restrict__ K, DevPlan d, int n_pairs, int n_padded) {
   __shared__ double red[4][2][4][64];
   __shared__ double xs[2][16][17];
-  const int p = xcd_task(n_padded);
-  if (p >= n_pairs) return;
+  const int pi = xcd_task(n_padded);
+  if (pi >= n_pairs) return;
+  const int p = d.pg_pairs[pi];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63, lr = L & 15, lk = L >> 4;
   const int A = d.pair_a[p], B = d.pair_b[p];
   const int bA = d.nb[A], bB = d.nb[B];
@@ -412,10 +414,147 @@ __global__ __launch_bounds__(256) void k_pgather(double* __restrict__ K, DevPlan
   }
 }
 
+// Tiled pattern contraction: one workgroup per tile of two V-stage groups (ga, gb), whose
+// TA x TB output tiles of 16 x 16 (the ga basis functions by the gb ones) sit in registers
+// of every wavefront.  The tile's entries (P, part) are dealt to the four wavefronts in turn;
+// an entry adds, over the s_P rows r of P, R[r][row column]^T C[r][column column] with
+// (R, C) = (T_P, H'_P) for part 0 (X'_AB) and (H'_P, T_P) for part 1 (the transpose of
+// X'_BA), so the sum is X'_AB + X'_BA^T for every atom pair of the tile.  Each k-round
+// issues the loads of four k-steps together; the four wavefront partials are added in a
+// fixed order.  Then K_AB += (X'_AB + X'_BA^T) / 2 on the tile's pattern pairs (upper
+// triangle of a diagonal tile), mirrored to K_BA.
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_ptile(double* __restrict__ K, DevPlan d, const PTile* __restrict__ tiles,
+                                               int n_tiles, int n_padded) {
+  __shared__ double red[4][TA * TB][4][64];
+  const int ti = xcd_task(n_padded);
+  if (ti >= n_tiles) return;
+  const PTile tl = tiles[ti];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63, lr = L & 15, lk = L >> 4;
+  // group atom (slot) and local basis index of the lane's output rows and columns
+  int rs[TA], rx[TA], cs[TB], cx[TB];
+#pragma unroll
+  for (int t = 0; t < TA; ++t) {
+    int i = 16 * t + lr, sl = -1;
+    for (int a = 0; a < tl.na && sl < 0; ++a) {
+      const int nbs = d.nb[tl.a0 + a];
+      if (i < nbs) sl = a; else i -= nbs;
+    }
+    rs[t] = sl;
+    rx[t] = i;
+  }
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    int i = 16 * t + lr, sl = -1;
+    for (int a = 0; a < tl.nbt && sl < 0; ++a) {
+      const int nbs = d.nb[tl.b0 + a];
+      if (i < nbs) sl = a; else i -= nbs;
+    }
+    cs[t] = sl;
+    cx[t] = i;
+  }
+  d4 acc[TA][TB];
+#pragma unroll
+  for (int t = 0; t < TA; ++t)
+#pragma unroll
+    for (int u = 0; u < TB; ++u) acc[t][u] = d4{0, 0, 0, 0};
+  for (int e = tl.e_beg + wv; e < tl.e_end; e += 4) {
+    const PTEnt pe = d.pt_ent[e];
+    const int P = pe.P;
+    const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
+    const double* Tm = d.T + d.t_off[P];
+    const double* Hm = d.H + d.h_off[P];
+    const double* Rm = pe.part ? Hm : Tm;
+    const double* Cm = pe.part ? Tm : Hm;
+    const int rp = pe.part ? mP : nP, cp = pe.part ? nP : mP;
+    int rcol[TA], ccol[TB];
+    bool rok[TA], cok[TB];
+#pragma unroll
+    for (int t = 0; t < TA; ++t) {
+      const int c = rs[t] >= 0 ? pe.rc[rs[t]] : -1;
+      rok[t] = c >= 0;
+      rcol[t] = rok[t] ? c + rx[t] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      const int c = cs[t] >= 0 ? pe.cc[cs[t]] : -1;
+      cok[t] = c >= 0;
+      ccol[t] = cok[t] ? c + cx[t] : 0;
+    }
+    for (int r0 = 0; r0 < sP; r0 += 16) {
+      double a[4][TA], b[4][TB];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + 4 * u + lk;
+        const bool ok = r < sP;
+#pragma unroll
+        for (int t = 0; t < TA; ++t) {
+          const bool v = ok && rok[t];
+          const double x = Rm[v ? (size_t)r * rp + rcol[t] : 0];
+          a[u][t] = v ? x : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+          const bool v = ok && cok[t];
+          const double x = Cm[v ? (size_t)r * cp + ccol[t] : 0];
+          b[u][t] = v ? x : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < TA; ++t)
+#pragma unroll
+          for (int v = 0; v < TB; ++v) acc[t][v] = mfma64(a[u][t], b[u][v], acc[t][v]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TA; ++t)
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wv][t * TB + u][v][L] = acc[t][u][v];
+  __syncthreads();
+  const int64_t ns = d.sys_n[0];
+  double* Kp = K + d.sys_d_off[0];
+  const bool diag = tl.a0 == tl.b0;
+  for (int idx = threadIdx.x; idx < TA * TB * 256; idx += 256) {
+    const int tile = idx >> 8, v = (idx >> 6) & 3, Lx = idx & 63;
+    const int i0 = 16 * (tile / TB) + (Lx >> 4) + 4 * v, k0 = 16 * (tile % TB) + (Lx & 15);
+    int sa = -1, xa = i0, sb = -1, xb = k0;
+    for (int a = 0; a < tl.na && sa < 0; ++a) {
+      const int nbs = d.nb[tl.a0 + a];
+      if (xa < nbs) sa = a; else xa -= nbs;
+    }
+    for (int a = 0; a < tl.nbt && sb < 0; ++a) {
+      const int nbs = d.nb[tl.b0 + a];
+      if (xb < nbs) sb = a; else xb -= nbs;
+    }
+    if (sa < 0 || sb < 0 || !((tl.mask >> (3 * sa + sb)) & 1)) continue;
+    if (diag && (sa > sb || (sa == sb && xa > xb))) continue;
+    const double x = 0.5 * (((red[0][tile][v][Lx] + red[1][tile][v][Lx]) + red[2][tile][v][Lx]) + red[3][tile][v][Lx]);
+    const int A = tl.a0 + sa, B = tl.b0 + sb;
+    const size_t ab = (size_t)(d.bo[A] + xa) * ns + d.bo[B] + xb;
+    const double val = Kp[ab] + x;
+    Kp[ab] = val;
+    if (!(diag && sa == sb && xa == xb)) Kp[(size_t)(d.bo[B] + xb) * ns + d.bo[A] + xa] = val;
+  }
+}
+
 void launch_pgather(exx_plan plan, double* K, hipStream_t st) {
-  const int n = (int)plan->hp.pair_a.size(), np_ = (n + 7) / 8 * 8;
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_pgather, dim3(np_), dim3(256), 0, st, K, plan->d, n, np_);
+  const HostPlan& hp = plan->hp;
+  for (const PTClass& c : hp.pt_classes) {
+    const int n = c.end - c.beg, np_ = (n + 7) / 8 * 8;
+    const PTile* tl = plan->d.pt_tiles + c.beg;
+    switch (c.ta * 4 + c.tb) {
+#define PTC(TA, TB) case TA * 4 + TB: hipLaunchKernelGGL((k_ptile<TA, TB>), dim3(np_), dim3(256), 0, st, K, plan->d, tl, n, np_); break;
+      PTC(1, 1) PTC(1, 2) PTC(1, 3) PTC(2, 1) PTC(2, 2) PTC(2, 3) PTC(3, 1) PTC(3, 2) PTC(3, 3)
+#undef PTC
+      default: break;
+    }
+  }
+  const int n = (int)hp.pg_pairs.size(), np_ = (n + 7) / 8 * 8;
+  if (n > 0) hipLaunchKernelGGL(k_pgather, dim3(np_), dim3(256), 0, st, K, plan->d, n, np_);
 }
 
 void launch_Y(exx_plan plan, int choice, hipStream_t st) {

@@ -578,12 +578,124 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
   hp.y_total = 0;
   // ---- final contraction on the pattern: per canonical pair (A, B) at image n, the terms
   // X'_AB = sum_P T_P[:, A]^T H'_P[:, (B, a + n)] over the P with A in N[P] at image a, and
-  // X'_BA likewise (B in N[P] at image b, H' column (A, b - n))
+  // X'_BA likewise (B in N[P] at image b, H' column (A, b - n)).  They are evaluated by
+  // tiles of two V-stage groups (one image for the whole tile, one image per P for each
+  // group); the pairs of tiles without such images keep per-pair term lists.
   hp.pg_beg.assign(npairs, 0);
   hp.pg_mid.assign(npairs, 0);
   hp.pg_end.assign(npairs, 0);
   hp.pg_ent.clear();
+  hp.pg_pairs.clear();
+  hp.pt_tiles.clear();
+  hp.pt_ent.clear();
+  hp.pt_classes.clear();
+  auto lcol_in = [&](int P, int R) {   // first T_P column of R (R in N[P])
+    auto jt = std::lower_bound(nat.begin() + np[P], nat.begin() + np[P + 1], R);
+    return hp.nbr_lcol[jt - nat.begin()];
+  };
+  // algorithmic flops: the pair terms, whichever route evaluates them
   for (int64_t p = 0; p < npairs; ++p) {
+    const int A = hp.pair_a[p], B = hp.pair_b[p], n = hp.pair_img[p];
+    for (int dir = 0; dir < (A == B ? 1 : 2); ++dir) {
+      const int R = dir ? B : A, S = dir ? A : B, img_rs = dir ? img_neg(n) : n;
+      for (int k = np[R]; k < np[R + 1]; ++k) {
+        const int P = nat[k];
+        if (n2col(P, S, img_add(hp.pimg[(size_t)P * NA + R], img_rs)) >= 0)
+          hp.flops[4] += 2LL * hp.nb[R] * hp.nb[S] * hp.na[P] * hp.nb[P];
+      }
+    }
+  }
+  const int NG = (int)hp.grp_first.size();
+  std::vector<int> grp_of(NA);
+  for (int g = 0; g < NG; ++g)
+    for (int a = hp.grp_first[g]; a < (g + 1 < NG ? hp.grp_first[g + 1] : NA); ++a) grp_of[a] = g;
+  std::vector<std::pair<int64_t, int>> tp(npairs);
+  for (int64_t p = 0; p < npairs; ++p)
+    tp[p] = {(int64_t)grp_of[hp.pair_a[p]] * NG + grp_of[hp.pair_b[p]], (int)p};
+  std::sort(tp.begin(), tp.end());
+  std::vector<PTile> tiles;
+  std::vector<int> tile_ta, tile_tb;
+  std::vector<int> plist;
+  std::vector<int> mark(NA, -1);
+  for (size_t i0 = 0; i0 < tp.size();) {
+    size_t i1 = i0;
+    while (i1 < tp.size() && tp[i1].first == tp[i0].first) ++i1;
+    const int ga = (int)(tp[i0].first / NG), gb = (int)(tp[i0].first % NG);
+    const int a0 = hp.grp_first[ga], na_ = (ga + 1 < NG ? hp.grp_first[ga + 1] : NA) - a0;
+    const int b0 = hp.grp_first[gb], nb_ = (gb + 1 < NG ? hp.grp_first[gb + 1] : NA) - b0;
+    const int n = hp.pair_img[tp[i0].second];
+    bool ok = true;
+    int mask = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      const int p = tp[i].second;
+      ok = ok && hp.pair_img[p] == n;
+      mask |= 1 << (3 * (hp.pair_a[p] - a0) + (hp.pair_b[p] - b0));
+    }
+    if (ga == gb) ok = ok && n == IMG0;
+    PTile tl{a0, na_, b0, nb_, (int)hp.pt_ent.size(), 0, mask, 0};
+    for (int part = 0; part < 2 && ok; ++part) {
+      // part 0: P with a ga atom in N[P]; part 1: P with a gb atom in N[P]
+      const int r0 = part ? b0 : a0, nr = part ? nb_ : na_;
+      const int o0 = part ? a0 : b0, no = part ? na_ : nb_;
+      const int img_ro = part ? img_neg(n) : n;   // image of the other group relative to this one
+      plist.clear();
+      for (int t = 0; t < nr; ++t)
+        for (int k = np[r0 + t]; k < np[r0 + t + 1]; ++k)
+          if (mark[nat[k]] != (int)i0 * 2 + part) { mark[nat[k]] = (int)i0 * 2 + part; plist.push_back(nat[k]); }
+      std::sort(plist.begin(), plist.end());
+      for (int P : plist) {
+        int rimg = -1;
+        int tc[3] = {-1, -1, -1}, hc[3] = {-1, -1, -1};
+        for (int t = 0; t < nr; ++t) {
+          const int im = hp.pimg[(size_t)P * NA + r0 + t];
+          if (im < 0) continue;
+          if (rimg >= 0 && im != rimg) ok = false;
+          rimg = im;
+          tc[t] = lcol_in(P, r0 + t);
+        }
+        if (!ok) break;
+        bool anyh = false;
+        for (int t = 0; t < no; ++t) {
+          hc[t] = n2col(P, o0 + t, img_add(rimg, img_ro));
+          anyh = anyh || hc[t] >= 0;
+        }
+        if (!anyh) continue;
+        PTEnt e{P, part, {-1, -1, -1}, {-1, -1, -1}};
+        for (int t = 0; t < 3; ++t) {
+          e.rc[t] = part ? hc[t] : tc[t];
+          e.cc[t] = part ? tc[t] : hc[t];
+        }
+        hp.pt_ent.push_back(e);
+      }
+    }
+    if (!ok) {
+      hp.pt_ent.resize(tl.e_beg);
+      for (size_t i = i0; i < i1; ++i) hp.pg_pairs.push_back(tp[i].second);
+    } else {
+      tl.e_end = (int)hp.pt_ent.size();
+      int ba = 0, bb = 0;
+      for (int t = 0; t < na_; ++t) ba += hp.nb[a0 + t];
+      for (int t = 0; t < nb_; ++t) bb += hp.nb[b0 + t];
+      tiles.push_back(tl);
+      tile_ta.push_back((ba + 15) / 16);
+      tile_tb.push_back((bb + 15) / 16);
+      for (int e = tl.e_beg; e < tl.e_end; ++e) {
+        const int P = hp.pt_ent[e].P;
+        hp.issued[4] += 2048LL * tile_ta.back() * tile_tb.back() * ((hp.na[P] * hp.nb[P] + 3) / 4);
+      }
+    }
+    i0 = i1;
+  }
+  // tiles by class (ta, tb), group-pair order kept inside a class
+  for (int ta = 1; ta <= GROUP_ATOMS; ++ta)
+    for (int tb = 1; tb <= GROUP_ATOMS; ++tb) {
+      const int beg = (int)hp.pt_tiles.size();
+      for (size_t i = 0; i < tiles.size(); ++i)
+        if (tile_ta[i] == ta && tile_tb[i] == tb) hp.pt_tiles.push_back(tiles[i]);
+      if ((int)hp.pt_tiles.size() > beg) hp.pt_classes.push_back(PTClass{ta, tb, beg, (int)hp.pt_tiles.size()});
+    }
+  std::sort(hp.pg_pairs.begin(), hp.pg_pairs.end());
+  for (int p : hp.pg_pairs) {
     const int A = hp.pair_a[p], B = hp.pair_b[p], n = hp.pair_img[p];
     hp.pg_beg[p] = (int)hp.pg_ent.size();
     for (int dir = 0; dir < (A == B ? 1 : 2); ++dir) {
@@ -593,9 +705,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         const int r_img = hp.pimg[(size_t)P * NA + R];   // image of R within r_cut of P
         const int hc = n2col(P, S, img_add(r_img, img_rs));
         if (hc < 0) continue;
-        auto jt = std::lower_bound(nat.begin() + np[P], nat.begin() + np[P + 1], R);
-        hp.pg_ent.push_back(PGEnt{P, hp.nbr_lcol[jt - nat.begin()], hc, 0});
-        hp.flops[4] += 2LL * hp.nb[R] * hp.nb[S] * hp.na[P] * hp.nb[P];
+        hp.pg_ent.push_back(PGEnt{P, lcol_in(P, R), hc, 0});
         hp.issued[4] += 2048LL * ((hp.na[P] * hp.nb[P] + 3) / 4);
       }
       if (dir == 0) hp.pg_mid[p] = (int)hp.pg_ent.size();
