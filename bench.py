@@ -216,6 +216,11 @@ def path_record(plan, dt, stage_ms, mixed, names, workload):
     }
 
 
+def progress(msg):
+    """One line on stderr as each part of the run ends."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def periodic_record(exx, torch, steps, backward_steps=1):
     """The periodic 1024-water box (3072 atoms, 24576 basis, r_cut 8 A): FP64 and
     mixed K builds per second (the pattern-folded real-space X), stage times,
@@ -229,6 +234,7 @@ def periodic_record(exx, torch, steps, backward_steps=1):
     t0 = time.perf_counter()
     plan = exx.Plan.for_system(sysm)
     t_plan = time.perf_counter() - t0
+    progress(f"periodic box: inputs {t_in:.1f} s, plan {t_plan:.1f} s")
     dev = torch.device("cuda:0")
     C, V, D = (torch.from_numpy(a).to(dev) for a in (inp.C, inp.V, inp.D))
     del inp
@@ -241,7 +247,9 @@ def periodic_record(exx, torch, steps, backward_steps=1):
            "atoms": sysm.n_atoms, "pairs": int(plan.info["n_pairs"]), "input_generation_s": t_in,
            "plan_create_s": t_plan, "algorithmic_gflop_per_build": plan.flops() / 1e9,
            "workspace_gb": plan.info["workspace_bytes"] / 1e9}
+    progress("periodic box: autotuned")
     dt, st = time_builds(plan, C, V, D, K, Ex, exx.PREC_FP64, steps, 1, stream)
+    progress(f"periodic box: FP64 {1e3 * dt:.1f} ms per build")
     K64, E64 = K.clone(), float(Ex.item())
     rec["fp64"] = {"ms_per_build": 1e3 * dt, "builds_per_s": 1.0 / dt,
                    "tflops": plan.flops() / dt / 1e12, "frac_fp64_peak": plan.flops() / dt / PEAK["fp64"],
@@ -253,6 +261,7 @@ def periodic_record(exx, torch, steps, backward_steps=1):
                     "max_abs_dK_vs_fp64": float((K - K64).abs().max().item()),
                     "dE_x_per_atom_vs_fp64": abs(float(Ex.item()) - E64) / sysm.n_atoms}
     rec["mixed"]["within_bar"] = rec["mixed"]["max_abs_dK_vs_fp64"] <= 1e-5 and rec["mixed"]["dE_x_per_atom_vs_fp64"] <= 1e-6
+    progress(f"periodic box: mixed {1e3 * dt:.1f} ms per build")
     rec["E_x_per_atom"] = E64 / sysm.n_atoms
     if backward_steps > 0:
         dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D)
@@ -268,6 +277,7 @@ def periodic_record(exx, torch, steps, backward_steps=1):
                 plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
             torch.cuda.synchronize()
             tb = (time.perf_counter() - t0) / backward_steps
+            progress(f"periodic box: {name} forward + backward {1e3 * tb:.1f} ms")
             fb[name] = {"workload": f"{name} forward E_x; FP64 backward: dE/dC, dE/dV, dE/dD, forces",
                         "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
                         "net_force_max": float(F.view(-1, 3).sum(0).abs().max().item()),
@@ -332,10 +342,13 @@ def main():
     stream = torch.cuda.current_stream()
     names = exx._lib.STAGE_NAMES
 
+    progress(f"{wname}: plan and inputs ready")
     if not args.no_autotune:
         plan.autotune(C, V, D, K, stream=stream.cuda_stream)
+        progress("autotuned")
     tuning = plan.tuning()
     dt64, st64 = time_builds(plan, C, V, D, K, Ex, exx.PREC_FP64, args.steps, args.warmup, stream)
+    progress(f"FP64 {1e3 * dt64:.2f} ms per build")
     K64, E64 = K.clone(), float(Ex[0].item())
     rec64 = path_record(plan, dt64, st64, False, names, args.workload)
     recm = None
@@ -343,6 +356,7 @@ def main():
         plan.set_mixed_split(args.mixed_split)
         dtm, stm = time_builds(plan, C, V, D, K, Ex, exx.PREC_MIXED, args.steps, args.warmup, stream)
         recm = path_record(plan, dtm, stm, True, names, args.workload)
+        progress(f"mixed {1e3 * dtm:.2f} ms per build")
         Em = float(Ex[0].item())
         recm["mixed_split_A"] = args.mixed_split
         recm["error_vs_fp64_gpu"] = {

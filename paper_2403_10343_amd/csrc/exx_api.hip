@@ -514,8 +514,8 @@ static int upload_plan(exx_plan_s* pl) {
   UP(nbr_ptr); UP(nbr_atom); UP(nbr_pair); UP(nbr_lcol); UP(nbr_owner);
   UP(pair_a); UP(pair_b); UP(c_off); UP(v_off); UP(n_loc); UP(m_loc);
   UP(map_off); UP(col1g_off); UP(col2g_off); UP(map1); UP(map2); UP(col1g); UP(col2g);
-  UP(t_off); UP(ct_run_ptr); UP(ct_klen); UP(runs);
-  UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos);
+  UP(t_off); UP(ct_run_ptr); UP(ct_klen); UP(runs); UP(ct_kflag); UP(ct_kflag_off);
+  UP(gd_run_ptr); UP(gd_klen); UP(gd_runs); UP(pos); UP(gd_kflag); UP(gd_kflag_off);
   UP(grp_first); UP(grp_unit_ptr); UP(grp_col_ptr); UP(grp_cols); UP(grp_units);
   UP(gq); UP(gx); UP(en_sys); UP(en_pbeg); UP(en_pend);
   UP(pimg); UP(col2img); UP(col1img); UP(atom_of_col); UP(grp_colimg); UP(grp_cmap); UP(t2col_off); UP(t2col);
@@ -855,13 +855,15 @@ int exx_plan_stage_times(exx_plan plan, double* ms, int64_t* n_builds) {
 static RowD rowd_E(exx_plan plan) {
   DevPlan& d = plan->d;
   return RowD{d.T, d.t_off, d.n_loc, d.E, d.e_off, d.m_loc, d.col2g, d.col2g_off,
-              d.e_items, d.ct_run_ptr, d.ct_klen, d.runs, plan->hp.periodic ? d.col2img : nullptr};
+              d.e_items, d.ct_run_ptr, d.ct_klen, d.runs, plan->hp.periodic ? d.col2img : nullptr,
+              d.ct_kflag, d.ct_kflag_off};
 }
 
 static RowD rowd_GD(exx_plan plan) {
   DevPlan& d = plan->d;
   return RowD{d.H, d.h_off, d.m_loc, d.GD, d.t_off, d.n_loc, d.col1g, d.col1g_off,
-              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs, plan->hp.periodic ? d.col1img : nullptr};
+              d.gd_items, d.gd_run_ptr, d.gd_klen, d.gd_runs, plan->hp.periodic ? d.col1img : nullptr,
+              d.gd_kflag, d.gd_kflag_off};
 }
 
 static const ChunkDev& cur_chunk(exx_plan plan) { return plan->chunks[plan->cur]; }

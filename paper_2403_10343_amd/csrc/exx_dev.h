@@ -101,9 +101,13 @@ struct DevPlan {
   int64_t *t_off, *e_off, *h_off;   // offsets of T_P, E_P and H'_P (those of the current chunk)
   EItem* e_items;
   int *ct_run_ptr, *ct_klen;
+  uint8_t* ct_kflag;
+  int64_t* ct_kflag_off;
   Run* runs;
   EItem* gd_items;
   int *gd_run_ptr, *gd_klen;
+  uint8_t* gd_kflag;
+  int64_t* gd_kflag_off;
   Run* gd_runs;
   double* pos;
   int *grp_first, *grp_unit_ptr, *grp_col_ptr, *grp_cols;
@@ -269,6 +273,10 @@ struct RowD {
   // between a k-row atom J at image m (that of its run) and the column's atom L at image b
   // is used only if n_JL = b - m (everything else is beyond the cutoff)
   const int* ocolimg;
+  // per column tile: one byte per 16 k rows, bit q set unless D is structurally zero on
+  // those rows and tile columns 16q.. (the MFMAs of an all-zero block are skipped)
+  const uint8_t* kflag;
+  const int64_t* kflag_off;
 };
 
 // Batched GEMM: 64 x 64 output tile per workgroup of four wavefronts (32 x 32

@@ -142,9 +142,13 @@ struct HostPlan {
   // task lists
   std::vector<EItem> e_items;
   std::vector<int> ct_run_ptr, ct_klen;
+  std::vector<uint8_t> ct_kflag;                    // per E column tile and 16 k rows: bit q set if the 16 columns
+  std::vector<int64_t> ct_kflag_off;                // 16q.. of D are not all structurally zero there
   std::vector<Run> runs;
   std::vector<EItem> gd_items;                       // G_P = H_P D (backward)
   std::vector<int> gd_run_ptr, gd_klen;
+  std::vector<uint8_t> gd_kflag;                    // the same for the gradient product
+  std::vector<int64_t> gd_kflag_off;
   std::vector<Run> gd_runs;
   std::vector<int> grp_first, grp_unit_ptr, grp_col_ptr, grp_cols;
   std::vector<Unit> grp_units;
@@ -200,6 +204,15 @@ int derive_lists(HostPlan& hp, std::string& err);
 
 // Periodic plans: the same lists with image-labelled entries (after the
 // neighbour lists with their images; see exx_plan_periodic.cpp).
+// Structural zero blocks of one E (or gradient-product) column tile: krow lists the k-side
+// entries in k order (atom, image code, first k, length), ccol the output entries (atom,
+// image, first column inside the tile, length).  Appends ceil(klen / 16) bytes to out:
+// bit q of byte g is set if D has a structurally nonzero element in k rows 16g.. and tile
+// columns 16q.. (D_JL with L in N[J], at the matching image for periodic plans).
+struct KEnt { int atom, img, beg, len; };
+void tile_kflags(const HostPlan& hp, const std::vector<KEnt>& krow, const std::vector<KEnt>& ccol, int klen,
+                 std::vector<uint8_t>& out);
+int64_t kflag_issued(const uint8_t* f, int klen, int sP);
 int derive_lists_periodic(HostPlan& hp, std::string& err);
 
 // Host version of the periodic screening (the device builder's arithmetic):

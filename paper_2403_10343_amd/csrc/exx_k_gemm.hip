@@ -112,19 +112,30 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
   sstore(0);
   __syncthreads();
   int buf = 0;
+  const uint8_t* kf = r.kflag + r.kflag_off[it.ct];
+  const int q0 = wn >> 4;   // this wavefront's column quarters q0, q0 + 1
+  // and its two 16-row blocks: skipped where they lie past s_P (uniform per wavefront)
+  const bool rv0 = it.r0 + wm < sP, rv1 = it.r0 + wm + 16 < sP;
   for (int k0 = 0; k0 < klen; k0 += EK) {
     const bool more = k0 + EK < klen;
     if (more) gload(k0 + EK);
 #pragma unroll
     for (int ks = 0; ks < EK; ks += 4) {
+      // skip the products of 16 x 16 blocks where D is structurally zero (uniform per wavefront)
+      const int f = (k0 + ks < klen) ? (kf[(k0 + ks) >> 4] >> q0) : 0;
       const double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
 #pragma unroll
       for (int sp = 0; sp < NSP; ++sp) {
-        const double b0 = Bs[sp][buf][ks + lk][wn + lr], b1 = Bs[sp][buf][ks + lk][wn + 16 + lr];
-        acc[sp][0][0] = mfma64(a0, b0, acc[sp][0][0]);
-        acc[sp][0][1] = mfma64(a0, b1, acc[sp][0][1]);
-        acc[sp][1][0] = mfma64(a1, b0, acc[sp][1][0]);
-        acc[sp][1][1] = mfma64(a1, b1, acc[sp][1][1]);
+        if (f & 1) {
+          const double b0 = Bs[sp][buf][ks + lk][wn + lr];
+          if (rv0) acc[sp][0][0] = mfma64(a0, b0, acc[sp][0][0]);
+          if (rv1) acc[sp][1][0] = mfma64(a1, b0, acc[sp][1][0]);
+        }
+        if (f & 2) {
+          const double b1 = Bs[sp][buf][ks + lk][wn + 16 + lr];
+          if (rv0) acc[sp][0][1] = mfma64(a0, b1, acc[sp][0][1]);
+          if (rv1) acc[sp][1][1] = mfma64(a1, b1, acc[sp][1][1]);
+        }
       }
     }
     if (more) {
@@ -420,8 +431,8 @@ __global__ __launch_bounds__(256) void k_pgather(double* __restrict__ K, DevPlan
 // an entry adds, over the s_P rows r of P, R[r][row column]^T C[r][column column] with
 // (R, C) = (T_P, H'_P) for part 0 (X'_AB) and (H'_P, T_P) for part 1 (the transpose of
 // X'_BA), so the sum is X'_AB + X'_BA^T for every atom pair of the tile.  Each k-round
-// issues the loads of four k-steps together; the four wavefront partials are added in a
-// fixed order.  Then K_AB += (X'_AB + X'_BA^T) / 2 on the tile's pattern pairs (upper
+// covers four k-steps, whose loads are issued one round ahead (across entries too); the
+// four wavefront partials are added in a fixed order.  Then K_AB += (X'_AB + X'_BA^T) / 2 on the tile's pattern pairs (upper
 // triangle of a diagonal tile), mirrored to K_BA.
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_ptile(double* __restrict__ K, DevPlan d, const PTile* __restrict__ tiles,
@@ -458,54 +469,90 @@ __global__ __launch_bounds__(256) void k_ptile(double* __restrict__ K, DevPlan d
   for (int t = 0; t < TA; ++t)
 #pragma unroll
     for (int u = 0; u < TB; ++u) acc[t][u] = d4{0, 0, 0, 0};
-  for (int e = tl.e_beg + wv; e < tl.e_end; e += 4) {
-    const PTEnt pe = d.pt_ent[e];
-    const int P = pe.P;
-    const int sP = d.na[P] * d.nb[P], nP = d.n_loc[P], mP = d.m_loc[P];
-    const double* Tm = d.T + d.t_off[P];
-    const double* Hm = d.H + d.h_off[P];
-    const double* Rm = pe.part ? Hm : Tm;
-    const double* Cm = pe.part ? Tm : Hm;
-    const int rp = pe.part ? mP : nP, cp = pe.part ? nP : mP;
+  // The rounds (16 rows of P) of this wavefront's entries in one stream: the loads of the
+  // next round are issued before the MFMAs of the current one.
+  struct Src {
+    const double *R, *C;
+    int rp, cp, sP, r0;
     int rcol[TA], ccol[TB];
     bool rok[TA], cok[TB];
+  } ls;
+  int e = tl.e_beg + wv;
+  auto setup = [&](int ei) {
+    const PTEnt pe = d.pt_ent[ei];
+    const int P = pe.P;
+    const int nP = d.n_loc[P], mP = d.m_loc[P];
+    const double* Tm = d.T + d.t_off[P];
+    const double* Hm = d.H + d.h_off[P];
+    ls.R = pe.part ? Hm : Tm;
+    ls.C = pe.part ? Tm : Hm;
+    ls.rp = pe.part ? mP : nP;
+    ls.cp = pe.part ? nP : mP;
+    ls.sP = d.na[P] * d.nb[P];
+    ls.r0 = 0;
 #pragma unroll
     for (int t = 0; t < TA; ++t) {
       const int c = rs[t] >= 0 ? pe.rc[rs[t]] : -1;
-      rok[t] = c >= 0;
-      rcol[t] = rok[t] ? c + rx[t] : 0;
+      ls.rok[t] = c >= 0;
+      ls.rcol[t] = ls.rok[t] ? c + rx[t] : 0;
     }
 #pragma unroll
     for (int t = 0; t < TB; ++t) {
       const int c = cs[t] >= 0 ? pe.cc[cs[t]] : -1;
-      cok[t] = c >= 0;
-      ccol[t] = cok[t] ? c + cx[t] : 0;
+      ls.cok[t] = c >= 0;
+      ls.ccol[t] = ls.cok[t] ? c + cx[t] : 0;
     }
-    for (int r0 = 0; r0 < sP; r0 += 16) {
-      double a[4][TA], b[4][TB];
+  };
+  // loads one round of the entry in ls, then moves ls to the next round (or entry)
+  auto load = [&](double (&a)[4][TA], double (&b)[4][TB]) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = r0 + 4 * u + lk;
-        const bool ok = r < sP;
+    for (int u = 0; u < 4; ++u) {
+      const int r = ls.r0 + 4 * u + lk;
+      const bool ok = r < ls.sP;
 #pragma unroll
-        for (int t = 0; t < TA; ++t) {
-          const bool v = ok && rok[t];
-          const double x = Rm[v ? (size_t)r * rp + rcol[t] : 0];
-          a[u][t] = v ? x : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-          const bool v = ok && cok[t];
-          const double x = Cm[v ? (size_t)r * cp + ccol[t] : 0];
-          b[u][t] = v ? x : 0.0;
-        }
+      for (int t = 0; t < TA; ++t) {
+        const bool v = ok && ls.rok[t];
+        const double x = ls.R[v ? (size_t)r * ls.rp + ls.rcol[t] : 0];
+        a[u][t] = v ? x : 0.0;
       }
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        const bool v = ok && ls.cok[t];
+        const double x = ls.C[v ? (size_t)r * ls.cp + ls.ccol[t] : 0];
+        b[u][t] = v ? x : 0.0;
+      }
+    }
+    ls.r0 += 16;
+    if (ls.r0 >= ls.sP) {
+      e += 4;
+      if (e < tl.e_end) setup(e);
+    }
+  };
+  if (e < tl.e_end) {
+    setup(e);
+    double a[4][TA], b[4][TB];
+    load(a, b);
+    bool valid = true;
+    while (valid) {
+      const bool nvalid = e < tl.e_end;
+      double an[4][TA], bn[4][TB];
+      if (nvalid) load(an, bn);
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int t = 0; t < TA; ++t)
 #pragma unroll
           for (int v = 0; v < TB; ++v) acc[t][v] = mfma64(a[u][t], b[u][v], acc[t][v]);
+      if (nvalid) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int t = 0; t < TA; ++t) a[u][t] = an[u][t];
+#pragma unroll
+          for (int t = 0; t < TB; ++t) b[u][t] = bn[u][t];
+        }
+      }
+      valid = nvalid;
     }
   }
 #pragma unroll

@@ -123,7 +123,7 @@ __device__ __forceinline__ void h_q(typename Mf<R>::acc (&Hc)[NSP][U][H_CPW], co
 // formed once); H'^0 goes to d.H, H'^1 to hl.H1.  Four wavefronts per SIMD for one density
 // matrix (at most 128 VGPRs: measured faster than three with 168 since the V and D operands
 // are coalesced rows), two for two (their accumulators double).
-template <int U, typename R, int NSP>
+template <int U, typename R, int NSP, bool WIDE>
 __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NSP == 1 ? 4 : 2))) void k_H(
     const double* __restrict__ V, const double* __restrict__ D, DevPlan d, HLists hl, int n_tiles,
     int n_padded, double gscale, int mode) {
@@ -204,7 +204,9 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
       switch (h_class(nsQ, nlQ)) {
         case 0: h_q<4, 2, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
         case 1: h_q<10, 4, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
-        default: h_q<16, 4, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1); break;
+        default:   // more than 40 aux functions on Q: plans with such a species only
+          if constexpr (WIDE) h_q<16, 4, U, NSP, R>(Hc, sT, un, nU, qm_p[ei], Q, aQ, bQ, qm_lc[ei], ncols, c0, lr, lk, d, hl.Dr1);
+          break;
       }
       __syncthreads();
     }
@@ -299,12 +301,13 @@ void launch_H_lists(exx_plan plan, const double* V, const double* D, const HList
   const int np_ = (n + 7) / 8 * 8;
   const size_t lds = mode == H_G_ADD ? 0 : (sizeof(R) == sizeof(double) ? plan->h_lds : plan->h_lds32);
   const dim3 grid(np_), blk(64 * H_WAVES);
-  if (hp.h_waves <= 2)
-    hipLaunchKernelGGL((k_H<2, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
-  else if (hp.h_waves <= 5)
-    hipLaunchKernelGGL((k_H<5, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
-  else
-    hipLaunchKernelGGL((k_H<8, R, NSP>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode);
+  // the widest shape class (chains of 16 aux steps) is compiled in only where a species needs it
+  const bool wide = *std::max_element(hp.na.begin(), hp.na.end()) > 40;
+#define KH(UU, W) hipLaunchKernelGGL((k_H<UU, R, NSP, W>), grid, blk, lds, st, V, D, plan->d, hl, n, np_, gscale, mode)
+  if (hp.h_waves <= 2) { if (wide) KH(2, true); else KH(2, false); }
+  else if (hp.h_waves <= 5) { if (wide) KH(5, true); else KH(5, false); }
+  else { if (wide) KH(8, true); else KH(8, false); }
+#undef KH
 }
 template void launch_H_lists<double, 1>(exx_plan, const double*, const double*, const HLists&, int, double, int,
                                         hipStream_t);

@@ -137,6 +137,39 @@ int64_t ceil_to(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace
 
+void tile_kflags(const HostPlan& hp, const std::vector<KEnt>& krow, const std::vector<KEnt>& ccol, int klen,
+                 std::vector<uint8_t>& out) {
+  const size_t base = out.size();
+  out.resize(base + (klen + 15) / 16, 0);
+  const int NA = hp.n_atoms;
+  for (const KEnt& r : krow) {
+    const int* nb0 = hp.nbr_atom.data() + hp.nbr_ptr[r.atom];
+    const int* nb1 = hp.nbr_atom.data() + hp.nbr_ptr[r.atom + 1];
+    for (const KEnt& c : ccol) {
+      bool rel;
+      if (hp.periodic) {
+        const int n = hp.pimg[(size_t)r.atom * NA + c.atom];
+        rel = n >= 0 && img_add(n, r.img) == c.img;
+      } else {
+        rel = std::binary_search(nb0, nb1, c.atom);
+      }
+      if (!rel) continue;
+      int bits = 0;
+      for (int q = c.beg / 16; q <= (c.beg + c.len - 1) / 16; ++q) bits |= 1 << q;
+      for (int g = r.beg / 16; g <= (r.beg + r.len - 1) / 16; ++g) out[base + g] |= (uint8_t)bits;
+    }
+  }
+}
+
+// issued MFMA flops of the E (or gradient) GEMM on one column tile with flags f
+// (ceil(klen / 16) bytes) over an output of s_P rows: 16 x 16 x 16 blocks, skipped where D
+// is structurally zero or the 16 rows lie past s_P
+int64_t kflag_issued(const uint8_t* f, int klen, int sP) {
+  int64_t n = 0;
+  for (int g = 0; g < (klen + 15) / 16; ++g) n += __builtin_popcount(f[g]);
+  return n * ((sP + 15) / 16) * 2LL * 16 * 16 * 16;
+}
+
 int derive_lists(HostPlan& hp, std::string& err) {
   const int NA = hp.n_atoms;
   const auto& np = hp.nbr_ptr;
@@ -261,11 +294,15 @@ int derive_lists(HostPlan& hp, std::string& err) {
   int stampv = 0;
   std::vector<int> stamp2(NA, -1);
   auto rowd_lists = [&](bool grad, std::vector<EItem>& items, std::vector<int>& run_ptr,
-                        std::vector<int>& klens, std::vector<Run>& runs, int64_t& issued) {
+                        std::vector<int>& klens, std::vector<Run>& runs, std::vector<uint8_t>& kflag,
+                        std::vector<int64_t>& kflag_off, int64_t& issued) {
     items.clear();
     run_ptr.assign(1, 0);
     klens.clear();
     runs.clear();
+    kflag.clear();
+    kflag_off.assign(1, 0);
+    std::vector<KEnt> krow, ccol;
     for (int a = 0; a < NA; ++a) {
       const int sP = hp.na[a] * hp.nb[a];
       // input atoms (k side) and output atoms (column side) with local offsets
@@ -278,9 +315,15 @@ int derive_lists(HostPlan& hp, std::string& err) {
         ++stampv;
         const int c1 = std::min(mOut, c0 + E_TILE);
         int c = 0;
+        ccol.clear();
+        krow.clear();
         for (int k = 0; k < n_out; ++k) {
           const int l = out_b[k];
-          if (c < c1 && c + hp.nb[l] > c0) stamp2[l] = stampv;
+          if (c < c1 && c + hp.nb[l] > c0) {
+            stamp2[l] = stampv;
+            const int b0 = std::max(c, c0), b1 = std::min(c + hp.nb[l], c1);
+            ccol.push_back(KEnt{l, 0, b0 - c0, b1 - b0});
+          }
           c += hp.nb[l];
           if (c >= c1) break;
         }
@@ -299,6 +342,7 @@ int derive_lists(HostPlan& hp, std::string& err) {
               cur = Run{lcol, hp.bo[j], hp.nb[j], 0};
             }
             prevJ = j;
+            krow.push_back(KEnt{j, 0, klen, hp.nb[j]});
             klen += hp.nb[j];
           } else {
             prevJ = -2;
@@ -308,10 +352,10 @@ int derive_lists(HostPlan& hp, std::string& err) {
         if (cur.len > 0) runs.push_back(cur);
         run_ptr.push_back((int)runs.size());
         klens.push_back(klen);
-        for (int r0 = 0; r0 < sP; r0 += E_TILE) {
-          items.push_back(EItem{a, r0, c0, ct});
-          issued += 2LL * E_TILE * E_TILE * ceil_to(klen, 16);
-        }
+        tile_kflags(hp, krow, ccol, klen, kflag);
+        kflag_off.push_back((int64_t)kflag.size());
+        issued += kflag_issued(kflag.data() + kflag_off[ct], klen, sP);
+        for (int r0 = 0; r0 < sP; r0 += E_TILE) items.push_back(EItem{a, r0, c0, ct});
       }
     }
   };
@@ -326,9 +370,9 @@ int derive_lists(HostPlan& hp, std::string& err) {
     }
     hp.flops[1] += 2 * (int64_t)sP * kk;
   }
-  rowd_lists(false, hp.e_items, hp.ct_run_ptr, hp.ct_klen, hp.runs, hp.issued[1]);
+  rowd_lists(false, hp.e_items, hp.ct_run_ptr, hp.ct_klen, hp.runs, hp.ct_kflag, hp.ct_kflag_off, hp.issued[1]);
   int64_t gd_issued = 0;
-  rowd_lists(true, hp.gd_items, hp.gd_run_ptr, hp.gd_klen, hp.gd_runs, gd_issued);
+  rowd_lists(true, hp.gd_items, hp.gd_run_ptr, hp.gd_klen, hp.gd_runs, hp.gd_kflag, hp.gd_kflag_off, gd_issued);
   // ---- H tasks: atom groups (runs of consecutive, nearby atoms of one
   // system; one wavefront per 16-wide aux tile of each atom) x 16-wide tiles
   // of the group's second-neighbourhood columns.  Q-lists (V (x) D part) and

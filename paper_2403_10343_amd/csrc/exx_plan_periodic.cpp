@@ -235,6 +235,11 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
   hp.gd_run_ptr.assign(1, 0);
   hp.gd_klen.clear();
   hp.gd_runs.clear();
+  hp.ct_kflag.clear();
+  hp.ct_kflag_off.assign(1, 0);
+  hp.gd_kflag.clear();
+  hp.gd_kflag_off.assign(1, 0);
+  std::vector<KEnt> krow, ccol;
   {
     // an entry (J, m) of N[P] is relevant to a tile column (L, b) if J lies in N[L] at
     // image b + n_LJ = m: mark those J per tile
@@ -249,8 +254,14 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         const int c1 = std::min(mOut, c0 + E_TILE);
         ++stamp;
         while (kstart < e1 && cstart + hp.nb[hp.n2_atom[kstart]] <= c0) { cstart += hp.nb[hp.n2_atom[kstart]]; ++kstart; }
+        ccol.clear();
+        krow.clear();
         for (int k = kstart, c = cstart; k < e1 && c < c1; c += hp.nb[hp.n2_atom[k]], ++k) {
           const int l = hp.n2_atom[k], b = hp.n2_img[k];
+          {
+            const int b0 = std::max(c, c0), b1 = std::min(c + hp.nb[l], c1);
+            ccol.push_back(KEnt{l, b, b0 - c0, b1 - b0});
+          }
           for (int k2 = np[l]; k2 < np[l + 1]; ++k2) {
             const int j = nat[k2];
             if (hp.pimg[(size_t)a * NA + j] == img_add(b, nim[k2])) mark[j] = stamp;
@@ -270,6 +281,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
             }
             prevJ = j;
             prevImg = nim[k];
+            krow.push_back(KEnt{j, nim[k], klen, hp.nb[j]});
             klen += hp.nb[j];
           } else {
             prevJ = -2;
@@ -279,10 +291,10 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         if (cur.len > 0) hp.runs.push_back(cur);
         hp.ct_run_ptr.push_back((int)hp.runs.size());
         hp.ct_klen.push_back(klen);
-        for (int r0 = 0; r0 < sP; r0 += E_TILE) {
-          hp.e_items.push_back(EItem{a, r0, c0, ct});
-          hp.issued[1] += 2LL * E_TILE * E_TILE * ceil_to(klen, 16);
-        }
+        tile_kflags(hp, krow, ccol, klen, hp.ct_kflag);
+        hp.ct_kflag_off.push_back((int64_t)hp.ct_kflag.size());
+        hp.issued[1] += kflag_issued(hp.ct_kflag.data() + hp.ct_kflag_off[ct], klen, sP);
+        for (int r0 = 0; r0 < sP; r0 += E_TILE) hp.e_items.push_back(EItem{a, r0, c0, ct});
       }
     }
   }
@@ -301,8 +313,14 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         const int c1 = std::min(nOut, c0 + E_TILE);
         ++stamp;
         while (kstart < np[a + 1] && cstart + hp.nb[nat[kstart]] <= c0) { cstart += hp.nb[nat[kstart]]; ++kstart; }
+        ccol.clear();
+        krow.clear();
         for (int k = kstart, c = cstart; k < np[a + 1] && c < c1; c += hp.nb[nat[k]], ++k) {
           const int j = nat[k], m = nim[k];
+          {
+            const int b0 = std::max(c, c0), b1 = std::min(c + hp.nb[j], c1);
+            ccol.push_back(KEnt{j, m, b0 - c0, b1 - b0});
+          }
           for (int k2 = np[j]; k2 < np[j + 1]; ++k2) {
             const int l = nat[k2], b = img_add(m, nim[k2]);   // L = nat[k2] at image m + n_JL
             for (int e = n2first[(size_t)a * NA + l]; e >= 0 && e < hp.n2_ptr[a + 1] && hp.n2_atom[e] == l; ++e)
@@ -323,6 +341,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
             }
             prevL = l;
             prevImg = b;
+            krow.push_back(KEnt{l, b, klen, hp.nb[l]});
             klen += hp.nb[l];
           } else {
             prevL = -2;
@@ -332,6 +351,8 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         if (cur.len > 0) hp.gd_runs.push_back(cur);
         hp.gd_run_ptr.push_back((int)hp.gd_runs.size());
         hp.gd_klen.push_back(klen);
+        tile_kflags(hp, krow, ccol, klen, hp.gd_kflag);
+        hp.gd_kflag_off.push_back((int64_t)hp.gd_kflag.size());
         for (int r0 = 0; r0 < sP; r0 += E_TILE) {
           hp.gd_items.push_back(EItem{a, r0, c0, ct});
           gd_issued += 2LL * E_TILE * E_TILE * ceil_to(klen, 16);
