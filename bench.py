@@ -29,15 +29,15 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # HBM bytes per dispatch, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
 # this script on the 768-atom box, scaled by what the counters read for kernels
-# of known traffic in the same runs (k_repack reads C once: read x1.94; k_zero
-# writes K once: write x1.00).  They describe the
+# of known traffic in the same runs (k_repack reads C once: read x1.939; k_zero
+# writes K once: write x1.000).  They describe the
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "c7fd1bd8d5a74a5d",
+    "sources": "a7777b0fbd552f8b",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 30.028e9 + 5.239e9, ("fp64", "T2"): 35.684e9 + 0.025e9,
-              ("fp64", "final"): 10.250e9 + 4.280e9, ("fp64", "E"): 2.756e9 + 2.476e9},
+    "bytes": {("fp64", "H"): 29.270e9 + 4.210e9, ("fp64", "T2"): 35.991e9 + 0.025e9,
+              ("fp64", "final"): 10.246e9 + 4.280e9, ("fp64", "E"): 2.770e9 + 2.477e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>", "H32": "k_H<U, float, 1>",
                    "T2": "k_T2<NT, NS, double, COLS, WAVES, 1>", "T2_32": "k_T2<NT, NS, float, COLS, WAVES, 1>",
