@@ -513,7 +513,8 @@ int derive_lists(HostPlan& hp, std::string& err) {
     hp.t2col_off[p + 1] = (int64_t)hp.t2col.size();
   }
   // shape classes: aux tiles of 16 of the row atom, nu steps of 4 (rounded up
-  // to a compiled size) of the column atom; stable sort keeps pair order inside
+  // to a compiled size) of the column atom; inside a class the items of one column atom Q
+  // are consecutive, so the workgroups of one XCD (consecutive items) share T_Q in its L2
   {
     auto ns_class = [](int ns) { return ns <= 4 ? 4 : ns <= 8 ? 8 : ns <= 10 ? 10 : ns <= 12 ? 12 : 16; };
     auto key = [&](int item) {
@@ -522,7 +523,10 @@ int derive_lists(HostPlan& hp, std::string& err) {
       const int a = flip ? hp.pair_b[p] : hp.pair_a[p], b = flip ? hp.pair_a[p] : hp.pair_b[p];
       return ((hp.na[a] + 15) / 16) * 64 + ns_class((hp.na[b] + 3) / 4);
     };
-    std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    auto col_atom = [&](int item) { return (item & 1) ? hp.pair_a[item >> 1] : hp.pair_b[item >> 1]; };
+    std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) {
+      return key(x) != key(y) ? key(x) < key(y) : col_atom(x) < col_atom(y);
+    });
     hp.t2_classes.clear();
     for (int i = 0; i < (int)hp.t2_items.size(); ++i) {
       const int k = key(hp.t2_items[i]);
@@ -540,7 +544,10 @@ int derive_lists(HostPlan& hp, std::string& err) {
     };
     hp.dv_items.resize(npairs);
     for (int64_t p = 0; p < npairs; ++p) hp.dv_items[p] = (int)p;
-    std::stable_sort(hp.dv_items.begin(), hp.dv_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    // pairs of one second atom Q consecutive inside a class (T_Q shared in an XCD's L2)
+    std::stable_sort(hp.dv_items.begin(), hp.dv_items.end(), [&](int x, int y) {
+      return key(x) != key(y) ? key(x) < key(y) : hp.pair_b[x] < hp.pair_b[y];
+    });
     hp.dv_classes.clear();
     for (int i = 0; i < (int)hp.dv_items.size(); ++i) {
       const int k = key(hp.dv_items[i]);

@@ -550,7 +550,11 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
       const int x = flip ? hp.pair_b[p] : hp.pair_a[p], y = flip ? hp.pair_a[p] : hp.pair_b[p];
       return ((hp.na[x] + 15) / 16) * 64 + ns_class((hp.na[y] + 3) / 4);
     };
-    std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    // items of one column atom consecutive inside a class (T_Q shared in an XCD's L2)
+    auto col_atom = [&](int item) { return (item & 1) ? hp.pair_a[item >> 1] : hp.pair_b[item >> 1]; };
+    std::stable_sort(hp.t2_items.begin(), hp.t2_items.end(), [&](int x, int y) {
+      return key(x) != key(y) ? key(x) < key(y) : col_atom(x) < col_atom(y);
+    });
     hp.t2_classes.clear();
     for (int i = 0; i < (int)hp.t2_items.size(); ++i) {
       const int k = key(hp.t2_items[i]);
@@ -568,7 +572,10 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
     };
     hp.dv_items.resize(npairs);
     for (int64_t p = 0; p < npairs; ++p) hp.dv_items[p] = (int)p;
-    std::stable_sort(hp.dv_items.begin(), hp.dv_items.end(), [&](int x, int y) { return key(x) < key(y); });
+    // pairs of one second atom Q consecutive inside a class (T_Q shared in an XCD's L2)
+    std::stable_sort(hp.dv_items.begin(), hp.dv_items.end(), [&](int x, int y) {
+      return key(x) != key(y) ? key(x) < key(y) : hp.pair_b[x] < hp.pair_b[y];
+    });
     hp.dv_classes.clear();
     for (int i = 0; i < (int)hp.dv_items.size(); ++i) {
       const int k = key(hp.dv_items[i]);
