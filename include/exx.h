@@ -55,11 +55,11 @@
  * B at n_AB), and E_x = -1/4 sum over those blocks of X o D is the exchange
  * energy per cell.  exx_pair_images() returns n_AB.  Periodic plans take
  * build_K (every precision), graphs, the autotuner, the energy entry points
- * and exchange_backward (gradients per stored entry of the home-cell blocks:
+ * exchange_backward (gradients per stored entry of the home-cell blocks:
  * E_x per cell differentiated with every image of a block moving with it;
- * forces use the image separation x_A - (x_B + n_AB.L)); spin and two-kernel
- * calls return EXX_EUNSUPPORTED, and so does a workspace budget that would
- * need chunks.
+ * forces use the image separation x_A - (x_B + n_AB.L)), build_K_spin and
+ * build_K_two_kernels (each result on the same pattern); a workspace budget
+ * that would need chunks returns EXX_EUNSUPPORTED.
  *
  * Ownership: the caller owns every device array passed in; the plan owns its
  * bookkeeping lists and workspace.  Output arrays are fully overwritten

@@ -1090,7 +1090,6 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
   if (n_chunks(plan) > 1)
     return fail(EXX_EUNSUPPORTED, "build_K_spin: needs an unbounded workspace (the plan is chunked)");
-  if (plan->hp.periodic) return fail(EXX_EUNSUPPORTED, "build_K_spin: not implemented for periodic plans");
   const HostPlan& hp = plan->hp;
   const int64_t ds = hp.d_size;
   {
@@ -1155,7 +1154,6 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_two_kernels: unknown precision");
   if (n_chunks(plan) > 1)
     return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: needs an unbounded workspace (the plan is chunked)");
-  if (plan->hp.periodic) return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: not implemented for periodic plans");
   const int rcw = second_workspace(plan);
   if (rcw != EXX_OK) return rcw;
   const HostPlan& hp = plan->hp;

@@ -339,10 +339,11 @@ void launch_rowD_spin(exx_plan plan, const double* D, const double* D1, double* 
                       hipStream_t st) {
   if (n <= 0) return;
   const int nwgp = (n + 7) / 8 * 8;
-  if (plan->tune[TUNE_E] == 1)
-    hipLaunchKernelGGL((k_rowD<32, 2, false>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
-  else
-    hipLaunchKernelGGL((k_rowD<16, 2, false>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1);
+  const bool per = r.ocolimg != nullptr;   // periodic plans: the image check on every D element
+#define RDS(EK, PER) hipLaunchKernelGGL((k_rowD<EK, 2, PER>), dim3(nwgp), dim3(256), 0, st, D, r, plan->d, n, nwgp, D1, O1)
+  if (plan->tune[TUNE_E] == 1) { if (per) RDS(32, true); else RDS(32, false); }
+  else { if (per) RDS(16, true); else RDS(16, false); }
+#undef RDS
 }
 
 // ---------------------------------------------------------------------------

@@ -252,15 +252,63 @@ def test_periodic_gradients_vacuum_and_supercell(exx):
         assert relmax(g2["dV"][l2.v_off[p]:l2.v_off[p + 1]], g1["dV"][l1.v_off[q]:l1.v_off[q + 1]]) < 1e-12
 
 
-def test_periodic_unsupported_calls(exx):
-    sysm = synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4)
+def test_periodic_spin_and_two_kernels(exx):
+    """Collinear spin and two Coulomb matrices on periodic cells: each X^s and X^a
+    against the periodic oracle with D^s or V^a (a skewed 5-atom cell and one ice
+    cell), the spin E_x = -1/2 sum_s <X^s, D^s> and E_x per Coulomb matrix; on a
+    2x2x2-cell box every result bitwise equal to build_K with that D or V."""
+    dev = "cuda:0"
+    for sysm in (_tiny(1), synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4)):
+        inp = synth.make_inputs(sysm)
+        plan = exx.Plan.for_system(sysm)
+        n = int(inp.layout.sys_nbas[0])
+        ds = n * n
+        C, V, D = device_inputs(inp, torch)
+        Ds = synth.spin_densities(inp)
+        K2 = torch.empty(2 * ds, dtype=torch.float64, device=dev)
+        Ex = torch.empty(1, dtype=torch.float64, device=dev)
+        plan.build_K_spin(C, V, torch.from_numpy(Ds.reshape(-1)).to(dev), K2, Ex)
+        torch.cuda.synchronize()
+        Kg = K2.cpu().numpy()
+        Es = 0.0
+        for s in range(2):
+            Xo = O.x_periodic(O.with_density(inp, Ds[s]))
+            print(f"{sysm.name} spin {s}: rel {relmax(Kg[s * ds:(s + 1) * ds].reshape(n, n), Xo):.2e}", flush=True)
+            assert relmax(Kg[s * ds:(s + 1) * ds].reshape(n, n), Xo) < TOL
+            Es += 2.0 * O.periodic_energy(Xo, Ds[s].reshape(n, n))
+        assert abs(float(Ex.item()) - Es) < TOL * abs(Es)
+        V2 = synth.short_range_V(inp)
+        E2 = torch.empty(2, dtype=torch.float64, device=dev)
+        plan.build_K_two_kernels(C, V, torch.from_numpy(V2).to(dev), D, K2, E2)
+        torch.cuda.synchronize()
+        Kg, Eg = K2.cpu().numpy(), E2.cpu().numpy()
+        for a, Va in enumerate((inp.V, V2)):
+            Xo = O.x_periodic(O.with_coulomb(inp, Va))
+            assert relmax(Kg[a * ds:(a + 1) * ds].reshape(n, n), Xo) < TOL
+            Eo = O.periodic_energy(Xo, inp.D.reshape(n, n))
+            assert abs(Eg[a] - Eo) < TOL * abs(Eo)
+    sysm = synth.ice_box_periodic(2, 2, 2, seed=9, r_cut=6.0)
     inp = synth.make_inputs(sysm)
     plan = exx.Plan.for_system(sysm)
+    ds = int(inp.layout.d_size)
     C, V, D = device_inputs(inp, torch)
-    with pytest.raises(exx.ExxError) as e:
-        plan.build_K_spin(C, V, torch.cat([D, D]), torch.empty(2 * D.numel(), dtype=torch.float64, device="cuda:0"))
-    assert e.value.code == -5
-    with pytest.raises(exx.ExxError) as e:
+    Ds = torch.from_numpy(synth.spin_densities(inp).reshape(-1)).to(dev)
+    V2 = torch.from_numpy(synth.short_range_V(inp)).to(dev)
+    K2 = torch.empty(2 * ds, dtype=torch.float64, device=dev)
+    K1 = torch.empty(ds, dtype=torch.float64, device=dev)
+    plan.build_K_spin(C, V, Ds, K2)
+    for s in range(2):
+        plan.build_K(C, V, Ds[s * ds:(s + 1) * ds].contiguous(), K1)
+        assert torch.equal(K1, K2[s * ds:(s + 1) * ds])
+    plan.build_K_two_kernels(C, V, V2, D, K2)
+    for a, Va in enumerate((V, V2)):
+        plan.build_K(C, Va, D, K1)
+        assert torch.equal(K1, K2[a * ds:(a + 1) * ds])
+
+
+def test_periodic_unsupported_calls(exx):
+    sysm = synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4)
+    with pytest.raises(exx.ExxError) as e:   # a workspace budget that would need chunks
         exx.Plan.for_system(sysm, ws_budget_bytes=1 << 20)
     assert e.value.code == -5
     with pytest.raises(exx.ExxError) as e:   # cutoff not below half the cell width
