@@ -34,10 +34,11 @@ CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "a7777b0fbd552f8b",
+    "sources": "6d970a239e1efa49",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 29.270e9 + 4.210e9, ("fp64", "T2"): 35.991e9 + 0.025e9,
-              ("fp64", "final"): 10.246e9 + 4.280e9, ("fp64", "E"): 2.770e9 + 2.477e9},
+    "bytes": {("fp64", "H"): 29.280e9 + 4.210e9, ("fp64", "T2"): 25.231e9 + 0.036e9,
+              ("fp64", "final"): 10.247e9 + 4.281e9, ("fp64", "E"): 2.771e9 + 2.477e9,
+              ("mixed", "H"): 12.353e9 + 3.755e9, ("mixed", "H32"): 25.952e9 + 4.124e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>", "H32": "k_H<U, float, 1>",
                    "T2": "k_T2<NT, NS, double, COLS, WAVES, 1>", "T2_32": "k_T2<NT, NS, float, COLS, WAVES, 1>",
