@@ -142,23 +142,40 @@ void tile_kflags(const HostPlan& hp, const std::vector<KEnt>& krow, const std::v
   const size_t base = out.size();
   out.resize(base + (klen + 15) / 16, 0);
   const int NA = hp.n_atoms;
-  for (const KEnt& r : krow) {
-    const int* nb0 = hp.nbr_atom.data() + hp.nbr_ptr[r.atom];
-    const int* nb1 = hp.nbr_atom.data() + hp.nbr_ptr[r.atom + 1];
-    for (const KEnt& c : ccol) {
-      bool rel;
-      if (hp.periodic) {
+  if (hp.periodic) {
+    for (const KEnt& r : krow) {
+      int bits = 0;   // quarters holding a column at the image of a neighbour of r
+      for (const KEnt& c : ccol) {
         const int n = hp.pimg[(size_t)r.atom * NA + c.atom];
-        rel = n >= 0 && img_add(n, r.img) == c.img;
-      } else {
-        rel = std::binary_search(nb0, nb1, c.atom);
+        if (n >= 0 && img_add(n, r.img) == c.img)
+          for (int q = c.beg / 16; q <= (c.beg + c.len - 1) / 16; ++q) bits |= 1 << q;
       }
-      if (!rel) continue;
-      int bits = 0;
-      for (int q = c.beg / 16; q <= (c.beg + c.len - 1) / 16; ++q) bits |= 1 << q;
-      for (int g = r.beg / 16; g <= (r.beg + r.len - 1) / 16; ++g) out[base + g] |= (uint8_t)bits;
+      if (bits)
+        for (int g = r.beg / 16; g <= (r.beg + r.len - 1) / 16; ++g) out[base + g] |= (uint8_t)bits;
+    }
+    return;
+  }
+  // clusters: D_JL is nonzero for J in N[L]; mark the neighbours of every column atom with
+  // the column's quarter bits, then read them off for the k-side atoms
+  static thread_local std::vector<uint8_t> qbits;
+  static thread_local std::vector<int> touched;
+  if ((int)qbits.size() < NA) qbits.assign(NA, 0);
+  touched.clear();
+  for (const KEnt& c : ccol) {
+    int bits = 0;
+    for (int q = c.beg / 16; q <= (c.beg + c.len - 1) / 16; ++q) bits |= 1 << q;
+    for (int k = hp.nbr_ptr[c.atom]; k < hp.nbr_ptr[c.atom + 1]; ++k) {
+      const int j = hp.nbr_atom[k];
+      if (!qbits[j]) touched.push_back(j);
+      qbits[j] |= (uint8_t)bits;
     }
   }
+  for (const KEnt& r : krow) {
+    const int bits = qbits[r.atom];
+    if (bits)
+      for (int g = r.beg / 16; g <= (r.beg + r.len - 1) / 16; ++g) out[base + g] |= (uint8_t)bits;
+  }
+  for (int j : touched) qbits[j] = 0;
 }
 
 // issued MFMA flops of the E (or gradient) GEMM on one column tile with flags f
@@ -292,7 +309,7 @@ int derive_lists(HostPlan& hp, std::string& err) {
   // tiles of 32; the k-range of a tile is the list of runs of input atoms J
   // with some tile atom in N[J] (D is zero elsewhere).
   int stampv = 0;
-  std::vector<int> stamp2(NA, -1);
+  std::vector<int> stamp2(NA, -1), stamp3(NA, -1), colcnt(NA, 0);
   auto rowd_lists = [&](bool grad, std::vector<EItem>& items, std::vector<int>& run_ptr,
                         std::vector<int>& klens, std::vector<Run>& runs, std::vector<uint8_t>& kflag,
                         std::vector<int64_t>& kflag_off, int64_t& issued) {
@@ -321,6 +338,8 @@ int derive_lists(HostPlan& hp, std::string& err) {
           const int l = out_b[k];
           if (c < c1 && c + hp.nb[l] > c0) {
             stamp2[l] = stampv;
+            // input atoms J with this tile atom in N[J], i.e. the neighbours of l
+            for (int k2 = np[l]; k2 < np[l + 1]; ++k2) stamp3[nat[k2]] = stampv;
             const int b0 = std::max(c, c0), b1 = std::min(c + hp.nb[l], c1);
             ccol.push_back(KEnt{l, 0, b0 - c0, b1 - b0});
           }
@@ -332,8 +351,7 @@ int derive_lists(HostPlan& hp, std::string& err) {
         Run cur{-1, -1, 0, 0};
         for (int k = 0; k < n_in; ++k) {
           const int j = in_b[k];
-          bool rel = false;
-          for (int k2 = np[j]; k2 < np[j + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
+          const bool rel = stamp3[j] == stampv;   // some tile atom in N[j]
           if (rel) {
             if (cur.len > 0 && j == prevJ + 1) {
               cur.len += hp.nb[j];
@@ -438,39 +456,50 @@ int derive_lists(HostPlan& hp, std::string& err) {
         for (int k = np[a + t]; k < np[a + t + 1]; ++k)
           if (stamp2[nat[k]] != stampv) { stamp2[nat[k]] = stampv; nbrs.push_back(nat[k]); }
       std::sort(nbrs.begin(), nbrs.end());
-      auto pair_slots = [&](int q) {
+      // the list entry of every neighbour (pair ids per group slot), formed once per group
+      std::vector<Slot4> nbr_slots(nbrs.size());
+      for (size_t i = 0; i < nbrs.size(); ++i) {
+        const int q = nbrs[i];
         Slot4 e{q, -1, -1, -1};
         int* sl = &e.p0;
         for (int t = 0; t < n; ++t) {
           auto it = std::lower_bound(nat.begin() + np[a + t], nat.begin() + np[a + t + 1], q);
           if (it != nat.begin() + np[a + t + 1] && *it == q) sl[t] = hp.nbr_pair[it - nat.begin()];
         }
-        return e;
-      };
+        nbr_slots[i] = e;
+      }
       for (int c0 = 0; c0 < ncol; c0 += H_COLS) {
         const int c1 = std::min(ncol, c0 + H_COLS);
         ++stampv;
-        for (int c = c0; c < c1; ++c) stamp2[col_atom[c]] = stampv;
+        for (int c = c0; c < c1; ++c) {
+          const int l = col_atom[c];
+          int ncl = 1;   // tile columns on l (consecutive)
+          while (c + ncl < c1 && col_atom[c + ncl] == l) ++ncl;
+          stamp2[l] = stampv;
+          for (int k2 = np[l]; k2 < np[l + 1]; ++k2) {   // Q with l in N[Q]
+            const int q = nat[k2];
+            if (stamp3[q] != stampv) { stamp3[q] = stampv; colcnt[q] = 0; }
+            colcnt[q] += ncl;                              // tile columns present in N[q]
+          }
+          c += ncl - 1;
+        }
         GTile tl{};
         tl.grp = g;
         tl.col_beg = col0 + c0;
         tl.ncols = c1 - c0;
         tl.q_beg = (int)hp.gq.size();
         tl.x_beg = (int)hp.gx.size();
-        for (int q : nbrs) {
-          bool rel = false;
-          for (int k2 = np[q]; k2 < np[q + 1] && !rel; ++k2) rel = (stamp2[nat[k2]] == stampv);
-          if (rel) hp.gq.push_back(pair_slots(q));
-          if (stamp2[q] == stampv) hp.gx.push_back(pair_slots(q));
+        for (size_t i = 0; i < nbrs.size(); ++i) {
+          const int q = nbrs[i];
+          if (stamp3[q] == stampv) hp.gq.push_back(nbr_slots[i]);   // a tile column in N[q]
+          if (stamp2[q] == stampv) hp.gx.push_back(nbr_slots[i]);
         }
         tl.q_end = (int)hp.gq.size();
         tl.x_end = (int)hp.gx.size();
         for (int e = tl.q_beg; e < tl.q_end; ++e) {
           const int q = hp.gq[e].atom;
           const int* sl = &hp.gq[e].p0;
-          int cq = 0;   // tile columns present in N[Q]
-          for (int c = c0; c < c1; ++c)
-            cq += std::binary_search(nat.begin() + np[q], nat.begin() + np[q + 1], col_atom[c]);
+          const int cq = colcnt[q];   // tile columns present in N[Q]
           for (int t = 0; t < n; ++t)
             if (sl[t] >= 0)
               hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * cq *

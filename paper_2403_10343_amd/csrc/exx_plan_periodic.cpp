@@ -394,7 +394,7 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
   hp.h_waves = 1;
   {
     const double gr2 = GROUP_RADIUS * GROUP_RADIUS;
-    std::vector<int> mark(NA, -1), mark_img(NA, 0);
+    std::vector<int> mark(NA, -1), mark_img(NA, 0), qcnt(NA, 0), qsel;
     int stamp = 0;
     int a = 0;
     while (a < NA) {
@@ -476,40 +476,48 @@ int derive_lists_periodic(HostPlan& hp, std::string& err) {
         tl.q_beg = (int)hp.gq.size();
         tl.x_beg = (int)hp.gx.size();
         // Q-list: entries (Q, q) with some tile column (L, b) in N[Q + q], i.e. Q in N[L] at
-        // image b + n_LQ = q
+        // image b + n_LQ = q; counted per tile column, listed in slot order
         ++stamp;
-        for (int c = c0; c < c1; ++c) {
+        qsel.clear();
+        for (int c = c0; c < c1;) {
           const int l = col_atom[c], b = col_img[c];
-          if (c > c0 && l == col_atom[c - 1] && b == col_img[c - 1]) continue;
+          int ncl = 1;   // consecutive tile columns on (l, b)
+          while (c + ncl < c1 && col_atom[c + ncl] == l && col_img[c + ncl] == b) ++ncl;
           for (int k2 = np[l]; k2 < np[l + 1]; ++k2) {
             const int q = nat[k2];
             const int i = mark_img[q];
-            if (i < (int)slots.size() && slots[i].atom == q && slots[i].img == img_add(b, nim[k2])) mark[q] = stamp;
+            if (i < (int)slots.size() && slots[i].atom == q && slots[i].img == img_add(b, nim[k2])) {
+              if (mark[q] != stamp) { mark[q] = stamp; qcnt[q] = 0; qsel.push_back(i); }
+              qcnt[q] += ncl;
+            }
           }
+          c += ncl;
         }
-        for (size_t i = 0; i < slots.size(); ++i) {
+        std::sort(qsel.begin(), qsel.end());
+        for (int i : qsel) {
           const Slot4& s4 = slots[i];
           const int q = s4.atom;
-          if (mark[q] == stamp) {
-            hp.gq.push_back(s4);
-            int cq = 0;
-            for (int c = c0; c < c1; ++c) {
-              const int nq = hp.pimg[(size_t)q * NA + col_atom[c]];
-              cq += nq >= 0 && img_add(s4.img, nq) == col_img[c];
-            }
-            const int* sl = &s4.p0;
-            for (int t = 0; t < n; ++t)
-              if (sl[t] >= 0)
-                hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * cq * (((hp.na[q] + 3) / 4) + ((hp.nb[q] + 3) / 4));
-          }
-          int cx = 0;   // X-list: tile columns on (X, x)
-          for (int c = c0; c < c1; ++c) cx += col_atom[c] == q && col_img[c] == s4.img;
-          if (cx > 0) {
+          hp.gq.push_back(s4);
+          const int cq = qcnt[q];
+          const int* sl = &s4.p0;
+          for (int t = 0; t < n; ++t)
+            if (sl[t] >= 0)
+              hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * cq * (((hp.na[q] + 3) / 4) + ((hp.nb[q] + 3) / 4));
+        }
+        // X-list: the group neighbours (X, x) that are tile columns, in slot (atom) order
+        for (int c = c0; c < c1;) {
+          const int l = col_atom[c], b = col_img[c];
+          int ncl = 1;
+          while (c + ncl < c1 && col_atom[c + ncl] == l && col_img[c + ncl] == b) ++ncl;
+          const int i = mark_img[l];
+          if (i < (int)slots.size() && slots[i].atom == l && slots[i].img == b) {
+            const Slot4& s4 = slots[i];
             hp.gx.push_back(s4);
             const int* sl = &s4.p0;
             for (int t = 0; t < n; ++t)
-              if (sl[t] >= 0) hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * cx * ((hp.na[q] + 3) / 4);
+              if (sl[t] >= 0) hp.issued[2] += 2048LL * ((hp.na[a + t] + 15) / 16) * ncl * ((hp.na[l] + 3) / 4);
           }
+          c += ncl;
         }
         tl.q_end = (int)hp.gq.size();
         tl.x_end = (int)hp.gx.size();
