@@ -335,7 +335,9 @@ def main():
     cfg, wname = WORKLOADS[args.workload]
     sysm = synth.config(cfg)
     inp = synth.make_inputs(sysm)
+    t_plan = time.perf_counter()
     plan = exx.Plan.for_system(sysm)
+    t_plan = time.perf_counter() - t_plan
     dev = torch.device("cuda:0")
     C, V, D = (torch.from_numpy(a).to(dev) for a in (inp.C, inp.V, inp.D))
     K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=dev)
@@ -399,6 +401,7 @@ def main():
         "mixed_speedup_vs_fp64": (dt64 / recm["ms_per_build"] * 1e3) if recm else None,
         "E_x": E64,
         "E_x_per_atom": E64 / sysm.n_atoms,
+        "plan_create_s": t_plan,
     }
     if args.backward_steps > 0:
         dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D)
