@@ -191,8 +191,10 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D,
  * (with D^0 = D^1 = D/2 this is the E_x of build_K for D).
  * The repack of C and the F = V C part of the V stage (Eq. temp_F) are formed
  * once for both spins.  precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns
- * EXX_EUNSUPPORTED).  The first call allocates a second E and H' workspace
- * (EXX_ENOMEM if that fails); calls on one plan must not overlap. */
+ * EXX_EUNSUPPORTED, and so does a plan split into chunks by a workspace
+ * budget).  Clusters and periodic plans.  The first call allocates a second E
+ * and H' workspace (EXX_ENOMEM if that fails); calls on one plan must not
+ * overlap. */
 int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D,
                  int precision, double* K, double* Ex, void* stream);
 
@@ -204,8 +206,9 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
  * [2 * n_systems]: E_x of K^0 for every system, then of K^1 (each as in
  * exchange_energy).  The repack of C and E = M D (Eq. temp_E) are shared by
  * both kernels; the V stage, T2 and the final contraction run per kernel.
- * precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns EXX_EUNSUPPORTED).
- * Uses the second workspace of build_K_spin (allocated on first use). */
+ * precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns EXX_EUNSUPPORTED, and
+ * so does a chunked plan).  Clusters and periodic plans.  Uses the second
+ * workspace of build_K_spin (allocated on first use). */
 int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2,
                         const double* D, int precision, double* K, double* Ex, void* stream);
 
