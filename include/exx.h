@@ -58,8 +58,9 @@
  * exchange_backward (gradients per stored entry of the home-cell blocks:
  * E_x per cell differentiated with every image of a block moving with it;
  * forces use the image separation x_A - (x_B + n_AB.L)), build_K_spin and
- * build_K_two_kernels (each result on the same pattern); a workspace budget
- * that would need chunks returns EXX_EUNSUPPORTED.
+ * build_K_two_kernels (each result on the same pattern) and workspace
+ * budgets (chunks, below; each chunk's part of the pattern-folded X is the
+ * sum of the terms of its aux atoms).
  *
  * Ownership: the caller owns every device array passed in; the plan owns its
  * bookkeeping lists and workspace.  Output arrays are fully overwritten
@@ -146,7 +147,9 @@ typedef struct {
  * of being stored.  The result equals the unbounded build up to the rounding
  * order of the final sum (the per-chunk parts of K are added in chunk order).
  * EXX_ENOMEM if one V-stage group (at most three neighbouring atoms) alone
- * needs more than the bound.  Collinear-spin and two-kernel builds need the
+ * needs more than the bound.  Clusters and periodic plans (in a small
+ * periodic cell nearly every atom neighbours every group, so the smallest
+ * budget there is close to the stored layout's).  Collinear-spin and two-kernel builds need the
  * unbounded layout (EXX_EUNSUPPORTED on a chunked plan). */
 int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_bytes, exx_plan* out);
 

@@ -547,6 +547,12 @@ static int upload_plan(exx_plan_s* pl) {
     if ((rc = upload(pl, c.y_off, hp.y_off))) return rc;
     c.h_base = hp.e_total;
     c.y_base = 2 * hp.e_total;
+    c.pt_tiles = d.pt_tiles;
+    c.pt_ent = d.pt_ent;
+    c.pt_classes = hp.pt_classes;
+    c.pg_beg = d.pg_beg; c.pg_mid = d.pg_mid; c.pg_end = d.pg_end; c.pg_ent = d.pg_ent;
+    c.pg_pairs = d.pg_pairs;
+    c.n_pg = (int)hp.pg_pairs.size();
     pl->chunks.push_back(std::move(c));
   } else {
     for (const ChunkHost& h : hp.chunks) {
@@ -568,6 +574,17 @@ static int upload_plan(exx_plan_s* pl) {
       if ((rc = upload(pl, c.y_off, h.y_off))) return rc;
       c.h_base = h.e_total;
       c.y_base = h.e_total + h.h_total;
+      if (hp.periodic) {
+        if ((rc = upload(pl, c.pt_tiles, h.pt_tiles))) return rc;
+        if ((rc = upload(pl, c.pt_ent, h.pt_ent))) return rc;
+        c.pt_classes = h.pt_classes;
+        if ((rc = upload(pl, c.pg_beg, h.pg_beg))) return rc;
+        if ((rc = upload(pl, c.pg_mid, h.pg_mid))) return rc;
+        if ((rc = upload(pl, c.pg_end, h.pg_end))) return rc;
+        if ((rc = upload(pl, c.pg_ent, h.pg_ent))) return rc;
+        if ((rc = upload(pl, c.pg_pairs, h.pg_pairs))) return rc;
+        c.n_pg = (int)h.pg_pairs.size();
+      }
       pl->chunks.push_back(std::move(c));
     }
   }
@@ -614,6 +631,13 @@ void set_chunk(exx_plan pl, int c) {
   d.y_off = ch.y_off;
   d.y_tiles = pl->y_tiles_all + ch.y_beg;
   d.gd_items = pl->gd_items_all + ch.gd_beg;
+  d.pt_tiles = ch.pt_tiles;
+  d.pt_ent = ch.pt_ent;
+  d.pg_beg = ch.pg_beg;
+  d.pg_mid = ch.pg_mid;
+  d.pg_end = ch.pg_end;
+  d.pg_ent = ch.pg_ent;
+  d.pg_pairs = ch.pg_pairs;
   d.E = pl->W;
   d.H = pl->W ? pl->W + ch.h_base : nullptr;
   d.Y = pl->W ? pl->W + ch.y_base : nullptr;

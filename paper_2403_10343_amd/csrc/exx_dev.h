@@ -183,6 +183,13 @@ struct ChunkDev {
   int* t2m_items[2] = {nullptr, nullptr};   // per mixed set
   std::vector<T2Class> t2m_classes[2];
   int64_t h_base = 0, y_base = 0;           // H' and Y within the intermediate buffer (E at 0)
+  // periodic plans: pattern tiles (classes on the host) and the per-pair gather
+  PTile* pt_tiles = nullptr;
+  PTEnt* pt_ent = nullptr;
+  std::vector<PTClass> pt_classes;
+  int *pg_beg = nullptr, *pg_mid = nullptr, *pg_end = nullptr, *pg_pairs = nullptr;
+  PGEnt* pg_ent = nullptr;
+  int n_pg = 0;
 };
 
 // Device copies of one mixed-precision list set (HostPlan::mixed).

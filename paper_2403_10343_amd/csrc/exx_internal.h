@@ -66,6 +66,15 @@ struct MixedSet {
   int64_t issued64[5] = {0, 0, 0, 0, 0};            // issued binary64 MFMA flops
 };
 
+struct PGEnt { int P, tcol, hcol, pad; };       // pattern gather: T_P column, H'_P column
+// Tiled pattern contraction: a tile is a pair of V-stage groups (ga <= gb); an entry is one
+// P and one part (0: rows of T_P on the ga atoms times columns of H'_P on the gb atoms;
+// 1: rows of H'_P on the ga atoms times columns of T_P on the gb atoms), with the first
+// column of each group atom in the row and column matrices, or -1.
+struct PTEnt { int P, part, rc[3], cc[3]; };
+struct PTile { int a0, na, b0, nbt, e_beg, e_end, mask, pad; };   // mask bit 3 sa + sb: pair in the pattern
+struct PTClass { int ta, tb, beg, end; };        // tiles with ta x tb 16 x 16 output tiles
+
 // One chunk of a workspace-bounded plan: the aux atoms [a0, a1) (whole V-stage
 // groups [g0, g1)), whose H' and Y are formed, and the atoms whose E is
 // (re)computed for them: the chunk's atoms and their neighbours.
@@ -81,18 +90,17 @@ struct ChunkHost {
   std::vector<int> f_plist;
   std::vector<int64_t> e_off, h_off, y_off;         // per atom, element offsets in the chunk buffers
   int64_t e_total = 0, h_total = 0, y_total = 0;
+  // periodic plans: the pattern-contraction tiles and the per-pair gather terms, each
+  // restricted to the chunk's P (the X' terms of the chunk)
+  std::vector<PTile> pt_tiles;
+  std::vector<PTEnt> pt_ent;
+  std::vector<PTClass> pt_classes;
+  std::vector<int> pg_beg, pg_mid, pg_end, pg_pairs;
+  std::vector<PGEnt> pg_ent;
 };
 
 constexpr int EN_PAIRS = 64;         // canonical pairs per energy chunk
 
-struct PGEnt { int P, tcol, hcol, pad; };       // pattern gather: T_P column, H'_P column
-// Tiled pattern contraction: a tile is a pair of V-stage groups (ga <= gb); an entry is one
-// P and one part (0: rows of T_P on the ga atoms times columns of H'_P on the gb atoms;
-// 1: rows of H'_P on the ga atoms times columns of T_P on the gb atoms), with the first
-// column of each group atom in the row and column matrices, or -1.
-struct PTEnt { int P, part, rc[3], cc[3]; };
-struct PTile { int a0, na, b0, nbt, e_beg, e_end, mask, pad; };   // mask bit 3 sa + sb: pair in the pattern
-struct PTClass { int ta, tb, beg, end; };        // tiles with ta x tb 16 x 16 output tiles
 
 struct HostPlan {
   // system description

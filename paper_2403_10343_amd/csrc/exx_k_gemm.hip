@@ -590,8 +590,8 @@ __global__ __launch_bounds__(256) void k_ptile(double* __restrict__ K, DevPlan d
 }
 
 void launch_pgather(exx_plan plan, double* K, hipStream_t st) {
-  const HostPlan& hp = plan->hp;
-  for (const PTClass& c : hp.pt_classes) {
+  const ChunkDev& ch = plan->chunks[plan->cur];
+  for (const PTClass& c : ch.pt_classes) {
     const int n = c.end - c.beg, np_ = (n + 7) / 8 * 8;
     const PTile* tl = plan->d.pt_tiles + c.beg;
     switch (c.ta * 4 + c.tb) {
@@ -601,7 +601,7 @@ void launch_pgather(exx_plan plan, double* K, hipStream_t st) {
       default: break;
     }
   }
-  const int n = (int)hp.pg_pairs.size(), np_ = (n + 7) / 8 * 8;
+  const int n = ch.n_pg, np_ = (n + 7) / 8 * 8;
   if (n > 0) hipLaunchKernelGGL(k_pgather, dim3(np_), dim3(256), 0, st, K, plan->d, n, np_);
 }
 

@@ -841,6 +841,42 @@ void derive_mixed_lists(HostPlan& hp, int set) {
 // the neighbours X of P and the dV pairs read E_Q, so each chunk computes E for
 // its atoms and their neighbours: E of an atom near a chunk boundary is
 // recomputed by every chunk that needs it.
+// The X' terms of a chunk of a periodic plan: the pattern tiles keep their entries
+// whose P is one of the chunk's aux atoms (tiles left without entries are dropped, the
+// shape classes formed again), and the per-pair gather keeps its terms of those P.
+// X' is linear in the terms over P, so the chunks' parts add up to the whole.
+static void chunk_pattern_lists(const HostPlan& hp, ChunkHost& ch) {
+  auto own = [&](int P) { return P >= ch.a0 && P < ch.a1; };
+  for (const PTClass& c : hp.pt_classes) {
+    const int tb = (int)ch.pt_tiles.size();
+    for (int i = c.beg; i < c.end; ++i) {
+      PTile t = hp.pt_tiles[i];
+      const int eb = (int)ch.pt_ent.size();
+      for (int e = t.e_beg; e < t.e_end; ++e)
+        if (own(hp.pt_ent[e].P)) ch.pt_ent.push_back(hp.pt_ent[e]);
+      if ((int)ch.pt_ent.size() == eb) continue;
+      t.e_beg = eb;
+      t.e_end = (int)ch.pt_ent.size();
+      ch.pt_tiles.push_back(t);
+    }
+    if ((int)ch.pt_tiles.size() > tb) ch.pt_classes.push_back(PTClass{c.ta, c.tb, tb, (int)ch.pt_tiles.size()});
+  }
+  const size_t npairs = hp.pg_beg.size();
+  ch.pg_beg.assign(npairs, 0);
+  ch.pg_mid.assign(npairs, 0);
+  ch.pg_end.assign(npairs, 0);
+  for (int p : hp.pg_pairs) {
+    ch.pg_beg[p] = (int)ch.pg_ent.size();
+    for (int i = hp.pg_beg[p]; i < hp.pg_mid[p]; ++i)
+      if (own(hp.pg_ent[i].P)) ch.pg_ent.push_back(hp.pg_ent[i]);
+    ch.pg_mid[p] = (int)ch.pg_ent.size();
+    for (int i = hp.pg_mid[p]; i < hp.pg_end[p]; ++i)
+      if (own(hp.pg_ent[i].P)) ch.pg_ent.push_back(hp.pg_ent[i]);
+    ch.pg_end[p] = (int)ch.pg_ent.size();
+    if (ch.pg_end[p] > ch.pg_beg[p]) ch.pg_pairs.push_back(p);
+  }
+}
+
 int derive_chunks(HostPlan& hp, int64_t budget, std::string& err) {
   const int NA = hp.n_atoms;
   hp.chunks.clear();
@@ -849,11 +885,6 @@ int derive_chunks(HostPlan& hp, int64_t budget, std::string& err) {
   hp.inter_stored = stored;
   hp.ws_total = 2 * hp.e_total + hp.y_total;
   if (budget <= 0 || stored <= budget) return 0;
-  if (hp.periodic) {
-    err = "exx_plan_create: a periodic plan needs room for all its intermediates (" + std::to_string(stored) +
-          " bytes); chunked builds are not implemented for it";
-    return -5;
-  }
   const auto& np = hp.nbr_ptr;
   const auto& nat = hp.nbr_atom;
   auto esz = [&](int a) { return hp.e_off[a + 1] - hp.e_off[a]; };
@@ -956,6 +987,7 @@ int derive_chunks(HostPlan& hp, int64_t budget, std::string& err) {
       x.pend = (int)ch.f_plist.size();
       if (x.pend > x.pbeg) ch.f_items.push_back(x);
     }
+    if (hp.periodic) chunk_pattern_lists(hp, ch);
     hp.ws_total = std::max(hp.ws_total, ch.e_total + ch.h_total + ch.y_total);
     hp.chunks.push_back(std::move(ch));
   }

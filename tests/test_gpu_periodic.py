@@ -306,11 +306,49 @@ def test_periodic_spin_and_two_kernels(exx):
         assert torch.equal(K1, K2[a * ds:(a + 1) * ds])
 
 
+@pytest.mark.parametrize("which", ["cell", "box"])
+def test_periodic_chunked_plan_equals_stored(exx, which):
+    """A workspace budget half the stored intermediates splits a periodic plan
+    into chunks of V-stage groups; per chunk the pattern contraction keeps the
+    terms of the chunk's aux atoms.  K, E_x (FP64, mixed, FP32) and every
+    gradient agree with the unbounded plan (dV bit for bit)."""
+    sysm = (synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4) if which == "cell"
+            else synth.ice_box_periodic(2, 2, 2, seed=8, r_cut=6.0))
+    inp = synth.make_inputs(sysm)
+    full = exx.Plan.for_system(sysm)
+    stored = full.info["intermediate_bytes_stored"]
+    part = exx.Plan.for_system(sysm, ws_budget_bytes=stored // 2)
+    nch = part.info["n_chunks"]
+    print(f"{which}: stored {stored / 1e9:.3f} GB, {nch} chunks, held {part.info['intermediate_bytes'] / 1e9:.3f} GB",
+          flush=True)
+    assert full.info["n_chunks"] == 1 and nch >= 3
+    assert part.info["intermediate_bytes"] <= stored // 2
+    K1, E1 = run_build(full, inp, torch)
+    K2, E2 = run_build(part, inp, torch)
+    n = int(inp.layout.sys_nbas[0])
+    print(f"{which}: rel {relmax(K2, K1):.2e}", flush=True)
+    assert relmax(K2, K1) < 1e-12 and abs(E2[0] - E1[0]) < 1e-12 * abs(E1[0])
+    assert np.array_equal(K2.reshape(n, n), K2.reshape(n, n).T)
+    if which == "cell":
+        assert relmax(K2.reshape(n, n), O.x_periodic(inp)) < TOL
+    for prec in (exx.PREC_MIXED, exx.PREC_FP32):
+        Km1, Em1 = run_build(full, inp, torch, prec)
+        Km2, Em2 = run_build(part, inp, torch, prec)
+        assert relmax(Km2, Km1) < 1e-12 and abs(Em2[0] - Em1[0]) < 1e-12 * abs(Em1[0])
+    g1, g2 = _grads(full, inp), _grads(part, inp)
+    assert relmax(g2["dC"], g1["dC"]) < 1e-12 and np.array_equal(g1["dV"], g2["dV"])
+    assert relmax(g2["dD"], g1["dD"]) < 1e-12 and relmax(g2["F"], g1["F"]) < 1e-12
+    C, V, D = device_inputs(inp, torch)
+    with pytest.raises(exx.ExxError) as e:   # the spin build needs an unbounded workspace
+        part.build_K_spin(C, V, torch.cat([D, D]), torch.empty(2 * n * n, dtype=torch.float64, device="cuda:0"))
+    assert e.value.code == -5
+
+
 def test_periodic_unsupported_calls(exx):
     sysm = synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4)
-    with pytest.raises(exx.ExxError) as e:   # a workspace budget that would need chunks
+    with pytest.raises(exx.ExxError) as e:   # a budget below one V-stage group's E atoms
         exx.Plan.for_system(sysm, ws_budget_bytes=1 << 20)
-    assert e.value.code == -5
+    assert e.value.code == -2
     with pytest.raises(exx.ExxError) as e:   # cutoff not below half the cell width
         exx.Plan(sysm.species, sysm.pos, sysm.basis_table, sysm.aux_table, 3.7, lattice=sysm.lattice)
     assert e.value.code == -1

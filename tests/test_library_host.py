@@ -136,10 +136,14 @@ def test_periodic_host_plan_layout_matches_generator():
     with pytest.raises(ExxError) as e:
         Plan(tiny.species, tiny.pos, synth.N_BASIS, synth.N_AUX, 1.6, host_only=True, lattice=lat)
     assert e.value.code == -1
+    # periodic plans chunk like clusters; a budget below one group's E atoms is EXX_ENOMEM
     big = synth.ice_box_periodic(2, 2, 2, seed=0, r_cut=6.0)
+    stored = Plan.for_system(big, host_only=True).info["intermediate_bytes_stored"]
+    p = Plan.for_system(big, host_only=True, ws_budget_bytes=stored // 2)
+    assert p.info["n_chunks"] >= 2 and p.info["intermediate_bytes"] <= stored // 2
     with pytest.raises(ExxError) as e:
         Plan.for_system(big, host_only=True, ws_budget_bytes=1 << 20)
-    assert e.value.code == -5
+    assert e.value.code == -2
 
 
 def test_workspace_budget_chunks_on_host_plan():
