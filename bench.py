@@ -309,6 +309,8 @@ def main():
                     help="also time the collinear-spin build (two density matrices, FP64); 0 = skip")
     ap.add_argument("--two-kernel-steps", type=int, default=5,
                     help="also time two Coulomb matrices in one call (FP64); 0 = skip")
+    ap.add_argument("--screening-steps", type=int, default=3,
+                    help="timed FP64 builds per screening threshold (0: no screening record)")
     ap.add_argument("--periodic-only", action="store_true",
                     help="time only the periodic 3072-atom box (its record as the JSON line)")
     ap.add_argument("--periodic-steps", type=int, default=2,
@@ -469,6 +471,30 @@ def main():
             "stage_ms": {n_: float(x) for n_, x in zip(names, kst / max(nrec, 1))},
             "E_x": [float(x) for x in E2.cpu().numpy()],
         }
+    if args.screening_steps > 0:
+        progress("screening")
+        Kref = torch.empty_like(K)
+        Eref = torch.empty_like(Ex)
+        plan.build_K(C, V, D, Kref, Eref)
+        runs = []
+        for eps in (0.3, 1.0):
+            plan.set_screening(eps)
+            plan.build_K(C, V, D, K, Ex)
+            torch.cuda.synchronize()
+            tq0 = time.perf_counter()
+            for _ in range(args.screening_steps):
+                plan.build_K(C, V, D, K, Ex)
+            torch.cuda.synchronize()
+            tq = (time.perf_counter() - tq0) / args.screening_steps
+            frac = float(plan.screened_pairs().float().mean().item())
+            plan.set_screening(0.0)
+            runs.append({"eps": eps, "pairs_screened": frac, "ms_per_build": 1e3 * tq,
+                         "vs_unscreened": dt64 / tq,
+                         "max_abs_dK": float((K - Kref).abs().max().item()),
+                         "dE_x_per_atom": float(abs(Ex[0].item() - Eref[0].item()) / sysm.n_atoms)})
+        out["screening"] = {
+            "workload": wname + " (FP64 build_K with V blocks skipped below a maximum-norm estimate; lossy)",
+            "runs": runs}
     if args.periodic_steps > 0:
         out["periodic"] = periodic_record(exx, torch, args.periodic_steps, min(args.backward_steps, 1))
     if args.calibrate_copy:

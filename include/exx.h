@@ -258,6 +258,39 @@ int exx_plan_set_tuning(exx_plan plan, const int32_t* choices);
  * captured graph.  Returns EXX_EINVAL unless 0 <= r_split <= 1e6. */
 int exx_plan_set_mixed_split(exx_plan plan, double r_split);
 
+/* Maximum-norm estimates (Sec. "Evaluation of the EXX matrix in real space":
+ * whether a product of temporaries is formed is decided from estimates of the
+ * maximum norms of the arrays involved, such as D and the RI coefficients).
+ * exx_block_norms writes, in binary64, for every canonical pair p = (A, B) the
+ * three doubles norms[3p..3p+2] = max|C| over the pair's stored C block, max|V|
+ * over its V block, max|D| over the (A, B) and (B, A) blocks of D (device array
+ * [n_pairs][3], caller-owned; C, V, D as in build_K).  Maxima are exact, so the
+ * output does not depend on the order of evaluation.  Asynchronous on stream. */
+int exx_block_norms(exx_plan plan, const double* C, const double* V, const double* D, double* norms,
+                    void* stream);
+
+/* Screening by those estimates (lossy; off by default).  With eps > 0 every
+ * later build_K (any precision; graphs captured afterwards too) first forms the
+ * norms of its C, V and D and, per atom A, tau_A = the largest max|C| of a pair
+ * with A, rho_A = the largest max|D| of a pair with A, sigma_A = the largest
+ * rho_J over J in N[A].  The estimate of pair (P, Q),
+ *     est = ((max|V_PQ| * tau_P) * tau_Q) * min(sigma_P, sigma_Q)   (binary64),
+ * bounds the modulus of every term C^mu_ij V_{mu nu} C^nu_kl D_jl with mu on P
+ * and nu on Q.  Pairs with est < eps take no part in the build: every product
+ * through their V block is skipped, so K equals the exact K of V with those
+ * blocks set to zero.  eps = 0 switches screening off (the build is then the
+ * unscreened one, bit for bit).  The first eps > 0 allocates the plan's norm
+ * and flag buffers (n_pairs * 3 + n_atoms * 3 doubles, n_pairs bytes).
+ * build_K_spin and build_K_two_kernels return EXX_EUNSUPPORTED while eps > 0;
+ * exchange_backward is never screened.  EXX_EINVAL unless eps is finite and
+ * >= 0; EXX_ESTATE on a host-only plan. */
+int exx_set_screening(exx_plan plan, double eps);
+
+/* The screening flags of the last screened build_K issued (device uint8
+ * [n_pairs], caller-owned: 1 = pair skipped), copied on stream after that
+ * build.  EXX_ESTATE if no screened build has been issued. */
+int exx_screened_pairs(exx_plan plan, uint8_t* flags, void* stream);
+
 /* E_x = -1/4 sum_ik K_ik D_ik for every system (device Ex [n_systems]),
  * summed over the screened pair blocks (D beyond r_cut counts as zero), a
  * fixed-order binary64 reduction (bitwise reproducible).  The per-chunk

@@ -409,6 +409,76 @@ def spin_exchange_energy(K_spin, D_spin):
 
 
 # ----------------------------------------------------------------------------
+# maximum-norm estimates and screening (Sec. "Evaluation of the EXX matrix in
+# real space": whether a product of temporaries is formed is decided from
+# estimates of the maximum norms of the arrays involved, e.g. D and C)
+
+
+def block_max_norms(inputs):
+    """Per canonical pair p = (A, B): [max|C block|, max|V block|, max|D|] with
+    the C and V blocks as stored (C: every aux function of A and of B, rows on
+    A, columns on B; V: aux of A by aux of B) and D over both the (A, B) and
+    the (B, A) blocks of the pair's system.  Maxima of absolute values are
+    exact in any order."""
+    sysm, lay = inputs.system, inputs.layout
+    nb = sysm.basis_table[sysm.species].astype(np.int64)
+    sys_of = np.zeros(sysm.n_atoms, dtype=np.int64)
+    bo = np.zeros(sysm.n_atoms, dtype=np.int64)
+    for s in range(sysm.n_systems):
+        lo, hi = int(sysm.sys_off[s]), int(sysm.sys_off[s + 1])
+        sys_of[lo:hi] = s
+        bo[lo:hi] = np.concatenate([[0], np.cumsum(nb[lo:hi])[:-1]])
+    out = np.zeros((lay.n_pairs, 3))
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        out[p, 0] = np.abs(inputs.C[lay.c_off[p]:lay.c_off[p + 1]]).max()
+        out[p, 1] = np.abs(inputs.V[lay.v_off[p]:lay.v_off[p + 1]]).max()
+        s = sys_of[a]
+        n = int(lay.sys_nbas[s])
+        Ds = inputs.D[lay.sys_bas_off[s]:lay.sys_bas_off[s] + n * n].reshape(n, n)
+        ia, ib = slice(bo[a], bo[a] + nb[a]), slice(bo[b], bo[b] + nb[b])
+        out[p, 2] = max(np.abs(Ds[ia, ib]).max(), np.abs(Ds[ib, ia]).max())
+    return out
+
+
+def screening_estimates(inputs, norms):
+    """The maximum-norm estimate of the terms C^mu_ij V_{mu nu} C^nu_kl D_jl that
+    run through the V block of each canonical pair (P, Q) (mu on P, nu on Q):
+
+        est_PQ = ((max|V_PQ| * tau_P) * tau_Q) * min(sigma_P, sigma_Q)
+
+    tau_A = the largest max|C| of a pair block with A (it bounds every C^mu with
+    mu on A); rho_A = the largest max|D| of a pair with A; sigma_A = the largest
+    rho_J over the neighbours J of A (j of C^mu_ij with mu on P lies on an atom of
+    N[P], l on an atom of N[Q]).  Every such term has modulus at most est_PQ."""
+    lay = inputs.layout
+    nat = inputs.system.n_atoms
+    tau = np.zeros(nat)
+    rho = np.zeros(nat)
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        for x in (a, b):
+            tau[x] = max(tau[x], norms[p, 0])
+            rho[x] = max(rho[x], norms[p, 2])
+    sigma = np.zeros(nat)
+    for a, b in zip(lay.pair_a, lay.pair_b):
+        sigma[a] = max(sigma[a], rho[b])
+        sigma[b] = max(sigma[b], rho[a])
+    est = np.empty(lay.n_pairs)
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        est[p] = ((norms[p, 1] * tau[a]) * tau[b]) * min(sigma[a], sigma[b])
+    return est
+
+
+def screened_coulomb(inputs, flags):
+    """A copy of ``inputs`` with the V blocks of the flagged pairs set to zero:
+    the result of a build that skips every product through those blocks."""
+    V = inputs.V.copy()
+    lay = inputs.layout
+    for p in np.nonzero(flags)[0]:
+        V[lay.v_off[p]:lay.v_off[p + 1]] = 0.0
+    return with_coulomb(inputs, V)
+
+
+# ----------------------------------------------------------------------------
 # gradients and forces (dense; small systems)
 
 

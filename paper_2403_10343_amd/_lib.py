@@ -55,7 +55,8 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "exx_plan_flops", "exx_last_error", "exx_plan_set_profiling", "exx_plan_stage_times",
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
            "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
-           "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images")
+           "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images", "exx_block_norms",
+           "exx_set_screening", "exx_screened_pairs")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -83,6 +84,9 @@ def lib():
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
+    L.exx_block_norms.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.exx_set_screening.argtypes = [vp, dp]
+    L.exx_screened_pairs.argtypes = [vp, vp, vp]
     L.exx_plan_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp]
     L.exx_plan_tuning.argtypes = [vp, vp, vp]
     L.exx_plan_set_tuning.argtypes = [vp, vp]
@@ -231,6 +235,28 @@ class Plan:
         _check(lib().build_K_two_kernels(self._h, c, v, _dev(V2, self.info["v_size"], "V2"), d, int(precision),
                                          _dev(K, 2 * self.info["d_size"], "K"),
                                          _dev(Ex, 2 * self.n_systems, "Ex", True), _stream(stream)))
+
+    def block_norms(self, C, V, D, stream=None):
+        """Per canonical pair: max|C block|, max|V block|, max|D| over both D
+        blocks, in binary64 (a new device tensor [n_pairs, 3])."""
+        import torch
+        c, v, d = self._cvd(C, V, D)
+        n = self.info["n_pairs"]
+        out = torch.empty((n, 3), dtype=torch.float64, device=C.device)
+        _check(lib().exx_block_norms(self._h, c, v, d, _dev(out, 3 * n, "norms"), _stream(stream)))
+        return out
+
+    def set_screening(self, eps):
+        """Skip the V blocks whose maximum-norm estimate is below eps in later
+        build_K calls (0: off)."""
+        _check(lib().exx_set_screening(self._h, float(eps)))
+
+    def screened_pairs(self, stream=None):
+        """Flags of the last screened build_K (a new device uint8 tensor [n_pairs])."""
+        import torch
+        out = torch.empty(max(1, self.info["n_pairs"]), dtype=torch.uint8, device="cuda")
+        _check(lib().exx_screened_pairs(self._h, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out[:self.info["n_pairs"]]
 
     def exchange_energy(self, K, D, Ex, stream=None):
         n = self.info["d_size"]

@@ -327,6 +327,77 @@ __global__ __launch_bounds__(256) void k_dmask(const double* __restrict__ D, dou
   }
 }
 
+// ---------------------------------------------------------------------------
+// maximum-norm estimates (binary64).  Per canonical pair (A, B): max|C| over its stored
+// block, max|V| over its block, max|D| over the (A, B) and (B, A) blocks of D (one
+// workgroup per pair; maxima are exact in any order).  Then per atom A: tau_A, the largest
+// max|C| of a pair with A, and rho_A, the largest max|D| of a pair with A; sigma_A, the
+// largest rho_J over J in N[A].  The estimate of the V block of a pair (P, Q),
+// ((max|V_PQ| tau_P) tau_Q) min(sigma_P, sigma_Q), bounds every term C^mu_ij V_mu,nu
+// C^nu_kl D_jl with mu on P and nu on Q (j lies on an atom of N[P], l on one of N[Q]);
+// below the threshold the build skips every product through that block.
+
+__global__ __launch_bounds__(256) void k_block_norms(const double* __restrict__ C, const double* __restrict__ V,
+                                                     const double* __restrict__ D, DevPlan d,
+                                                     double* __restrict__ nrm) {
+  __shared__ double red[3][256];
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const int s = d.atom_sys[A];
+  const int64_t base = d.sys_d_off[s], ns = d.sys_n[s];
+  const int bA = d.nb[A], bB = d.nb[B];
+  const int64_t oA = d.bo[A], oB = d.bo[B];
+  double mc = 0.0, mv = 0.0, md = 0.0;
+  for (int64_t e = d.c_off[p] + threadIdx.x; e < d.c_off[p + 1]; e += 256) mc = fmax(mc, fabs(C[e]));
+  for (int64_t e = d.v_off[p] + threadIdx.x; e < d.v_off[p + 1]; e += 256) mv = fmax(mv, fabs(V[e]));
+  for (int e = threadIdx.x; e < bA * bB; e += 256) {
+    const int i = e / bB, k = e - i * bB;
+    md = fmax(md, fmax(fabs(D[base + (oA + i) * ns + oB + k]), fabs(D[base + (oB + k) * ns + oA + i])));
+  }
+  red[0][threadIdx.x] = mc;
+  red[1][threadIdx.x] = mv;
+  red[2][threadIdx.x] = md;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int j = 0; j < 3; ++j) red[j][threadIdx.x] = fmax(red[j][threadIdx.x], red[j][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) nrm[3 * (int64_t)p + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// tau_A, rho_A (pass 0) or sigma_A (pass 1) for every atom; nrm + 3 n_pairs holds tau, rho, sigma
+__global__ void k_atom_norms(DevPlan d, double* __restrict__ nrm, int n_pairs, int pass) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= d.n_atoms) return;
+  double* at = nrm + 3 * (int64_t)n_pairs;
+  if (pass == 0) {
+    double t = 0.0, r = 0.0;
+    for (int k = d.nbr_ptr[A]; k < d.nbr_ptr[A + 1]; ++k) {
+      const int64_t p = d.nbr_pair[k];
+      t = fmax(t, nrm[3 * p]);
+      r = fmax(r, nrm[3 * p + 2]);
+    }
+    at[A] = t;
+    at[d.n_atoms + A] = r;
+  } else {
+    double sg = 0.0;
+    for (int k = d.nbr_ptr[A]; k < d.nbr_ptr[A + 1]; ++k) sg = fmax(sg, at[d.n_atoms + d.nbr_atom[k]]);
+    at[2 * d.n_atoms + A] = sg;
+  }
+}
+
+__global__ void k_screen(DevPlan d, const double* __restrict__ nrm, int n_pairs, double eps,
+                         uint8_t* __restrict__ flags) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const double* tau = nrm + 3 * (int64_t)n_pairs;
+  const double* sigma = tau + 2 * d.n_atoms;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const double est = ((nrm[3 * (int64_t)p + 1] * tau[A]) * tau[B]) * fmin(sigma[A], sigma[B]);
+  flags[p] = est < eps ? 1 : 0;
+}
+
 __global__ void k_zero(double* x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = 0.0;
@@ -911,6 +982,18 @@ static void launch_E(exx_plan plan, hipStream_t st) {
 
 // the lane-ordered V and D operands of the V stage (DevPlan::Vr, Dr; with fp32 also the
 // binary32 copies Vr32, Dr32) for these V and D
+// maximum-norm estimates of C, V and D into plan->scr_nrm, then the screening flags of the
+// plan's threshold into plan->scr_flags
+static void launch_screening(exx_plan plan, const double* C, const double* V, const double* D, hipStream_t st) {
+  const int np = (int)plan->hp.pair_a.size(), na = plan->hp.n_atoms;
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_block_norms, dim3(np), dim3(256), 0, st, C, V, D, plan->d, plan->scr_nrm);
+  hipLaunchKernelGGL(k_atom_norms, dim3((na + 255) / 256), dim3(256), 0, st, plan->d, plan->scr_nrm, np, 0);
+  hipLaunchKernelGGL(k_atom_norms, dim3((na + 255) / 256), dim3(256), 0, st, plan->d, plan->scr_nrm, np, 1);
+  hipLaunchKernelGGL(k_screen, dim3((np + 255) / 256), dim3(256), 0, st, plan->d, plan->scr_nrm, np,
+                     plan->scr_eps, plan->scr_flags);
+}
+
 static void launch_vd_operands(exx_plan plan, const double* V, const double* D, hipStream_t st, bool fp32 = false) {
   const unsigned np = (unsigned)plan->hp.pair_a.size();
   if (np) hipLaunchKernelGGL(k_vdrepack, dim3(np), dim3(256), 0, st, V, D, plan->d.Dr, plan->d, fp32 ? 1 : 0);
@@ -1072,8 +1155,15 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   launch_dmask(plan, D, plan->d.Dm, st);
   launch_repack(plan, C, st);
   launch_vd_operands(plan, V, D, st, m >= 0);
+  const bool screened = plan->scr_eps > 0;
+  if (screened) {
+    launch_screening(plan, C, V, D, st);
+    plan->d.scr = plan->scr_flags;
+  }
   stage_mark(plan, 1, st);
   build_chunks(plan, V, D, K, m, st);
+  plan->d.scr = nullptr;
+  if (screened) plan->scr_done = true;
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
@@ -1109,6 +1199,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (!plan) return fail(EXX_EINVAL, "build_K_spin: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "build_K_spin: host-only plan");
   if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K_spin: NULL array");
+  if (plan->scr_eps > 0) return fail(EXX_EUNSUPPORTED, "build_K_spin: norm screening applies to build_K only");
   if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
     return fail(EXX_EUNSUPPORTED, "build_K_spin: only the binary64 build takes two spins");
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
@@ -1173,6 +1264,8 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   if (!plan) return fail(EXX_EINVAL, "build_K_two_kernels: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "build_K_two_kernels: host-only plan");
   if (!C || !V || !V2 || !D || !K) return fail(EXX_EINVAL, "build_K_two_kernels: NULL array");
+  if (plan->scr_eps > 0)
+    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: norm screening applies to build_K only");
   if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
     return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: only the binary64 build takes two Coulomb matrices");
   if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_two_kernels: unknown precision");
@@ -1361,6 +1454,42 @@ int exx_plan_set_mixed_split(exx_plan plan, double r_split) {
   HIP_TRY(hipDeviceSynchronize());   // lists of an earlier split may still be in use
   plan->mdev[0].uploaded = false;
   return prepare_mixed(plan, 0);
+}
+
+int exx_block_norms(exx_plan plan, const double* C, const double* V, const double* D, double* norms,
+                    void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_block_norms: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_block_norms: host-only plan");
+  if (!C || !V || !D || !norms) return fail(EXX_EINVAL, "exx_block_norms: NULL array");
+  const unsigned np = (unsigned)plan->hp.pair_a.size();
+  if (np) hipLaunchKernelGGL(k_block_norms, dim3(np), dim3(256), 0, (hipStream_t)stream, C, V, D, plan->d, norms);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+int exx_set_screening(exx_plan plan, double eps) {
+  if (!plan) return fail(EXX_EINVAL, "exx_set_screening: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_set_screening: host-only plan");
+  if (!(eps >= 0.0) || eps > 1e300) return fail(EXX_EINVAL, "exx_set_screening: eps must be finite and >= 0");
+  if (eps > 0 && !plan->scr_nrm) {
+    const int64_t np = (int64_t)plan->hp.pair_a.size(), na = plan->hp.n_atoms;
+    HIP_TRY(hipMalloc((void**)&plan->scr_nrm, sizeof(double) * std::max<int64_t>(1, 3 * np + 3 * na)));
+    plan->allocs.push_back(plan->scr_nrm);
+    HIP_TRY(hipMalloc((void**)&plan->scr_flags, std::max<int64_t>(1, np)));
+    plan->allocs.push_back(plan->scr_flags);
+    plan->dev_bytes += (int64_t)sizeof(double) * (3 * np + 3 * na) + np;
+  }
+  plan->scr_eps = eps;
+  return EXX_OK;
+}
+
+int exx_screened_pairs(exx_plan plan, uint8_t* flags, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_screened_pairs: NULL plan");
+  if (!flags) return fail(EXX_EINVAL, "exx_screened_pairs: NULL array");
+  if (!plan->scr_done) return fail(EXX_ESTATE, "exx_screened_pairs: no screened build has been issued");
+  const size_t np = plan->hp.pair_a.size();
+  if (np) HIP_TRY(hipMemcpyAsync(flags, plan->scr_flags, np, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return EXX_OK;
 }
 
 int exchange_energy(exx_plan plan, const double* K, const double* D, double* Ex, void* stream) {

@@ -150,6 +150,9 @@ struct DevPlan {
   // (2 p + o) * 256, [k-step q < 4][lane L] = D_PQ[L % 16][4 (L / 16) + q] (the binary32 MFMA
   // accumulator puts rows 4 (L / 16) + v in lane L, so its D chain runs four k-steps)
   float *Vr32, *Dr32;
+  // maximum-norm screening of a build_K (exx_set_screening): per canonical pair 1 where every
+  // product through its V block is skipped; null when the build is not screened
+  const uint8_t* scr;
 };
 
 constexpr int N_STAGE_EV = EXX_N_STAGES + 1;   // stage boundaries, start and end included
@@ -240,6 +243,12 @@ struct exx_plan_s {
   GTile* g_tiles_all = nullptr;     // global (all-chunk) device lists the chunk ranges index
   YTile* y_tiles_all = nullptr;
   EItem* gd_items_all = nullptr;
+  // maximum-norm screening: threshold (0: off); per pair max|C|, max|V|, max|D| (3 doubles),
+  // then per atom tau, rho, sigma (n_atoms each); the flags of the last screened build
+  double scr_eps = 0;
+  double* scr_nrm = nullptr;
+  uint8_t* scr_flags = nullptr;
+  bool scr_done = false;
 };
 
 // Point the device plan and the launchers at chunk c.

@@ -189,7 +189,8 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
         qm_bo[ei] = d.bo[Q];
         qm_toff[ei] = d.t_off[Q];
         const int pp[3] = {qe.p0, qe.p1, qe.p2};
-        for (int k = 0; k < GROUP_ATOMS; ++k) qm_p[ei][k] = pp[k];
+        // a pair whose V block is screened out takes no part (as if the block were zero)
+        for (int k = 0; k < GROUP_ATOMS; ++k) qm_p[ei][k] = (pp[k] >= 0 && d.scr && d.scr[pp[k]]) ? -1 : pp[k];
       }
     }
     __syncthreads();
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(64 * H_WAVES) __attribute__((amdgpu_waves_per_eu(NS
         for (int u = 0; u < U; ++u) {
           if (u < nU) {
             const int p = pp[un.slot[u]];
-            if (p >= 0) {
+            if (p >= 0 && !(d.scr && d.scr[p])) {
               const int P = un.P[u], aP = un.a[u], bP = un.b[u];
               const int muB = un.mu0[u] + lr;
               const bool muv = muB < aP;

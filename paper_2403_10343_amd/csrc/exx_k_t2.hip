@@ -30,6 +30,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_T2(const double* __restrict__ V,
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int lr = L & 15, lk = L >> 4;
   const int p = items[item_base + w] >> 1;
+  if (d.scr && d.scr[p]) return;   // V_PQ screened out: the pair adds nothing
   const bool flip = items[item_base + w] & 1;
   const int P = flip ? d.pair_b[p] : d.pair_a[p], Q = flip ? d.pair_a[p] : d.pair_b[p];
   const int aP = d.na[P], bP = d.nb[P], aQ = d.na[Q], bQ = d.nb[Q];

@@ -426,6 +426,106 @@ def pin_two_kernels(seed=15):
     return r < TOL, f"{r:.1e}"
 
 
+def _signed_problem(sysm, seed, cmag, vmag, dmag):
+    """A random_problem whose entries are random signs times a magnitude that is
+    constant per block: cmag[p], vmag[p] per canonical pair, dmag[A, B] (symmetric)
+    per atom pair of D."""
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    nb, na, bo, ao = _offsets(sysm)
+    lay = inp.layout
+    C3, Vd, Dd = np.sign(C3), np.sign(Vd), np.sign(Dd)
+    C, V = np.sign(inp.C), np.sign(inp.V)
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        ia, ib = slice(bo[a], bo[a + 1]), slice(bo[b], bo[b + 1])
+        ma, mb = slice(ao[a], ao[a + 1]), slice(ao[b], ao[b + 1])
+        for m in ((ma,) if a == b else (ma, mb)):
+            C3[m, ia, ib] *= cmag[p]
+            if a != b:
+                C3[m, ib, ia] *= cmag[p]
+        C[lay.c_off[p]:lay.c_off[p + 1]] *= cmag[p]
+        Vd[ma, mb] *= vmag[p]
+        if a != b:
+            Vd[mb, ma] *= vmag[p]
+        V[lay.v_off[p]:lay.v_off[p + 1]] *= vmag[p]
+    atom = np.repeat(np.arange(sysm.n_atoms), nb)
+    Dd = Dd * dmag[atom][:, atom]
+    return synth.Inputs(sysm, lay, C, V, Dd.ravel().copy()), C3, Vd, Dd
+
+
+def _term_maxima(sysm, lay, C3, Vd, Dd):
+    """Per canonical pair (P, Q): the largest |C^mu_ij V_mu,nu C^nu_kl D_jl| over mu
+    on P, nu on Q and the reverse, by brute force over the dense arrays (D on the
+    screened atom pairs only, as the exchange contracts it)."""
+    nb, na, bo, ao = _offsets(sysm)
+    near = np.zeros((sysm.n_atoms, sysm.n_atoms), bool)
+    for a, b in zip(lay.pair_a, lay.pair_b):
+        near[a, b] = near[b, a] = True
+    atom = np.repeat(np.arange(sysm.n_atoms), nb)
+    Dm = np.where(near[atom][:, atom], np.abs(Dd), 0.0)
+    amax = np.abs(C3).max(axis=1)                   # [mu, j]: max over i of |C^mu_ij|
+    out = np.zeros(lay.n_pairs)
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        for P, Q in ((a, b), (b, a)):
+            mP, mQ = slice(ao[P], ao[P + 1]), slice(ao[Q], ao[Q + 1])
+            x = np.max(amax[mP][:, :, None] * Dm[None], axis=1)          # [mu, l]
+            t = np.max(x[:, None, :] * amax[mQ][None, :, :], axis=2)     # [mu, nu]
+            out[p] = max(out[p], float(np.max(np.abs(Vd[mP, mQ]) * t)))
+    return out, near
+
+
+def pin_norm_estimates(seed=20):
+    """Maximum-norm estimates and screening.  (i) The per-pair maxima of C, V
+    and D equal maxima over the dense arrays' blocks.  (ii) Every term C^mu_ij
+    V_mu,nu C^nu_kl D_jl with mu on P and nu on Q (or the reverse) is at most
+    the estimate of (P, Q), by brute force.  (iii) The estimate is attained
+    when the blocks have constant magnitudes and either D or C is uniform (all
+    atoms neighbours): then the largest term is max|V_PQ| tau_P tau_Q times the
+    largest D entry reachable, exactly.  (iv) The screened V is zero exactly on
+    the flagged pairs' dense blocks, and K of the screened V plus K of the V of
+    only the flagged blocks is K (linearity)."""
+    sysm = synth.water_cluster(2, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    nb, na, bo, ao = _offsets(sysm)
+    lay = inp.layout
+    nrm = O.block_max_norms(inp)
+    bad = 0
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        ia, ib = slice(bo[a], bo[a + 1]), slice(bo[b], bo[b + 1])
+        mu = np.r_[ao[a]:ao[a + 1], ao[b]:ao[b + 1]] if a != b else np.r_[ao[a]:ao[a + 1]]
+        want = [np.abs(C3[mu][:, ia, ib]).max(), np.abs(Vd[ao[a]:ao[a + 1], ao[b]:ao[b + 1]]).max(),
+                max(np.abs(Dd[ia, ib]).max(), np.abs(Dd[ib, ia]).max())]
+        bad += int(not np.array_equal(nrm[p], want))
+    est = O.screening_estimates(inp, nrm)
+    tmax, near = _term_maxima(sysm, lay, C3, Vd, Dd)
+    worst = float(np.max(tmax / est))
+    # constant-magnitude blocks: the estimate is attained
+    rng = np.random.default_rng(seed + 1)
+    nat, npr = sysm.n_atoms, lay.n_pairs
+    sym = lambda m: np.triu(m) + np.triu(m, 1).T
+    cases = ((rng.uniform(0.5, 2.0, npr), rng.uniform(0.5, 2.0, npr), np.ones((nat, nat))),
+             (np.ones(npr), rng.uniform(0.5, 2.0, npr), sym(rng.uniform(0.5, 2.0, (nat, nat)))))
+    tight = 0.0
+    for cm, vm, dm in cases:
+        ci, c3, vd, dd = _signed_problem(sysm, seed, cm, vm, dm)
+        e = O.screening_estimates(ci, O.block_max_norms(ci))
+        t, _ = _term_maxima(sysm, lay, c3, vd, dd)
+        tight = max(tight, float(np.max(np.abs(t / e - 1.0))))
+    flags = est < np.quantile(est, 0.4)
+    scr = O.screened_coulomb(inp, flags)
+    Vs = O.Blocks(scr).dense_V()
+    blk_ok = True
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        ma, mb = slice(ao[a], ao[a + 1]), slice(ao[b], ao[b + 1])
+        want = 0.0 * Vd[ma, mb] if flags[p] else Vd[ma, mb]
+        blk_ok = blk_ok and np.array_equal(Vs[ma, mb], want) and np.array_equal(Vs[mb, ma], want.T)
+    only = O.with_coulomb(inp, inp.V - scr.V)
+    r = rel(O.k_eigen(scr) + O.k_eigen(only), O.k_eigen(inp))
+    ok = (bad == 0 and worst <= 1.0 + 1e-12 and tight < 1e-12 and near.all()
+          and 0 < flags.sum() < len(flags) and blk_ok and r < TOL)
+    return ok, (f"norm mismatches {bad}, worst term / estimate {worst:.3f}, attained to {tight:.1e}, "
+                f"blocks {blk_ok}, linearity {r:.1e}")
+
+
 def _tiny_periodic(seed):
     lat = np.array([[3.0, 0.0, 0.0], [0.4, 3.2, 0.0], [0.2, -0.3, 3.4]])
     pos = np.array([[0.2, 0.3, 0.1], [2.6, 0.5, 0.4], [1.3, 2.9, 3.0], [1.5, 1.6, 1.7], [0.5, 2.8, 3.2]])
@@ -505,4 +605,5 @@ ALL_PINS = {
     "periodic_unfolded": pin_periodic_unfolded,
     "periodic_vacuum": pin_periodic_vacuum,
     "periodic_supercell": pin_periodic_supercell,
+    "norm_estimates": pin_norm_estimates,
 }

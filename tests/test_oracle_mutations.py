@@ -40,6 +40,15 @@ MUTATIONS = {
     "periodic_V_relative_image": ("        r = tuple(b - a for a, b in zip(p, q))", "        r = q"),
     "spin_ignores_D": ("return [f(with_density(inputs, D), s) for D in D_spin]",
                        "return [f(inputs, s) for D in D_spin]"),
+    "estimate_sigma_one_hop": ("        sigma[a] = max(sigma[a], rho[b])\n        sigma[b] = max(sigma[b], rho[a])",
+                               "        sigma[a] = max(sigma[a], rho[a])\n        sigma[b] = max(sigma[b], rho[b])"),
+    "estimate_tau_of_first_atom": ("            tau[x] = max(tau[x], norms[p, 0])",
+                                   "            tau[a] = max(tau[a], norms[p, 0])"),
+    "estimate_max_for_min": ("* min(sigma[a], sigma[b])", "* max(sigma[a], sigma[b]) * 0.5"),
+    "norms_C_first_atom_only": ("out[p, 0] = np.abs(inputs.C[lay.c_off[p]:lay.c_off[p + 1]]).max()",
+                                "out[p, 0] = np.abs(inputs.C[lay.c_off[p]:(lay.c_off[p] + lay.c_off[p + 1]) // 2]).max()"),
+    "screened_V_neighbour_block": ("        V[lay.v_off[p]:lay.v_off[p + 1]] = 0.0",
+                                   "        V[lay.v_off[p]:lay.v_off[p + 1] - 1] = 0.0"),
 }
 
 
