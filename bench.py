@@ -450,6 +450,19 @@ def main():
             "stage_ms": {n_: float(x) for n_, x in zip(names, sst / max(nrec, 1))},
             "E_x": float(Ex[0].item()),
         }
+        if args.backward_steps > 0:
+            dCs, dVs, dDs = torch.empty_like(C), torch.empty_like(V), torch.empty_like(Ds)
+            Fs = torch.empty(3 * sysm.n_atoms, dtype=torch.float64, device=dev)
+            plan.exchange_backward_spin(C, V, Ds, 1.0, dC=dCs, dV=dVs, dD=dDs, forces=Fs, K=K2)
+            torch.cuda.synchronize()
+            tsb0 = time.perf_counter()
+            for _ in range(args.backward_steps):
+                plan.build_K_spin(C, V, Ds, K2, Ex)
+                plan.exchange_backward_spin(C, V, Ds, 1.0, dC=dCs, dV=dVs, dD=dDs, forces=Fs, K=K2)
+            torch.cuda.synchronize()
+            tsb = (time.perf_counter() - tsb0) / args.backward_steps
+            out["spin"]["forward_backward_ms"] = 1e3 * tsb
+            out["spin"]["net_force_max"] = float(Fs.view(-1, 3).sum(0).abs().max().item())
     if args.two_kernel_steps > 0:
         V2 = torch.from_numpy(synth.short_range_V(inp)).to(dev)
         K2 = torch.empty(2 * plan.info["d_size"], dtype=torch.float64, device=dev)

@@ -338,6 +338,20 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
                       double* dC, double* dV, double* dD, double* forces,
                       double c_decay, double v_2s2, void* stream);
 
+/* Gradients of the collinear-spin energy sum_s gE[s] * E_x[s] with
+ * E_x = -1/2 sum_sigma sum_ik K^sigma_ik D^sigma_ik (build_K_spin; the spin
+ * index of Eq. realspace_exchange selects the density matrix): D, K (optional)
+ * and dD hold two d_size blocks (spin 0, then spin 1); dC, dV, forces as in
+ * exchange_backward.  Each spin's term is twice the one-density energy of
+ * D^sigma, so dC and dV are twice the sum over the spins of the one-density
+ * gradients (formed spin by spin, the second spin into plan-owned buffers and
+ * then added), and dE/dD^sigma = -gE K^sigma.  Clusters, batches and periodic
+ * plans, chunked plans included; precision EXX_PREC_FP64 only. */
+int exchange_backward_spin(exx_plan plan, const double* C, const double* V,
+                           const double* D, const double* K, const double* gE, int precision,
+                           double* dC, double* dV, double* dD, double* forces,
+                           double c_decay, double v_2s2, void* stream);
+
 /* Algorithmic flop count of one stage of build_K (stage -1 = total):
  * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction:
  * 2*m*n*k summed over the structurally nonzero blocks.  Stages 10..14 give

@@ -520,6 +520,20 @@ def gradients(inputs, s=0):
     return dict(E=E, K=K, dC=dC, dV=dV, dD=-0.5 * K, sC=sC, sV=sV, blk=blk)
 
 
+def spin_gradients(inputs, D_spin, s=0):
+    """Gradients of the collinear-spin E_x = -1/2 sum_s sum_ik K^s_ik D^s_ik.
+
+    Each spin's term is twice the one-density energy -1/4 <K(D^s), D^s>, so dC,
+    dV, sC and sV are twice the sums over the spins of the one-density
+    gradients, and dE/dD^s = -K^s (twice the one-density -1/2 K(D^s))."""
+    parts = [gradients(with_density(inputs, D), s) for D in D_spin]
+    out = {k: 2.0 * (parts[0][k] + parts[1][k]) for k in ("E", "dC", "dV", "sC", "sV")}
+    out["K"] = [p["K"] for p in parts]
+    out["dD"] = [2.0 * p["dD"] for p in parts]
+    out["blk"] = parts[0]["blk"]
+    return out
+
+
 def forces(inputs, grads, c_decay=1.5, v_2s2=8.0):
     """-dE/dR_A through C_AB ~ exp(-r/c_decay) and V_AB ~ exp(-r^2/v_2s2).
 

@@ -56,7 +56,7 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
            "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
            "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images", "exx_block_norms",
-           "exx_set_screening", "exx_screened_pairs")
+           "exx_set_screening", "exx_screened_pairs", "exchange_backward_spin")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -82,6 +82,7 @@ def lib():
     L.exchange_energy.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_energy_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exchange_backward_spin.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
     L.exx_block_norms.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -295,6 +296,21 @@ class Plan:
                                        _dev(dD, i["d_size"], "dD", True), _dev(forces, 3 * self.n_atoms, "forces", True),
                                        float(c_decay), float(v_2s2), _stream(stream)))
         self._last_gE = g   # keeps the per-system array alive while the call may still run
+
+    def exchange_backward_spin(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
+                               precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):
+        """Gradients of sum_s gE[s] E_x[s] for the collinear-spin energy of
+        build_K_spin: D, K (optional) and dD hold spin 0 then spin 1."""
+        i = self.info
+        c, v, d = self._cvd(C, V, D, 2)
+        g = self.gE_tensor(gE, C.device)
+        _check(lib().exchange_backward_spin(self._h, c, v, d, _dev(K, 2 * i["d_size"], "K", True),
+                                            _dev(g, self.n_systems, "gE"), int(precision),
+                                            _dev(dC, i["c_size"], "dC", True), _dev(dV, i["v_size"], "dV", True),
+                                            _dev(dD, 2 * i["d_size"], "dD", True),
+                                            _dev(forces, 3 * self.n_atoms, "forces", True),
+                                            float(c_decay), float(v_2s2), _stream(stream)))
+        self._last_gE = g
 
     def graph_build(self, C, V, D, K, Ex, stream, precision=PREC_FP64):
         """Capture one build_K on `stream` (a created stream) into a HIP graph."""

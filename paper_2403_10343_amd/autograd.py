@@ -4,6 +4,8 @@
 mixed forward); its backward calls the library's binary64 exchange_backward
 kernels for dE/dC, dE/dV and dE/dD with each system's upstream gradient,
 reusing the forward K for dE/dD.
+``spin_exchange_energy(plan, C, V, D)`` is the same for the collinear-spin
+energy (two density matrices, binary64).
 ``exchange_forces(plan, C, V, D)`` returns -dE_x/dR for the synthetic
 exp(-r/1.5) / exp(-r^2/8) position dependence of C and V.
 """
@@ -34,6 +36,35 @@ class _ExchangeEnergy(torch.autograd.Function):
             # binary64 gradient kernels; dE/dD = -K/2 reuses the forward K (of either precision)
             ctx.plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K)
         return dC, dV, dD, None, None
+
+
+class _SpinExchangeEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, C, V, D, plan):
+        K = torch.empty(2 * plan.info["d_size"], dtype=torch.float64, device=C.device)
+        Ex = torch.empty(plan.n_systems, dtype=torch.float64, device=C.device)
+        plan.build_K_spin(C, V, D, K, Ex)
+        ctx.save_for_backward(C, V, D, K)
+        ctx.plan = plan
+        return Ex
+
+    @staticmethod
+    def backward(ctx, gEx):
+        C, V, D, K = ctx.saved_tensors
+        gE = gEx.detach().to(torch.float64).contiguous()
+        need = ctx.needs_input_grad
+        dC = torch.empty_like(C) if need[0] else None
+        dV = torch.empty_like(V) if need[1] else None
+        dD = torch.empty_like(D) if need[2] else None
+        if dC is not None or dV is not None or dD is not None:
+            ctx.plan.exchange_backward_spin(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K)
+        return dC, dV, dD, None
+
+
+def spin_exchange_energy(plan, C, V, D):
+    """Collinear-spin E_x = -1/2 sum_s <K^s, D^s> of every system (D: spin 0 then
+    spin 1, 2 d_size), differentiable in C, V and both density matrices."""
+    return _SpinExchangeEnergy.apply(C, V, D, plan)
 
 
 def exchange_energy(plan, C, V, D, precision=PREC_FP64):

@@ -1525,33 +1525,17 @@ static void backward_chunk(exx_plan plan, const double* V, const double* D, doub
   if (needV) launch_dV(plan, V, D, dVb, gE, st);
 }
 
-int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
-                      const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
-                      double c_decay, double v_2s2, void* stream) {
-  if (!plan) return fail(EXX_EINVAL, "exchange_backward: NULL plan");
-  if (plan->host_only) return fail(EXX_ESTATE, "exchange_backward: host-only plan");
-  if (!C || !V || !D || !gE) return fail(EXX_EINVAL, "exchange_backward: NULL input array");
-  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
-    return fail(EXX_EUNSUPPORTED, "exchange_backward: only the binary64 backward is implemented");
-  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "exchange_backward: unknown precision");
-  if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, "exchange_backward: decay lengths must be positive");
-  hipStream_t st = (hipStream_t)stream;
+// One density matrix's part of the backward pass: dD (if asked) from K or a rebuild, and the
+// dC, dV blocks of sum_s gE[s] E_x[s] written (not added) into dCb, dVb.  C is repacked
+// into T when repack is set (it does not depend on D).  (Launches only.)
+static void backward_density(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                             const double* gE, double* dCb, double* dVb, double* dD, bool needC, bool needV,
+                             bool repack, hipStream_t st) {
   const HostPlan& hp = plan->hp;
   DevPlan& d = plan->d;
-  const bool needC = dC || forces, needV = dV || forces;
-  if (needC && !dC && !plan->dC_scratch) {
-    HIP_TRY(hipMalloc((void**)&plan->dC_scratch, sizeof(double) * std::max<int64_t>(1, hp.c_off.back())));
-    plan->allocs.push_back(plan->dC_scratch);
-  }
-  if (needV && !dV && !plan->dV_scratch) {
-    HIP_TRY(hipMalloc((void**)&plan->dV_scratch, sizeof(double) * std::max<int64_t>(1, hp.v_off.back())));
-    plan->allocs.push_back(plan->dV_scratch);
-  }
-  double* dCb = dC ? dC : plan->dC_scratch;
-  double* dVb = dV ? dV : plan->dV_scratch;
   const dim3 gsys(256, hp.n_sys);
   launch_dmask(plan, D, d.Dm, st);
-  launch_repack(plan, C, st);
+  if (repack) launch_repack(plan, C, st);
   launch_vd_operands(plan, V, D, st);
   bool h_ready = false;   // E and H (G taken once) of the only chunk already in place
   if (dD && K) {
@@ -1583,16 +1567,97 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
     }
     set_chunk(plan, 0);
   }
-  if (needC) {
-    hipLaunchKernelGGL(k_unrepack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, d.GD, dCb, d, gE, -1.0);
-    if (forces)
-      hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dCb, C, d.c_off, d.sC);
-  }
-  if (needV && forces)
-    hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dVb, V, d.v_off, d.sV);
-  if (forces)
-    hipLaunchKernelGGL(k_forces, dim3((hp.n_atoms + 127) / 128), dim3(128), 0, st, d.pos, d.sC, d.sV, forces, d,
-                       c_decay, v_2s2);
+  if (needC) hipLaunchKernelGGL(k_unrepack, dim3(hp.nbr_ptr[hp.n_atoms]), dim3(256), 0, st, d.GD, dCb, d, gE, -1.0);
+}
+
+// forces from the summed dC, dV blocks (per-pair <gradient, block> sums, then per atom)
+static void launch_forces(exx_plan plan, const double* C, const double* V, const double* dCb, const double* dVb,
+                          double* forces, double c_decay, double v_2s2, hipStream_t st) {
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dCb, C, d.c_off, d.sC);
+  hipLaunchKernelGGL(k_block_dot, dim3((int)hp.pair_a.size()), dim3(256), 0, st, dVb, V, d.v_off, d.sV);
+  hipLaunchKernelGGL(k_forces, dim3((hp.n_atoms + 127) / 128), dim3(128), 0, st, d.pos, d.sC, d.sV, forces, d,
+                     c_decay, v_2s2);
+}
+
+static int backward_checks(exx_plan plan, const char* who, const double* C, const double* V, const double* D,
+                           const double* gE, int precision, const double* forces, double c_decay, double v_2s2) {
+  const std::string w(who);
+  if (!plan) return fail(EXX_EINVAL, w + ": NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, w + ": host-only plan");
+  if (!C || !V || !D || !gE) return fail(EXX_EINVAL, w + ": NULL input array");
+  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
+    return fail(EXX_EUNSUPPORTED, w + ": only the binary64 backward is implemented");
+  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, w + ": unknown precision");
+  if (forces && (!(c_decay > 0) || !(v_2s2 > 0))) return fail(EXX_EINVAL, w + ": decay lengths must be positive");
+  return EXX_OK;
+}
+
+// plan-owned gradient buffers of size n (allocated on first use)
+static int scratch_buf(exx_plan plan, double*& buf, int64_t n) {
+  if (buf) return EXX_OK;
+  HIP_TRY(hipMalloc((void**)&buf, sizeof(double) * std::max<int64_t>(1, n)));
+  plan->allocs.push_back(buf);
+  return EXX_OK;
+}
+
+int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                      const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
+                      double c_decay, double v_2s2, void* stream) {
+  int rc = backward_checks(plan, "exchange_backward", C, V, D, gE, precision, forces, c_decay, v_2s2);
+  if (rc != EXX_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  const bool needC = dC || forces, needV = dV || forces;
+  if (needC && !dC && (rc = scratch_buf(plan, plan->dC_scratch, hp.c_off.back())) != EXX_OK) return rc;
+  if (needV && !dV && (rc = scratch_buf(plan, plan->dV_scratch, hp.v_off.back())) != EXX_OK) return rc;
+  double* dCb = dC ? dC : plan->dC_scratch;
+  double* dVb = dV ? dV : plan->dV_scratch;
+  backward_density(plan, C, V, D, K, gE, dCb, dVb, dD, needC, needV, true, st);
+  if (forces) launch_forces(plan, C, V, dCb, dVb, forces, c_decay, v_2s2, st);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+// y += x over n doubles
+__global__ void k_add(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
+// gE2 = a gE over n values
+__global__ void k_scale_vec(double* __restrict__ y, const double* __restrict__ x, double a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+int exchange_backward_spin(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                           const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
+                           double c_decay, double v_2s2, void* stream) {
+  int rc = backward_checks(plan, "exchange_backward_spin", C, V, D, gE, precision, forces, c_decay, v_2s2);
+  if (rc != EXX_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  const int64_t ds = hp.d_size, nc = hp.c_off.back(), nv = hp.v_off.back();
+  const bool needC = dC || forces, needV = dV || forces;
+  if (needC && !dC && (rc = scratch_buf(plan, plan->dC_scratch, nc)) != EXX_OK) return rc;
+  if (needV && !dV && (rc = scratch_buf(plan, plan->dV_scratch, nv)) != EXX_OK) return rc;
+  if (needC && (rc = scratch_buf(plan, plan->dC_spin1, nc)) != EXX_OK) return rc;
+  if (needV && (rc = scratch_buf(plan, plan->dV_spin1, nv)) != EXX_OK) return rc;
+  if ((rc = scratch_buf(plan, plan->gE_spin, hp.n_sys)) != EXX_OK) return rc;
+  double* dCb = dC ? dC : plan->dC_scratch;
+  double* dVb = dV ? dV : plan->dV_scratch;
+  // E_x = -1/2 sum_s K^s D^s is twice the one-density energy of each spin, so each spin
+  // is the one-density backward with upstream 2 gE
+  hipLaunchKernelGGL(k_scale_vec, dim3((hp.n_sys + 255) / 256), dim3(256), 0, st, plan->gE_spin, gE, 2.0, hp.n_sys);
+  for (int s = 0; s < 2; ++s)
+    backward_density(plan, C, V, D + s * ds, K ? K + s * ds : nullptr, plan->gE_spin,
+                     s ? plan->dC_spin1 : dCb, s ? plan->dV_spin1 : dVb, dD ? dD + s * ds : nullptr, needC, needV,
+                     s == 0, st);
+  if (needC) hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dCb, plan->dC_spin1, nc);
+  if (needV) hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dVb, plan->dV_spin1, nv);
+  if (forces) launch_forces(plan, C, V, dCb, dVb, forces, c_decay, v_2s2, st);
   HIP_TRY(hipGetLastError());
   return EXX_OK;
 }

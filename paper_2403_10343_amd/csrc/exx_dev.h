@@ -231,6 +231,9 @@ struct exx_plan_s {
   hipGraphExec_t graph_exec = nullptr;
   double* dC_scratch = nullptr;     // gradient buffers used when the caller passes NULL
   double* dV_scratch = nullptr;
+  double* dC_spin1 = nullptr;       // the second spin's dC, dV (exchange_backward_spin), and 2 gE
+  double* dV_spin1 = nullptr;
+  double* gE_spin = nullptr;
   double* spin_E1 = nullptr;        // E and H' of the second spin (build_K_spin), allocated on first use
   double* spin_H1 = nullptr;
   double* spin_Dr1 = nullptr;       // lane-ordered D operands of the second spin

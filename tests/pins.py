@@ -412,6 +412,52 @@ def pin_spin(seed=14):
     return ok, f"K {r:.1e}, E(D/2, D/2) {e_half:.12e} vs {e_cs:.12e}, E {e_spin:.12e} vs {e_direct:.12e}"
 
 
+def pin_spin_gradients(seed=21, h=1e-4, n_entries=4):
+    """Collinear-spin gradients against central differences of the spin energy
+    -1/2 sum_s <K(D^s), D^s> (evaluated from the 4-index tensor) in stored C and
+    V entries and in symmetric entry pairs of D^0 and of D^1 (unequal spins)."""
+    sysm = synth.water_cluster(2, seed)
+    inp, C3, Vd, Dd = random_problem(sysm, seed)
+    n = Dd.shape[0]
+    rng = np.random.default_rng(seed)
+    S = rng.normal(size=(n, n))
+    D0 = 0.5 * (Dd + 0.4 * (S + S.T))
+    D1 = Dd - D0
+    Ds = [D0.ravel().copy(), D1.ravel().copy()]
+    g = O.spin_gradients(inp, Ds)
+
+    def energy():
+        Ks = O.k_spin(inp, Ds, route="4index")
+        return O.spin_exchange_energy(Ks, [x.reshape(n, n) for x in Ds])
+
+    worst = 0.0
+    for arr_name in ("C", "V"):
+        arr = getattr(inp, arr_name)
+        for idx in rng.integers(0, arr.size, n_entries):
+            a0 = arr[idx]
+            arr[idx] = a0 + h
+            ep = energy()
+            arr[idx] = a0 - h
+            em = energy()
+            arr[idx] = a0
+            an = g["d" + arr_name][idx]
+            worst = max(worst, abs((ep - em) / (2 * h) - an) / max(abs(an), 1e-3))
+    for sp in (0, 1):
+        Dm = Ds[sp].reshape(n, n)
+        for _ in range(n_entries):
+            i, k = (int(x) for x in rng.integers(0, n, 2))
+            d0 = Dm[i, k]
+            Dm[i, k] = Dm[k, i] = d0 + h
+            ep = energy()
+            Dm[i, k] = Dm[k, i] = d0 - h
+            em = energy()
+            Dm[i, k] = Dm[k, i] = d0
+            an = g["dD"][sp][i, k] * (1 if i == k else 2)
+            worst = max(worst, abs((ep - em) / (2 * h) - an) / max(abs(an), 1e-3))
+    e_ok = abs(g["E"] - energy()) <= TOL * abs(g["E"])
+    return worst < 1e-6 and e_ok, f"worst rel {worst:.1e}, energy {e_ok}"
+
+
 def pin_two_kernels(seed=15):
     """Two Coulomb matrices: the second K against brute force over dense
     arrays (C V2 C contracted with D by einsum), the first unchanged, and
@@ -606,4 +652,5 @@ ALL_PINS = {
     "periodic_vacuum": pin_periodic_vacuum,
     "periodic_supercell": pin_periodic_supercell,
     "norm_estimates": pin_norm_estimates,
+    "spin_gradients": pin_spin_gradients,
 }

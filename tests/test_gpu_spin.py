@@ -122,3 +122,125 @@ def test_spin_rejects_mixed(exx):
         C, V, _ = device_inputs(inp, torch)
         plan.build_K_spin(C, V, spin_build_mixed, torch.empty_like(spin_build_mixed),
                           precision=exx.PREC_MIXED)
+
+
+def _spin_grads(plan, inp, Ds, gE=1.0, K=None):
+    dev = "cuda:0"
+    C, V, _ = device_inputs(inp, torch)
+    D2 = torch.from_numpy(np.ascontiguousarray(Ds.reshape(-1))).to(dev)
+    dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D2)
+    F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device=dev)
+    plan.exchange_backward_spin(C, V, D2, gE, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+    torch.cuda.synchronize()
+    return {"dC": dC.cpu().numpy(), "dV": dV.cpu().numpy(), "dD": dD.cpu().numpy().reshape(2, -1),
+            "F": F.cpu().numpy().reshape(-1, 3)}
+
+
+@pytest.mark.parametrize("n_mol,seed", [(2, 4), (8, 5)])
+def test_spin_backward_matches_oracle(exx, n_mol, seed):
+    """dE/dC, dE/dV, dE/dD^s and forces of the spin energy against the oracle's
+    spin gradients (pinned by central differences of the spin energy)."""
+    sysm = synth.water_cluster(n_mol, seed)
+    inp = synth.make_inputs(sysm)
+    Ds = synth.spin_densities(inp)
+    plan = exx.Plan.for_system(sysm)
+    g = _spin_grads(plan, inp, Ds)
+    go = O.spin_gradients(inp, Ds)
+    print(f"spin backward, {n_mol} waters: dC {relmax(g['dC'], go['dC']):.1e}, dV {relmax(g['dV'], go['dV']):.1e}",
+          flush=True)
+    assert relmax(g["dC"], go["dC"]) < 1e-10 and relmax(g["dV"], go["dV"]) < 1e-10
+    for s in range(2):
+        assert relmax(system_block(g["dD"][s], inp.layout, 0), go["dD"][s]) < 1e-10
+    assert relmax(g["F"], O.forces(inp, go)) < 1e-10
+
+
+def test_spin_backward_identities(exx):
+    """768-atom box, in a chunked plan too: K^s passed in gives dD^s = -K^s
+    exactly; equal spins D/2, D/2 give the one-density gradients of D; the spin
+    gradients are twice the one-density gradients of D^0 plus those of D^1
+    (each spin's term is twice a one-density energy)."""
+    sysm = synth.config(2)
+    inp = synth.make_inputs(sysm)
+    Ds = synth.spin_densities(inp)
+    plan = exx.Plan.for_system(sysm)
+    K2, _ = spin_build(plan, inp, Ds)
+    g = _spin_grads(plan, inp, Ds)
+    gk = _spin_grads(plan, inp, Ds, K=torch.from_numpy(K2.reshape(-1)).to("cuda:0"))
+    assert np.array_equal(gk["dD"], -K2)
+    assert relmax(gk["dD"], g["dD"]) < 1e-12
+    assert relmax(gk["dC"], g["dC"]) < 1e-12 and np.array_equal(gk["dV"], g["dV"])
+
+    def one(D, gE):
+        C, V, Dd = device_inputs(O.with_density(inp, D), torch)
+        dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(Dd)
+        F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device="cuda:0")
+        plan.exchange_backward(C, V, Dd, gE, dC=dC, dV=dV, dD=dD, forces=F)
+        torch.cuda.synchronize()
+        return {"dC": dC.cpu().numpy(), "dV": dV.cpu().numpy(), "dD": dD.cpu().numpy(),
+                "F": F.cpu().numpy().reshape(-1, 3)}
+
+    g0, g1 = one(Ds[0], 2.0), one(Ds[1], 2.0)
+    for k in ("dC", "dV", "F"):
+        assert relmax(g[k], g0[k] + g1[k]) < 1e-12, k
+    assert np.array_equal(g["dD"][0], g0["dD"]) and np.array_equal(g["dD"][1], g1["dD"])
+    half = np.stack([0.5 * inp.D, 0.5 * inp.D])
+    gh, gd = _spin_grads(plan, inp, half), one(inp.D, 1.0)
+    for k in ("dC", "dV", "F"):
+        assert relmax(gh[k], gd[k]) < 1e-12, k
+    part = exx.Plan.for_system(sysm, ws_budget_bytes=plan.info["intermediate_bytes_stored"] // 4)
+    gp = _spin_grads(part, inp, Ds)
+    for k in ("dC", "dV", "dD", "F"):
+        assert relmax(gp[k], g[k]) < 1e-12, k
+
+
+def test_spin_backward_periodic(exx):
+    """Periodic cell: equal spins give the one-density gradients of D, and
+    unequal spins twice the sum of the one-density gradients of each spin."""
+    cell = synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4)
+    inp = synth.make_inputs(cell)
+    Ds = synth.spin_densities(inp)
+    plan = exx.Plan.for_system(cell)
+    g = _spin_grads(plan, inp, Ds)
+
+    def one(D, gE):
+        C, V, Dd = device_inputs(O.with_density(inp, D), torch)
+        dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(Dd)
+        F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device="cuda:0")
+        plan.exchange_backward(C, V, Dd, gE, dC=dC, dV=dV, dD=dD, forces=F)
+        torch.cuda.synchronize()
+        return {"dC": dC.cpu().numpy(), "dV": dV.cpu().numpy(), "dD": dD.cpu().numpy(),
+                "F": F.cpu().numpy().reshape(-1, 3)}
+
+    g0, g1 = one(Ds[0], 2.0), one(Ds[1], 2.0)
+    for k in ("dC", "dV", "F"):
+        assert relmax(g[k], g0[k] + g1[k]) < 1e-12, k
+    half = np.stack([0.5 * inp.D, 0.5 * inp.D])
+    gh, gd = _spin_grads(plan, inp, half), one(inp.D, 1.0)
+    for k in ("dC", "dV", "F"):
+        assert relmax(gh[k], gd[k]) < 1e-12, k
+    with pytest.raises(exx.ExxError) as e:
+        C, V, _ = device_inputs(inp, torch)
+        D2 = torch.from_numpy(np.ascontiguousarray(Ds.reshape(-1))).to("cuda:0")
+        plan.exchange_backward_spin(C, V, D2, 1.0, dC=torch.empty_like(C), precision=exx.PREC_MIXED)
+    assert e.value.code == -5
+
+
+def test_spin_autograd(exx):
+    """torch.autograd through the spin energy: the gradients of a weighted sum
+    of the per-system energies of a batch equal exchange_backward_spin's."""
+    b = synth.cluster_batch(3, n_min=6, n_max=18)
+    inp = synth.make_inputs(b)
+    Ds = synth.spin_densities(inp)
+    plan = exx.Plan.for_system(b)
+    C, V, _ = device_inputs(inp, torch)
+    D2 = torch.from_numpy(np.ascontiguousarray(Ds.reshape(-1))).to("cuda:0")
+    C.requires_grad_(True)
+    D2.requires_grad_(True)
+    w = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device="cuda:0")
+    E = exx.spin_exchange_energy(plan, C, V, D2)
+    (w * E).sum().backward()
+    dC, dD = torch.empty_like(C), torch.empty_like(D2)
+    plan.exchange_backward_spin(C.detach(), V, D2.detach(), w, dC=dC, dD=dD)
+    torch.cuda.synchronize()
+    assert relmax(C.grad.cpu().numpy(), dC.cpu().numpy()) < 1e-12
+    assert relmax(D2.grad.cpu().numpy(), dD.cpu().numpy()) < 1e-12

@@ -47,6 +47,8 @@ MUTATIONS = {
     "estimate_max_for_min": ("* min(sigma[a], sigma[b])", "* max(sigma[a], sigma[b]) * 0.5"),
     "norms_C_first_atom_only": ("out[p, 0] = np.abs(inputs.C[lay.c_off[p]:lay.c_off[p + 1]]).max()",
                                 "out[p, 0] = np.abs(inputs.C[lay.c_off[p]:(lay.c_off[p] + lay.c_off[p + 1]) // 2]).max()"),
+    "spin_gradient_factor": ("out = {k: 2.0 * (parts[0][k] + parts[1][k]) for k in", "out = {k: (parts[0][k] + parts[1][k]) for k in"),
+    "spin_dD_one_density": ('out["dD"] = [2.0 * p["dD"] for p in parts]', 'out["dD"] = [p["dD"] for p in parts]'),
     "screened_V_neighbour_block": ("        V[lay.v_off[p]:lay.v_off[p + 1]] = 0.0",
                                    "        V[lay.v_off[p]:lay.v_off[p + 1] - 1] = 0.0"),
 }
