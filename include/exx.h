@@ -192,10 +192,12 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D,
  * K: device output, 2 * d_size doubles, K^0 then K^1 (each exactly symmetric).
  * Ex: NULL, or device [n_systems]: E_x = -1/2 sum_s sum_ik K^s_ik D^s_ik
  * (with D^0 = D^1 = D/2 this is the E_x of build_K for D).
- * The repack of C and the F = V C part of the V stage (Eq. temp_F) are formed
- * once for both spins.  precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns
- * EXX_EUNSUPPORTED, and so does a plan split into chunks by a workspace
- * budget).  Clusters and periodic plans.  The first call allocates a second E
+ * The repack of C and E = M D^s for both spins run once; in binary64 the
+ * F = V C part of the V stage (Eq. temp_F) is also formed once for both
+ * spins.  precision as in build_K: mixed and FP32 run the V stage, T2 and
+ * the final contraction of that precision per spin (each K^s equals build_K
+ * of D^s in that precision bit for bit).  A plan split into chunks by a
+ * workspace budget returns EXX_EUNSUPPORTED.  Clusters and periodic plans.  The first call allocates a second E
  * and H' workspace (EXX_ENOMEM if that fails); calls on one plan must not
  * overlap. */
 int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D,
@@ -209,9 +211,10 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
  * [2 * n_systems]: E_x of K^0 for every system, then of K^1 (each as in
  * exchange_energy).  The repack of C and E = M D (Eq. temp_E) are shared by
  * both kernels; the V stage, T2 and the final contraction run per kernel.
- * precision: EXX_PREC_FP64 only (EXX_PREC_MIXED returns EXX_EUNSUPPORTED, and
- * so does a chunked plan).  Clusters and periodic plans.  Uses the second
- * workspace of build_K_spin (allocated on first use). */
+ * precision as in build_K (mixed and FP32 split each kernel's pair terms the
+ * same way; each K^a equals build_K with V^a in that precision bit for bit).
+ * A chunked plan returns EXX_EUNSUPPORTED.  Clusters and periodic plans.  Uses
+ * the second workspace of build_K_spin (allocated on first use). */
 int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2,
                         const double* D, int precision, double* K, double* Ex, void* stream);
 

@@ -1200,14 +1200,15 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (plan->host_only) return fail(EXX_ESTATE, "build_K_spin: host-only plan");
   if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K_spin: NULL array");
   if (plan->scr_eps > 0) return fail(EXX_EUNSUPPORTED, "build_K_spin: norm screening applies to build_K only");
-  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
-    return fail(EXX_EUNSUPPORTED, "build_K_spin: only the binary64 build takes two spins");
-  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_spin: unknown precision");
+  int m = -1;
+  int rc = check_precision("build_K_spin", precision, m);
+  if (rc != EXX_OK) return rc;
   if (n_chunks(plan) > 1)
     return fail(EXX_EUNSUPPORTED, "build_K_spin: needs an unbounded workspace (the plan is chunked)");
+  if (m >= 0 && (rc = prepare_mixed(plan, m)) != EXX_OK) return rc;
   const HostPlan& hp = plan->hp;
   const int64_t ds = hp.d_size;
-  {
+  if (m < 0) {
     static const int t2c[3][2] = {{4, 4}, {8, 4}, {8, 8}};
     const int* cw = t2c[std::min(std::max(plan->tune[TUNE_T2], 0), 2)];
     if (t2_lds_bytes(plan->h_smax_t2, sizeof(double), cw[0], cw[1], 2) > (size_t)plan->lds_max)
@@ -1227,27 +1228,43 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   stage_mark(plan, 1, st);
   launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), cur_chunk(plan).n_e, st);
   stage_mark(plan, 2, st);
-  launch_vd_operands(plan, V, D, st);   // V and D^0 operands
-  if (!hp.pair_a.empty())
-    hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
-                       plan->spin_Dr1, plan->d, 0);   // D^1 operands
-  launch_H_lists<double, 2>(plan, V, D,
-                            HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
-                                   plan->spin_H1, plan->spin_Dr1},
-                            (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
-  stage_mark(plan, 3, st);
-  stage_mark(plan, 4, st);
-  launch_T2_spin(plan, V, K, st);
-  stage_mark(plan, 5, st);
-  stage_mark(plan, 6, st);
+  double* const E0 = d.E;
   double* const H0 = d.H;
-  launch_final(plan, K, st);
-  d.H = plan->spin_H1;
-  launch_final(plan, K + ds, st);
-  d.H = H0;
+  if (m >= 0) {
+    // mixed / FP32: per spin the V stage, T2 and the final contraction of a mixed build_K,
+    // with E and H' pointed at that spin's workspace (F is not shared between the spins)
+    for (int s = 0; s < 2; ++s) {
+      d.E = s ? plan->spin_E1 : E0;
+      d.H = s ? plan->spin_H1 : H0;
+      launch_vd_operands(plan, V, D + s * ds, st, true);
+      launch_H_mixed(plan, m, V, D + s * ds, st);
+      launch_T2(plan, V, K + s * ds, st, m, 0);
+      launch_T2(plan, V, K + s * ds, st, m, 1);
+      launch_final(plan, K + s * ds, st);
+    }
+    d.E = E0;
+    d.H = H0;
+  } else {
+    launch_vd_operands(plan, V, D, st);   // V and D^0 operands
+    if (!hp.pair_a.empty())
+      hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
+                         plan->spin_Dr1, plan->d, 0);   // D^1 operands
+    launch_H_lists<double, 2>(plan, V, D,
+                              HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
+                                     plan->spin_H1, plan->spin_Dr1},
+                              (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
+    stage_mark(plan, 3, st);
+    stage_mark(plan, 4, st);
+    launch_T2_spin(plan, V, K, st);
+    stage_mark(plan, 5, st);
+    stage_mark(plan, 6, st);
+    launch_final(plan, K, st);
+    d.H = plan->spin_H1;
+    launch_final(plan, K + ds, st);
+    d.H = H0;
+  }
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
-  int rc = EXX_OK;
   if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
   stage_mark(plan, 8, st);
   return rc;
@@ -1266,11 +1283,12 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   if (!C || !V || !V2 || !D || !K) return fail(EXX_EINVAL, "build_K_two_kernels: NULL array");
   if (plan->scr_eps > 0)
     return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: norm screening applies to build_K only");
-  if (precision == EXX_PREC_MIXED || precision == EXX_PREC_FP32 || precision == EXX_PREC_BF16X3)
-    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: only the binary64 build takes two Coulomb matrices");
-  if (precision != EXX_PREC_FP64) return fail(EXX_EINVAL, "build_K_two_kernels: unknown precision");
+  int m = -1;
+  int rc = check_precision("build_K_two_kernels", precision, m);
+  if (rc != EXX_OK) return rc;
   if (n_chunks(plan) > 1)
     return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: needs an unbounded workspace (the plan is chunked)");
+  if (m >= 0 && (rc = prepare_mixed(plan, m)) != EXX_OK) return rc;
   const int rcw = second_workspace(plan);
   if (rcw != EXX_OK) return rcw;
   const HostPlan& hp = plan->hp;
@@ -1287,15 +1305,18 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   launch_E(plan, st);
   stage_mark(plan, 2, st);
   // T2 reads the lane-ordered copy of the V operands that the V stage reads: each Coulomb
-  // matrix's operands are written before its own V stage
-  launch_vd_operands(plan, V, D, st);
-  launch_H(plan, V, D, 2.0, H_WRITE, st);
-  launch_T2(plan, V, K, st);
-  d.H = plan->spin_H1;
-  launch_vd_operands(plan, V2, D, st);
-  launch_H(plan, V2, D, 2.0, H_WRITE, st);
-  d.H = H0;
-  launch_T2(plan, V2, K + ds, st);
+  // matrix's operands (binary32 copies too for a mixed build) are written before its own
+  // V stage, and its T2 blocks run before the next matrix's operands replace them
+  const double* Va[2] = {V, V2};
+  for (int a = 0; a < 2; ++a) {
+    d.H = a ? plan->spin_H1 : H0;
+    launch_vd_operands(plan, Va[a], D, st, m >= 0);
+    if (m >= 0) launch_H_mixed(plan, m, Va[a], D, st);
+    else launch_H(plan, Va[a], D, 2.0, H_WRITE, st);
+    d.H = H0;
+    launch_T2(plan, Va[a], K + a * ds, st, m, 0);
+    if (m >= 0) launch_T2(plan, Va[a], K + a * ds, st, m, 1);
+  }
   stage_mark(plan, 3, st);
   stage_mark(plan, 4, st);
   stage_mark(plan, 5, st);
@@ -1306,7 +1327,6 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   d.H = H0;
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
-  int rc = EXX_OK;
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
   if (Ex && rc == EXX_OK) rc = launch_energy(plan, K + ds, D, Ex + hp.n_sys, st);
   stage_mark(plan, 8, st);

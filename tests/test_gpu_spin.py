@@ -113,15 +113,37 @@ def test_spin_equals_one_density_builds_768(exx):
     assert abs(Eh[0] - E1.item()) <= 1e-13 * abs(E1.item())
 
 
-def test_spin_rejects_mixed(exx):
-    sysm = synth.water_cluster(1, 1)
+def test_spin_mixed_and_fp32(exx):
+    """Mixed and all-FP32 spin builds on the 768-atom box: each K^s equals the
+    one-density build_K of D^s in the same precision bit for bit, and the mixed
+    K^s and E_x are within the mixed bar of the FP64 spin build."""
+    sysm = synth.config(2)
     inp = synth.make_inputs(sysm)
+    Ds = synth.spin_densities(inp)
     plan = exx.Plan.for_system(sysm)
-    with pytest.raises(exx.ExxError):
-        spin_build_mixed = torch.zeros(2 * plan.info["d_size"], dtype=torch.float64, device="cuda:0")
-        C, V, _ = device_inputs(inp, torch)
-        plan.build_K_spin(C, V, spin_build_mixed, torch.empty_like(spin_build_mixed),
-                          precision=exx.PREC_MIXED)
+    dev = "cuda:0"
+    C, V, _ = device_inputs(inp, torch)
+    D2 = torch.from_numpy(np.ascontiguousarray(Ds.reshape(-1))).to(dev)
+    n = plan.info["d_size"]
+    K64, E64 = spin_build(plan, inp, Ds)
+    for prec in (exx.PREC_MIXED, exx.PREC_FP32):
+        K2 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        Ex = torch.empty(1, dtype=torch.float64, device=dev)
+        plan.build_K_spin(C, V, D2, K2, Ex, precision=prec)
+        torch.cuda.synchronize()
+        Km = K2.cpu().numpy().reshape(2, n)
+        for s in range(2):
+            K1 = torch.empty(n, dtype=torch.float64, device=dev)
+            plan.build_K(C, V, torch.from_numpy(np.ascontiguousarray(Ds[s])).to(dev), K1, precision=prec)
+            torch.cuda.synchronize()
+            assert np.array_equal(Km[s], K1.cpu().numpy())
+        if prec == exx.PREC_MIXED:
+            dK, dE = np.abs(Km - K64).max(), abs(Ex.item() - E64[0]) / sysm.n_atoms
+            print(f"mixed spin: max|dK| {dK:.2e}, |dE|/atom {dE:.2e}", flush=True)
+            assert dK <= 1e-5 and dE <= 1e-6
+    with pytest.raises(exx.ExxError) as e:
+        plan.build_K_spin(C, V, D2, torch.empty(2 * n, dtype=torch.float64, device=dev), precision=exx.PREC_BF16X3)
+    assert e.value.code == -5
 
 
 def _spin_grads(plan, inp, Ds, gE=1.0, K=None):

@@ -21,25 +21,25 @@ def exx():
     return m
 
 
-def two_build(plan, inp, V2):
+def two_build(plan, inp, V2, precision=0):
     dev = "cuda:0"
     C, V, D = device_inputs(inp, torch)
     V2d = torch.from_numpy(np.ascontiguousarray(V2)).to(dev)
     n = plan.info["d_size"]
     K2 = torch.empty(2 * n, dtype=torch.float64, device=dev)
     Ex = torch.empty(2 * plan.n_systems, dtype=torch.float64, device=dev)
-    plan.build_K_two_kernels(C, V, V2d, D, K2, Ex)
+    plan.build_K_two_kernels(C, V, V2d, D, K2, Ex, precision=precision)
     torch.cuda.synchronize()
     return K2.cpu().numpy().reshape(2, n), Ex.cpu().numpy().reshape(2, plan.n_systems)
 
 
-def one_build(plan, inp, Vx):
+def one_build(plan, inp, Vx, precision=0):
     dev = "cuda:0"
     C, _, D = device_inputs(inp, torch)
     Vd = torch.from_numpy(np.ascontiguousarray(Vx)).to(dev)
     K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=dev)
     Ex = torch.empty(plan.n_systems, dtype=torch.float64, device=dev)
-    plan.build_K(C, Vd, D, K, Ex)
+    plan.build_K(C, Vd, D, K, Ex, precision=precision)
     torch.cuda.synchronize()
     return K.cpu().numpy(), Ex.cpu().numpy()
 
@@ -102,11 +102,22 @@ def test_two_kernels_equal_one_kernel_builds_768(exx):
     assert np.array_equal(Ks[0], Ks[1])
 
 
-def test_two_kernels_rejects_mixed(exx):
-    sysm = synth.water_cluster(1, 1)
+def test_two_kernels_mixed_and_fp32(exx):
+    """Mixed and all-FP32 two-kernel builds on the 768-atom box: each K^a equals
+    build_K with V^a in the same precision bit for bit, and the mixed results
+    are within the mixed bar of the FP64 two-kernel results."""
+    sysm = synth.config(2)
     inp = synth.make_inputs(sysm)
     plan = exx.Plan.for_system(sysm)
-    C, V, D = device_inputs(inp, torch)
-    K = torch.empty(2 * plan.info["d_size"], dtype=torch.float64, device="cuda:0")
-    with pytest.raises(exx.ExxError):
-        plan.build_K_two_kernels(C, V, V, D, K, precision=exx.PREC_MIXED)
+    V2 = synth.short_range_V(inp)
+    K64, E64 = two_build(plan, inp, V2)
+    for prec in (exx.PREC_MIXED, exx.PREC_FP32):
+        K2, Ex = two_build(plan, inp, V2, prec)
+        for a, Vx in enumerate((inp.V, V2)):
+            K1, E1 = one_build(plan, inp, Vx, prec)
+            assert np.array_equal(K2[a], K1) and np.array_equal(Ex[a], E1)
+        if prec == exx.PREC_MIXED:
+            for a in range(2):
+                dK, dE = np.abs(K2[a] - K64[a]).max(), abs(Ex[a, 0] - E64[a, 0]) / sysm.n_atoms
+                print(f"mixed, kernel {a}: max|dK| {dK:.2e}, |dE|/atom {dE:.2e}", flush=True)
+                assert dK <= 1e-5 and dE <= 1e-6
