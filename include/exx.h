@@ -149,8 +149,9 @@ typedef struct {
  * EXX_ENOMEM if one V-stage group (at most three neighbouring atoms) alone
  * needs more than the bound.  Clusters and periodic plans (in a small
  * periodic cell nearly every atom neighbours every group, so the smallest
- * budget there is close to the stored layout's).  Collinear-spin and two-kernel builds need the
- * unbounded layout (EXX_EUNSUPPORTED on a chunked plan). */
+ * budget there is close to the stored layout's).  Collinear-spin and
+ * two-kernel builds on a chunked plan run chunk by chunk too; their second
+ * result's E and H' take one more chunk-sized workspace (outside the bound). */
 int exx_plan_create(const exx_system* sys, uint32_t flags, size_t ws_budget_bytes, exx_plan* out);
 
 /* Release the plan and its device memory (after work on it has finished). */
@@ -196,10 +197,10 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D,
  * F = V C part of the V stage (Eq. temp_F) is also formed once for both
  * spins.  precision as in build_K: mixed and FP32 run the V stage, T2 and
  * the final contraction of that precision per spin (each K^s equals build_K
- * of D^s in that precision bit for bit).  A plan split into chunks by a
- * workspace budget returns EXX_EUNSUPPORTED.  Clusters and periodic plans.  The first call allocates a second E
- * and H' workspace (EXX_ENOMEM if that fails); calls on one plan must not
- * overlap. */
+ * of D^s in that precision bit for bit).  Clusters and periodic plans,
+ * chunked plans included (chunk by chunk).  The first call allocates a second
+ * E and H' workspace (of the largest chunk's size on a chunked plan;
+ * EXX_ENOMEM if that fails); calls on one plan must not overlap. */
 int build_K_spin(exx_plan plan, const double* C, const double* V, const double* D,
                  int precision, double* K, double* Ex, void* stream);
 
@@ -213,8 +214,9 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
  * both kernels; the V stage, T2 and the final contraction run per kernel.
  * precision as in build_K (mixed and FP32 split each kernel's pair terms the
  * same way; each K^a equals build_K with V^a in that precision bit for bit).
- * A chunked plan returns EXX_EUNSUPPORTED.  Clusters and periodic plans.  Uses
- * the second workspace of build_K_spin (allocated on first use). */
+ * Clusters and periodic plans, chunked plans included (chunk by chunk: E once
+ * per chunk, then both kernels).  Uses the second workspace of build_K_spin
+ * (allocated on first use). */
 int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const double* V2,
                         const double* D, int precision, double* K, double* Ex, void* stream);
 

@@ -1174,7 +1174,13 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
 // E and H' workspaces of a second result (build_K_spin, build_K_two_kernels), allocated once
 static int second_workspace(exx_plan plan) {
   if (plan->spin_E1) return EXX_OK;
-  const int64_t ne = std::max<int64_t>(1, plan->hp.e_total);
+  // E and H' of the second result in the layout of one chunk (the whole plan when unbounded)
+  int64_t ne = plan->hp.e_total;
+  if (!plan->hp.chunks.empty()) {
+    ne = 0;
+    for (const ChunkHost& c : plan->hp.chunks) ne = std::max(ne, std::max(c.e_total, c.h_total));
+  }
+  ne = std::max<int64_t>(1, ne);
   HIP_TRY(hipMalloc((void**)&plan->spin_E1, sizeof(double) * ne));
   plan->allocs.push_back(plan->spin_E1);
   HIP_TRY(hipMalloc((void**)&plan->spin_H1, sizeof(double) * ne));
@@ -1203,8 +1209,6 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   int m = -1;
   int rc = check_precision("build_K_spin", precision, m);
   if (rc != EXX_OK) return rc;
-  if (n_chunks(plan) > 1)
-    return fail(EXX_EUNSUPPORTED, "build_K_spin: needs an unbounded workspace (the plan is chunked)");
   if (m >= 0 && (rc = prepare_mixed(plan, m)) != EXX_OK) return rc;
   const HostPlan& hp = plan->hp;
   const int64_t ds = hp.d_size;
@@ -1225,44 +1229,56 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   launch_dmask(plan, D, d.Dm, st);
   launch_dmask(plan, D + ds, plan->spin_Dm1, st);
   launch_repack(plan, C, st);
-  stage_mark(plan, 1, st);
-  launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), cur_chunk(plan).n_e, st);
-  stage_mark(plan, 2, st);
-  double* const E0 = d.E;
-  double* const H0 = d.H;
-  if (m >= 0) {
-    // mixed / FP32: per spin the V stage, T2 and the final contraction of a mixed build_K,
-    // with E and H' pointed at that spin's workspace (F is not shared between the spins)
-    for (int s = 0; s < 2; ++s) {
-      d.E = s ? plan->spin_E1 : E0;
-      d.H = s ? plan->spin_H1 : H0;
-      launch_vd_operands(plan, V, D + s * ds, st, true);
-      launch_H_mixed(plan, m, V, D + s * ds, st);
-      launch_T2(plan, V, K + s * ds, st, m, 0);
-      launch_T2(plan, V, K + s * ds, st, m, 1);
-      launch_final(plan, K + s * ds, st);
-    }
-    d.E = E0;
-    d.H = H0;
-  } else {
+  if (m < 0) {
     launch_vd_operands(plan, V, D, st);   // V and D^0 operands
     if (!hp.pair_a.empty())
       hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
                          plan->spin_Dr1, plan->d, 0);   // D^1 operands
-    launch_H_lists<double, 2>(plan, V, D,
-                              HLists{d.g_tiles, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
-                                     plan->spin_H1, plan->spin_Dr1},
-                              (int)hp.g_tiles.size(), 2.0, H_WRITE, st);
-    stage_mark(plan, 3, st);
-    stage_mark(plan, 4, st);
-    launch_T2_spin(plan, V, K, st);
-    stage_mark(plan, 5, st);
-    stage_mark(plan, 6, st);
-    launch_final(plan, K, st);
-    d.H = plan->spin_H1;
-    launch_final(plan, K + ds, st);
-    d.H = H0;
   }
+  stage_mark(plan, 1, st);
+  // per chunk of aux atoms (one for an unbounded plan): E^s for both spins, then the rest
+  for (int c = 0; c < n_chunks(plan); ++c) {
+    set_chunk(plan, c);
+    const ChunkDev& ch = cur_chunk(plan);
+    launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), ch.n_e, st);
+    if (c == 0) stage_mark(plan, 2, st);
+    double* const E0 = d.E;
+    double* const H0 = d.H;
+    if (m >= 0) {
+      // mixed / FP32: per spin the V stage, T2 and the final contraction of a mixed build_K,
+      // with E and H' pointed at that spin's workspace (F is not shared between the spins)
+      for (int s = 0; s < 2; ++s) {
+        d.E = s ? plan->spin_E1 : E0;
+        d.H = s ? plan->spin_H1 : H0;
+        launch_vd_operands(plan, V, D + s * ds, st, true);
+        launch_H_mixed(plan, m, V, D + s * ds, st);
+        launch_T2(plan, V, K + s * ds, st, m, 0);
+        launch_T2(plan, V, K + s * ds, st, m, 1);
+        launch_final(plan, K + s * ds, st);
+      }
+      d.E = E0;
+      d.H = H0;
+    } else {
+      launch_H_lists<double, 2>(plan, V, D,
+                                HLists{d.g_tiles + ch.gt_beg, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
+                                       plan->spin_H1, plan->spin_Dr1},
+                                ch.gt_end - ch.gt_beg, 2.0, H_WRITE, st);
+      if (c == 0) {
+        stage_mark(plan, 3, st);
+        stage_mark(plan, 4, st);
+      }
+      launch_T2_spin(plan, V, K, st);
+      if (c == 0) {
+        stage_mark(plan, 5, st);
+        stage_mark(plan, 6, st);
+      }
+      launch_final(plan, K, st);
+      d.H = plan->spin_H1;
+      launch_final(plan, K + ds, st);
+      d.H = H0;
+    }
+  }
+  set_chunk(plan, 0);
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
@@ -1286,8 +1302,6 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   int m = -1;
   int rc = check_precision("build_K_two_kernels", precision, m);
   if (rc != EXX_OK) return rc;
-  if (n_chunks(plan) > 1)
-    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: needs an unbounded workspace (the plan is chunked)");
   if (m >= 0 && (rc = prepare_mixed(plan, m)) != EXX_OK) return rc;
   const int rcw = second_workspace(plan);
   if (rcw != EXX_OK) return rcw;
@@ -1296,35 +1310,41 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   hipStream_t st = (hipStream_t)stream;
   DevPlan& d = plan->d;
   set_chunk(plan, 0);
-  double* const H0 = d.H;
   stage_mark(plan, 0, st);
   hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, K, 2 * ds);
   launch_dmask(plan, D, d.Dm, st);
   launch_repack(plan, C, st);
   stage_mark(plan, 1, st);
-  launch_E(plan, st);
-  stage_mark(plan, 2, st);
-  // T2 reads the lane-ordered copy of the V operands that the V stage reads: each Coulomb
-  // matrix's operands (binary32 copies too for a mixed build) are written before its own
-  // V stage, and its T2 blocks run before the next matrix's operands replace them
   const double* Va[2] = {V, V2};
-  for (int a = 0; a < 2; ++a) {
-    d.H = a ? plan->spin_H1 : H0;
-    launch_vd_operands(plan, Va[a], D, st, m >= 0);
-    if (m >= 0) launch_H_mixed(plan, m, Va[a], D, st);
-    else launch_H(plan, Va[a], D, 2.0, H_WRITE, st);
+  for (int c = 0; c < n_chunks(plan); ++c) {
+    set_chunk(plan, c);
+    double* const H0 = d.H;
+    launch_E(plan, st);
+    if (c == 0) stage_mark(plan, 2, st);
+    // T2 reads the lane-ordered copy of the V operands that the V stage reads: each Coulomb
+    // matrix's operands (binary32 copies too for a mixed build) are written before its own
+    // V stage, and its T2 blocks run before the next matrix's operands replace them
+    for (int a = 0; a < 2; ++a) {
+      d.H = a ? plan->spin_H1 : H0;
+      launch_vd_operands(plan, Va[a], D, st, m >= 0);
+      if (m >= 0) launch_H_mixed(plan, m, Va[a], D, st);
+      else launch_H(plan, Va[a], D, 2.0, H_WRITE, st);
+      d.H = H0;
+      launch_T2(plan, Va[a], K + a * ds, st, m, 0);
+      if (m >= 0) launch_T2(plan, Va[a], K + a * ds, st, m, 1);
+    }
+    if (c == 0) {
+      stage_mark(plan, 3, st);
+      stage_mark(plan, 4, st);
+      stage_mark(plan, 5, st);
+      stage_mark(plan, 6, st);
+    }
+    launch_final(plan, K, st);
+    d.H = plan->spin_H1;
+    launch_final(plan, K + ds, st);
     d.H = H0;
-    launch_T2(plan, Va[a], K + a * ds, st, m, 0);
-    if (m >= 0) launch_T2(plan, Va[a], K + a * ds, st, m, 1);
   }
-  stage_mark(plan, 3, st);
-  stage_mark(plan, 4, st);
-  stage_mark(plan, 5, st);
-  stage_mark(plan, 6, st);
-  launch_final(plan, K, st);
-  d.H = plan->spin_H1;
-  launch_final(plan, K + ds, st);
-  d.H = H0;
+  set_chunk(plan, 0);
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);

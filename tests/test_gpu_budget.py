@@ -86,14 +86,40 @@ def test_budget_errors(exx):
     with pytest.raises(exx.ExxError) as e:
         exx.Plan.for_system(sysm, ws_budget_bytes=1000)
     assert e.value.code == -2
+
+
+def test_chunked_spin_and_two_kernels(exx):
+    """Collinear-spin and two-Coulomb-matrix builds on a chunked plan (FP64 and
+    mixed) equal those of the unbounded plan, and so does the spin backward."""
+    sysm = synth.ice_box(2, 2, 2, seed=3)
     inp = synth.make_inputs(sysm)
     full = exx.Plan.for_system(sysm)
     part = exx.Plan.for_system(sysm, ws_budget_bytes=full.info["intermediate_bytes_stored"] // 3)
+    assert part.info["n_chunks"] >= 3
     C, V, D = device_inputs(inp, torch)
-    K2 = torch.empty(2 * part.info["d_size"], dtype=torch.float64, device="cuda:0")
-    with pytest.raises(exx.ExxError) as e:
-        part.build_K_spin(C, V, torch.cat([D, D]), K2)
-    assert e.value.code == -5
+    Ds = torch.from_numpy(synth.spin_densities(inp).reshape(-1)).to("cuda:0")
+    V2 = torch.from_numpy(synth.short_range_V(inp)).to("cuda:0")
+    n = full.info["d_size"]
+    for prec in (exx.PREC_FP64, exx.PREC_MIXED):
+        out = []
+        for plan in (full, part):
+            Ks = torch.empty(2 * n, dtype=torch.float64, device="cuda:0")
+            Es = torch.empty(1, dtype=torch.float64, device="cuda:0")
+            plan.build_K_spin(C, V, Ds, Ks, Es, precision=prec)
+            Kt = torch.empty(2 * n, dtype=torch.float64, device="cuda:0")
+            Et = torch.empty(2, dtype=torch.float64, device="cuda:0")
+            plan.build_K_two_kernels(C, V, V2, D, Kt, Et, precision=prec)
+            torch.cuda.synchronize()
+            out.append([x.cpu().numpy() for x in (Ks, Es, Kt, Et)])
+        for a, b in zip(*out):
+            assert relmax(b, a) < 1e-12
+    g = []
+    for plan in (full, part):
+        dC, dV = torch.empty_like(C), torch.empty_like(V)
+        plan.exchange_backward_spin(C, V, Ds, 1.0, dC=dC, dV=dV)
+        torch.cuda.synchronize()
+        g.append((dC.cpu().numpy(), dV.cpu().numpy()))
+    assert relmax(g[1][0], g[0][0]) < 1e-12 and np.array_equal(g[1][1], g[0][1])
 
 
 def test_density_beyond_cutoff_is_ignored(exx):

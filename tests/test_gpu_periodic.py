@@ -310,8 +310,8 @@ def test_periodic_spin_and_two_kernels(exx):
 def test_periodic_chunked_plan_equals_stored(exx, which):
     """A workspace budget half the stored intermediates splits a periodic plan
     into chunks of V-stage groups; per chunk the pattern contraction keeps the
-    terms of the chunk's aux atoms.  K, E_x (FP64, mixed, FP32) and every
-    gradient agree with the unbounded plan (dV bit for bit)."""
+    terms of the chunk's aux atoms.  K, E_x (FP64, mixed, FP32), every
+    gradient (dV bit for bit) and the spin build agree with the unbounded plan."""
     sysm = (synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4) if which == "cell"
             else synth.ice_box_periodic(2, 2, 2, seed=8, r_cut=6.0))
     inp = synth.make_inputs(sysm)
@@ -339,9 +339,12 @@ def test_periodic_chunked_plan_equals_stored(exx, which):
     assert relmax(g2["dC"], g1["dC"]) < 1e-12 and np.array_equal(g1["dV"], g2["dV"])
     assert relmax(g2["dD"], g1["dD"]) < 1e-12 and relmax(g2["F"], g1["F"]) < 1e-12
     C, V, D = device_inputs(inp, torch)
-    with pytest.raises(exx.ExxError) as e:   # the spin build needs an unbounded workspace
-        part.build_K_spin(C, V, torch.cat([D, D]), torch.empty(2 * n * n, dtype=torch.float64, device="cuda:0"))
-    assert e.value.code == -5
+    Ds = torch.from_numpy(synth.spin_densities(inp).reshape(-1)).to("cuda:0")
+    Kf, Kp = (torch.empty(2 * n * n, dtype=torch.float64, device="cuda:0") for _ in range(2))
+    full.build_K_spin(C, V, Ds, Kf)
+    part.build_K_spin(C, V, Ds, Kp)
+    torch.cuda.synchronize()
+    assert relmax(Kp.cpu().numpy(), Kf.cpu().numpy()) < 1e-12
 
 
 def test_periodic_unsupported_calls(exx):
