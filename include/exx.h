@@ -357,6 +357,41 @@ int exchange_backward_spin(exx_plan plan, const double* C, const double* V,
                            double* dC, double* dV, double* dD, double* forces,
                            double c_decay, double v_2s2, void* stream);
 
+/* Strain derivative of the energy (the stress contribution of Sec. "EXX
+ * force and stress contributions", for the synthetic model of exchange_backward):
+ * dEde (device [3][3], row-major) = dE/d(eps_ab) for the homogeneous
+ * deformation x -> (1 + eps) x of every position and lattice vector, given dC
+ * and dV of exchange_backward (or exchange_backward_spin) for these C, V:
+ *   dE/d(eps_ab) = sum over canonical pairs of g_a r_b,
+ * r the pair's separation x_A - (x_B + n_AB L), g = dE/dr through C_AB ~
+ * exp(-r / c_decay) and V_AB ~ exp(-r^2 / v_2s2) with D held fixed.  Divided by
+ * the cell volume it is the stress tensor of this energy.  Clusters and
+ * periodic plans; a fixed-order binary64 reduction.  The first call allocates
+ * a per-atom buffer (9 doubles per atom). */
+int exx_strain_derivative(exx_plan plan, const double* C, const double* V, const double* dC,
+                          const double* dV, double c_decay, double v_2s2, double* dEde, void* stream);
+
+/* Bloch sums (Eq. fock_operator_k and Eq. realspace_dm).  k-points are given in
+ * fractional reciprocal coordinates (host [n_k][3]; k.R = 2 pi k.n for the
+ * lattice vector R = n L); complex arrays are interleaved (re, im) doubles,
+ * [n_k][d_size] complex.  With the cutoff below half the cell width every pair
+ * (A, B) has the one image n_AB (exx_pair_images), so only R = n_AB enters:
+ *   exx_bloch_sum:      Kk(k)_AB = e^{2 pi i k.n_AB} X_AB, Kk(k)_BA = e^{-2 pi i k.n_AB} X_BA
+ *                       from the folded real-space X of build_K (device d_size);
+ *                       entries outside the pair blocks are zero;
+ *   exx_density_from_k: D_AB = Re (1 / n_k) sum_k e^{2 pi i k.n_AB} Dk(k)_AB (and the
+ *                       conjugate phase for D_BA): the folded real-space density
+ *                       matrix build_K takes, from D(k) on a k-grid (device
+ *                       [n_k][d_size] complex); zero outside the pair blocks.  The
+ *                       imaginary part vanishes for grids closed under k -> -k
+ *                       with D(-k) = conj(D(k)); it is dropped.
+ * A cluster plan has n = 0 for every pair.  EXX_EINVAL if n_k <= 0 or a
+ * k-point is not finite.  Asynchronous on stream (k-points are read before the
+ * call returns). */
+int exx_bloch_sum(exx_plan plan, const double* X, int n_k, const double* k_frac, double* Kk, void* stream);
+int exx_density_from_k(exx_plan plan, int n_k, const double* k_frac, const double* Dk, double* D,
+                       void* stream);
+
 /* Algorithmic flop count of one stage of build_K (stage -1 = total):
  * 0 repack, 1 E = M D, 2 V stage (F, H, G), 3 T2, 4 final contraction:
  * 2*m*n*k summed over the structurally nonzero blocks.  Stages 10..14 give

@@ -833,6 +833,52 @@ def x_unfolded(inputs, reach=2.0):
     return X
 
 
+# ----------------------------------------------------------------------------
+# k-point Bloch sums (Eq. fock_operator_k, Eq. realspace_dm).  k-points are in
+# fractional reciprocal coordinates: for the lattice vector R = n L, k.R = 2 pi k.n.
+
+
+def _pair_blocks(inputs):
+    """(A, B, n_AB, rows of A, rows of B) for every canonical pair of a one-system plan."""
+    sysm, lay = inputs.system, inputs.layout
+    nb = sysm.basis_table[sysm.species].astype(np.int64)
+    bo = np.concatenate([[0], np.cumsum(nb)])
+    img = lay.pair_img if lay.pair_img is not None else np.zeros((lay.n_pairs, 3), np.int64)
+    for p, (a, b) in enumerate(zip(lay.pair_a, lay.pair_b)):
+        yield int(a), int(b), np.asarray(img[p], dtype=np.int64), slice(bo[a], bo[a + 1]), slice(bo[b], bo[b + 1])
+
+
+def bloch_sum(inputs, X, kpts):
+    """K(k) = sum_R e^{i k.R} X(R) from the folded real-space X (dense, one system):
+    every pair (A, B) has the single image n_AB inside the cutoff, so block (A, B)
+    of K(k) is e^{2 pi i k.n_AB} X_AB and block (B, A) takes the conjugate phase;
+    zero outside the pair blocks."""
+    n = X.shape[0]
+    out = []
+    for k in np.asarray(kpts, dtype=np.float64).reshape(-1, 3):
+        Kk = np.zeros((n, n), dtype=complex)
+        for a, b, nab, ia, ib in _pair_blocks(inputs):
+            ph = np.exp(2j * np.pi * float(np.dot(k, nab)))
+            Kk[ia, ib] = ph * X[ia, ib]
+            Kk[ib, ia] = np.conj(ph) * X[ib, ia]
+        out.append(Kk)
+    return out
+
+
+def density_from_k(inputs, Dk, kpts):
+    """The folded real-space density matrix from D(k) on a k-grid:
+    D_AB(n_AB) = Re (1 / N_k) sum_k e^{2 pi i k.n_AB} D_AB(k) (block (B, A) with the
+    conjugate phase), zero outside the pair blocks."""
+    kp = np.asarray(kpts, dtype=np.float64).reshape(-1, 3)
+    n = Dk[0].shape[0]
+    D = np.zeros((n, n))
+    for a, b, nab, ia, ib in _pair_blocks(inputs):
+        ph = np.exp(2j * np.pi * (kp @ nab))
+        D[ia, ib] = np.real(sum(ph[q] * Dk[q][ia, ib] for q in range(len(kp)))) / len(kp)
+        D[ib, ia] = np.real(sum(np.conj(ph[q]) * Dk[q][ib, ia] for q in range(len(kp)))) / len(kp)
+    return D
+
+
 def periodic_energy(X, D):
     """E_x per cell: -1/4 sum over the pattern blocks of X o D (D is zero off the pattern)."""
     return -0.25 * float(np.sum(X * D))

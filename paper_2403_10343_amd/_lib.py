@@ -56,7 +56,8 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "exx_graph_build", "exx_graph_launch", "exx_plan_set_mixed_split", "exx_plan_autotune",
            "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
            "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images", "exx_block_norms",
-           "exx_set_screening", "exx_screened_pairs", "exchange_backward_spin")
+           "exx_set_screening", "exx_screened_pairs", "exchange_backward_spin",
+           "exx_strain_derivative", "exx_bloch_sum", "exx_density_from_k")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -83,6 +84,9 @@ def lib():
     L.exchange_energy_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exchange_backward_spin.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exx_strain_derivative.argtypes = [vp, vp, vp, vp, vp, dp, dp, vp, vp]
+    L.exx_bloch_sum.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+    L.exx_density_from_k.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.exx_graph_build.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_plan_set_mixed_split.argtypes = [vp, dp]
     L.exx_block_norms.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -311,6 +315,48 @@ class Plan:
                                             _dev(forces, 3 * self.n_atoms, "forces", True),
                                             float(c_decay), float(v_2s2), _stream(stream)))
         self._last_gE = g
+
+    def strain_derivative(self, C, V, dC, dV, c_decay=1.5, v_2s2=8.0, stream=None):
+        """dE/d(eps) [3, 3] for the homogeneous deformation x -> (1 + eps) x, from dC, dV of
+        exchange_backward (a new device tensor)."""
+        import torch
+        i = self.info
+        out = torch.empty((3, 3), dtype=torch.float64, device=C.device)
+        _check(lib().exx_strain_derivative(self._h, _dev(C, i["c_size"], "C"), _dev(V, i["v_size"], "V"),
+                                           _dev(dC, i["c_size"], "dC"), _dev(dV, i["v_size"], "dV"),
+                                           float(c_decay), float(v_2s2), _dev(out, 9, "dEde"), _stream(stream)))
+        return out
+
+    @staticmethod
+    def _kpts(k_frac):
+        k = np.ascontiguousarray(np.asarray(k_frac, dtype=np.float64).reshape(-1, 3))
+        if len(k) == 0:
+            raise ExxError(EXX_EINVAL, "k_frac: at least one k-point")
+        return k
+
+    def bloch_sum(self, X, k_frac, stream=None):
+        """K(k) = sum_R e^{ik.R} X(R) on the pair blocks for fractional k-points: a new
+        complex128 device tensor [n_k, d_size]."""
+        import torch
+        k = self._kpts(k_frac)
+        n = self.info["d_size"]
+        out = torch.empty((len(k), n), dtype=torch.complex128, device=X.device)
+        _check(lib().exx_bloch_sum(self._h, _dev(X, n, "X"), len(k), k.ctypes.data,
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def density_from_k(self, Dk, k_frac, stream=None):
+        """The folded real-space D (device, d_size) from D(k) (complex128 [n_k, d_size])."""
+        import torch
+        k = self._kpts(k_frac)
+        n = self.info["d_size"]
+        if not (isinstance(Dk, torch.Tensor) and Dk.dtype == torch.complex128 and Dk.is_cuda
+                and Dk.is_contiguous() and Dk.numel() == len(k) * n):
+            raise ExxError(EXX_EINVAL, "Dk: expected a contiguous complex128 GPU tensor of n_k * d_size elements")
+        out = torch.empty(n, dtype=torch.float64, device=Dk.device)
+        _check(lib().exx_density_from_k(self._h, len(k), k.ctypes.data, ctypes.c_void_p(Dk.data_ptr()),
+                                        _dev(out, n, "D"), _stream(stream)))
+        return out
 
     def graph_build(self, C, V, D, K, Ex, stream, precision=PREC_FP64):
         """Capture one build_K on `stream` (a created stream) into a HIP graph."""

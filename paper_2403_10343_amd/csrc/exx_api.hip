@@ -480,6 +480,138 @@ __global__ void k_forces(const double* __restrict__ pos, const double* __restric
   F[3 * A + 2] = f2;
 }
 
+// Strain derivative dE/d(eps_ab) of the energy under a homogeneous deformation x -> (1 + eps) x
+// of every position (and of the lattice): sum over canonical pairs of g_a r_b, where r is the
+// pair's separation (at its image) and g = dE/dr from the same per-pair sums as the forces.
+// Per atom the half sum over its neighbour entries (each pair is seen from both ends with r
+// and g negated), then one fixed-order reduction over the atoms.
+__global__ void k_strain_part(const double* __restrict__ pos, const double* __restrict__ sC,
+                              const double* __restrict__ sV, double* __restrict__ part, DevPlan d,
+                              double c_decay, double v_2s2) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= d.n_atoms) return;
+  double w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = d.nbr_ptr[A]; k < d.nbr_ptr[A + 1]; ++k) {
+    const int J = d.nbr_atom[k];
+    if (J == A) continue;
+    const int p = d.nbr_pair[k];
+    double r3[3];
+    for (int x = 0; x < 3; ++x) r3[x] = d.periodic ? d.nbr_sep[3 * (size_t)k + x] : pos[3 * A + x] - pos[3 * J + x];
+    const double r = sqrt(r3[0] * r3[0] + r3[1] * r3[1] + r3[2] * r3[2]);
+    const double f = sC[p] * (-1.0 / c_decay) / r + sV[p] * (-2.0 / v_2s2);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) w[3 * a + b] += (f * r3[a]) * r3[b];
+  }
+  for (int x = 0; x < 9; ++x) part[9 * (size_t)A + x] = 0.5 * w[x];
+}
+
+__global__ __launch_bounds__(256) void k_strain_sum(const double* __restrict__ part, int n_atoms,
+                                                    double* __restrict__ out) {
+  __shared__ double red[256];
+  for (int x = 0; x < 9; ++x) {
+    double acc = 0.0;
+    for (int A = threadIdx.x; A < n_atoms; A += 256) acc += part[9 * (size_t)A + x];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[x] = red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bloch sums.  With the cutoff below half the cell width every pair (A, B) has one image
+// n_AB, so K_AB(k) = sum_R e^{i k.R} X_AB(R) keeps one term, e^{2 pi i k.n_AB} X_AB (k in
+// fractional reciprocal coordinates), and the (B, A) block takes the conjugate phase.  The
+// density matrix in real space, D_AB(R) = (1 / N_k) sum_k D_AB(k) e^{i k.R}, is needed at
+// R = n_AB only: the real part of (1 / N_k) sum_k e^{2 pi i k.n_AB} D_AB(k).  One workgroup
+// per canonical pair; the k-points (at most KPT_MAX per launch) are kernel arguments.
+
+constexpr int KPT_MAX = 32;
+struct KPts { double k[KPT_MAX][3]; int n; };
+
+__device__ __forceinline__ void pair_image(const DevPlan& d, int A, int B, int (&n)[3]) {
+  const int code = d.periodic ? d.pimg[(size_t)A * d.n_atoms + B] : IMG0;
+  n[0] = code % IMG_S - IMG_OFF;
+  n[1] = (code / IMG_S) % IMG_S - IMG_OFF;
+  n[2] = code / (IMG_S * IMG_S) - IMG_OFF;
+}
+
+// Kk[k0 + q] (complex, interleaved) on the pair blocks from the real folded X
+__global__ __launch_bounds__(256) void k_bloch(const double* __restrict__ X, double* __restrict__ Kk, DevPlan d,
+                                               KPts kp, int k0) {
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const int s = d.atom_sys[A];
+  const int64_t base = d.sys_d_off[s], ns = d.sys_n[s], dsz = d.sys_d_off[d.n_sys];
+  const int bA = d.nb[A], bB = d.nb[B];
+  const int64_t oA = d.bo[A], oB = d.bo[B];
+  int n[3];
+  pair_image(d, A, B, n);
+  for (int q = 0; q < kp.n; ++q) {
+    double sn, cs;
+    sincospi(2.0 * (kp.k[q][0] * n[0] + kp.k[q][1] * n[1] + kp.k[q][2] * n[2]), &sn, &cs);
+    double* Kq = Kk + 2 * (size_t)(k0 + q) * dsz;
+    for (int e = threadIdx.x; e < bA * bB; e += 256) {
+      const int i = e / bB, j = e - i * bB;
+      const int64_t x = base + (oA + i) * ns + oB + j, y = base + (oB + j) * ns + oA + i;
+      Kq[2 * x] = cs * X[x];
+      Kq[2 * x + 1] = sn * X[x];
+      if (A != B) {
+        Kq[2 * y] = cs * X[y];
+        Kq[2 * y + 1] = -sn * X[y];
+      }
+    }
+  }
+}
+
+// D (pair blocks) += sum over the launch's k-points of Re(e^{2 pi i k.n} Dk[k0 + q])
+__global__ __launch_bounds__(256) void k_density_k(const double* __restrict__ Dk, double* __restrict__ D, DevPlan d,
+                                                   KPts kp, int k0) {
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const int s = d.atom_sys[A];
+  const int64_t base = d.sys_d_off[s], ns = d.sys_n[s], dsz = d.sys_d_off[d.n_sys];
+  const int bA = d.nb[A], bB = d.nb[B];
+  const int64_t oA = d.bo[A], oB = d.bo[B];
+  int n[3];
+  pair_image(d, A, B, n);
+  double cs[KPT_MAX], sn[KPT_MAX];
+  for (int q = 0; q < kp.n; ++q)
+    sincospi(2.0 * (kp.k[q][0] * n[0] + kp.k[q][1] * n[1] + kp.k[q][2] * n[2]), &sn[q], &cs[q]);
+  for (int e = threadIdx.x; e < bA * bB; e += 256) {
+    const int i = e / bB, j = e - i * bB;
+    const int64_t x = base + (oA + i) * ns + oB + j, y = base + (oB + j) * ns + oA + i;
+    double ax = D[x], ay = D[y];
+    for (int q = 0; q < kp.n; ++q) {
+      const double* Dq = Dk + 2 * (size_t)(k0 + q) * dsz;
+      ax += cs[q] * Dq[2 * x] - sn[q] * Dq[2 * x + 1];
+      if (A != B) ay += cs[q] * Dq[2 * y] + sn[q] * Dq[2 * y + 1];
+    }
+    D[x] = ax;
+    if (A != B) D[y] = ay;
+  }
+}
+
+// D *= a on the pair blocks
+__global__ __launch_bounds__(256) void k_scale_pairs(double* __restrict__ D, DevPlan d, double a) {
+  const int p = blockIdx.x;
+  const int A = d.pair_a[p], B = d.pair_b[p];
+  const int s = d.atom_sys[A];
+  const int64_t base = d.sys_d_off[s], ns = d.sys_n[s];
+  const int bA = d.nb[A], bB = d.nb[B];
+  const int64_t oA = d.bo[A], oB = d.bo[B];
+  for (int e = threadIdx.x; e < bA * bB; e += 256) {
+    const int i = e / bB, j = e - i * bB;
+    const int64_t x = base + (oA + i) * ns + oB + j, y = base + (oB + j) * ns + oA + i;
+    D[x] *= a;
+    if (A != B) D[y] *= a;
+  }
+}
+
 // y = a gE[s] x over the dense block of every system s (blockIdx.y = s); y == x scales in place
 __global__ void k_scaled_copy_sys(double* y, const double* x, const double* __restrict__ gE, DevPlan d, double a) {
   const int s = blockIdx.y;
@@ -1529,6 +1661,79 @@ int exx_screened_pairs(exx_plan plan, uint8_t* flags, void* stream) {
   if (!plan->scr_done) return fail(EXX_ESTATE, "exx_screened_pairs: no screened build has been issued");
   const size_t np = plan->hp.pair_a.size();
   if (np) HIP_TRY(hipMemcpyAsync(flags, plan->scr_flags, np, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return EXX_OK;
+}
+
+static int check_kpts(const char* who, int n_k, const double* k_frac) {
+  if (n_k <= 0 || !k_frac) return fail(EXX_EINVAL, std::string(who) + ": need n_k > 0 and k-points");
+  for (int i = 0; i < 3 * n_k; ++i)
+    if (!(std::fabs(k_frac[i]) <= 1e6)) return fail(EXX_EINVAL, std::string(who) + ": k-points must be finite");
+  return EXX_OK;
+}
+
+static KPts kpt_chunk(const double* k_frac, int k0, int n_k) {
+  KPts kp{};
+  kp.n = std::min(KPT_MAX, n_k - k0);
+  for (int q = 0; q < kp.n; ++q)
+    for (int x = 0; x < 3; ++x) kp.k[q][x] = k_frac[3 * (k0 + q) + x];
+  return kp;
+}
+
+int exx_bloch_sum(exx_plan plan, const double* X, int n_k, const double* k_frac, double* Kk, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_bloch_sum: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_bloch_sum: host-only plan");
+  if (!X || !Kk) return fail(EXX_EINVAL, "exx_bloch_sum: NULL array");
+  int rc = check_kpts("exx_bloch_sum", n_k, k_frac);
+  if (rc != EXX_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  const unsigned np = (unsigned)hp.pair_a.size();
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, Kk, 2 * (int64_t)n_k * hp.d_size);
+  for (int k0 = 0; k0 < n_k && np; k0 += KPT_MAX)
+    hipLaunchKernelGGL(k_bloch, dim3(np), dim3(256), 0, st, X, Kk, plan->d, kpt_chunk(k_frac, k0, n_k), k0);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+int exx_density_from_k(exx_plan plan, int n_k, const double* k_frac, const double* Dk, double* D, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_density_from_k: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_density_from_k: host-only plan");
+  if (!Dk || !D) return fail(EXX_EINVAL, "exx_density_from_k: NULL array");
+  int rc = check_kpts("exx_density_from_k", n_k, k_frac);
+  if (rc != EXX_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  const unsigned np = (unsigned)hp.pair_a.size();
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, D, hp.d_size);
+  for (int k0 = 0; k0 < n_k && np; k0 += KPT_MAX)
+    hipLaunchKernelGGL(k_density_k, dim3(np), dim3(256), 0, st, Dk, D, plan->d, kpt_chunk(k_frac, k0, n_k), k0);
+  if (np) hipLaunchKernelGGL(k_scale_pairs, dim3(np), dim3(256), 0, st, D, plan->d, 1.0 / n_k);
+  HIP_TRY(hipGetLastError());
+  return EXX_OK;
+}
+
+int exx_strain_derivative(exx_plan plan, const double* C, const double* V, const double* dC, const double* dV,
+                          double c_decay, double v_2s2, double* dEde, void* stream) {
+  if (!plan) return fail(EXX_EINVAL, "exx_strain_derivative: NULL plan");
+  if (plan->host_only) return fail(EXX_ESTATE, "exx_strain_derivative: host-only plan");
+  if (!C || !V || !dC || !dV || !dEde) return fail(EXX_EINVAL, "exx_strain_derivative: NULL array");
+  if (!(c_decay > 0) || !(v_2s2 > 0)) return fail(EXX_EINVAL, "exx_strain_derivative: decay lengths must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
+  if (!plan->strain_part) {
+    HIP_TRY(hipMalloc((void**)&plan->strain_part, sizeof(double) * 9 * std::max(1, hp.n_atoms)));
+    plan->allocs.push_back(plan->strain_part);
+  }
+  const unsigned np = (unsigned)hp.pair_a.size();
+  if (np) {
+    hipLaunchKernelGGL(k_block_dot, dim3(np), dim3(256), 0, st, dC, C, d.c_off, d.sC);
+    hipLaunchKernelGGL(k_block_dot, dim3(np), dim3(256), 0, st, dV, V, d.v_off, d.sV);
+  }
+  hipLaunchKernelGGL(k_strain_part, dim3((hp.n_atoms + 127) / 128), dim3(128), 0, st, d.pos, d.sC, d.sV,
+                     plan->strain_part, d, c_decay, v_2s2);
+  hipLaunchKernelGGL(k_strain_sum, dim3(1), dim3(256), 0, st, plan->strain_part, hp.n_atoms, dEde);
+  HIP_TRY(hipGetLastError());
   return EXX_OK;
 }
 

@@ -234,6 +234,7 @@ struct exx_plan_s {
   double* dC_spin1 = nullptr;       // the second spin's dC, dV (exchange_backward_spin), and 2 gE
   double* dV_spin1 = nullptr;
   double* gE_spin = nullptr;
+  double* strain_part = nullptr;    // per atom partial strain derivatives (9 each), on first use
   double* spin_E1 = nullptr;        // E and H' of the second spin (build_K_spin), allocated on first use
   double* spin_H1 = nullptr;
   double* spin_Dr1 = nullptr;       // lane-ordered D operands of the second spin

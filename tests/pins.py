@@ -21,7 +21,8 @@ TOL = 1e-12
 
 
 def rel(a, b):
-    a, b = np.asarray(a, float), np.asarray(b, float)
+    cplx = np.iscomplexobj(a) or np.iscomplexobj(b)
+    a, b = np.asarray(a, complex if cplx else float), np.asarray(b, complex if cplx else float)
     s = max(np.abs(a).max(), np.abs(b).max(), 1e-300)
     return float(np.abs(a - b).max() / s)
 
@@ -579,6 +580,69 @@ def _tiny_periodic(seed):
                         basis_table=np.array([2, 1]), aux_table=np.array([3, 2]))
 
 
+def pin_bloch(seed=22):
+    """Bloch sums on a skewed cell whose pairs cross faces, edges and corners:
+    (i) K(k) of the pair-block route equals the sum over Cartesian lattice
+    vectors R = n L of e^{i k_c.R} X(R), k_c = k B with B = 2 pi inv(L)^T, over
+    the pairs of the oracle's own periodic search; (ii) K(0) = X, K(k) is
+    Hermitian and K(-k) = conj K(k); (iii) on a full 3x3x3 Gamma-centred grid
+    density_from_k inverts D(k) = sum_R e^{-i k.R} D(R) exactly, also with a term
+    at a second image of one pair added (the grid's phases are orthogonal);
+    (iv) -1/4 (1/N_k) sum_k <K(k), D(k)> equals E_x of the folded matrices."""
+    sysm = _tiny_periodic(seed)
+    inp = synth.make_inputs(sysm)
+    X = O.x_periodic(inp)
+    n = X.shape[0]
+    D = inp.D.reshape(n, n)
+    lat = sysm.lattice
+    Bm = 2 * np.pi * np.linalg.inv(lat).T
+    nb, _, bo, _ = _offsets(sysm)
+    pairs = O.periodic_pairs(sysm.pos, lat, sysm.r_cut)
+    kpts = np.array([(0.25, -0.1, 0.4), (0.5, 0.5, 0.0), (-0.3, 0.2, 0.1)])
+    Kk = O.bloch_sum(inp, X, kpts)
+    worst = 0.0
+    for k, K1 in zip(kpts, Kk):
+        kc = k @ Bm
+        K2 = np.zeros((n, n), dtype=complex)
+        for a, b, nn in pairs:
+            ia, ib = slice(bo[a], bo[a + 1]), slice(bo[b], bo[b + 1])
+            ph = np.exp(1j * float(kc @ (np.asarray(nn) @ lat)))
+            K2[ia, ib] += ph * X[ia, ib]
+            if a != b:
+                K2[ib, ia] += np.conj(ph) * X[ib, ia]
+        worst = max(worst, rel(K1, K2), rel(K1, K1.conj().T))
+    K0 = O.bloch_sum(inp, X, [(0.0, 0.0, 0.0)])[0]
+    Km = O.bloch_sum(inp, X, -kpts)
+    worst = max(worst, rel(K0, X), max(rel(a, b.conj()) for a, b in zip(Km, Kk)))
+    grid = np.array([(i / 3, j / 3, l / 3) for i in range(3) for j in range(3) for l in range(3)])
+    rng = np.random.default_rng(seed)
+    lay = inp.layout
+    q = next(p for p in range(lay.n_pairs) if lay.pair_a[p] != lay.pair_b[p])
+    a, b = int(lay.pair_a[q]), int(lay.pair_b[q])
+    Z = rng.normal(size=(nb[a], nb[b]))
+    n2 = np.asarray(lay.pair_img[q]) + np.array([1, 0, 0])
+    Dk = []
+    for k in grid:
+        Dq = np.zeros((n, n), dtype=complex)
+        for pa, pb, nn in zip(lay.pair_a, lay.pair_b, lay.pair_img):
+            ia, ib = slice(bo[pa], bo[pa + 1]), slice(bo[pb], bo[pb + 1])
+            ph = np.exp(-2j * np.pi * float(k @ nn))
+            Dq[ia, ib] = ph * D[ia, ib]
+            Dq[ib, ia] = np.conj(ph) * D[ib, ia]
+        ia, ib = slice(bo[a], bo[a + 1]), slice(bo[b], bo[b + 1])
+        ph2 = np.exp(-2j * np.pi * float(k @ n2))
+        Dq[ia, ib] += ph2 * Z
+        Dq[ib, ia] += np.conj(ph2) * Z.T
+        Dk.append(Dq)
+    Dback = O.density_from_k(inp, Dk, grid)
+    r_inv = rel(Dback, D)
+    Kg = O.bloch_sum(inp, X, grid)
+    e_k = -0.25 * np.real(sum(np.sum(K * Dq) for K, Dq in zip(Kg, Dk))) / len(grid)
+    e_r = O.periodic_energy(X, D)
+    ok = worst < TOL and r_inv < TOL and abs(e_k - e_r) <= TOL * abs(e_r)
+    return ok, f"K(k) routes {worst:.1e}, D round trip {r_inv:.1e}, E {e_k:.12e} vs {e_r:.12e}"
+
+
 def pin_periodic_unfolded(seed=17):
     """Periodic route against an explicit cluster of the home cell and its
     images (copied blocks, 4-index route), on a skewed cell whose atoms pair
@@ -653,4 +717,5 @@ ALL_PINS = {
     "periodic_supercell": pin_periodic_supercell,
     "norm_estimates": pin_norm_estimates,
     "spin_gradients": pin_spin_gradients,
+    "bloch": pin_bloch,
 }

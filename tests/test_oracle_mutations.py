@@ -49,6 +49,10 @@ MUTATIONS = {
                                 "out[p, 0] = np.abs(inputs.C[lay.c_off[p]:(lay.c_off[p] + lay.c_off[p + 1]) // 2]).max()"),
     "spin_gradient_factor": ("out = {k: 2.0 * (parts[0][k] + parts[1][k]) for k in", "out = {k: (parts[0][k] + parts[1][k]) for k in"),
     "spin_dD_one_density": ('out["dD"] = [2.0 * p["dD"] for p in parts]', 'out["dD"] = [p["dD"] for p in parts]'),
+    "bloch_same_phase_both_blocks": ("            Kk[ib, ia] = np.conj(ph) * X[ib, ia]", "            Kk[ib, ia] = ph * X[ib, ia]"),
+    "density_k_no_average": ("ph[q] * Dk[q][ia, ib] for q in range(len(kp)))) / len(kp)",
+                             "ph[q] * Dk[q][ia, ib] for q in range(len(kp))))"),
+    "density_k_phase_sign": ("        ph = np.exp(2j * np.pi * (kp @ nab))", "        ph = np.exp(-2j * np.pi * (kp @ nab))"),
     "screened_V_neighbour_block": ("        V[lay.v_off[p]:lay.v_off[p + 1]] = 0.0",
                                    "        V[lay.v_off[p]:lay.v_off[p + 1] - 1] = 0.0"),
 }
