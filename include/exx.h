@@ -275,7 +275,8 @@ int exx_block_norms(exx_plan plan, const double* C, const double* V, const doubl
                     void* stream);
 
 /* Screening by those estimates (lossy; off by default).  With eps > 0 every
- * later build_K (any precision; graphs captured afterwards too) first forms the
+ * later build_K (any precision; graphs captured afterwards too; and the spin and
+ * two-kernel builds, below) first forms the
  * norms of its C, V and D and, per atom A, tau_A = the largest max|C| of a pair
  * with A, rho_A = the largest max|D| of a pair with A, sigma_A = the largest
  * rho_J over J in N[A].  The estimate of pair (P, Q),
@@ -286,8 +287,10 @@ int exx_block_norms(exx_plan plan, const double* C, const double* V, const doubl
  * blocks set to zero.  eps = 0 switches screening off (the build is then the
  * unscreened one, bit for bit).  The first eps > 0 allocates the plan's norm
  * and flag buffers (n_pairs * 3 + n_atoms * 3 doubles, n_pairs bytes).
- * build_K_spin and build_K_two_kernels return EXX_EUNSUPPORTED while eps > 0;
- * exchange_backward is never screened.  EXX_EINVAL unless eps is finite and
+ * build_K_spin screens both spins with one flag per pair (max|D| over D^0 and
+ * D^1); build_K_two_kernels screens each Coulomb matrix by its own estimates
+ * (exx_screened_pairs then returns those of V2).  The backward passes are
+ * never screened.  EXX_EINVAL unless eps is finite and
  * >= 0; EXX_ESTATE on a host-only plan. */
 int exx_set_screening(exx_plan plan, double eps);
 

@@ -337,9 +337,10 @@ __global__ __launch_bounds__(256) void k_dmask(const double* __restrict__ D, dou
 // C^nu_kl D_jl with mu on P and nu on Q (j lies on an atom of N[P], l on one of N[Q]);
 // below the threshold the build skips every product through that block.
 
+// D1 (may be null): a second density matrix (collinear spin) whose blocks enter max|D| too
 __global__ __launch_bounds__(256) void k_block_norms(const double* __restrict__ C, const double* __restrict__ V,
                                                      const double* __restrict__ D, DevPlan d,
-                                                     double* __restrict__ nrm) {
+                                                     double* __restrict__ nrm, const double* __restrict__ D1) {
   __shared__ double red[3][256];
   const int p = blockIdx.x;
   const int A = d.pair_a[p], B = d.pair_b[p];
@@ -353,6 +354,7 @@ __global__ __launch_bounds__(256) void k_block_norms(const double* __restrict__ 
   for (int e = threadIdx.x; e < bA * bB; e += 256) {
     const int i = e / bB, k = e - i * bB;
     md = fmax(md, fmax(fabs(D[base + (oA + i) * ns + oB + k]), fabs(D[base + (oB + k) * ns + oA + i])));
+    if (D1) md = fmax(md, fmax(fabs(D1[base + (oA + i) * ns + oB + k]), fabs(D1[base + (oB + k) * ns + oA + i])));
   }
   red[0][threadIdx.x] = mc;
   red[1][threadIdx.x] = mv;
@@ -1116,10 +1118,11 @@ static void launch_E(exx_plan plan, hipStream_t st) {
 // binary32 copies Vr32, Dr32) for these V and D
 // maximum-norm estimates of C, V and D into plan->scr_nrm, then the screening flags of the
 // plan's threshold into plan->scr_flags
-static void launch_screening(exx_plan plan, const double* C, const double* V, const double* D, hipStream_t st) {
+static void launch_screening(exx_plan plan, const double* C, const double* V, const double* D, hipStream_t st,
+                             const double* D1 = nullptr) {
   const int np = (int)plan->hp.pair_a.size(), na = plan->hp.n_atoms;
   if (np <= 0) return;
-  hipLaunchKernelGGL(k_block_norms, dim3(np), dim3(256), 0, st, C, V, D, plan->d, plan->scr_nrm);
+  hipLaunchKernelGGL(k_block_norms, dim3(np), dim3(256), 0, st, C, V, D, plan->d, plan->scr_nrm, D1);
   hipLaunchKernelGGL(k_atom_norms, dim3((na + 255) / 256), dim3(256), 0, st, plan->d, plan->scr_nrm, np, 0);
   hipLaunchKernelGGL(k_atom_norms, dim3((na + 255) / 256), dim3(256), 0, st, plan->d, plan->scr_nrm, np, 1);
   hipLaunchKernelGGL(k_screen, dim3((np + 255) / 256), dim3(256), 0, st, plan->d, plan->scr_nrm, np,
@@ -1337,7 +1340,6 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   if (!plan) return fail(EXX_EINVAL, "build_K_spin: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "build_K_spin: host-only plan");
   if (!C || !V || !D || !K) return fail(EXX_EINVAL, "build_K_spin: NULL array");
-  if (plan->scr_eps > 0) return fail(EXX_EUNSUPPORTED, "build_K_spin: norm screening applies to build_K only");
   int m = -1;
   int rc = check_precision("build_K_spin", precision, m);
   if (rc != EXX_OK) return rc;
@@ -1361,6 +1363,11 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   launch_dmask(plan, D, d.Dm, st);
   launch_dmask(plan, D + ds, plan->spin_Dm1, st);
   launch_repack(plan, C, st);
+  const bool screened = plan->scr_eps > 0;
+  if (screened) {   // one flag per pair for both spins: max|D| over D^0 and D^1
+    launch_screening(plan, C, V, D, st, D + ds);
+    d.scr = plan->scr_flags;
+  }
   if (m < 0) {
     launch_vd_operands(plan, V, D, st);   // V and D^0 operands
     if (!hp.pair_a.empty())
@@ -1411,6 +1418,8 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
     }
   }
   set_chunk(plan, 0);
+  d.scr = nullptr;
+  if (screened) plan->scr_done = true;
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
@@ -1429,8 +1438,6 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   if (!plan) return fail(EXX_EINVAL, "build_K_two_kernels: NULL plan");
   if (plan->host_only) return fail(EXX_ESTATE, "build_K_two_kernels: host-only plan");
   if (!C || !V || !V2 || !D || !K) return fail(EXX_EINVAL, "build_K_two_kernels: NULL array");
-  if (plan->scr_eps > 0)
-    return fail(EXX_EUNSUPPORTED, "build_K_two_kernels: norm screening applies to build_K only");
   int m = -1;
   int rc = check_precision("build_K_two_kernels", precision, m);
   if (rc != EXX_OK) return rc;
@@ -1458,12 +1465,17 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
     // V stage, and its T2 blocks run before the next matrix's operands replace them
     for (int a = 0; a < 2; ++a) {
       d.H = a ? plan->spin_H1 : H0;
+      if (plan->scr_eps > 0) {   // each Coulomb matrix screened by its own estimates
+        launch_screening(plan, C, Va[a], D, st);
+        d.scr = plan->scr_flags;
+      }
       launch_vd_operands(plan, Va[a], D, st, m >= 0);
       if (m >= 0) launch_H_mixed(plan, m, Va[a], D, st);
       else launch_H(plan, Va[a], D, 2.0, H_WRITE, st);
       d.H = H0;
       launch_T2(plan, Va[a], K + a * ds, st, m, 0);
       if (m >= 0) launch_T2(plan, Va[a], K + a * ds, st, m, 1);
+      d.scr = nullptr;
     }
     if (c == 0) {
       stage_mark(plan, 3, st);
@@ -1477,6 +1489,7 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
     d.H = H0;
   }
   set_chunk(plan, 0);
+  if (plan->scr_eps > 0) plan->scr_done = true;
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
@@ -1634,7 +1647,9 @@ int exx_block_norms(exx_plan plan, const double* C, const double* V, const doubl
   if (plan->host_only) return fail(EXX_ESTATE, "exx_block_norms: host-only plan");
   if (!C || !V || !D || !norms) return fail(EXX_EINVAL, "exx_block_norms: NULL array");
   const unsigned np = (unsigned)plan->hp.pair_a.size();
-  if (np) hipLaunchKernelGGL(k_block_norms, dim3(np), dim3(256), 0, (hipStream_t)stream, C, V, D, plan->d, norms);
+  if (np)
+    hipLaunchKernelGGL(k_block_norms, dim3(np), dim3(256), 0, (hipStream_t)stream, C, V, D, plan->d, norms,
+                       (const double*)nullptr);
   HIP_TRY(hipGetLastError());
   return EXX_OK;
 }

@@ -145,9 +145,45 @@ def test_screened_768_box_rows_mixed_chunks_and_graph(exx):
         assert np.array_equal(Kd.cpu().numpy(), K) and Ed.item() == Ex[0]
 
 
+def test_screened_spin_and_two_kernels(exx):
+    """Spin builds screen both spins with one flag per pair (the D norm over both
+    spins), two-kernel builds each Coulomb matrix by its own estimates; each K
+    equals the oracle's exchange of the screened V."""
+    sysm = synth.water_cluster(8, 5)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    n = int(inp.layout.sys_nbas[0])
+    dev = "cuda:0"
+    C, V, D = device_inputs(inp, torch)
+    Ds = synth.spin_densities(inp)
+    both = O.with_density(inp, np.maximum(np.abs(Ds[0]), np.abs(Ds[1])))
+    est = O.screening_estimates(inp, O.block_max_norms(both))
+    eps = _eps_at(est, 0.3)
+    plan.set_screening(eps)
+    K2 = torch.empty(2 * n * n, dtype=torch.float64, device=dev)
+    plan.build_K_spin(C, V, torch.from_numpy(Ds.reshape(-1)).to(dev), K2)
+    flags = plan.screened_pairs().cpu().numpy().astype(bool)
+    assert np.array_equal(flags, est < eps) and flags.any()
+    Ko = O.k_spin(O.screened_coulomb(inp, flags), list(Ds))
+    Kg = K2.cpu().numpy().reshape(2, n, n)
+    for s in range(2):
+        assert relmax(Kg[s], Ko[s]) < 1e-10
+    V2 = synth.short_range_V(inp)
+    Kt = torch.empty(2 * n * n, dtype=torch.float64, device=dev)
+    plan.build_K_two_kernels(C, V, torch.from_numpy(V2).to(dev), D, Kt)
+    f2 = plan.screened_pairs().cpu().numpy().astype(bool)
+    plan.set_screening(0.0)
+    Kt = Kt.cpu().numpy().reshape(2, n, n)
+    for a, Vx in enumerate((inp.V, V2)):
+        ia = O.with_coulomb(inp, Vx)
+        fa = O.screening_estimates(ia, O.block_max_norms(ia)) < eps
+        if a == 1:
+            assert np.array_equal(f2, fa)
+        assert relmax(Kt[a], O.k_eigen(O.screened_coulomb(ia, fa))) < 1e-10
+
+
 def test_screening_errors(exx):
     sysm = synth.water_cluster(2, 3)
-    inp = synth.make_inputs(sysm)
     plan = exx.Plan.for_system(sysm)
     with pytest.raises(exx.ExxError) as e:            # no screened build yet
         plan.screened_pairs()
@@ -156,16 +192,3 @@ def test_screening_errors(exx):
         with pytest.raises(exx.ExxError) as e:
             plan.set_screening(bad)
         assert e.value.code == -1
-    C, V, D = device_inputs(inp, torch)
-    n = plan.info["d_size"]
-    plan.set_screening(1e-3)
-    with pytest.raises(exx.ExxError) as e:
-        plan.build_K_spin(C, V, torch.cat([D, D]), torch.empty(2 * n, dtype=torch.float64, device="cuda:0"))
-    assert e.value.code == -5
-    with pytest.raises(exx.ExxError) as e:
-        plan.build_K_two_kernels(C, V, V, D, torch.empty(2 * n, dtype=torch.float64, device="cuda:0"))
-    assert e.value.code == -5
-    plan.set_screening(0.0)
-    K = torch.empty(2 * n, dtype=torch.float64, device="cuda:0")
-    plan.build_K_spin(C, V, torch.cat([D, D]), K)
-    torch.cuda.synchronize()
