@@ -184,3 +184,37 @@ def test_binding_rejects_arrays_before_the_library():
         assert e.value.code == -1
     with pytest.raises(ExxError):
         p.exchange_backward(C, V, D, 1.0, dC=torch.empty_like(C))
+
+
+def test_new_entry_points_reject_before_the_library():
+    """The spin backward, block norms, strain derivative and Bloch-sum bindings
+    reject host (CPU) arrays with EXX_EINVAL; on a host-only plan the library
+    itself answers EXX_ESTATE for the screening threshold, and EXX_EINVAL for
+    bad k-points or a bad threshold, without touching a device."""
+    import ctypes
+    import torch
+    from paper_2403_10343_amd import ExxError, Plan, lib
+    sysm = synth.water_cluster(2, seed=0)
+    inp = synth.make_inputs(sysm)
+    p = Plan.for_system(sysm, host_only=True)
+    C, V, D = (torch.from_numpy(a) for a in (inp.C, inp.V, inp.D))
+    calls = (lambda: p.exchange_backward_spin(C, V, torch.cat([D, D]), 1.0, dC=torch.empty_like(C)),
+             lambda: p.block_norms(C, V, D),
+             lambda: p.strain_derivative(C, V, C, V),
+             lambda: p.bloch_sum(D, [(0.1, 0.2, 0.3)]),
+             lambda: p.density_from_k(torch.zeros(p.info["d_size"], dtype=torch.complex128), [(0, 0, 0)]))
+    for f in calls:
+        with pytest.raises(ExxError) as e:
+            f()
+        assert e.value.code == -1
+    with pytest.raises(ExxError) as e:
+        p.bloch_sum(D, np.zeros((0, 3)))
+    assert e.value.code == -1
+    with pytest.raises(ExxError) as e:
+        p.set_screening(1e-3)
+    assert e.value.code == -4
+    L = lib()
+    assert L.exx_set_screening(None, 0.0) == -1
+    k = np.array([np.nan, 0.0, 0.0])
+    assert L.exx_bloch_sum(p._h, ctypes.c_void_p(1), 1, k.ctypes.data, ctypes.c_void_p(1), None) == -4
+    assert L.exx_density_from_k(None, 1, k.ctypes.data, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
