@@ -217,6 +217,43 @@ def path_record(plan, dt, stage_ms, mixed, names, workload):
     }
 
 
+def attainable_peaks(torch, n=8192, reps=5):
+    """What the vendor libraries reach on this GPU, beside the published peaks: a dense
+    n x n x n GEMM in binary64 and binary32 (torch.matmul, rocBLAS / hipBLASLt) and a
+    device-to-device copy of 2 GiB (read + write bytes), median of reps after a warm-up,
+    timed with HIP events."""
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        return sorted(ts)[len(ts) // 2]
+
+    for name, dt, peak in (("dgemm", torch.float64, 78.6), ("sgemm", torch.float32, 157.3)):
+        x = torch.randn(n, n, dtype=dt, device=dev)
+        y = torch.randn(n, n, dtype=dt, device=dev)
+        t = timed(lambda: torch.matmul(x, y))
+        out[name] = {"n": n, "tflops": 2.0 * n ** 3 / t / 1e12, "published_peak_tflops": peak,
+                     "frac": 2.0 * n ** 3 / t / 1e12 / peak}
+        del x, y
+    src = torch.empty(1 << 28, dtype=torch.float64, device=dev)
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src))
+    out["copy"] = {"bytes": 2 * src.numel() * 8, "tb_per_s": 2 * src.numel() * 8 / t / 1e12,
+                   "published_peak_tb_per_s": 8.0}
+    return out
+
+
 def progress(msg):
     """One line on stderr as each part of the run ends."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -311,6 +348,8 @@ def main():
                     help="also time two Coulomb matrices in one call (FP64); 0 = skip")
     ap.add_argument("--screening-steps", type=int, default=3,
                     help="timed FP64 builds per screening threshold (0: no screening record)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="print what the vendor GEMMs and a copy reach on this GPU, then exit")
     ap.add_argument("--periodic-only", action="store_true",
                     help="time only the periodic 3072-atom box (its record as the JSON line)")
     ap.add_argument("--periodic-steps", type=int, default=2,
@@ -333,6 +372,9 @@ def main():
     if args.periodic_only:
         print(json.dumps({"periodic": periodic_record(exx, torch, max(args.periodic_steps, 1),
                                                       min(args.backward_steps, 1))}), flush=True)
+        return
+    if args.peaks:
+        print(json.dumps({"attainable_peaks": attainable_peaks(torch)}), flush=True)
         return
     cfg, wname = WORKLOADS[args.workload]
     sysm = synth.config(cfg)
