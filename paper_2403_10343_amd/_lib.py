@@ -108,6 +108,35 @@ def lib():
     return L
 
 
+TUNE_CACHE_ENV = "EXX_TUNE_CACHE"
+
+
+def load_tune_cache(path):
+    """{key: {"choices": [3 ints], "ms": [9 floats]}} from a tile cache file ({} if the
+    file is missing or unreadable)."""
+    import json
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_tune_cache(path, key, entry):
+    """Add or replace one entry of a tile cache file (written to a temporary file in the
+    same directory, then renamed over the old one)."""
+    import json
+    import tempfile
+    data = load_tune_cache(path)
+    data[key] = entry
+    d = os.path.dirname(os.path.abspath(path))
+    fd, tmp = tempfile.mkstemp(dir=d, prefix=".tune", suffix=".json")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 def _check(rc):
     if rc != EXX_OK:
         raise ExxError(rc, lib().exx_last_error().decode())
@@ -366,12 +395,39 @@ class Plan:
 
     TUNING_NAMES = (("E k-chunk", (16, 32)), ("T2 columns x waves", ("4x4", "8x4", "8x8")), ("Y k-chunk", (16, 32)))
 
-    def autotune(self, C, V, D, K, precision=PREC_FP64, stream=None):
+    def tune_key(self, arch, precision=PREC_FP64):
+        """Key of this plan's shape in a tile cache: GPU architecture, precision and the
+        plan's sizes and flop count."""
+        i = self.info
+        return (f"{arch}|prec{int(precision)}|atoms{i['n_atoms']}|systems{i['n_systems']}|pairs{i['n_pairs']}"
+                f"|d{i['d_size']}|flops{i['flops_fp64']}|chunks{i['n_chunks']}")
+
+    def autotune(self, C, V, D, K, precision=PREC_FP64, stream=None, cache=None):
         """Time the compiled tile variants of the E, T2 and Y stages on these
-        inputs and keep the fastest (blocking); K holds a build afterwards."""
+        inputs and keep the fastest (blocking); K holds a build afterwards.
+
+        cache: path of a JSON file of chosen tiles keyed by tune_key (default: the
+        EXX_TUNE_CACHE environment variable; no cache when neither is given).  A hit
+        sets the stored tiles and runs one build instead of the timings; a miss times
+        the variants and stores the choice."""
+        path = cache if cache is not None else os.environ.get(TUNE_CACHE_ENV)
+        key = None
+        if path:
+            import torch
+            key = self.tune_key(torch.cuda.get_device_properties(C.device).gcnArchName, precision)
+            entry = load_tune_cache(path).get(key)
+            if entry is not None:
+                self.set_tuning(entry["choices"])
+                self.build_K(C, V, D, K, precision=precision, stream=stream)
+                return
         c, v, d = self._cvd(C, V, D)
         _check(lib().exx_plan_autotune(self._h, c, v, d, int(precision), _dev(K, self.info["d_size"], "K"),
                                        _stream(stream)))
+        if key is not None:
+            ch = np.zeros(3, np.int32)
+            ms = np.zeros(9, np.float32)
+            _check(lib().exx_plan_tuning(self._h, ch.ctypes.data, ms.ctypes.data))
+            store_tune_cache(path, key, {"choices": [int(x) for x in ch], "ms": [float(x) for x in ms]})
 
     def tuning(self):
         """{stage: (chosen tile value, {tile value: ms})} (ms empty before tuning)."""

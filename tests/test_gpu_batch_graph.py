@@ -132,3 +132,31 @@ def test_every_tile_variant_and_the_autotuner(exx):
     assert relmax(Kt.cpu().numpy(), base) < 1e-12
     K2, _ = run_build(plan, inp, torch)
     assert np.array_equal(K2, Kt.cpu().numpy())
+
+
+def test_autotuner_tile_cache(exx, tmp_path, monkeypatch):
+    """A tile cache file (EXX_TUNE_CACHE): the first autotune times the variants and
+    stores the choice; a second plan of the same shape takes it without timing and
+    builds the same K bit for bit."""
+    from paper_2403_10343_amd._lib import load_tune_cache
+    path = str(tmp_path / "tiles.json")
+    monkeypatch.setenv("EXX_TUNE_CACHE", path)
+    sysm = synth.ice_box(2, 2, 1, seed=3)
+    inp = synth.make_inputs(sysm)
+    C, V, D = device_inputs(inp, torch)
+    p1 = exx.Plan.for_system(sysm)
+    K1 = torch.empty_like(D)
+    p1.autotune(C, V, D, K1)
+    t1 = p1.tuning()
+    assert all(len(ms) > 0 for _, ms in t1.values())
+    assert len(load_tune_cache(path)) == 1
+    p2 = exx.Plan.for_system(sysm)
+    K2 = torch.empty_like(D)
+    p2.autotune(C, V, D, K2)
+    t2 = p2.tuning()
+    assert {k: v[0] for k, v in t2.items()} == {k: v[0] for k, v in t1.items()}
+    assert all(len(ms) == 0 for _, ms in t2.values())
+    K3 = torch.empty_like(D)
+    p1.build_K(C, V, D, K3)
+    torch.cuda.synchronize()
+    assert torch.equal(K2, K3)

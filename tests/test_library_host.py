@@ -218,3 +218,28 @@ def test_new_entry_points_reject_before_the_library():
     k = np.array([np.nan, 0.0, 0.0])
     assert L.exx_bloch_sum(p._h, ctypes.c_void_p(1), 1, k.ctypes.data, ctypes.c_void_p(1), None) == -4
     assert L.exx_density_from_k(None, 1, k.ctypes.data, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+
+
+def test_tile_cache_file(tmp_path):
+    """The tile cache: entries stored and read back by key, other entries kept,
+    a missing or corrupt file reads as empty; keys separate precisions, plan
+    shapes and chunking."""
+    from paper_2403_10343_amd import Plan
+    from paper_2403_10343_amd._lib import load_tune_cache, store_tune_cache
+    path = str(tmp_path / "tiles.json")
+    assert load_tune_cache(path) == {}
+    store_tune_cache(path, "a", {"choices": [0, 2, 1], "ms": [1.0] * 9})
+    store_tune_cache(path, "b", {"choices": [1, 0, 0], "ms": [2.0] * 9})
+    c = load_tune_cache(path)
+    assert c["a"]["choices"] == [0, 2, 1] and c["b"]["choices"] == [1, 0, 0]
+    (tmp_path / "bad.json").write_text("{not json")
+    assert load_tune_cache(str(tmp_path / "bad.json")) == {}
+    s1, s2 = synth.water_cluster(2, seed=0), synth.water_cluster(3, seed=0)
+    p1, p2 = Plan.for_system(s1, host_only=True), Plan.for_system(s2, host_only=True)
+    assert p1.tune_key("gfx950") == Plan.for_system(s1, host_only=True).tune_key("gfx950")
+    assert p1.tune_key("gfx950") != p2.tune_key("gfx950")
+    assert p1.tune_key("gfx950", 0) != p1.tune_key("gfx950", 1)
+    big = synth.ice_box(2, 2, 2, seed=0)
+    st = Plan.for_system(big, host_only=True).info["intermediate_bytes_stored"]
+    assert (Plan.for_system(big, host_only=True).tune_key("gfx950")
+            != Plan.for_system(big, host_only=True, ws_budget_bytes=st // 2).tune_key("gfx950"))
