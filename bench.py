@@ -196,11 +196,11 @@ def path_record(plan, dt, stage_ms, mixed, names, workload):
     fp32_stage = names[dom].endswith("_32") or names[dom] == "H32"
     peak = PEAK["fp32"] if fp32_stage else PEAK["fp64"]
     achieved = alg[dom] / (stage_ms[dom] * 1e-3) if stage_ms[dom] > 0 else 0.0
-    key = ("mixed" if mixed else "fp64", names[dom])
-    traffic = None
-    if (MEASURED_TRAFFIC["workload"] == workload and sources_fingerprint() == MEASURED_TRAFFIC["sources"]
-            and key in MEASURED_TRAFFIC["bytes"]):
-        traffic = MEASURED_TRAFFIC["bytes"][key]
+    path = "mixed" if mixed else "fp64"
+    measured = {}
+    if MEASURED_TRAFFIC["workload"] == workload and sources_fingerprint() == MEASURED_TRAFFIC["sources"]:
+        measured = {st: b for (pth, st), b in MEASURED_TRAFFIC["bytes"].items() if pth == path}
+    traffic = measured.get(names[dom])
     per_stage = lambda f: {names[i]: f(i) for i in range(len(names))}
     return {
         "builds_per_s": 1.0 / dt, "ms_per_build": 1e3 * dt,
@@ -210,6 +210,10 @@ def path_record(plan, dt, stage_ms, mixed, names, workload):
             lambda i: issued[i] / (stage_ms[i] * 1e-3) / (PEAK["fp32"] if names[i] in ("H32", "T2_32") else PEAK["fp64"])
             if stage_ms[i] > 0 else 0.0),
         "fp32_flop_fraction": (alg[3] + alg[5]) / max(sum(alg), 1),
+        # HBM read + write bytes of a stage's kernels from the committed counter runs (same
+        # sources and workload only) over the stage's time
+        "stage_hbm_gb_per_s": {st: float(b / (stage_ms[names.index(st)] * 1e-3) / 1e9)
+                               for st, b in measured.items() if st in names and stage_ms[names.index(st)] > 0},
         "roofline": {"bound": "mfma", "kernel": KERNEL_OF_STAGE[names[dom]], "stage": names[dom],
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
