@@ -1899,24 +1899,84 @@ int exchange_backward_spin(exx_plan plan, const double* C, const double* V, cons
   if (rc != EXX_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
+  DevPlan& d = plan->d;
   const int64_t ds = hp.d_size, nc = hp.c_off.back(), nv = hp.v_off.back();
   const bool needC = dC || forces, needV = dV || forces;
   if (needC && !dC && (rc = scratch_buf(plan, plan->dC_scratch, nc)) != EXX_OK) return rc;
   if (needV && !dV && (rc = scratch_buf(plan, plan->dV_scratch, nv)) != EXX_OK) return rc;
   if (needC && (rc = scratch_buf(plan, plan->dC_spin1, nc)) != EXX_OK) return rc;
+  if (needC && (rc = scratch_buf(plan, plan->spin_GD1, hp.t_total)) != EXX_OK) return rc;
   if (needV && (rc = scratch_buf(plan, plan->dV_spin1, nv)) != EXX_OK) return rc;
   if ((rc = scratch_buf(plan, plan->gE_spin, hp.n_sys)) != EXX_OK) return rc;
+  if ((rc = second_workspace(plan)) != EXX_OK) return rc;
   double* dCb = dC ? dC : plan->dC_scratch;
   double* dVb = dV ? dV : plan->dV_scratch;
-  // E_x = -1/2 sum_s K^s D^s is twice the one-density energy of each spin, so each spin
+  // E_x = -1/2 sum_s K^s D^s is twice the one-density energy of each spin: every spin's part
   // is the one-density backward with upstream 2 gE
   hipLaunchKernelGGL(k_scale_vec, dim3((hp.n_sys + 255) / 256), dim3(256), 0, st, plan->gE_spin, gE, 2.0, hp.n_sys);
-  for (int s = 0; s < 2; ++s)
-    backward_density(plan, C, V, D + s * ds, K ? K + s * ds : nullptr, plan->gE_spin,
-                     s ? plan->dC_spin1 : dCb, s ? plan->dV_spin1 : dVb, dD ? dD + s * ds : nullptr, needC, needV,
-                     s == 0, st);
-  if (needC) hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dCb, plan->dC_spin1, nc);
-  if (needV) hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dVb, plan->dV_spin1, nv);
+  const dim3 gsys(256, hp.n_sys);
+  if (dD) {
+    // dE/dD^s = -gE K^s: from the caller's K, or from a (never screened) spin build into dD
+    if (!K) {
+      const double eps = plan->scr_eps;
+      const bool prof = plan->profiling;
+      plan->scr_eps = 0;
+      plan->profiling = false;
+      rc = build_K_spin(plan, C, V, D, EXX_PREC_FP64, dD, nullptr, stream);
+      plan->scr_eps = eps;
+      plan->profiling = prof;
+      if (rc != EXX_OK) return rc;
+    }
+    for (int s = 0; s < 2; ++s)
+      hipLaunchKernelGGL(k_scaled_copy_sys, gsys, dim3(256), 0, st, dD + s * ds, (K ? K : dD) + s * ds,
+                         plan->gE_spin, d, -0.5);
+  }
+  if (needC || needV) {
+    // both spins in one pass per chunk: E^s together, the V stage with F shared (G term taken
+    // once), then the gradient products and dV blocks per spin
+    launch_dmask(plan, D, d.Dm, st);
+    launch_dmask(plan, D + ds, plan->spin_Dm1, st);
+    launch_repack(plan, C, st);
+    launch_vd_operands(plan, V, D, st);
+    if (!hp.pair_a.empty())
+      hipLaunchKernelGGL(k_vdrepack, dim3((unsigned)hp.pair_a.size()), dim3(256), 0, st, nullptr, D + ds,
+                         plan->spin_Dr1, d, 0);
+    for (int c = 0; c < n_chunks(plan); ++c) {
+      set_chunk(plan, c);
+      const ChunkDev& ch = cur_chunk(plan);
+      launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), ch.n_e, st);
+      if (needC) {
+        launch_H_lists<double, 2>(plan, V, D,
+                                  HLists{d.g_tiles + ch.gt_beg, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
+                                         plan->spin_H1, plan->spin_Dr1},
+                                  ch.gt_end - ch.gt_beg, 1.0, H_WRITE, st);
+        launch_rowD(plan, d.Dm, rowd_GD(plan), ch.gd_end - ch.gd_beg, st);
+        double* const H0 = d.H;
+        double* const GD0 = d.GD;
+        d.H = plan->spin_H1;
+        d.GD = plan->spin_GD1;
+        launch_rowD(plan, plan->spin_Dm1, rowd_GD(plan), ch.gd_end - ch.gd_beg, st);
+        d.H = H0;
+        d.GD = GD0;
+      }
+      if (needV) {
+        launch_dV(plan, V, D, dVb, plan->gE_spin, st);
+        double* const E0 = d.E;
+        d.E = plan->spin_E1;
+        launch_dV(plan, V, D + ds, plan->dV_spin1, plan->gE_spin, st);
+        d.E = E0;
+      }
+    }
+    set_chunk(plan, 0);
+    if (needC) {
+      const unsigned ne = (unsigned)hp.nbr_ptr[hp.n_atoms];
+      hipLaunchKernelGGL(k_unrepack, dim3(ne), dim3(256), 0, st, d.GD, dCb, d, plan->gE_spin, -1.0);
+      hipLaunchKernelGGL(k_unrepack, dim3(ne), dim3(256), 0, st, plan->spin_GD1, plan->dC_spin1, d, plan->gE_spin,
+                         -1.0);
+      hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dCb, plan->dC_spin1, nc);
+    }
+    if (needV) hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dVb, plan->dV_spin1, nv);
+  }
   if (forces) launch_forces(plan, C, V, dCb, dVb, forces, c_decay, v_2s2, st);
   HIP_TRY(hipGetLastError());
   return EXX_OK;

@@ -239,6 +239,7 @@ struct exx_plan_s {
   double* spin_H1 = nullptr;
   double* spin_Dr1 = nullptr;       // lane-ordered D operands of the second spin
   double* spin_Dm1 = nullptr;       // pair-block copy of the second spin's D
+  double* spin_GD1 = nullptr;       // the second spin's gradient product (exchange_backward_spin)
   int64_t dr_total = 0;             // doubles of the lane-ordered D operands (DevPlan::Dr)
   // chunks of aux atoms (one for an unbounded plan) and the one the launchers use
   std::vector<ChunkDev> chunks;
