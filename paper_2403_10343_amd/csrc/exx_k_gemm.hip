@@ -260,14 +260,18 @@ __global__ __launch_bounds__(256) void k_Y(DevPlan d, int n_tiles, int n_padded)
 // stage 4b: K = T2 + (X + X^T)/2 with X[i, l] = sum_P Y_P[c1_P(i), c2_P(l)]
 // (c1: column of T_P, c2: column of H'_P).  One workgroup per 32 x 32 tile
 // pair of the upper triangle; the aux atoms of its list are visited in a
-// fixed order.  X[i, l] is gathered with l fastest across threads and
+// fixed order, two per step (the loads of both issued together, the maps of
+// the next two fetched meanwhile).  X[i, l] is gathered with l fastest across threads and
 // X[l, i] with i fastest (both coalesced), the two halves are combined in
 // LDS, and every element is written together with its mirror.
 
 __global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPlan d, int n_items,
                                                    int n_padded) {
-  __shared__ int cmap[4][32];      // c1(I rows), c2(I rows), c1(L cols), c2(L cols)
+  constexpr int PB = 128;                 // aux atoms whose list data are staged per round
+  __shared__ int cmap[2][4][32];   // two aux atoms: c1(I rows), c2(I rows), c1(L cols), c2(L cols)
   __shared__ double xa[32][33], xb[32][33];
+  __shared__ int64_t s_yoff[PB], s_moff[PB];
+  __shared__ int s_n[PB];
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
   const FItem it = d.f_items[w];
@@ -276,27 +280,66 @@ __global__ __launch_bounds__(256) void k_symreduce(double* __restrict__ K, DevPl
   const int t = threadIdx.x;
   const int ta = t & 31, tb = t >> 5;   // element (tb + 8 r, ta)
   double acc_a[4] = {0, 0, 0, 0}, acc_b[4] = {0, 0, 0, 0};
-  for (int pi = it.pbeg; pi < it.pend; ++pi) {
-    const int P = d.f_plist[pi];
-    const int nP_ = d.m_loc[P];
-    const double* Y = d.Y + d.y_off[P];
+  // per round of PB aux atoms their list data in LDS; per step two atoms' column maps in LDS
+  // (threads < 128 load the next two atoms' maps while the current Y entries are gathered)
+  const int which = (t >> 5) & 3, xm = t & 31;
+  const int gm = ((which < 2) ? it.gI0 : it.gL0) + xm;
+  const int* mbase = (which & 1) ? d.map2 : d.map1;
+  for (int p0 = it.pbeg; p0 < it.pend; p0 += PB) {
+    const int nb = min(PB, it.pend - p0);
     __syncthreads();
-    if (t < 128) {
-      const int which = t >> 5, x = t & 31;
-      const int g = ((which < 2) ? it.gI0 : it.gL0) + x;
-      const int* mp = ((which & 1) ? d.map2 : d.map1) + d.map_off[P];
-      cmap[which][x] = g < ns ? mp[g] : -1;
+    for (int j = t; j < nb; j += 256) {
+      const int P = d.f_plist[p0 + j];
+      s_n[j] = d.m_loc[P];
+      s_yoff[j] = d.y_off[P];
+      s_moff[j] = d.map_off[P];
     }
     __syncthreads();
+    auto map_at = [&](int j) { return (t < 128 && j < nb && gm < ns) ? mbase[s_moff[j] + gm] : -1; };
+    if (t < 128) {
+      cmap[0][which][xm] = map_at(0);
+      cmap[1][which][xm] = map_at(1);
+    }
+    int m2 = map_at(2), m3 = map_at(3);
+    __syncthreads();
+    // two aux atoms per step: the loads of both are issued together, then added in list order
+    for (int j = 0; j < nb; j += 2) {
+      double ya[2][4], yb[2][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ii = tb + 8 * r;
-      // X[i = I0 + ii, l = L0 + ta] = Y_P[c1(i), c2(l)]
-      const int c1 = cmap[0][ii], c2 = cmap[3][ta];
-      if (c1 >= 0 && c2 >= 0) acc_a[r] += Y[(size_t)c1 * nP_ + c2];
-      // X[l = L0 + ii, i = I0 + ta] = Y_P[c1(l), c2(i)], stored at (ta, ii)
-      const int d1 = cmap[2][ii], d2 = cmap[1][ta];
-      if (d1 >= 0 && d2 >= 0) acc_b[r] += Y[(size_t)d1 * nP_ + d2];
+      for (int u = 0; u < 2; ++u) {
+        const bool jv = j + u < nb;
+        const int nP_ = s_n[jv ? j + u : j];
+        const double* Y = d.Y + s_yoff[jv ? j + u : j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = tb + 8 * r;
+          // X[i = I0 + ii, l = L0 + ta] = Y_P[c1(i), c2(l)]
+          const int c1 = cmap[u][0][ii], c2 = cmap[u][3][ta];
+          ya[u][r] = (jv && c1 >= 0 && c2 >= 0) ? Y[(size_t)c1 * nP_ + c2] : 0.0;
+          // X[l = L0 + ii, i = I0 + ta] = Y_P[c1(l), c2(i)], stored at (ta, ii)
+          const int d1 = cmap[u][2][ii], d2 = cmap[u][1][ta];
+          yb[u][r] = (jv && d1 >= 0 && d2 >= 0) ? Y[(size_t)d1 * nP_ + d2] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (j + u < nb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ii = tb + 8 * r;
+            if (cmap[u][0][ii] >= 0 && cmap[u][3][ta] >= 0) acc_a[r] += ya[u][r];
+            if (cmap[u][2][ii] >= 0 && cmap[u][1][ta] >= 0) acc_b[r] += yb[u][r];
+          }
+        }
+      }
+      __syncthreads();
+      if (t < 128) {
+        cmap[0][which][xm] = m2;
+        cmap[1][which][xm] = m3;
+      }
+      m2 = map_at(j + 4);
+      m3 = map_at(j + 5);
+      __syncthreads();
     }
   }
   __syncthreads();
