@@ -301,7 +301,8 @@ struct RowD {
 };
 
 // Batched GEMM: 64 x 64 output tile per workgroup of four wavefronts (32 x 32
-// each), k in steps of 16 staged through double-buffered LDS.  The k index
+// each), k in chunks staged through one LDS stage, the next chunk loaded into
+// registers meanwhile.  The k index
 // runs over the basis functions of the input atoms listed for the tile's
 // column tile (runs of consecutive atoms: column lcol.. of A, row grow.. of D).
 constexpr int ET = 64, EPITCH = ET + 4;

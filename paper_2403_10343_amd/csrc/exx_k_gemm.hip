@@ -6,14 +6,17 @@
 using namespace exx;
 
 
-// EK: k-chunk per LDS stage (a tuning choice: 16 or 32).  NSP = 2 (collinear spin): the
+// EK: k-chunk per LDS stage (a tuning choice: 16 or 32); the next chunk is loaded into
+// registers while the current one is multiplied.  NSP = 2 (collinear spin): the
 // products with D (into r.O) and D1 (into O1) in one pass, the A_P tile staged once.
 // PER: periodic plans (image check on every D element, see RowD::ocolimg)
 template <int EK, int NSP, bool PER>
 __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD r, DevPlan d, int n_items,
                                               int n_padded, const double* __restrict__ D1, double* __restrict__ O1) {
-  __shared__ double As[2][EK][EPITCH];
-  __shared__ double Bs[NSP][2][EK][EPITCH];
+  // one LDS stage (the next chunk waits in registers): half the LDS of two stages, so more
+  // workgroups are resident per CU
+  __shared__ double As[EK][EPITCH];
+  __shared__ double Bs[NSP][EK][EPITCH];
   const int w = xcd_task(n_padded);
   if (w >= n_items) return;
   const EItem it = r.items[w];
@@ -91,15 +94,15 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&]() {
 #pragma unroll
-    for (int x = 0; x < NA_; ++x) As[buf][ka][ma + MS * x] = va[x];
+    for (int x = 0; x < NA_; ++x) As[ka][ma + MS * x] = va[x];
 #pragma unroll
     for (int sp = 0; sp < NSP; ++sp)
 #pragma unroll
       for (int pz = 0; pz < NP; ++pz)
 #pragma unroll
-        for (int x = 0; x < 4; ++x) Bs[sp][buf][16 * pz + kb][nb0 + x] = vb[sp][pz][x];
+        for (int x = 0; x < 4; ++x) Bs[sp][16 * pz + kb][nb0 + x] = vb[sp][pz][x];
   };
   d4 acc[NSP][2][2];
 #pragma unroll
@@ -109,9 +112,8 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
 #pragma unroll
       for (int y = 0; y < 2; ++y) acc[sp][x][y] = d4{0, 0, 0, 0};
   gload(0);
-  sstore(0);
+  sstore();
   __syncthreads();
-  int buf = 0;
   const uint8_t* kf = r.kflag + r.kflag_off[it.ct];
   const int q0 = wn >> 4;   // this wavefront's column quarters q0, q0 + 1
   // and its two 16-row blocks: skipped where they lie past s_P (uniform per wavefront)
@@ -123,25 +125,25 @@ __global__ __launch_bounds__(256) void k_rowD(const double* __restrict__ D, RowD
     for (int ks = 0; ks < EK; ks += 4) {
       // skip the products of 16 x 16 blocks where D is structurally zero (uniform per wavefront)
       const int f = (k0 + ks < klen) ? (kf[(k0 + ks) >> 4] >> q0) : 0;
-      const double a0 = As[buf][ks + lk][wm + lr], a1 = As[buf][ks + lk][wm + 16 + lr];
+      const double a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
 #pragma unroll
       for (int sp = 0; sp < NSP; ++sp) {
         if (f & 1) {
-          const double b0 = Bs[sp][buf][ks + lk][wn + lr];
+          const double b0 = Bs[sp][ks + lk][wn + lr];
           if (rv0) acc[sp][0][0] = mfma64(a0, b0, acc[sp][0][0]);
           if (rv1) acc[sp][1][0] = mfma64(a1, b0, acc[sp][1][0]);
         }
         if (f & 2) {
-          const double b1 = Bs[sp][buf][ks + lk][wn + 16 + lr];
+          const double b1 = Bs[sp][ks + lk][wn + 16 + lr];
           if (rv0) acc[sp][0][1] = mfma64(a0, b1, acc[sp][0][1]);
           if (rv1) acc[sp][1][1] = mfma64(a1, b1, acc[sp][1][1]);
         }
       }
     }
-    if (more) {
-      sstore(buf ^ 1);
+    if (more) {   // every wavefront is done with the stage before it is overwritten
       __syncthreads();
-      buf ^= 1;
+      sstore();
+      __syncthreads();
     }
   }
 #pragma unroll
