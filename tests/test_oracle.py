@@ -72,3 +72,16 @@ def test_hand_worked_two_atom_case():
     assert np.abs(O.k_full_rows(inp) - Kx).max() < 1e-12
     assert abs(e_k - g["E_x"]) < 1e-12 and abs(e_direct - g["E_x"]) < 1e-12
     assert abs(O.exchange_energy(Kx, inp.D.reshape(2, 2)) - g["E_x"]) < 1e-12
+
+
+def test_periodic_rows_of_atom_subsets():
+    """The periodic row route on a few atoms (what the GPU tests sample on large
+    boxes) gives the same rows as the whole cell, in any atom order, and with
+    the image table built by an earlier call."""
+    inp = synth.make_inputs(pins._tiny_periodic(23))
+    pb = O.PBlocks(inp)
+    X = O.x_periodic(inp)
+    for atoms in ([3], [4, 1], [0, 2, 3]):
+        rows = np.concatenate([np.arange(pb.bo[a], pb.bo[a + 1]) for a in atoms])
+        Xr = O.x_atom_rows_periodic(inp, atoms, pb)
+        assert pins.rel(Xr, X[rows]) < 1e-13
