@@ -311,16 +311,18 @@ def periodic_record(exx, torch, steps, backward_steps=1):
         fb = {}
         for name, prec in (("fp64", exx.PREC_FP64), ("mixed", exx.PREC_MIXED)):
             plan.build_K(C, V, D, K, Ex, precision=prec)
-            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K, build_id=plan.build_id())
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(backward_steps):
                 plan.build_K(C, V, D, K, Ex, precision=prec)
-                plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+                reused = plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K,
+                                                build_id=plan.build_id())
             torch.cuda.synchronize()
             tb = (time.perf_counter() - t0) / backward_steps
             progress(f"periodic box: {name} forward + backward {1e3 * tb:.1f} ms")
             fb[name] = {"workload": f"{name} forward E_x; FP64 backward: dE/dC, dE/dV, dE/dD, forces",
+                        "forward_intermediates_reused": reused,
                         "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
                         "net_force_max": float(F.view(-1, 3).sum(0).abs().max().item()),
                         "euler_C": float((dC * C).sum().item() / (2 * E64)),
@@ -459,17 +461,19 @@ def main():
             if prec == exx.PREC_MIXED and recm is None:
                 continue
             plan.build_K(C, V, D, K, Ex, precision=prec)
-            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+            plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K, build_id=plan.build_id())
             torch.cuda.synchronize()
             tb0 = time.perf_counter()
             for _ in range(args.backward_steps):
                 plan.build_K(C, V, D, K, Ex, precision=prec)
-                plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K)
+                reused = plan.exchange_backward(C, V, D, 1.0, dC=dC, dV=dV, dD=dD, forces=F, K=K,
+                                                build_id=plan.build_id())
             torch.cuda.synchronize()
             tb = (time.perf_counter() - tb0) / args.backward_steps
             Ff = F.view(-1, 3)
             fb[name] = {
                 "workload": wname + f" ({name} forward E_x; FP64 backward: dE/dC, dE/dV, dE/dD, forces)",
+                "forward_intermediates_reused": reused,
                 "ms_per_step": 1e3 * tb, "steps_per_s": 1.0 / tb,
                 "net_force_max": float(Ff.sum(0).abs().max().item()),
                 "euler_C": float((dC * C).sum().item() / (2 * E64)),

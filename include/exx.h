@@ -346,6 +346,30 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
                       double* dC, double* dV, double* dD, double* forces,
                       double c_decay, double v_2s2, void* stream);
 
+/* Generation of the plan's workspace (the intermediates E and H' of
+ * Eqs. temp_E and temp_H): a counter that every call writing them advances
+ * (build_K, build_K_spin, build_K_two_kernels, graph builds and replays, the
+ * backward calls).  Read it right after the build_K whose intermediates a
+ * later exchange_backward_reuse is to take.  EXX_EINVAL on NULL arguments. */
+int exx_plan_build_id(exx_plan plan, uint64_t* id);
+
+/* exchange_backward (same arguments, results and errors) taking E and H' from
+ * the workspace instead of recomputing them, when build_id is the current
+ * generation and that generation is a binary64 build_K without screening on a
+ * plan of one workspace chunk: H' then gets its G term back from factor 2 to
+ * factor 1 (Eq. ri_lvl_exchange_matrix with Eqs. temp_G and temp_H) by one
+ * G-only pass, and the rest is as in exchange_backward.  By passing build_id
+ * the caller vouches that C, V and D are unchanged since that build_K.  In any
+ * other case (another call wrote the workspace since, a mixed or screened
+ * build, a chunked plan) the intermediates are recomputed as in
+ * exchange_backward.  *reused (may be NULL) is set to 1 when they were taken,
+ * else 0.  Results agree with exchange_backward to rounding. */
+int exchange_backward_reuse(exx_plan plan, uint64_t build_id, const double* C,
+                            const double* V, const double* D, const double* K,
+                            const double* gE, int precision, double* dC,
+                            double* dV, double* dD, double* forces, double c_decay,
+                            double v_2s2, int* reused, void* stream);
+
 /* Gradients of the collinear-spin energy sum_s gE[s] * E_x[s] with
  * E_x = -1/2 sum_sigma sum_ik K^sigma_ik D^sigma_ik (build_K_spin; the spin
  * index of Eq. realspace_exchange selects the density matrix): D, K (optional)

@@ -57,7 +57,8 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "exx_plan_tuning", "exx_plan_set_tuning", "build_K_spin",
            "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images", "exx_block_norms",
            "exx_set_screening", "exx_screened_pairs", "exchange_backward_spin",
-           "exx_strain_derivative", "exx_bloch_sum", "exx_density_from_k")
+           "exx_strain_derivative", "exx_bloch_sum", "exx_density_from_k", "exx_plan_build_id",
+           "exchange_backward_reuse")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -84,6 +85,9 @@ def lib():
     L.exchange_energy_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.exchange_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
     L.exchange_backward_spin.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, dp, dp, vp]
+    L.exx_plan_build_id.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.exchange_backward_reuse.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp,
+                                          dp, dp, ctypes.POINTER(ctypes.c_int), vp]
     L.exx_strain_derivative.argtypes = [vp, vp, vp, vp, vp, dp, dp, vp, vp]
     L.exx_bloch_sum.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_density_from_k.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
@@ -315,20 +319,37 @@ class Plan:
         g[:] = np.asarray(gE, dtype=np.float64)
         return torch.from_numpy(g).to(device)
 
+    def build_id(self):
+        """Generation of the plan's workspace (advanced by every call that writes E and H')."""
+        x = ctypes.c_uint64(0)
+        _check(lib().exx_plan_build_id(self._h, ctypes.byref(x)))
+        return int(x.value)
+
     def exchange_backward(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
-                          precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):
+                          precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None, build_id=None):
         """Gradients of sum_s gE[s] E_x[s] (gE: a scalar for every system, or one
         value per system); K (optional) is this input's build_K result, reused
-        for dE/dD = -gE K/2 instead of a rebuild."""
+        for dE/dD = -gE K/2 instead of a rebuild.  build_id (optional): build_id()
+        read right after that build_K; the call then takes its E and H' when they
+        are still in the workspace (exchange_backward_reuse) and returns whether it
+        did, else None."""
         i = self.info
         c, v, d = self._cvd(C, V, D)
         g = self.gE_tensor(gE, C.device)
-        _check(lib().exchange_backward(self._h, c, v, d, _dev(K, i["d_size"], "K", True),
-                                       _dev(g, self.n_systems, "gE"), int(precision),
-                                       _dev(dC, i["c_size"], "dC", True), _dev(dV, i["v_size"], "dV", True),
-                                       _dev(dD, i["d_size"], "dD", True), _dev(forces, 3 * self.n_atoms, "forces", True),
-                                       float(c_decay), float(v_2s2), _stream(stream)))
+        args = (c, v, d, _dev(K, i["d_size"], "K", True), _dev(g, self.n_systems, "gE"), int(precision),
+                _dev(dC, i["c_size"], "dC", True), _dev(dV, i["v_size"], "dV", True),
+                _dev(dD, i["d_size"], "dD", True), _dev(forces, 3 * self.n_atoms, "forces", True),
+                float(c_decay), float(v_2s2))
+        used = None
+        if build_id is None:
+            _check(lib().exchange_backward(self._h, *args, _stream(stream)))
+        else:
+            r = ctypes.c_int(0)
+            _check(lib().exchange_backward_reuse(self._h, ctypes.c_uint64(int(build_id)), *args, ctypes.byref(r),
+                                                 _stream(stream)))
+            used = bool(r.value)
         self._last_gE = g   # keeps the per-system array alive while the call may still run
+        return used
 
     def exchange_backward_spin(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
                                precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):

@@ -3,7 +3,8 @@
 ``exchange_energy(plan, C, V, D, precision)`` returns E_x per system (FP64 or
 mixed forward); its backward calls the library's binary64 exchange_backward
 kernels for dE/dC, dE/dV and dE/dD with each system's upstream gradient,
-reusing the forward K for dE/dD.
+reusing the forward K for dE/dD and, after a binary64 forward whose workspace
+no other call has overwritten, the forward's intermediates E and H'.
 ``spin_exchange_energy(plan, C, V, D)`` is the same for the collinear-spin
 energy (two density matrices, binary64).
 ``exchange_forces(plan, C, V, D)`` returns -dE_x/dR for the synthetic
@@ -22,6 +23,9 @@ class _ExchangeEnergy(torch.autograd.Function):
         plan.build_K(C, V, D, K, Ex, precision=precision)
         ctx.save_for_backward(C, V, D, K)
         ctx.plan = plan
+        # the workspace generation of this build: the backward takes its E and H' if no
+        # other call has written the workspace since (binary64 builds only)
+        ctx.build_id = plan.build_id() if precision == PREC_FP64 else None
         return Ex
 
     @staticmethod
@@ -34,7 +38,7 @@ class _ExchangeEnergy(torch.autograd.Function):
         dD = torch.empty_like(D) if need[2] else None
         if dC is not None or dV is not None or dD is not None:
             # binary64 gradient kernels; dE/dD = -K/2 reuses the forward K (of either precision)
-            ctx.plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K)
+            ctx.plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K, build_id=ctx.build_id)
         return dC, dV, dD, None, None
 
 

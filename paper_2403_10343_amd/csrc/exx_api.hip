@@ -1256,6 +1256,13 @@ static void build_chunks(exx_plan plan, const double* V, const double* D, double
   set_chunk(plan, 0);
 }
 
+// a call has written the workspace; fp64_build: E and H' are now those of a binary64,
+// unscreened, single-chunk build_K of the call's inputs
+static void ws_written(exx_plan plan, bool fp64_build) {
+  ++plan->ws_seq;
+  plan->ws_fp64 = fp64_build ? plan->ws_seq : 0;
+}
+
 // mixed list set of a precision, or -1 for binary64; -2: unknown, -3: reserved
 static int precision_set(int precision) {
   switch (precision) {
@@ -1299,6 +1306,7 @@ int build_K(exx_plan plan, const double* C, const double* V, const double* D, in
   build_chunks(plan, V, D, K, m, st);
   plan->d.scr = nullptr;
   if (screened) plan->scr_done = true;
+  ws_written(plan, m < 0 && !screened && n_chunks(plan) == 1);
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
@@ -1420,6 +1428,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   set_chunk(plan, 0);
   d.scr = nullptr;
   if (screened) plan->scr_done = true;
+  ws_written(plan, false);
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
@@ -1490,6 +1499,7 @@ int build_K_two_kernels(exx_plan plan, const double* C, const double* V, const d
   }
   set_chunk(plan, 0);
   if (plan->scr_eps > 0) plan->scr_done = true;
+  ws_written(plan, false);
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st);
@@ -1518,6 +1528,7 @@ int exx_graph_build(exx_plan plan, const double* C, const double* V, const doubl
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(st, &g);
   plan->profiling = prof;
+  ws_written(plan, false);   // the capture ran nothing
   if (rc != EXX_OK) { if (g) hipGraphDestroy(g); return rc; }
   if (e != hipSuccess) return fail(EXX_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   plan->graph = g;
@@ -1529,6 +1540,7 @@ int exx_graph_launch(exx_plan plan, void* stream) {
   if (!plan) return fail(EXX_EINVAL, "exx_graph_launch: NULL plan");
   if (!plan->graph_exec) return fail(EXX_ESTATE, "exx_graph_launch: no graph built");
   HIP_TRY(hipGraphLaunch(plan->graph_exec, (hipStream_t)stream));
+  ws_written(plan, false);
   return EXX_OK;
 }
 
@@ -1788,9 +1800,11 @@ static void backward_chunk(exx_plan plan, const double* V, const double* D, doub
 // One density matrix's part of the backward pass: dD (if asked) from K or a rebuild, and the
 // dC, dV blocks of sum_s gE[s] E_x[s] written (not added) into dCb, dVb.  C is repacked
 // into T when repack is set (it does not depend on D).  (Launches only.)
+// reuse: E and H' in the workspace are those of a binary64 build_K of these inputs (single
+// chunk); they are taken instead of recomputed, with the G term brought back to once.
 static void backward_density(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
                              const double* gE, double* dCb, double* dVb, double* dD, bool needC, bool needV,
-                             bool repack, hipStream_t st) {
+                             bool repack, hipStream_t st, bool reuse = false) {
   const HostPlan& hp = plan->hp;
   DevPlan& d = plan->d;
   const dim3 gsys(256, hp.n_sys);
@@ -1819,6 +1833,11 @@ static void backward_density(exx_plan plan, const double* C, const double* V, co
       plan->profiling = prof;
     }
     hipLaunchKernelGGL(k_scaled_copy_sys, gsys, dim3(256), 0, st, dD, dD, gE, d, -0.5);
+  }
+  if (reuse && !h_ready && (needC || needV)) {
+    // the build wrote H' with the G term twice (factor 2); the gradient takes it once
+    if (needC) launch_H(plan, V, D, -1.0, H_G_ADD, st);
+    h_ready = true;
   }
   if (needC || needV) {
     for (int c = 0; c < n_chunks(plan); ++c) {
@@ -1862,10 +1881,10 @@ static int scratch_buf(exx_plan plan, double*& buf, int64_t n) {
   return EXX_OK;
 }
 
-int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
-                      const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
-                      double c_decay, double v_2s2, void* stream) {
-  int rc = backward_checks(plan, "exchange_backward", C, V, D, gE, precision, forces, c_decay, v_2s2);
+static int backward_one(exx_plan plan, const char* who, bool reuse, const double* C, const double* V,
+                        const double* D, const double* K, const double* gE, int precision, double* dC, double* dV,
+                        double* dD, double* forces, double c_decay, double v_2s2, void* stream) {
+  int rc = backward_checks(plan, who, C, V, D, gE, precision, forces, c_decay, v_2s2);
   if (rc != EXX_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
@@ -1874,10 +1893,35 @@ int exchange_backward(exx_plan plan, const double* C, const double* V, const dou
   if (needV && !dV && (rc = scratch_buf(plan, plan->dV_scratch, hp.v_off.back())) != EXX_OK) return rc;
   double* dCb = dC ? dC : plan->dC_scratch;
   double* dVb = dV ? dV : plan->dV_scratch;
-  backward_density(plan, C, V, D, K, gE, dCb, dVb, dD, needC, needV, true, st);
+  backward_density(plan, C, V, D, K, gE, dCb, dVb, dD, needC, needV, true, st, reuse);
+  if (needC || needV || (dD && !K)) ws_written(plan, false);
   if (forces) launch_forces(plan, C, V, dCb, dVb, forces, c_decay, v_2s2, st);
   HIP_TRY(hipGetLastError());
   return EXX_OK;
+}
+
+int exchange_backward(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                      const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
+                      double c_decay, double v_2s2, void* stream) {
+  return backward_one(plan, "exchange_backward", false, C, V, D, K, gE, precision, dC, dV, dD, forces, c_decay,
+                      v_2s2, stream);
+}
+
+int exx_plan_build_id(exx_plan plan, uint64_t* id) {
+  if (!plan || !id) return fail(EXX_EINVAL, "exx_plan_build_id: NULL argument");
+  *id = plan->ws_seq;
+  return EXX_OK;
+}
+
+int exchange_backward_reuse(exx_plan plan, uint64_t build_id, const double* C, const double* V, const double* D,
+                            const double* K, const double* gE, int precision, double* dC, double* dV, double* dD,
+                            double* forces, double c_decay, double v_2s2, int* reused, void* stream) {
+  const bool reuse = plan && build_id != 0 && build_id == plan->ws_seq && build_id == plan->ws_fp64 &&
+                     n_chunks(plan) == 1;
+  const int rc = backward_one(plan, "exchange_backward_reuse", reuse, C, V, D, K, gE, precision, dC, dV, dD, forces,
+                              c_decay, v_2s2, stream);
+  if (reused) *reused = (rc == EXX_OK && reuse) ? 1 : 0;
+  return rc;
 }
 
 // y += x over n doubles
@@ -1976,6 +2020,7 @@ int exchange_backward_spin(exx_plan plan, const double* C, const double* V, cons
       hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dCb, plan->dC_spin1, nc);
     }
     if (needV) hipLaunchKernelGGL(k_add, dim3(2048), dim3(256), 0, st, dVb, plan->dV_spin1, nv);
+    ws_written(plan, false);
   }
   if (forces) launch_forces(plan, C, V, dCb, dVb, forces, c_decay, v_2s2, st);
   HIP_TRY(hipGetLastError());

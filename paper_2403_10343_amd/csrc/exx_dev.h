@@ -254,6 +254,11 @@ struct exx_plan_s {
   double* scr_nrm = nullptr;
   uint8_t* scr_flags = nullptr;
   bool scr_done = false;
+  // workspace generations: ws_seq counts the calls that write E and H'; ws_fp64 is the
+  // generation whose E and H' are those of a binary64, unscreened, single-chunk build_K
+  // (0: none), which exchange_backward_reuse may take instead of recomputing them
+  uint64_t ws_seq = 0;
+  uint64_t ws_fp64 = 0;
 };
 
 // Point the device plan and the launchers at chunk c.

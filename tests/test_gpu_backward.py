@@ -228,3 +228,93 @@ def test_forces_fd_on_24_atoms_of_the_768_box(exx):
     go = O.gradients(ci)
     assert relmax(gc["dC"], go["dC"]) < 1e-10 and relmax(gc["dV"], go["dV"]) < 1e-10
     assert relmax(gc["F"], O.forces(ci, go)) < 1e-10
+
+
+def _grads(plan, C, V, D, gE, K, build_id=None, want=("dC", "dV", "dD", "F")):
+    dC = torch.empty_like(C) if "dC" in want else None
+    dV = torch.empty_like(V) if "dV" in want else None
+    dD = torch.empty_like(D) if "dD" in want else None
+    F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device="cuda:0") if "F" in want else None
+    used = plan.exchange_backward(C, V, D, gE, dC=dC, dV=dV, dD=dD, forces=F, K=K, build_id=build_id)
+    torch.cuda.synchronize()
+    return used, {k: x.cpu().numpy() for k, x in (("dC", dC), ("dV", dV), ("dD", dD), ("F", F)) if x is not None}
+
+
+def test_backward_reuses_forward_intermediates(exx):
+    """After a binary64 build_K, exchange_backward_reuse takes E and H' from the
+    workspace: dD and dV equal the recomputing backward's bit for bit (E is the
+    same), dC and the forces to rounding (H' gets its G term back to once by a
+    pass of its own).  Once any call has written the workspace since, or after
+    a mixed or screened build, it recomputes and equals exchange_backward bit
+    for bit."""
+    sysm = synth.water_cluster(8, 3)
+    inp = synth.make_inputs(sysm)
+    plan = exx.Plan.for_system(sysm)
+    C, V, D = device_inputs(inp, torch)
+    K = torch.empty(plan.info["d_size"], dtype=torch.float64, device="cuda:0")
+    plan.build_K(C, V, D, K)
+    used, ref = _grads(plan, C, V, D, 0.7, K)
+    assert used is None
+    plan.build_K(C, V, D, K)
+    bid = plan.build_id()
+    used, g = _grads(plan, C, V, D, 0.7, K, bid)
+    print("reuse after an FP64 build:", used, flush=True)
+    assert used
+    assert np.array_equal(g["dD"], ref["dD"]) and np.array_equal(g["dV"], ref["dV"])
+    assert relmax(g["dC"], ref["dC"]) < 1e-12 and relmax(g["F"], ref["F"]) < 1e-12
+    go = O.gradients(inp)
+    assert relmax(g["dC"], 0.7 * go["dC"]) < 1e-10 and relmax(g["dV"], 0.7 * go["dV"]) < 1e-10
+    used, g2 = _grads(plan, C, V, D, 0.7, K, bid)      # the backward itself moved the generation on
+    assert not used and all(np.array_equal(g2[k], ref[k]) for k in ref)
+    plan.build_K(C, V, D, K)
+    bid = plan.build_id()
+    K2 = torch.empty_like(K)
+    plan.build_K(C, V, 0.5 * D, K2)                   # another build in between
+    used, g3 = _grads(plan, C, V, D, 0.7, K, bid)
+    assert not used and all(np.array_equal(g3[k], ref[k]) for k in ref)
+    plan.build_K(C, V, D, K2, precision=exx.PREC_MIXED)
+    used, _ = _grads(plan, C, V, D, 0.7, K, plan.build_id())
+    assert not used
+    plan.set_screening(1e-300)
+    plan.build_K(C, V, D, K2)
+    plan.set_screening(0.0)
+    used, _ = _grads(plan, C, V, D, 0.7, K, plan.build_id())
+    assert not used
+    plan.build_K(C, V, D, K2)
+    used, g4 = _grads(plan, C, V, D, 0.7, K, plan.build_id(), want=("dV",))
+    assert used and np.array_equal(g4["dV"], ref["dV"])
+
+
+def test_backward_reuse_batch_periodic_and_chunked(exx):
+    """Per-system upstream gradients on a batch and a periodic cell: the reuse
+    backward agrees with the recomputing one to rounding; a chunked plan does not
+    reuse and gives the same gradients."""
+    dev = "cuda:0"
+    for name, sysm in (("batch", synth.cluster_batch(4, n_min=6, n_max=30)),
+                       ("periodic", synth.ice_box_periodic(1, 1, 1, seed=4, r_cut=3.4))):
+        inp = synth.make_inputs(sysm)
+        plan = exx.Plan.for_system(sysm)
+        C, V, D = device_inputs(inp, torch)
+        K = torch.empty(plan.info["d_size"], dtype=torch.float64, device=dev)
+        gE = torch.linspace(0.5, 1.5, plan.n_systems, dtype=torch.float64, device=dev)
+        plan.build_K(C, V, D, K)
+        _, ref = _grads(plan, C, V, D, gE, K)
+        plan.build_K(C, V, D, K)
+        used, g = _grads(plan, C, V, D, gE, K, plan.build_id())
+        print(name, "reused:", used, flush=True)
+        assert used
+        assert np.array_equal(g["dD"], ref["dD"]) and np.array_equal(g["dV"], ref["dV"])
+        assert relmax(g["dC"], ref["dC"]) < 1e-12 and relmax(g["F"], ref["F"]) < 1e-12
+    sysm = synth.ice_box(2, 2, 2, seed=3)
+    inp = synth.make_inputs(sysm)
+    whole = exx.Plan.for_system(sysm)
+    part = exx.Plan.for_system(sysm, ws_budget_bytes=whole.info["intermediate_bytes_stored"] // 3)
+    assert part.info["n_chunks"] >= 3
+    C, V, D = device_inputs(inp, torch)
+    K = torch.empty(part.info["d_size"], dtype=torch.float64, device=dev)
+    whole.build_K(C, V, D, K)
+    _, ref = _grads(whole, C, V, D, 1.0, K)
+    part.build_K(C, V, D, K)
+    used, g = _grads(part, C, V, D, 1.0, K, part.build_id())
+    assert not used
+    assert relmax(g["dC"], ref["dC"]) < 1e-12 and relmax(g["dV"], ref["dV"]) < 1e-12

@@ -243,3 +243,27 @@ def test_tile_cache_file(tmp_path):
     st = Plan.for_system(big, host_only=True).info["intermediate_bytes_stored"]
     assert (Plan.for_system(big, host_only=True).tune_key("gfx950")
             != Plan.for_system(big, host_only=True, ws_budget_bytes=st // 2).tune_key("gfx950"))
+
+
+def test_backward_reuse_entry_points_on_host():
+    """The workspace generation starts at 0 on a new plan; the reuse backward
+    answers like exchange_backward (EXX_EINVAL for a NULL plan, EXX_ESTATE for a
+    host-only plan) and reports that nothing was reused."""
+    import ctypes
+    from paper_2403_10343_amd import Plan, lib
+    sysm = synth.water_cluster(2, seed=0)
+    p = Plan.for_system(sysm, host_only=True)
+    assert p.build_id() == 0
+    L = lib()
+    x = ctypes.c_uint64(7)
+    assert L.exx_plan_build_id(None, ctypes.byref(x)) == -1
+    assert L.exx_plan_build_id(p._h, None) == -1
+    one = ctypes.c_void_p(1)
+    r = ctypes.c_int(5)
+    assert L.exchange_backward_reuse(None, 1, one, one, one, None, one, 0, one, None, None, None, 1.5, 8.0,
+                                     ctypes.byref(r), None) == -1
+    assert r.value == 0
+    r.value = 5
+    assert L.exchange_backward_reuse(p._h, 0, one, one, one, None, one, 0, one, None, None, None, 1.5, 8.0,
+                                     ctypes.byref(r), None) == -4
+    assert r.value == 0
