@@ -34,11 +34,11 @@ CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "27c02e3d1651e76f",
+    "sources": "6ddad5b983d9a706",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 29.201e9 + 4.205e9, ("fp64", "T2"): 25.151e9 + 0.036e9,
-              ("fp64", "final"): 10.245e9 + 4.282e9, ("fp64", "E"): 2.845e9 + 2.473e9,
-              ("mixed", "H"): 12.320e9 + 3.750e9, ("mixed", "H32"): 25.863e9 + 4.119e9},
+    "bytes": {("fp64", "H"): 29.215e9 + 4.208e9, ("fp64", "T2"): 25.176e9 + 0.036e9,
+              ("fp64", "final"): 10.246e9 + 4.282e9, ("fp64", "E"): 2.845e9 + 2.473e9,
+              ("mixed", "H"): 12.323e9 + 3.758e9, ("mixed", "H32"): 25.864e9 + 4.120e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>", "H32": "k_H<U, float, 1>",
                    "T2": "k_T2<NT, NS, double, COLS, WAVES, 1>", "T2_32": "k_T2<NT, NS, float, COLS, WAVES, 1>",
