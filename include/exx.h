@@ -348,9 +348,10 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
 
 /* Generation of the plan's workspace (the intermediates E and H' of
  * Eqs. temp_E and temp_H): a counter that every call writing them advances
- * (build_K, build_K_spin, build_K_two_kernels, graph builds and replays, the
- * backward calls).  Read it right after the build_K whose intermediates a
- * later exchange_backward_reuse is to take.  EXX_EINVAL on NULL arguments. */
+ * (build_K, build_K_spin, build_K_two_kernels, graph builds and replays, and
+ * the backward calls that form dC, dV or forces, or rebuild K for dD).  Read
+ * it right after the build_K whose intermediates a later
+ * exchange_backward_reuse is to take.  EXX_EINVAL on NULL arguments. */
 int exx_plan_build_id(exx_plan plan, uint64_t* id);
 
 /* exchange_backward (same arguments, results and errors) taking E and H' from
