@@ -508,10 +508,12 @@ def main():
             tsb0 = time.perf_counter()
             for _ in range(args.backward_steps):
                 plan.build_K_spin(C, V, Ds, K2, Ex)
-                plan.exchange_backward_spin(C, V, Ds, 1.0, dC=dCs, dV=dVs, dD=dDs, forces=Fs, K=K2)
+                reused = plan.exchange_backward_spin(C, V, Ds, 1.0, dC=dCs, dV=dVs, dD=dDs, forces=Fs, K=K2,
+                                                     build_id=plan.build_id())
             torch.cuda.synchronize()
             tsb = (time.perf_counter() - tsb0) / args.backward_steps
             out["spin"]["forward_backward_ms"] = 1e3 * tsb
+            out["spin"]["forward_intermediates_reused"] = reused
             out["spin"]["net_force_max"] = float(Fs.view(-1, 3).sum(0).abs().max().item())
     if args.two_kernel_steps > 0:
         V2 = torch.from_numpy(synth.short_range_V(inp)).to(dev)

@@ -350,8 +350,9 @@ int exchange_backward(exx_plan plan, const double* C, const double* V,
  * Eqs. temp_E and temp_H): a counter that every call writing them advances
  * (build_K, build_K_spin, build_K_two_kernels, graph builds and replays, and
  * the backward calls that form dC, dV or forces, or rebuild K for dD).  Read
- * it right after the build_K whose intermediates a later
- * exchange_backward_reuse is to take.  EXX_EINVAL on NULL arguments. */
+ * it right after the build_K (or build_K_spin) whose intermediates a later
+ * exchange_backward_reuse (exchange_backward_spin_reuse) is to take.
+ * EXX_EINVAL on NULL arguments. */
 int exx_plan_build_id(exx_plan plan, uint64_t* id);
 
 /* exchange_backward (same arguments, results and errors) taking E and H' from
@@ -384,6 +385,19 @@ int exchange_backward_spin(exx_plan plan, const double* C, const double* V,
                            const double* D, const double* K, const double* gE, int precision,
                            double* dC, double* dV, double* dD, double* forces,
                            double c_decay, double v_2s2, void* stream);
+
+/* exchange_backward_spin taking E^s and H'^s of both spins from the workspace,
+ * as exchange_backward_reuse does for one density matrix: when build_id is
+ * the current generation and that generation is a binary64 build_K_spin
+ * without screening on a plan of one workspace chunk (the caller vouches that
+ * C, V and both density matrices are unchanged since); otherwise they are
+ * recomputed.  *reused (may be NULL): 1 when they were taken, else 0. */
+int exchange_backward_spin_reuse(exx_plan plan, uint64_t build_id, const double* C,
+                                 const double* V, const double* D, const double* K,
+                                 const double* gE, int precision, double* dC,
+                                 double* dV, double* dD, double* forces,
+                                 double c_decay, double v_2s2, int* reused,
+                                 void* stream);
 
 /* Strain derivative of the energy (the stress contribution of Sec. "EXX
  * force and stress contributions", for the synthetic model of exchange_backward):

@@ -58,7 +58,7 @@ EXPORTS = ("exx_plan_create", "exx_plan_destroy", "exx_plan_info", "exx_pair_lay
            "build_K_two_kernels", "exchange_energy_noalloc", "exx_pair_images", "exx_block_norms",
            "exx_set_screening", "exx_screened_pairs", "exchange_backward_spin",
            "exx_strain_derivative", "exx_bloch_sum", "exx_density_from_k", "exx_plan_build_id",
-           "exchange_backward_reuse")
+           "exchange_backward_reuse", "exchange_backward_spin_reuse")
 N_STAGES = 8
 STAGE_NAMES = ("repack", "E", "H", "H32", "T2", "T2_32", "final", "energy")
 
@@ -88,6 +88,8 @@ def lib():
     L.exx_plan_build_id.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.exchange_backward_reuse.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp,
                                           dp, dp, ctypes.POINTER(ctypes.c_int), vp]
+    L.exchange_backward_spin_reuse.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp,
+                                               vp, dp, dp, ctypes.POINTER(ctypes.c_int), vp]
     L.exx_strain_derivative.argtypes = [vp, vp, vp, vp, vp, dp, dp, vp, vp]
     L.exx_bloch_sum.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
     L.exx_density_from_k.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
@@ -352,19 +354,28 @@ class Plan:
         return used
 
     def exchange_backward_spin(self, C, V, D, gE, dC=None, dV=None, dD=None, forces=None,
-                               precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None):
+                               precision=PREC_FP64, c_decay=1.5, v_2s2=8.0, stream=None, K=None, build_id=None):
         """Gradients of sum_s gE[s] E_x[s] for the collinear-spin energy of
-        build_K_spin: D, K (optional) and dD hold spin 0 then spin 1."""
+        build_K_spin: D, K (optional) and dD hold spin 0 then spin 1.  build_id
+        (optional): build_id() read right after that build_K_spin, as in
+        exchange_backward (returns whether E and H' were taken, else None)."""
         i = self.info
         c, v, d = self._cvd(C, V, D, 2)
         g = self.gE_tensor(gE, C.device)
-        _check(lib().exchange_backward_spin(self._h, c, v, d, _dev(K, 2 * i["d_size"], "K", True),
-                                            _dev(g, self.n_systems, "gE"), int(precision),
-                                            _dev(dC, i["c_size"], "dC", True), _dev(dV, i["v_size"], "dV", True),
-                                            _dev(dD, 2 * i["d_size"], "dD", True),
-                                            _dev(forces, 3 * self.n_atoms, "forces", True),
-                                            float(c_decay), float(v_2s2), _stream(stream)))
+        args = (c, v, d, _dev(K, 2 * i["d_size"], "K", True), _dev(g, self.n_systems, "gE"), int(precision),
+                _dev(dC, i["c_size"], "dC", True), _dev(dV, i["v_size"], "dV", True),
+                _dev(dD, 2 * i["d_size"], "dD", True), _dev(forces, 3 * self.n_atoms, "forces", True),
+                float(c_decay), float(v_2s2))
+        used = None
+        if build_id is None:
+            _check(lib().exchange_backward_spin(self._h, *args, _stream(stream)))
+        else:
+            r = ctypes.c_int(0)
+            _check(lib().exchange_backward_spin_reuse(self._h, ctypes.c_uint64(int(build_id)), *args,
+                                                      ctypes.byref(r), _stream(stream)))
+            used = bool(r.value)
         self._last_gE = g
+        return used
 
     def strain_derivative(self, C, V, dC, dV, c_decay=1.5, v_2s2=8.0, stream=None):
         """dE/d(eps) [3, 3] for the homogeneous deformation x -> (1 + eps) x, from dC, dV of

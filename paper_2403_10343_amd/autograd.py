@@ -6,7 +6,7 @@ kernels for dE/dC, dE/dV and dE/dD with each system's upstream gradient,
 reusing the forward K for dE/dD and, after a binary64 forward whose workspace
 no other call has overwritten, the forward's intermediates E and H'.
 ``spin_exchange_energy(plan, C, V, D)`` is the same for the collinear-spin
-energy (two density matrices, binary64).
+energy (two density matrices, binary64; the forward's E and H' likewise).
 ``exchange_forces(plan, C, V, D)`` returns -dE_x/dR for the synthetic
 exp(-r/1.5) / exp(-r^2/8) position dependence of C and V.
 """
@@ -50,6 +50,7 @@ class _SpinExchangeEnergy(torch.autograd.Function):
         plan.build_K_spin(C, V, D, K, Ex)
         ctx.save_for_backward(C, V, D, K)
         ctx.plan = plan
+        ctx.build_id = plan.build_id()
         return Ex
 
     @staticmethod
@@ -61,7 +62,7 @@ class _SpinExchangeEnergy(torch.autograd.Function):
         dV = torch.empty_like(V) if need[1] else None
         dD = torch.empty_like(D) if need[2] else None
         if dC is not None or dV is not None or dD is not None:
-            ctx.plan.exchange_backward_spin(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K)
+            ctx.plan.exchange_backward_spin(C, V, D, gE, dC=dC, dV=dV, dD=dD, K=K, build_id=ctx.build_id)
         return dC, dV, dD, None
 
 

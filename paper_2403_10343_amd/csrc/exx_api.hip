@@ -1257,10 +1257,11 @@ static void build_chunks(exx_plan plan, const double* V, const double* D, double
 }
 
 // a call has written the workspace; fp64_build: E and H' are now those of a binary64,
-// unscreened, single-chunk build_K of the call's inputs
-static void ws_written(exx_plan plan, bool fp64_build) {
+// unscreened, single-chunk build_K of the call's inputs (fp64_spin: of such a build_K_spin)
+static void ws_written(exx_plan plan, bool fp64_build, bool fp64_spin = false) {
   ++plan->ws_seq;
   plan->ws_fp64 = fp64_build ? plan->ws_seq : 0;
+  plan->ws_fp64_spin = fp64_spin ? plan->ws_seq : 0;
 }
 
 // mixed list set of a precision, or -1 for binary64; -2: unknown, -3: reserved
@@ -1428,7 +1429,7 @@ int build_K_spin(exx_plan plan, const double* C, const double* V, const double* 
   set_chunk(plan, 0);
   d.scr = nullptr;
   if (screened) plan->scr_done = true;
-  ws_written(plan, false);
+  ws_written(plan, false, m < 0 && !screened && n_chunks(plan) == 1);
   stage_mark(plan, 7, st);
   HIP_TRY(hipGetLastError());
   if (Ex) rc = launch_energy(plan, K, D, Ex, st, 2);
@@ -1936,10 +1937,12 @@ __global__ void k_scale_vec(double* __restrict__ y, const double* __restrict__ x
   if (i < n) y[i] = a * x[i];
 }
 
-int exchange_backward_spin(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
-                           const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
-                           double c_decay, double v_2s2, void* stream) {
-  int rc = backward_checks(plan, "exchange_backward_spin", C, V, D, gE, precision, forces, c_decay, v_2s2);
+// reuse: E^s and H'^s in the workspace are those of a binary64 build_K_spin of these inputs
+// (single chunk): taken instead of recomputed, the G terms brought back to once.
+static int backward_spin(exx_plan plan, const char* who, bool reuse, const double* C, const double* V,
+                         const double* D, const double* K, const double* gE, int precision, double* dC, double* dV,
+                         double* dD, double* forces, double c_decay, double v_2s2, void* stream) {
+  int rc = backward_checks(plan, who, C, V, D, gE, precision, forces, c_decay, v_2s2);
   if (rc != EXX_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   const HostPlan& hp = plan->hp;
@@ -1988,12 +1991,13 @@ int exchange_backward_spin(exx_plan plan, const double* C, const double* V, cons
     for (int c = 0; c < n_chunks(plan); ++c) {
       set_chunk(plan, c);
       const ChunkDev& ch = cur_chunk(plan);
-      launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), ch.n_e, st);
+      if (!reuse) launch_rowD_spin(plan, d.Dm, plan->spin_Dm1, plan->spin_E1, rowd_E(plan), ch.n_e, st);
       if (needC) {
+        // recomputed with the G term once, or the build's (G twice) with one G-only pass of factor -1
         launch_H_lists<double, 2>(plan, V, D,
                                   HLists{d.g_tiles + ch.gt_beg, d.gq, d.gx, plan->h_vbase, plan->spin_E1,
                                          plan->spin_H1, plan->spin_Dr1},
-                                  ch.gt_end - ch.gt_beg, 1.0, H_WRITE, st);
+                                  ch.gt_end - ch.gt_beg, reuse ? -1.0 : 1.0, reuse ? H_G_ADD : H_WRITE, st);
         launch_rowD(plan, d.Dm, rowd_GD(plan), ch.gd_end - ch.gd_beg, st);
         double* const H0 = d.H;
         double* const GD0 = d.GD;
@@ -2025,6 +2029,25 @@ int exchange_backward_spin(exx_plan plan, const double* C, const double* V, cons
   if (forces) launch_forces(plan, C, V, dCb, dVb, forces, c_decay, v_2s2, st);
   HIP_TRY(hipGetLastError());
   return EXX_OK;
+}
+
+int exchange_backward_spin(exx_plan plan, const double* C, const double* V, const double* D, const double* K,
+                           const double* gE, int precision, double* dC, double* dV, double* dD, double* forces,
+                           double c_decay, double v_2s2, void* stream) {
+  return backward_spin(plan, "exchange_backward_spin", false, C, V, D, K, gE, precision, dC, dV, dD, forces, c_decay,
+                       v_2s2, stream);
+}
+
+int exchange_backward_spin_reuse(exx_plan plan, uint64_t build_id, const double* C, const double* V,
+                                 const double* D, const double* K, const double* gE, int precision, double* dC,
+                                 double* dV, double* dD, double* forces, double c_decay, double v_2s2, int* reused,
+                                 void* stream) {
+  const bool reuse = plan && build_id != 0 && build_id == plan->ws_seq && build_id == plan->ws_fp64_spin &&
+                     n_chunks(plan) == 1;
+  const int rc = backward_spin(plan, "exchange_backward_spin_reuse", reuse, C, V, D, K, gE, precision, dC, dV, dD,
+                               forces, c_decay, v_2s2, stream);
+  if (reused) *reused = (rc == EXX_OK && reuse) ? 1 : 0;
+  return rc;
 }
 
 }  // extern "C"

@@ -259,6 +259,7 @@ struct exx_plan_s {
   // (0: none), which exchange_backward_reuse may take instead of recomputing them
   uint64_t ws_seq = 0;
   uint64_t ws_fp64 = 0;
+  uint64_t ws_fp64_spin = 0;   // the same for a binary64 build_K_spin (E, H' of both spins)
 };
 
 // Point the device plan and the launchers at chunk c.

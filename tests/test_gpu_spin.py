@@ -266,3 +266,44 @@ def test_spin_autograd(exx):
     torch.cuda.synchronize()
     assert relmax(C.grad.cpu().numpy(), dC.cpu().numpy()) < 1e-12
     assert relmax(D2.grad.cpu().numpy(), dD.cpu().numpy()) < 1e-12
+
+
+def test_spin_backward_reuses_forward_intermediates(exx):
+    """After a binary64 build_K_spin, exchange_backward_spin_reuse takes E^s and
+    H'^s from the workspace: dD and dV equal the recomputing spin backward's bit
+    for bit, dC and the forces to rounding; after another build, or after a
+    one-density build, it recomputes (bit for bit the plain spin backward)."""
+    dev = "cuda:0"
+    sysm = synth.water_cluster(8, 5)
+    inp = synth.make_inputs(sysm)
+    Ds = synth.spin_densities(inp)
+    plan = exx.Plan.for_system(sysm)
+    C, V, D = device_inputs(inp, torch)
+    D2 = torch.from_numpy(np.ascontiguousarray(Ds.reshape(-1))).to(dev)
+    n = plan.info["d_size"]
+    K2 = torch.empty(2 * n, dtype=torch.float64, device=dev)
+
+    def grads(build_id=None):
+        dC, dV, dD = torch.empty_like(C), torch.empty_like(V), torch.empty_like(D2)
+        F = torch.empty(plan.n_atoms * 3, dtype=torch.float64, device=dev)
+        used = plan.exchange_backward_spin(C, V, D2, 0.6, dC=dC, dV=dV, dD=dD, forces=F, K=K2, build_id=build_id)
+        torch.cuda.synchronize()
+        return used, {k: x.cpu().numpy() for k, x in (("dC", dC), ("dV", dV), ("dD", dD), ("F", F))}
+
+    plan.build_K_spin(C, V, D2, K2)
+    _, ref = grads()
+    plan.build_K_spin(C, V, D2, K2)
+    used, g = grads(plan.build_id())
+    print("spin reuse after an FP64 spin build:", used, flush=True)
+    assert used
+    assert np.array_equal(g["dD"], ref["dD"]) and np.array_equal(g["dV"], ref["dV"])
+    assert relmax(g["dC"], ref["dC"]) < 1e-12 and relmax(g["F"], ref["F"]) < 1e-12
+    go = O.spin_gradients(inp, Ds)
+    assert relmax(g["dC"], 0.6 * go["dC"]) < 1e-10 and relmax(g["dV"], 0.6 * go["dV"]) < 1e-10
+    plan.build_K_spin(C, V, D2, K2)
+    bid = plan.build_id()
+    plan.build_K(C, V, D, torch.empty(n, dtype=torch.float64, device=dev))
+    used, g2 = grads(bid)
+    assert not used and all(np.array_equal(g2[k], ref[k]) for k in ref)
+    used, _ = grads(plan.build_id())                  # a one-density build is not a spin build
+    assert not used

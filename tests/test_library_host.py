@@ -267,3 +267,19 @@ def test_backward_reuse_entry_points_on_host():
     assert L.exchange_backward_reuse(p._h, 0, one, one, one, None, one, 0, one, None, None, None, 1.5, 8.0,
                                      ctypes.byref(r), None) == -4
     assert r.value == 0
+
+
+def test_spin_backward_reuse_entry_point_on_host():
+    import ctypes
+    from paper_2403_10343_amd import Plan, lib
+    p = Plan.for_system(synth.water_cluster(2, seed=0), host_only=True)
+    one = ctypes.c_void_p(1)
+    r = ctypes.c_int(5)
+    L = lib()
+    assert L.exchange_backward_spin_reuse(None, 1, one, one, one, None, one, 0, one, None, None, None, 1.5, 8.0,
+                                          ctypes.byref(r), None) == -1
+    assert r.value == 0
+    r.value = 5
+    assert L.exchange_backward_spin_reuse(p._h, 0, one, one, one, None, one, 0, one, None, None, None, 1.5, 8.0,
+                                          ctypes.byref(r), None) == -4
+    assert r.value == 0
