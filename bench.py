@@ -34,11 +34,11 @@ CSRC = os.path.join(ROOT, "paper_2403_10343_amd", "csrc")
 # kernels built from the sources with this fingerprint only; for any other
 # sources the roofline's traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "sources": "6ddad5b983d9a706",
+    "sources": "280086a1867b8e10",
     "workload": "ice768",
-    "bytes": {("fp64", "H"): 29.215e9 + 4.208e9, ("fp64", "T2"): 25.176e9 + 0.036e9,
-              ("fp64", "final"): 10.246e9 + 4.282e9, ("fp64", "E"): 2.845e9 + 2.473e9,
-              ("mixed", "H"): 12.323e9 + 3.758e9, ("mixed", "H32"): 25.864e9 + 4.120e9},
+    "bytes": {("fp64", "H"): 29.228e9 + 4.206e9, ("fp64", "T2"): 25.185e9 + 0.036e9,
+              ("fp64", "final"): 10.246e9 + 4.282e9, ("fp64", "E"): 2.847e9 + 2.473e9,
+              ("mixed", "H"): 12.329e9 + 3.757e9, ("mixed", "H32"): 25.900e9 + 4.117e9},
 }
 KERNEL_OF_STAGE = {"repack": "k_repack", "E": "k_rowD", "H": "k_H<U, double, 1>", "H32": "k_H<U, float, 1>",
                    "T2": "k_T2<NT, NS, double, COLS, WAVES, 1>", "T2_32": "k_T2<NT, NS, float, COLS, WAVES, 1>",
